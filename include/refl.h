@@ -1,0 +1,179 @@
+/*
+ * refl.h -- prescribed-index reflectors R_k = I - 2 P_k = sgn(H - sI) of a
+ * dense symmetric matrix on one MI355X (gfx950), by the shifted
+ * Newton-Schulz matrix-sign iteration.
+ *
+ * Problem statement (paper, section 1 eq. Rk_intro and section 2.1 eq. Pk):
+ * H in R^{d x d} symmetric with eigenvalues lambda_1 <= ... <= lambda_d,
+ * k in {1, ..., d-1}, P_k the spectral projector onto the eigenvectors of the
+ * k smallest eigenvalues.  For any shift s in (lambda_k, lambda_{k+1}),
+ * R_k = sgn(H - sI) (Prop. 2.1).  R_k is computed by the scaled iteration
+ * X_0 = (H - sI)/alpha, X_{m+1} = X_m (3I - X_m^2)/2 (section 3.2, eq. NS),
+ * with the midpoint shift s = (lambda_k + lambda_{k+1})/2 (Prop. 4.1)
+ * supplied or estimated by block Lanczos (section 4.3, recommended default
+ * realization), and alpha = ||H - sI||_inf (the cheap surrogate of
+ * section 4.3) or a supplied value.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Pointers named d* are DEVICE pointers on the handle's device; they are
+ *   owned by the caller and never freed or retained by the library.
+ * - Matrices are dense FP64, row-major with a leading dimension >= d.
+ *   H is read from its UPPER triangle only (entries (i, j), i <= j); the
+ *   strictly lower triangle is never read.  R is written in full and is
+ *   exactly symmetric.  Blocks of vectors V, Y are d x nrhs, column-major
+ *   (column c starts at V + c*ldv, ldv >= d).
+ * - All device work is enqueued on the handle's HIP stream.  refl_sign,
+ *   refl_sign_apply and refl_estimate_shift synchronise that stream before
+ *   returning (their info outputs live on the host); refl_apply does not.
+ * - A handle is not thread-safe; use one handle per host thread.  Calls on
+ *   one handle are serialised by its stream.
+ * - Errors are reported only through refl_status_t; nothing throws or aborts
+ *   across this boundary.  refl_last_error(h) gives a message for the last
+ *   failing call on h.  On REFL_ERR_NOT_CONVERGED, R holds the last iterate
+ *   and info is complete; on any other error the outputs are unspecified.
+ */
+#ifndef REFL_H_
+#define REFL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct refl_handle_s *refl_handle_t;
+
+typedef enum {
+  REFL_OK = 0,
+  REFL_ERR_INVALID_ARG = 1,    /* null pointer, d < 2, k outside 1..d-1, ld < d, bad mode */
+  REFL_ERR_DEVICE = 2,         /* a HIP runtime call failed */
+  REFL_ERR_NO_MEMORY = 3,      /* workspace allocation failed or caller workspace too small */
+  REFL_ERR_NOT_CONVERGED = 4,  /* max_iter reached before the stopping rule held */
+  REFL_ERR_NOT_ADMISSIBLE = 5, /* the iterate's index certificate found j != k negatives,
+                                  or the Lanczos margin test of Prop. 4.2 failed */
+  REFL_ERR_NO_GAP = 6,         /* lambda_k == lambda_{k+1} to working precision */
+  REFL_ERR_NOT_FINITE = 7,     /* H (or the shift/scale) holds a NaN or an infinity */
+  REFL_ERR_UNSUPPORTED = 8     /* valid request this build does not implement */
+} refl_status_t;
+
+/* Arithmetic of the Newton-Schulz matrix products. */
+typedef enum {
+  REFL_PREC_FP64 = 0,  /* FP64 MFMA products, FP64 iterate: the plain method */
+  REFL_PREC_FP32 = 1,  /* FP32 MFMA products, FP32 iterate (error floor ~1e-5 relative) */
+  REFL_PREC_MIXED = 2  /* products on split-BF16 words with FP32 accumulation, then an
+                          FP64 correction of the target subspace that uses H itself */
+} refl_precision_t;
+
+typedef enum { REFL_SHIFT_GIVEN = 0, REFL_SHIFT_LANCZOS = 1 } refl_shift_mode_t;
+
+typedef enum {
+  REFL_SCALE_INF = 0,   /* alpha = ||H - sI||_inf (max absolute row sum) */
+  REFL_SCALE_GIVEN = 1  /* alpha = params.alpha; X_0 = (H - sI)/alpha */
+} refl_scale_mode_t;
+
+typedef struct {
+  int32_t k;            /* target index, 1 <= k <= d-1 (section 2.1) */
+  double s;             /* shift (shift_mode == REFL_SHIFT_GIVEN) */
+  int32_t shift_mode;   /* refl_shift_mode_t */
+  int32_t scale_mode;   /* refl_scale_mode_t */
+  int32_t precision;    /* refl_precision_t */
+  double alpha;         /* scale (scale_mode == REFL_SCALE_GIVEN), must exceed 0 */
+  double tol;           /* FP64/FP32: stop when ||X^2 - I||_F < tol.
+                           MIXED: stop the FP64 correction when the certified bound on
+                           ||R - R_k||_F falls below tol */
+  int32_t max_iter;     /* cap on Newton-Schulz steps (default 100) */
+  int32_t fixed_steps;  /* > 0: exactly this many steps, no convergence test: the
+                           finite-step filter p_m of eq. pm (FP64/FP32 only) */
+  int32_t words;        /* MIXED: BF16 words per operand, 2 (bf16x3) or 3 (bf16x6) */
+  int32_t polish_sweeps;/* MIXED: maximum FP64 correction sweeps (default 2) */
+  double cg_tol;        /* MIXED: relative residual target of the inner solves (default 1e-6) */
+  int32_t cg_max_iter;  /* MIXED: cap on inner iterations per sweep (default 400) */
+  int32_t lanczos_steps;/* REFL_SHIFT_LANCZOS: cap on block steps (0 = automatic) */
+  uint64_t seed;        /* start blocks of Lanczos and of the subspace extraction */
+} refl_params_t;
+
+typedef struct {
+  int32_t ns_steps;       /* Newton-Schulz steps taken */
+  int32_t polish_sweeps;  /* MIXED: correction sweeps taken */
+  int32_t cg_iters;       /* MIXED: inner iterations, summed over sweeps */
+  int32_t index_j;        /* number of negative eigenvalues certified for the iterate
+                             (-1 if the certificate did not hold) */
+  int32_t lanczos_steps;  /* block Lanczos steps (shift estimated) */
+  double s;               /* shift used */
+  double alpha;           /* scale used: X_0 = (H - sI)/alpha */
+  double lam_k, lam_k1;   /* Lanczos estimates of lambda_k, lambda_{k+1} (NaN if s given) */
+  double eps;             /* Lanczos residual bound on both estimates (Prop. 4.2) */
+  double margin;          /* certified shift margin m_hat - eps (Prop. 4.2), NaN if s given */
+  double resid_fro;       /* ||X^2 - I||_F of the last bulk iterate */
+  double trace;           /* trace of the last bulk iterate */
+  double commutator_fro;  /* MIXED: ||H R - R H||_F of the returned R (= 2 sqrt2 ||E||_F,
+                             E = (I - V V^T) H V); FP64/FP32: NaN */
+  double dk_bound;        /* MIXED: Davis-Kahan bound on ||R - R_k||_F; FP64/FP32: NaN */
+  double ms_setup, ms_bulk, ms_polish, ms_total; /* host wall-clock per phase */
+} refl_info_t;
+
+/* Fill *p with defaults: k = 1, s = 0, shift given, scale inf-norm, FP64,
+ * tol = 1e-12, max_iter = 100, fixed_steps = 0, words = 2, polish_sweeps = 2,
+ * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0. */
+refl_status_t refl_params_default(refl_params_t *p);
+
+/* Create a handle bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t, or NULL for the device's null stream).  Allocates no
+ * device memory. */
+refl_status_t refl_create(refl_handle_t *h, int device, void *hip_stream);
+
+/* Release the handle and any workspace the library allocated itself.  Waits
+ * for the handle's stream first. */
+refl_status_t refl_destroy(refl_handle_t h);
+
+refl_status_t refl_set_stream(refl_handle_t h, void *hip_stream);
+
+/* Bytes of device workspace refl_sign / refl_sign_apply need for order d
+ * and parameters *p (refl_estimate_shift needs no more than this). */
+refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_t *p,
+                                  size_t *bytes);
+
+/* Hand the library a caller-owned device workspace (256-byte aligned).  If
+ * none is set, or it is too small, the library allocates its own and keeps
+ * it until refl_destroy.  Passing NULL reverts to the library's own. */
+refl_status_t refl_set_workspace(refl_handle_t h, void *dptr, size_t bytes);
+
+/* Shift estimation by block Lanczos with full reorthogonalisation on H
+ * (section 4.3, recommended default realization; Prop. 4.2).  Returns the
+ * midpoint *s of the estimates *lam_k, *lam_k1 of lambda_k, lambda_{k+1},
+ * a common residual bound *eps on both (|lam_hat - lam| <= eps when the
+ * Ritz values are attributed to the right eigenvalues), and an estimate
+ * *rho of max_i |lambda_i - s|.  REFL_ERR_NOT_ADMISSIBLE if the margin
+ * m_hat = min(s - lam_k, lam_k1 - s) does not exceed eps; REFL_ERR_NO_GAP if
+ * the estimates coincide. */
+refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
+                                  int32_t k, int32_t steps, uint64_t seed, double *s,
+                                  double *lam_k, double *lam_k1, double *eps, double *rho);
+
+/* R_k = sgn(H - sI) into dR (d x d, leading dimension ldr).  info may be
+ * NULL.  See refl_params_t for the modes. */
+refl_status_t refl_sign(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
+                        const refl_params_t *p, double *dR, int64_t ldr, refl_info_t *info);
+
+/* Y = R V for a d x d matrix R (full storage, row-major, ldr >= d) and a
+ * d x nrhs block V; the direction d = -R g of eq. discrete_step and
+ * Prop. 3.3 is refl_apply with V = -g.  Asynchronous. */
+refl_status_t refl_apply(refl_handle_t h, int64_t d, const double *dR, int64_t ldr,
+                         int64_t nrhs, const double *dV, int64_t ldv, double *dY, int64_t ldy);
+
+/* Y = R_k V without writing R: the same computation as refl_sign, then the
+ * product with the d x nrhs block V. */
+refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
+                              const refl_params_t *p, int64_t nrhs, const double *dV,
+                              int64_t ldv, double *dY, int64_t ldy, refl_info_t *info);
+
+/* Static strings; never NULL. */
+const char *refl_status_string(refl_status_t s);
+const char *refl_last_error(refl_handle_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REFL_H_ */

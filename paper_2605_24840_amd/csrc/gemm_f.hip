@@ -1,0 +1,240 @@
+// Symmetric FP64 / FP32 products of the Newton-Schulz step (section 3.2,
+// eq. NS) on 16x16x4 MFMA, with the step's elementwise work fused into the
+// epilogue.
+//
+// One Newton-Schulz step X <- X (3I - X^2)/2 is written as two products,
+//   GEMM_RESIDUAL:  T = X X,  N = I - T            (and ||N||_F^2 = ||X^2 - I||_F^2)
+//   GEMM_UPDATE:    P = X N,  X_new = X + P/2      (and trace X_new)
+// which equals X (3I - X^2)/2 exactly in real arithmetic.  X and N are
+// symmetric and commute, so both products are symmetric: only the tiles
+// (I, J) with I <= J are multiplied, and each result tile is stored twice,
+// at (I, J) and transposed at (J, I).  Because X = X^T and N = N^T, the
+// (i, j) entry of either product is the dot product of row i of the left
+// factor with row j of the right factor, so both operands stream row panels
+// with K contiguous.
+//
+// Work-group: 256 threads = 4 waves, output tile 128 x 128, each wave a
+// 64 x 64 quadrant = 4 x 4 MFMA blocks of 16 x 16.  K advances 16 at a time
+// through two LDS buffers (global loads of step k+1 overlap the MFMAs of
+// step k).  The epilogue stages the tile in LDS, so that the direct and the
+// transposed stores are both row-contiguous.
+#include "common.h"
+#include "launch.h"
+
+namespace refl {
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct FMfma;
+template <>
+struct FMfma<double> {
+  typedef f64x4_t acc_t;
+  // 16x16 result block: lane l, register r holds row 4r + l/16, column l%16.
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct FMfma<float> {
+  typedef f32x4_t acc_t;
+  // 16x16 result block: lane l, register r holds row 4(l/16) + r, column l%16.
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T>
+struct FCfg {
+  static constexpr int BK = 16;
+  static constexpr int LDA = BK + 16 / (int)sizeof(T);  // 16 B pad per LDS row
+  static constexpr int OPER = 2 * 2 * TILE * LDA;       // 2 buffers x 2 operands
+  static constexpr int SLD = TILE + 1;                  // staging row stride
+  static constexpr int STG = TILE * SLD;
+  static constexpr int LDS = OPER > STG ? OPER : STG;
+  static constexpr int NV = 8 * (int)sizeof(T) / 16;    // 16 B vectors per thread per operand
+  static constexpr int VE = 16 / (int)sizeof(T);        // elements per 16 B
+};
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
+                                                    const T* __restrict__ B,
+                                                    const T* __restrict__ Xold,
+                                                    T* __restrict__ out, int ld, int d, int dp,
+                                                    const int2* __restrict__ tiles,
+                                                    double* __restrict__ partials) {
+  typedef FCfg<T> C;
+  typedef FMfma<T> M;
+  typedef typename M::acc_t acc_t;
+  __shared__ T lds[C::LDS];
+  __shared__ double red[4];
+
+  const int2 tl = tiles[blockIdx.x];
+  const int i0 = tl.x * TILE, j0 = tl.y * TILE;
+  const bool diag = (tl.x == tl.y);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // Loader: thread -> row (tid >> 1), 8 consecutive k at (tid & 1) * 8.
+  const int lrow = tid >> 1, lk = (tid & 1) * 8;
+  const T* gA = A + (int64_t)(i0 + lrow) * ld + lk;
+  const T* gB = B + (int64_t)(j0 + lrow) * ld + lk;
+  u32x4_t ra[C::NV], rb[C::NV];
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
+
+  const int nk = dp / C::BK;
+  auto gload = [&](int kt) {
+    const u32x4_t* pa = reinterpret_cast<const u32x4_t*>(gA + (int64_t)kt * C::BK);
+    const u32x4_t* pb = reinterpret_cast<const u32x4_t*>(gB + (int64_t)kt * C::BK);
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v) {
+      ra[v] = pa[v];
+      rb[v] = pb[v];
+    }
+  };
+  auto sstore = [&](int buf) {
+    T* sa = lds + buf * (2 * TILE * C::LDA);
+    T* sb = sa + TILE * C::LDA;
+    u32x4_t* da = reinterpret_cast<u32x4_t*>(sa + lrow * C::LDA + lk);
+    u32x4_t* db = reinterpret_cast<u32x4_t*>(sb + lrow * C::LDA + lk);
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v) {
+      da[v] = ra[v];
+      db[v] = rb[v];
+    }
+  };
+
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+    const T* sa = lds + cur * (2 * TILE * C::LDA);
+    const T* sb = sa + TILE * C::LDA;
+#pragma unroll
+    for (int kk = 0; kk < C::BK / 4; ++kk) {
+      T av[4], bv[4];
+      const int kof = kk * 4 + (lane >> 4);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sa[(wr * 64 + a * 16 + (lane & 15)) * C::LDA + kof];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = sb[(wc * 64 + b * 16 + (lane & 15)) * C::LDA + kof];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = M::op(av[a], bv[b], acc[a][b]);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue: stage the 128 x 128 result tile ----
+  T* stg = lds;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * 64 + a * 16 + M::row(lane, r);
+        const int col = wc * 64 + b * 16 + (lane & 15);
+        stg[row * C::SLD + col] = acc[a][b][r];
+      }
+  __syncthreads();
+
+  // Direct pass: row-contiguous 16 B stores.  In a diagonal tile entry (r, c)
+  // takes the value computed at (min, max) so the stored tile is exactly
+  // symmetric.
+  constexpr int LPR = TILE / C::VE;      // lanes per tile row
+  constexpr int RPI = 256 / LPR;         // rows per iteration
+  const int cofs = (tid % LPR) * C::VE;
+  double part = 0.0;
+  alignas(16) T vals[TILE / RPI][C::VE];
+#pragma unroll
+  for (int it = 0; it < TILE / RPI; ++it) {
+    const int r = it * RPI + tid / LPR;
+    const int gi = i0 + r;
+    alignas(16) T xo[C::VE];
+    if (MODE == GEMM_UPDATE) {
+      const u32x4_t v = *reinterpret_cast<const u32x4_t*>(Xold + (int64_t)gi * ld + j0 + cofs);
+      *reinterpret_cast<u32x4_t*>(xo) = v;
+    }
+#pragma unroll
+    for (int e = 0; e < C::VE; ++e) {
+      const int c = cofs + e;
+      const int rr = (diag && r > c) ? c : r, cc = (diag && r > c) ? r : c;
+      const T v = stg[rr * C::SLD + cc];
+      const int gj = j0 + c;
+      T n;
+      if (MODE == GEMM_RESIDUAL) {
+        n = ((gi == gj && gi < d) ? T(1) : T(0)) - v;
+        part += (diag ? 1.0 : 2.0) * (double)n * (double)n;
+      } else {
+        n = xo[e] + T(0.5) * v;
+        if (gi == gj) part += (double)n;
+      }
+      vals[it][e] = n;
+    }
+    *reinterpret_cast<u32x4_t*>(out + (int64_t)gi * ld + j0 + cofs) =
+        *reinterpret_cast<const u32x4_t*>(&vals[it][0]);
+  }
+  __syncthreads();
+  if (!diag) {
+    // Write the final values back to staging, then store the transposed tile.
+#pragma unroll
+    for (int it = 0; it < TILE / RPI; ++it) {
+      const int r = it * RPI + tid / LPR;
+#pragma unroll
+      for (int e = 0; e < C::VE; ++e) stg[r * C::SLD + cofs + e] = vals[it][e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < TILE / RPI; ++it) {
+      const int c = it * RPI + tid / LPR;   // output row j0 + c
+      alignas(16) T v[C::VE];
+#pragma unroll
+      for (int e = 0; e < C::VE; ++e) v[e] = stg[(cofs + e) * C::SLD + c];
+      *reinterpret_cast<u32x4_t*>(out + (int64_t)(j0 + c) * ld + i0 + cofs) =
+          *reinterpret_cast<const u32x4_t*>(v);
+    }
+  }
+  const double tot = block_sum_256(part, red);
+  if (tid == 0) partials[blockIdx.x] = tot;
+}
+
+template <typename T>
+static hipError_t launch_f(int mode, const T* A, const T* B, const T* Xold, T* out, int ld, int d,
+                           int dp, const int2* tiles, int ntiles, double* partials,
+                           hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (mode == GEMM_RESIDUAL)
+    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_RESIDUAL>), dim3(ntiles), dim3(256), 0, st, A, B,
+                       Xold, out, ld, d, dp, tiles, partials);
+  else
+    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_UPDATE>), dim3(ntiles), dim3(256), 0, st, A, B, Xold,
+                       out, ld, d, dp, tiles, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_gemm_f64(int mode, const double* A, const double* B, const double* Xold,
+                               double* out, int ld, int d, int dp, const int2* tiles, int ntiles,
+                               double* partials, hipStream_t st) {
+  return launch_f<double>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+}
+hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const float* Xold,
+                               float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
+                               double* partials, hipStream_t st) {
+  return launch_f<float>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+}
+
+}  // namespace refl

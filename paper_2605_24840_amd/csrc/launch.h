@@ -1,0 +1,116 @@
+// Host-side launchers of the reflector kernels (implemented in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace refl {
+
+// Epilogue of a symmetric product C = A B (both operands symmetric and
+// commuting, so C is symmetric; only upper tiles are multiplied and each is
+// mirrored on store).
+enum GemmMode {
+  GEMM_RESIDUAL = 0,  // T = X X : writes N = I - T, partial ||N||_F^2 per tile
+  GEMM_UPDATE = 1     // P = X N : writes X_new = X + P/2, partial trace per tile
+};
+
+// FP64 / FP32 products on 16x16x4 MFMA.  Matrices are dp x dp, leading
+// dimension ld, dp a multiple of 128.  tiles holds (I, J), I <= J, in units
+// of 128; partials receives one FP64 value per tile.
+hipError_t launch_sym_gemm_f64(int mode, const double* A, const double* B, const double* Xold,
+                               double* out, int ld, int d, int dp, const int2* tiles, int ntiles,
+                               double* partials, hipStream_t st);
+hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const float* Xold,
+                               float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
+                               double* partials, hipStream_t st);
+
+// Products of matrices held as W BF16 words per entry (planes ps elements
+// apart), FP32 accumulation on 32x32x16 BF16 MFMA.  Word products kept:
+// W=1 {00}; W=2 {00,01,10}; W=3 {00,01,10,02,11,20}.
+hipError_t launch_sym_gemm_words(int words, int mode, const uint16_t* A, const uint16_t* B,
+                                 const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d,
+                                 int dp, const int2* tiles, int ntiles, double* partials,
+                                 hipStream_t st);
+
+// ---- set-up: H (upper triangle) -> padded full FP64 copy, scale, X_0 ----
+hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, int dp,
+                               hipStream_t st);
+// scal[SC_ALPHA] = max_i sum_j |Hf_ij - s delta_ij| (only if scale_given == 0,
+// else scal[SC_ALPHA] = alpha_given); scal[SC_NONFINITE] = count of non-finite.
+hipError_t launch_scale_inf(const double* Hf, int dp, int d, double s, int scale_given,
+                            double alpha_given, double* rowsum, double* scal, hipStream_t st);
+// X_0 = (Hf - sI)/scal[SC_ALPHA] into FP64, FP32 or W-word storage; partial
+// traces per 256-row block into partials (nblk = dp/256 rounded up).
+hipError_t launch_init_x0_f64(const double* Hf, int dp, int d, double s, const double* scal,
+                              double* X, hipStream_t st);
+hipError_t launch_init_x0_f32(const double* Hf, int dp, int d, double s, const double* scal,
+                              float* X, hipStream_t st);
+hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, double s,
+                                const double* scal, uint16_t* X, int64_t ps, hipStream_t st);
+// FP32 copy of H - sI (the operator of the inner solves).
+hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* Hs,
+                              hipStream_t st);
+// dst[slot] = sum of partials[0..n) in a fixed order.
+hipError_t launch_reduce_sum(const double* partials, int n, double* scal, int slot,
+                             hipStream_t st);
+// trace of an FP64/FP32/word matrix (diagonal sum) into scal[slot].
+hipError_t launch_trace_f64(const double* X, int dp, int d, double* scal, int slot,
+                            hipStream_t st);
+hipError_t launch_trace_f32(const float* X, int dp, int d, double* scal, int slot,
+                            hipStream_t st);
+hipError_t launch_trace_words(int words, const uint16_t* X, int64_t ps, int dp, int d,
+                              double* scal, int slot, hipStream_t st);
+
+// R (d x d, ldr) from an FP64 / FP32 iterate.
+hipError_t launch_copy_out_f64(const double* X, int dp, int d, double* R, int64_t ldr,
+                               hipStream_t st);
+hipError_t launch_copy_out_f32(const float* X, int dp, int d, double* R, int64_t ldr,
+                               hipStream_t st);
+
+// R (d x d, ldr) = sum of the words of a W-word iterate.
+hipError_t launch_copy_out_words(int words, const uint16_t* X, int64_t ps, int dp, int d,
+                                 double* R, int64_t ldr, hipStream_t st);
+
+// ---- thin products and block-vector kernels (FP64 vectors, column-major) ----
+// Y[:, c] = M V[:, c], c < nb <= 32.  work: thin_work_doubles(d) doubles.
+size_t thin_work_doubles(int d);
+hipError_t thin_gemm_f64(const double* M, int64_t ldm, int d, const double* V, int64_t ldv, int nb,
+                         double* Y, int64_t ldy, double* work, hipStream_t st);
+hipError_t thin_gemm_f32(const float* M, int64_t ldm, int d, const double* V, int64_t ldv, int nb,
+                         double* Y, int64_t ldy, double* work, hipStream_t st);
+hipError_t thin_gemm_words(int words, const uint16_t* X, int ld, int64_t ps, int d,
+                           const double* V, int64_t ldv, int nb, double* Y, int64_t ldy,
+                           double* work, hipStream_t st);
+// G (na x nb, column-major) = A^T B; work: gram_work_doubles(d) doubles.
+size_t gram_work_doubles(int d);
+hipError_t gram(const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int d,
+                double* G, double* work, hipStream_t st);
+// Y = alpha Y + beta A C  (A: d x na, C: na x nb column-major, Y must not alias A).
+hipError_t block_axpy(int d, int na, int nb, double alpha, double* Y, int64_t ldy, double beta,
+                      const double* A, int64_t lda, const double* C, hipStream_t st);
+// Y[:, c] += coef[c] X[:, c]  (coef on the device).
+hipError_t col_axpy(int d, int nb, double* Y, int64_t ldy, const double* coef, const double* X,
+                    int64_t ldx, hipStream_t st);
+// Y = a X + b Y (d x nb blocks).
+hipError_t lincomb(int d, int nb, double a, const double* X, int64_t ldx, double b, double* Y,
+                   int64_t ldy, hipStream_t st);
+// R = I - 2 V V^T (d x d, ldr).
+hipError_t form_reflector(const double* V, int64_t ldv, int k, int d, double* R, int64_t ldr,
+                          hipStream_t st);
+// V[:, c] uniform in (-1, 1) from a counter-based hash of (seed, c, row).
+hipError_t random_block(double* V, int64_t ldv, int d, int nb, uint64_t seed, hipStream_t st);
+
+// ---- block CG (see misc.hip) ----
+struct CgHost {
+  double theta[32], rho[32], rho0[32], alpha[32], beta[32];
+  double C[32 * 32];
+  double tol2;
+  int iters, done, k, nb;
+  unsigned int counter[2];
+};
+size_t cg_state_bytes();
+size_t cg_part_doubles(int d);
+hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const double* V, int64_t ldv,
+                        double* Rr, const double* Pold, double* Pnext, double* AP, double* Z,
+                        void* state, double* work, double* part, int max_iter, hipStream_t st);
+
+}  // namespace refl

@@ -1,0 +1,791 @@
+// Memory-bound kernels around the Newton-Schulz products: set-up of the
+// scaled iterate (section 3.2 eq. NS with the inf-norm scaling of section
+// 4.3), reductions, output, and the thin products and block-vector updates
+// of the FP64 subspace correction and of block Lanczos.
+#include "common.h"
+#include "launch.h"
+
+namespace refl {
+
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// ----------------------------------------------------------------- set-up
+// Hf (dp x dp, ld dp) = symmetric matrix whose upper triangle is that of H,
+// zero outside the leading d x d block.  Block (bx, by) handles the 64 x 64
+// tile (I, J) = (by, bx); tiles with I > J are written by their mirror.
+__global__ __launch_bounds__(256) void k_mirror_upper(const double* __restrict__ H, int64_t ldh,
+                                                      int d, double* __restrict__ Hf, int dp) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ double t[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i0 = I * 64, j0 = J * 64;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    double v = 0.0;
+    if (i < d && j < d && i <= j) v = H[(int64_t)i * ldh + j];
+    t[r][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    // Diagonal tile: lower part from the upper part.
+    const double v = (I == J && r > tx) ? t[tx][r] : t[r][tx];
+    Hf[(int64_t)i * dp + j] = v;
+  }
+  if (I != J) {
+    for (int r = ty; r < 64; r += 4) Hf[(int64_t)(j0 + r) * dp + i0 + tx] = t[tx][r];
+  }
+}
+
+// rowsum[i] = sum_j |Hf_ij - s delta_ij|, one wave per row; counts non-finite.
+__global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ Hf, int dp, int d,
+                                                double s, double* __restrict__ rowsum,
+                                                double* __restrict__ nonfinite_rows) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= d) return;
+  const double* h = Hf + (int64_t)row * dp;
+  double acc = 0.0;
+  int bad = 0;
+  for (int j = lane; j < d; j += 64) {
+    double v = h[j];
+    if (!isfinite(v)) bad = 1;
+    if (j == row) v -= s;
+    acc += fabs(v);
+  }
+  acc = wave_sum(acc);
+  const double nb = wave_sum((double)bad);
+  if (lane == 0) {
+    rowsum[row] = acc;
+    nonfinite_rows[row] = nb;
+  }
+}
+
+// scal[SC_ALPHA] = max rowsum (or alpha_given), scal[SC_NONFINITE] = sum of flags.
+__global__ __launch_bounds__(256) void k_scale_finish(const double* __restrict__ rowsum,
+                                                      const double* __restrict__ nonfinite_rows,
+                                                      int d, int scale_given, double alpha_given,
+                                                      double* __restrict__ scal) {
+  __shared__ double red[4], redb[4];
+  double m = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    m = fmax(m, rowsum[i]);
+    b += nonfinite_rows[i];
+  }
+  m = wave_max(m);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+    red[w] = m;
+    redb[w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    scal[SC_ALPHA] = scale_given ? alpha_given : mx;
+    scal[SC_NONFINITE] = (redb[0] + redb[1]) + (redb[2] + redb[3]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_x0(const double* __restrict__ Hf, int dp, int d,
+                                                 double s, const double* __restrict__ scal,
+                                                 T* __restrict__ X) {
+  const int64_t n = (int64_t)dp * dp;
+  const double inv = 1.0 / scal[SC_ALPHA];
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx / dp), j = (int)(idx % dp);
+    double v = Hf[idx];
+    if (i == j && i < d) v -= s;
+    X[idx] = (T)(v * inv);
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_init_x0_w(const double* __restrict__ Hf, int dp, int d,
+                                                   double s, const double* __restrict__ scal,
+                                                   uint16_t* __restrict__ X, int64_t ps) {
+  const int64_t n = (int64_t)dp * dp;
+  const double inv = 1.0 / scal[SC_ALPHA];
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx / dp), j = (int)(idx % dp);
+    double v = Hf[idx];
+    if (i == j && i < d) v -= s;
+    uint16_t w[W];
+    split_words<W>((float)(v * inv), w);
+#pragma unroll
+    for (int q = 0; q < W; ++q) X[q * ps + idx] = w[q];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_shifted_f32(const double* __restrict__ Hf, int dp, int d,
+                                                     double s, float* __restrict__ Hs) {
+  const int64_t n = (int64_t)dp * dp;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * 256) {
+    const int i = (int)(idx / dp), j = (int)(idx % dp);
+    double v = Hf[idx];
+    if (i == j && i < d) v -= s;
+    Hs[idx] = (float)v;
+  }
+}
+
+// ------------------------------------------------------------- reductions
+__global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ p, int n,
+                                                    double* __restrict__ scal, int slot) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += p[i];
+  const double t = block_sum_256(a, red);
+  if (threadIdx.x == 0) scal[slot] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trace(const T* __restrict__ X, int dp, int d,
+                                               double* __restrict__ scal, int slot) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) a += (double)X[(int64_t)i * dp + i];
+  const double t = block_sum_256(a, red);
+  if (threadIdx.x == 0) scal[slot] = t;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_trace_w(const uint16_t* __restrict__ X, int64_t ps,
+                                                 int dp, int d, double* __restrict__ scal,
+                                                 int slot) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    float x = 0.f;
+#pragma unroll
+    for (int q = 0; q < W; ++q) x += bf16_to_f32(X[q * ps + (int64_t)i * dp + i]);
+    a += (double)x;
+  }
+  const double t = block_sum_256(a, red);
+  if (threadIdx.x == 0) scal[slot] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_out(const T* __restrict__ X, int dp, int d,
+                                                  double* __restrict__ R, int64_t ldr) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < d; j += gridDim.x * 256)
+    R[(int64_t)i * ldr + j] = (double)X[(int64_t)i * dp + j];
+}
+
+// ------------------------------------------------------- thin products
+// Y (d x nb, column-major) = M V.  Grid (row groups of 64, column chunks of
+// CH); each wave owns 16 rows.  A lane keeps V[j, 0..NB) for the CH/64
+// columns j it reads in registers, multiplies them into one row at a time
+// (row-contiguous, coalesced), and the wave sums its lanes.  Per-chunk
+// partial sums go to work[chunk][c][row]; k_thin_finish adds the chunks in
+// a fixed order.
+template <typename MT>
+struct MLoad {
+  static __device__ __forceinline__ double at(const MT* M, int64_t idx, int64_t) {
+    return (double)M[idx];
+  }
+};
+template <int W>
+struct WordsM {};
+template <int W>
+struct MLoad<WordsM<W>> {
+  static __device__ __forceinline__ double at(const WordsM<W>* M, int64_t idx, int64_t ps) {
+    const uint16_t* m = reinterpret_cast<const uint16_t*>(M);
+    float x = 0.f;
+#pragma unroll
+    for (int q = 0; q < W; ++q) x += bf16_to_f32(m[q * ps + idx]);
+    return (double)x;
+  }
+};
+
+template <typename MT, int NB, int CH>
+__global__ __launch_bounds__(256) void k_thin_partial(const MT* __restrict__ M, int64_t ldm,
+                                                      int64_t ps, int d, const double* __restrict__ V,
+                                                      int64_t ldv, int nb, double* __restrict__ work,
+                                                      int64_t wld) {
+  constexpr int PER = CH / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.y * CH;
+  double v[PER][NB];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int j = j0 + t * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[t][c] = (j < d && c < nb) ? V[(int64_t)c * ldv + j] : 0.0;
+  }
+  const int rbeg = blockIdx.x * 64 + wave * 16;
+  for (int rr = 0; rr < 16; ++rr) {
+    const int row = rbeg + rr;
+    if (row >= d) break;
+    double acc[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = j0 + t * 64 + lane;
+      const double m = (j < d) ? MLoad<MT>::at(M, (int64_t)row * ldm + j, ps) : 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = fma(m, v[t][c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double s = wave_sum(acc[c]);
+      if (lane == 0 && c < nb) work[((int64_t)blockIdx.y * NB + c) * wld + row] = s;
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_thin_finish(const double* __restrict__ work, int64_t wld,
+                                                     int nchunk, int d, int nb,
+                                                     double* __restrict__ Y, int64_t ldy) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (row >= d || c >= nb) return;
+  double s = 0.0;
+  for (int q = 0; q < nchunk; ++q) s += work[((int64_t)q * NB + c) * wld + row];
+  Y[(int64_t)c * ldy + row] = s;
+}
+
+
+// ---------------------------------------------------- block-vector kernels
+// work[block][i + na*j] = sum over the block's 64 rows of A[r, i] B[r, j].
+__global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__ A, int64_t lda,
+                                                      int na, const double* __restrict__ B,
+                                                      int64_t ldb, int nb, int d,
+                                                      double* __restrict__ work) {
+  __shared__ double sa[64][33], sb[64][33];
+  const int r0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    const int row = r0 + r;
+    sa[r][c] = (row < d && c < na) ? A[(int64_t)c * lda + row] : 0.0;
+    sb[r][c] = (row < d && c < nb) ? B[(int64_t)c * ldb + row] : 0.0;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < na * nb; o += 256) {
+    const int i = o % na, j = o / na;
+    double acc = 0.0;
+    for (int r = 0; r < 64; ++r) acc = fma(sa[r][i], sb[r][j], acc);
+    work[(int64_t)blockIdx.x * na * nb + o] = acc;
+  }
+}
+__global__ __launch_bounds__(256) void k_gram_finish(const double* __restrict__ work, int nblk,
+                                                     int n, double* __restrict__ G) {
+  for (int o = blockIdx.x * 256 + threadIdx.x; o < n; o += gridDim.x * 256) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += work[(int64_t)b * n + o];
+    G[o] = s;
+  }
+}
+
+// Y[:, c] = alpha Y[:, c] + beta sum_i A[:, i] C[i, c]
+__global__ __launch_bounds__(256) void k_block_axpy(int d, int na, int nb, double alpha,
+                                                    double* __restrict__ Y, int64_t ldy,
+                                                    double beta, const double* __restrict__ A,
+                                                    int64_t lda, const double* __restrict__ C) {
+  __shared__ double sc[32 * 32];
+  for (int e = threadIdx.x; e < na * nb; e += 256) sc[e] = C[e];
+  __syncthreads();
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= d) return;
+  double a[32];
+  for (int i = 0; i < na; ++i) a[i] = A[(int64_t)i * lda + row];
+  for (int c = 0; c < nb; ++c) {
+    double acc = 0.0;
+    for (int i = 0; i < na; ++i) acc = fma(a[i], sc[i + na * c], acc);
+    double* y = Y + (int64_t)c * ldy + row;
+    *y = (alpha == 0.0 ? 0.0 : alpha * *y) + beta * acc;
+  }
+}
+
+// Y[:, c] *= 1 (columns c >= ncol zeroed) -- and per-column scale: Y[:, c] = Y[:, c] - sh[c] V[:, c]
+__global__ __launch_bounds__(256) void k_col_axpy(int d, int nb, double* __restrict__ Y, int64_t ldy,
+                                                  const double* __restrict__ coef,
+                                                  const double* __restrict__ X, int64_t ldx) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= d) return;
+  for (int c = 0; c < nb; ++c) Y[(int64_t)c * ldy + row] += coef[c] * X[(int64_t)c * ldx + row];
+}
+
+// R = I - 2 V V^T on the d x d block (ldr), 64 x 64 tiles.
+__global__ __launch_bounds__(256) void k_form_reflector(const double* __restrict__ V, int64_t ldv,
+                                                        int k, int d, double* __restrict__ R,
+                                                        int64_t ldr) {
+  __shared__ double vi[64][33], vj[64][33];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    vi[r][c] = (i0 + r < d && c < k) ? V[(int64_t)c * ldv + i0 + r] : 0.0;
+    vj[r][c] = (j0 + r < d && c < k) ? V[(int64_t)c * ldv + j0 + r] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i >= d || j >= d) continue;
+    double acc = 0.0;
+    for (int c = 0; c < k; ++c) acc = fma(vi[r][c], vj[tx][c], acc);
+    R[(int64_t)i * ldr + j] = (i == j ? 1.0 : 0.0) - 2.0 * acc;
+  }
+}
+
+// Seeded start block: V[j + c ldv] uniform in (-1, 1) from splitmix64.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__global__ __launch_bounds__(256) void k_random_block(double* __restrict__ V, int64_t ldv, int d,
+                                                      int nb, uint64_t seed) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= d) return;
+  for (int c = 0; c < nb; ++c) {
+    const uint64_t h = splitmix64(seed * 0x100000001B3ull + (uint64_t)c * (uint64_t)d + row);
+    V[(int64_t)c * ldv + row] = ((double)(h >> 11) * 0x1.0p-53) * 2.0 - 1.0;
+  }
+}
+
+// ------------------------------------------------------------ block CG
+// Solves, column by column (c < nb), the projected correction equations
+//   (I - V V^T)(H - theta_c I)(I - V V^T) z_c = b_c,  z_c, b_c orthogonal to V,
+// by conjugate gradients (the operator is positive definite on the
+// complement of V when theta_c lies below the spectrum there).  One
+// iteration = k_thin_partial on P (formed on the fly as Rr + beta P_old),
+// k_cg_apply (operator finish, projection coefficients, alpha), k_cg_update
+// (z, r updates, beta, convergence).  Per-column scalars live in CgState.
+// Each kernel returns at once when state->done is set, so a batch of
+// iterations can be enqueued without host synchronisation.
+struct CgState {
+  double theta[32], rho[32], rho0[32], alpha[32], beta[32];
+  double C[32 * 32];      // V^T (H - theta) p, k x nb column-major
+  double tol2;
+  int iters, done, k, nb;
+  unsigned int counter[2];
+};
+
+template <int NB, int CH>
+__global__ __launch_bounds__(256) void k_cg_thin(const double* __restrict__ M, int64_t ldm, int d,
+                                                 const double* __restrict__ Rr,
+                                                 const double* __restrict__ Pold, int64_t ldv,
+                                                 const CgState* __restrict__ st,
+                                                 double* __restrict__ work, int64_t wld) {
+  if (st->done) return;
+  constexpr int PER = CH / 64;
+  const int nb = st->nb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j0 = blockIdx.y * CH;
+  double v[PER][NB];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int j = j0 + t * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      v[t][c] = (j < d && c < nb)
+                    ? Rr[(int64_t)c * ldv + j] + st->beta[c] * Pold[(int64_t)c * ldv + j]
+                    : 0.0;
+  }
+  const int rbeg = blockIdx.x * 64 + wave * 16;
+  for (int rr = 0; rr < 16; ++rr) {
+    const int row = rbeg + rr;
+    if (row >= d) break;
+    double acc[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = j0 + t * 64 + lane;
+      const double m = (j < d) ? M[(int64_t)row * ldm + j] : 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = fma(m, v[t][c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double s = wave_sum(acc[c]);
+      if (lane == 0 && c < nb) work[((int64_t)blockIdx.y * NB + c) * wld + row] = s;
+    }
+  }
+}
+
+// AP = M P - theta P; P_next = P; partial V^T AP and P . AP; last block: C, alpha.
+template <int NB>
+__global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ work, int64_t wld,
+                                                  int nchunk, int d, const double* __restrict__ V,
+                                                  const double* __restrict__ Rr,
+                                                  const double* __restrict__ Pold,
+                                                  double* __restrict__ Pnext,
+                                                  double* __restrict__ AP, int64_t ldv,
+                                                  CgState* __restrict__ st,
+                                                  double* __restrict__ part) {
+  if (st->done) return;
+  const int nb = st->nb, k = st->k;
+  const int nout = k * nb + nb;
+  __shared__ double sred[256 / 64][32 * 32 + 32];
+  __shared__ bool last;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double p[NB], ap[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    p[c] = 0.0;
+    ap[c] = 0.0;
+  }
+  if (row < d) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c >= nb) break;
+      const double pc = Rr[(int64_t)c * ldv + row] + st->beta[c] * Pold[(int64_t)c * ldv + row];
+      double s = 0.0;
+      for (int q = 0; q < nchunk; ++q) s += work[((int64_t)q * NB + c) * wld + row];
+      s -= st->theta[c] * pc;
+      p[c] = pc;
+      ap[c] = s;
+      Pnext[(int64_t)c * ldv + row] = pc;
+      AP[(int64_t)c * ldv + row] = s;
+    }
+  }
+  // Partials: V^T AP (k x nb) then P . AP (nb).
+  for (int i = 0; i < k; ++i) {
+    const double vi = (row < d) ? V[(int64_t)i * ldv + row] : 0.0;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c >= nb) break;
+      const double s = wave_sum(vi * ap[c]);
+      if (lane == 0) sred[wave][i + k * c] = s;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c >= nb) break;
+    const double s = wave_sum(p[c] * ap[c]);
+    if (lane == 0) sred[wave][k * nb + c] = s;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += 256)
+    part[(int64_t)blockIdx.x * nout + o] = (sred[0][o] + sred[1][o]) + (sred[2][o] + sred[3][o]);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&st->counter[0], 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int o = threadIdx.x; o < nout; o += 256) {
+    double s = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) s += part[(int64_t)b * nout + o];
+    if (o < k * nb)
+      st->C[o] = s;
+    else {
+      const int c = o - k * nb;
+      st->alpha[c] = (s != 0.0) ? st->rho[c] / s : 0.0;
+    }
+  }
+  if (threadIdx.x == 0) st->counter[0] = 0u;
+}
+
+// z += alpha p; r -= alpha (AP - V C); partial |r|^2; last block: beta, done.
+template <int NB>
+__global__ __launch_bounds__(256) void k_cg_update(int d, const double* __restrict__ V,
+                                                   const double* __restrict__ P,
+                                                   const double* __restrict__ AP,
+                                                   double* __restrict__ Z, double* __restrict__ Rr,
+                                                   int64_t ldv, CgState* __restrict__ st,
+                                                   double* __restrict__ part, int max_iter) {
+  if (st->done) return;
+  const int nb = st->nb, k = st->k;
+  __shared__ double sred[4][32];
+  __shared__ bool last;
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double rr[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) rr[c] = 0.0;
+  if (row < d) {
+    double vrow[32];
+    for (int i = 0; i < k; ++i) vrow[i] = V[(int64_t)i * ldv + row];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      if (c >= nb) break;
+      double proj = 0.0;
+      for (int i = 0; i < k; ++i) proj = fma(vrow[i], st->C[i + k * c], proj);
+      const int64_t o = (int64_t)c * ldv + row;
+      const double a = st->alpha[c];
+      Z[o] = fma(a, P[o], Z[o]);
+      const double r = Rr[o] - a * (AP[o] - proj);
+      Rr[o] = r;
+      rr[c] = r * r;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c >= nb) break;
+    const double s = wave_sum(rr[c]);
+    if (lane == 0) sred[wave][c] = s;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nb; c += 256)
+    part[(int64_t)blockIdx.x * nb + c] = (sred[0][c] + sred[1][c]) + (sred[2][c] + sred[3][c]);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&st->counter[1], 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    int conv = 1;
+    for (int c = 0; c < nb; ++c) {
+      double s = 0.0;
+      for (int b = 0; b < (int)gridDim.x; ++b) s += part[(int64_t)b * nb + c];
+      st->beta[c] = (st->rho[c] > 0.0) ? s / st->rho[c] : 0.0;
+      st->rho[c] = s;
+      if (!(s <= st->tol2 * st->rho0[c])) conv = 0;
+    }
+    st->iters += 1;
+    if (conv || st->iters >= max_iter) st->done = 1;
+    st->counter[1] = 0u;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_copy_out_w(const uint16_t* __restrict__ X, int64_t ps,
+                                                    int dp, int d, double* __restrict__ R,
+                                                    int64_t ldr) {
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < d; j += gridDim.x * 256) {
+    float x = 0.f;
+#pragma unroll
+    for (int q = 0; q < W; ++q) x += bf16_to_f32(X[q * ps + (int64_t)i * dp + j]);
+    R[(int64_t)i * ldr + j] = (double)x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lincomb(int d, int nb, double a, const double* __restrict__ X,
+                                                 int64_t ldx, double b, double* __restrict__ Y,
+                                                 int64_t ldy) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= d) return;
+  for (int c = 0; c < nb; ++c) {
+    double* y = Y + (int64_t)c * ldy + row;
+    *y = a * X[(int64_t)c * ldx + row] + (b == 0.0 ? 0.0 : b * *y);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, int dp,
+                               hipStream_t st) {
+  const int nt = dp / 64;
+  hipLaunchKernelGGL(k_mirror_upper, dim3(nt, nt), dim3(256), 0, st, H, ldh, d, Hf, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_inf(const double* Hf, int dp, int d, double s, int scale_given,
+                            double alpha_given, double* rowsum, double* scal, hipStream_t st) {
+  double* flags = rowsum + dp;
+  hipLaunchKernelGGL(k_rowabs, dim3(nblocks(d, 4)), dim3(256), 0, st, Hf, dp, d, s, rowsum, flags);
+  hipLaunchKernelGGL(k_scale_finish, dim3(1), dim3(256), 0, st, rowsum, flags, d, scale_given,
+                     alpha_given, scal);
+  return hipGetLastError();
+}
+
+static int grid_elems(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b > 65536 ? 65536 : b);
+}
+
+hipError_t launch_init_x0_f64(const double* Hf, int dp, int d, double s, const double* scal,
+                              double* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_x0<double>, dim3(grid_elems((int64_t)dp * dp)), dim3(256), 0, st, Hf,
+                     dp, d, s, scal, X);
+  return hipGetLastError();
+}
+hipError_t launch_init_x0_f32(const double* Hf, int dp, int d, double s, const double* scal,
+                              float* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_x0<float>, dim3(grid_elems((int64_t)dp * dp)), dim3(256), 0, st, Hf,
+                     dp, d, s, scal, X);
+  return hipGetLastError();
+}
+hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, double s,
+                                const double* scal, uint16_t* X, int64_t ps, hipStream_t st) {
+  const dim3 g(grid_elems((int64_t)dp * dp));
+  switch (words) {
+    case 1: hipLaunchKernelGGL(k_init_x0_w<1>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps); break;
+    case 2: hipLaunchKernelGGL(k_init_x0_w<2>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps); break;
+    case 3: hipLaunchKernelGGL(k_init_x0_w<3>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* Hs,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_shifted_f32, dim3(grid_elems((int64_t)dp * dp)), dim3(256), 0, st, Hf, dp,
+                     d, s, Hs);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_sum(const double* partials, int n, double* scal, int slot,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partials, n, scal, slot);
+  return hipGetLastError();
+}
+hipError_t launch_trace_f64(const double* X, int dp, int d, double* scal, int slot,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_trace<double>, dim3(1), dim3(256), 0, st, X, dp, d, scal, slot);
+  return hipGetLastError();
+}
+hipError_t launch_trace_f32(const float* X, int dp, int d, double* scal, int slot,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_trace<float>, dim3(1), dim3(256), 0, st, X, dp, d, scal, slot);
+  return hipGetLastError();
+}
+hipError_t launch_trace_words(int words, const uint16_t* X, int64_t ps, int dp, int d,
+                              double* scal, int slot, hipStream_t st) {
+  switch (words) {
+    case 1: hipLaunchKernelGGL(k_trace_w<1>, dim3(1), dim3(256), 0, st, X, ps, dp, d, scal, slot); break;
+    case 2: hipLaunchKernelGGL(k_trace_w<2>, dim3(1), dim3(256), 0, st, X, ps, dp, d, scal, slot); break;
+    case 3: hipLaunchKernelGGL(k_trace_w<3>, dim3(1), dim3(256), 0, st, X, ps, dp, d, scal, slot); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_copy_out_f64(const double* X, int dp, int d, double* R, int64_t ldr,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_out<double>, dim3(nblocks(d, 256), d), dim3(256), 0, st, X, dp, d, R, ldr);
+  return hipGetLastError();
+}
+hipError_t launch_copy_out_f32(const float* X, int dp, int d, double* R, int64_t ldr,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_out<float>, dim3(nblocks(d, 256), d), dim3(256), 0, st, X, dp, d, R, ldr);
+  return hipGetLastError();
+}
+
+// Thin products: column chunk CH = 256 for up to 16 columns, 128 above.
+template <typename MT>
+static hipError_t thin_dispatch(const MT* M, int64_t ldm, int64_t ps, int d, const double* V,
+                                int64_t ldv, int nb, double* Y, int64_t ldy, double* work,
+                                hipStream_t st) {
+  const int64_t wld = d;
+  const int rows = nblocks(d, 64);
+#define REFL_THIN(NBV, CHV)                                                                      \
+  {                                                                                              \
+    const int nch = nblocks(d, CHV);                                                             \
+    hipLaunchKernelGGL((k_thin_partial<MT, NBV, CHV>), dim3(rows, nch), dim3(256), 0, st, M, ldm, \
+                       ps, d, V, ldv, nb, work, wld);                                            \
+    hipLaunchKernelGGL((k_thin_finish<NBV>), dim3(nblocks(d, 256), nb), dim3(256), 0, st, work,  \
+                       wld, nch, d, nb, Y, ldy);                                                 \
+  }
+  if (nb <= 0) return hipSuccess;
+  if (nb <= 1) REFL_THIN(1, 512)
+  else if (nb <= 4) REFL_THIN(4, 256)
+  else if (nb <= 8) REFL_THIN(8, 256)
+  else if (nb <= 16) REFL_THIN(16, 256)
+  else if (nb <= 32) REFL_THIN(32, 128)
+  else return hipErrorInvalidValue;
+#undef REFL_THIN
+  return hipGetLastError();
+}
+
+hipError_t thin_gemm_f64(const double* M, int64_t ldm, int d, const double* V, int64_t ldv, int nb,
+                         double* Y, int64_t ldy, double* work, hipStream_t st) {
+  return thin_dispatch<double>(M, ldm, 0, d, V, ldv, nb, Y, ldy, work, st);
+}
+hipError_t thin_gemm_f32(const float* M, int64_t ldm, int d, const double* V, int64_t ldv, int nb,
+                         double* Y, int64_t ldy, double* work, hipStream_t st) {
+  return thin_dispatch<float>(M, ldm, 0, d, V, ldv, nb, Y, ldy, work, st);
+}
+hipError_t thin_gemm_words(int words, const uint16_t* X, int ld, int64_t ps, int d,
+                           const double* V, int64_t ldv, int nb, double* Y, int64_t ldy,
+                           double* work, hipStream_t st) {
+  switch (words) {
+    case 1: return thin_dispatch<WordsM<1>>(reinterpret_cast<const WordsM<1>*>(X), ld, ps, d, V, ldv, nb, Y, ldy, work, st);
+    case 2: return thin_dispatch<WordsM<2>>(reinterpret_cast<const WordsM<2>*>(X), ld, ps, d, V, ldv, nb, Y, ldy, work, st);
+    case 3: return thin_dispatch<WordsM<3>>(reinterpret_cast<const WordsM<3>*>(X), ld, ps, d, V, ldv, nb, Y, ldy, work, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_copy_out_words(int words, const uint16_t* X, int64_t ps, int dp, int d,
+                                 double* R, int64_t ldr, hipStream_t st) {
+  const dim3 g(nblocks(d, 256), d);
+  switch (words) {
+    case 1: hipLaunchKernelGGL(k_copy_out_w<1>, g, dim3(256), 0, st, X, ps, dp, d, R, ldr); break;
+    case 2: hipLaunchKernelGGL(k_copy_out_w<2>, g, dim3(256), 0, st, X, ps, dp, d, R, ldr); break;
+    case 3: hipLaunchKernelGGL(k_copy_out_w<3>, g, dim3(256), 0, st, X, ps, dp, d, R, ldr); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t lincomb(int d, int nb, double a, const double* X, int64_t ldx, double b, double* Y,
+                   int64_t ldy, hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb, dim3(nblocks(d, 256)), dim3(256), 0, st, d, nb, a, X, ldx, b, Y, ldy);
+  return hipGetLastError();
+}
+hipError_t gram(const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int d,
+                double* G, double* work, hipStream_t st) {
+  const int nblk = nblocks(d, 64);
+  hipLaunchKernelGGL(k_gram_partial, dim3(nblk), dim3(256), 0, st, A, lda, na, B, ldb, nb, d, work);
+  hipLaunchKernelGGL(k_gram_finish, dim3(nblocks(na * nb, 256)), dim3(256), 0, st, work, nblk,
+                     na * nb, G);
+  return hipGetLastError();
+}
+hipError_t block_axpy(int d, int na, int nb, double alpha, double* Y, int64_t ldy, double beta,
+                      const double* A, int64_t lda, const double* C, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_axpy, dim3(nblocks(d, 256)), dim3(256), 0, st, d, na, nb, alpha, Y,
+                     ldy, beta, A, lda, C);
+  return hipGetLastError();
+}
+hipError_t col_axpy(int d, int nb, double* Y, int64_t ldy, const double* coef, const double* X,
+                    int64_t ldx, hipStream_t st) {
+  hipLaunchKernelGGL(k_col_axpy, dim3(nblocks(d, 256)), dim3(256), 0, st, d, nb, Y, ldy, coef, X, ldx);
+  return hipGetLastError();
+}
+hipError_t form_reflector(const double* V, int64_t ldv, int k, int d, double* R, int64_t ldr,
+                          hipStream_t st) {
+  const int nt = nblocks(d, 64);
+  hipLaunchKernelGGL(k_form_reflector, dim3(nt, nt), dim3(256), 0, st, V, ldv, k, d, R, ldr);
+  return hipGetLastError();
+}
+hipError_t random_block(double* V, int64_t ldv, int d, int nb, uint64_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_random_block, dim3(nblocks(d, 256)), dim3(256), 0, st, V, ldv, d, nb, seed);
+  return hipGetLastError();
+}
+
+size_t cg_state_bytes() {
+  static_assert(sizeof(CgState) == sizeof(CgHost), "CgState and CgHost must match");
+  return sizeof(CgState);
+}
+size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 256) * (32 * 32 + 32); }
+size_t thin_work_doubles(int d) { return (size_t)nblocks(d, 128) * 32 * (size_t)d; }
+size_t gram_work_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 32; }
+
+// One CG iteration (three launches).  Pold/Pnext alternate between calls.
+hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const double* V, int64_t ldv,
+                        double* Rr, const double* Pold, double* Pnext, double* AP, double* Z,
+                        void* state, double* work, double* part, int max_iter, hipStream_t st) {
+  CgState* s = reinterpret_cast<CgState*>(state);
+  const int64_t wld = d;
+  const int rows = nblocks(d, 64), nrb = nblocks(d, 256);
+#define REFL_CG(NBV, CHV)                                                                        \
+  {                                                                                              \
+    const int nch = nblocks(d, CHV);                                                             \
+    hipLaunchKernelGGL((k_cg_thin<NBV, CHV>), dim3(rows, nch), dim3(256), 0, st, M, ldm, d, Rr,   \
+                       Pold, ldv, s, work, wld);                                                 \
+    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb), dim3(256), 0, st, work, wld, nch, d, V, Rr,  \
+                       Pold, Pnext, AP, ldv, s, part);                                           \
+    hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrb), dim3(256), 0, st, d, V, Pnext, AP, Z, Rr,   \
+                       ldv, s, part, max_iter);                                                  \
+  }
+  if (nb <= 4) REFL_CG(4, 256)
+  else if (nb <= 8) REFL_CG(8, 256)
+  else if (nb <= 16) REFL_CG(16, 256)
+  else if (nb <= 32) REFL_CG(32, 128)
+  else return hipErrorInvalidValue;
+#undef REFL_CG
+  return hipGetLastError();
+}
+
+}  // namespace refl

@@ -1,0 +1,718 @@
+// C-ABI of the reflector library (include/refl.h): argument checks,
+// workspace layout, and the host-side sequencing of the kernels.
+//
+// refl_sign, all precisions:
+//   set-up  H upper triangle -> padded symmetric FP64 copy Hf; alpha =
+//           ||H - sI||_inf (section 4.3) unless given; X_0 = (H - sI)/alpha
+//           in the bulk storage (FP64, FP32 or BF16 words).
+//   bulk    Newton-Schulz steps X <- X (3I - X^2)/2 (eq. NS), each two
+//           symmetric MFMA products with fused epilogues; after the first
+//           product of every step the host reads ||X^2 - I||_F and trace X
+//           (one 16-byte copy) and applies the stopping rule.
+//   output  FP64/FP32: R = the last iterate.  MIXED: an FP64 correction of
+//           the target eigenspace that uses H itself (subspace extraction
+//           from (I - X)/2, Rayleigh-Ritz, projected CG correction sweeps),
+//           then R = I - 2 V V^T and the Davis-Kahan certificate.
+//
+// Index certificate (used by every path): for symmetric X with
+// b = sqrt(d) ||X^2 - I||_F < 1, the number j of negative eigenvalues of X
+// satisfies |trace X - (d - 2j)| <= b, so j is the integer nearest to
+// (d - trace X)/2 whenever that distance is below 1/2 ... more precisely j
+// is the unique integer with |trace X - (d - 2j)| < 1.  Sign preservation
+// of the Newton-Schulz polynomials (Lemma 3.4) makes j the inertia of
+// H - sI when the iterate is accurate.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "../../include/refl.h"
+#include "common.h"
+#include "hostla.h"
+#include "launch.h"
+
+using namespace refl;
+
+struct refl_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* ws_user = nullptr;
+  size_t ws_user_bytes = 0;
+  void* ws_own = nullptr;
+  size_t ws_own_bytes = 0;
+  double* pinned = nullptr;  // host pinned scalars (SC_COUNT doubles + CG state)
+  char err[512] = {0};
+};
+
+namespace {
+
+constexpr double NaN = std::numeric_limits<double>::quiet_NaN();
+
+refl_status_t fail(refl_handle_t h, refl_status_t st, const char* fmt, ...) {
+  if (h) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(h->err, sizeof(h->err), fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(h, REFL_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Bump allocator over one device allocation (256-byte aligned pieces).
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+constexpr int MAXB = 32;  // widest block of vectors
+
+struct Work {
+  int d, dp, ntiles, words;
+  int64_t ps;  // plane stride (elements) of word storage
+  double* Hf;
+  double* scal;
+  double* rowsum;
+  double* partials;
+  int2* tiles;
+  // bulk (only the ones of the precision are non-null)
+  double *X64[2], *N64;
+  float *X32[2], *N32;
+  uint16_t *Xw[2], *Nw;
+  // block vectors (ld = dp), polish and apply
+  double *V, *W, *Z, *Rr, *P[2], *AP, *T1, *T2, *G, *thin, *gwork, *cgpart;
+  void* cgstate;
+};
+
+size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, bool for_apply) {
+  Carve c(base);
+  w.d = (int)d;
+  w.dp = (int)round_up(d, TILE);
+  const int64_t dp = w.dp, n2 = dp * dp;
+  const int nt = w.dp / TILE;
+  w.ntiles = nt * (nt + 1) / 2;
+  w.words = p.words;
+  w.ps = n2;
+  w.scal = c.take<double>(SC_COUNT);
+  w.tiles = c.take<int2>(w.ntiles);
+  w.partials = c.take<double>(w.ntiles);
+  w.rowsum = c.take<double>(2 * dp);
+  w.X64[0] = w.X64[1] = w.N64 = nullptr;
+  w.X32[0] = w.X32[1] = w.N32 = nullptr;
+  w.Xw[0] = w.Xw[1] = w.Nw = nullptr;
+  if (!for_apply) {
+    w.Hf = c.take<double>(n2);
+    if (p.precision == REFL_PREC_FP64) {
+      w.X64[0] = c.take<double>(n2);
+      w.X64[1] = c.take<double>(n2);
+      w.N64 = c.take<double>(n2);
+    } else if (p.precision == REFL_PREC_FP32) {
+      w.X32[0] = c.take<float>(n2);
+      w.X32[1] = c.take<float>(n2);
+      w.N32 = c.take<float>(n2);
+    } else {
+      const int W = p.words;
+      w.Xw[0] = c.take<uint16_t>(W * n2);
+      w.Xw[1] = c.take<uint16_t>(W * n2);
+      w.Nw = c.take<uint16_t>(W * n2);
+    }
+  } else {
+    w.Hf = nullptr;
+  }
+  w.V = c.take<double>(dp * MAXB);
+  w.W = c.take<double>(dp * MAXB);
+  w.Z = c.take<double>(dp * MAXB);
+  w.Rr = c.take<double>(dp * MAXB);
+  w.P[0] = c.take<double>(dp * MAXB);
+  w.P[1] = c.take<double>(dp * MAXB);
+  w.AP = c.take<double>(dp * MAXB);
+  w.T1 = c.take<double>(dp * MAXB);
+  w.T2 = c.take<double>(dp * MAXB);
+  w.G = c.take<double>(MAXB * MAXB * 2);
+  w.thin = c.take<double>(thin_work_doubles((int)dp));
+  w.gwork = c.take<double>(gram_work_doubles((int)dp));
+  w.cgpart = c.take<double>(cg_part_doubles((int)dp));
+  w.cgstate = c.take<char>(cg_state_bytes());
+  return c.off + 256;
+}
+
+refl_status_t ensure_workspace(refl_handle_t h, size_t need, void** out) {
+  if (h->ws_user && h->ws_user_bytes >= need) {
+    *out = h->ws_user;
+    return REFL_OK;
+  }
+  if (h->ws_own && h->ws_own_bytes >= need) {
+    *out = h->ws_own;
+    return REFL_OK;
+  }
+  if (h->ws_own) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipFree(h->ws_own));
+    h->ws_own = nullptr;
+    h->ws_own_bytes = 0;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess || !p)
+    return fail(h, REFL_ERR_NO_MEMORY, "workspace allocation of %zu bytes failed", need);
+  h->ws_own = p;
+  h->ws_own_bytes = need;
+  *out = p;
+  return REFL_OK;
+}
+
+refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
+  if (!p) return fail(h, REFL_ERR_INVALID_ARG, "params is NULL");
+  if (d < 2 || d > (int64_t)1 << 16) return fail(h, REFL_ERR_INVALID_ARG, "d=%lld outside 2..65536", (long long)d);
+  if (p->k < 1 || p->k > d - 1) return fail(h, REFL_ERR_INVALID_ARG, "k=%d outside 1..d-1", p->k);
+  if (p->precision < 0 || p->precision > 2) return fail(h, REFL_ERR_INVALID_ARG, "bad precision");
+  if (p->shift_mode != REFL_SHIFT_GIVEN && p->shift_mode != REFL_SHIFT_LANCZOS)
+    return fail(h, REFL_ERR_INVALID_ARG, "bad shift_mode");
+  if (p->scale_mode != REFL_SCALE_INF && p->scale_mode != REFL_SCALE_GIVEN)
+    return fail(h, REFL_ERR_INVALID_ARG, "bad scale_mode");
+  if (p->scale_mode == REFL_SCALE_GIVEN && !(p->alpha > 0.0 && std::isfinite(p->alpha)))
+    return fail(h, REFL_ERR_INVALID_ARG, "alpha must be finite and > 0");
+  if (p->shift_mode == REFL_SHIFT_GIVEN && !std::isfinite(p->s))
+    return fail(h, REFL_ERR_NOT_FINITE, "shift is not finite");
+  if (p->max_iter < 1) return fail(h, REFL_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (p->fixed_steps < 0) return fail(h, REFL_ERR_INVALID_ARG, "fixed_steps must be >= 0");
+  if (p->precision == REFL_PREC_MIXED) {
+    if (p->words < 1 || p->words > 3) return fail(h, REFL_ERR_INVALID_ARG, "words must be 1..3");
+    if (p->fixed_steps == 0 && p->k > MAXB)
+      return fail(h, REFL_ERR_UNSUPPORTED, "MIXED correction supports k <= %d", MAXB);
+    if (p->polish_sweeps < 0 || p->cg_max_iter < 1 || !(p->cg_tol > 0.0))
+      return fail(h, REFL_ERR_INVALID_ARG, "bad polish parameters");
+  }
+  if (!(p->tol >= 0.0)) return fail(h, REFL_ERR_INVALID_ARG, "tol must be >= 0");
+  return REFL_OK;
+}
+
+void upload_tiles(const Work& w, hipStream_t st, std::vector<int2>& host) {
+  const int nt = w.dp / TILE;
+  host.clear();
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) host.push_back(make_int2(I, J));
+}
+
+// Index certificate: returns j, or -1 if b = sqrt(d)||X^2-I||_F >= 1 or no
+// integer j has |trace - (d - 2j)| < 1.
+int index_certificate(int64_t d, double resid, double trace) {
+  const double b = std::sqrt((double)d) * resid;
+  if (!(b < 1.0)) return -1;
+  const double jr = std::nearbyint(((double)d - trace) / 2.0);
+  if (std::fabs(trace - ((double)d - 2.0 * jr)) < 1.0) return (int)jr;
+  return -1;
+}
+
+struct Bulk {
+  int steps = 0;
+  double resid = NaN, trace = NaN;
+  int cur = 0;  // which X buffer holds the last iterate
+  bool converged = false;
+};
+
+// Orthonormalise the d x nb block V (ld dp) by two rounds of Cholesky QR.
+refl_status_t orthonormalise(refl_handle_t h, Work& w, double*& V, double*& spare, int nb) {
+  std::vector<double> G(nb * nb), L(nb * nb), C(nb * nb);
+  for (int round = 0; round < 2; ++round) {
+    HIPCHK(gram(V, w.dp, nb, V, w.dp, nb, w.d, w.G, w.gwork, h->stream));
+    HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * nb * nb, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    // G column-major == row-major for a symmetric matrix.
+    if (cholesky_small(nb, G.data(), L.data()) != 0)
+      return fail(h, REFL_ERR_NOT_CONVERGED, "Cholesky QR: block lost rank");
+    inv_lower_transpose(nb, L.data(), C.data());
+    HIPCHK(hipMemcpyAsync(w.G, C.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(block_axpy(w.d, nb, nb, 0.0, spare, w.dp, 1.0, V, w.dp, w.G, h->stream));
+    std::swap(V, spare);
+  }
+  return REFL_OK;
+}
+
+// FP64 correction of the target eigenspace for the MIXED path.  On entry
+// X (words) is the bulk iterate.  On exit V (ld dp, k columns) is an
+// orthonormal basis, and *E_fro, *theta_max describe the last Rayleigh-Ritz.
+refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
+                     const uint16_t* X, double** Vout, refl_info_t* info) {
+  const int d = w.d, k = p.k;
+  const int64_t ld = w.dp;
+  hipStream_t st = h->stream;
+  double* V = w.V;
+  double* spare = w.T1;
+  HIPCHK(random_block(V, ld, d, k, p.seed ^ 0x5EEDull, st));
+  // Subspace extraction with the approximate projector (I - X)/2.
+  for (int it = 0; it < 2; ++it) {
+    HIPCHK(thin_gemm_words(w.words, X, w.dp, w.ps, d, V, ld, k, w.T2, ld, w.thin, st));
+    HIPCHK(lincomb(d, k, -0.5, w.T2, ld, 0.5, V, ld, st));  // V = (V - X V)/2
+    refl_status_t r = orthonormalise(h, w, V, spare, k);
+    if (r != REFL_OK) return r;
+  }
+  std::vector<double> G(k * k), Q(k * k), th(k), Cc(k * k), nrm(k);
+  double* Wm = w.W;
+  double* Wspare = w.T2;
+  double E_fro = NaN, theta_max = NaN, dk = NaN;
+  int sweeps = 0, cg_total = 0;
+  CgHost* hs = reinterpret_cast<CgHost*>(h->pinned + SC_COUNT);
+  while (true) {
+    // Rayleigh-Ritz on span(V) with H (FP64).
+    HIPCHK(thin_gemm_f64(w.Hf, ld, d, V, ld, k, Wm, ld, w.thin, st));
+    HIPCHK(gram(V, ld, k, Wm, ld, k, d, w.G, w.gwork, st));
+    HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (sym_eig_small(k, G.data(), th.data(), Q.data()) != 0)
+      return fail(h, REFL_ERR_NOT_CONVERGED, "Rayleigh-Ritz eigensolver failed");
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Cc[i + k * j] = Q[(size_t)i * k + j];  // column-major
+    HIPCHK(hipMemcpyAsync(w.G, Cc.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+    HIPCHK(block_axpy(d, k, k, 0.0, spare, ld, 1.0, V, ld, w.G, st));
+    std::swap(V, spare);
+    HIPCHK(block_axpy(d, k, k, 0.0, Wspare, ld, 1.0, Wm, ld, w.G, st));
+    std::swap(Wm, Wspare);
+    // Residual E = W - V Theta, projected onto the complement of V.
+    for (int c = 0; c < k; ++c) nrm[c] = -th[c];
+    HIPCHK(hipMemcpyAsync(w.G + MAXB * MAXB, nrm.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    HIPCHK(lincomb(d, k, 1.0, Wm, ld, 0.0, w.Rr, ld, st));
+    HIPCHK(col_axpy(d, k, w.Rr, ld, w.G + MAXB * MAXB, V, ld, st));
+    HIPCHK(gram(V, ld, k, w.Rr, ld, k, d, w.G, w.gwork, st));
+    HIPCHK(block_axpy(d, k, k, 1.0, w.Rr, ld, -1.0, V, ld, w.G, st));
+    HIPCHK(gram(w.Rr, ld, k, w.Rr, ld, k, d, w.G, w.gwork, st));
+    HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double e2 = 0.0;
+    for (int c = 0; c < k; ++c) e2 += G[c + k * c];
+    E_fro = std::sqrt(e2);
+    theta_max = th[k - 1];
+    dk = (theta_max < s) ? 2.0 * std::sqrt(2.0) * E_fro / (s - theta_max) : INFINITY;
+    if (dk <= p.tol || sweeps >= p.polish_sweeps) break;
+    // Correction: (I - VV^T)(H - theta_c)(I - VV^T) z_c = -E_c by block CG.
+    HIPCHK(lincomb(d, k, -1.0, w.Rr, ld, 0.0, w.Rr, ld, st));
+    HIPCHK(lincomb(d, k, 0.0, w.Rr, ld, 0.0, w.Z, ld, st));
+    HIPCHK(lincomb(d, k, 0.0, w.Rr, ld, 0.0, w.P[0], ld, st));
+    std::memset(hs, 0, sizeof(CgHost));
+    for (int c = 0; c < k; ++c) {
+      hs->theta[c] = th[c];
+      hs->rho[c] = hs->rho0[c] = G[c + k * c];
+      hs->beta[c] = 0.0;
+    }
+    hs->tol2 = p.cg_tol * p.cg_tol;
+    hs->k = k;
+    hs->nb = k;
+    HIPCHK(hipMemcpyAsync(w.cgstate, hs, sizeof(CgHost), hipMemcpyHostToDevice, st));
+    int issued = 0;
+    while (true) {
+      const int batch = 16;
+      for (int b = 0; b < batch; ++b, ++issued)
+        HIPCHK(cg_iteration(w.Hf, ld, d, k, V, ld, w.Rr, w.P[issued & 1], w.P[(issued + 1) & 1],
+                            w.AP, w.Z, w.cgstate, w.thin, w.cgpart, p.cg_max_iter, st));
+      HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hs->done) break;
+    }
+    cg_total += hs->iters;
+    // V <- orth(V + Z)
+    HIPCHK(lincomb(d, k, 1.0, w.Z, ld, 1.0, V, ld, st));
+    refl_status_t r = orthonormalise(h, w, V, spare, k);
+    if (r != REFL_OK) return r;
+    ++sweeps;
+  }
+  *Vout = V;
+  if (info) {
+    info->polish_sweeps = sweeps;
+    info->cg_iters = cg_total;
+    info->commutator_fro = 2.0 * std::sqrt(2.0) * E_fro;
+    info->dk_bound = dk;
+  }
+  if (!(dk <= p.tol) && p.tol > 0.0)
+    return fail(h, REFL_ERR_NOT_CONVERGED, "certified bound %.3e above tol %.3e after %d sweeps",
+                dk, p.tol, sweeps);
+  return REFL_OK;
+}
+
+// Shared body of refl_sign and refl_sign_apply.  If dR is non-null, R is
+// written; otherwise dY = R dV.
+refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                        const refl_params_t* pin, double* dR, int64_t ldr, int64_t nrhs,
+                        const double* dV, int64_t ldv, double* dY, int64_t ldy,
+                        refl_info_t* info) {
+  const double t_start = now_ms();
+  refl_status_t rs = check_params(h, d, pin);
+  if (rs != REFL_OK) return rs;
+  if (!dH || ldh < d) return fail(h, REFL_ERR_INVALID_ARG, "H is NULL or ldh < d");
+  refl_params_t p = *pin;
+  refl_info_t inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.lam_k = inf.lam_k1 = inf.eps = inf.margin = NaN;
+  inf.commutator_fro = inf.dk_bound = NaN;
+  inf.index_j = -1;
+  if (p.shift_mode == REFL_SHIFT_LANCZOS) {
+    double s, lk, lk1, eps, rho;
+    rs = refl_estimate_shift(h, d, dH, ldh, p.k, p.lanczos_steps, p.seed, &s, &lk, &lk1, &eps, &rho);
+    if (rs != REFL_OK) return rs;
+    p.s = s;
+    inf.lam_k = lk;
+    inf.lam_k1 = lk1;
+    inf.eps = eps;
+    inf.margin = std::fmin(s - lk, lk1 - s) - eps;
+  }
+  const double s = p.s;
+  inf.s = s;
+  HIPCHK(hipSetDevice(h->device));
+  Work w;
+  const size_t need = layout(w, nullptr, d, p, false);
+  void* base = nullptr;
+  rs = ensure_workspace(h, need, &base);
+  if (rs != REFL_OK) return rs;
+  layout(w, base, d, p, false);
+  hipStream_t st = h->stream;
+  double* hsc = h->pinned;
+
+  // ---- set-up ----
+  std::vector<int2> tl;
+  upload_tiles(w, st, tl);
+  HIPCHK(hipMemcpyAsync(w.tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, st));
+  HIPCHK(launch_scale_inf(w.Hf, w.dp, (int)d, s, p.scale_mode == REFL_SCALE_GIVEN, p.alpha,
+                          w.rowsum, w.scal, st));
+  const int W = p.words;
+  if (p.precision == REFL_PREC_FP64) {
+    HIPCHK(launch_init_x0_f64(w.Hf, w.dp, (int)d, s, w.scal, w.X64[0], st));
+    HIPCHK(launch_trace_f64(w.X64[0], w.dp, (int)d, w.scal, SC_TRACE, st));
+  } else if (p.precision == REFL_PREC_FP32) {
+    HIPCHK(launch_init_x0_f32(w.Hf, w.dp, (int)d, s, w.scal, w.X32[0], st));
+    HIPCHK(launch_trace_f32(w.X32[0], w.dp, (int)d, w.scal, SC_TRACE, st));
+  } else {
+    HIPCHK(launch_init_x0_words(W, w.Hf, w.dp, (int)d, s, w.scal, w.Xw[0], w.ps, st));
+    HIPCHK(launch_trace_words(W, w.Xw[0], w.ps, w.dp, (int)d, w.scal, SC_TRACE, st));
+  }
+  HIPCHK(hipMemcpyAsync(hsc, w.scal, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hsc[SC_NONFINITE] > 0.0) return fail(h, REFL_ERR_NOT_FINITE, "H holds non-finite entries");
+  inf.alpha = hsc[SC_ALPHA];
+  if (!(inf.alpha > 0.0) || !std::isfinite(inf.alpha))
+    return fail(h, REFL_ERR_NOT_FINITE, "scale alpha=%g is not a positive finite number", inf.alpha);
+  const double t_setup = now_ms();
+
+  // ---- bulk ----
+  Bulk b;
+  double trace_cur = hsc[SC_TRACE];
+  std::vector<double> hist;
+  const bool fixed = p.fixed_steps > 0;
+  const int cap = fixed ? p.fixed_steps : p.max_iter;
+  int cert_steps = 0;
+  refl_status_t bulk_status = REFL_OK;
+  while (true) {
+    const int c = b.cur;
+    if (p.precision == REFL_PREC_FP64)
+      HIPCHK(launch_sym_gemm_f64(GEMM_RESIDUAL, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
+                                 w.dp, w.tiles, w.ntiles, w.partials, st));
+    else if (p.precision == REFL_PREC_FP32)
+      HIPCHK(launch_sym_gemm_f32(GEMM_RESIDUAL, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
+                                 w.dp, w.tiles, w.ntiles, w.partials, st));
+    else
+      HIPCHK(launch_sym_gemm_words(W, GEMM_RESIDUAL, w.Xw[c], w.Xw[c], nullptr, w.Nw, w.dp, w.ps,
+                                   (int)d, w.dp, w.tiles, w.ntiles, w.partials, st));
+    HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
+    HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, w.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double resid = std::sqrt(std::fmax(hsc[SC_RESID2], 0.0));
+    b.resid = resid;
+    b.trace = trace_cur;
+    hist.push_back(resid);
+    if (!std::isfinite(resid)) {
+      bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
+      break;
+    }
+    // Stopping rule.
+    if (fixed) {
+      if (b.steps >= cap) {
+        b.converged = true;
+        break;
+      }
+    } else if (p.precision != REFL_PREC_MIXED) {
+      if (resid < p.tol) {
+        b.converged = true;
+        break;
+      }
+      // Stagnation once quadratic convergence should have set in: no halving
+      // over two steps below 1e-6.
+      const size_t n = hist.size();
+      if (n >= 3 && resid < 1e-6 && resid > 0.5 * hist[n - 3]) break;
+      if (b.steps >= cap) break;
+    } else {
+      // MIXED bulk: run until the index certificate holds and the residual
+      // stops decreasing quadratically (the BF16-word floor), or two steps
+      // after the certificate first held.
+      const int j = index_certificate(d, resid, trace_cur);
+      const size_t n = hist.size();
+      if (j >= 0) {
+        ++cert_steps;
+        const bool floor = n >= 2 && resid > 0.25 * hist[n - 2];
+        if (floor || cert_steps > 2) {
+          b.converged = true;
+          break;
+        }
+      }
+      if (b.steps >= cap) break;
+    }
+    if (p.precision == REFL_PREC_FP64)
+      HIPCHK(launch_sym_gemm_f64(GEMM_UPDATE, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp, (int)d,
+                                 w.dp, w.tiles, w.ntiles, w.partials, st));
+    else if (p.precision == REFL_PREC_FP32)
+      HIPCHK(launch_sym_gemm_f32(GEMM_UPDATE, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp, (int)d,
+                                 w.dp, w.tiles, w.ntiles, w.partials, st));
+    else
+      HIPCHK(launch_sym_gemm_words(W, GEMM_UPDATE, w.Xw[c], w.Nw, w.Xw[c], w.Xw[c ^ 1], w.dp, w.ps,
+                                   (int)d, w.dp, w.tiles, w.ntiles, w.partials, st));
+    HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
+    HIPCHK(hipMemcpyAsync(hsc + SC_TRACE, w.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
+    b.cur ^= 1;
+    b.steps += 1;
+    HIPCHK(hipStreamSynchronize(st));
+    trace_cur = hsc[SC_TRACE];
+  }
+  inf.ns_steps = b.steps;
+  inf.resid_fro = b.resid;
+  inf.trace = b.trace;
+  inf.index_j = index_certificate(d, b.resid, b.trace);
+  const double t_bulk = now_ms();
+  if (bulk_status != REFL_OK) {
+    if (info) *info = inf;
+    return bulk_status;
+  }
+
+  // ---- output ----
+  refl_status_t out_status = REFL_OK;
+  if (!b.converged) out_status = fail(h, REFL_ERR_NOT_CONVERGED, "no convergence after %d steps (resid %.3e)", b.steps, b.resid);
+  if (!fixed && inf.index_j >= 0 && inf.index_j != p.k)
+    out_status = fail(h, REFL_ERR_NOT_ADMISSIBLE,
+                      "index certificate found %d negative eigenvalues of H - sI, not k=%d",
+                      inf.index_j, p.k);
+  const int c = b.cur;
+  if (p.precision == REFL_PREC_MIXED && !fixed) {
+    if (inf.index_j != p.k) {
+      if (out_status == REFL_OK)
+        out_status = fail(h, REFL_ERR_NOT_ADMISSIBLE, "index certificate did not hold for k=%d", p.k);
+      if (info) *info = inf;
+      return out_status;
+    }
+    double* V = nullptr;
+    refl_status_t pr = polish(h, w, p, s, w.Xw[c], &V, &inf);
+    if (pr != REFL_OK && pr != REFL_ERR_NOT_CONVERGED) {
+      if (info) *info = inf;
+      return pr;
+    }
+    if (out_status == REFL_OK) out_status = pr;
+    if (dR) {
+      HIPCHK(form_reflector(V, w.dp, p.k, (int)d, dR, ldr, st));
+    } else {
+      // Y = V_in - 2 V (V^T V_in), in blocks of MAXB columns.
+      for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
+        const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
+        HIPCHK(gram(V, w.dp, p.k, dV + c0 * ldv, ldv, nb, (int)d, w.G, w.gwork, st));
+        HIPCHK(lincomb((int)d, nb, 1.0, dV + c0 * ldv, ldv, 0.0, dY + c0 * ldy, ldy, st));
+        HIPCHK(block_axpy((int)d, p.k, nb, 1.0, dY + c0 * ldy, ldy, -2.0, V, w.dp, w.G, st));
+      }
+    }
+  } else {
+    if (dR) {
+      if (p.precision == REFL_PREC_FP64)
+        HIPCHK(launch_copy_out_f64(w.X64[c], w.dp, (int)d, dR, ldr, st));
+      else if (p.precision == REFL_PREC_FP32)
+        HIPCHK(launch_copy_out_f32(w.X32[c], w.dp, (int)d, dR, ldr, st));
+      else
+        HIPCHK(launch_copy_out_words(W, w.Xw[c], w.ps, w.dp, (int)d, dR, ldr, st));
+    } else {
+      for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
+        const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
+        if (p.precision == REFL_PREC_FP64)
+          HIPCHK(thin_gemm_f64(w.X64[c], w.dp, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, st));
+        else if (p.precision == REFL_PREC_FP32)
+          HIPCHK(thin_gemm_f32(w.X32[c], w.dp, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, st));
+        else
+          HIPCHK(thin_gemm_words(W, w.Xw[c], w.dp, w.ps, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, st));
+      }
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  const double t_end = now_ms();
+  inf.ms_setup = t_setup - t_start;
+  inf.ms_bulk = t_bulk - t_setup;
+  inf.ms_polish = t_end - t_bulk;
+  inf.ms_total = t_end - t_start;
+  if (info) *info = inf;
+  return out_status;
+}
+
+}  // namespace
+
+extern "C" {
+
+refl_status_t refl_params_default(refl_params_t* p) {
+  if (!p) return REFL_ERR_INVALID_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->k = 1;
+  p->s = 0.0;
+  p->shift_mode = REFL_SHIFT_GIVEN;
+  p->scale_mode = REFL_SCALE_INF;
+  p->precision = REFL_PREC_FP64;
+  p->alpha = 0.0;
+  p->tol = 1e-12;
+  p->max_iter = 100;
+  p->fixed_steps = 0;
+  p->words = 2;
+  p->polish_sweeps = 2;
+  p->cg_tol = 1e-6;
+  p->cg_max_iter = 400;
+  p->lanczos_steps = 0;
+  p->seed = 0;
+  return REFL_OK;
+}
+
+refl_status_t refl_create(refl_handle_t* out, int device, void* hip_stream) {
+  if (!out) return REFL_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return REFL_ERR_DEVICE;
+  refl_handle_s* h = new (std::nothrow) refl_handle_s();
+  if (!h) return REFL_ERR_NO_MEMORY;
+  h->device = device;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete h;
+    return REFL_ERR_DEVICE;
+  }
+  const size_t pin_bytes = sizeof(double) * SC_COUNT + sizeof(CgHost) + 256;
+  if (hipHostMalloc((void**)&h->pinned, pin_bytes, hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return REFL_ERR_NO_MEMORY;
+  }
+  std::memset(h->pinned, 0, pin_bytes);
+  *out = h;
+  return REFL_OK;
+}
+
+refl_status_t refl_destroy(refl_handle_t h) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  if (h->ws_own) (void)hipFree(h->ws_own);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return REFL_OK;
+}
+
+refl_status_t refl_set_stream(refl_handle_t h, void* hip_stream) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  h->stream = (hipStream_t)hip_stream;
+  return REFL_OK;
+}
+
+refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_t* p,
+                                  size_t* bytes) {
+  if (!h || !bytes) return REFL_ERR_INVALID_ARG;
+  refl_status_t rs = check_params(h, d, p);
+  if (rs != REFL_OK) return rs;
+  Work w;
+  *bytes = layout(w, nullptr, d, *p, false);
+  return REFL_OK;
+}
+
+refl_status_t refl_set_workspace(refl_handle_t h, void* dptr, size_t bytes) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  if (dptr && ((uintptr_t)dptr % 256) != 0)
+    return fail(h, REFL_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  h->ws_user = dptr;
+  h->ws_user_bytes = dptr ? bytes : 0;
+  return REFL_OK;
+}
+
+refl_status_t refl_sign(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                        const refl_params_t* p, double* dR, int64_t ldr, refl_info_t* info) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  if (!dR || ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "R is NULL or ldr < d");
+  return sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info);
+}
+
+refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                              const refl_params_t* p, int64_t nrhs, const double* dV,
+                              int64_t ldv, double* dY, int64_t ldy, refl_info_t* info) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  if (nrhs < 1 || !dV || !dY || ldv < d || ldy < d)
+    return fail(h, REFL_ERR_INVALID_ARG, "bad V/Y block (nrhs >= 1, ld >= d)");
+  return sign_impl(h, d, dH, ldh, p, nullptr, 0, nrhs, dV, ldv, dY, ldy, info);
+}
+
+refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t ldr, int64_t nrhs,
+                         const double* dV, int64_t ldv, double* dY, int64_t ldy) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  if (d < 1 || !dR || ldr < d || nrhs < 1 || !dV || !dY || ldv < d || ldy < d)
+    return fail(h, REFL_ERR_INVALID_ARG, "bad arguments to refl_apply");
+  HIPCHK(hipSetDevice(h->device));
+  refl_params_t p;
+  refl_params_default(&p);
+  Work w;
+  const size_t need = layout(w, nullptr, d, p, true);
+  void* base = nullptr;
+  refl_status_t rs = ensure_workspace(h, need, &base);
+  if (rs != REFL_OK) return rs;
+  layout(w, base, d, p, true);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
+    const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
+    HIPCHK(thin_gemm_f64(dR, ldr, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, h->stream));
+  }
+  return REFL_OK;
+}
+
+refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                                  int32_t k, int32_t steps, uint64_t seed, double* s,
+                                  double* lam_k, double* lam_k1, double* eps, double* rho) {
+  (void)d; (void)dH; (void)ldh; (void)k; (void)steps; (void)seed;
+  (void)s; (void)lam_k; (void)lam_k1; (void)eps; (void)rho;
+  if (!h) return REFL_ERR_INVALID_ARG;
+  return fail(h, REFL_ERR_UNSUPPORTED, "Lanczos shift estimation not built yet");
+}
+
+const char* refl_status_string(refl_status_t s) {
+  switch (s) {
+    case REFL_OK: return "REFL_OK";
+    case REFL_ERR_INVALID_ARG: return "REFL_ERR_INVALID_ARG";
+    case REFL_ERR_DEVICE: return "REFL_ERR_DEVICE";
+    case REFL_ERR_NO_MEMORY: return "REFL_ERR_NO_MEMORY";
+    case REFL_ERR_NOT_CONVERGED: return "REFL_ERR_NOT_CONVERGED";
+    case REFL_ERR_NOT_ADMISSIBLE: return "REFL_ERR_NOT_ADMISSIBLE";
+    case REFL_ERR_NO_GAP: return "REFL_ERR_NO_GAP";
+    case REFL_ERR_NOT_FINITE: return "REFL_ERR_NOT_FINITE";
+    case REFL_ERR_UNSUPPORTED: return "REFL_ERR_UNSUPPORTED";
+  }
+  return "REFL_ERR_UNKNOWN";
+}
+
+const char* refl_last_error(refl_handle_t h) { return h ? h->err : "NULL handle"; }
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+"""Python binding of ``librefl.so`` (include/refl.h): argument marshalling only.
+
+The functions named ``refl_*`` are the C entry points, called with device
+pointers.  ``sign``, ``apply``, ``sign_apply`` and ``estimate_shift`` wrap
+them for torch tensors on a ROCm device (torch provides the device memory and
+the stream; every step of the computation runs in the library's kernels).
+There is no CPU fallback: if the library is missing, loading raises.
+"""
+import ctypes
+import math
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librefl.so")
+
+REFL_OK = 0
+STATUS = {0: "REFL_OK", 1: "REFL_ERR_INVALID_ARG", 2: "REFL_ERR_DEVICE", 3: "REFL_ERR_NO_MEMORY",
+          4: "REFL_ERR_NOT_CONVERGED", 5: "REFL_ERR_NOT_ADMISSIBLE", 6: "REFL_ERR_NO_GAP",
+          7: "REFL_ERR_NOT_FINITE", 8: "REFL_ERR_UNSUPPORTED"}
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
+SHIFT = {"given": 0, "lanczos": 1}
+SCALE = {"inf": 0, "given": 1}
+
+EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
+           "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
+           "refl_apply", "refl_sign_apply", "refl_status_string", "refl_last_error"]
+
+
+class refl_params_t(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("s", ctypes.c_double), ("shift_mode", ctypes.c_int32),
+                ("scale_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("fixed_steps", ctypes.c_int32),
+                ("words", ctypes.c_int32), ("polish_sweeps", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class refl_info_t(ctypes.Structure):
+    _fields_ = [("ns_steps", ctypes.c_int32), ("polish_sweeps", ctypes.c_int32),
+                ("cg_iters", ctypes.c_int32), ("index_j", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("s", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("lam_k", ctypes.c_double),
+                ("lam_k1", ctypes.c_double), ("eps", ctypes.c_double),
+                ("margin", ctypes.c_double), ("resid_fro", ctypes.c_double),
+                ("trace", ctypes.c_double), ("commutator_fro", ctypes.c_double),
+                ("dk_bound", ctypes.c_double), ("ms_setup", ctypes.c_double),
+                ("ms_bulk", ctypes.c_double), ("ms_polish", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load ``librefl.so`` and declare the C signatures.  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2605_24840_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    H = ctypes.c_void_p
+    i64, i32, u64, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+    P = ctypes.POINTER
+    sig = {
+        "refl_params_default": [P(refl_params_t)],
+        "refl_create": [P(H), ctypes.c_int, vp],
+        "refl_destroy": [H],
+        "refl_set_stream": [H, vp],
+        "refl_workspace_size": [H, i64, P(refl_params_t), P(ctypes.c_size_t)],
+        "refl_set_workspace": [H, vp, ctypes.c_size_t],
+        "refl_estimate_shift": [H, i64, vp, i64, i32, i32, u64, P(dbl), P(dbl), P(dbl), P(dbl), P(dbl)],
+        "refl_sign": [H, i64, vp, i64, P(refl_params_t), vp, i64, P(refl_info_t)],
+        "refl_apply": [H, i64, vp, i64, i64, vp, i64, vp, i64],
+        "refl_sign_apply": [H, i64, vp, i64, P(refl_params_t), i64, vp, i64, vp, i64, P(refl_info_t)],
+        "refl_status_string": [ctypes.c_int],
+        "refl_last_error": [H],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name in ("refl_status_string", "refl_last_error") else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ---------------------------------------------------------------- C names
+def refl_params_default():
+    p = refl_params_t()
+    _check(None, load().refl_params_default(ctypes.byref(p)))
+    return p
+
+
+def refl_create(device: int = 0, stream: int = 0):
+    h = ctypes.c_void_p()
+    st = load().refl_create(ctypes.byref(h), device, ctypes.c_void_p(stream))
+    if st != REFL_OK:
+        raise ReflError(st, "refl_create failed")
+    return h
+
+
+def refl_destroy(h):
+    return load().refl_destroy(h)
+
+
+def refl_set_stream(h, stream: int):
+    return _check(h, load().refl_set_stream(h, ctypes.c_void_p(stream)))
+
+
+def refl_workspace_size(h, d: int, params) -> int:
+    n = ctypes.c_size_t()
+    _check(h, load().refl_workspace_size(h, d, ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def refl_set_workspace(h, ptr: int, nbytes: int):
+    return _check(h, load().refl_set_workspace(h, ctypes.c_void_p(ptr), nbytes))
+
+
+def refl_sign(h, d, H_ptr, ldh, params, R_ptr, ldr, info=None, check=True):
+    info = info if info is not None else refl_info_t()
+    st = load().refl_sign(h, d, ctypes.c_void_p(H_ptr), ldh, ctypes.byref(params),
+                          ctypes.c_void_p(R_ptr), ldr, ctypes.byref(info))
+    if check:
+        _check(h, st)
+    return st, info
+
+
+def refl_apply(h, d, R_ptr, ldr, nrhs, V_ptr, ldv, Y_ptr, ldy):
+    return _check(h, load().refl_apply(h, d, ctypes.c_void_p(R_ptr), ldr, nrhs,
+                                       ctypes.c_void_p(V_ptr), ldv, ctypes.c_void_p(Y_ptr), ldy))
+
+
+def refl_sign_apply(h, d, H_ptr, ldh, params, nrhs, V_ptr, ldv, Y_ptr, ldy, info=None, check=True):
+    info = info if info is not None else refl_info_t()
+    st = load().refl_sign_apply(h, d, ctypes.c_void_p(H_ptr), ldh, ctypes.byref(params), nrhs,
+                                ctypes.c_void_p(V_ptr), ldv, ctypes.c_void_p(Y_ptr), ldy,
+                                ctypes.byref(info))
+    if check:
+        _check(h, st)
+    return st, info
+
+
+def refl_estimate_shift(h, d, H_ptr, ldh, k, steps=0, seed=0, check=True):
+    out = [ctypes.c_double() for _ in range(5)]
+    st = load().refl_estimate_shift(h, d, ctypes.c_void_p(H_ptr), ldh, k, steps, seed,
+                                    *[ctypes.byref(o) for o in out])
+    if check:
+        _check(h, st)
+    return st, tuple(o.value for o in out)
+
+
+def refl_status_string(st: int) -> str:
+    return load().refl_status_string(st).decode()
+
+
+def refl_last_error(h) -> str:
+    return load().refl_last_error(h).decode()
+
+
+class ReflError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(h, st):
+    if st != REFL_OK:
+        raise ReflError(st, refl_last_error(h) if h is not None else "")
+    return st
+
+
+# ------------------------------------------------------------ torch wrapper
+class Handle:
+    """A library handle bound to a torch device and its current stream."""
+
+    def __init__(self, device=None):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.h = refl_create(self.device.index or 0, torch.cuda.current_stream(self.device).cuda_stream)
+        self._ws = None
+
+    def sync_stream(self):
+        import torch
+        refl_set_stream(self.h, torch.cuda.current_stream(self.device).cuda_stream)
+
+    def reserve(self, d, params):
+        """Give the library a torch-allocated workspace large enough for (d, params)."""
+        import torch
+        n = refl_workspace_size(self.h, d, params)
+        if self._ws is None or self._ws.numel() < n + 256:
+            self._ws = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        ptr = self._ws.data_ptr()
+        ptr = (ptr + 255) // 256 * 256
+        refl_set_workspace(self.h, ptr, n)
+
+    def close(self):
+        if self.h is not None:
+            refl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
+                alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0):
+    p = refl_params_default()
+    p.k = int(k)
+    p.shift_mode = SHIFT["lanczos"] if s is None else SHIFT["given"]
+    p.s = 0.0 if s is None else float(s)
+    p.precision = PRECISION[precision]
+    if tol is not None:
+        p.tol = float(tol)
+    elif precision == "mixed":
+        p.tol = 0.0
+    p.max_iter = int(max_iter)
+    p.fixed_steps = int(fixed_steps)
+    p.words = int(words)
+    if alpha is not None:
+        p.scale_mode = SCALE["given"]
+        p.alpha = float(alpha)
+    p.polish_sweeps = int(polish_sweeps)
+    p.cg_tol = float(cg_tol)
+    p.cg_max_iter = int(cg_max_iter)
+    p.lanczos_steps = int(lanczos_steps)
+    p.seed = int(seed)
+    return p
+
+
+def _dev_f64(t):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 tensor on a ROCm device")
+    return t
+
+
+def sign(H, k, s=None, handle=None, out=None, check=True, **kw):
+    """R_k = sgn(H - sI) for a float64 device tensor H (upper triangle read).
+
+    Returns ``(R, info_dict, status)``."""
+    import torch
+    H = _dev_f64(H)
+    d = H.shape[0]
+    if H.dim() != 2 or H.shape[1] < d or H.stride(1) != 1:
+        raise ValueError("H must be d x d (or d x ld) with unit column stride")
+    h = handle or Handle(H.device)
+    h.sync_stream()
+    p = make_params(k, s, **kw)
+    R = out if out is not None else torch.empty((d, d), dtype=torch.float64, device=H.device)
+    st, info = refl_sign(h.h, d, H.data_ptr(), H.stride(0), p, R.data_ptr(), R.stride(0), check=check)
+    return R, info.as_dict(), st
+
+
+def apply(R, V, handle=None):
+    """Y = R V for a d x d float64 R and a d x nrhs (or length-d) float64 V."""
+    import torch
+    R = _dev_f64(R)
+    V = _dev_f64(V)
+    vec = V.dim() == 1
+    Vc = V.reshape(-1, 1) if vec else V
+    d, nrhs = Vc.shape
+    Vcm = Vc.t().contiguous()   # column-major d x nrhs == row-major nrhs x d
+    Ycm = torch.empty_like(Vcm)
+    h = handle or Handle(R.device)
+    h.sync_stream()
+    refl_apply(h.h, d, R.data_ptr(), R.stride(0), nrhs, Vcm.data_ptr(), d, Ycm.data_ptr(), d)
+    Y = Ycm.t()
+    return Y.reshape(-1) if vec else Y.contiguous()
+
+
+def sign_apply(H, V, k, s=None, handle=None, check=True, **kw):
+    """Y = R_k V without materialising R.  Returns ``(Y, info_dict, status)``."""
+    import torch
+    H = _dev_f64(H)
+    V = _dev_f64(V)
+    vec = V.dim() == 1
+    Vc = V.reshape(-1, 1) if vec else V
+    d, nrhs = Vc.shape
+    Vcm = Vc.t().contiguous()
+    Ycm = torch.empty_like(Vcm)
+    h = handle or Handle(H.device)
+    h.sync_stream()
+    p = make_params(k, s, **kw)
+    st, info = refl_sign_apply(h.h, d, H.data_ptr(), H.stride(0), p, nrhs, Vcm.data_ptr(), d,
+                               Ycm.data_ptr(), d, check=check)
+    Y = Ycm.t()
+    return (Y.reshape(-1) if vec else Y.contiguous()), info.as_dict(), st
+
+
+def estimate_shift(H, k, steps=0, seed=0, handle=None, check=True):
+    """Block-Lanczos midpoint shift: returns ``(s, lam_k, lam_k1, eps, rho, status)``."""
+    H = _dev_f64(H)
+    d = H.shape[0]
+    h = handle or Handle(H.device)
+    h.sync_stream()
+    st, vals = refl_estimate_shift(h.h, d, H.data_ptr(), H.stride(0), k, steps, seed, check=check)
+    return vals + (st,)
+
+
+def nan():
+    return math.nan

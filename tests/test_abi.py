@@ -1,0 +1,84 @@
+"""The C-ABI library loads, exports every symbol include/refl.h declares, and
+its struct layouts agree with the Python binding (no compute calls)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2605_24840_amd import refl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "refl.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:refl_status_t|const char\s*\*)\s*(refl_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    assert set(names) == set(refl.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = refl.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", refl.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (refl_\w+)", out))
+    assert set(_declared_functions()) <= exported
+    # Nothing else leaks out under the refl_ prefix.
+    assert exported == set(_declared_functions())
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "refl.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu\\n", sizeof(refl_params_t), sizeof(refl_info_t));\n'
+        'printf("%zu %zu %zu\\n", offsetof(refl_params_t, seed), offsetof(refl_params_t, cg_tol),'
+        " offsetof(refl_params_t, lanczos_steps));\n"
+        'printf("%zu %zu %zu\\n", offsetof(refl_info_t, s), offsetof(refl_info_t, dk_bound),'
+        " offsetof(refl_info_t, ms_total));\n"
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    sp, si = map(int, lines[0].split())
+    assert sp == ctypes.sizeof(refl.refl_params_t)
+    assert si == ctypes.sizeof(refl.refl_info_t)
+    o = list(map(int, lines[1].split()))
+    assert o == [refl.refl_params_t.seed.offset, refl.refl_params_t.cg_tol.offset,
+                 refl.refl_params_t.lanczos_steps.offset]
+    o = list(map(int, lines[2].split()))
+    assert o == [refl.refl_info_t.s.offset, refl.refl_info_t.dk_bound.offset, refl.refl_info_t.ms_total.offset]
+
+
+def test_params_default_and_status_strings():
+    p = refl.refl_params_default()
+    assert (p.k, p.tol, p.max_iter, p.fixed_steps, p.words, p.polish_sweeps) == (1, 1e-12, 100, 0, 2, 2)
+    assert p.precision == refl.PRECISION["fp64"] and p.shift_mode == refl.SHIFT["given"]
+    for code, name in refl.STATUS.items():
+        assert refl.refl_status_string(code) == name
+    assert refl.refl_status_string(99) == "REFL_ERR_UNKNOWN"
+
+
+def test_null_arguments_rejected_without_device():
+    lib = refl.load()
+    assert lib.refl_params_default(None) == 1
+    assert lib.refl_create(None, 0, None) == 1
+    assert lib.refl_destroy(None) == 1
+    assert lib.refl_sign(None, 4, None, 4, None, None, 4, None) == 1
+    assert refl.load().refl_last_error(None) == b"NULL handle"
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p()
+    assert refl.load().refl_create(ctypes.byref(h), 0, None) == 2

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle.
+
+Tolerances:
+* FP64 iterates: the library and the oracle run the same recurrence (eq. NS)
+  in FP64 with different summation orders; the difference of X_m stays at
+  the FP64 rounding level times the growth of the iteration (<= 1e-13 for
+  d <= 300 and m <= 20, measured against the spectral closed form in the
+  oracle pins).
+* FP64 converged: ||X^2 - I||_F < 1e-12 gives ||X - sgn||_F < 1e-12 for a
+  commuting iterate (eigenwise |p - s| <= |p^2 - 1|), plus rounding.
+* MIXED: the target ||R - R_k||_F <= 1e-8 sqrt(d).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_24840_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2605_24840_amd import refl
+    refl.load()
+    return refl
+
+
+@pytest.fixture(scope="module")
+def handle(R):
+    h = R.Handle(torch.device("cuda", 0))
+    yield h
+    h.close()
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _cfg0():
+    H, lam, Q = inputs.planted_hessian(64, 4, 0.1, 0)
+    return H, lam, Q, 0.5 * (lam[3] + lam[4])
+
+
+# ------------------------------------------------------------------ FP64
+@pytest.mark.parametrize("m", [1, 2, 5, 10, 17, 20])
+def test_fp64_iterates_match_oracle(R, handle, m):
+    _say(f"fp64 iterate d=64 k=4 m={m}")
+    H, lam, Q, s = _cfg0()
+    Rg, info, st = R.sign(_gpu(H), 4, s, handle=handle, precision="fp64", fixed_steps=m)
+    assert st == 0
+    alpha = oracle.inf_norm_shifted(H, s)
+    assert info["alpha"] == pytest.approx(alpha, rel=1e-15)
+    Xm = oracle.ns_iterates(H, s, alpha, m)[m]
+    err = np.abs(Rg.cpu().numpy() - Xm).max()
+    _say(f"  max|X_m - oracle| = {err:.2e}")
+    assert err < 1e-13
+
+
+def test_fp64_ragged_size(R, handle):
+    # d = 300: a 3 x 3 grid of 128-tiles (6 upper tiles) with a ragged tail.
+    d, k = 300, 7
+    _say(f"fp64 iterate d={d} k={k} m=6")
+    H, lam, Q = inputs.planted_hessian(d, k, 0.05, 3)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="fp64", fixed_steps=6)
+    alpha = oracle.inf_norm_shifted(H, s)
+    X6 = oracle.ns_iterates(H, s, alpha, 6)[6]
+    err = np.abs(Rg.cpu().numpy() - X6).max()
+    _say(f"  max|X_6 - oracle| = {err:.2e}")
+    assert err < 1e-13
+    d2 = oracle.certificates(H, X6, s)
+    assert info["trace"] == pytest.approx(d2["trace"], abs=1e-10)
+    assert info["resid_fro"] == pytest.approx(d2["resid_fro"], rel=1e-9)
+
+
+def test_fp64_converged_config0(R, handle):
+    _say("fp64 converged d=64 k=4 gap=0.1 midpoint tol=1e-12")
+    H, lam, Q, s = _cfg0()
+    Rg, info, st = R.sign(_gpu(H), 4, s, handle=handle, precision="fp64", tol=1e-12)
+    assert st == 0
+    Rk, w, V = oracle.reflector(H, 4)
+    err = np.linalg.norm(Rg.cpu().numpy() - Rk)
+    pred = oracle.ns_depth_scalar((w - s) / info["alpha"], 1e-12)
+    _say(f"  ||R - R_k||_F = {err:.2e} steps={info['ns_steps']} predicted={pred} resid={info['resid_fro']:.2e}")
+    assert info["resid_fro"] < 1e-12
+    assert err < 2e-12
+    assert info["index_j"] == 4
+    assert abs(info["ns_steps"] - pred) <= 1
+
+
+def test_fp64_off_centre_shifts(R, handle):
+    H, lam, Q, s_mid = _cfg0()
+    Rk, w, V = oracle.reflector(H, 4)
+    steps = {}
+    for theta in (0.1, 0.5, 0.9):
+        s = lam[3] + theta * (lam[4] - lam[3])
+        _say(f"fp64 d=64 theta={theta}")
+        Rg, info, st = R.sign(_gpu(H), 4, s, handle=handle, precision="fp64", tol=1e-12)
+        assert st == 0
+        assert np.linalg.norm(Rg.cpu().numpy() - Rk) < 2e-12
+        steps[theta] = info["ns_steps"]
+    assert steps[0.5] < steps[0.1] and steps[0.5] < steps[0.9]
+
+
+def test_fp64_symmetric_upper_only_deterministic(R, handle):
+    d, k = 200, 5
+    _say(f"fp64 upper-triangle-only d={d}")
+    H, lam, Q = inputs.planted_hessian(d, k, 0.1, 4)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Hg = H.copy()
+    Hg[np.tril_indices(d, -1)] = np.nan   # never read
+    R1, _, st1 = R.sign(_gpu(Hg), k, s, handle=handle, precision="fp64")
+    R2, _, st2 = R.sign(_gpu(H), k, s, handle=handle, precision="fp64")
+    a, b = R1.cpu().numpy(), R2.cpu().numpy()
+    assert st1 == 0 and st2 == 0
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, a.T)
+    Rk = np.eye(d) - 2 * Q[:, :k] @ Q[:, :k].T
+    assert np.linalg.norm(a - Rk) < 2e-12
+
+
+def test_apply_and_sign_apply(R, handle):
+    d, k = 257, 6
+    _say(f"apply d={d}")
+    H, lam, Q = inputs.planted_hessian(d, k, 0.1, 5)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    rng = np.random.default_rng(0)
+    Vn = rng.standard_normal((d, 3))
+    Rg, _, _ = R.sign(_gpu(H), k, s, handle=handle, precision="fp64")
+    Y = R.apply(Rg, _gpu(Vn), handle=handle).cpu().numpy()
+    ref = Rg.cpu().numpy() @ Vn
+    assert np.abs(Y - ref).max() < 1e-12
+    y = R.apply(Rg, _gpu(Vn[:, 0].copy()), handle=handle).cpu().numpy()
+    assert np.abs(y - ref[:, 0]).max() < 1e-12
+    Y2, info, st = R.sign_apply(_gpu(H), _gpu(Vn), k, s, handle=handle, precision="fp64")
+    assert st == 0
+    assert np.abs(Y2.cpu().numpy() - ref).max() < 1e-12
+    # Prop. 3.3: the direction error is bounded by the operator error.
+    Rk = np.eye(d) - 2 * Q[:, :k] @ Q[:, :k].T
+    g = Vn[:, 0]
+    assert np.linalg.norm(y - Rk @ g) <= oracle.spectral_norm_sym(Rg.cpu().numpy() - Rk) * np.linalg.norm(g) + 1e-14
+
+
+# --------------------------------------------------------------- errors
+def test_error_paths(R, handle):
+    H, lam, Q, s = _cfg0()
+    Hg = _gpu(H)
+    _say("errors: bad k")
+    for k in (0, 64):
+        _, _, st = R.sign(Hg, k, s, handle=handle, check=False)
+        assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
+    _say("errors: non-finite H")
+    Hn = H.copy()
+    Hn[3, 10] = np.nan
+    _, _, st = R.sign(_gpu(Hn), 4, s, handle=handle, check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_FINITE"
+    _, _, st = R.sign(Hg, 4, float("nan"), handle=handle, check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_FINITE"
+    _say("errors: shift outside the gap")
+    _, info, st = R.sign(Hg, 4, 0.5 * (lam[4] + lam[5]), handle=handle, check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_ADMISSIBLE" and info["index_j"] == 5
+    _say("errors: max_iter too small")
+    Rg, info, st = R.sign(Hg, 4, s, handle=handle, max_iter=2, check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_CONVERGED" and info["ns_steps"] == 2
+    alpha = oracle.inf_norm_shifted(H, s)
+    assert np.abs(Rg.cpu().numpy() - oracle.ns_iterates(H, s, alpha, 2)[2]).max() < 1e-13
+    _say("errors: shift equal to an eigenvalue")
+    D = np.diag(np.linspace(-1, 1, 16))
+    _, info, st = R.sign(_gpu(D), 8, D[7, 7], handle=handle, check=False, max_iter=60)
+    assert R.STATUS[st] == "REFL_ERR_NOT_CONVERGED" and info["index_j"] == -1
+
+
+# ------------------------------------------------------------------ FP32
+@pytest.mark.parametrize("grel,theta", [(1e-1, 0.5), (1e-2, 0.5), (1e-2, 0.1)])
+def test_fp32_controlled_spectra(R, handle, grel, theta):
+    d, k = 1024, 8
+    _say(f"fp32 d={d} k={k} grel={grel} theta={theta}")
+    H, lam, Q = inputs.planted_hessian(d, k, 2 * grel, 0)
+    s = lam[k - 1] + theta * (lam[k] - lam[k - 1])
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="fp32", tol=1e-3, check=False)
+    Rk = np.eye(d) - 2 * Q[:, :k] @ Q[:, :k].T
+    err = np.linalg.norm(Rg.cpu().numpy() - Rk)
+    _say(f"  status={R.STATUS[st]} steps={info['ns_steps']} resid={info['resid_fro']:.2e} ||R-R_k||_F={err:.2e}")
+    assert info["index_j"] == k
+    assert err < 1e-2
+
+
+# ----------------------------------------------------------------- MIXED
+def test_mixed_bulk_iterate(R, handle):
+    d, k = 256, 4
+    _say(f"mixed bulk fixed steps d={d}")
+    H, lam, Q = inputs.planted_hessian(d, k, 0.2, 1)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    for words in (2, 3):
+        Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", words=words, fixed_steps=8)
+        alpha = oracle.inf_norm_shifted(H, s)
+        X8 = oracle.ns_iterates(H, s, alpha, 8)[8]
+        err = np.abs(Rg.cpu().numpy() - X8).max()
+        _say(f"  words={words} max|X_8 - oracle| = {err:.2e}")
+        assert err < (1e-3 if words == 2 else 1e-5)
+
+
+@pytest.mark.parametrize("grel", [1e-1, 1e-2])
+def test_mixed_planted_d1024(R, handle, grel):
+    d, k = 1024, 8
+    _say(f"mixed d={d} k={k} grel={grel}")
+    H, lam, Q = inputs.planted_hessian(d, k, 2 * grel, 0)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", check=False)
+    Rk = np.eye(d) - 2 * Q[:, :k] @ Q[:, :k].T
+    err = np.linalg.norm(Rg.cpu().numpy() - Rk)
+    _say(f"  status={R.STATUS[st]} steps={info['ns_steps']} sweeps={info['polish_sweeps']} "
+         f"cg={info['cg_iters']} dk={info['dk_bound']:.2e} ||R-R_k||_F={err:.2e}")
+    assert st == 0
+    assert err <= 1e-8 * np.sqrt(d)
+
+
+def _allen_cahn_golden(seed=0):
+    path = os.path.join(GOLDEN, f"allen_cahn_n64_seed{seed}.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing")
+    g = np.load(path)
+    H, u = inputs.allen_cahn_2d(64, float(g["eps"]), seed)
+    np.testing.assert_array_equal(u, g["u"])
+    return H, g["w"], g["V"]
+
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_mixed_allen_cahn_d4096(R, handle, k):
+    _say(f"mixed Allen-Cahn d=4096 k={k}")
+    H, w, Vk = _allen_cahn_golden(0)
+    d = H.shape[0]
+    s = 0.5 * (w[k - 1] + w[k])
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", check=False)
+    Rn = Rg.cpu().numpy()
+    Rn -= np.eye(d)
+    Rn += 2.0 * Vk[:, :k] @ Vk[:, :k].T
+    err = np.linalg.norm(Rn)
+    _say(f"  status={R.STATUS[st]} steps={info['ns_steps']} sweeps={info['polish_sweeps']} "
+         f"cg={info['cg_iters']} dk={info['dk_bound']:.2e} ||R-R_k||_F={err:.2e} "
+         f"bulk={info['ms_bulk']:.1f}ms polish={info['ms_polish']:.1f}ms")
+    assert st == 0
+    assert err <= 1e-8 * np.sqrt(d)

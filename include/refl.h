@@ -92,6 +92,8 @@ typedef struct {
   int32_t cg_max_iter;  /* MIXED: cap on inner iterations per sweep (default 400) */
   int32_t lanczos_steps;/* REFL_SHIFT_LANCZOS: cap on block steps (0 = automatic) */
   uint64_t seed;        /* start blocks of Lanczos and of the subspace extraction */
+  int32_t timing;       /* 1: record HIP events around every bulk product and report their
+                           summed durations in info (adds no synchronisation) */
 } refl_params_t;
 
 typedef struct {
@@ -112,11 +114,13 @@ typedef struct {
                              E = (I - V V^T) H V); FP64/FP32: NaN */
   double dk_bound;        /* MIXED: Davis-Kahan bound on ||R - R_k||_F; FP64/FP32: NaN */
   double ms_setup, ms_bulk, ms_polish, ms_total; /* host wall-clock per phase */
+  double ms_gemm;         /* params.timing: summed device time of the bulk products (HIP events) */
+  int32_t gemm_launches;  /* params.timing: number of bulk product launches timed */
 } refl_info_t;
 
 /* Fill *p with defaults: k = 1, s = 0, shift given, scale inf-norm, FP64,
  * tol = 1e-12, max_iter = 100, fixed_steps = 0, words = 2, polish_sweeps = 2,
- * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0. */
+ * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0, timing = 0. */
 refl_status_t refl_params_default(refl_params_t *p);
 
 /* Create a handle bound to HIP device `device` and stream `hip_stream`

@@ -46,6 +46,7 @@ struct refl_handle_s {
   void* ws_own = nullptr;
   size_t ws_own_bytes = 0;
   double* pinned = nullptr;  // host pinned scalars (SC_COUNT doubles + CG state)
+  std::vector<hipEvent_t> ev;  // params.timing: start/stop pairs of the bulk products
   char err[512] = {0};
 };
 
@@ -424,10 +425,30 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   std::vector<double> hist;
   const bool fixed = p.fixed_steps > 0;
   const int cap = fixed ? p.fixed_steps : p.max_iter;
+  // Optional event pairs around each bulk product (2 per step).
+  size_t nev = 0;
+  const size_t max_ev = 2 * (size_t)(cap + 1);
+  if (p.timing) {
+    while (h->ev.size() < 2 * max_ev) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      h->ev.push_back(e);
+    }
+  }
+  auto ev_start = [&]() -> hipError_t {
+    return p.timing ? hipEventRecord(h->ev[2 * nev], st) : hipSuccess;
+  };
+  auto ev_stop = [&]() -> hipError_t {
+    if (!p.timing) return hipSuccess;
+    hipError_t e = hipEventRecord(h->ev[2 * nev + 1], st);
+    ++nev;
+    return e;
+  };
   int cert_steps = 0;
   refl_status_t bulk_status = REFL_OK;
   while (true) {
     const int c = b.cur;
+    HIPCHK(ev_start());
     if (p.precision == REFL_PREC_FP64)
       HIPCHK(launch_sym_gemm_f64(GEMM_RESIDUAL, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
@@ -437,6 +458,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     else
       HIPCHK(launch_sym_gemm_words(W, GEMM_RESIDUAL, w.Xw[c], w.Xw[c], nullptr, w.Nw, w.dp, w.ps,
                                    (int)d, w.dp, w.tiles, w.ntiles, w.partials, st));
+    HIPCHK(ev_stop());
     HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
     HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, w.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -480,6 +502,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       }
       if (b.steps >= cap) break;
     }
+    HIPCHK(ev_start());
     if (p.precision == REFL_PREC_FP64)
       HIPCHK(launch_sym_gemm_f64(GEMM_UPDATE, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
@@ -489,12 +512,24 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     else
       HIPCHK(launch_sym_gemm_words(W, GEMM_UPDATE, w.Xw[c], w.Nw, w.Xw[c], w.Xw[c ^ 1], w.dp, w.ps,
                                    (int)d, w.dp, w.tiles, w.ntiles, w.partials, st));
+    HIPCHK(ev_stop());
     HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
     HIPCHK(hipMemcpyAsync(hsc + SC_TRACE, w.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
     b.cur ^= 1;
     b.steps += 1;
     HIPCHK(hipStreamSynchronize(st));
     trace_cur = hsc[SC_TRACE];
+  }
+  if (p.timing) {
+    HIPCHK(hipStreamSynchronize(st));
+    double tot = 0.0;
+    for (size_t i = 0; i < nev; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+      tot += ms;
+    }
+    inf.ms_gemm = tot;
+    inf.gemm_launches = (int)nev;
   }
   inf.ns_steps = b.steps;
   inf.resid_fro = b.resid;
@@ -591,6 +626,7 @@ refl_status_t refl_params_default(refl_params_t* p) {
   p->cg_max_iter = 400;
   p->lanczos_steps = 0;
   p->seed = 0;
+  p->timing = 0;
   return REFL_OK;
 }
 
@@ -622,6 +658,7 @@ refl_status_t refl_destroy(refl_handle_t h) {
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
   if (h->ws_own) (void)hipFree(h->ws_own);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return REFL_OK;

@@ -33,7 +33,8 @@ class refl_params_t(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("fixed_steps", ctypes.c_int32),
                 ("words", ctypes.c_int32), ("polish_sweeps", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
-                ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("timing", ctypes.c_int32)]
 
 
 class refl_info_t(ctypes.Structure):
@@ -46,7 +47,8 @@ class refl_info_t(ctypes.Structure):
                 ("trace", ctypes.c_double), ("commutator_fro", ctypes.c_double),
                 ("dk_bound", ctypes.c_double), ("ms_setup", ctypes.c_double),
                 ("ms_bulk", ctypes.c_double), ("ms_polish", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_gemm", ctypes.c_double),
+                ("gemm_launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -211,7 +213,8 @@ class Handle:
 
 
 def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
-                alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0):
+                alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
+                timing=False):
     p = refl_params_default()
     p.k = int(k)
     p.shift_mode = SHIFT["lanczos"] if s is None else SHIFT["given"]
@@ -232,6 +235,7 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     p.cg_max_iter = int(cg_max_iter)
     p.lanczos_steps = int(lanczos_steps)
     p.seed = int(seed)
+    p.timing = 1 if timing else 0
     return p
 
 

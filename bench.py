@@ -101,7 +101,7 @@ def main():
     err_mixed = err_vs_oracle()
     last = infos[-1]
     log(f"mixed: {1e3 * t_mixed:.2f} ms/reflector, steps={last['ns_steps']} sweeps={last['polish_sweeps']} "
-        f"cg={last['cg_iters']} bulk={last['ms_bulk']:.2f} polish={last['ms_polish']:.2f} err={err_mixed:.2e}")
+        f"cg={last['cg_iters']} dk={last['dk_bound']:.1e} bulk={last['ms_bulk']:.2f} polish={last['ms_polish']:.2f} err={err_mixed:.2e}")
     nprod = {1: 1, 2: 3, 3: 6}[args.words]
     gemm_ms = sum(i["ms_gemm"] for i in infos)
     gemm_n = sum(i["gemm_launches"] for i in infos)
@@ -160,6 +160,7 @@ def main():
         "ns_steps": last["ns_steps"],
         "polish_sweeps": last["polish_sweeps"],
         "cg_iters": last["cg_iters"],
+        "dk_bound": last["dk_bound"],
         "ms_bulk": float(np.mean([i["ms_bulk"] for i in infos])),
         "ms_polish": float(np.mean([i["ms_polish"] for i in infos])),
         "bulk_algorithmic_tflops": bulk_alg_tflops,

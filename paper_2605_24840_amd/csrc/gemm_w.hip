@@ -11,11 +11,19 @@
 // with the result re-split into W words on store.  X enters the update as
 // the exact FP32 sum of its words.
 //
-// Work-group: 256 threads = 4 waves, output tile 128 x 128, each wave a
-// 64 x 64 quadrant = 2 x 2 blocks of the 32x32x16 BF16 MFMA.  K advances 32
-// at a time through two LDS buffers.  LDS rows are 32 BF16 + 16 B of pad
-// (80 B), so the 16-byte fragment reads of 16 consecutive rows hit distinct
-// banks.
+// Work-group: 256 threads = 4 waves in a 2 x 2 arrangement; output tile
+// TS x TS (TS = 128 or 192), each wave a (TS/2)^2 quadrant of 32x32x16 MFMA
+// blocks.  Larger wave quadrants cut the LDS fragment reads per MFMA
+// (192: 6 fragment reads of 1 KB feed 27 MFMAs per word pair and K-slice of
+// 16, against 4 for 12 at 128), and 192 x 192 tiles cover the upper triangle
+// of a 4096 x 4096 matrix with 253 tiles: one work-group per compute unit of
+// a 256-CU device, with no split of K and no fix-up pass.
+//
+// K advances 32 at a time through two LDS buffers; global loads run two
+// K-steps ahead in two register sets (one K-step for the 192 tiles, whose
+// accumulators take the registers a second set would need).  LDS rows are 32 BF16 + 16 B of pad
+// (80 B): the 16-byte fragment reads of 16 consecutive rows then fall in
+// distinct bank groups whether the LDS serves 8 or 16 lanes per cycle.
 #include "common.h"
 #include "launch.h"
 
@@ -23,18 +31,25 @@ namespace refl {
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-template <int W>
+template <int W, int TS>
 struct WCfg {
   static constexpr int BK = 32;
   static constexpr int LDA = BK + 8;                    // BF16 elements per LDS row (80 B)
-  static constexpr int PLANE = TILE * LDA;              // one operand word plane in LDS
+  static constexpr int PLANE = TS * LDA;                // one operand word plane in LDS
   static constexpr int BUF = 2 * W * PLANE;             // both operands, all words
   static constexpr int OPER_BYTES = 2 * BUF * 2;        // 2 buffers, 2 B per element
-  static constexpr int SLD = TILE + 1;                  // FP32 staging row stride
-  static constexpr int STG_BYTES = TILE * SLD * 4;
+  static constexpr int SLD = TS + 1;                    // FP32 staging row stride
+  static constexpr int STG_BYTES = TS * SLD * 4;
   static constexpr int LDS_BYTES = OPER_BYTES > STG_BYTES ? OPER_BYTES : STG_BYTES;
+  static constexpr int NB = TS / 64;                    // 32x32 blocks per wave dimension
+  static constexpr int CHUNKS = TS * (BK / 8);          // 16-byte chunks per operand word plane
+  static constexpr int CPT = CHUNKS / 256;              // chunks per thread
   // Word products (a, b) kept: weight 2^-8(a+b) >= 2^-8(W-1).
   static constexpr int NPROD = W == 1 ? 1 : (W == 2 ? 3 : 6);
+  // Register sets for the global-load prefetch: two (loads run two K-steps
+  // ahead) unless the accumulators of a 192 tile leave no room.
+  static constexpr int DEPTH = (TS == 192 && W >= 2) ? 1 : 2;
+  static_assert(CHUNKS % 256 == 0, "tile rows must split evenly over the work-group");
 };
 
 __device__ __forceinline__ constexpr int prod_a(int W, int p) {
@@ -44,141 +59,170 @@ __device__ __forceinline__ constexpr int prod_b(int W, int p) {
   return W == 1 ? 0 : (W == 2 ? (p == 1 ? 1 : 0) : (p < 3 ? (p == 1 ? 1 : 0) : (p == 3 ? 2 : (p == 4 ? 1 : 0))));
 }
 
-template <int W, int MODE>
+template <int W, int MODE, int TS>
 __global__ __launch_bounds__(256) void k_sym_gemm_w(const uint16_t* __restrict__ A,
                                                     const uint16_t* __restrict__ B,
                                                     const uint16_t* __restrict__ Xold,
                                                     uint16_t* __restrict__ out, int ld, int64_t ps,
-                                                    int d, int dp, const int2* __restrict__ tiles,
+                                                    int d, int dk, const int2* __restrict__ tiles,
                                                     double* __restrict__ partials) {
-  typedef WCfg<W> C;
+  typedef WCfg<W, TS> C;
+  constexpr int NB = C::NB;
   __shared__ __attribute__((aligned(16))) unsigned char lds_raw[C::LDS_BYTES];
   __shared__ double red[4];
   uint16_t* lds = reinterpret_cast<uint16_t*>(lds_raw);
 
   const int2 tl = tiles[blockIdx.x];
-  const int i0 = tl.x * TILE, j0 = tl.y * TILE;
+  const int i0 = tl.x * TS, j0 = tl.y * TS;
   const bool diag = (tl.x == tl.y);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // Loader: thread -> row (tid >> 1), 16 consecutive k at (tid & 1) * 16:
-  // two 16 B vectors per word plane per operand.
-  const int lrow = tid >> 1, lk = (tid & 1) * 16;
-  const int64_t goffA = (int64_t)(i0 + lrow) * ld + lk;
-  const int64_t goffB = (int64_t)(j0 + lrow) * ld + lk;
-  u32x4_t ra[W][2], rb[W][2];
+  // Loader: chunk q = tid + 256 i -> row q / 4, 16-byte chunk q % 4 of the
+  // K-slice (consecutive threads read consecutive 16 B of a row).
+  int64_t goffA[C::CPT], goffB[C::CPT];
+  int soff[C::CPT];
+#pragma unroll
+  for (int i = 0; i < C::CPT; ++i) {
+    const int q = tid + 256 * i, row = q >> 2, ch = q & 3;
+    goffA[i] = (int64_t)(i0 + row) * ld + ch * 8;
+    goffB[i] = (int64_t)(j0 + row) * ld + ch * 8;
+    soff[i] = row * C::LDA + ch * 8;
+  }
+  u32x4_t ra[W][C::DEPTH][C::CPT], rb[W][C::DEPTH][C::CPT];
 
-  f32x16_t acc[2][2];
+  f32x16_t acc[NB][NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  const int nk = dp / C::BK;
-  auto gload = [&](int kt) {
+  const int nk = dk / C::BK;
+  auto gload = [&](int kt, int set) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const u32x4_t* pa = reinterpret_cast<const u32x4_t*>(A + w * ps + goffA + kt * C::BK);
-      const u32x4_t* pb = reinterpret_cast<const u32x4_t*>(B + w * ps + goffB + kt * C::BK);
-      ra[w][0] = pa[0];
-      ra[w][1] = pa[1];
-      rb[w][0] = pb[0];
-      rb[w][1] = pb[1];
-    }
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int i = 0; i < C::CPT; ++i) {
+        ra[w][set][i] = *reinterpret_cast<const u32x4_t*>(A + w * ps + goffA[i] + kt * C::BK);
+        rb[w][set][i] = *reinterpret_cast<const u32x4_t*>(B + w * ps + goffB[i] + kt * C::BK);
+      }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int set) {
     uint16_t* base = lds + buf * C::BUF;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      u32x4_t* da = reinterpret_cast<u32x4_t*>(base + w * C::PLANE + lrow * C::LDA + lk);
-      u32x4_t* db = reinterpret_cast<u32x4_t*>(base + (W + w) * C::PLANE + lrow * C::LDA + lk);
-      da[0] = ra[w][0];
-      da[1] = ra[w][1];
-      db[0] = rb[w][0];
-      db[1] = rb[w][1];
-    }
+    for (int w = 0; w < W; ++w)
+#pragma unroll
+      for (int i = 0; i < C::CPT; ++i) {
+        *reinterpret_cast<u32x4_t*>(base + w * C::PLANE + soff[i]) = ra[w][set][i];
+        *reinterpret_cast<u32x4_t*>(base + (W + w) * C::PLANE + soff[i]) = rb[w][set][i];
+      }
   };
-
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
-    const uint16_t* base = lds + cur * C::BUF;
+  auto compute = [&](int buf) {
+    const uint16_t* base = lds + buf * C::BUF;
 #pragma unroll
     for (int kk = 0; kk < C::BK / 16; ++kk) {
-      bf16x8_t af[W][2], bfr[W][2];
+      bf16x8_t af[W][NB], bfr[W][NB];
       const int kof = kk * 16 + (lane >> 5) * 8;
 #pragma unroll
       for (int w = 0; w < W; ++w)
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
+        for (int a = 0; a < NB; ++a) {
           af[w][a] = *reinterpret_cast<const bf16x8_t*>(
-              base + w * C::PLANE + (wr * 64 + a * 32 + (lane & 31)) * C::LDA + kof);
+              base + w * C::PLANE + (wr * (TS / 2) + a * 32 + (lane & 31)) * C::LDA + kof);
           bfr[w][a] = *reinterpret_cast<const bf16x8_t*>(
-              base + (W + w) * C::PLANE + (wc * 64 + a * 32 + (lane & 31)) * C::LDA + kof);
+              base + (W + w) * C::PLANE + (wc * (TS / 2) + a * 32 + (lane & 31)) * C::LDA + kof);
         }
       // Smaller word products first.
 #pragma unroll
       for (int p = C::NPROD - 1; p >= 0; --p)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < NB; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(W, p)][a],
                                                                bfr[prod_b(W, p)][b], acc[a][b],
                                                                0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+
+  if constexpr (C::DEPTH == 2) {
+    // LDS buffer kt & 1 holds K-slice kt; register set (kt + 1) & 1 holds or
+    // receives slice kt + 1 while slice kt + 2 is fetched into the other set.
+    gload(0, 0);
+    if (nk > 1) gload(1, 1 % C::DEPTH);
+    sstore(0, 0);
     __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      // even step: register set 1 holds slice kt + 1, set 0 is free
+      if (kt + 2 < nk) gload(kt + 2, 0);
+      compute(0);
+      if (kt + 1 < nk) sstore(1, 1 % C::DEPTH);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      // odd step: set 0 holds slice kt + 2, set 1 is free
+      if (kt + 3 < nk) gload(kt + 3, 1 % C::DEPTH);
+      compute(1);
+      if (kt + 2 < nk) sstore(0, 0);
+      __syncthreads();
+    }
+  } else {
+    // One register set: slice kt + 1 is fetched while slice kt is multiplied.
+    gload(0, 0);
+    sstore(0, 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + 1 < nk) gload(kt + 1, 0);
+      compute(kt & 1);
+      if (kt + 1 < nk) sstore((kt + 1) & 1, 0);
+      __syncthreads();
+    }
   }
 
   // ---- epilogue: stage the FP32 tile.  32x32 block layout: lane holds
   // column lane&31, rows 8*(r>>2) + 4*(lane>>5) + (r&3), r = 0..15. ----
   float* stg = reinterpret_cast<float*>(lds_raw);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = wr * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int col = wc * 64 + b * 32 + (lane & 31);
+        const int row = wr * (TS / 2) + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wc * (TS / 2) + b * 32 + (lane & 31);
         stg[row * C::SLD + col] = acc[a][b][r];
       }
   __syncthreads();
 
   // Direct pass: 8 consecutive entries (one 16 B vector per word plane) per
-  // thread; 16 threads per tile row, 16 rows per iteration.
-  constexpr int VE = 8, LPR = TILE / VE, RPI = 256 / LPR, NIT = TILE / RPI;
-  const int cofs = (tid % LPR) * VE;
+  // thread and iteration, row-contiguous.  In a diagonal tile entry (r, c)
+  // takes the value computed at (min, max), so the stored tile is exactly
+  // symmetric; off-diagonal tiles write their final values back in place for
+  // the transposed pass.
+  constexpr int VE = 8, CPR = TS / VE;
   double part = 0.0;
-  float vals[NIT][VE];
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int r = it * RPI + tid / LPR;
+  for (int e = tid; e < TS * CPR; e += 256) {
+    const int r = e / CPR, cofs = (e % CPR) * VE;
     const int gi = i0 + r;
     float xo[VE];
     if (MODE == GEMM_UPDATE) {
 #pragma unroll
-      for (int e = 0; e < VE; ++e) xo[e] = 0.f;
+      for (int q = 0; q < VE; ++q) xo[q] = 0.f;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         alignas(16) uint16_t xw[VE];
         *reinterpret_cast<u32x4_t*>(xw) =
             *reinterpret_cast<const u32x4_t*>(Xold + w * ps + (int64_t)gi * ld + j0 + cofs);
 #pragma unroll
-        for (int e = 0; e < VE; ++e) xo[e] += bf16_to_f32(xw[e]);
+        for (int q = 0; q < VE; ++q) xo[q] += bf16_to_f32(xw[q]);
       }
     }
     alignas(16) uint16_t ow[W][VE];
+    float nv[VE];
 #pragma unroll
-    for (int e = 0; e < VE; ++e) {
-      const int c = cofs + e;
+    for (int q = 0; q < VE; ++q) {
+      const int c = cofs + q;
       const int rr = (diag && r > c) ? c : r, cc = (diag && r > c) ? r : c;
       const float v = stg[rr * C::SLD + cc];
       const int gj = j0 + c;
@@ -187,43 +231,40 @@ __global__ __launch_bounds__(256) void k_sym_gemm_w(const uint16_t* __restrict__
         n = ((gi == gj && gi < d) ? 1.f : 0.f) - v;
         part += (diag ? 1.0 : 2.0) * (double)n * (double)n;
       } else {
-        n = xo[e] + 0.5f * v;
+        n = xo[q] + 0.5f * v;
         if (gi == gj) part += (double)n;
       }
-      vals[it][e] = n;
+      nv[q] = n;
       uint16_t wv[W];
       split_words<W>(n, wv);
 #pragma unroll
-      for (int w = 0; w < W; ++w) ow[w][e] = wv[w];
+      for (int w = 0; w < W; ++w) ow[w][q] = wv[w];
+    }
+    if (!diag) {
+#pragma unroll
+      for (int q = 0; q < VE; ++q) stg[r * C::SLD + cofs + q] = nv[q];
     }
 #pragma unroll
     for (int w = 0; w < W; ++w)
       *reinterpret_cast<u32x4_t*>(out + w * ps + (int64_t)gi * ld + j0 + cofs) =
           *reinterpret_cast<const u32x4_t*>(ow[w]);
   }
-  __syncthreads();
   if (!diag) {
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int r = it * RPI + tid / LPR;
-#pragma unroll
-      for (int e = 0; e < VE; ++e) stg[r * C::SLD + cofs + e] = vals[it][e];
-    }
     __syncthreads();
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int c = it * RPI + tid / LPR;  // output row j0 + c
+    // Transposed pass: output row j0 + c, columns i0 + rofs .. + 7.
+    for (int e = tid; e < TS * CPR; e += 256) {
+      const int c = e / CPR, rofs = (e % CPR) * VE;
       alignas(16) uint16_t ow[W][VE];
 #pragma unroll
-      for (int e = 0; e < VE; ++e) {
+      for (int q = 0; q < VE; ++q) {
         uint16_t wv[W];
-        split_words<W>(stg[(cofs + e) * C::SLD + c], wv);
+        split_words<W>(stg[(rofs + q) * C::SLD + c], wv);
 #pragma unroll
-        for (int w = 0; w < W; ++w) ow[w][e] = wv[w];
+        for (int w = 0; w < W; ++w) ow[w][q] = wv[w];
       }
 #pragma unroll
       for (int w = 0; w < W; ++w)
-        *reinterpret_cast<u32x4_t*>(out + w * ps + (int64_t)(j0 + c) * ld + i0 + cofs) =
+        *reinterpret_cast<u32x4_t*>(out + w * ps + (int64_t)(j0 + c) * ld + i0 + rofs) =
             *reinterpret_cast<const u32x4_t*>(ow[w]);
     }
   }
@@ -231,30 +272,53 @@ __global__ __launch_bounds__(256) void k_sym_gemm_w(const uint16_t* __restrict__
   if (tid == 0) partials[blockIdx.x] = tot;
 }
 
-template <int W>
+template <int W, int TS>
 static hipError_t launch_w(int mode, const uint16_t* A, const uint16_t* B, const uint16_t* Xold,
-                           uint16_t* out, int ld, int64_t ps, int d, int dp, const int2* tiles,
+                           uint16_t* out, int ld, int64_t ps, int d, int dk, const int2* tiles,
                            int ntiles, double* partials, hipStream_t st) {
   if (mode == GEMM_RESIDUAL)
-    hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_RESIDUAL>), dim3(ntiles), dim3(256), 0, st, A, B,
-                       Xold, out, ld, ps, d, dp, tiles, partials);
+    hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
+                       Xold, out, ld, ps, d, dk, tiles, partials);
   else
-    hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_UPDATE>), dim3(ntiles), dim3(256), 0, st, A, B, Xold,
-                       out, ld, ps, d, dp, tiles, partials);
+    hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
+                       Xold, out, ld, ps, d, dk, tiles, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_sym_gemm_words(int words, int mode, const uint16_t* A, const uint16_t* B,
-                                 const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d,
-                                 int dp, const int2* tiles, int ntiles, double* partials,
-                                 hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
+template <int TS>
+static hipError_t launch_ts_impl(int words, int mode, const uint16_t* A, const uint16_t* B,
+                            const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d, int dk,
+                            const int2* tiles, int ntiles, double* partials, hipStream_t st) {
   switch (words) {
-    case 1: return launch_w<1>(mode, A, B, Xold, out, ld, ps, d, dp, tiles, ntiles, partials, st);
-    case 2: return launch_w<2>(mode, A, B, Xold, out, ld, ps, d, dp, tiles, ntiles, partials, st);
-    case 3: return launch_w<3>(mode, A, B, Xold, out, ld, ps, d, dp, tiles, ntiles, partials, st);
+    case 1: return launch_w<1, TS>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    case 2: return launch_w<2, TS>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
     default: return hipErrorInvalidValue;
   }
+}
+template <>
+hipError_t launch_ts_impl<128>(int words, int mode, const uint16_t* A, const uint16_t* B,
+                               const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d,
+                               int dk, const int2* tiles, int ntiles, double* partials,
+                               hipStream_t st) {
+  switch (words) {
+    case 1: return launch_w<1, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    case 2: return launch_w<2, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    case 3: return launch_w<3, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sym_gemm_words(int words, int tile, int mode, const uint16_t* A,
+                                 const uint16_t* B, const uint16_t* Xold, uint16_t* out, int ld,
+                                 int64_t ps, int d, int dk, const int2* tiles, int ntiles,
+                                 double* partials, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (tile == 128)
+    return launch_ts_impl<128>(words, mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+  // 192-row tiles need 4 * 192 * 80 B of operand LDS per word: W <= 2 only.
+  if (tile == 192 && words <= 2)
+    return launch_ts_impl<192>(words, mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace refl

@@ -25,11 +25,13 @@ hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const f
 
 // Products of matrices held as W BF16 words per entry (planes ps elements
 // apart), FP32 accumulation on 32x32x16 BF16 MFMA.  Word products kept:
-// W=1 {00}; W=2 {00,01,10}; W=3 {00,01,10,02,11,20}.
-hipError_t launch_sym_gemm_words(int words, int mode, const uint16_t* A, const uint16_t* B,
-                                 const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d,
-                                 int dp, const int2* tiles, int ntiles, double* partials,
-                                 hipStream_t st);
+// W=1 {00}; W=2 {00,01,10}; W=3 {00,01,10,02,11,20}.  tile = 128 or 192
+// (192 for W <= 2); tiles in units of `tile`; the matrices are zero outside
+// the leading d x d block and K runs over dk = d rounded up to 32.
+hipError_t launch_sym_gemm_words(int words, int tile, int mode, const uint16_t* A,
+                                 const uint16_t* B, const uint16_t* Xold, uint16_t* out, int ld,
+                                 int64_t ps, int d, int dk, const int2* tiles, int ntiles,
+                                 double* partials, hipStream_t st);
 
 // ---- set-up: H (upper triangle) -> padded full FP64 copy, scale, X_0 ----
 hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, int dp,
@@ -80,6 +82,12 @@ hipError_t thin_gemm_f32(const float* M, int64_t ldm, int d, const double* V, in
 hipError_t thin_gemm_words(int words, const uint16_t* X, int ld, int64_t ps, int d,
                            const double* V, int64_t ldv, int nb, double* Y, int64_t ldy,
                            double* work, hipStream_t st);
+// The same for SYMMETRIC M (faster: column-per-lane, no cross-lane sums).
+hipError_t symthin_f64(const double* M, int64_t ldm, int d, const double* V, int64_t ldv, int nb,
+                       double* Y, int64_t ldy, double* work, hipStream_t st);
+hipError_t symthin_words(int words, const uint16_t* X, int ld, int64_t ps, int d, const double* V,
+                         int64_t ldv, int nb, double* Y, int64_t ldy, double* work,
+                         hipStream_t st);
 // G (na x nb, column-major) = A^T B; work: gram_work_doubles(d) doubles.
 size_t gram_work_doubles(int d);
 hipError_t gram(const double* A, int64_t lda, int na, const double* B, int64_t ldb, int nb, int d,
@@ -101,16 +109,16 @@ hipError_t random_block(double* V, int64_t ldv, int d, int nb, uint64_t seed, hi
 
 // ---- block CG (see misc.hip) ----
 struct CgHost {
-  double theta[32], rho[32], rho0[32], alpha[32], beta[32];
-  double C[32 * 32];
+  double theta[32], rho0[32], rho[2][32], beta[32];
   double tol2;
   int iters, done, k, nb;
-  unsigned int counter[2];
 };
 size_t cg_state_bytes();
 size_t cg_part_doubles(int d);
+// One CG iteration; `it` counts from 0 within a solve.
 hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const double* V, int64_t ldv,
                         double* Rr, const double* Pold, double* Pnext, double* AP, double* Z,
-                        void* state, double* work, double* part, int max_iter, hipStream_t st);
+                        void* state, double* work, double* part, int it, int max_iter,
+                        hipStream_t st);
 
 }  // namespace refl

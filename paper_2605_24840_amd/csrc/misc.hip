@@ -276,11 +276,13 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
 }
 __global__ __launch_bounds__(256) void k_gram_finish(const double* __restrict__ work, int nblk,
                                                      int n, double* __restrict__ G) {
-  for (int o = blockIdx.x * 256 + threadIdx.x; o < n; o += gridDim.x * 256) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += work[(int64_t)b * n + o];
-    G[o] = s;
-  }
+  // One wave per output; lanes own blocks in a fixed order.
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (o >= n) return;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += work[(int64_t)b * n + o];
+  s = wave_sum(s);
+  if (lane == 0) G[o] = s;
 }
 
 // Y[:, c] = alpha Y[:, c] + beta sum_i A[:, i] C[i, c]
@@ -351,203 +353,249 @@ __global__ __launch_bounds__(256) void k_random_block(double* __restrict__ V, in
   }
 }
 
+// ------------------------------------------------- symmetric thin products
+// Y = M V for SYMMETRIC M, computed as M^T V: y_r = sum_j M[j, r] V[j, :].
+// Block = 256 threads = 256 consecutive output rows r (one per lane), and a
+// chunk of SRC rows j of M; the rows of M stream coalesced across the lanes,
+// the SRC x NB block of V sits in LDS and is read as a wave-uniform
+// broadcast, and no cross-lane reduction is needed.  Partial sums per chunk
+// go to work[chunk][c][r]; a finishing kernel adds the chunks in order.
+constexpr int SRC = 128;
+
+template <typename MT, int NB>
+__device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t ldm, int64_t ps, int d,
+                                             const double (*pv)[NB], double* __restrict__ work,
+                                             int64_t wld, int nb) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * SRC;
+  const int jn = min(SRC, d - j0);
+  double acc[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+  if (r < d) {
+    int jj = 0;
+    for (; jj + 8 <= jn; jj += 8) {
+      double m[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m[u] = MLoad<MT>::at(M, (int64_t)(j0 + jj + u) * ldm + r, ps);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pv[jj + u][c], acc[c]);
+    }
+    for (; jj < jn; ++jj) {
+      const double m = MLoad<MT>::at(M, (int64_t)(j0 + jj) * ldm + r, ps);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] = fma(m, pv[jj][c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) work[((int64_t)blockIdx.y * NB + c) * wld + r] = acc[c];
+  }
+}
+
+template <typename MT, int NB>
+__global__ __launch_bounds__(256) void k_symthin(const MT* __restrict__ M, int64_t ldm, int64_t ps,
+                                                 int d, const double* __restrict__ V, int64_t ldv,
+                                                 int nb, double* __restrict__ work, int64_t wld) {
+  __shared__ double pv[SRC][NB];
+  const int j0 = blockIdx.y * SRC;
+  for (int e = threadIdx.x; e < SRC * NB; e += 256) {
+    const int jj = e / NB, c = e % NB, j = j0 + jj;
+    pv[jj][c] = (j < d && c < nb) ? V[(int64_t)c * ldv + j] : 0.0;
+  }
+  __syncthreads();
+  symthin_body<MT, NB>(M, ldm, ps, d, pv, work, wld, nb);
+}
+
 // ------------------------------------------------------------ block CG
 // Solves, column by column (c < nb), the projected correction equations
 //   (I - V V^T)(H - theta_c I)(I - V V^T) z_c = b_c,  z_c, b_c orthogonal to V,
 // by conjugate gradients (the operator is positive definite on the
-// complement of V when theta_c lies below the spectrum there).  One
-// iteration = k_thin_partial on P (formed on the fly as Rr + beta P_old),
-// k_cg_apply (operator finish, projection coefficients, alpha), k_cg_update
-// (z, r updates, beta, convergence).  Per-column scalars live in CgState.
-// Each kernel returns at once when state->done is set, so a batch of
-// iterations can be enqueued without host synchronisation.
+// complement of V when theta_c lies below the spectrum there).
+//
+// Iteration `it` is three launches with no atomics or fences between
+// blocks: each kernel re-reduces, in a fixed order, the per-block partial
+// sums the previous kernel wrote, and the kernel boundary makes them
+// visible.
+//   k_cg_thin    rho_c = |r_c|^2 (partials of the last update; rho0 at it 0),
+//                convergence test, beta_c = rho_c / rho_prev; block 0
+//                records rho, beta, iters, done.  Then the chunk partials of
+//                M p with p = r + beta p_old formed in LDS.
+//   k_cg_apply   Ap = chunk sums - theta_c p; p_next = p; per-block partials
+//                of V^T Ap and p . Ap.
+//   k_cg_update  reduces those for its column: C = V^T Ap, alpha_c =
+//                rho_c / (p . Ap); z += alpha p, r -= alpha (Ap - V C);
+//                per-block partials of |r_c|^2.
+// Every kernel returns at once when state->done is set, so batches of
+// iterations are enqueued without host synchronisation.
 struct CgState {
-  double theta[32], rho[32], rho0[32], alpha[32], beta[32];
-  double C[32 * 32];      // V^T (H - theta) p, k x nb column-major
+  double theta[32], rho0[32], rho[2][32], beta[32];
   double tol2;
   int iters, done, k, nb;
-  unsigned int counter[2];
 };
 
-template <int NB, int CH>
+// Grid (column blocks of 256 output rows, chunks of SRC rows of M).
+template <int NB>
 __global__ __launch_bounds__(256) void k_cg_thin(const double* __restrict__ M, int64_t ldm, int d,
                                                  const double* __restrict__ Rr,
                                                  const double* __restrict__ Pold, int64_t ldv,
-                                                 const CgState* __restrict__ st,
-                                                 double* __restrict__ work, int64_t wld) {
+                                                 CgState* __restrict__ st,
+                                                 const double* __restrict__ upart, int ngroups,
+                                                 double* __restrict__ work, int64_t wld, int it,
+                                                 int max_iter) {
   if (st->done) return;
-  constexpr int PER = CH / 64;
+  __shared__ double pv[SRC][NB];
+  __shared__ double sbeta[NB];
+  __shared__ int sdone;
   const int nb = st->nb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int j0 = blockIdx.y * CH;
-  double v[PER][NB];
+  if (threadIdx.x == 0) sdone = 0;
+  if (threadIdx.x < NB) sbeta[threadIdx.x] = 0.0;
+  __syncthreads();
+  if (it > 0 && wave == 0) {
+    int conv = 1;
+    for (int c0 = 0; c0 < nb; c0 += 8) {
+      double a[8];
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int j = j0 + t * 64 + lane;
+      for (int u = 0; u < 8; ++u) {
+        a[u] = 0.0;
+        if (c0 + u < nb)
+          for (int g = lane; g < ngroups; g += 64) a[u] += upart[(int64_t)g * nb + c0 + u];
+      }
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      v[t][c] = (j < d && c < nb)
-                    ? Rr[(int64_t)c * ldv + j] + st->beta[c] * Pold[(int64_t)c * ldv + j]
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u;
+        if (c < nb) {
+          const double rho = wave_sum(a[u]);
+          const double prev = st->rho[(it - 1) & 1][c];
+          const double beta = prev > 0.0 ? rho / prev : 0.0;
+          if (!(rho <= st->tol2 * st->rho0[c])) conv = 0;
+          if (lane == 0) {
+            sbeta[c] = beta;
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
+              st->rho[it & 1][c] = rho;
+              st->beta[c] = beta;
+            }
+          }
+        }
+      }
+    }
+    if (lane == 0 && (conv || it >= max_iter)) {
+      sdone = 1;
+      if (blockIdx.x == 0 && blockIdx.y == 0) {
+        st->iters = it;
+        st->done = 1;
+      }
+    }
+  } else if (it == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < nb) {
+    st->rho[0][threadIdx.x] = st->rho0[threadIdx.x];
+    st->beta[threadIdx.x] = 0.0;
+  }
+  __syncthreads();
+  if (sdone) return;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st->iters = it + 1;
+  const int j0 = blockIdx.y * SRC;
+  for (int e = threadIdx.x; e < SRC * NB; e += 256) {
+    const int jj = e / NB, c = e % NB, j = j0 + jj;
+    pv[jj][c] = (j < d && c < nb)
+                    ? Rr[(int64_t)c * ldv + j] + sbeta[c] * Pold[(int64_t)c * ldv + j]
                     : 0.0;
   }
-  const int rbeg = blockIdx.x * 64 + wave * 16;
-  for (int rr = 0; rr < 16; ++rr) {
-    const int row = rbeg + rr;
-    if (row >= d) break;
-    double acc[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) acc[c] = 0.0;
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int j = j0 + t * 64 + lane;
-      const double m = (j < d) ? M[(int64_t)row * ldm + j] : 0.0;
-#pragma unroll
-      for (int c = 0; c < NB; ++c) acc[c] = fma(m, v[t][c], acc[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double s = wave_sum(acc[c]);
-      if (lane == 0 && c < nb) work[((int64_t)blockIdx.y * NB + c) * wld + row] = s;
-    }
-  }
+  __syncthreads();
+  symthin_body<double, NB>(M, ldm, 0, d, pv, work, wld, nb);
 }
 
-// AP = M P - theta P; P_next = P; partial V^T AP and P . AP; last block: C, alpha.
+// Grid (row groups of 64, column c): one wave per block, one row per lane.
 template <int NB>
-__global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ work, int64_t wld,
-                                                  int nchunk, int d, const double* __restrict__ V,
-                                                  const double* __restrict__ Rr,
-                                                  const double* __restrict__ Pold,
-                                                  double* __restrict__ Pnext,
-                                                  double* __restrict__ AP, int64_t ldv,
-                                                  CgState* __restrict__ st,
-                                                  double* __restrict__ part) {
+__global__ __launch_bounds__(64) void k_cg_apply(const double* __restrict__ work, int64_t wld,
+                                                 int nchunk, int d, const double* __restrict__ V,
+                                                 const double* __restrict__ Rr,
+                                                 const double* __restrict__ Pold,
+                                                 double* __restrict__ Pnext,
+                                                 double* __restrict__ AP, int64_t ldv,
+                                                 const CgState* __restrict__ st,
+                                                 double* __restrict__ apart) {
   if (st->done) return;
   const int nb = st->nb, k = st->k;
-  const int nout = k * nb + nb;
-  __shared__ double sred[256 / 64][32 * 32 + 32];
-  __shared__ bool last;
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double p[NB], ap[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    p[c] = 0.0;
-    ap[c] = 0.0;
-  }
+  const int c = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int row = blockIdx.x * 64 + lane;
+  double pc = 0.0, s = 0.0;
   if (row < d) {
+    const int64_t o = (int64_t)c * ldv + row;
+    pc = Rr[o] + st->beta[c] * Pold[o];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int q = 0;
+    for (; q + 8 <= nchunk; q += 8) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c >= nb) break;
-      const double pc = Rr[(int64_t)c * ldv + row] + st->beta[c] * Pold[(int64_t)c * ldv + row];
-      double s = 0.0;
-      for (int q = 0; q < nchunk; ++q) s += work[((int64_t)q * NB + c) * wld + row];
-      s -= st->theta[c] * pc;
-      p[c] = pc;
-      ap[c] = s;
-      Pnext[(int64_t)c * ldv + row] = pc;
-      AP[(int64_t)c * ldv + row] = s;
+      for (int u = 0; u < 8; ++u) acc[u] += work[((int64_t)(q + u) * NB + c) * wld + row];
     }
+    for (; q < nchunk; ++q) acc[0] += work[((int64_t)q * NB + c) * wld + row];
+    s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    s -= st->theta[c] * pc;
+    Pnext[o] = pc;
+    AP[o] = s;
   }
-  // Partials: V^T AP (k x nb) then P . AP (nb).
+  // Partials: V^T Ap (k values) then p . Ap, at apart[group][c][0..k].
+  double* mypart = apart + ((int64_t)blockIdx.x * nb + c) * (k + 1);
   for (int i = 0; i < k; ++i) {
     const double vi = (row < d) ? V[(int64_t)i * ldv + row] : 0.0;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c >= nb) break;
-      const double s = wave_sum(vi * ap[c]);
-      if (lane == 0) sred[wave][i + k * c] = s;
-    }
+    const double t = wave_sum(vi * s);
+    if (lane == 0) mypart[i] = t;
   }
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c >= nb) break;
-    const double s = wave_sum(p[c] * ap[c]);
-    if (lane == 0) sred[wave][k * nb + c] = s;
-  }
-  __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += 256)
-    part[(int64_t)blockIdx.x * nout + o] = (sred[0][o] + sred[1][o]) + (sred[2][o] + sred[3][o]);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&st->counter[0], 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int o = threadIdx.x; o < nout; o += 256) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += part[(int64_t)b * nout + o];
-    if (o < k * nb)
-      st->C[o] = s;
-    else {
-      const int c = o - k * nb;
-      st->alpha[c] = (s != 0.0) ? st->rho[c] / s : 0.0;
-    }
-  }
-  if (threadIdx.x == 0) st->counter[0] = 0u;
+  const double t = wave_sum(pc * s);
+  if (lane == 0) mypart[k] = t;
 }
 
-// z += alpha p; r -= alpha (AP - V C); partial |r|^2; last block: beta, done.
+// Grid (row groups of 64, column c).
 template <int NB>
-__global__ __launch_bounds__(256) void k_cg_update(int d, const double* __restrict__ V,
-                                                   const double* __restrict__ P,
-                                                   const double* __restrict__ AP,
-                                                   double* __restrict__ Z, double* __restrict__ Rr,
-                                                   int64_t ldv, CgState* __restrict__ st,
-                                                   double* __restrict__ part, int max_iter) {
+__global__ __launch_bounds__(64) void k_cg_update(int d, const double* __restrict__ V,
+                                                  const double* __restrict__ P,
+                                                  const double* __restrict__ AP,
+                                                  double* __restrict__ Z, double* __restrict__ Rr,
+                                                  int64_t ldv, const CgState* __restrict__ st,
+                                                  const double* __restrict__ apart,
+                                                  double* __restrict__ upart, int it) {
   if (st->done) return;
   const int nb = st->nb, k = st->k;
-  __shared__ double sred[4][32];
-  __shared__ bool last;
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double rr[NB];
+  const int c = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int row = blockIdx.x * 64 + lane;
+  const int ngroups = gridDim.x;
+  __shared__ double sC[33];
+  // Reduce this column's apply partials (fixed order): C[:, c], p . Ap.
+  for (int i0 = 0; i0 <= k; i0 += 8) {
+    double a[8];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) rr[c] = 0.0;
+    for (int u = 0; u < 8; ++u) {
+      a[u] = 0.0;
+      if (i0 + u <= k)
+        for (int g = lane; g < ngroups; g += 64) a[u] += apart[((int64_t)g * nb + c) * (k + 1) + i0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u <= k) {
+        const double t = wave_sum(a[u]);
+        if (lane == 0) sC[i0 + u] = t;
+      }
+    }
+  }
+  __syncthreads();
+  const double alpha = (sC[k] != 0.0) ? st->rho[it & 1][c] / sC[k] : 0.0;
+  double rr = 0.0;
   if (row < d) {
-    double vrow[32];
-    for (int i = 0; i < k; ++i) vrow[i] = V[(int64_t)i * ldv + row];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c >= nb) break;
-      double proj = 0.0;
-      for (int i = 0; i < k; ++i) proj = fma(vrow[i], st->C[i + k * c], proj);
-      const int64_t o = (int64_t)c * ldv + row;
-      const double a = st->alpha[c];
-      Z[o] = fma(a, P[o], Z[o]);
-      const double r = Rr[o] - a * (AP[o] - proj);
-      Rr[o] = r;
-      rr[c] = r * r;
-    }
+    double proj = 0.0;
+    for (int i = 0; i < k; ++i) proj = fma(V[(int64_t)i * ldv + row], sC[i], proj);
+    const int64_t o = (int64_t)c * ldv + row;
+    const double pz = P[o], ap = AP[o], z = Z[o], r0 = Rr[o];
+    Z[o] = fma(alpha, pz, z);
+    const double r = r0 - alpha * (ap - proj);
+    Rr[o] = r;
+    rr = r * r;
   }
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    if (c >= nb) break;
-    const double s = wave_sum(rr[c]);
-    if (lane == 0) sred[wave][c] = s;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < nb; c += 256)
-    part[(int64_t)blockIdx.x * nb + c] = (sred[0][c] + sred[1][c]) + (sred[2][c] + sred[3][c]);
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&st->counter[1], 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    int conv = 1;
-    for (int c = 0; c < nb; ++c) {
-      double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += part[(int64_t)b * nb + c];
-      st->beta[c] = (st->rho[c] > 0.0) ? s / st->rho[c] : 0.0;
-      st->rho[c] = s;
-      if (!(s <= st->tol2 * st->rho0[c])) conv = 0;
-    }
-    st->iters += 1;
-    if (conv || st->iters >= max_iter) st->done = 1;
-    st->counter[1] = 0u;
-  }
+  const double t = wave_sum(rr);
+  if (lane == 0) upart[(int64_t)blockIdx.x * nb + c] = t;
 }
 
 template <int W>
@@ -728,7 +776,7 @@ hipError_t gram(const double* A, int64_t lda, int na, const double* B, int64_t l
                 double* G, double* work, hipStream_t st) {
   const int nblk = nblocks(d, 64);
   hipLaunchKernelGGL(k_gram_partial, dim3(nblk), dim3(256), 0, st, A, lda, na, B, ldb, nb, d, work);
-  hipLaunchKernelGGL(k_gram_finish, dim3(nblocks(na * nb, 256)), dim3(256), 0, st, work, nblk,
+  hipLaunchKernelGGL(k_gram_finish, dim3(nblocks(na * nb, 4)), dim3(256), 0, st, work, nblk,
                      na * nb, G);
   return hipGetLastError();
 }
@@ -758,31 +806,79 @@ size_t cg_state_bytes() {
   static_assert(sizeof(CgState) == sizeof(CgHost), "CgState and CgHost must match");
   return sizeof(CgState);
 }
-size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 256) * (32 * 32 + 32); }
-size_t thin_work_doubles(int d) { return (size_t)nblocks(d, 128) * 32 * (size_t)d; }
+size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 34; }
+size_t thin_work_doubles(int d) {
+  const size_t a = (size_t)nblocks(d, 128) * 32 * (size_t)d;
+  const size_t b = (size_t)nblocks(d, SRC) * 32 * (size_t)d;
+  return a > b ? a : b;
+}
 size_t gram_work_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 32; }
 
-// One CG iteration (three launches).  Pold/Pnext alternate between calls.
+// Symmetric thin products (Hf, the word iterate): column-lane kernel plus
+// the ordered chunk sum.
+template <typename MT>
+static hipError_t symthin_dispatch(const MT* M, int64_t ldm, int64_t ps, int d, const double* V,
+                                   int64_t ldv, int nb, double* Y, int64_t ldy, double* work,
+                                   hipStream_t st) {
+  const int64_t wld = d;
+  const dim3 grid(nblocks(d, 256), nblocks(d, SRC));
+#define REFL_STHIN(NBV)                                                                          \
+  {                                                                                              \
+    hipLaunchKernelGGL((k_symthin<MT, NBV>), grid, dim3(256), 0, st, M, ldm, ps, d, V, ldv, nb,  \
+                       work, wld);                                                               \
+    hipLaunchKernelGGL((k_thin_finish<NBV>), dim3(nblocks(d, 256), nb), dim3(256), 0, st, work,  \
+                       wld, (int)grid.y, d, nb, Y, ldy);                                         \
+  }
+  if (nb <= 0) return hipSuccess;
+  if (nb <= 4) REFL_STHIN(4)
+  else if (nb <= 8) REFL_STHIN(8)
+  else if (nb <= 16) REFL_STHIN(16)
+  else if (nb <= 32) REFL_STHIN(32)
+  else return hipErrorInvalidValue;
+#undef REFL_STHIN
+  return hipGetLastError();
+}
+
+hipError_t symthin_f64(const double* M, int64_t ldm, int d, const double* V, int64_t ldv, int nb,
+                       double* Y, int64_t ldy, double* work, hipStream_t st) {
+  return symthin_dispatch<double>(M, ldm, 0, d, V, ldv, nb, Y, ldy, work, st);
+}
+hipError_t symthin_words(int words, const uint16_t* X, int ld, int64_t ps, int d, const double* V,
+                         int64_t ldv, int nb, double* Y, int64_t ldy, double* work,
+                         hipStream_t st) {
+  switch (words) {
+    case 1: return symthin_dispatch<WordsM<1>>(reinterpret_cast<const WordsM<1>*>(X), ld, ps, d, V, ldv, nb, Y, ldy, work, st);
+    case 2: return symthin_dispatch<WordsM<2>>(reinterpret_cast<const WordsM<2>*>(X), ld, ps, d, V, ldv, nb, Y, ldy, work, st);
+    case 3: return symthin_dispatch<WordsM<3>>(reinterpret_cast<const WordsM<3>*>(X), ld, ps, d, V, ldv, nb, Y, ldy, work, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One CG iteration (three launches).  Pold/Pnext alternate between calls;
+// `it` counts from 0.  part holds the apply partials, then the update ones.
 hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const double* V, int64_t ldv,
                         double* Rr, const double* Pold, double* Pnext, double* AP, double* Z,
-                        void* state, double* work, double* part, int max_iter, hipStream_t st) {
+                        void* state, double* work, double* part, int it, int max_iter,
+                        hipStream_t st) {
   CgState* s = reinterpret_cast<CgState*>(state);
   const int64_t wld = d;
-  const int rows = nblocks(d, 64), nrb = nblocks(d, 256);
-#define REFL_CG(NBV, CHV)                                                                        \
+  const dim3 grid(nblocks(d, 256), nblocks(d, SRC));
+  const int nrb = nblocks(d, 64);
+  double* apart = part;
+  double* upart = part + (size_t)nrb * 32 * 33;
+#define REFL_CG(NBV)                                                                             \
   {                                                                                              \
-    const int nch = nblocks(d, CHV);                                                             \
-    hipLaunchKernelGGL((k_cg_thin<NBV, CHV>), dim3(rows, nch), dim3(256), 0, st, M, ldm, d, Rr,   \
-                       Pold, ldv, s, work, wld);                                                 \
-    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb), dim3(256), 0, st, work, wld, nch, d, V, Rr,  \
-                       Pold, Pnext, AP, ldv, s, part);                                           \
-    hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrb), dim3(256), 0, st, d, V, Pnext, AP, Z, Rr,   \
-                       ldv, s, part, max_iter);                                                  \
+    hipLaunchKernelGGL((k_cg_thin<NBV>), grid, dim3(256), 0, st, M, ldm, d, Rr, Pold, ldv, s,    \
+                       upart, nrb, work, wld, it, max_iter);                                     \
+    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb, nb), dim3(64), 0, st, work, wld, (int)grid.y, \
+                       d, V, Rr, Pold, Pnext, AP, ldv, s, apart);                                \
+    hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrb, nb), dim3(64), 0, st, d, V, Pnext, AP, Z,    \
+                       Rr, ldv, s, apart, upart, it);                                            \
   }
-  if (nb <= 4) REFL_CG(4, 256)
-  else if (nb <= 8) REFL_CG(8, 256)
-  else if (nb <= 16) REFL_CG(16, 256)
-  else if (nb <= 32) REFL_CG(32, 128)
+  if (nb <= 4) REFL_CG(4)
+  else if (nb <= 8) REFL_CG(8)
+  else if (nb <= 16) REFL_CG(16)
+  else if (nb <= 32) REFL_CG(32)
   else return hipErrorInvalidValue;
 #undef REFL_CG
   return hipGetLastError();

@@ -23,10 +23,12 @@
 // H - sI when the iterate is accurate.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -47,6 +49,7 @@ struct refl_handle_s {
   size_t ws_own_bytes = 0;
   double* pinned = nullptr;  // host pinned scalars (SC_COUNT doubles + CG state)
   std::vector<hipEvent_t> ev;  // params.timing: start/stop pairs of the bulk products
+  int ncu = 256;               // compute units of the device
   char err[512] = {0};
 };
 
@@ -97,6 +100,7 @@ constexpr int MAXB = 32;  // widest block of vectors
 
 struct Work {
   int d, dp, ntiles, words;
+  int ts, dk;  // bulk tile edge and K extent of the bulk products
   int64_t ps;  // plane stride (elements) of word storage
   double* Hf;
   double* scal;
@@ -112,12 +116,38 @@ struct Work {
   void* cgstate;
 };
 
-size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, bool for_apply) {
+// Bulk tile edge for the word products: the edge whose upper-triangle tile
+// count, spread over the device's compute units, finishes first (a 192 tile
+// does 2.25x the work of a 128 tile at about 1.4x its per-CU throughput).
+int choose_tile(int64_t d, int words, int ncu) {
+  if (words > 2) return 128;
+  // REFL_BULK_TILE=128|192 overrides the choice (tests, tuning).
+  if (const char* e = std::getenv("REFL_BULK_TILE")) {
+    const int v = std::atoi(e);
+    if (v == 128 || v == 192) return v;
+  }
+  double best = 1e300;
+  int bt = 128;
+  for (int ts : {128, 192}) {
+    const int64_t nt = (d + ts - 1) / ts, tiles = nt * (nt + 1) / 2;
+    const int64_t rounds = (tiles + ncu - 1) / ncu;
+    const double cost = (double)rounds * ts * ts / (ts == 192 ? 1.4 : 1.0);
+    if (cost < best) {
+      best = cost;
+      bt = ts;
+    }
+  }
+  return bt;
+}
+
+size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, bool for_apply, int ncu) {
   Carve c(base);
   w.d = (int)d;
-  w.dp = (int)round_up(d, TILE);
+  w.ts = (!for_apply && p.precision == REFL_PREC_MIXED) ? choose_tile(d, p.words, ncu) : TILE;
+  w.dp = (int)round_up(d, w.ts);
+  w.dk = (p.precision == REFL_PREC_MIXED) ? (int)round_up(d, 32) : w.dp;
   const int64_t dp = w.dp, n2 = dp * dp;
-  const int nt = w.dp / TILE;
+  const int nt = w.dp / w.ts;
   w.ntiles = nt * (nt + 1) / 2;
   w.words = p.words;
   w.ps = n2;
@@ -214,11 +244,25 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
   return REFL_OK;
 }
 
-void upload_tiles(const Work& w, hipStream_t st, std::vector<int2>& host) {
-  const int nt = w.dp / TILE;
-  host.clear();
-  for (int I = 0; I < nt; ++I)
-    for (int J = I; J < nt; ++J) host.push_back(make_int2(I, J));
+// Upper tiles (I <= J) ordered so that the work-groups that share an XCD
+// (block b runs on XCD b % 8) take a compact patch of the triangle: tiles
+// are listed by bands of 4 tile rows, column by column, the list is cut into
+// 8 consecutive pieces, and block b takes element b / 8 of piece b % 8.
+void build_tiles(const Work& w, std::vector<int2>& host) {
+  const int nt = w.dp / w.ts;
+  std::vector<int2> order;
+  for (int b0 = 0; b0 < nt; b0 += 4)
+    for (int J = b0; J < nt; ++J)
+      for (int I = b0; I < std::min(b0 + 4, nt); ++I)
+        if (I <= J) order.push_back(make_int2(I, J));
+  const int T = (int)order.size();
+  int start[8], s0 = 0;
+  for (int x = 0; x < 8; ++x) {
+    start[x] = s0;
+    s0 += (T - x + 7) / 8;
+  }
+  host.resize(T);
+  for (int b = 0; b < T; ++b) host[b] = order[start[b % 8] + b / 8];
 }
 
 // Index certificate: returns j, or -1 if b = sqrt(d)||X^2-I||_F >= 1 or no
@@ -269,7 +313,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
   HIPCHK(random_block(V, ld, d, k, p.seed ^ 0x5EEDull, st));
   // Subspace extraction with the approximate projector (I - X)/2.
   for (int it = 0; it < 2; ++it) {
-    HIPCHK(thin_gemm_words(w.words, X, w.dp, w.ps, d, V, ld, k, w.T2, ld, w.thin, st));
+    HIPCHK(symthin_words(w.words, X, w.dp, w.ps, d, V, ld, k, w.T2, ld, w.thin, st));
     HIPCHK(lincomb(d, k, -0.5, w.T2, ld, 0.5, V, ld, st));  // V = (V - X V)/2
     refl_status_t r = orthonormalise(h, w, V, spare, k);
     if (r != REFL_OK) return r;
@@ -282,7 +326,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
   CgHost* hs = reinterpret_cast<CgHost*>(h->pinned + SC_COUNT);
   while (true) {
     // Rayleigh-Ritz on span(V) with H (FP64).
-    HIPCHK(thin_gemm_f64(w.Hf, ld, d, V, ld, k, Wm, ld, w.thin, st));
+    HIPCHK(symthin_f64(w.Hf, ld, d, V, ld, k, Wm, ld, w.thin, st));
     HIPCHK(gram(V, ld, k, Wm, ld, k, d, w.G, w.gwork, st));
     HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -318,8 +362,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     std::memset(hs, 0, sizeof(CgHost));
     for (int c = 0; c < k; ++c) {
       hs->theta[c] = th[c];
-      hs->rho[c] = hs->rho0[c] = G[c + k * c];
-      hs->beta[c] = 0.0;
+      hs->rho0[c] = G[c + k * c];
     }
     hs->tol2 = p.cg_tol * p.cg_tol;
     hs->k = k;
@@ -327,13 +370,16 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     HIPCHK(hipMemcpyAsync(w.cgstate, hs, sizeof(CgHost), hipMemcpyHostToDevice, st));
     int issued = 0;
     while (true) {
-      const int batch = 16;
-      for (int b = 0; b < batch; ++b, ++issued)
+      // First batch 32 iterations (every correction solve here needs more),
+      // then 16 between host checks of the convergence flag.  Iteration
+      // cg_max_iter only runs the convergence test.
+      const int batch = issued == 0 ? 32 : 16;
+      for (int b = 0; b < batch && issued <= p.cg_max_iter; ++b, ++issued)
         HIPCHK(cg_iteration(w.Hf, ld, d, k, V, ld, w.Rr, w.P[issued & 1], w.P[(issued + 1) & 1],
-                            w.AP, w.Z, w.cgstate, w.thin, w.cgpart, p.cg_max_iter, st));
+                            w.AP, w.Z, w.cgstate, w.thin, w.cgpart, issued, p.cg_max_iter, st));
       HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      if (hs->done) break;
+      if (hs->done || issued > p.cg_max_iter) break;
     }
     cg_total += hs->iters;
     // V <- orth(V + Z)
@@ -385,17 +431,17 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   inf.s = s;
   HIPCHK(hipSetDevice(h->device));
   Work w;
-  const size_t need = layout(w, nullptr, d, p, false);
+  const size_t need = layout(w, nullptr, d, p, false, h->ncu);
   void* base = nullptr;
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, false);
+  layout(w, base, d, p, false, h->ncu);
   hipStream_t st = h->stream;
   double* hsc = h->pinned;
 
   // ---- set-up ----
   std::vector<int2> tl;
-  upload_tiles(w, st, tl);
+  build_tiles(w, tl);
   HIPCHK(hipMemcpyAsync(w.tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice, st));
   HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, st));
   HIPCHK(launch_scale_inf(w.Hf, w.dp, (int)d, s, p.scale_mode == REFL_SCALE_GIVEN, p.alpha,
@@ -445,6 +491,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     return e;
   };
   int cert_steps = 0;
+  int bulk_extra = 0;
+  if (const char* e = std::getenv("REFL_BULK_EXTRA")) bulk_extra = std::max(0, std::atoi(e));
   refl_status_t bulk_status = REFL_OK;
   while (true) {
     const int c = b.cur;
@@ -456,8 +504,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       HIPCHK(launch_sym_gemm_f32(GEMM_RESIDUAL, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
     else
-      HIPCHK(launch_sym_gemm_words(W, GEMM_RESIDUAL, w.Xw[c], w.Xw[c], nullptr, w.Nw, w.dp, w.ps,
-                                   (int)d, w.dp, w.tiles, w.ntiles, w.partials, st));
+      HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, w.Xw[c], w.Xw[c], nullptr, w.Nw, w.dp,
+                                   w.ps, (int)d, w.dk, w.tiles, w.ntiles, w.partials, st));
     HIPCHK(ev_stop());
     HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
     HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, w.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -487,15 +535,16 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       if (n >= 3 && resid < 1e-6 && resid > 0.5 * hist[n - 3]) break;
       if (b.steps >= cap) break;
     } else {
-      // MIXED bulk: run until the index certificate holds and the residual
-      // stops decreasing quadratically (the BF16-word floor), or two steps
-      // after the certificate first held.
+      // MIXED bulk: hand over to the FP64 correction as soon as the index
+      // certificate holds (the correction restores full accuracy), or after
+      // REFL_BULK_EXTRA further steps (tuning), or when the residual stops
+      // decreasing quadratically (the BF16-word floor).
       const int j = index_certificate(d, resid, trace_cur);
       const size_t n = hist.size();
       if (j >= 0) {
         ++cert_steps;
         const bool floor = n >= 2 && resid > 0.25 * hist[n - 2];
-        if (floor || cert_steps > 2) {
+        if (floor || cert_steps > bulk_extra) {
           b.converged = true;
           break;
         }
@@ -510,8 +559,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       HIPCHK(launch_sym_gemm_f32(GEMM_UPDATE, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
     else
-      HIPCHK(launch_sym_gemm_words(W, GEMM_UPDATE, w.Xw[c], w.Nw, w.Xw[c], w.Xw[c ^ 1], w.dp, w.ps,
-                                   (int)d, w.dp, w.tiles, w.ntiles, w.partials, st));
+      HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, w.Xw[c], w.Nw, w.Xw[c], w.Xw[c ^ 1], w.dp,
+                                   w.ps, (int)d, w.dk, w.tiles, w.ntiles, w.partials, st));
     HIPCHK(ev_stop());
     HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
     HIPCHK(hipMemcpyAsync(hsc + SC_TRACE, w.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -643,6 +692,10 @@ refl_status_t refl_create(refl_handle_t* out, int device, void* hip_stream) {
     delete h;
     return REFL_ERR_DEVICE;
   }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      ncu > 0)
+    h->ncu = ncu;
   const size_t pin_bytes = sizeof(double) * SC_COUNT + sizeof(CgHost) + 256;
   if (hipHostMalloc((void**)&h->pinned, pin_bytes, hipHostMallocDefault) != hipSuccess) {
     delete h;
@@ -676,7 +729,7 @@ refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_
   refl_status_t rs = check_params(h, d, p);
   if (rs != REFL_OK) return rs;
   Work w;
-  *bytes = layout(w, nullptr, d, *p, false);
+  *bytes = layout(w, nullptr, d, *p, false, h->ncu);
   return REFL_OK;
 }
 
@@ -714,11 +767,11 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t l
   refl_params_t p;
   refl_params_default(&p);
   Work w;
-  const size_t need = layout(w, nullptr, d, p, true);
+  const size_t need = layout(w, nullptr, d, p, true, h->ncu);
   void* base = nullptr;
   refl_status_t rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, true);
+  layout(w, base, d, p, true, h->ncu);
   for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
     const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
     HIPCHK(thin_gemm_f64(dR, ldr, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, h->stream));

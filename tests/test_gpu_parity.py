@@ -210,6 +210,26 @@ def test_mixed_bulk_iterate(R, handle):
         assert err < (1e-3 if words == 2 else 1e-5)
 
 
+@pytest.mark.parametrize("tile", ["128", "192"])
+def test_mixed_bulk_ragged_tiles(R, handle, tile, monkeypatch):
+    # d = 500 is ragged for both bulk tile edges (4 x 128, 3 x 192 tiles).
+    d, k = 500, 6
+    monkeypatch.setenv("REFL_BULK_TILE", tile)
+    _say(f"mixed bulk fixed steps d={d} tile={tile}")
+    H, lam, Q = inputs.planted_hessian(d, k, 0.1, 2)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", words=2, fixed_steps=6)
+    alpha = oracle.inf_norm_shifted(H, s)
+    X6 = oracle.ns_iterates(H, s, alpha, 6)[6]
+    a = Rg.cpu().numpy()
+    err = np.abs(a - X6).max()
+    _say(f"  max|X_6 - oracle| = {err:.2e}")
+    assert np.array_equal(a, a.T)
+    assert err < 1e-3
+    d2 = oracle.certificates(H, X6, s)
+    assert info["trace"] == pytest.approx(d2["trace"], abs=1e-2)
+
+
 @pytest.mark.parametrize("grel", [1e-1, 1e-2])
 def test_mixed_planted_d1024(R, handle, grel):
     d, k = 1024, 8

@@ -24,6 +24,8 @@
 // accumulators take the registers a second set would need).  LDS rows are 32 BF16 + 16 B of pad
 // (80 B): the 16-byte fragment reads of 16 consecutive rows then fall in
 // distinct bank groups whether the LDS serves 8 or 16 lanes per cycle.
+#include <cstdlib>
+
 #include "common.h"
 #include "launch.h"
 
@@ -272,10 +274,285 @@ __global__ __launch_bounds__(256) void k_sym_gemm_w(const uint16_t* __restrict__
   if (tid == 0) partials[blockIdx.x] = tot;
 }
 
+// ---------------------------------------------------------------------
+// Direct-to-LDS variant: K-slices reach LDS by global_load_lds_dwordx4 (each
+// lane's 16 B land at the wave's LDS base + 16 * lane, so a wave writes 1 KB
+// = 16 rows of 64 B), through a ring of three stages: the loads of slice
+// kt + 2 are issued while slice kt is multiplied, with no staging registers.
+// Rows are 64 B without padding; the 16-byte chunk c of row r is stored at
+// position c ^ swz(r), swz(r) = ((r >> 1) ^ (r >> 2)) & 3, which keeps the
+// fragment reads of 16 consecutive rows on distinct bank groups whether the
+// LDS serves 8 or 16 lanes per cycle.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+template <int W, int TS>
+struct DCfg {
+  static constexpr int BK = 32;
+  static constexpr int ROWB = 64;                       // bytes per LDS row (BK BF16)
+  static constexpr int NS = 3;                          // ring stages
+  static constexpr int PLANE_B = TS * ROWB;
+  static constexpr int STAGE_B = 2 * W * PLANE_B;
+  static constexpr int NINST = 2 * W * (TS / 16);       // 1 KB load instructions per stage
+  static constexpr int NLW = NINST / 4;                 // per wave
+  static constexpr int NB = TS / 64;
+  static constexpr int NPROD = W == 1 ? 1 : (W == 2 ? 3 : 6);
+  static_assert(NINST % 4 == 0, "load instructions must split over 4 waves");
+  static_assert(NS * STAGE_B <= 160 * 1024, "ring exceeds LDS");
+};
+
+// Work-group barrier that orders LDS only.  __syncthreads() would also wait
+// for every outstanding vector-memory operation, which includes the
+// direct-to-LDS loads of the slices still in flight; here each wave first
+// waits (vmcnt) for the slice about to be read, then the barrier makes all
+// waves' copies of it visible.  The memory clobber keeps the compiler from
+// moving LDS accesses across the barrier.
+#define REFL_LDS_BARRIER() asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory")
+
+// s_waitcnt with vmcnt = n (0..63) and no wait on the other counters.
+#define REFL_WAIT_VMCNT(n) \
+  __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
+
+template <int W, int MODE, int TS>
+__global__ __launch_bounds__(256) void k_sym_gemm_wd(const uint16_t* __restrict__ A,
+                                                     const uint16_t* __restrict__ B,
+                                                     const uint16_t* __restrict__ Xold,
+                                                     uint16_t* __restrict__ out, int ld,
+                                                     int64_t ps, int d, int dk,
+                                                     const int2* __restrict__ tiles,
+                                                     double* __restrict__ partials) {
+  typedef DCfg<W, TS> C;
+  constexpr int NB = C::NB;
+  // Three separate arrays: the compiler's per-variable alias scopes then let
+  // LDS reads of one stage proceed while direct loads into another are in
+  // flight (one array would make it wait for every outstanding load).
+  __shared__ __attribute__((aligned(1024))) unsigned char ring0[C::STAGE_B];
+  __shared__ __attribute__((aligned(1024))) unsigned char ring1[C::STAGE_B];
+  __shared__ __attribute__((aligned(1024))) unsigned char ring2[C::STAGE_B];
+  __shared__ double red[4];
+
+  const int2 tl = tiles[blockIdx.x];
+  const int i0 = tl.x * TS, j0 = tl.y * TS;
+  const bool diag = (tl.x == tl.y);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // Load descriptors of this wave: instruction m -> operand, word plane,
+  // block of 16 rows; lane -> row, swizzled chunk.
+  const uint16_t* gsrc[C::NLW];
+  int ldsoff[C::NLW];
+#pragma unroll
+  for (int j = 0; j < C::NLW; ++j) {
+    const int m = wave * C::NLW + j;
+    const int op = m / (W * (TS / 16));
+    const int rem = m % (W * (TS / 16));
+    const int word = rem / (TS / 16), rb = rem % (TS / 16);
+    const int r = rb * 16 + (lane >> 2);
+    const int c = (lane & 3) ^ swz(r);
+    const uint16_t* base = op == 0 ? A : B;
+    const int row0 = op == 0 ? i0 : j0;
+    gsrc[j] = base + word * ps + (int64_t)(row0 + r) * ld + 8 * c;
+    ldsoff[j] = ((op * W + word) * TS + rb * 16) * C::ROWB;
+  }
+  auto issue = [&](int kt, unsigned char* stage) {
+#pragma unroll
+    for (int j = 0; j < C::NLW; ++j)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(gsrc[j] + kt * C::BK),
+          (__attribute__((address_space(3))) void*)(stage + ldsoff[j]), 16, 0, 0);
+  };
+
+  f32x16_t acc[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  auto compute = [&](const unsigned char* sb) {
+#pragma unroll
+    for (int kk = 0; kk < C::BK / 16; ++kk) {
+      bf16x8_t af[W][NB], bfr[W][NB];
+      const int c = kk * 2 + (lane >> 5);
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const int ra = wr * (TS / 2) + a * 32 + (lane & 31);
+          const int rbb = wc * (TS / 2) + a * 32 + (lane & 31);
+          af[w][a] = *reinterpret_cast<const bf16x8_t*>(
+              sb + (w * TS + ra) * C::ROWB + 16 * (c ^ swz(ra)));
+          bfr[w][a] = *reinterpret_cast<const bf16x8_t*>(
+              sb + ((W + w) * TS + rbb) * C::ROWB + 16 * (c ^ swz(rbb)));
+        }
+#pragma unroll
+      for (int p = C::NPROD - 1; p >= 0; --p)
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(W, p)][a],
+                                                               bfr[prod_b(W, p)][b], acc[a][b],
+                                                               0, 0, 0);
+    }
+  };
+
+  // K-slice kt lives in stage kt % 3; the loads of slice kt + 2 are issued
+  // once every wave is past slice kt - 1, which used the same stage.  The
+  // steady-state loop has no conditional loads or waits (so the compiler
+  // keeps track of which stage each in-flight load writes and does not drain
+  // them all before the next LDS read); the last slices are peeled.
+  const int nk = dk / C::BK;
+  auto step = [&](int kt, const unsigned char* cur, unsigned char* next2) {
+    REFL_WAIT_VMCNT(C::NLW);
+    REFL_LDS_BARRIER();
+    issue(kt + 2, next2);
+    compute(cur);
+  };
+  // Slice 1 is fetched even when nk == 1: the matrices are at least 128
+  // columns wide, so the read stays in bounds, and an unconditional
+  // prologue keeps the in-flight-load bookkeeping exact at the loop head.
+  issue(0, ring0);
+  issue(1, ring1);
+  int kt = 0;
+  for (; kt + 4 < nk; kt += 3) {
+    step(kt, ring0, ring2);
+    step(kt + 1, ring1, ring0);
+    step(kt + 2, ring2, ring1);
+  }
+  // Tail: slices kt .. nk - 1 (at most five), stages continuing from ring0.
+  for (int t = 0; kt + t < nk; ++t) {
+    const int kk = kt + t;
+    unsigned char* cur = (t % 3 == 0) ? ring0 : ((t % 3 == 1) ? ring1 : ring2);
+    unsigned char* nx = (t % 3 == 0) ? ring2 : ((t % 3 == 1) ? ring0 : ring1);
+    if (kk + 1 < nk) {
+      REFL_WAIT_VMCNT(C::NLW);
+    } else {
+      REFL_WAIT_VMCNT(0);
+    }
+    REFL_LDS_BARRIER();
+    if (kk + 2 < nk) issue(kk + 2, nx);
+    compute(cur);
+  }
+  __syncthreads();
+
+  // ---- epilogue.  The FP32 tile is staged across the three ring arrays,
+  // RPA rows per array, row-major without padding; entry (r, c) sits at
+  // column c ^ ((r >> 3) & 31) of its row, so the transposed pass (eight
+  // consecutive rows of one column per lane, 24 lanes per column) reads
+  // distinct banks. ----
+  constexpr int RPA = C::STAGE_B / (TS * 4);
+  static_assert(3 * RPA >= TS, "staging must fit in the ring");
+  auto stg = [&](int r, int c) -> float& {
+    unsigned char* base = r < RPA ? ring0 : (r < 2 * RPA ? ring1 : ring2);
+    const int rr = r % RPA;
+    return reinterpret_cast<float*>(base)[rr * TS + (c ^ ((r >> 3) & 31))];
+  };
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * (TS / 2) + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int col = wc * (TS / 2) + b * 32 + (lane & 31);
+        stg(row, col) = acc[a][b][r];
+      }
+  __syncthreads();
+  constexpr int VE = 8, CPR = TS / VE;
+  double part = 0.0;
+  for (int e = tid; e < TS * CPR; e += 256) {
+    const int r = e / CPR, cofs = (e % CPR) * VE;
+    const int gi = i0 + r;
+    float xo[VE];
+    if (MODE == GEMM_UPDATE) {
+#pragma unroll
+      for (int q = 0; q < VE; ++q) xo[q] = 0.f;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        alignas(16) uint16_t xw[VE];
+        *reinterpret_cast<u32x4_t*>(xw) =
+            *reinterpret_cast<const u32x4_t*>(Xold + w * ps + (int64_t)gi * ld + j0 + cofs);
+#pragma unroll
+        for (int q = 0; q < VE; ++q) xo[q] += bf16_to_f32(xw[q]);
+      }
+    }
+    alignas(16) uint16_t ow[W][VE];
+    float nv[VE];
+#pragma unroll
+    for (int q = 0; q < VE; ++q) {
+      const int c = cofs + q;
+      const int rr = (diag && r > c) ? c : r, cc = (diag && r > c) ? r : c;
+      const float v = stg(rr, cc);
+      const int gj = j0 + c;
+      float n;
+      if (MODE == GEMM_RESIDUAL) {
+        n = ((gi == gj && gi < d) ? 1.f : 0.f) - v;
+        part += (diag ? 1.0 : 2.0) * (double)n * (double)n;
+      } else {
+        n = xo[q] + 0.5f * v;
+        if (gi == gj) part += (double)n;
+      }
+      nv[q] = n;
+      uint16_t wv[W];
+      split_words<W>(n, wv);
+#pragma unroll
+      for (int w = 0; w < W; ++w) ow[w][q] = wv[w];
+    }
+    if (!diag) {
+#pragma unroll
+      for (int q = 0; q < VE; ++q) stg(r, cofs + q) = nv[q];
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      *reinterpret_cast<u32x4_t*>(out + w * ps + (int64_t)gi * ld + j0 + cofs) =
+          *reinterpret_cast<const u32x4_t*>(ow[w]);
+  }
+  if (!diag) {
+    __syncthreads();
+    for (int e = tid; e < TS * CPR; e += 256) {
+      const int c = e / CPR, rofs = (e % CPR) * VE;
+      alignas(16) uint16_t ow[W][VE];
+#pragma unroll
+      for (int q = 0; q < VE; ++q) {
+        uint16_t wv[W];
+        split_words<W>(stg(rofs + q, c), wv);
+#pragma unroll
+        for (int w = 0; w < W; ++w) ow[w][q] = wv[w];
+      }
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        *reinterpret_cast<u32x4_t*>(out + w * ps + (int64_t)(j0 + c) * ld + i0 + rofs) =
+            *reinterpret_cast<const u32x4_t*>(ow[w]);
+    }
+  }
+  const double tot = block_sum_256(part, red);
+  if (tid == 0) partials[blockIdx.x] = tot;
+}
+
+static bool use_register_staging() {
+  static const int v = [] {
+    const char* e = std::getenv("REFL_GEMM_STAGING");
+    return (e && e[0] == 'r') ? 1 : 0;
+  }();
+  return v != 0;
+}
+
 template <int W, int TS>
 static hipError_t launch_w(int mode, const uint16_t* A, const uint16_t* B, const uint16_t* Xold,
                            uint16_t* out, int ld, int64_t ps, int d, int dk, const int2* tiles,
                            int ntiles, double* partials, hipStream_t st) {
+  if constexpr (W >= 2) {
+    if (!use_register_staging()) {
+      if (mode == GEMM_RESIDUAL)
+        hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st,
+                           A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+      else
+        hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st, A,
+                           B, Xold, out, ld, ps, d, dk, tiles, partials);
+      return hipGetLastError();
+    }
+  }
   if (mode == GEMM_RESIDUAL)
     hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
                        Xold, out, ld, ps, d, dk, tiles, partials);

@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--words", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
+                         "kernel (reads 256 MiB, writes 256 MiB) that calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the reflector of one Hessian "
@@ -86,6 +89,18 @@ def main():
         Rn -= np.eye(d)
         Rn += 2.0 * Vk @ Vk.T
         return float(np.linalg.norm(Rn))
+
+    if args.profile:
+        info = run(mixed_kw)
+        log(f"profile solve: {info['ms_total']:.2f} ms, steps={info['ns_steps']}")
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        log("calibration kernel done (256 MiB read + 256 MiB write per launch)")
+        h.close()
+        return
 
     # ---- mixed path ----
     for i in range(args.warmup):

@@ -312,8 +312,10 @@ struct DCfg {
 #define REFL_WAIT_VMCNT(n) \
   __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
 
-template <int W, int MODE, int TS>
-__global__ __launch_bounds__(256) void k_sym_gemm_wd(const uint16_t* __restrict__ A,
+// One wave per SIMD (the ring fills the LDS); telling the compiler so lets it
+// keep a whole K-slice of fragments in registers instead of re-reading LDS.
+template <int W, int MODE, int TS, int PIPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_sym_gemm_wd(const uint16_t* __restrict__ A,
                                                      const uint16_t* __restrict__ B,
                                                      const uint16_t* __restrict__ Xold,
                                                      uint16_t* __restrict__ out, int ld,
@@ -336,29 +338,27 @@ __global__ __launch_bounds__(256) void k_sym_gemm_wd(const uint16_t* __restrict_
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // Load descriptors of this wave: instruction m -> operand, word plane,
-  // block of 16 rows; lane -> row, swizzled chunk.
-  const uint16_t* gsrc[C::NLW];
-  int ldsoff[C::NLW];
-#pragma unroll
-  for (int j = 0; j < C::NLW; ++j) {
-    const int m = wave * C::NLW + j;
-    const int op = m / (W * (TS / 16));
-    const int rem = m % (W * (TS / 16));
-    const int word = rem / (TS / 16), rb = rem % (TS / 16);
-    const int r = rb * 16 + (lane >> 2);
-    const int c = (lane & 3) ^ swz(r);
-    const uint16_t* base = op == 0 ? A : B;
-    const int row0 = op == 0 ? i0 : j0;
-    gsrc[j] = base + word * ps + (int64_t)(row0 + r) * ld + 8 * c;
-    ldsoff[j] = ((op * W + word) * TS + rb * 16) * C::ROWB;
-  }
+  // Load descriptors.  Instruction m (of this wave's NLW) covers 16 rows of
+  // one word plane of one operand; lane l loads row 16 rb + l/4, logical
+  // chunk (l & 3) ^ swz(l/4) (the swizzle only involves row bits 0..3, so it
+  // is the same for every 16-row block).  The per-instruction part of the
+  // address is wave-uniform; the per-lane part is one offset.
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int lane_goff = (lane >> 2) * ld + 8 * ((lane & 3) ^ swz(lane >> 2));
   auto issue = [&](int kt, unsigned char* stage) {
 #pragma unroll
-    for (int j = 0; j < C::NLW; ++j)
+    for (int j = 0; j < C::NLW; ++j) {
+      const int m = wave_u * C::NLW + j;
+      const int op = m / (W * (TS / 16));
+      const int rem = m % (W * (TS / 16));
+      const int word = rem / (TS / 16), rb = rem % (TS / 16);
+      const uint16_t* gbase = (op == 0 ? A : B) + word * ps +
+                              (int64_t)((op == 0 ? i0 : j0) + rb * 16) * ld + kt * C::BK;
       __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)(gsrc[j] + kt * C::BK),
-          (__attribute__((address_space(3))) void*)(stage + ldsoff[j]), 16, 0, 0);
+          (const __attribute__((address_space(1))) void*)(gbase + lane_goff),
+          (__attribute__((address_space(3))) void*)(stage + ((op * W + word) * TS + rb * 16) * C::ROWB),
+          16, 0, 0);
+    }
   };
 
   f32x16_t acc[NB][NB];
@@ -369,71 +369,135 @@ __global__ __launch_bounds__(256) void k_sym_gemm_wd(const uint16_t* __restrict_
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  auto compute = [&](const unsigned char* sb) {
+  // Fragments of one K-slice in two halves: H[0] for k 0..15, H[1] for
+  // k 16..31 of the slice, all word planes.
+  constexpr int KH = C::BK / 16;
+  static_assert(KH == 2, "two 16-wide halves per K-slice");
+  bf16x8_t fa[KH][W][NB], fb[KH][W][NB];
+  // Fragment reads: lane l reads row (block row) + l % 32, logical chunk
+  // 2 kk + l / 32; block rows are multiples of 32, so the swizzle is swz(l % 32)
+  // and every read is one lane offset plus an immediate.
+  const int frag_lane[KH] = {
+      (lane & 31) * C::ROWB + 16 * ((0 + (lane >> 5)) ^ swz(lane & 31)),
+      (lane & 31) * C::ROWB + 16 * ((2 + (lane >> 5)) ^ swz(lane & 31))};
+  auto load_half = [&](const unsigned char* sb, int kk) {
+    const unsigned char* p = sb + frag_lane[kk];
 #pragma unroll
-    for (int kk = 0; kk < C::BK / 16; ++kk) {
-      bf16x8_t af[W][NB], bfr[W][NB];
-      const int c = kk * 2 + (lane >> 5);
+    for (int w = 0; w < W; ++w)
 #pragma unroll
-      for (int w = 0; w < W; ++w)
+      for (int a = 0; a < NB; ++a) {
+        fa[kk][w][a] = *reinterpret_cast<const bf16x8_t*>(
+            p + (w * TS + wr * (TS / 2) + a * 32) * C::ROWB);
+        fb[kk][w][a] = *reinterpret_cast<const bf16x8_t*>(
+            p + ((W + w) * TS + wc * (TS / 2) + a * 32) * C::ROWB);
+      }
+  };
+  auto mfma_half = [&](int kk) {
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          const int ra = wr * (TS / 2) + a * 32 + (lane & 31);
-          const int rbb = wc * (TS / 2) + a * 32 + (lane & 31);
-          af[w][a] = *reinterpret_cast<const bf16x8_t*>(
-              sb + (w * TS + ra) * C::ROWB + 16 * (c ^ swz(ra)));
-          bfr[w][a] = *reinterpret_cast<const bf16x8_t*>(
-              sb + ((W + w) * TS + rbb) * C::ROWB + 16 * (c ^ swz(rbb)));
-        }
+    for (int p = C::NPROD - 1; p >= 0; --p)
 #pragma unroll
-      for (int p = C::NPROD - 1; p >= 0; --p)
+      for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[prod_a(W, p)][a],
-                                                               bfr[prod_b(W, p)][b], acc[a][b],
-                                                               0, 0, 0);
-    }
+        for (int b = 0; b < NB; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              fa[kk][prod_a(W, p)][a], fb[kk][prod_b(W, p)][b], acc[a][b], 0, 0, 0);
   };
 
-  // K-slice kt lives in stage kt % 3; the loads of slice kt + 2 are issued
-  // once every wave is past slice kt - 1, which used the same stage.  The
-  // steady-state loop has no conditional loads or waits (so the compiler
-  // keeps track of which stage each in-flight load writes and does not drain
-  // them all before the next LDS read); the last slices are peeled.
+  // Pipeline.  Slice j lives in stage j % 3.  Step kt: issue the loads of
+  // slice kt + 2; MFMAs of the first half of slice kt; wait for slice kt + 1
+  // (this wave's loads, then the barrier for everyone's); read its first
+  // half while the second half of slice kt is multiplied; then read its
+  // second half.  The stage written by the loads of slice kt + 2 held slice
+  // kt - 1, whose last reads every wave completed before the barrier of
+  // step kt - 1.  The steady-state loop is unconditional (the compiler then
+  // keeps track of which stage each in-flight load writes); the last two
+  // steps are peeled.
   const int nk = dk / C::BK;
-  auto step = [&](int kt, const unsigned char* cur, unsigned char* next2) {
+  if constexpr (PIPE == 1) {
+    auto step = [&](int kt, unsigned char* dma, const unsigned char* nxt) {
+      issue(kt + 2, dma);
+      mfma_half(0);
+      REFL_WAIT_VMCNT(C::NLW);
+      REFL_LDS_BARRIER();
+      load_half(nxt, 0);
+      mfma_half(1);
+      load_half(nxt, 1);
+    };
+    // Slice 1 is fetched even when nk == 1: the matrices are at least 128
+    // columns wide, so the read stays in bounds, and an unconditional
+    // prologue keeps the in-flight-load bookkeeping exact.
+    issue(0, ring0);
+    issue(1, ring1);
     REFL_WAIT_VMCNT(C::NLW);
     REFL_LDS_BARRIER();
-    issue(kt + 2, next2);
-    compute(cur);
-  };
-  // Slice 1 is fetched even when nk == 1: the matrices are at least 128
-  // columns wide, so the read stays in bounds, and an unconditional
-  // prologue keeps the in-flight-load bookkeeping exact at the loop head.
-  issue(0, ring0);
-  issue(1, ring1);
-  int kt = 0;
-  for (; kt + 4 < nk; kt += 3) {
-    step(kt, ring0, ring2);
-    step(kt + 1, ring1, ring0);
-    step(kt + 2, ring2, ring1);
-  }
-  // Tail: slices kt .. nk - 1 (at most five), stages continuing from ring0.
-  for (int t = 0; kt + t < nk; ++t) {
-    const int kk = kt + t;
-    unsigned char* cur = (t % 3 == 0) ? ring0 : ((t % 3 == 1) ? ring1 : ring2);
-    unsigned char* nx = (t % 3 == 0) ? ring2 : ((t % 3 == 1) ? ring0 : ring1);
-    if (kk + 1 < nk) {
-      REFL_WAIT_VMCNT(C::NLW);
-    } else {
-      REFL_WAIT_VMCNT(0);
+    load_half(ring0, 0);
+    load_half(ring0, 1);
+    int kt = 0;
+    for (; kt + 4 < nk; kt += 3) {
+      step(kt, ring2, ring1);
+      step(kt + 1, ring0, ring2);
+      step(kt + 2, ring1, ring0);
     }
-    REFL_LDS_BARRIER();
-    if (kk + 2 < nk) issue(kk + 2, nx);
-    compute(cur);
+    // Tail: slices kt .. nk - 1, stages continuing from ring0 (kt % 3 == 0).
+    for (int t = 0; kt + t < nk; ++t) {
+      const int j = kt + t;
+      unsigned char* dma = (t % 3 == 0) ? ring2 : ((t % 3 == 1) ? ring0 : ring1);
+      const unsigned char* nxt = (t % 3 == 0) ? ring1 : ((t % 3 == 1) ? ring2 : ring0);
+      if (j + 2 < nk) issue(j + 2, dma);
+      mfma_half(0);
+      if (j + 1 < nk) {
+        if (j + 2 < nk) {
+          REFL_WAIT_VMCNT(C::NLW);
+        } else {
+          REFL_WAIT_VMCNT(0);
+        }
+        REFL_LDS_BARRIER();
+        load_half(nxt, 0);
+        mfma_half(1);
+        load_half(nxt, 1);
+      } else {
+        mfma_half(1);
+      }
+    }
+  } else {
+    // Barrier at the start of each slice, then all of its fragment reads,
+    // the loads of slice kt + 2, and the MFMAs.
+    auto step = [&](int kt, const unsigned char* cur, unsigned char* next2) {
+      REFL_WAIT_VMCNT(C::NLW);
+      REFL_LDS_BARRIER();
+      load_half(cur, 0);
+      load_half(cur, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      issue(kt + 2, next2);
+      mfma_half(0);
+      mfma_half(1);
+    };
+    issue(0, ring0);
+    issue(1, ring1);
+    int kt = 0;
+    for (; kt + 4 < nk; kt += 3) {
+      step(kt, ring0, ring2);
+      step(kt + 1, ring1, ring0);
+      step(kt + 2, ring2, ring1);
+    }
+    for (int t = 0; kt + t < nk; ++t) {
+      const int j = kt + t;
+      const unsigned char* cur = (t % 3 == 0) ? ring0 : ((t % 3 == 1) ? ring1 : ring2);
+      unsigned char* nx = (t % 3 == 0) ? ring2 : ((t % 3 == 1) ? ring0 : ring1);
+      if (j + 1 < nk) {
+        REFL_WAIT_VMCNT(C::NLW);
+      } else {
+        REFL_WAIT_VMCNT(0);
+      }
+      REFL_LDS_BARRIER();
+      load_half(cur, 0);
+      load_half(cur, 1);
+      if (j + 2 < nk) issue(j + 2, nx);
+      mfma_half(0);
+      mfma_half(1);
+    }
   }
+  REFL_WAIT_VMCNT(0);
   __syncthreads();
 
   // ---- epilogue.  The FP32 tile is staged across the three ring arrays,
@@ -530,6 +594,14 @@ __global__ __launch_bounds__(256) void k_sym_gemm_wd(const uint16_t* __restrict_
   if (tid == 0) partials[blockIdx.x] = tot;
 }
 
+static int gemm_pipe() {
+  static const int v = [] {
+    const char* e = std::getenv("REFL_GEMM_PIPE");
+    return (e && e[0] == '1') ? 1 : 0;
+  }();
+  return v;
+}
+
 static bool use_register_staging() {
   static const int v = [] {
     const char* e = std::getenv("REFL_GEMM_STAGING");
@@ -544,12 +616,22 @@ static hipError_t launch_w(int mode, const uint16_t* A, const uint16_t* B, const
                            int ntiles, double* partials, hipStream_t st) {
   if constexpr (W >= 2) {
     if (!use_register_staging()) {
-      if (mode == GEMM_RESIDUAL)
-        hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st,
-                           A, B, Xold, out, ld, ps, d, dk, tiles, partials);
-      else
-        hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st, A,
-                           B, Xold, out, ld, ps, d, dk, tiles, partials);
+      const bool p1 = gemm_pipe() == 1;
+      if (mode == GEMM_RESIDUAL) {
+        if (p1)
+          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_RESIDUAL, TS, 1>), dim3(ntiles), dim3(256), 0,
+                             st, A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+        else
+          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_RESIDUAL, TS, 0>), dim3(ntiles), dim3(256), 0,
+                             st, A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+      } else {
+        if (p1)
+          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_UPDATE, TS, 1>), dim3(ntiles), dim3(256), 0, st,
+                             A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+        else
+          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_UPDATE, TS, 0>), dim3(ntiles), dim3(256), 0, st,
+                             A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+      }
       return hipGetLastError();
     }
   }

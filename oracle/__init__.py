@@ -12,7 +12,10 @@ Contents
               shifted sign sgn(H - sI), the plain FP64 Newton-Schulz iterates
               (eq. NS), the scalar polynomials p_m (eq. pm) and the error
               recurrence (Prop. 3.6), the midpoint rule (Prop. 4.1) and the
-              Prop. 4.2 admissibility test, and reference certificate values.
+              Prop. 4.2 admissibility test, reference certificate values, and
+              the block-Lanczos estimate of the gap endpoints, error radius,
+              midpoint shift and spectral radius (section 4.3) with its
+              SplitMix64 start block.
 ``build.py``  compiles ``jacobi.c`` into ``liboracle_jacobi.so``.
 """
 from .oracle import *  # noqa: F401,F403

@@ -19,7 +19,8 @@ __all__ = [
     "shifted_sign_from_eig", "midpoint", "ns_poly", "ns_scalar_error",
     "ns_error_recurrence", "ns_iterate", "ns_iterates", "ns_closed_form",
     "ns_depth_scalar", "inf_norm_shifted", "admissible", "certificates",
-    "spectral_norm_sym",
+    "spectral_norm_sym", "splitmix64", "start_block", "lanczos_block_size",
+    "lanczos_check_steps", "block_lanczos",
 ]
 
 
@@ -198,3 +199,118 @@ def certificates(H, X, s: float):
         "resid_fro": float(np.linalg.norm(T - np.eye(d))),
         "commutator_fro": float(np.linalg.norm(C)),
     }
+
+
+# ---------------------------------------------------------------------------
+# Shift estimation: block Lanczos for the gap endpoints (section 4.3)
+# ---------------------------------------------------------------------------
+_SM_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(x):
+    """SplitMix64 output from state x (Steele, Lea and Flood, "Fast splittable
+    pseudorandom number generators", OOPSLA 2014): z = x + 0x9E3779B97F4A7C15,
+    then the two xor-shift-multiply rounds and a final xor-shift.  uint64
+    arithmetic wraps modulo 2^64."""
+    z = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + _SM_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def start_block(d: int, nb: int, seed: int):
+    """The seeded start block of the Lanczos run: entry (row, c) is
+    splitmix64(seed * 0x100000001B3 + c * d + row) mapped to (-1, 1) through
+    its top 53 bits (u = top53 * 2^-53, value 2u - 1)."""
+    rows = np.arange(d, dtype=np.uint64)[:, None]
+    cols = np.arange(nb, dtype=np.uint64)[None, :]
+    with np.errstate(over="ignore"):
+        ctr = np.uint64(seed) * np.uint64(0x100000001B3) + cols * np.uint64(d) + rows
+    u = (splitmix64(ctr) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return 2.0 * u - 1.0
+
+
+def lanczos_block_size(d: int, k: int) -> int:
+    """Block width b = min(k + 4, 32, d) (a few guard vectors beyond the k + 1
+    wanted Ritz values; the paper leaves the partial eigensolver open)."""
+    return int(min(k + 4, 32, d))
+
+
+def lanczos_check_steps(d: int, k: int, b: int, max_steps: int = 0):
+    """Steps after which the convergence test runs: j0 = ceil((k+1)/b), then
+    every ceil(32/b) steps, and always at the cap J (max_steps, or floor(d/b)
+    when 0 or larger than that)."""
+    cap = d // b
+    J = cap if max_steps <= 0 else min(max_steps, cap)
+    j0 = max(1, -(-(k + 1) // b))
+    ci = max(1, -(-32 // b))
+    out = list(range(j0, J + 1, ci))
+    if not out or out[-1] != J:
+        out.append(J)
+    return [j for j in out if j <= J]
+
+
+def block_lanczos(H, k: int, max_steps: int = 0, seed: int = 0):
+    """Estimates of lambda_k, lambda_{k+1}, the error radius eps, the midpoint
+    shift and the spectral radius of H - sI by block Lanczos with full
+    reorthogonalisation (the partial-eigensolver route of section 4.3; the
+    estimates feed Prop. 4.1 and the admissibility test of Prop. 4.2).
+
+    Steps, in order: Q_1 = orthonormal basis of the start block (library QR);
+    for j = 1, 2, ...: W = H Q_j, A_j = Q_j^T W, W <- W - V (V^T W) twice
+    with V = [Q_1 .. Q_j], Q_{j+1} B_j = W (library QR; B_j = 0 once the
+    basis spans the whole space).  At the steps of ``lanczos_check_steps``
+    the block tridiagonal T_j (diagonal blocks A_i, sub-diagonal blocks B_i)
+    is diagonalised (library eigh): Ritz values theta, and residual norms
+    ||H x_i - theta_i x_i|| = ||B_j y_i(last block)||, each a radius that
+    holds an eigenvalue of H.  Converged when eps = max(res_k, res_{k+1}) <
+    (theta_{k+1} - theta_k)/4.  Returns a dict with the estimates, the step
+    of the last test, and whether it converged.
+    """
+    H = np.asarray(H, dtype=np.float64)
+    d = H.shape[0]
+    if not (1 <= k <= d - 1):
+        raise ValueError("k must lie in 1..d-1")
+    b = lanczos_block_size(d, k)
+    checks = set(lanczos_check_steps(d, k, b, max_steps))
+    J = max(checks)
+    Q, _ = np.linalg.qr(start_block(d, b, seed))
+    blocks = [Q]
+    A_list, B_list = [], []
+    res = None
+    for j in range(1, J + 1):
+        Qj = blocks[-1]
+        W = H @ Qj
+        A_list.append(0.5 * (Qj.T @ W + (Qj.T @ W).T))
+        V = np.hstack(blocks)
+        for _ in range(2):
+            W = W - V @ (V.T @ W)
+        if j * b >= d:
+            Bj = np.zeros((b, b))
+            Qn = np.zeros((d, b))
+        else:
+            Qn, Bj = np.linalg.qr(W)
+        B_list.append(Bj)
+        blocks.append(Qn)
+        if j in checks:
+            n = j * b
+            T = np.zeros((n, n))
+            for i in range(j):
+                T[i * b:(i + 1) * b, i * b:(i + 1) * b] = A_list[i]
+                if i + 1 < j:
+                    T[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] = B_list[i]
+                    T[i * b:(i + 1) * b, (i + 1) * b:(i + 2) * b] = B_list[i].T
+            theta, Y = np.linalg.eigh(T)
+            res = np.linalg.norm(B_list[-1] @ Y[-b:, :], axis=0)
+            lk, lk1 = float(theta[k - 1]), float(theta[k])
+            eps = float(max(res[k - 1], res[k]))
+            converged = eps < 0.25 * (lk1 - lk)
+            if converged or j == J:
+                s = 0.5 * (lk + lk1)
+                rho = float(max(theta[-1] - s, s - theta[0]))
+                return {"lam_k": lk, "lam_k1": lk1, "eps": eps, "s": s, "rho": rho,
+                        "steps": j, "b": b, "converged": bool(converged),
+                        "theta": theta, "res": res, "basis": np.hstack(blocks[:-1])}
+    raise AssertionError("unreachable: the cap is always a check step")

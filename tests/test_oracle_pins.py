@@ -236,3 +236,110 @@ def test_allen_cahn_2d_periodic_spectrum_closed_form():
     h = 1.0 / n
     ref = eps ** 2 * 4.0 / h ** 2 * (np.sin(np.pi * a / n) ** 2 + np.sin(np.pi * b / n) ** 2)
     np.testing.assert_allclose(w, np.sort(ref.ravel()), atol=1e-12)
+
+
+# ------------------------------------------------------ shift estimation pins
+def test_splitmix64_published_outputs():
+    # The first two outputs of SplitMix64 started from state 0 (the values the
+    # generator's published reference implementation prints): state advances
+    # by the golden gamma before each output, so output i is splitmix64(i*gamma).
+    gamma = 0x9E3779B97F4A7C15
+    out = oracle.splitmix64(np.array([0, gamma], dtype=np.uint64))
+    assert int(out[0]) == 0xE220A8397B1DCDAF
+    assert int(out[1]) == 0x6E789E6AA1B965F4
+
+
+def test_start_block_range_and_counter():
+    X = oracle.start_block(1000, 3, seed=7)
+    assert X.shape == (1000, 3) and np.all(np.abs(X) < 1.0)
+    assert abs(X.mean()) < 0.05 and abs(X.var() - 1.0 / 3.0) < 0.03  # U(-1, 1)
+    # Entry (row, c) depends only on the counter seed*0x100000001B3 + c*d + row.
+    Y = oracle.start_block(1000, 1, seed=7)
+    np.testing.assert_array_equal(X[:, :1], Y)
+    assert not np.array_equal(X, oracle.start_block(1000, 3, seed=8))
+
+
+def test_lanczos_full_space_is_exact():
+    # Once the basis spans R^d, the Ritz values are the eigenvalues of H and
+    # every residual vanishes.
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((24, 24))
+    H = 0.5 * (G + G.T)
+    r = oracle.block_lanczos(H, 2, max_steps=0, seed=1)   # b = 6, 4 steps
+    assert r["steps"] * r["b"] == 24 and r["converged"]
+    w, _, _ = oracle.jacobi_eigh(H)
+    np.testing.assert_allclose(r["theta"], w, atol=1e-12)
+    assert np.max(r["res"]) < 1e-12
+
+
+def test_lanczos_matches_explicit_krylov_rayleigh_ritz():
+    # Brute force: Rayleigh-Ritz on an orthonormal basis of the explicit block
+    # Krylov space [X, HX, H^2 X] gives the same Ritz values as three steps.
+    d, k = 40, 1                                           # b = 5
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((d, d))
+    H = (G + G.T) / np.sqrt(8 * d)
+    X = oracle.start_block(d, 5, seed=2)
+    K = np.hstack([X, H @ X, H @ H @ X])
+    P, _ = np.linalg.qr(K)
+    ref = np.linalg.eigvalsh(P.T @ H @ P)
+    r = oracle.block_lanczos(H, k, max_steps=3, seed=2)
+    assert r["steps"] == 3
+    np.testing.assert_allclose(r["theta"], ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("steps", [2, 5, 9])
+def test_lanczos_interlacing_and_residual_radius(steps):
+    # Ritz values of an n-dimensional subspace interlace (Cauchy):
+    # lambda_i <= theta_i <= lambda_{d-n+i}; each residual norm is a radius
+    # around theta_i that holds an eigenvalue; and the residual equals
+    # ||H x - theta x|| for the Ritz vector x built from the returned basis.
+    d, k = 90, 3                                           # b = 7
+    rng = np.random.default_rng(11)
+    G = rng.standard_normal((d, d))
+    H = 0.5 * (G + G.T)
+    r = oracle.block_lanczos(H, k, max_steps=steps, seed=4)
+    w, _, _ = oracle.jacobi_eigh(H)
+    th, res, Vb = r["theta"], r["res"], r["basis"]
+    n = th.size
+    assert n == steps * r["b"] and Vb.shape == (d, n)
+    np.testing.assert_allclose(Vb.T @ Vb, np.eye(n), atol=1e-12)
+    assert np.all(th >= w[:n] - 1e-10) and np.all(th <= w[d - n:] + 1e-10)
+    dist = np.min(np.abs(w[None, :] - th[:, None]), axis=1)
+    assert np.all(dist <= res * (1 + 1e-8) + 1e-10)
+    thx, Y = np.linalg.eigh(Vb.T @ H @ Vb)
+    np.testing.assert_allclose(thx, th, atol=1e-10)
+    Xr = Vb @ Y
+    true_res = np.linalg.norm(H @ Xr - Xr * thx[None, :], axis=0)
+    sep = np.min(np.abs(np.diff(thx)))
+    if sep > 1e-6:
+        np.testing.assert_allclose(res, true_res, rtol=1e-6, atol=1e-10)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lanczos_planted_gap_certified(seed):
+    # Planted spectrum (exact eigenvalues from the generator): at convergence
+    # both endpoint estimates lie within eps of the truth, eps is below a
+    # quarter of the estimated gap, the midpoint lies in the true gap and the
+    # Prop. 4.2 test passes; the spectral-radius estimate is a lower bound
+    # of rho(H - sI) and close to it.
+    d, k, g = 400, 4, 0.1
+    H, lam, _ = inputs.planted_hessian(d, k, g, seed)
+    r = oracle.block_lanczos(H, k, seed=seed)
+    assert r["converged"]
+    assert abs(r["lam_k"] - lam[k - 1]) <= r["eps"] and abs(r["lam_k1"] - lam[k]) <= r["eps"]
+    assert r["eps"] < 0.25 * (r["lam_k1"] - r["lam_k"])
+    assert lam[k - 1] < r["s"] < lam[k]
+    ok, _, margin = oracle.admissible(r["lam_k"], r["lam_k1"], r["eps"], r["s"])
+    assert ok and margin > 0
+    rho = max(lam[-1] - r["s"], r["s"] - lam[0])
+    assert r["rho"] <= rho + 1e-12 and r["rho"] > 0.99 * rho
+
+
+def test_lanczos_check_schedule():
+    assert oracle.lanczos_block_size(4096, 5) == 9
+    assert oracle.lanczos_block_size(4096, 40) == 32
+    assert oracle.lanczos_block_size(6, 4) == 6
+    c = oracle.lanczos_check_steps(4096, 5, 9)
+    assert c[0] == 1 and c[1] == 5 and c[-1] == 4096 // 9
+    assert oracle.lanczos_check_steps(100, 3, 7, max_steps=6) == [1, 6]

@@ -69,8 +69,11 @@ typedef enum {
 typedef enum { REFL_SHIFT_GIVEN = 0, REFL_SHIFT_LANCZOS = 1 } refl_shift_mode_t;
 
 typedef enum {
-  REFL_SCALE_INF = 0,   /* alpha = ||H - sI||_inf (max absolute row sum) */
-  REFL_SCALE_GIVEN = 1  /* alpha = params.alpha; X_0 = (H - sI)/alpha */
+  REFL_SCALE_INF = 0,    /* alpha = ||H - sI||_inf (max absolute row sum) */
+  REFL_SCALE_GIVEN = 1,  /* alpha = params.alpha; X_0 = (H - sI)/alpha */
+  REFL_SCALE_LANCZOS = 2 /* alpha = 1.05 rho_hat with rho_hat the Lanczos estimate of
+                            max_i |lambda_i - s| (the spectral-norm scaling of section 4.3);
+                            needs shift_mode == REFL_SHIFT_LANCZOS */
 } refl_scale_mode_t;
 
 typedef struct {
@@ -135,7 +138,9 @@ refl_status_t refl_destroy(refl_handle_t h);
 refl_status_t refl_set_stream(refl_handle_t h, void *hip_stream);
 
 /* Bytes of device workspace refl_sign / refl_sign_apply need for order d
- * and parameters *p (refl_estimate_shift needs no more than this). */
+ * and parameters *p.  With shift_mode = REFL_SHIFT_LANCZOS this includes the
+ * Lanczos basis (d x (cap + 1) b doubles), and covers refl_estimate_shift
+ * for the same d, k and lanczos_steps. */
 refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_t *p,
                                   size_t *bytes);
 
@@ -145,13 +150,29 @@ refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_
 refl_status_t refl_set_workspace(refl_handle_t h, void *dptr, size_t bytes);
 
 /* Shift estimation by block Lanczos with full reorthogonalisation on H
- * (section 4.3, recommended default realization; Prop. 4.2).  Returns the
- * midpoint *s of the estimates *lam_k, *lam_k1 of lambda_k, lambda_{k+1},
- * a common residual bound *eps on both (|lam_hat - lam| <= eps when the
- * Ritz values are attributed to the right eigenvalues), and an estimate
- * *rho of max_i |lambda_i - s|.  REFL_ERR_NOT_ADMISSIBLE if the margin
- * m_hat = min(s - lam_k, lam_k1 - s) does not exceed eps; REFL_ERR_NO_GAP if
- * the estimates coincide. */
+ * (section 4.3, recommended default realization: a partial eigensolver near
+ * the target gap; Prop. 4.1 midpoint; Prop. 4.2 margin test).
+ *
+ * Block width b = min(k + 4, 32, d), start block from the SplitMix64 hash of
+ * (seed, column, row) mapped to (-1, 1), at most floor(d / b) block steps
+ * (`steps` > 0 lowers that cap).  After step ceil((k + 1) / b), then every
+ * ceil(32 / b) steps and at the cap, the Ritz values theta of the block
+ * tridiagonal projection and the residual norms ||H x - theta x|| of the
+ * Ritz pairs k and k+1 are formed; the run stops once
+ * eps = max(res_k, res_k+1) < (theta_k+1 - theta_k) / 4.
+ *
+ * Outputs: *lam_k, *lam_k1 the Ritz values theta_k, theta_k+1; *eps the
+ * residual bound (each estimate lies within eps of an eigenvalue of H:
+ * |lam_hat - lam| <= eps when the Ritz values are attributed to the right
+ * eigenvalues, which the index certificate of refl_sign then confirms);
+ * *s = (lam_k + lam_k1)/2; *rho = max(theta_max - s, s - theta_min), an
+ * estimate (from below) of max_i |lambda_i - s|.  The outputs are written
+ * also on REFL_ERR_NOT_ADMISSIBLE and REFL_ERR_NO_GAP.
+ *
+ * Status: REFL_OK when the margin m_hat = min(s - lam_k, lam_k1 - s)
+ * exceeds eps (Prop. 4.2), REFL_ERR_NOT_ADMISSIBLE when it does not at the
+ * step cap, REFL_ERR_NO_GAP when the two estimates coincide.  Device
+ * workspace: as refl_workspace_size for shift_mode = REFL_SHIFT_LANCZOS. */
 refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
                                   int32_t k, int32_t steps, uint64_t seed, double *s,
                                   double *lam_k, double *lam_k1, double *eps, double *rho);

@@ -1,7 +1,11 @@
-// Small dense linear algebra on the host for the k x k and block-Lanczos
-// problems of the driver (never larger than a few hundred): symmetric
-// eigen-decomposition by Householder reduction to tridiagonal form followed
-// by the implicit QL iteration with shifts, and a Cholesky factorisation.
+// Small dense linear algebra on the host for the k x k problems of the
+// driver: symmetric eigen-decomposition by Householder reduction to
+// tridiagonal form followed by the implicit QL iteration with shifts, and a
+// Cholesky factorisation.  For the block tridiagonal matrices of the
+// Lanczos run (order up to d, half-bandwidth b <= 32): reduction of a band
+// matrix to tridiagonal form by plane rotations that chase the bulge down the
+// band (Schwarz, Numer. Math. 12, 1968), Sturm-sequence bisection for single
+// eigenvalues (Kahan's LDL^T count), and inverse iteration with banded LU.
 #include "hostla.h"
 
 #include <algorithm>
@@ -153,6 +157,201 @@ void inv_lower_transpose(int n, const double* L, double* C) {
   // (L^{-T})_{ij} = (L^{-1})_{ji}
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) C[i + (size_t)n * j] = Li[(size_t)j * n + i];
+}
+
+void band_tridiag(int n, int bw, const double* Lb, double* diag, double* sub) {
+  // Working storage with one extra diagonal for the bulge:
+  // A[i][j] (i >= j, i - j <= bw + 1) at S[i * ws + (i - j)], ws = bw + 2.
+  const int ws = bw + 2;
+  std::vector<double> S((size_t)n * ws, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t <= bw && t <= i; ++t) S[(size_t)i * ws + t] = Lb[(size_t)i * (bw + 1) + t];
+  double* A = S.data();
+  // Rotation in the plane (p, q = p + 1) that zeroes A[q][col] (col < p):
+  // rows p and q of the lower band (columns m < p) are contiguous, and for
+  // m > q the pair (A[m][q], A[m][p]) is adjacent in row m.
+  auto rotate = [&](int p, int col) {
+    const int q = p + 1;
+    double* rp = A + (size_t)p * ws;  // rp[t] = A[p][p - t]
+    double* rq = A + (size_t)q * ws;  // rq[t] = A[q][q - t]
+    const double a = rp[p - col], e = rq[q - col];
+    if (e == 0.0) return;
+    const double r = std::hypot(a, e), c = a / r, s = e / r;
+    const int lo = std::max(0, q - bw - 1);
+    for (int m = lo; m < p; ++m) {
+      const double x = rp[p - m], y = rq[q - m];
+      rp[p - m] = c * x + s * y;
+      rq[q - m] = -s * x + c * y;
+    }
+    const int hi = std::min(n - 1, p + bw + 1);
+    for (int m = q + 1; m <= hi; ++m) {
+      double* rm = A + (size_t)m * ws;
+      const double x = rm[m - p], y = rm[m - q];
+      rm[m - p] = c * x + s * y;
+      rm[m - q] = -s * x + c * y;
+    }
+    const double app = rp[0], aqq = rq[0], apq = rq[1];
+    rp[0] = c * c * app + 2.0 * c * s * apq + s * s * aqq;
+    rq[0] = s * s * app - 2.0 * c * s * apq + c * c * aqq;
+    rq[1] = c * s * (aqq - app) + (c * c - s * s) * apq;
+    rq[q - col] = 0.0;
+  };
+  if (bw > 1) {
+    for (int k = 0; k + 2 < n; ++k) {
+      for (int r = std::min(bw, n - 1 - k); r >= 2; --r) {
+        int i = k + r, col = k;
+        rotate(i - 1, col);
+        while (i + bw < n) {  // bulge at (i + bw, i - 1)
+          col = i - 1;
+          i += bw;
+          rotate(i - 1, col);
+        }
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) diag[i] = A[(size_t)i * ws];
+  for (int i = 0; i + 1 < n; ++i) sub[i] = (bw >= 1) ? A[(size_t)(i + 1) * ws + 1] : 0.0;
+}
+
+int tridiag_count_below(int n, const double* diag, const double* sub, double x) {
+  // Number of negative pivots of the LDL^T factorisation of T - xI.
+  const double tiny = 1e-300;
+  int cnt = 0;
+  double q = diag[0] - x;
+  if (q == 0.0) q = -tiny;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    q = (diag[i] - x) - sub[i - 1] * sub[i - 1] / q;
+    if (q == 0.0) q = -tiny;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+double tridiag_eigval(int n, const double* diag, const double* sub, int m) {
+  // Gershgorin interval, then bisection on the Sturm count.
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(sub[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(sub[i]) : 0.0);
+    lo = std::min(lo, diag[i] - r);
+    hi = std::max(hi, diag[i] + r);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  lo -= 1e-14 * scale + 1e-300;
+  hi += 1e-14 * scale + 1e-300;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= 4.0 * 2.220446049250313e-16 * std::max(std::fabs(lo), std::fabs(hi))) break;
+    if (tridiag_count_below(n, diag, sub, mid) > m)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+int band_count_below(int n, int bw, const double* Lb, double x, double* work) {
+  // T - xI = L D L^T without pivoting; L (unit lower, band) row i at
+  // work[i * bw + (i - j - 1)], j = i - bw .. i - 1; D at work[n * bw + i].
+  // Returns the number of negative pivots, or -1 if a multiplier exceeds
+  // 1e8 in size (element growth: the count is not trusted).
+  double* L = work;
+  double* D = work + (size_t)n * bw;
+  const double tiny = 1e-300;
+  int cnt = 0;
+  for (int i = 0; i < n; ++i) {
+    const int j0 = std::max(0, i - bw);
+    const double* ai = Lb + (size_t)i * (bw + 1);  // ai[t] = T[i][i - t]
+    double* li = L + (size_t)i * bw;                // li[t - 1] = L[i][i - t]
+    double di = ai[0] - x;
+    for (int j = j0; j < i; ++j) {
+      // u = T[i][j] - sum_{m < j} L[i][m] D[m] L[j][m]
+      double u = ai[i - j];
+      const double* lj = L + (size_t)j * bw;
+      for (int m = std::max(j0, j - bw); m < j; ++m) u -= li[i - m - 1] * D[m] * lj[j - m - 1];
+      const double l = u / D[j];
+      if (!(std::fabs(l) < 1e8)) return -1;
+      li[i - j - 1] = l;
+      di -= l * u;
+    }
+    if (di == 0.0) di = -tiny;
+    D[i] = di;
+    if (di < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters,
+                              double* y) {
+  // LU with partial pivoting of B = T - sigma I (band, half-bandwidth bw).
+  // Row i is held for columns i - bw .. i + 2 bw at U[i * uw + (c - i + bw)].
+  const int uw = 3 * bw + 1;
+  auto tij = [&](int i, int j) -> double {
+    const int t = i >= j ? i - j : j - i;
+    if (t > bw) return 0.0;
+    return i >= j ? Lb[(size_t)i * (bw + 1) + t] : Lb[(size_t)j * (bw + 1) + t];
+  };
+  std::vector<double> U((size_t)n * uw, 0.0), Lm((size_t)n * (bw + 1), 0.0);
+  std::vector<int> piv(n);
+  double tnorm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double rs = 0.0;
+    for (int j = std::max(0, i - bw); j <= std::min(n - 1, i + bw); ++j) {
+      const double v = tij(i, j) - (i == j ? sigma : 0.0);
+      U[(size_t)i * uw + (j - i + bw)] = v;
+      rs += std::fabs(tij(i, j));
+    }
+    tnorm = std::max(tnorm, rs);
+  }
+  const double tiny = 2.220446049250313e-16 * std::max(tnorm, 1e-300);
+  auto u = [&](int i, int c) -> double& { return U[(size_t)i * uw + (c - i + bw)]; };
+  for (int j = 0; j < n; ++j) {
+    const int last = std::min(n - 1, j + bw);
+    int p = j;
+    for (int i = j + 1; i <= last; ++i)
+      if (std::fabs(u(i, j)) > std::fabs(u(p, j))) p = i;
+    piv[j] = p;
+    const int cend = std::min(n - 1, j + 2 * bw);
+    if (p != j)
+      for (int c = j; c <= cend; ++c) std::swap(u(j, c), u(p, c));
+    if (std::fabs(u(j, j)) < tiny) u(j, j) = (u(j, j) < 0.0 ? -tiny : tiny);
+    for (int i = j + 1; i <= last; ++i) {
+      const double m = u(i, j) / u(j, j);
+      Lm[(size_t)i * (bw + 1) + (i - j)] = m;
+      u(i, j) = 0.0;
+      if (m != 0.0)
+        for (int c = j + 1; c <= cend; ++c) u(i, c) -= m * u(j, c);
+    }
+  }
+  // Start vector: a fixed, non-special sequence.
+  for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * std::sin(1.0 + 0.7 * i);
+  for (int it = 0; it < iters; ++it) {
+    // Forward: apply the row swaps and unit-lower multipliers in order.
+    for (int j = 0; j < n; ++j) {
+      if (piv[j] != j) std::swap(y[j], y[piv[j]]);
+      const int last = std::min(n - 1, j + bw);
+      for (int i = j + 1; i <= last; ++i) y[i] -= Lm[(size_t)i * (bw + 1) + (i - j)] * y[j];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      const int cend = std::min(n - 1, i + 2 * bw);
+      for (int c = i + 1; c <= cend; ++c) s -= u(i, c) * y[c];
+      y[i] = s / u(i, i);
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
+    nrm = std::sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) return INFINITY;
+    for (int i = 0; i < n; ++i) y[i] /= nrm;
+  }
+  double r2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double s = -sigma * y[i];
+    for (int j = std::max(0, i - bw); j <= std::min(n - 1, i + bw); ++j) s += tij(i, j) * y[j];
+    r2 += s * s;
+  }
+  return std::sqrt(r2);
 }
 
 }  // namespace refl

@@ -14,4 +14,26 @@ int cholesky_small(int n, const double* G, double* L);
 // C = L^{-T} for lower-triangular L (row-major), written column-major.
 void inv_lower_transpose(int n, const double* L, double* C);
 
+// Symmetric band matrices of order n and half-bandwidth bw, given by their
+// lower band: Lb[i * (bw + 1) + (i - j)] = T[i][j] for 0 <= i - j <= bw.
+
+// Orthogonally similar tridiagonal matrix: diag[0..n), sub[0..n-1).
+void band_tridiag(int n, int bw, const double* Lb, double* diag, double* sub);
+
+// Number of eigenvalues of the symmetric tridiagonal (diag, sub) below x.
+int tridiag_count_below(int n, const double* diag, const double* sub, double x);
+
+// The m-th smallest eigenvalue (m = 0 .. n-1) of (diag, sub) by bisection.
+double tridiag_eigval(int n, const double* diag, const double* sub, int m);
+
+// Number of eigenvalues of the band matrix below x, from the signs of the
+// pivots of T - xI = L D L^T (Sylvester's law of inertia), or -1 if the
+// factorisation without pivoting grew (a multiplier above 1e8).  work holds
+// n * (bw + 1) doubles.
+int band_count_below(int n, int bw, const double* Lb, double x, double* work);
+
+// Unit vector y (length n) from `iters` steps of inverse iteration with
+// T - sigma I; returns ||T y - sigma y||_2.
+double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters, double* y);
+
 }  // namespace refl

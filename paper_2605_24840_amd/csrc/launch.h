@@ -121,4 +121,28 @@ hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const doubl
                         void* state, double* work, double* part, int it, int max_iter,
                         hipStream_t st);
 
+// ---- block Lanczos (see lanczos.hip) ----
+// Workspace sizes (doubles) for a d-row basis of up to nmax columns and
+// blocks of nb <= 32 columns.
+int lz_nb_pad(int nb);
+size_t lz_proj_part_doubles(int d, int nmax, int nb);
+size_t lz_apply_part_doubles(int d, int nmax, int nb);
+size_t lz_gram_part_doubles(int d, int nb);
+// One block Gram-Schmidt pass of W (d x nb) against V (d x n): C = V^T W,
+// W <- W - V C.  The rows of C on the last b columns of V go to Arec
+// (accumulate: added).  With gpart != null the Gram partials of the new W
+// are written for lz_chol.
+hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
+                      double* C, double* Arec, int b, int accumulate, double* ppart,
+                      double* apart, double* gpart, hipStream_t st);
+// dst = W R^{-1} (R upper triangular nb x nb on the device; R == null: a
+// copy), with optional Gram partials of the result.
+hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R, double* dst,
+                   int64_t ldd, double* gpart, hipStream_t st);
+// Cholesky of the summed Gram partials (+ shift_rel * trace I); R = L^T;
+// Bacc = R (round 0) or R Bacc; see lanczos.hip for Brec and flag.
+hipError_t lz_chol(const double* gpart, int d, int nb, double shift_rel, double* R, double* Bacc,
+                   int round, const double* Arec, double* Brec, int* flag, int tag,
+                   hipStream_t st);
+
 }  // namespace refl

@@ -98,6 +98,15 @@ struct Carve {
 
 constexpr int MAXB = 32;  // widest block of vectors
 
+// Block-Lanczos buffers (carved only when the shift is estimated).
+struct LzWork {
+  int b = 0, J = 0, nmax = 0;
+  double *V = nullptr, *W = nullptr, *C = nullptr;
+  double *ppart = nullptr, *apart = nullptr, *gpart = nullptr;
+  double *R = nullptr, *Bacc = nullptr, *TA = nullptr, *TB = nullptr;
+  int* flag = nullptr;
+};
+
 struct Work {
   int d, dp, ntiles, words;
   int ts, dk;  // bulk tile edge and K extent of the bulk products
@@ -114,6 +123,7 @@ struct Work {
   // block vectors (ld = dp), polish and apply
   double *V, *W, *Z, *Rr, *P[2], *AP, *T1, *T2, *G, *thin, *gwork, *cgpart;
   void* cgstate;
+  LzWork lz;
 };
 
 // Bulk tile edge for the word products: the edge whose upper-triangle tile
@@ -140,8 +150,16 @@ int choose_tile(int64_t d, int words, int ncu) {
   return bt;
 }
 
-size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, bool for_apply, int ncu) {
+void carve_lanczos(Carve& c, LzWork& z, int64_t d, int dp, int k, int steps);
+
+// Workspace of refl_sign / refl_sign_apply (kind SIGN), refl_apply (APPLY)
+// or refl_estimate_shift (ESTIMATE: the FP64 copy of H and the Lanczos
+// buffers only).
+enum LayoutKind { LAYOUT_SIGN, LAYOUT_APPLY, LAYOUT_ESTIMATE };
+
+size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind kind, int ncu) {
   Carve c(base);
+  const bool for_apply = kind == LAYOUT_APPLY;
   w.d = (int)d;
   w.ts = (!for_apply && p.precision == REFL_PREC_MIXED) ? choose_tile(d, p.words, ncu) : TILE;
   w.dp = (int)round_up(d, w.ts);
@@ -158,6 +176,13 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, bool for_a
   w.X64[0] = w.X64[1] = w.N64 = nullptr;
   w.X32[0] = w.X32[1] = w.N32 = nullptr;
   w.Xw[0] = w.Xw[1] = w.Nw = nullptr;
+  w.lz = LzWork();
+  if (kind == LAYOUT_ESTIMATE) {
+    w.Hf = c.take<double>(n2);
+    w.thin = c.take<double>(thin_work_doubles((int)dp));
+    carve_lanczos(c, w.lz, d, w.dp, p.k, p.lanczos_steps);
+    return c.off + 256;
+  }
   if (!for_apply) {
     w.Hf = c.take<double>(n2);
     if (p.precision == REFL_PREC_FP64) {
@@ -191,6 +216,7 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, bool for_a
   w.gwork = c.take<double>(gram_work_doubles((int)dp));
   w.cgpart = c.take<double>(cg_part_doubles((int)dp));
   w.cgstate = c.take<char>(cg_state_bytes());
+  if (!for_apply && p.shift_mode == REFL_SHIFT_LANCZOS) carve_lanczos(c, w.lz, d, w.dp, p.k, p.lanczos_steps);
   return c.off + 256;
 }
 
@@ -225,8 +251,12 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
   if (p->precision < 0 || p->precision > 2) return fail(h, REFL_ERR_INVALID_ARG, "bad precision");
   if (p->shift_mode != REFL_SHIFT_GIVEN && p->shift_mode != REFL_SHIFT_LANCZOS)
     return fail(h, REFL_ERR_INVALID_ARG, "bad shift_mode");
-  if (p->scale_mode != REFL_SCALE_INF && p->scale_mode != REFL_SCALE_GIVEN)
+  if (p->scale_mode != REFL_SCALE_INF && p->scale_mode != REFL_SCALE_GIVEN &&
+      p->scale_mode != REFL_SCALE_LANCZOS)
     return fail(h, REFL_ERR_INVALID_ARG, "bad scale_mode");
+  if (p->scale_mode == REFL_SCALE_LANCZOS && p->shift_mode != REFL_SHIFT_LANCZOS)
+    return fail(h, REFL_ERR_INVALID_ARG, "scale_mode LANCZOS needs shift_mode LANCZOS");
+  if (p->lanczos_steps < 0) return fail(h, REFL_ERR_INVALID_ARG, "lanczos_steps must be >= 0");
   if (p->scale_mode == REFL_SCALE_GIVEN && !(p->alpha > 0.0 && std::isfinite(p->alpha)))
     return fail(h, REFL_ERR_INVALID_ARG, "alpha must be finite and > 0");
   if (p->shift_mode == REFL_SHIFT_GIVEN && !std::isfinite(p->s))
@@ -401,6 +431,241 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
   return REFL_OK;
 }
 
+// ------------------------------------------------------------ block Lanczos
+// Shift estimation (section 4.3: a partial eigensolver near the target gap,
+// then the midpoint of Prop. 4.1 and the margin test of Prop. 4.2).  Block
+// width b = min(k + 4, 32, d); at most floor(d / b) steps; the convergence
+// test runs after step ceil((k + 1) / b) and then every ceil(32 / b) steps,
+// and always at the last step.
+
+
+int lz_block(int64_t d, int k) { return (int)std::min<int64_t>(std::min(k + 4, 32), d); }
+int lz_cap(int64_t d, int b, int steps) {
+  const int cap = (int)(d / b);
+  return steps > 0 ? std::min(steps, cap) : cap;
+}
+
+void carve_lanczos(Carve& c, LzWork& z, int64_t d, int dp, int k, int steps) {
+  z.b = lz_block(d, k);
+  z.J = lz_cap(d, z.b, steps);
+  z.nmax = (z.J + 1) * z.b;
+  const int64_t ld = dp;
+  z.V = c.take<double>(ld * z.nmax);
+  z.W = c.take<double>(ld * z.b);
+  z.C = c.take<double>((size_t)z.nmax * z.b);
+  z.ppart = c.take<double>(lz_proj_part_doubles((int)d, z.nmax, z.b));
+  z.apart = c.take<double>(lz_apply_part_doubles((int)d, z.nmax, z.b));
+  z.gpart = c.take<double>(lz_gram_part_doubles((int)d, z.b));
+  z.R = c.take<double>((size_t)z.b * z.b);
+  z.Bacc = c.take<double>((size_t)z.b * z.b);
+  z.TA = c.take<double>((size_t)z.J * z.b * z.b);
+  z.TB = c.take<double>((size_t)z.J * z.b * z.b);
+  z.flag = c.take<int>(2);
+}
+
+struct LzResult {
+  double lam_k = NaN, lam_k1 = NaN, eps = NaN, s = NaN, rho = NaN;
+  int steps = 0;
+  bool converged = false;
+};
+
+// Ritz values and residual radii of the first j steps.  TA/TB hold the
+// blocks A_i (symmetric) and B_i (upper triangular), b x b column-major.
+struct RitzCheck {
+  double th_k = NaN, th_k1 = NaN, res_k = NaN, res_k1 = NaN, th_min = NaN, th_max = NaN;
+};
+
+void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
+                RitzCheck& out) {
+  const int n = j * b;
+  std::vector<double> Lb((size_t)n * (b + 1), 0.0);  // lower band of T_j
+  for (int i = 0; i < n; ++i) {
+    const int I = i / b, r = i % b;
+    const double* A = TA + (size_t)I * b * b;
+    for (int c = 0; c <= r; ++c) Lb[(size_t)i * (b + 1) + (r - c)] = 0.5 * (A[r + c * b] + A[c + r * b]);
+    if (I > 0) {
+      const double* B = TB + (size_t)(I - 1) * b * b;  // T[I b + r][(I-1) b + c] = B[r][c], r <= c
+      for (int c = r; c < b; ++c) Lb[(size_t)i * (b + 1) + (b + r - c)] = B[r + c * b];
+    }
+  }
+  // Gershgorin bounds.
+  double glo = INFINITY, ghi = -INFINITY;
+  {
+    std::vector<double> rad(n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int t = 1; t <= b && t <= i; ++t) {
+        const double v = std::fabs(Lb[(size_t)i * (b + 1) + t]);
+        rad[i] += v;
+        rad[i - t] += v;
+      }
+    for (int i = 0; i < n; ++i) {
+      glo = std::min(glo, Lb[(size_t)i * (b + 1)] - rad[i]);
+      ghi = std::max(ghi, Lb[(size_t)i * (b + 1)] + rad[i]);
+    }
+  }
+  const double scale = std::max({std::fabs(glo), std::fabs(ghi), 1e-300});
+  std::vector<double> work((size_t)n * (b + 1)), diag, sub;
+  bool reduced = false;
+  // Bracket the m-th smallest eigenvalue (0-based) to width 1e-9 * scale by
+  // bisection on the inertia of T - xI; if the factorisation declines, use
+  // the band-to-tridiagonal reduction and its Sturm count instead.
+  auto count = [&](double x) {
+    if (!reduced) {
+      const int c = band_count_below(n, b, Lb.data(), x, work.data());
+      if (c >= 0) return c;
+      diag.resize(n);
+      sub.resize(std::max(n - 1, 1));
+      band_tridiag(n, b, Lb.data(), diag.data(), sub.data());
+      reduced = true;
+    }
+    return tridiag_count_below(n, diag.data(), sub.data(), x);
+  };
+  auto bracket = [&](int m) {
+    double lo = glo - 1e-12 * scale, hi = ghi + 1e-12 * scale;
+    while (hi - lo > 1e-9 * scale) {
+      const double mid = 0.5 * (lo + hi);
+      if (count(mid) > m) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+  };
+  // Residual radius of the Ritz pair near sigma: inverse iteration gives the
+  // vector y of T, theta its Rayleigh quotient, and
+  // ||H x - theta x||^2 = ||(T - theta) y||^2 + ||B_j y(last block)||^2.
+  std::vector<double> y(n), ty(n);
+  const double* Bj = TB + (size_t)(j - 1) * b * b;
+  auto pair = [&](double sigma, double& theta, double& res) {
+    band_inverse_iteration(n, b, Lb.data(), sigma, 3, y.data());
+    double q = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int t = 0; t <= b; ++t) {
+        if (i - t >= 0) s += Lb[(size_t)i * (b + 1) + t] * y[i - t];
+        if (t > 0 && i + t < n) s += Lb[(size_t)(i + t) * (b + 1) + t] * y[i + t];
+      }
+      ty[i] = s;
+      q += s * y[i];
+    }
+    theta = q;
+    double r1 = 0.0;
+    for (int i = 0; i < n; ++i) r1 += (ty[i] - q * y[i]) * (ty[i] - q * y[i]);
+    double r2 = 0.0;
+    for (int r = 0; r < b; ++r) {
+      double s = 0.0;
+      for (int c = r; c < b; ++c) s += Bj[r + c * b] * y[n - b + c];
+      r2 += s * s;
+    }
+    res = std::sqrt(r1 + r2);
+  };
+  pair(bracket(k - 1), out.th_k, out.res_k);
+  pair(bracket(k), out.th_k1, out.res_k1);
+  if (extremes) {
+    double unused;
+    pair(bracket(0), out.th_min, unused);
+    pair(bracket(n - 1), out.th_max, unused);
+  }
+}
+
+// Runs the estimate on the padded symmetric copy Hf (ld dp).  Returns
+// REFL_OK with r filled (converged or at the step cap), or a device error.
+refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, int k, uint64_t seed,
+                          LzWork& z, double* thin, LzResult& r) {
+  hipStream_t st = h->stream;
+  const int b = z.b, J = z.J;
+  const int64_t ld = dp;
+  const double shift_rel = 11.0 * ((double)d * b + (double)b * (b + 1)) * 2.220446049250313e-16;
+  HIPCHK(hipMemsetAsync(z.flag, 0, 2 * sizeof(int), st));
+  // Q_1: the start block, orthonormalised by shifted CholQR3.
+  auto cholqr3 = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
+    HIPCHK(lz_rows(z.W, ld, b, (int)d, nullptr, z.W, ld, z.gpart, st));
+    for (int round = 0; round < 3; ++round) {
+      HIPCHK(lz_chol(z.gpart, (int)d, b, round == 0 ? shift_rel : 0.0, z.R, z.Bacc, round,
+                     round == 2 ? Arec : nullptr, round == 2 ? Brec : nullptr, z.flag, tag, st));
+      HIPCHK(lz_rows(z.W, ld, b, (int)d, z.R, round == 2 ? dst : z.W, ld,
+                     round == 2 ? nullptr : z.gpart, st));
+    }
+    return REFL_OK;
+  };
+  HIPCHK(random_block(z.W, ld, (int)d, b, seed, st));
+  refl_status_t rs = cholqr3(z.V, nullptr, nullptr, 0);
+  if (rs != REFL_OK) return rs;
+  const int j0 = std::max(1, (k + 1 + b - 1) / b);
+  const int ci = std::max(1, (32 + b - 1) / b);
+  std::vector<double> TA, TB;
+  int hflag[2] = {0, 0};
+  for (int j = 1; j <= J; ++j) {
+    const int n = j * b;
+    const double* Qj = z.V + (int64_t)(n - b) * ld;
+    double* Aj = z.TA + (size_t)(j - 1) * b * b;
+    double* Bj = z.TB + (size_t)(j - 1) * b * b;
+    HIPCHK(symthin_f64(Hf, ld, (int)d, Qj, ld, b, z.W, ld, thin, st));
+    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, z.apart, nullptr, st));
+    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.apart, z.gpart, st));
+    if ((int64_t)n >= d) {
+      HIPCHK(hipMemsetAsync(Bj, 0, sizeof(double) * b * b, st));  // the basis spans R^d
+    } else {
+      // The Gram partials of W are already in gpart: rounds of CholQR3.
+      for (int round = 0; round < 3; ++round) {
+        HIPCHK(lz_chol(z.gpart, (int)d, b, round == 0 ? shift_rel : 0.0, z.R, z.Bacc, round,
+                       round == 2 ? Aj : nullptr, round == 2 ? Bj : nullptr, z.flag, j, st));
+        HIPCHK(lz_rows(z.W, ld, b, (int)d, z.R, round == 2 ? z.V + (int64_t)n * ld : z.W, ld,
+                       round == 2 ? nullptr : z.gpart, st));
+      }
+    }
+    const bool check = (j >= j0 && (j - j0) % ci == 0) || j == J;
+    if (!check) continue;
+    TA.resize((size_t)j * b * b);
+    TB.resize((size_t)j * b * b);
+    HIPCHK(hipMemcpyAsync(TA.data(), z.TA, sizeof(double) * TA.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(TB.data(), z.TB, sizeof(double) * TB.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hflag, z.flag, sizeof(hflag), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // A QR that lost rank at step jb: with only a near-invariant space (bit 2)
+    // B_jb is still valid, so T_jb and its residual are used; after a failed
+    // Cholesky (bit 1) the last valid state is step jb - 1.
+    int jj = j;
+    bool stop = (j == J);
+    if (hflag[1] > 0 && hflag[1] <= j) {
+      jj = (hflag[0] & 1) ? hflag[1] - 1 : hflag[1];
+      stop = true;
+      if (jj < 1) return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: start block lost rank");
+    }
+    if (jj * b < k + 1) {
+      if (stop) return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: basis too small for k=%d", k);
+      continue;
+    }
+    RitzCheck rc;
+    ritz_check(jj, b, k, TA.data(), TB.data(), false, rc);
+    const double eps = std::max(rc.res_k, rc.res_k1);
+    const bool conv = eps < 0.25 * (rc.th_k1 - rc.th_k);
+    if (conv || stop) {
+      ritz_check(jj, b, k, TA.data(), TB.data(), true, rc);
+      r.lam_k = rc.th_k;
+      r.lam_k1 = rc.th_k1;
+      r.eps = eps;
+      r.s = 0.5 * (rc.th_k + rc.th_k1);
+      r.rho = std::max(rc.th_max - r.s, r.s - rc.th_min);
+      r.steps = jj;
+      r.converged = conv;
+      return REFL_OK;
+    }
+  }
+  return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: no test at the step cap");
+}
+
+// Status of an estimate by Prop. 4.2: the margin m_hat must exceed eps.
+refl_status_t lanczos_status(refl_handle_t h, const LzResult& r) {
+  const double gap = r.lam_k1 - r.lam_k;
+  if (!(gap > 1e-14 * std::max(std::fabs(r.lam_k), std::fabs(r.lam_k1))))
+    return fail(h, REFL_ERR_NO_GAP, "Lanczos estimates of lambda_k and lambda_k+1 coincide (%.6e, %.6e)",
+                r.lam_k, r.lam_k1);
+  const double m_hat = std::min(r.s - r.lam_k, r.lam_k1 - r.s);
+  if (!(m_hat > r.eps))
+    return fail(h, REFL_ERR_NOT_ADMISSIBLE,
+                "Lanczos margin %.3e does not exceed the residual bound %.3e after %d steps", m_hat,
+                r.eps, r.steps);
+  return REFL_OK;
+}
+
 // Shared body of refl_sign and refl_sign_apply.  If dR is non-null, R is
 // written; otherwise dY = R dV.
 refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -417,25 +682,13 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   inf.lam_k = inf.lam_k1 = inf.eps = inf.margin = NaN;
   inf.commutator_fro = inf.dk_bound = NaN;
   inf.index_j = -1;
-  if (p.shift_mode == REFL_SHIFT_LANCZOS) {
-    double s, lk, lk1, eps, rho;
-    rs = refl_estimate_shift(h, d, dH, ldh, p.k, p.lanczos_steps, p.seed, &s, &lk, &lk1, &eps, &rho);
-    if (rs != REFL_OK) return rs;
-    p.s = s;
-    inf.lam_k = lk;
-    inf.lam_k1 = lk1;
-    inf.eps = eps;
-    inf.margin = std::fmin(s - lk, lk1 - s) - eps;
-  }
-  const double s = p.s;
-  inf.s = s;
   HIPCHK(hipSetDevice(h->device));
   Work w;
-  const size_t need = layout(w, nullptr, d, p, false, h->ncu);
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_SIGN, h->ncu);
   void* base = nullptr;
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, false, h->ncu);
+  layout(w, base, d, p, LAYOUT_SIGN, h->ncu);
   hipStream_t st = h->stream;
   double* hsc = h->pinned;
 
@@ -444,7 +697,28 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   build_tiles(w, tl);
   HIPCHK(hipMemcpyAsync(w.tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice, st));
   HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, st));
-  HIPCHK(launch_scale_inf(w.Hf, w.dp, (int)d, s, p.scale_mode == REFL_SCALE_GIVEN, p.alpha,
+  double alpha_given = p.alpha;
+  if (p.shift_mode == REFL_SHIFT_LANCZOS) {
+    LzResult lr;
+    rs = lanczos_run(h, w.Hf, w.dp, d, p.k, p.seed, w.lz, w.thin, lr);
+    if (rs != REFL_OK) return rs;
+    inf.lanczos_steps = lr.steps;
+    inf.lam_k = lr.lam_k;
+    inf.lam_k1 = lr.lam_k1;
+    inf.eps = lr.eps;
+    inf.margin = std::min(lr.s - lr.lam_k, lr.lam_k1 - lr.s) - lr.eps;
+    inf.s = lr.s;
+    rs = lanczos_status(h, lr);
+    if (rs != REFL_OK) {
+      if (info) *info = inf;
+      return rs;
+    }
+    p.s = lr.s;
+    if (p.scale_mode == REFL_SCALE_LANCZOS) alpha_given = 1.05 * lr.rho;
+  }
+  const double s = p.s;
+  inf.s = s;
+  HIPCHK(launch_scale_inf(w.Hf, w.dp, (int)d, s, p.scale_mode != REFL_SCALE_INF, alpha_given,
                           w.rowsum, w.scal, st));
   const int W = p.words;
   if (p.precision == REFL_PREC_FP64) {
@@ -729,7 +1003,7 @@ refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_
   refl_status_t rs = check_params(h, d, p);
   if (rs != REFL_OK) return rs;
   Work w;
-  *bytes = layout(w, nullptr, d, *p, false, h->ncu);
+  *bytes = layout(w, nullptr, d, *p, LAYOUT_SIGN, h->ncu);
   return REFL_OK;
 }
 
@@ -767,11 +1041,11 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t l
   refl_params_t p;
   refl_params_default(&p);
   Work w;
-  const size_t need = layout(w, nullptr, d, p, true, h->ncu);
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_APPLY, h->ncu);
   void* base = nullptr;
   refl_status_t rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, true, h->ncu);
+  layout(w, base, d, p, LAYOUT_APPLY, h->ncu);
   for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
     const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
     HIPCHK(thin_gemm_f64(dR, ldr, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, h->stream));
@@ -782,10 +1056,34 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t l
 refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
                                   int32_t k, int32_t steps, uint64_t seed, double* s,
                                   double* lam_k, double* lam_k1, double* eps, double* rho) {
-  (void)d; (void)dH; (void)ldh; (void)k; (void)steps; (void)seed;
-  (void)s; (void)lam_k; (void)lam_k1; (void)eps; (void)rho;
   if (!h) return REFL_ERR_INVALID_ARG;
-  return fail(h, REFL_ERR_UNSUPPORTED, "Lanczos shift estimation not built yet");
+  if (!dH || ldh < d) return fail(h, REFL_ERR_INVALID_ARG, "H is NULL or ldh < d");
+  if (!s || !lam_k || !lam_k1 || !eps || !rho) return fail(h, REFL_ERR_INVALID_ARG, "NULL output");
+  refl_params_t p;
+  refl_params_default(&p);
+  p.k = k;
+  p.shift_mode = REFL_SHIFT_LANCZOS;
+  p.lanczos_steps = steps;
+  p.seed = seed;
+  refl_status_t rs = check_params(h, d, &p);
+  if (rs != REFL_OK) return rs;
+  HIPCHK(hipSetDevice(h->device));
+  Work w;
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_ESTIMATE, h->ncu);
+  void* base = nullptr;
+  rs = ensure_workspace(h, need, &base);
+  if (rs != REFL_OK) return rs;
+  layout(w, base, d, p, LAYOUT_ESTIMATE, h->ncu);
+  HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, h->stream));
+  LzResult lr;
+  rs = lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr);
+  if (rs != REFL_OK) return rs;
+  *s = lr.s;
+  *lam_k = lr.lam_k;
+  *lam_k1 = lr.lam_k1;
+  *eps = lr.eps;
+  *rho = lr.rho;
+  return lanczos_status(h, lr);
 }
 
 const char* refl_status_string(refl_status_t s) {

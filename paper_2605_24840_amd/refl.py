@@ -17,9 +17,11 @@ REFL_OK = 0
 STATUS = {0: "REFL_OK", 1: "REFL_ERR_INVALID_ARG", 2: "REFL_ERR_DEVICE", 3: "REFL_ERR_NO_MEMORY",
           4: "REFL_ERR_NOT_CONVERGED", 5: "REFL_ERR_NOT_ADMISSIBLE", 6: "REFL_ERR_NO_GAP",
           7: "REFL_ERR_NOT_FINITE", 8: "REFL_ERR_UNSUPPORTED"}
+(REFL_ERR_INVALID_ARG, REFL_ERR_DEVICE, REFL_ERR_NO_MEMORY, REFL_ERR_NOT_CONVERGED,
+ REFL_ERR_NOT_ADMISSIBLE, REFL_ERR_NO_GAP, REFL_ERR_NOT_FINITE, REFL_ERR_UNSUPPORTED) = range(1, 9)
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 SHIFT = {"given": 0, "lanczos": 1}
-SCALE = {"inf": 0, "given": 1}
+SCALE = {"inf": 0, "given": 1, "lanczos": 2}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
@@ -214,7 +216,10 @@ class Handle:
 
 def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
                 alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
-                timing=False):
+                timing=False, scale=None):
+    """refl_params_t from keyword arguments.  s=None estimates the shift by
+    block Lanczos; scale is "inf" (default), "given" (with alpha) or
+    "lanczos" (1.05 times the Lanczos spectral-radius estimate)."""
     p = refl_params_default()
     p.k = int(k)
     p.shift_mode = SHIFT["lanczos"] if s is None else SHIFT["given"]
@@ -230,6 +235,8 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     if alpha is not None:
         p.scale_mode = SCALE["given"]
         p.alpha = float(alpha)
+    if scale is not None:
+        p.scale_mode = SCALE[scale]
     p.polish_sweeps = int(polish_sweeps)
     p.cg_tol = float(cg_tol)
     p.cg_max_iter = int(cg_max_iter)

@@ -10,6 +10,9 @@ reflector R_k from H resident in HBM to R resident in HBM.
                correction), which must reach ||R - R_k||_F <= 1e-8 sqrt(d)
   fp64_nsd     the plain FP64 Newton-Schulz iteration on the same input, run
                to the same accuracy (||X^2 - I||_F <= 1e-8 sqrt(d))
+  with_shift_estimate  the same mixed solve with the shift estimated on the
+               GPU by block Lanczos (setup included: the right-hand
+               convention of the paper's timing comparison)
   roofline     the dominant kernel (the bulk BF16-word product), from HIP
                events around every launch in the timed region
   cpu_baseline the oracle (FP64 cyclic Jacobi) on the host cores: one sweep
@@ -46,6 +49,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--words", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--lanczos-steps", type=int, default=3, help="timed solves with the shift estimated")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
@@ -126,6 +130,27 @@ def main():
     steps_mixed = float(np.mean([i["ns_steps"] for i in infos]))
     bulk_alg_tflops = steps_mixed * 2 * float(d) ** 3 / (np.mean([i["ms_bulk"] for i in infos]) / 1e3) / 1e12
 
+    # ---- mixed path with the shift estimated by block Lanczos ----
+    lz_kw = dict(mixed_kw)
+    h.reserve(d, refl.make_params(k, None, **lz_kw))
+
+    def run_lz():
+        _, info, st = refl.sign(Hg, k, None, handle=h, out=R, check=False, seed=seed, **lz_kw)
+        if st != 0:
+            raise RuntimeError(f"refl_sign (Lanczos shift) returned {refl.STATUS[st]}: {refl.refl_last_error(h.h)}")
+        return info
+
+    run_lz()
+    torch.cuda.synchronize()
+    tl = time.perf_counter()
+    infos_lz = [run_lz() for _ in range(args.lanczos_steps)]
+    torch.cuda.synchronize()
+    t_lz = (time.perf_counter() - tl) / args.lanczos_steps
+    err_lz = err_vs_oracle()
+    il = infos_lz[-1]
+    log(f"mixed + Lanczos shift: {1e3 * t_lz:.2f} ms/reflector, lanczos steps={il['lanczos_steps']} "
+        f"setup={il['ms_setup']:.2f} ms s={il['s']:.9f} eps={il['eps']:.2e} err={err_lz:.2e}")
+
     # ---- plain FP64 iteration to the same accuracy ----
     info64 = run(fp64_kw)
     torch.cuda.synchronize()
@@ -183,6 +208,9 @@ def main():
                     "ns_steps": infos64[-1]["ns_steps"], "err_fro": err_fp64,
                     "gemm_tflops": fp64_achieved / 1e12, "gemm_frac_of_fp64_peak": fp64_achieved / FP64_PEAK},
         "speedup_vs_fp64": t_fp64 / t_mixed,
+        "with_shift_estimate": {"value": 1.0 / t_lz, "unit": "reflectors/s", "ms_per_step": 1e3 * t_lz,
+                                "lanczos_steps": il["lanczos_steps"], "ms_setup": il["ms_setup"],
+                                "s": il["s"], "eps": il["eps"], "margin": il["margin"], "err_fro": err_lz},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "traffic": None,
                      "kernel": f"k_sym_gemm_w<{args.words}>", "launches": gemm_n,

@@ -156,7 +156,7 @@ refl_status_t refl_set_workspace(refl_handle_t h, void *dptr, size_t bytes);
  * Block width b = min(k + 4, 32, d), start block from the SplitMix64 hash of
  * (seed, column, row) mapped to (-1, 1), at most floor(d / b) block steps
  * (`steps` > 0 lowers that cap).  After step ceil((k + 1) / b), then every
- * ceil(32 / b) steps and at the cap, the Ritz values theta of the block
+ * ceil(64 / b) steps and at the cap, the Ritz values theta of the block
  * tridiagonal projection and the residual norms ||H x - theta x|| of the
  * Ritz pairs k and k+1 are formed; the run stops once
  * eps = max(res_k, res_k+1) < (theta_k+1 - theta_k) / 4.

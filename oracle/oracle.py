@@ -240,12 +240,12 @@ def lanczos_block_size(d: int, k: int) -> int:
 
 def lanczos_check_steps(d: int, k: int, b: int, max_steps: int = 0):
     """Steps after which the convergence test runs: j0 = ceil((k+1)/b), then
-    every ceil(32/b) steps, and always at the cap J (max_steps, or floor(d/b)
+    every ceil(64/b) steps, and always at the cap J (max_steps, or floor(d/b)
     when 0 or larger than that)."""
     cap = d // b
     J = cap if max_steps <= 0 else min(max_steps, cap)
     j0 = max(1, -(-(k + 1) // b))
-    ci = max(1, -(-32 // b))
+    ci = max(1, -(-64 // b))
     out = list(range(j0, J + 1, ci))
     if not out or out[-1] != J:
         out.append(J)

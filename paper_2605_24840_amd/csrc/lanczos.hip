@@ -8,7 +8,7 @@
 //   then three rounds of Cholesky QR, the first one shifted (shifted
 //   CholQR3 of Fukaya, Kannan, Nakatsukasa, Zhang and Yamamoto, 2020)
 //     k_lz_rows(GRAM)  partial Gram matrices of 256-row slabs
-//     k_lz_chol        one wave: G = L L^T, R = L^T, B <- R B
+//     k_lz_chol        one block: G = L L^T, R = L^T, B <- R B
 //     k_lz_rows(TRSM)  W <- W R^{-1}
 //   so that W_in = Q_{j+1} B_j with B_j upper triangular.
 //
@@ -21,52 +21,77 @@
 
 namespace refl {
 
-constexpr int LZ_RC = 512;  // rows per block of the projection partials
-constexpr int LZ_CC = 128;  // basis columns per block of the update partials
+constexpr int LZ_RC = 128;  // rows per block of the projection partials
+constexpr int LZ_CC = 64;   // basis columns per block of the update partials
 
 static inline int lz_nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 // part[(rc * n + c) * NB + j] = sum over the rows of chunk rc of V[r, c] W[r, j].
-// Block = one wave; CV = 256 / NB basis columns, 4 outputs per lane; the
-// 64-row slabs of V and W are staged in LDS.
+// Block = 256 threads, 64 basis columns x NB (>= 8) block columns; 32-row
+// slabs of V and W staged in LDS; thread t owns columns t % 32 and
+// t % 32 + 32 and block columns t / 32 + 8 q, q < NB / 8.
 template <int NB>
-__global__ __launch_bounds__(64) void k_lz_proj_partial(const double* __restrict__ V, int64_t ldv,
-                                                        int n, const double* __restrict__ W,
-                                                        int64_t ldw, int nb, int d,
-                                                        double* __restrict__ part) {
-  constexpr int CV = 256 / NB;
-  __shared__ double sV[64][CV + 1];
-  __shared__ double sW[64][NB + 1];
-  const int lane = threadIdx.x;
-  const int c0 = blockIdx.x * CV;
+__global__ __launch_bounds__(256) void k_lz_proj_partial(const double* __restrict__ V, int64_t ldv,
+                                                         int n, const double* __restrict__ W,
+                                                         int64_t ldw, int nb, int d,
+                                                         double* __restrict__ part) {
+  static_assert(NB >= 8, "block width padded to at least 8");
+  constexpr int JQ = NB / 8;
+  __shared__ double sV[32][65];
+  __shared__ double sW[32][NB + 1];
+  const int t = threadIdx.x;
+  const int cg = t & 31, jg = t >> 5;
+  const int c0 = blockIdx.x * 64;
   const int r0 = blockIdx.y * LZ_RC;
   const int r1 = min(d, r0 + LZ_RC);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int rs = r0; rs < r1; rs += 64) {
-    const int r = rs + lane;
-    const bool in = r < r1;
-#pragma unroll 4
-    for (int cl = 0; cl < CV; ++cl) {
-      const int c = c0 + cl;
-      sV[lane][cl] = (in && c < n) ? V[(int64_t)c * ldv + r] : 0.0;
-    }
-#pragma unroll 4
-    for (int j = 0; j < NB; ++j) sW[lane][j] = (in && j < nb) ? W[(int64_t)j * ldw + r] : 0.0;
-    __syncthreads();
+  double acc[2][JQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int o = lane + 64 * q, cl = o / NB, j = o % NB;
-      double a = acc[q];
-      for (int i = 0; i < 64; ++i) a = fma(sV[i][cl], sW[i][j], a);
-      acc[q] = a;
+  for (int q = 0; q < JQ; ++q) acc[0][q] = acc[1][q] = 0.0;
+  // The next slab's loads are issued before the current slab is consumed.
+  const int lr = t & 31;
+  double pv[8], pw[JQ];
+  auto load = [&](int rs) {
+    const int r = rs + lr;
+    const bool in = r < r1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + (t >> 5) + 8 * u;
+      pv[u] = (in && c < n) ? V[(int64_t)c * ldv + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < JQ; ++u) {
+      const int j = (t >> 5) + 8 * u;
+      pw[u] = (in && j < nb) ? W[(int64_t)j * ldw + r] : 0.0;
+    }
+  };
+  if (r0 < r1) load(r0);
+  for (int rs = r0; rs < r1; rs += 32) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sV[lr][(t >> 5) + 8 * u] = pv[u];
+#pragma unroll
+    for (int u = 0; u < JQ; ++u) sW[lr][(t >> 5) + 8 * u] = pw[u];
+    __syncthreads();
+    if (rs + 32 < r1) load(rs + 32);
+#pragma unroll 8
+    for (int i = 0; i < 32; ++i) {
+      const double v0 = sV[i][cg], v1 = sV[i][cg + 32];
+#pragma unroll
+      for (int q = 0; q < JQ; ++q) {
+        const double w = sW[i][jg + 8 * q];
+        acc[0][q] = fma(v0, w, acc[0][q]);
+        acc[1][q] = fma(v1, w, acc[1][q]);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int o = lane + 64 * q, cl = o / NB, j = o % NB;
-    const int c = c0 + cl;
-    if (c < n && j < nb) part[((int64_t)blockIdx.y * n + c) * NB + j] = acc[q];
+  for (int h = 0; h < 2; ++h) {
+    const int c = c0 + cg + 32 * h;
+#pragma unroll
+    for (int q = 0; q < JQ; ++q) {
+      const int j = jg + 8 * q;
+      if (c < n && j < nb) part[((int64_t)blockIdx.y * n + c) * NB + j] = acc[h][q];
+    }
   }
 }
 
@@ -81,8 +106,17 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
   const int o = blockIdx.x * 256 + threadIdx.x;
   if (o >= n * nb) return;
   const int c = o % n, j = o / n;
+  // Eight independent loads per round, added in chunk order.
   double s = 0.0;
-  for (int rc = 0; rc < nrc; ++rc) s += part[((int64_t)rc * n + c) * NB + j];
+  int rc = 0;
+  for (; rc + 8 <= nrc; rc += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = part[((int64_t)(rc + u) * n + c) * NB + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += a[u];
+  }
+  for (; rc < nrc; ++rc) s += part[((int64_t)rc * n + c) * NB + j];
   C[c + (int64_t)j * n] = s;
   if (Arec && c >= n - b) {
     double* a = Arec + (c - (n - b)) + (int64_t)j * b;
@@ -91,33 +125,34 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
 }
 
 // apart[(cc * NB + j) * d + r] = sum over the columns c of chunk cc of
-// V[r, c] C[c + j n].  One row per thread; the chunk of C sits in LDS.
+// V[r, c] C[c + j n].  One row per thread (128-row blocks); the chunk of C
+// sits in LDS.
 template <int NB>
-__global__ __launch_bounds__(256) void k_lz_apply_partial(const double* __restrict__ V, int64_t ldv,
+__global__ __launch_bounds__(128) void k_lz_apply_partial(const double* __restrict__ V, int64_t ldv,
                                                           int n, const double* __restrict__ C,
                                                           int nb, int d,
                                                           double* __restrict__ apart) {
   __shared__ double sC[LZ_CC][NB];
   const int c0 = blockIdx.y * LZ_CC;
   const int cn = min(LZ_CC, n - c0);
-  for (int e = threadIdx.x; e < LZ_CC * NB; e += 256) {
+  for (int e = threadIdx.x; e < LZ_CC * NB; e += 128) {
     const int cl = e / NB, j = e % NB;
     sC[cl][j] = (cl < cn && j < nb) ? C[(c0 + cl) + (int64_t)j * n] : 0.0;
   }
   __syncthreads();
-  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int r = blockIdx.x * 128 + threadIdx.x;
   if (r >= d) return;
   double acc[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) acc[j] = 0.0;
   const double* v = V + (int64_t)c0 * ldv + r;
   int cl = 0;
-  for (; cl + 4 <= cn; cl += 4) {
-    double x[4];
+  for (; cl + 8 <= cn; cl += 8) {
+    double x[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = v[(int64_t)(cl + u) * ldv];
+    for (int u = 0; u < 8; ++u) x[u] = v[(int64_t)(cl + u) * ldv];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
 #pragma unroll
       for (int j = 0; j < NB; ++j) acc[j] = fma(x[u], sC[cl + u][j], acc[j]);
   }
@@ -162,7 +197,22 @@ __global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, i
     for (int j = 0; j < NB; ++j)
       if (j < nb) x[j] = W[(int64_t)j * ldw + r];
     if (apart) {
-      for (int cc = 0; cc < ncc; ++cc)
+      // UNR chunks of loads in flight per round, subtracted in chunk order.
+      constexpr int UNR = NB <= 16 ? 4 : 2;
+      int cc = 0;
+      for (; cc + UNR <= ncc; cc += UNR) {
+        double a[UNR][NB];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            a[u][j] = (j < nb) ? apart[((int64_t)(cc + u) * NB + j) * d + r] : 0.0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) x[j] -= a[u][j];
+      }
+      for (; cc < ncc; ++cc)
 #pragma unroll
         for (int j = 0; j < NB; ++j)
           if (j < nb) x[j] -= apart[((int64_t)cc * NB + j) * d + r];
@@ -194,7 +244,7 @@ __global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, i
   }
 }
 
-// One wave.  G = sum of the slab Gram matrices (fixed order), symmetrised,
+// One block.  G = sum of the slab Gram matrices (fixed order), symmetrised,
 // plus sigma I with sigma = shift_rel * trace(G) when shift_rel > 0.
 // Cholesky G = L L^T in LDS; R = L^T (nb x nb, col-major) to Rout; Bacc = R
 // (round 0) or R Bacc.  A non-positive pivot is replaced by 1 and bit 1 of
@@ -203,27 +253,38 @@ __global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, i
 // times the largest entry of Arec or Bacc, bit 2 of flag[0] is set (the
 // block Krylov space has become, to working accuracy, invariant).  flag[1]
 // keeps the first `tag` (the step number) at which a bit was set.
-__global__ __launch_bounds__(64) void k_lz_chol(const double* __restrict__ gpart, int nblk, int nb,
-                                                int NB, double shift_rel,
-                                                double* __restrict__ Rout,
-                                                double* __restrict__ Bacc, int round,
-                                                const double* __restrict__ Arec,
-                                                double* __restrict__ Brec, int* __restrict__ flag,
-                                                int tag) {
+__global__ __launch_bounds__(256) void k_lz_chol(const double* __restrict__ gpart, int nblk, int nb,
+                                                 int NB, double shift_rel,
+                                                 double* __restrict__ Rout,
+                                                 double* __restrict__ Bacc, int round,
+                                                 const double* __restrict__ Arec,
+                                                 double* __restrict__ Brec, int* __restrict__ flag,
+                                                 int tag) {
   __shared__ double G[32][33];
+  __shared__ double Bo[32][33];
   __shared__ double Bt[32][33];
-  __shared__ double sig;
+  __shared__ double red[2];
   __shared__ int bad;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < nb * nb; e += 64) {
+  const int t = threadIdx.x;
+  // Sum of the slab partials: thread t takes entries t, t + 256, ...; the
+  // loads of one entry are independent and issued together.
+  for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += gpart[(int64_t)b * NB * NB + i + j * NB];
-    G[i][j] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = 0;
+    for (; b + 4 <= nblk; b += 4) {
+      s0 += gpart[(int64_t)(b + 0) * NB * NB + i + j * NB];
+      s1 += gpart[(int64_t)(b + 1) * NB * NB + i + j * NB];
+      s2 += gpart[(int64_t)(b + 2) * NB * NB + i + j * NB];
+      s3 += gpart[(int64_t)(b + 3) * NB * NB + i + j * NB];
+    }
+    for (; b < nblk; ++b) s0 += gpart[(int64_t)b * NB * NB + i + j * NB];
+    G[i][j] = (s0 + s1) + (s2 + s3);
+    if (round > 0) Bo[i][j] = Bacc[i + j * nb];
   }
-  if (lane == 0) bad = 0;
+  if (t == 0) bad = 0;
   __syncthreads();
-  for (int e = lane; e < nb * nb; e += 64) {
+  for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
     if (i < j) {
       const double v = 0.5 * (G[i][j] + G[j][i]);
@@ -232,17 +293,17 @@ __global__ __launch_bounds__(64) void k_lz_chol(const double* __restrict__ gpart
     }
   }
   __syncthreads();
-  if (lane == 0) {
+  if (t == 0) {
     double tr = 0.0;
     for (int i = 0; i < nb; ++i) tr += G[i][i];
-    sig = shift_rel > 0.0 ? shift_rel * tr : 0.0;
+    red[0] = shift_rel > 0.0 ? shift_rel * tr : 0.0;
   }
   __syncthreads();
-  if (lane < nb) G[lane][lane] += sig;
+  if (t < nb) G[t][t] += red[0];
   __syncthreads();
-  // Right-looking Cholesky, lower triangle.
+  // Right-looking Cholesky, lower triangle; thread t < nb owns row t.
   for (int p = 0; p < nb; ++p) {
-    if (lane == 0) {
+    if (t == 0) {
       double piv = G[p][p];
       if (!(piv > 0.0) || !isfinite(piv)) {
         piv = 1.0;
@@ -251,48 +312,53 @@ __global__ __launch_bounds__(64) void k_lz_chol(const double* __restrict__ gpart
       G[p][p] = sqrt(piv);
     }
     __syncthreads();
-    if (lane > p && lane < nb) G[lane][p] /= G[p][p];
-    __syncthreads();
-    if (lane > p && lane < nb)
-      for (int j = p + 1; j <= lane; ++j) G[lane][j] -= G[lane][p] * G[j][p];
-    __syncthreads();
-  }
-  // R = L^T (upper); R B into Bt.
-  if (lane < nb) {
-    for (int i = 0; i < nb; ++i) {
-      const double rij = (i <= lane) ? G[lane][i] : 0.0;  // R[i][lane] = L[lane][i]
-      Rout[i + lane * nb] = rij;
+    if (t > p && t < nb) {
+      const double l = G[t][p] / G[p][p];
+      G[t][p] = l;
+      for (int j = p + 1; j <= t; ++j) G[t][j] -= l * G[j][p];
     }
+    __syncthreads();
   }
-  __syncthreads();
-  if (lane < nb) {
+  // R = L^T (upper); Bt = R (round 0) or R Bo.
+  if (t < nb) {
     for (int i = 0; i < nb; ++i) {
+      const double rij = (i <= t) ? G[t][i] : 0.0;  // R[i][t] = L[t][i]
+      Rout[i + t * nb] = rij;
       double s;
       if (round == 0) {
-        s = (i <= lane) ? G[lane][i] : 0.0;
+        s = rij;
       } else {
         s = 0.0;
-        for (int m = i; m <= lane; ++m) s += G[m][i] * Bacc[m + lane * nb];  // R[i][m] B[m][lane]
+        for (int m = i; m <= t; ++m) s += G[m][i] * Bo[m][t];  // R[i][m] B[m][t]
       }
-      Bt[i][lane] = s;
+      Bt[i][t] = s;
     }
   }
   __syncthreads();
-  if (lane < nb)
-    for (int i = 0; i < nb; ++i) Bacc[i + lane * nb] = Bt[i][lane];
-  if (lane == 0 && bad) {
+  for (int e = t; e < nb * nb; e += 256) {
+    const int i = e % nb, j = e / nb;
+    Bacc[i + j * nb] = Bt[i][j];
+    if (Brec) Brec[i + j * nb] = Bt[i][j];
+  }
+  if (t == 0 && bad) {
     flag[0] |= 1;
     if (flag[1] == 0) flag[1] = tag;
   }
   if (!Brec) return;
-  if (lane < nb)
-    for (int i = 0; i < nb; ++i) Brec[i + lane * nb] = Bt[i][lane];
-  if (lane == 0) {
-    double big = 0.0, small = INFINITY;
-    for (int i = 0; i < nb; ++i) {
-      small = fmin(small, fabs(Bt[i][i]));
-      for (int j = 0; j < nb; ++j) big = fmax(big, fmax(fabs(Bt[i][j]), fabs(Arec[i + j * nb])));
-    }
+  // Near-invariance test: smallest |B_ii| against the largest entry of A_j, B_j.
+  double big = 0.0;
+  for (int e = t; e < nb * nb; e += 256) {
+    const int i = e % nb, j = e / nb;
+    big = fmax(big, fmax(fabs(Bt[i][j]), fabs(Arec[i + j * nb])));
+  }
+  big = wave_max(big);
+  __syncthreads();
+  if ((t & 63) == 0) G[0][1 + (t >> 6)] = big;
+  __syncthreads();
+  if (t == 0) {
+    big = fmax(fmax(G[0][1], G[0][2]), fmax(G[0][3], G[0][4]));
+    double small = INFINITY;
+    for (int i = 0; i < nb; ++i) small = fmin(small, fabs(Bt[i][i]));
     if (!(small > 1e-10 * big)) {
       flag[0] |= 2;
       if (flag[1] == 0) flag[1] = tag;
@@ -302,13 +368,12 @@ __global__ __launch_bounds__(64) void k_lz_chol(const double* __restrict__ gpart
 
 // ---------------------------------------------------------------- launchers
 #define LZ_DISPATCH(NBV, CALL) \
-  if (NBV <= 4) { constexpr int NB = 4; CALL; }       \
-  else if (NBV <= 8) { constexpr int NB = 8; CALL; }  \
+  if (NBV <= 8) { constexpr int NB = 8; CALL; }       \
   else if (NBV <= 16) { constexpr int NB = 16; CALL; } \
   else if (NBV <= 32) { constexpr int NB = 32; CALL; } \
   else return hipErrorInvalidValue;
 
-int lz_nb_pad(int nb) { return nb <= 4 ? 4 : nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
+int lz_nb_pad(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 
 size_t lz_proj_part_doubles(int d, int nmax, int nb) {
   return (size_t)lz_nblocks(d, LZ_RC) * nmax * lz_nb_pad(nb);
@@ -327,11 +392,11 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
   const int nrc = lz_nblocks(d, LZ_RC);
   const int ncc = lz_nblocks(n, LZ_CC);
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_proj_partial<NB>), dim3(lz_nblocks(n, 256 / NB), nrc), dim3(64), 0,
-                       st, V, ldv, n, W, ldw, nb, d, ppart);
+    hipLaunchKernelGGL((k_lz_proj_partial<NB>), dim3(lz_nblocks(n, 64), nrc), dim3(256), 0, st, V,
+                       ldv, n, W, ldw, nb, d, ppart);
     hipLaunchKernelGGL(k_lz_proj_finish, dim3(lz_nblocks((int64_t)n * nb, 256)), dim3(256), 0, st,
                        ppart, nrc, n, nb, NB, C, Arec, b, accumulate);
-    hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 256), ncc), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 128), ncc), dim3(128), 0, st,
                        V, ldv, n, C, nb, d, apart);
     hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, W, ldw, nb, d,
                        apart, ncc, nullptr, W, ldw, gpart);
@@ -352,7 +417,7 @@ hipError_t lz_chol(const double* gpart, int d, int nb, double shift_rel, double*
                    int round, const double* Arec, double* Brec, int* flag, int tag,
                    hipStream_t st) {
   if (nb > 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lz_chol, dim3(1), dim3(64), 0, st, gpart, lz_nblocks(d, 256), nb,
+  hipLaunchKernelGGL(k_lz_chol, dim3(1), dim3(256), 0, st, gpart, lz_nblocks(d, 256), nb,
                      lz_nb_pad(nb), shift_rel, R, Bacc, round, Arec, Brec, flag, tag);
   return hipGetLastError();
 }

@@ -49,6 +49,9 @@ struct refl_handle_s {
   size_t ws_own_bytes = 0;
   double* pinned = nullptr;  // host pinned scalars (SC_COUNT doubles + CG state)
   std::vector<hipEvent_t> ev;  // params.timing: start/stop pairs of the bulk products
+  double* lz_pin = nullptr;    // host pinned copies of the Lanczos blocks and flags
+  size_t lz_pin_bytes = 0;
+  hipEvent_t lz_ev[2] = {nullptr, nullptr};
   int ncu = 256;               // compute units of the device
   char err[512] = {0};
 };
@@ -435,7 +438,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
 // Shift estimation (section 4.3: a partial eigensolver near the target gap,
 // then the midpoint of Prop. 4.1 and the margin test of Prop. 4.2).  Block
 // width b = min(k + 4, 32, d); at most floor(d / b) steps; the convergence
-// test runs after step ceil((k + 1) / b) and then every ceil(32 / b) steps,
+// test runs after step ceil((k + 1) / b) and then every ceil(64 / b) steps,
 // and always at the last step.
 
 
@@ -520,13 +523,21 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
     }
     return tridiag_count_below(n, diag.data(), sub.data(), x);
   };
-  auto bracket = [&](int m) {
-    double lo = glo - 1e-12 * scale, hi = ghi + 1e-12 * scale;
-    while (hi - lo > 1e-9 * scale) {
-      const double mid = 0.5 * (lo + hi);
-      if (count(mid) > m) hi = mid; else lo = mid;
+  // Bisection to `width`, then (in pair) inverse iteration from the
+  // midpoint; if the Rayleigh quotient leaves the bracket (a neighbour was
+  // closer to the midpoint) the bracket is narrowed further and the
+  // iteration repeated.
+  struct Bracket {
+    double lo, hi;
+  };
+  auto bracket = [&](int m, double width, Bracket* b0) {
+    Bracket b = b0 ? *b0 : Bracket{glo - 1e-12 * scale, ghi + 1e-12 * scale};
+    while (b.hi - b.lo > width) {
+      const double mid = 0.5 * (b.lo + b.hi);
+      if (mid <= b.lo || mid >= b.hi) break;
+      if (count(mid) > m) b.hi = mid; else b.lo = mid;
     }
-    return 0.5 * (lo + hi);
+    return b;
   };
   // Residual radius of the Ritz pair near sigma: inverse iteration gives the
   // vector y of T, theta its Rayleigh quotient, and
@@ -556,12 +567,23 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
     }
     res = std::sqrt(r1 + r2);
   };
-  pair(bracket(k - 1), out.th_k, out.res_k);
-  pair(bracket(k), out.th_k1, out.res_k1);
+  auto ritz = [&](int m, double& theta, double& res) {
+    double width = 1e-6 * scale;
+    Bracket b = bracket(m, width, nullptr);
+    while (true) {
+      pair(0.5 * (b.lo + b.hi), theta, res);
+      const double slack = b.hi - b.lo;
+      if ((theta >= b.lo - slack && theta <= b.hi + slack) || width < 1e-14 * scale) return;
+      width *= 1e-3;
+      b = bracket(m, width, &b);
+    }
+  };
+  ritz(k - 1, out.th_k, out.res_k);
+  ritz(k, out.th_k1, out.res_k1);
   if (extremes) {
     double unused;
-    pair(bracket(0), out.th_min, unused);
-    pair(bracket(n - 1), out.th_max, unused);
+    ritz(0, out.th_min, unused);
+    ritz(n - 1, out.th_max, unused);
   }
 }
 
@@ -589,19 +611,77 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   refl_status_t rs = cholqr3(z.V, nullptr, nullptr, 0);
   if (rs != REFL_OK) return rs;
   const int j0 = std::max(1, (k + 1 + b - 1) / b);
-  const int ci = std::max(1, (32 + b - 1) / b);
-  std::vector<double> TA, TB;
-  int hflag[2] = {0, 0};
+  const int ci = std::max(1, (64 + b - 1) / b);
+  // Pinned host copies: TA blocks, TB blocks, then two flag slots.
+  const size_t blk = (size_t)b * b;
+  const size_t pin_need = sizeof(double) * 2 * J * blk + 4 * sizeof(int) + 64;
+  if (h->lz_pin_bytes < pin_need) {
+    if (h->lz_pin) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipHostFree(h->lz_pin));
+      h->lz_pin = nullptr;
+      h->lz_pin_bytes = 0;
+    }
+    if (hipHostMalloc((void**)&h->lz_pin, pin_need, hipHostMallocDefault) != hipSuccess)
+      return fail(h, REFL_ERR_NO_MEMORY, "pinned host buffer of %zu bytes", pin_need);
+    h->lz_pin_bytes = pin_need;
+  }
+  for (int e = 0; e < 2; ++e)
+    if (!h->lz_ev[e]) HIPCHK(hipEventCreateWithFlags(&h->lz_ev[e], hipEventDisableTiming));
+  double* hTA = h->lz_pin;
+  double* hTB = h->lz_pin + J * blk;
+  int* hflag = reinterpret_cast<int*>(h->lz_pin + 2 * J * blk);
+  // Evaluates the test made after step j (its copies in slot `slot`); sets
+  // done when the run is finished (r filled).
+  auto evaluate = [&](int j, int slot, int& done) -> refl_status_t {
+    done = 0;
+    HIPCHK(hipEventSynchronize(h->lz_ev[slot]));
+    const int* fl = hflag + 2 * slot;
+    // A QR that lost rank at step jb: with only a near-invariant space (bit
+    // 2) B_jb is still valid, so T_jb and its residual are used; after a
+    // failed Cholesky (bit 1) the last valid state is step jb - 1.
+    int jj = j;
+    bool stop = (j == J);
+    if (fl[1] > 0 && fl[1] <= j) {
+      jj = (fl[0] & 1) ? fl[1] - 1 : fl[1];
+      stop = true;
+      if (jj < 1) return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: start block lost rank");
+    }
+    if (jj * b < k + 1) {
+      if (stop) return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: basis too small for k=%d", k);
+      return REFL_OK;
+    }
+    RitzCheck rc;
+    ritz_check(jj, b, k, hTA, hTB, false, rc);
+    const double eps = std::max(rc.res_k, rc.res_k1);
+    const bool conv = eps < 0.25 * (rc.th_k1 - rc.th_k);
+    if (conv || stop) {
+      ritz_check(jj, b, k, hTA, hTB, true, rc);
+      r.lam_k = rc.th_k;
+      r.lam_k1 = rc.th_k1;
+      r.eps = eps;
+      r.s = 0.5 * (rc.th_k + rc.th_k1);
+      r.rho = std::max(rc.th_max - r.s, r.s - rc.th_min);
+      r.steps = jj;
+      r.converged = conv;
+      done = 1;
+    }
+    return REFL_OK;
+  };
+  // The test after step j is evaluated on the host while the device runs
+  // the steps up to the next test (steps enqueued past convergence are
+  // discarded).
+  int pending = -1, pending_slot = 0, ntest = 0, copied = 0;
   for (int j = 1; j <= J; ++j) {
     const int n = j * b;
     const double* Qj = z.V + (int64_t)(n - b) * ld;
-    double* Aj = z.TA + (size_t)(j - 1) * b * b;
-    double* Bj = z.TB + (size_t)(j - 1) * b * b;
+    double* Aj = z.TA + (size_t)(j - 1) * blk;
+    double* Bj = z.TB + (size_t)(j - 1) * blk;
     HIPCHK(symthin_f64(Hf, ld, (int)d, Qj, ld, b, z.W, ld, thin, st));
     HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, z.apart, nullptr, st));
     HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.apart, z.gpart, st));
     if ((int64_t)n >= d) {
-      HIPCHK(hipMemsetAsync(Bj, 0, sizeof(double) * b * b, st));  // the basis spans R^d
+      HIPCHK(hipMemsetAsync(Bj, 0, sizeof(double) * blk, st));  // the basis spans R^d
     } else {
       // The Gram partials of W are already in gpart: rounds of CholQR3.
       for (int round = 0; round < 3; ++round) {
@@ -611,43 +691,33 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
                        round == 2 ? nullptr : z.gpart, st));
       }
     }
-    const bool check = (j >= j0 && (j - j0) % ci == 0) || j == J;
-    if (!check) continue;
-    TA.resize((size_t)j * b * b);
-    TB.resize((size_t)j * b * b);
-    HIPCHK(hipMemcpyAsync(TA.data(), z.TA, sizeof(double) * TA.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(TB.data(), z.TB, sizeof(double) * TB.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(hflag, z.flag, sizeof(hflag), hipMemcpyDeviceToHost, st));
+    const bool test = (j >= j0 && (j - j0) % ci == 0) || j == J;
+    if (!test) continue;
+    const int slot = ntest++ & 1;
+    const size_t nb_new = (size_t)(j - copied) * blk;
+    HIPCHK(hipMemcpyAsync(hTA + copied * blk, z.TA + copied * blk, sizeof(double) * nb_new,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hTB + copied * blk, z.TB + copied * blk, sizeof(double) * nb_new,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hflag + 2 * slot, z.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(h->lz_ev[slot], st));
+    copied = j;
+    if (pending > 0) {
+      int done = 0;
+      refl_status_t e = evaluate(pending, pending_slot, done);
+      if (e != REFL_OK || done) {
+        HIPCHK(hipStreamSynchronize(st));
+        return e;
+      }
+    }
+    pending = j;
+    pending_slot = slot;
+  }
+  if (pending > 0) {
+    int done = 0;
+    refl_status_t e = evaluate(pending, pending_slot, done);
     HIPCHK(hipStreamSynchronize(st));
-    // A QR that lost rank at step jb: with only a near-invariant space (bit 2)
-    // B_jb is still valid, so T_jb and its residual are used; after a failed
-    // Cholesky (bit 1) the last valid state is step jb - 1.
-    int jj = j;
-    bool stop = (j == J);
-    if (hflag[1] > 0 && hflag[1] <= j) {
-      jj = (hflag[0] & 1) ? hflag[1] - 1 : hflag[1];
-      stop = true;
-      if (jj < 1) return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: start block lost rank");
-    }
-    if (jj * b < k + 1) {
-      if (stop) return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: basis too small for k=%d", k);
-      continue;
-    }
-    RitzCheck rc;
-    ritz_check(jj, b, k, TA.data(), TB.data(), false, rc);
-    const double eps = std::max(rc.res_k, rc.res_k1);
-    const bool conv = eps < 0.25 * (rc.th_k1 - rc.th_k);
-    if (conv || stop) {
-      ritz_check(jj, b, k, TA.data(), TB.data(), true, rc);
-      r.lam_k = rc.th_k;
-      r.lam_k1 = rc.th_k1;
-      r.eps = eps;
-      r.s = 0.5 * (rc.th_k + rc.th_k1);
-      r.rho = std::max(rc.th_max - r.s, r.s - rc.th_min);
-      r.steps = jj;
-      r.converged = conv;
-      return REFL_OK;
-    }
+    if (e != REFL_OK || done) return e;
   }
   return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: no test at the step cap");
 }
@@ -986,6 +1056,9 @@ refl_status_t refl_destroy(refl_handle_t h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->ws_own) (void)hipFree(h->ws_own);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->lz_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->lz_pin) (void)hipHostFree(h->lz_pin);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return REFL_OK;

@@ -341,5 +341,5 @@ def test_lanczos_check_schedule():
     assert oracle.lanczos_block_size(4096, 40) == 32
     assert oracle.lanczos_block_size(6, 4) == 6
     c = oracle.lanczos_check_steps(4096, 5, 9)
-    assert c[0] == 1 and c[1] == 5 and c[-1] == 4096 // 9
+    assert c[0] == 1 and c[1] == 9 and c[-1] == 4096 // 9
     assert oracle.lanczos_check_steps(100, 3, 7, max_steps=6) == [1, 6]

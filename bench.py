@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--words", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--lanczos-steps", type=int, default=3, help="timed solves with the shift estimated")
+    ap.add_argument("--cg-tol", type=float, default=None, help="inner solve tolerance (library default if unset)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
@@ -79,6 +80,8 @@ def main():
     R = torch.empty((d, d), dtype=torch.float64, device=dev)
     h = refl.Handle(dev)
     mixed_kw = dict(precision="mixed", words=args.words, tol=target, timing=True)
+    if args.cg_tol is not None:
+        mixed_kw["cg_tol"] = args.cg_tol
     fp64_kw = dict(precision="fp64", tol=target, timing=True)
     h.reserve(d, refl.make_params(k, s, **mixed_kw))
 

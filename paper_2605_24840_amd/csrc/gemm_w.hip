@@ -26,6 +26,8 @@
 // distinct bank groups whether the LDS serves 8 or 16 lanes per cycle.
 #include <cstdlib>
 
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -312,6 +314,21 @@ struct DCfg {
 #define REFL_WAIT_VMCNT(n) \
   __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
 
+// Scheduling hints for the two-register-set schedule: N LDS fragment reads
+// and NG global-to-LDS loads spread evenly through NMF MFMAs (groups of
+// MFMA, then one DS read, then at most one global load).
+template <int I, int N, int NMF, int NG>
+__device__ __forceinline__ void interleave_hints() {
+  if constexpr (I < N) {
+    constexpr int m = (NMF * (I + 1)) / N - (NMF * I) / N;
+    constexpr int g = (NG * (I + 1)) / N - (NG * I) / N;
+    if constexpr (m > 0) __builtin_amdgcn_sched_group_barrier(0x008, m, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    if constexpr (g > 0) __builtin_amdgcn_sched_group_barrier(0x020, g, 0);
+    interleave_hints<I + 1, N, NMF, NG>();
+  }
+}
+
 // One wave per SIMD (the ring fills the LDS); telling the compiler so lets it
 // keep a whole K-slice of fragments in registers instead of re-reading LDS.
 template <int W, int MODE, int TS, int PIPE>
@@ -459,6 +476,120 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         mfma_half(1);
       }
     }
+  } else if constexpr (PIPE == 2) {
+    // Two fragment register sets.  Step kt: wait for slice kt + 1 (own
+    // loads, then the barrier for everyone's); the stage of slice kt, whose
+    // fragments every wave already holds in registers, is then free and
+    // takes the loads of slice kt + 3; then the fragment reads of slice
+    // kt + 1 into the other set run interleaved with the MFMAs of slice kt.
+    // The LDS reads of the next slice overlap the matrix work of this one,
+    // and two slices beyond the one being read stay in flight.  Slice j sits
+    // in stage j % 3 and in register set j % 2: six steps form one static
+    // pattern.
+    struct Frag {
+      bf16x8_t a[KH][W][NB], b[KH][W][NB];
+    };
+    Frag F0, F1;
+    auto fset = [&](auto ci) -> Frag& {
+      if constexpr (decltype(ci)::value == 0) return F0;
+      else return F1;
+    };
+    auto read_frag = [&](Frag& f, const unsigned char* sb) {
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk) {
+        const unsigned char* p = sb + frag_lane[kk];
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            f.a[kk][w][a] = *reinterpret_cast<const bf16x8_t*>(
+                p + (w * TS + wr * (TS / 2) + a * 32) * C::ROWB);
+            f.b[kk][w][a] = *reinterpret_cast<const bf16x8_t*>(
+                p + ((W + w) * TS + wc * (TS / 2) + a * 32) * C::ROWB);
+          }
+      }
+    };
+    auto mfma_frag = [&](const Frag& f) {
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+        for (int p = C::NPROD - 1; p >= 0; --p)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  f.a[kk][prod_a(W, p)][a], f.b[kk][prod_b(W, p)][b], acc[a][b], 0, 0, 0);
+    };
+    auto ring_at = [&](auto si) -> unsigned char* {
+      constexpr int S = decltype(si)::value % 3;
+      if constexpr (S == 0) return ring0;
+      else if constexpr (S == 1) return ring1;
+      else return ring2;
+    };
+    constexpr int NDSR = 2 * KH * W * NB;
+    constexpr int NMF = KH * C::NPROD * NB * NB;
+    auto stepP = [&](auto ci, auto si, int kt, bool dma, bool more) {
+      constexpr int CI = decltype(ci)::value;
+      constexpr int SI = decltype(si)::value;
+      if (more) {
+        // Slices kt + 1 and kt + 2 were issued; kt + 2 may stay in flight.
+        if (kt + 2 < nk) {
+          REFL_WAIT_VMCNT(C::NLW);
+        } else {
+          REFL_WAIT_VMCNT(0);
+        }
+        REFL_LDS_BARRIER();
+        __builtin_amdgcn_sched_barrier(0);
+        if (dma) issue(kt + 3, ring_at(std::integral_constant<int, SI>()));
+        read_frag(fset(std::integral_constant<int, CI ^ 1>()), ring_at(std::integral_constant<int, SI + 1>()));
+        mfma_frag(fset(std::integral_constant<int, CI>()));
+        interleave_hints<0, NDSR, NMF, C::NLW>();
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        mfma_frag(fset(std::integral_constant<int, CI>()));
+      }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    // Prologue: slices 0, 1, 2 (slice 1 and 2 may be beyond K: the matrices
+    // are at least one tile wide, so the reads stay in bounds).
+    issue(0, ring0);
+    issue(1, ring1);
+    issue(2, ring2);
+    REFL_WAIT_VMCNT(2 * C::NLW);
+    REFL_LDS_BARRIER();
+    read_frag(F0, ring0);
+    int kt = 0;
+    for (; kt + 9 <= nk; kt += 6) {
+      stepP(I0(), I0(), kt, true, true);
+      stepP(I1(), I1(), kt + 1, true, true);
+      stepP(I0(), I2(), kt + 2, true, true);
+      stepP(I1(), I0(), kt + 3, true, true);
+      stepP(I0(), I1(), kt + 4, true, true);
+      stepP(I1(), I2(), kt + 5, true, true);
+    }
+    // Tail (at most 8 slices, entered at phase 0 with slice kt in F0 and
+    // slices kt + 1, kt + 2 in flight): one register set, reads after the
+    // MFMAs.
+    for (; kt < nk; ++kt) {
+      auto stage = [&](int j) -> unsigned char* {
+        const int m = j % 3;
+        return m == 0 ? ring0 : (m == 1 ? ring1 : ring2);
+      };
+      mfma_frag(F0);
+      if (kt + 1 < nk) {
+        if (kt + 2 < nk) {
+          REFL_WAIT_VMCNT(C::NLW);
+        } else {
+          REFL_WAIT_VMCNT(0);
+        }
+        REFL_LDS_BARRIER();
+        if (kt + 3 < nk) issue(kt + 3, stage(kt));
+        read_frag(F0, stage(kt + 1));
+      }
+    }
   } else {
     // Barrier at the start of each slice, then all of its fragment reads,
     // the loads of slice kt + 2, and the MFMAs.
@@ -597,7 +728,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 static int gemm_pipe() {
   static const int v = [] {
     const char* e = std::getenv("REFL_GEMM_PIPE");
-    return (e && e[0] == '1') ? 1 : 0;
+    return (e && (e[0] == '0' || e[0] == '1' || e[0] == '2')) ? e[0] - '0' : 2;
   }();
   return v;
 }
@@ -616,22 +747,20 @@ static hipError_t launch_w(int mode, const uint16_t* A, const uint16_t* B, const
                            int ntiles, double* partials, hipStream_t st) {
   if constexpr (W >= 2) {
     if (!use_register_staging()) {
-      const bool p1 = gemm_pipe() == 1;
+      const int pipe = gemm_pipe();
+#define REFL_WD(MODEV, PIPEV)                                                                \
+  hipLaunchKernelGGL((k_sym_gemm_wd<W, MODEV, TS, PIPEV>), dim3(ntiles), dim3(256), 0, st, A, B, \
+                     Xold, out, ld, ps, d, dk, tiles, partials)
       if (mode == GEMM_RESIDUAL) {
-        if (p1)
-          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_RESIDUAL, TS, 1>), dim3(ntiles), dim3(256), 0,
-                             st, A, B, Xold, out, ld, ps, d, dk, tiles, partials);
-        else
-          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_RESIDUAL, TS, 0>), dim3(ntiles), dim3(256), 0,
-                             st, A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+        if (pipe == 2) REFL_WD(GEMM_RESIDUAL, 2);
+        else if (pipe == 1) REFL_WD(GEMM_RESIDUAL, 1);
+        else REFL_WD(GEMM_RESIDUAL, 0);
       } else {
-        if (p1)
-          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_UPDATE, TS, 1>), dim3(ntiles), dim3(256), 0, st,
-                             A, B, Xold, out, ld, ps, d, dk, tiles, partials);
-        else
-          hipLaunchKernelGGL((k_sym_gemm_wd<W, GEMM_UPDATE, TS, 0>), dim3(ntiles), dim3(256), 0, st,
-                             A, B, Xold, out, ld, ps, d, dk, tiles, partials);
+        if (pipe == 2) REFL_WD(GEMM_UPDATE, 2);
+        else if (pipe == 1) REFL_WD(GEMM_UPDATE, 1);
+        else REFL_WD(GEMM_UPDATE, 0);
       }
+#undef REFL_WD
       return hipGetLastError();
     }
   }

@@ -49,6 +49,7 @@ struct refl_handle_s {
   size_t ws_own_bytes = 0;
   double* pinned = nullptr;  // host pinned scalars (SC_COUNT doubles + CG state)
   std::vector<hipEvent_t> ev;  // params.timing: start/stop pairs of the bulk products
+  std::vector<hipEvent_t> bulk_ev;  // completion of the pipelined bulk steps
   double* lz_pin = nullptr;    // host pinned copies of the Lanczos blocks and flags
   size_t lz_pin_bytes = 0;
   hipEvent_t lz_ev[2] = {nullptr, nullptr};
@@ -122,7 +123,7 @@ struct Work {
   // bulk (only the ones of the precision are non-null)
   double *X64[2], *N64;
   float *X32[2], *N32;
-  uint16_t *Xw[2], *Nw;
+  uint16_t *Xw[3], *Nw;
   // block vectors (ld = dp), polish and apply
   double *V, *W, *Z, *Rr, *P[2], *AP, *T1, *T2, *G, *thin, *gwork, *cgpart;
   void* cgstate;
@@ -178,7 +179,7 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind
   w.rowsum = c.take<double>(2 * dp);
   w.X64[0] = w.X64[1] = w.N64 = nullptr;
   w.X32[0] = w.X32[1] = w.N32 = nullptr;
-  w.Xw[0] = w.Xw[1] = w.Nw = nullptr;
+  w.Xw[0] = w.Xw[1] = w.Xw[2] = w.Nw = nullptr;
   w.lz = LzWork();
   if (kind == LAYOUT_ESTIMATE) {
     w.Hf = c.take<double>(n2);
@@ -200,6 +201,7 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind
       const int W = p.words;
       w.Xw[0] = c.take<uint16_t>(W * n2);
       w.Xw[1] = c.take<uint16_t>(W * n2);
+      w.Xw[2] = c.take<uint16_t>(W * n2);
       w.Nw = c.take<uint16_t>(W * n2);
     }
   } else {
@@ -817,7 +819,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   const int cap = fixed ? p.fixed_steps : p.max_iter;
   // Optional event pairs around each bulk product (2 per step).
   size_t nev = 0;
-  const size_t max_ev = 2 * (size_t)(cap + 1);
+  const size_t max_ev = 2 * (size_t)(cap + 2);
   if (p.timing) {
     while (h->ev.size() < 2 * max_ev) {
       hipEvent_t e;
@@ -838,6 +840,88 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   int bulk_extra = 0;
   if (const char* e = std::getenv("REFL_BULK_EXTRA")) bulk_extra = std::max(0, std::atoi(e));
   refl_status_t bulk_status = REFL_OK;
+  if (p.precision == REFL_PREC_MIXED && !fixed) {
+    // MIXED bulk, one step ahead: step m + 1 is enqueued before the host
+    // reads ||X_m^2 - I||_F and trace X_m, so the device never waits for the
+    // host.  X_m lives in buffer m % 3 (the two steps in flight past m write
+    // the other two).  Per-step results go to a ring of scalar slots.
+    constexpr int RING = 16;
+    // Step m fills the slot pair m: ||X_m^2 - I||_F^2 and trace X_{m+1}.
+    auto slot_r = [](int m) { return SC_SCRATCH + 2 * (m % RING); };
+    auto slot_t = [](int m) { return SC_SCRATCH + 2 * (m % RING) + 1; };
+    std::vector<hipEvent_t>& lev = h->bulk_ev;
+    while ((int)lev.size() < RING) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      lev.push_back(e);
+    }
+    auto enqueue_step = [&](int m) -> refl_status_t {
+      uint16_t* Xm = w.Xw[m % 3];
+      uint16_t* Xn = w.Xw[(m + 1) % 3];
+      HIPCHK(ev_start());
+      HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, Xm, Xm, nullptr, w.Nw, w.dp, w.ps,
+                                   (int)d, w.dk, w.tiles, w.ntiles, w.partials, st));
+      HIPCHK(ev_stop());
+      HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, slot_r(m), st));
+      HIPCHK(ev_start());
+      HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, Xm, w.Nw, Xm, Xn, w.dp, w.ps, (int)d,
+                                   w.dk, w.tiles, w.ntiles, w.partials, st));
+      HIPCHK(ev_stop());
+      HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, slot_t(m), st));
+      HIPCHK(hipMemcpyAsync(hsc + slot_r(m), w.scal + slot_r(m), 2 * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipEventRecord(lev[m % RING], st));
+      return REFL_OK;
+    };
+    refl_status_t es = enqueue_step(0);
+    if (es != REFL_OK) return es;
+    int enq = 0;  // last step enqueued
+    const double sqd = std::sqrt((double)d);
+    for (int m = 0;; ++m) {
+      // Enqueue step m + 1 ahead unless X_m may pass the index certificate
+      // (sqrt(d) ||X_m^2 - I||_F < 1): near convergence ||X_m^2 - I||_F is
+      // about 0.75 ||X_{m-1}^2 - I||_F^2, and within a factor 4 of passing
+      // the step is not issued speculatively.
+      const bool likely_last = !hist.empty() && sqd * 0.75 * hist.back() * hist.back() < 4.0;
+      if (enq < m + 1 && m + 1 <= cap && !likely_last) {
+        es = enqueue_step(m + 1);
+        if (es != REFL_OK) return es;
+        enq = m + 1;
+      }
+      HIPCHK(hipEventSynchronize(lev[m % RING]));
+      const double resid = std::sqrt(std::fmax(hsc[slot_r(m)], 0.0));
+      b.resid = resid;
+      b.trace = trace_cur;
+      b.steps = m;
+      b.cur = m % 3;
+      hist.push_back(resid);
+      if (!std::isfinite(resid)) {
+        bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", m);
+        break;
+      }
+      // Hand over to the FP64 correction as soon as the index certificate
+      // holds (the correction restores full accuracy), or after
+      // REFL_BULK_EXTRA further steps (tuning), or when the residual stops
+      // decreasing quadratically (the BF16-word floor).
+      const int j = index_certificate(d, resid, trace_cur);
+      const size_t n = hist.size();
+      if (j >= 0) {
+        ++cert_steps;
+        const bool floor = n >= 2 && resid > 0.25 * hist[n - 2];
+        if (floor || cert_steps > bulk_extra) {
+          b.converged = true;
+          break;
+        }
+      }
+      if (m >= cap) break;
+      trace_cur = hsc[slot_t(m)];
+      if (enq < m + 1) {
+        es = enqueue_step(m + 1);
+        if (es != REFL_OK) return es;
+        enq = m + 1;
+      }
+    }
+  } else
   while (true) {
     const int c = b.cur;
     HIPCHK(ev_start());
@@ -1056,6 +1140,7 @@ refl_status_t refl_destroy(refl_handle_t h) {
   (void)hipStreamSynchronize(h->stream);
   if (h->ws_own) (void)hipFree(h->ws_own);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->bulk_ev) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->lz_ev)
     if (e) (void)hipEventDestroy(e);
   if (h->lz_pin) (void)hipHostFree(h->lz_pin);

@@ -40,6 +40,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the bulk products from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes scaled by the copy-kernel
+    calibration), or None when the product source changed since the counters
+    were taken (the summary records the hash of the source it measured)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_words_pmc_allen_cahn_d4096.md")
+    src = [os.path.join(ROOT, "paper_2605_24840_amd", "csrc", f) for f in ("gemm_w.hip", "common.h")]
+    try:
+        fields = {}
+        for line in open(path):
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+                k, v = line.split(":", 1)
+                fields[k] = v.strip()
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()
+    except OSError:
+        return None
+    if fields.get("source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,9 +237,11 @@ def main():
                                 "lanczos_steps": il["lanczos_steps"], "ms_setup": il["ms_setup"],
                                 "s": il["s"], "eps": il["eps"], "margin": il["margin"], "err_fro": err_lz},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "traffic": None,
-                     "kernel": f"k_sym_gemm_w<{args.words}>", "launches": gemm_n,
-                     "avg_launch_ms": 1e3 * avg_launch_s, "flop_per_launch": flop_launch},
+                     "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, calibrated)",
+                     "kernel": f"k_sym_gemm_wd<{args.words}, GEMM_RESIDUAL|GEMM_UPDATE, tile>",
+                     "launches": gemm_n, "avg_launch_ms": 1e3 * avg_launch_s,
+                     "flop_per_launch": flop_launch},
         "cpu_baseline": cpu,
     }
     h.close()

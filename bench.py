@@ -19,6 +19,12 @@ reflector R_k from H resident in HBM to R resident in HBM.
                of the same matrix, scaled by the sweep count of a full solve
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+
+With --workload batched it times the batched solve instead: 256 planted
+problems (d uniform over 128/256/512/1024, k uniform in 1..16, relative gap
+log-uniform in [1e-3, 1e-1], midpoint shifts, seed 0) in FP32 with the FP64
+certificate, one refl_sign_batched call per step, against the same problems
+solved one refl_sign call at a time; it prints its own JSON line.
 """
 import argparse
 import json
@@ -74,6 +80,8 @@ def main():
     ap.add_argument("--lanczos-steps", type=int, default=3, help="timed solves with the shift estimated")
     ap.add_argument("--cg-tol", type=float, default=None, help="inner solve tolerance (library default if unset)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=("allen_cahn", "batched"), default="allen_cahn")
+    ap.add_argument("--batch", type=int, default=256, help="problems of the batched workload")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
                          "kernel (reads 256 MiB, writes 256 MiB) that calibrates FETCH_SIZE/WRITE_SIZE")
@@ -83,6 +91,10 @@ def main():
               "is computed on a single device; see the design notes for how it would shard.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched":
+        bench_batched(args)
+        return
 
     import torch
     from paper_2605_24840_amd import inputs, refl
@@ -245,6 +257,129 @@ def main():
         "cpu_baseline": cpu,
     }
     h.close()
+    print(json.dumps(out), flush=True)
+
+
+FP32_PEAK = 157.3e12
+
+
+def bench_batched(args):
+    """Batched planted solves (FP32 bulk, FP64 certificate): problems/s of one
+    refl_sign_batched call with the inputs resident in HBM, the same problems
+    through refl_sign one at a time, and the grouped product kernels against
+    the FP32 MFMA peak."""
+    import torch
+    from paper_2605_24840_amd import inputs, refl
+
+    n, seed = args.batch, args.seed
+    specs = inputs.batch_specs(n, seed=seed)
+    dev = torch.device("cuda", 0)
+    log(f"batched workload: {n} problems, generating")
+    Hs, ks, ss, Qs = [], [], [], {}
+    sample = {}
+    for p, spec in enumerate(specs):
+        H, lam, Q = inputs.batch_problem(spec)
+        k = spec[1]
+        Hs.append(torch.from_numpy(H).to(dev))
+        ks.append(k)
+        ss.append(0.5 * (lam[k - 1] + lam[k]))
+        if spec[0] not in sample:
+            sample[spec[0]] = (p, H, Q)
+    ds = [spec[0] for spec in specs]
+    Rs = [torch.empty_like(H) for H in Hs]
+    h = refl.Handle(dev)
+    kw = dict(precision="fp32", tol=1e-3, timing=True)
+
+    def run_batch():
+        _, infos, sts, st = refl.sign_batched(Hs, ks, ss, handle=h, outs=Rs, check=False, **kw)
+        if st != 0:
+            raise RuntimeError(f"refl_sign_batched returned {refl.STATUS[st]}: {refl.refl_last_error(h.h)}")
+        return infos
+
+    for i in range(args.warmup):
+        infos = run_batch()
+        log(f"warmup {i}: {infos[0]['ms_total']:.2f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [run_batch() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    infos = runs[-1]
+    steps = [i["ns_steps"] for i in infos]
+    # Algorithmic work of the grouped FP32 products: a symmetric d x d
+    # product is d^3 multiply-adds' worth of flops counted once (d^3 flops
+    # for the upper half, as for the single-problem products); problem p
+    # runs steps + 1 RESIDUAL and steps UPDATE products.
+    flop = sum((2 * st + 1) * float(d) ** 3 for st, d in zip(steps, ds))
+    gemm_s = np.mean([r[0]["ms_gemm"] for r in runs]) / 1e3
+    launches = runs[-1][0]["gemm_launches"]
+    achieved = flop / gemm_s
+    errs = {}
+    for d, (p, H, Q) in sorted(sample.items()):
+        Rk = np.eye(d) - 2.0 * Q[:, :ks[p]] @ Q[:, :ks[p]].T
+        errs[str(d)] = float(np.linalg.norm(Rs[p].cpu().numpy() - Rk))
+    log(f"batched: {1e3 * t_batch:.2f} ms per batch ({n / t_batch:.1f} problems/s), steps "
+        f"{min(steps)}..{max(steps)}, grouped products {1e3 * gemm_s:.2f} ms in {launches} launches "
+        f"= {achieved / 1e12:.1f} TFLOP/s; errors {errs}")
+
+    # The same problems one refl_sign call at a time.
+    def run_seq():
+        for p in range(n):
+            _, info, st = refl.sign(Hs[p], ks[p], ss[p], handle=h, out=Rs[p], check=False, **kw)
+            if st != 0:
+                raise RuntimeError(f"refl_sign returned {refl.STATUS[st]} on problem {p}")
+
+    run_seq()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_seq()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    log(f"sequential: {1e3 * t_seq:.2f} ms ({n / t_seq:.1f} problems/s)")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        # One full oracle solve per size, weighted by how often the size occurs.
+        t_size = {}
+        for d, (p, H, Q) in sorted(sample.items()):
+            tc = time.perf_counter()
+            oracle.jacobi_eigh(H)
+            t_size[d] = time.perf_counter() - tc
+            log(f"cpu oracle d={d}: {t_size[d]:.2f} s")
+        t_avg = sum(t_size[d] for d in ds) / n
+        cpu = {"value": 1.0 / t_avg, "unit": "problems/s", "cores": oracle.oracle_threads(),
+               "kind": "oracle",
+               "sample": "one full cyclic-Jacobi solve per size (" +
+                         ", ".join(f"d={d}: {t:.2f} s" for d, t in sorted(t_size.items())) +
+                         f"), weighted by the size mix of the {n} problems"}
+    h.close()
+    out = {
+        "metric": "problems/s, batched planted solves (FP32 bulk + FP64 certificate)",
+        "value": n / t_batch,
+        "unit": "problems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_batch,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 certificate)",
+        "data": "synthetic",
+        "config": {"workload": "batched_planted", "problems": n, "sizes": [128, 256, 512, 1024],
+                   "kmax": 16, "grel": [1e-3, 1e-1], "seed": seed, "tol": kw["tol"],
+                   "shift": "supplied midpoint"},
+        "ns_steps": {"min": min(steps), "max": max(steps), "mean": float(np.mean(steps))},
+        "err_fro_by_size": errs,
+        "sequential": {"value": n / t_seq, "unit": "problems/s", "ms": 1e3 * t_seq},
+        "speedup_vs_sequential": t_seq / t_batch,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": FP32_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": None,
+                     "kernel": "k_sym_gemm_f_grouped<float, GEMM_RESIDUAL|GEMM_UPDATE>",
+                     "launches": launches, "avg_launch_ms": 1e3 * gemm_s / max(launches, 1)},
+        "cpu_baseline": cpu,
+    }
     print(json.dumps(out), flush=True)
 
 

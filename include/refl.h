@@ -24,8 +24,9 @@
  *   exactly symmetric.  Blocks of vectors V, Y are d x nrhs, column-major
  *   (column c starts at V + c*ldv, ldv >= d).
  * - All device work is enqueued on the handle's HIP stream.  refl_sign,
- *   refl_sign_apply and refl_estimate_shift synchronise that stream before
- *   returning (their info outputs live on the host); refl_apply does not.
+ *   refl_sign_apply, refl_sign_batched and refl_estimate_shift synchronise
+ *   that stream before returning (their info outputs live on the host);
+ *   refl_apply does not.
  * - A handle is not thread-safe; use one handle per host thread.  Calls on
  *   one handle are serialised by its stream.
  * - Errors are reported only through refl_status_t; nothing throws or aborts
@@ -193,6 +194,38 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double *dR, int64_t l
 refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
                               const refl_params_t *p, int64_t nrhs, const double *dV,
                               int64_t ldv, double *dY, int64_t ldy, refl_info_t *info);
+
+/* Reflectors of nprob independent problems in one call (the batched dense
+ * regime of the section on computational regime and complexity: many
+ * moderate-size Hessians make full-matrix products efficient).
+ *
+ * Arguments are HOST arrays of length nprob: d[p], the device pointers
+ * dH[p] / dR[p] with leading dimensions ldh[p] / ldr[p] (each as in
+ * refl_sign), and params[p].  Every problem must use the same precision,
+ * REFL_PREC_FP64 or REFL_PREC_FP32, and a given shift (shift_mode
+ * REFL_SHIFT_GIVEN); k, s, scale, tol, max_iter and fixed_steps may differ.
+ * MIXED or a Lanczos shift gives REFL_ERR_UNSUPPORTED.
+ *
+ * Each Newton-Schulz product runs as one grouped launch over the upper tiles
+ * of every problem still iterating; each problem stops by refl_sign's rule
+ * and its R (and steps, scale, trace) equal, bit for bit, those of refl_sign
+ * with params[p].  In FP32 the certificate ||X^2 - I||_F reported in
+ * info[p].resid_fro and used for info[p].index_j is recomputed in FP64 from
+ * the final FP32 iterate.  info[p].ms_* and ms_gemm are batch-wide.
+ *
+ * info and status (length nprob, host) may be NULL.  status[p] is what
+ * refl_sign would return for problem p.  Returns REFL_OK if every problem
+ * succeeded, else the status of the first problem that did not (its index
+ * is in refl_last_error); argument errors are returned before any work.
+ * Device workspace: refl_sign_batched_workspace_size (the sum over the
+ * problems of about 28 dp^2 bytes in FP32 or 32 dp^2 in FP64, dp = d[p]
+ * rounded up to 128). */
+refl_status_t refl_sign_batched(refl_handle_t h, int32_t nprob, const int64_t *d,
+                                const double *const *dH, const int64_t *ldh,
+                                const refl_params_t *params, double *const *dR,
+                                const int64_t *ldr, refl_info_t *info, refl_status_t *status);
+refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, const int64_t *d,
+                                               const refl_params_t *params, size_t *bytes);
 
 /* Static strings; never NULL. */
 const char *refl_status_string(refl_status_t s);

@@ -58,22 +58,18 @@ struct FCfg {
   static constexpr int VE = 16 / (int)sizeof(T);        // elements per 16 B
 };
 
+// One output tile (I, J), I <= J; the tile's partial (||N||_F^2 or trace
+// contribution) goes to *partial.
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
-                                                    const T* __restrict__ B,
-                                                    const T* __restrict__ Xold,
-                                                    T* __restrict__ out, int ld, int d, int dp,
-                                                    const int2* __restrict__ tiles,
-                                                    double* __restrict__ partials) {
+__device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T* __restrict__ B,
+                                                const T* __restrict__ Xold, T* __restrict__ out,
+                                                int ld, int d, int dp, int I, int J, T* lds,
+                                                double* red, double* __restrict__ partial) {
   typedef FCfg<T> C;
   typedef FMfma<T> M;
   typedef typename M::acc_t acc_t;
-  __shared__ T lds[C::LDS];
-  __shared__ double red[4];
-
-  const int2 tl = tiles[blockIdx.x];
-  const int i0 = tl.x * TILE, j0 = tl.y * TILE;
-  const bool diag = (tl.x == tl.y);
+  const int i0 = I * TILE, j0 = J * TILE;
+  const bool diag = (I == J);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 
@@ -209,7 +205,46 @@ __global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
     }
   }
   const double tot = block_sum_256(part, red);
-  if (tid == 0) partials[blockIdx.x] = tot;
+  if (tid == 0) *partial = tot;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
+                                                    const T* __restrict__ B,
+                                                    const T* __restrict__ Xold,
+                                                    T* __restrict__ out, int ld, int d, int dp,
+                                                    const int2* __restrict__ tiles,
+                                                    double* __restrict__ partials) {
+  __shared__ T lds[FCfg<T>::LDS];
+  __shared__ double red[4];
+  const int2 tl = tiles[blockIdx.x];
+  sym_gemm_f_tile<T, MODE>(A, B, Xold, out, ld, d, dp, tl.x, tl.y, lds, red,
+                           partials + blockIdx.x);
+}
+
+// Grouped launch over the tiles of many problems: tile (p, I, J, slot) reads
+// the problem's iterate pair and N from its descriptor and writes its
+// partial to partials[slot]; `parity` selects which of the pair holds the
+// current iterate (every problem still iterating has taken the same number
+// of steps).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_sym_gemm_f_grouped(const GemmProblem* __restrict__ probs,
+                                                            const int4* __restrict__ tiles,
+                                                            int parity,
+                                                            double* __restrict__ partials) {
+  __shared__ T lds[FCfg<T>::LDS];
+  __shared__ double red[4];
+  const int4 tl = tiles[blockIdx.x];
+  const GemmProblem pr = probs[tl.x];
+  T* Xc = reinterpret_cast<T*>(pr.X[parity]);
+  T* Xn = reinterpret_cast<T*>(pr.X[parity ^ 1]);
+  T* N = reinterpret_cast<T*>(pr.N);
+  if (MODE == GEMM_RESIDUAL)
+    sym_gemm_f_tile<T, MODE>(Xc, Xc, nullptr, N, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
+                             partials + tl.w);
+  else
+    sym_gemm_f_tile<T, MODE>(Xc, N, Xc, Xn, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
+                             partials + tl.w);
 }
 
 template <typename T>
@@ -235,6 +270,23 @@ hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const f
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
                                double* partials, hipStream_t st) {
   return launch_f<float>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+}
+
+hipError_t launch_sym_gemm_grouped(int fp64, int mode, const GemmProblem* probs, const int4* tiles,
+                                   int ntiles, int parity, double* partials, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+#define REFL_GG(T, MODEV)                                                                      \
+  hipLaunchKernelGGL((k_sym_gemm_f_grouped<T, MODEV>), dim3(ntiles), dim3(256), 0, st, probs, \
+                     tiles, parity, partials)
+  if (fp64) {
+    if (mode == GEMM_RESIDUAL) REFL_GG(double, GEMM_RESIDUAL);
+    else REFL_GG(double, GEMM_UPDATE);
+  } else {
+    if (mode == GEMM_RESIDUAL) REFL_GG(float, GEMM_RESIDUAL);
+    else REFL_GG(float, GEMM_UPDATE);
+  }
+#undef REFL_GG
+  return hipGetLastError();
 }
 
 }  // namespace refl

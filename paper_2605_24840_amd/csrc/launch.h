@@ -23,6 +23,19 @@ hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const f
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
                                double* partials, hipStream_t st);
 
+// Grouped products over the upper tiles of many problems (FP64 or FP32): the
+// tile list holds (problem, I, J, slot); each problem's descriptor gives its
+// iterate pair X[0..1] (element type per `fp64`), N, and sizes.  The tile's
+// partial goes to partials[slot].  RESIDUAL reads X[parity] and writes N;
+// UPDATE reads X[parity] and N and writes X[parity ^ 1].
+struct GemmProblem {
+  void* X[2];
+  void* N;
+  int ld, d, dp, pad;
+};
+hipError_t launch_sym_gemm_grouped(int fp64, int mode, const GemmProblem* probs, const int4* tiles,
+                                   int ntiles, int parity, double* partials, hipStream_t st);
+
 // Products of matrices held as W BF16 words per entry (planes ps elements
 // apart), FP32 accumulation on 32x32x16 BF16 MFMA.  Word products kept:
 // W=1 {00}; W=2 {00,01,10}; W=3 {00,01,10,02,11,20}.  tile = 128 or 192
@@ -51,6 +64,10 @@ hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, doub
 // FP32 copy of H - sI (the operator of the inner solves).
 hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* Hs,
                               hipStream_t st);
+// out[slot ? slot[q] : q] = sum of partials[begin[q] .. begin[q + 1]), q < nq,
+// summed in the same order as launch_reduce_sum over that range.
+hipError_t launch_reduce_ranges(const double* partials, const int* begin, const int* slot, int nq,
+                                double* out, hipStream_t st);
 // dst[slot] = sum of partials[0..n) in a fixed order.
 hipError_t launch_reduce_sum(const double* partials, int n, double* scal, int slot,
                              hipStream_t st);

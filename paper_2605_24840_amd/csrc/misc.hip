@@ -142,6 +142,21 @@ __global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ p
   if (threadIdx.x == 0) scal[slot] = t;
 }
 
+// out[slot[q]] (or out[q]) = sum of p[begin[q] .. begin[q + 1]), in the same
+// order as k_reduce_sum over that range.
+__global__ __launch_bounds__(256) void k_reduce_ranges(const double* __restrict__ p,
+                                                       const int* __restrict__ begin,
+                                                       const int* __restrict__ slot,
+                                                       double* __restrict__ out) {
+  __shared__ double red[4];
+  const int q = blockIdx.x;
+  const int b = begin[q], n = begin[q + 1] - b;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += p[b + i];
+  const double t = block_sum_256(a, red);
+  if (threadIdx.x == 0) out[slot ? slot[q] : q] = t;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_trace(const T* __restrict__ X, int dp, int d,
                                                double* __restrict__ scal, int slot) {
@@ -678,6 +693,12 @@ hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* 
 hipError_t launch_reduce_sum(const double* partials, int n, double* scal, int slot,
                              hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partials, n, scal, slot);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_ranges(const double* partials, const int* begin, const int* slot, int nq,
+                                double* out, hipStream_t st) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_ranges, dim3(nq), dim3(256), 0, st, partials, begin, slot, out);
   return hipGetLastError();
 }
 hipError_t launch_trace_f64(const double* X, int dp, int d, double* scal, int slot,

@@ -52,6 +52,8 @@ struct refl_handle_s {
   std::vector<hipEvent_t> bulk_ev;  // completion of the pipelined bulk steps
   double* lz_pin = nullptr;    // host pinned copies of the Lanczos blocks and flags
   size_t lz_pin_bytes = 0;
+  void* batch_pin = nullptr;   // host pinned staging of the batched solve
+  size_t batch_pin_bytes = 0;
   hipEvent_t lz_ev[2] = {nullptr, nullptr};
   int ncu = 256;               // compute units of the device
   char err[512] = {0};
@@ -283,8 +285,7 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
 // (block b runs on XCD b % 8) take a compact patch of the triangle: tiles
 // are listed by bands of 4 tile rows, column by column, the list is cut into
 // 8 consecutive pieces, and block b takes element b / 8 of piece b % 8.
-void build_tiles(const Work& w, std::vector<int2>& host) {
-  const int nt = w.dp / w.ts;
+void build_tiles_nt(int nt, std::vector<int2>& host) {
   std::vector<int2> order;
   for (int b0 = 0; b0 < nt; b0 += 4)
     for (int J = b0; J < nt; ++J)
@@ -299,6 +300,7 @@ void build_tiles(const Work& w, std::vector<int2>& host) {
   host.resize(T);
   for (int b = 0; b < T; ++b) host[b] = order[start[b % 8] + b / 8];
 }
+void build_tiles(const Work& w, std::vector<int2>& host) { build_tiles_nt(w.dp / w.ts, host); }
 
 // Index certificate: returns j, or -1 if b = sqrt(d)||X^2-I||_F >= 1 or no
 // integer j has |trace - (d - 2j)| < 1.
@@ -1081,6 +1083,423 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   return out_status;
 }
 
+
+// ---------------------------------------------------------------- batched
+// Many independent problems (refl_sign_batched).  Each problem keeps its own
+// FP64 copy of H, iterate pair and N; the Newton-Schulz products of every
+// problem still iterating run as ONE grouped launch per product, over the
+// concatenated upper-tile lists.  Tile partials land in per-problem ranges
+// laid out exactly as refl_sign's, and each range is reduced in
+// refl_sign's order, so every problem takes the same steps and returns the
+// same R, bit for bit, as a refl_sign call with its parameters.
+struct BatchProb {
+  int d = 0, dp = 0, ntiles = 0;
+  double* Hf = nullptr;   // FP64 copy of H; FP32 after the bulk: FP64 copy of the iterate
+  void* X[2] = {nullptr, nullptr};
+  void* N = nullptr;
+  double* N64 = nullptr;  // FP32: N of the FP64 certificate product
+  double* scal = nullptr; // SC_ALPHA, SC_NONFINITE of this problem
+};
+
+struct BatchWork {
+  std::vector<BatchProb> pr;
+  int ttot = 0, maxdp = 0;
+  double *rowsum = nullptr, *scal = nullptr, *partials = nullptr;
+  GemmProblem *probs = nullptr, *probs64 = nullptr;
+  int4 *tiles = nullptr, *tiles_fin = nullptr;
+  int *begin = nullptr, *slot = nullptr, *begin_fin = nullptr, *slot_fin = nullptr;
+  double *res = nullptr, *trace = nullptr, *cert = nullptr;
+};
+
+constexpr int BSC = 2;  // scalar slots per problem (SC_ALPHA, SC_NONFINITE)
+
+size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, bool fp64) {
+  Carve c(base);
+  bw.pr.assign(nprob, BatchProb());
+  bw.ttot = 0;
+  bw.maxdp = 0;
+  const size_t es = fp64 ? sizeof(double) : sizeof(float);
+  bw.scal = c.take<double>((size_t)BSC * nprob);
+  for (int p = 0; p < nprob; ++p) {
+    BatchProb& q = bw.pr[p];
+    q.d = (int)d[p];
+    q.dp = (int)round_up(d[p], TILE);
+    const int nt = q.dp / TILE;
+    q.ntiles = nt * (nt + 1) / 2;
+    bw.ttot += q.ntiles;
+    bw.maxdp = std::max(bw.maxdp, q.dp);
+    const size_t n2 = (size_t)q.dp * q.dp;
+    q.Hf = c.take<double>(n2);
+    q.X[0] = c.take<char>(es * n2);
+    q.X[1] = c.take<char>(es * n2);
+    q.N = c.take<char>(es * n2);
+    q.N64 = fp64 ? nullptr : c.take<double>(n2);
+    q.scal = bw.scal ? bw.scal + (size_t)BSC * p : nullptr;
+  }
+  bw.rowsum = c.take<double>(2 * (size_t)bw.maxdp);
+  bw.probs = c.take<GemmProblem>(nprob);
+  bw.probs64 = c.take<GemmProblem>(nprob);
+  bw.tiles = c.take<int4>(bw.ttot);
+  bw.tiles_fin = c.take<int4>(bw.ttot);
+  bw.partials = c.take<double>(bw.ttot);
+  bw.begin = c.take<int>(nprob + 1);
+  bw.slot = c.take<int>(nprob);
+  bw.begin_fin = c.take<int>(nprob + 1);
+  bw.slot_fin = c.take<int>(nprob);
+  bw.res = c.take<double>(nprob);
+  bw.trace = c.take<double>(nprob);
+  bw.cert = c.take<double>(nprob);
+  return c.off + 256;
+}
+
+// Host staging of the batched solve: one pinned block, carved like the
+// device workspace.
+struct BatchPin {
+  GemmProblem *probs, *probs64;
+  double *scal, *res, *trace, *cert;
+  int4 *tiles, *tiles_fin;
+  int *begin, *slot, *begin_fin, *slot_fin;
+};
+
+size_t batch_pin_layout(BatchPin& bp, void* base, int nprob, int ttot) {
+  Carve c(base);
+  bp.probs = c.take<GemmProblem>(nprob);
+  bp.probs64 = c.take<GemmProblem>(nprob);
+  bp.scal = c.take<double>((size_t)BSC * nprob);
+  bp.res = c.take<double>(nprob);
+  bp.trace = c.take<double>(nprob);
+  bp.cert = c.take<double>(nprob);
+  bp.tiles = c.take<int4>(ttot);
+  bp.tiles_fin = c.take<int4>(ttot);
+  bp.begin = c.take<int>(nprob + 1);
+  bp.slot = c.take<int>(nprob);
+  bp.begin_fin = c.take<int>(nprob + 1);
+  bp.slot_fin = c.take<int>(nprob);
+  return c.off + 256;
+}
+
+// Grouped tile list over the problems ids[0..n): range q of the partials is
+// begin[q] .. begin[q + 1) and holds problem ids[q]'s tiles in the order of
+// build_tiles_nt; slot[q] = ids[q].  Blocks are listed largest problem first
+// (the longest tiles start first).  Returns the number of tiles.
+int batch_tiles(const BatchWork& bw, const std::vector<int>& ids, int4* tiles, int* begin,
+                int* slot) {
+  const int n = (int)ids.size();
+  begin[0] = 0;
+  for (int q = 0; q < n; ++q) {
+    begin[q + 1] = begin[q] + bw.pr[ids[q]].ntiles;
+    slot[q] = ids[q];
+  }
+  std::vector<int> ord(n);
+  for (int q = 0; q < n; ++q) ord[q] = q;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return bw.pr[ids[a]].dp > bw.pr[ids[b]].dp; });
+  std::vector<int2> tl;
+  int t = 0;
+  for (int q : ord) {
+    build_tiles_nt(bw.pr[ids[q]].dp / TILE, tl);
+    for (size_t i = 0; i < tl.size(); ++i)
+      tiles[t++] = make_int4(ids[q], tl[i].x, tl[i].y, begin[q] + (int)i);
+  }
+  return t;
+}
+
+refl_status_t batch_check(refl_handle_t h, int nprob, const int64_t* d, const double* const* dH,
+                          const int64_t* ldh, const refl_params_t* params, double* const* dR,
+                          const int64_t* ldr) {
+  if (nprob < 1) return fail(h, REFL_ERR_INVALID_ARG, "nprob must be >= 1");
+  if (!d || !params) return fail(h, REFL_ERR_INVALID_ARG, "d or params is NULL");
+  for (int p = 0; p < nprob; ++p) {
+    refl_status_t rs = check_params(h, d[p], &params[p]);
+    if (rs != REFL_OK) {
+      char msg[sizeof(h->err)];
+      std::snprintf(msg, sizeof(msg), "%s", h->err);
+      return fail(h, rs, "problem %d: %s", p, msg);
+    }
+    const refl_params_t& q = params[p];
+    if (q.precision != params[0].precision)
+      return fail(h, REFL_ERR_INVALID_ARG, "problem %d: every problem needs the same precision", p);
+    if (q.precision == REFL_PREC_MIXED)
+      return fail(h, REFL_ERR_UNSUPPORTED, "problem %d: batched solves run FP64 or FP32", p);
+    if (q.shift_mode != REFL_SHIFT_GIVEN)
+      return fail(h, REFL_ERR_UNSUPPORTED, "problem %d: batched solves need a given shift", p);
+  }
+  if (!dH || !ldh || !dR || !ldr) return fail(h, REFL_ERR_INVALID_ARG, "NULL pointer array");
+  for (int p = 0; p < nprob; ++p) {
+    if (!dH[p] || ldh[p] < d[p]) return fail(h, REFL_ERR_INVALID_ARG, "problem %d: H is NULL or ldh < d", p);
+    if (!dR[p] || ldr[p] < d[p]) return fail(h, REFL_ERR_INVALID_ARG, "problem %d: R is NULL or ldr < d", p);
+  }
+  return REFL_OK;
+}
+
+refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const double* const* dH,
+                           const int64_t* ldh, const refl_params_t* params, double* const* dR,
+                           const int64_t* ldr, refl_info_t* info, refl_status_t* status) {
+  const double t_start = now_ms();
+  refl_status_t rs = batch_check(h, nprob, d, dH, ldh, params, dR, ldr);
+  if (rs != REFL_OK) {
+    if (status && nprob > 0)
+      for (int p = 0; p < nprob; ++p) status[p] = rs;
+    return rs;
+  }
+  const bool fp64 = params[0].precision == REFL_PREC_FP64;
+  HIPCHK(hipSetDevice(h->device));
+  BatchWork bw;
+  const size_t need = batch_layout(bw, nullptr, nprob, d, fp64);
+  void* base = nullptr;
+  rs = ensure_workspace(h, need, &base);
+  if (rs != REFL_OK) return rs;
+  batch_layout(bw, base, nprob, d, fp64);
+  hipStream_t st = h->stream;
+  BatchPin bp;
+  const size_t pin_need = batch_pin_layout(bp, nullptr, nprob, bw.ttot);
+  if (h->batch_pin_bytes < pin_need) {
+    HIPCHK(hipStreamSynchronize(st));
+    if (h->batch_pin) (void)hipHostFree(h->batch_pin);
+    h->batch_pin = nullptr;
+    h->batch_pin_bytes = 0;
+    if (hipHostMalloc(&h->batch_pin, pin_need, hipHostMallocDefault) != hipSuccess || !h->batch_pin)
+      return fail(h, REFL_ERR_NO_MEMORY, "pinned staging of %zu bytes failed", pin_need);
+    h->batch_pin_bytes = pin_need;
+  }
+  batch_pin_layout(bp, h->batch_pin, nprob, bw.ttot);
+
+  std::vector<refl_info_t> inf(nprob);
+  std::vector<refl_status_t> pst(nprob, REFL_OK);
+  for (int p = 0; p < nprob; ++p) {
+    std::memset(&inf[p], 0, sizeof(refl_info_t));
+    refl_info_t& f = inf[p];
+    f.lam_k = f.lam_k1 = f.eps = f.margin = NaN;
+    f.commutator_fro = f.dk_bound = NaN;
+    f.resid_fro = f.trace = NaN;
+    f.index_j = -1;
+    f.s = params[p].s;
+  }
+  auto finish = [&](refl_status_t call_status) -> refl_status_t {
+    if (info)
+      for (int p = 0; p < nprob; ++p) info[p] = inf[p];
+    if (status)
+      for (int p = 0; p < nprob; ++p) status[p] = pst[p];
+    return call_status;
+  };
+
+  // ---- set-up (per problem) ----
+  {
+    std::vector<GemmProblem> g(nprob), g64(nprob);
+    for (int p = 0; p < nprob; ++p) {
+      const BatchProb& q = bw.pr[p];
+      g[p].X[0] = q.X[0];
+      g[p].X[1] = q.X[1];
+      g[p].N = q.N;
+      g64[p].X[0] = g64[p].X[1] = q.Hf;
+      g64[p].N = q.N64;
+      g[p].ld = g64[p].ld = q.dp;
+      g[p].d = g64[p].d = q.d;
+      g[p].dp = g64[p].dp = q.dp;
+      g[p].pad = g64[p].pad = 0;
+    }
+    const size_t gb = sizeof(GemmProblem) * nprob;
+    std::memcpy(bp.probs, g.data(), gb);
+    std::memcpy(bp.probs64, g64.data(), gb);
+    HIPCHK(hipMemcpyAsync(bw.probs, bp.probs, gb, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bw.probs64, bp.probs64, gb, hipMemcpyHostToDevice, st));
+  }
+  for (int p = 0; p < nprob; ++p) {
+    const BatchProb& q = bw.pr[p];
+    const refl_params_t& pp = params[p];
+    HIPCHK(launch_mirror_upper(dH[p], ldh[p], q.d, q.Hf, q.dp, st));
+    HIPCHK(launch_scale_inf(q.Hf, q.dp, q.d, pp.s, pp.scale_mode != REFL_SCALE_INF, pp.alpha,
+                            bw.rowsum, q.scal, st));
+    if (fp64) {
+      HIPCHK(launch_init_x0_f64(q.Hf, q.dp, q.d, pp.s, q.scal, (double*)q.X[0], st));
+      HIPCHK(launch_trace_f64((const double*)q.X[0], q.dp, q.d, bw.trace, p, st));
+    } else {
+      HIPCHK(launch_init_x0_f32(q.Hf, q.dp, q.d, pp.s, q.scal, (float*)q.X[0], st));
+      HIPCHK(launch_trace_f32((const float*)q.X[0], q.dp, q.d, bw.trace, p, st));
+    }
+  }
+  HIPCHK(hipMemcpyAsync(bp.scal, bw.scal, sizeof(double) * BSC * nprob, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(bp.trace, bw.trace, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int> cur;
+  std::vector<double> trace_cur(nprob, NaN);
+  for (int p = 0; p < nprob; ++p) {
+    inf[p].alpha = bp.scal[BSC * p + SC_ALPHA];
+    trace_cur[p] = bp.trace[p];
+    if (bp.scal[BSC * p + SC_NONFINITE] > 0.0) {
+      pst[p] = REFL_ERR_NOT_FINITE;
+    } else if (!(inf[p].alpha > 0.0) || !std::isfinite(inf[p].alpha)) {
+      pst[p] = REFL_ERR_NOT_FINITE;
+    } else {
+      cur.push_back(p);
+    }
+  }
+  const double t_setup = now_ms();
+
+  // ---- bulk: one grouped product per half-step for all live problems ----
+  const int fprec = fp64 ? 1 : 0;
+  std::vector<std::vector<double>> hist(nprob);
+  std::vector<char> converged(nprob, 0);
+  int nt_cur = batch_tiles(bw, cur, bp.tiles, bp.begin, bp.slot);
+  auto upload_step = [&](int nq) -> refl_status_t {
+    HIPCHK(hipMemcpyAsync(bw.tiles, bp.tiles, sizeof(int4) * nt_cur, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bw.begin, bp.begin, sizeof(int) * (nq + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bw.slot, bp.slot, sizeof(int) * nq, hipMemcpyHostToDevice, st));
+    return REFL_OK;
+  };
+  if (!cur.empty()) {
+    rs = upload_step((int)cur.size());
+    if (rs != REFL_OK) return rs;
+  }
+  const bool timing = params[0].timing != 0;
+  size_t nev = 0;
+  auto ev_pair = [&]() -> hipError_t {
+    while (h->ev.size() < 2 * (nev + 1)) {
+      hipEvent_t e;
+      hipError_t er = hipEventCreate(&e);
+      if (er != hipSuccess) return er;
+      h->ev.push_back(e);
+    }
+    return hipSuccess;
+  };
+  for (int m = 0; !cur.empty(); ++m) {
+    const int par = m & 1;
+    const int nq = (int)cur.size();
+    if (timing) {
+      HIPCHK(ev_pair());
+      HIPCHK(hipEventRecord(h->ev[2 * nev], st));
+    }
+    HIPCHK(launch_sym_gemm_grouped(fprec, GEMM_RESIDUAL, bw.probs, bw.tiles, nt_cur, par,
+                                   bw.partials, st));
+    if (timing) HIPCHK(hipEventRecord(h->ev[2 * nev++ + 1], st));
+    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin, bw.slot, nq, bw.res, st));
+    HIPCHK(hipMemcpyAsync(bp.res, bw.res, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
+    if (m > 0)
+      HIPCHK(hipMemcpyAsync(bp.trace, bw.trace, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // Stopping rule of refl_sign (FP64 / FP32), problem by problem.
+    std::vector<int> next, fin;
+    for (int p : cur) {
+      const refl_params_t& pp = params[p];
+      if (m > 0) trace_cur[p] = bp.trace[p];
+      const double resid = std::sqrt(std::fmax(bp.res[p], 0.0));
+      std::vector<double>& hs = hist[p];
+      hs.push_back(resid);
+      inf[p].ns_steps = m;
+      inf[p].resid_fro = resid;
+      inf[p].trace = trace_cur[p];
+      if (!std::isfinite(resid)) {
+        pst[p] = REFL_ERR_NOT_FINITE;
+        continue;
+      }
+      bool stop = false;
+      if (pp.fixed_steps > 0) {
+        if (m >= pp.fixed_steps) {
+          stop = true;
+          converged[p] = 1;
+        }
+      } else {
+        const size_t n = hs.size();
+        if (resid < pp.tol) {
+          stop = true;
+          converged[p] = 1;
+        } else if (n >= 3 && resid < 1e-6 && resid > 0.5 * hs[n - 3]) {
+          stop = true;
+        } else if (m >= pp.max_iter) {
+          stop = true;
+        }
+      }
+      if (stop) {
+        fin.push_back(p);
+      } else {
+        next.push_back(p);
+      }
+    }
+    // Output of the problems that stopped at this iterate.  FP32: the
+    // certificate ||X^2 - I||_F is recomputed from the iterate in FP64.
+    if (!fin.empty()) {
+      for (int p : fin) {
+        const BatchProb& q = bw.pr[p];
+        if (fp64) {
+          HIPCHK(launch_copy_out_f64((const double*)q.X[par], q.dp, q.d, dR[p], ldr[p], st));
+        } else {
+          HIPCHK(launch_copy_out_f32((const float*)q.X[par], q.dp, q.d, dR[p], ldr[p], st));
+          HIPCHK(launch_copy_out_f32((const float*)q.X[par], q.dp, q.dp, q.Hf, q.dp, st));
+        }
+      }
+      if (!fp64) {
+        const int ntf = batch_tiles(bw, fin, bp.tiles_fin, bp.begin_fin, bp.slot_fin);
+        const int nf = (int)fin.size();
+        HIPCHK(hipMemcpyAsync(bw.tiles_fin, bp.tiles_fin, sizeof(int4) * ntf, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(bw.begin_fin, bp.begin_fin, sizeof(int) * (nf + 1), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(bw.slot_fin, bp.slot_fin, sizeof(int) * nf, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_sym_gemm_grouped(1, GEMM_RESIDUAL, bw.probs64, bw.tiles_fin, ntf, 0,
+                                       bw.partials, st));
+        HIPCHK(launch_reduce_ranges(bw.partials, bw.begin_fin, bw.slot_fin, nf, bw.cert, st));
+      }
+    }
+    if (next.size() != cur.size()) {
+      cur.swap(next);
+      if (cur.empty()) break;
+      nt_cur = batch_tiles(bw, cur, bp.tiles, bp.begin, bp.slot);
+      rs = upload_step((int)cur.size());
+      if (rs != REFL_OK) return rs;
+    }
+    if (timing) {
+      HIPCHK(ev_pair());
+      HIPCHK(hipEventRecord(h->ev[2 * nev], st));
+    }
+    HIPCHK(launch_sym_gemm_grouped(fprec, GEMM_UPDATE, bw.probs, bw.tiles, nt_cur, par,
+                                   bw.partials, st));
+    if (timing) HIPCHK(hipEventRecord(h->ev[2 * nev++ + 1], st));
+    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin, bw.slot, (int)cur.size(), bw.trace, st));
+  }
+  HIPCHK(hipMemcpyAsync(bp.cert, bw.cert, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double ms_gemm = 0.0;
+  if (timing) {
+    for (size_t i = 0; i < nev; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+      ms_gemm += ms;
+    }
+  }
+  const double t_end = now_ms();
+
+  // ---- certificates and statuses ----
+  refl_status_t first = REFL_OK;
+  for (int p = 0; p < nprob; ++p) {
+    refl_info_t& f = inf[p];
+    const refl_params_t& pp = params[p];
+    f.ms_setup = t_setup - t_start;
+    f.ms_bulk = t_end - t_setup;
+    f.ms_total = t_end - t_start;
+    if (timing) {
+      f.ms_gemm = ms_gemm;
+      f.gemm_launches = (int)nev;
+    }
+    if (pst[p] == REFL_OK) {
+      if (!fp64) f.resid_fro = std::sqrt(std::fmax(bp.cert[p], 0.0));
+      f.index_j = index_certificate(d[p], f.resid_fro, f.trace);
+      if (!converged[p]) pst[p] = REFL_ERR_NOT_CONVERGED;
+      if (pp.fixed_steps == 0 && f.index_j >= 0 && f.index_j != pp.k)
+        pst[p] = REFL_ERR_NOT_ADMISSIBLE;
+    }
+    if (pst[p] != REFL_OK && first == REFL_OK) {
+      first = pst[p];
+      if (pst[p] == REFL_ERR_NOT_FINITE)
+        fail(h, first, "problem %d: H or the iterate is not finite", p);
+      else if (pst[p] == REFL_ERR_NOT_CONVERGED)
+        fail(h, first, "problem %d: no convergence after %d steps (resid %.3e)", p, f.ns_steps,
+             f.resid_fro);
+      else
+        fail(h, first, "problem %d: index certificate found %d negative eigenvalues, not k=%d", p,
+             f.index_j, pp.k);
+    }
+  }
+  return finish(first);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1144,6 +1563,7 @@ refl_status_t refl_destroy(refl_handle_t h) {
   for (hipEvent_t e : h->lz_ev)
     if (e) (void)hipEventDestroy(e);
   if (h->lz_pin) (void)hipHostFree(h->lz_pin);
+  if (h->batch_pin) (void)hipHostFree(h->batch_pin);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
   return REFL_OK;
@@ -1242,6 +1662,27 @@ refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, 
   *eps = lr.eps;
   *rho = lr.rho;
   return lanczos_status(h, lr);
+}
+
+refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, const int64_t* d,
+                                               const refl_params_t* params, size_t* bytes) {
+  if (!h || !bytes) return REFL_ERR_INVALID_ARG;
+  if (nprob < 1 || !d || !params) return fail(h, REFL_ERR_INVALID_ARG, "nprob, d or params");
+  for (int p = 0; p < nprob; ++p) {
+    refl_status_t rs = check_params(h, d[p], &params[p]);
+    if (rs != REFL_OK) return rs;
+  }
+  BatchWork bw;
+  *bytes = batch_layout(bw, nullptr, nprob, d, params[0].precision == REFL_PREC_FP64);
+  return REFL_OK;
+}
+
+refl_status_t refl_sign_batched(refl_handle_t h, int32_t nprob, const int64_t* d,
+                                const double* const* dH, const int64_t* ldh,
+                                const refl_params_t* params, double* const* dR,
+                                const int64_t* ldr, refl_info_t* info, refl_status_t* status) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  return batched_impl(h, nprob, d, dH, ldh, params, dR, ldr, info, status);
 }
 
 const char* refl_status_string(refl_status_t s) {

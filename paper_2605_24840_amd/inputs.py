@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "haar_orthogonal", "planted_eigenvalues", "planted_hessian",
     "allen_cahn_field", "allen_cahn_2d", "allen_cahn_1d_neumann",
-    "symmetric_normal", "diag_hessian",
+    "symmetric_normal", "diag_hessian", "batch_specs", "batch_problem",
 ]
 
 
@@ -166,3 +166,23 @@ def diag_hessian(d: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.nda
     """Diagonal H with distinct i.i.d. U(lo, hi) entries in random order."""
     rng = np.random.default_rng(seed)
     return np.diag(rng.uniform(lo, hi, size=d))
+
+
+def batch_specs(n: int = 256, seed: int = 0, sizes=(128, 256, 512, 1024), kmax: int = 16,
+                grel_range=(1e-3, 1e-1)):
+    """Shapes of a batch of planted problems: a list of ``(d, k, grel, pseed)``
+    with d uniform over ``sizes``, k uniform in 1..kmax, the relative gap grel
+    log-uniform over ``grel_range`` (absolute gap 2 grel), and pseed the seed
+    of problem p's matrix (seed * 65536 + p)."""
+    rng = np.random.default_rng(seed)
+    ds = rng.choice(np.asarray(sizes), size=n)
+    ks = rng.integers(1, kmax + 1, size=n)
+    lo, hi = math.log(grel_range[0]), math.log(grel_range[1])
+    gs = np.exp(rng.uniform(lo, hi, size=n))
+    return [(int(ds[p]), int(ks[p]), float(gs[p]), seed * 65536 + p) for p in range(n)]
+
+
+def batch_problem(spec):
+    """``planted_hessian`` of one ``batch_specs`` entry: ``(H, lam, Q)``."""
+    d, k, grel, pseed = spec
+    return planted_hessian(d, k, 2.0 * grel, pseed)

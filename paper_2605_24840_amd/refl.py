@@ -1,8 +1,8 @@
 """Python binding of ``librefl.so`` (include/refl.h): argument marshalling only.
 
 The functions named ``refl_*`` are the C entry points, called with device
-pointers.  ``sign``, ``apply``, ``sign_apply`` and ``estimate_shift`` wrap
-them for torch tensors on a ROCm device (torch provides the device memory and
+pointers.  ``sign``, ``apply``, ``sign_apply``, ``sign_batched`` and
+``estimate_shift`` wrap them for torch tensors on a ROCm device (torch provides the device memory and
 the stream; every step of the computation runs in the library's kernels).
 There is no CPU fallback: if the library is missing, loading raises.
 """
@@ -25,7 +25,8 @@ SCALE = {"inf": 0, "given": 1, "lanczos": 2}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
-           "refl_apply", "refl_sign_apply", "refl_status_string", "refl_last_error"]
+           "refl_apply", "refl_sign_apply", "refl_sign_batched",
+           "refl_sign_batched_workspace_size", "refl_status_string", "refl_last_error"]
 
 
 class refl_params_t(ctypes.Structure):
@@ -81,6 +82,9 @@ def load(path: str = LIB_PATH):
         "refl_sign": [H, i64, vp, i64, P(refl_params_t), vp, i64, P(refl_info_t)],
         "refl_apply": [H, i64, vp, i64, i64, vp, i64, vp, i64],
         "refl_sign_apply": [H, i64, vp, i64, P(refl_params_t), i64, vp, i64, vp, i64, P(refl_info_t)],
+        "refl_sign_batched": [H, i32, P(i64), P(vp), P(i64), P(refl_params_t), P(vp), P(i64),
+                              P(refl_info_t), P(ctypes.c_int)],
+        "refl_sign_batched_workspace_size": [H, i32, P(i64), P(refl_params_t), P(ctypes.c_size_t)],
         "refl_status_string": [ctypes.c_int],
         "refl_last_error": [H],
     }
@@ -156,6 +160,30 @@ def refl_estimate_shift(h, d, H_ptr, ldh, k, steps=0, seed=0, check=True):
     if check:
         _check(h, st)
     return st, tuple(o.value for o in out)
+
+
+def refl_sign_batched(h, ds, H_ptrs, ldhs, params, R_ptrs, ldrs, check=True):
+    """C call over host arrays; returns ``(status, [per-problem status], [info])``."""
+    n = len(ds)
+    i64a = ctypes.c_int64 * n
+    vpa = ctypes.c_void_p * n
+    pa = (refl_params_t * n)(*params)
+    infos = (refl_info_t * n)()
+    sts = (ctypes.c_int * n)()
+    st = load().refl_sign_batched(h, n, i64a(*ds), vpa(*H_ptrs), i64a(*ldhs), pa, vpa(*R_ptrs),
+                                  i64a(*ldrs), infos, sts)
+    if check:
+        _check(h, st)
+    return st, list(sts), list(infos)
+
+
+def refl_sign_batched_workspace_size(h, ds, params) -> int:
+    n = len(ds)
+    nb = ctypes.c_size_t()
+    _check(h, load().refl_sign_batched_workspace_size(h, n, (ctypes.c_int64 * n)(*ds),
+                                                      (refl_params_t * n)(*params),
+                                                      ctypes.byref(nb)))
+    return nb.value
 
 
 def refl_status_string(st: int) -> str:
@@ -304,6 +332,38 @@ def sign_apply(H, V, k, s=None, handle=None, check=True, **kw):
                                Ycm.data_ptr(), d, check=check)
     Y = Ycm.t()
     return (Y.reshape(-1) if vec else Y.contiguous()), info.as_dict(), st
+
+
+def sign_batched(Hs, ks, ss, handle=None, outs=None, check=True, **kw):
+    """R_k = sgn(H - sI) for a list of float64 device tensors in one call.
+
+    ``ks`` and ``ss`` give each problem's index and (given) shift; the other
+    keywords are make_params' and apply to every problem (``alpha``, ``tol``,
+    ``max_iter`` and ``fixed_steps`` may also be lists).  Returns
+    ``(Rs, [info_dict], [status], status)``."""
+    import torch
+    n = len(Hs)
+    if not (len(ks) == len(ss) == n) or n == 0:
+        raise ValueError("Hs, ks and ss must be non-empty and of equal length")
+    for H in Hs:
+        _dev_f64(H)
+        if H.dim() != 2 or H.shape[1] < H.shape[0] or H.stride(1) != 1:
+            raise ValueError("each H must be d x d (or d x ld) with unit column stride")
+    h = handle or Handle(Hs[0].device)
+    h.sync_stream()
+    per = {key: kw.pop(key) for key in ("alpha", "tol", "max_iter", "fixed_steps")
+           if isinstance(kw.get(key), (list, tuple))}
+    params = []
+    for p in range(n):
+        extra = {key: v[p] for key, v in per.items()}
+        params.append(make_params(ks[p], ss[p], **kw, **extra))
+    Rs = outs if outs is not None else [torch.empty((H.shape[0], H.shape[0]), dtype=torch.float64,
+                                                    device=H.device) for H in Hs]
+    st, sts, infos = refl_sign_batched(h.h, [H.shape[0] for H in Hs], [H.data_ptr() for H in Hs],
+                                       [H.stride(0) for H in Hs], params,
+                                       [R.data_ptr() for R in Rs], [R.stride(0) for R in Rs],
+                                       check=check)
+    return Rs, [i.as_dict() for i in infos], sts, st
 
 
 def estimate_shift(H, k, steps=0, seed=0, handle=None, check=True):

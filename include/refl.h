@@ -72,13 +72,19 @@ typedef enum { REFL_SHIFT_GIVEN = 0, REFL_SHIFT_LANCZOS = 1 } refl_shift_mode_t;
 typedef enum {
   REFL_SCALE_INF = 0,    /* alpha = ||H - sI||_inf (max absolute row sum) */
   REFL_SCALE_GIVEN = 1,  /* alpha = params.alpha; X_0 = (H - sI)/alpha */
-  REFL_SCALE_LANCZOS = 2 /* alpha = 1.05 rho_hat with rho_hat the Lanczos estimate of
+  REFL_SCALE_LANCZOS = 2,/* alpha = 1.05 rho_hat with rho_hat the Lanczos estimate of
                             max_i |lambda_i - s| (the spectral-norm scaling of section 4.3);
                             needs shift_mode == REFL_SHIFT_LANCZOS */
+  REFL_SCALE_FRO = 3     /* alpha = ||H - sI||_F, another cheap bound on the spectral
+                            radius of H - sI (looser than the inf-norm for spread spectra,
+                            tighter for a few dominant eigenvalues) */
 } refl_scale_mode_t;
 
 typedef struct {
-  int32_t k;            /* target index, 1 <= k <= d-1 (section 2.1) */
+  int32_t k;            /* target index, 1 <= k <= d-1 (section 2.1); 0 with a given
+                           shift: no target, the certified index j of the iterate is
+                           reported in info.index_j and R = sgn(H - sI) is returned for
+                           it (no admissibility test against k) */
   double s;             /* shift (shift_mode == REFL_SHIFT_GIVEN) */
   int32_t shift_mode;   /* refl_shift_mode_t */
   int32_t scale_mode;   /* refl_scale_mode_t */
@@ -120,6 +126,9 @@ typedef struct {
   double ms_setup, ms_bulk, ms_polish, ms_total; /* host wall-clock per phase */
   double ms_gemm;         /* params.timing: summed device time of the bulk products (HIP events) */
   int32_t gemm_launches;  /* params.timing: number of bulk product launches timed */
+  double rho;             /* Lanczos estimate of max_i |lambda_i - s| (NaN if s given) */
+  double gamma;           /* estimated scaled margin min(s - lam_k, lam_k1 - s)/alpha
+                             (section 3.2 gamma, from the Lanczos estimates; NaN if s given) */
 } refl_info_t;
 
 /* Fill *p with defaults: k = 1, s = 0, shift given, scale inf-norm, FP64,

@@ -18,7 +18,7 @@ __all__ = [
     "jacobi_eigh", "oracle_threads", "reflector_from_eig", "reflector",
     "shifted_sign_from_eig", "midpoint", "ns_poly", "ns_scalar_error",
     "ns_error_recurrence", "ns_iterate", "ns_iterates", "ns_closed_form",
-    "ns_depth_scalar", "inf_norm_shifted", "admissible", "certificates",
+    "ns_depth_scalar", "inf_norm_shifted", "fro_norm_shifted", "admissible", "certificates",
     "spectral_norm_sym", "splitmix64", "start_block", "lanczos_block_size",
     "lanczos_check_steps", "block_lanczos",
 ]
@@ -170,6 +170,13 @@ def inf_norm_shifted(H, s: float) -> float:
     scaling surrogate)."""
     A = np.asarray(H, dtype=np.float64) - s * np.eye(H.shape[0])
     return float(np.max(np.sum(np.abs(A), axis=1)))
+
+
+def fro_norm_shifted(H, s: float) -> float:
+    """||H - sI||_F, another cheap upper bound on the spectral radius of
+    H - sI (an alternative to the section 4.3 surrogates)."""
+    A = np.asarray(H, dtype=np.float64) - s * np.eye(H.shape[0])
+    return float(np.sqrt(np.sum(A * A)))
 
 
 def admissible(lam_k_hat: float, lam_k1_hat: float, eps: float, s: float):

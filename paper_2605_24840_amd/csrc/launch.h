@@ -49,9 +49,9 @@ hipError_t launch_sym_gemm_words(int words, int tile, int mode, const uint16_t* 
 // ---- set-up: H (upper triangle) -> padded full FP64 copy, scale, X_0 ----
 hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, int dp,
                                hipStream_t st);
-// scal[SC_ALPHA] = max_i sum_j |Hf_ij - s delta_ij| (only if scale_given == 0,
-// else scal[SC_ALPHA] = alpha_given); scal[SC_NONFINITE] = count of non-finite.
-hipError_t launch_scale_inf(const double* Hf, int dp, int d, double s, int scale_given,
+// scal[SC_ALPHA] = ||Hf - sI||_inf (norm 0) or ||Hf - sI||_F (norm 1), or
+// alpha_given if scale_given; scal[SC_NONFINITE] = count of non-finite.
+hipError_t launch_scale_inf(const double* Hf, int dp, int d, double s, int norm, int scale_given,
                             double alpha_given, double* rowsum, double* scal, hipStream_t st);
 // X_0 = (Hf - sI)/scal[SC_ALPHA] into FP64, FP32 or W-word storage; partial
 // traces per 256-row block into partials (nblk = dp/256 rounded up).
@@ -64,6 +64,36 @@ hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, doub
 // FP32 copy of H - sI (the operator of the inner solves).
 hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* Hs,
                               hipStream_t st);
+// Per-problem descriptor of the batched set-up and output kernels.
+struct BatchDesc {
+  const double* H;   // input, upper triangle read
+  int64_t ldh;
+  double* Hf;        // dp x dp FP64 copy of H
+  void* X[2];        // iterate pair (FP32 or FP64 per launch)
+  double* rowsum;    // 2 dp doubles: row sums, then non-finite flags
+  double* scal;      // [SC_ALPHA], [SC_NONFINITE]
+  double* R;         // output, d x d, ldr
+  int64_t ldr;
+  double s, alpha_given;
+  int d, dp, scale_given, par;  // par: which X holds the final iterate
+  int norm, pad;                // norm of the scale: 0 inf, 1 Frobenius
+};
+// Blocks of k_batch_init for one problem.
+int batch_init_blocks(int dp);
+// Set-up of every problem g < ng (the same values as launch_mirror_upper,
+// launch_scale_inf, launch_init_x0_* and launch_trace_* per problem): the
+// block ranges of the three grouped grids are given by prefix arrays
+// (ng + 1 entries) of (dp/64)^2, ceil(d/4) and batch_init_blocks(dp) blocks;
+// trace[g] = trace X_0.
+hipError_t launch_batch_setup(int fp64, const BatchDesc* desc, int ng, const int* mirror_begin,
+                              int mirror_blocks, const int* row_begin, int row_blocks,
+                              const int* init_begin, int init_blocks, double* trace,
+                              hipStream_t st);
+// Copy of X[par] of problems ids[g] (g < ng; ids == null: g) by rows:
+// to_hf == 0 writes R (d rows per problem), to_hf == 1 the FP64 copy Hf
+// (dp rows); begin is the prefix array of those row counts.
+hipError_t launch_batch_copy(int fp64, const BatchDesc* desc, const int* begin, const int* ids,
+                             int ng, int nblocks_total, int to_hf, hipStream_t st);
 // out[slot ? slot[q] : q] = sum of partials[begin[q] .. begin[q + 1]), q < nq,
 // summed in the same order as launch_reduce_sum over that range.
 hipError_t launch_reduce_ranges(const double* partials, const int* begin, const int* slot, int nq,

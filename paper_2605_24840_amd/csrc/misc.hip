@@ -13,11 +13,9 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 // Hf (dp x dp, ld dp) = symmetric matrix whose upper triangle is that of H,
 // zero outside the leading d x d block.  Block (bx, by) handles the 64 x 64
 // tile (I, J) = (by, bx); tiles with I > J are written by their mirror.
-__global__ __launch_bounds__(256) void k_mirror_upper(const double* __restrict__ H, int64_t ldh,
-                                                      int d, double* __restrict__ Hf, int dp) {
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (I > J) return;
-  __shared__ double t[64][65];
+__device__ __forceinline__ void mirror_tile(const double* __restrict__ H, int64_t ldh, int d,
+                                            double* __restrict__ Hf, int dp, int I, int J,
+                                            double (*t)[65]) {
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int i0 = I * 64, j0 = J * 64;
   for (int r = ty; r < 64; r += 4) {
@@ -38,11 +36,20 @@ __global__ __launch_bounds__(256) void k_mirror_upper(const double* __restrict__
   }
 }
 
-// rowsum[i] = sum_j |Hf_ij - s delta_ij|, one wave per row; counts non-finite.
-__global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ Hf, int dp, int d,
-                                                double s, double* __restrict__ rowsum,
-                                                double* __restrict__ nonfinite_rows) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+__global__ __launch_bounds__(256) void k_mirror_upper(const double* __restrict__ H, int64_t ldh,
+                                                      int d, double* __restrict__ Hf, int dp) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ double t[64][65];
+  mirror_tile(H, ldh, d, Hf, dp, I, J, t);
+}
+
+// rowsum[i] = sum_j |Hf_ij - s delta_ij| (norm 0) or sum_j (Hf_ij - s delta_ij)^2
+// (norm 1), one wave per row; counts non-finite entries.
+__device__ __forceinline__ void rowabs_row(const double* __restrict__ Hf, int dp, int d, double s,
+                                           int norm, double* __restrict__ rowsum,
+                                           double* __restrict__ nonfinite_rows, int row) {
+  const int lane = threadIdx.x & 63;
   if (row >= d) return;
   const double* h = Hf + (int64_t)row * dp;
   double acc = 0.0;
@@ -51,7 +58,7 @@ __global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ Hf, i
     double v = h[j];
     if (!isfinite(v)) bad = 1;
     if (j == row) v -= s;
-    acc += fabs(v);
+    acc += norm ? v * v : fabs(v);
   }
   acc = wave_sum(acc);
   const double nb = wave_sum((double)bad);
@@ -61,18 +68,26 @@ __global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ Hf, i
   }
 }
 
-// scal[SC_ALPHA] = max rowsum (or alpha_given), scal[SC_NONFINITE] = sum of flags.
-__global__ __launch_bounds__(256) void k_scale_finish(const double* __restrict__ rowsum,
-                                                      const double* __restrict__ nonfinite_rows,
-                                                      int d, int scale_given, double alpha_given,
-                                                      double* __restrict__ scal) {
-  __shared__ double red[4], redb[4];
+__global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ Hf, int dp, int d,
+                                                double s, int norm, double* __restrict__ rowsum,
+                                                double* __restrict__ nonfinite_rows) {
+  rowabs_row(Hf, dp, d, s, norm, rowsum, nonfinite_rows, blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
+// scal[SC_ALPHA] = max rowsum (norm 0: the inf-norm) or sqrt(sum rowsum)
+// (norm 1: the Frobenius norm), or alpha_given; scal[SC_NONFINITE] = sum of
+// the flags.
+__device__ __forceinline__ void scale_finish_block(const double* __restrict__ rowsum,
+                                                   const double* __restrict__ nonfinite_rows,
+                                                   int d, int norm, int scale_given,
+                                                   double alpha_given, double* __restrict__ scal,
+                                                   double* red, double* redb) {
   double m = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) {
-    m = fmax(m, rowsum[i]);
+    m = norm ? m + rowsum[i] : fmax(m, rowsum[i]);
     b += nonfinite_rows[i];
   }
-  m = wave_max(m);
+  m = norm ? wave_sum(m) : wave_max(m);
   b = wave_sum(b);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l == 0) {
@@ -81,9 +96,32 @@ __global__ __launch_bounds__(256) void k_scale_finish(const double* __restrict__
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double mx = norm ? sqrt((red[0] + red[1]) + (red[2] + red[3]))
+                           : fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     scal[SC_ALPHA] = scale_given ? alpha_given : mx;
     scal[SC_NONFINITE] = (redb[0] + redb[1]) + (redb[2] + redb[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scale_finish(const double* __restrict__ rowsum,
+                                                      const double* __restrict__ nonfinite_rows,
+                                                      int d, int norm, int scale_given,
+                                                      double alpha_given,
+                                                      double* __restrict__ scal) {
+  __shared__ double red[4], redb[4];
+  scale_finish_block(rowsum, nonfinite_rows, d, norm, scale_given, alpha_given, scal, red, redb);
+}
+
+// X = (Hf - sI)/alpha on the elements first, first + stride, ... < end.
+template <typename T>
+__device__ __forceinline__ void init_x0_elems(const double* __restrict__ Hf, int dp, int d,
+                                              double s, double inv, T* __restrict__ X,
+                                              int64_t first, int64_t end, int64_t stride) {
+  for (int64_t idx = first; idx < end; idx += stride) {
+    const int i = (int)(idx / dp), j = (int)(idx % dp);
+    double v = Hf[idx];
+    if (i == j && i < d) v -= s;
+    X[idx] = (T)(v * inv);
   }
 }
 
@@ -91,15 +129,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_init_x0(const double* __restrict__ Hf, int dp, int d,
                                                  double s, const double* __restrict__ scal,
                                                  T* __restrict__ X) {
-  const int64_t n = (int64_t)dp * dp;
   const double inv = 1.0 / scal[SC_ALPHA];
-  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * 256) {
-    const int i = (int)(idx / dp), j = (int)(idx % dp);
-    double v = Hf[idx];
-    if (i == j && i < d) v -= s;
-    X[idx] = (T)(v * inv);
-  }
+  init_x0_elems(Hf, dp, d, s, inv, X, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)dp * dp,
+                (int64_t)gridDim.x * 256);
 }
 
 template <int W>
@@ -158,13 +190,19 @@ __global__ __launch_bounds__(256) void k_reduce_ranges(const double* __restrict_
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trace(const T* __restrict__ X, int dp, int d,
-                                               double* __restrict__ scal, int slot) {
-  __shared__ double red[4];
+__device__ __forceinline__ void trace_block(const T* __restrict__ X, int dp, int d,
+                                            double* __restrict__ out, double* red) {
   double a = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) a += (double)X[(int64_t)i * dp + i];
   const double t = block_sum_256(a, red);
-  if (threadIdx.x == 0) scal[slot] = t;
+  if (threadIdx.x == 0) *out = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trace(const T* __restrict__ X, int dp, int d,
+                                               double* __restrict__ scal, int slot) {
+  __shared__ double red[4];
+  trace_block(X, dp, d, scal + slot, red);
 }
 
 template <int W>
@@ -189,6 +227,96 @@ __global__ __launch_bounds__(256) void k_copy_out(const T* __restrict__ X, int d
   const int i = blockIdx.y;
   for (int j = blockIdx.x * 256 + threadIdx.x; j < d; j += gridDim.x * 256)
     R[(int64_t)i * ldr + j] = (double)X[(int64_t)i * dp + j];
+}
+
+// ------------------------------------------------- batched set-up / output
+// Grouped forms of the kernels above over many problems (one descriptor per
+// problem): the blocks of problem ids[g] (or g) are begin[g] .. begin[g+1),
+// and each block does what the single-problem kernel's block does, so every
+// value equals the single-problem one bit for bit.
+__device__ __forceinline__ int find_group(const int* __restrict__ begin, int n, int b) {
+  int lo = 0, hi = n - 1;  // largest g with begin[g] <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int INIT_CHUNK = 2048;  // elements per block of k_batch_init
+
+// Blocks: (dp/64)^2 per problem, tile (I, J) = (local / nt, local % nt).
+__global__ __launch_bounds__(256) void k_batch_mirror(const BatchDesc* __restrict__ desc,
+                                                      const int* __restrict__ begin,
+                                                      const int* __restrict__ ids, int ng) {
+  const int g = find_group(begin, ng, blockIdx.x);
+  const BatchDesc q = desc[ids ? ids[g] : g];
+  const int local = blockIdx.x - begin[g], nt = q.dp / 64;
+  const int I = local / nt, J = local % nt;
+  if (I > J) return;
+  __shared__ double t[64][65];
+  mirror_tile(q.H, q.ldh, q.d, q.Hf, q.dp, I, J, t);
+}
+
+// Blocks: ceil(d / 4) per problem (one wave per row).
+__global__ __launch_bounds__(256) void k_batch_rowabs(const BatchDesc* __restrict__ desc,
+                                                      const int* __restrict__ begin,
+                                                      const int* __restrict__ ids, int ng) {
+  const int g = find_group(begin, ng, blockIdx.x);
+  const BatchDesc q = desc[ids ? ids[g] : g];
+  const int local = blockIdx.x - begin[g];
+  rowabs_row(q.Hf, q.dp, q.d, q.s, q.norm, q.rowsum, q.rowsum + q.dp,
+             local * 4 + (threadIdx.x >> 6));
+}
+
+// One block per problem.
+__global__ __launch_bounds__(256) void k_batch_scale_finish(const BatchDesc* __restrict__ desc,
+                                                            const int* __restrict__ ids) {
+  __shared__ double red[4], redb[4];
+  const BatchDesc q = desc[ids ? ids[blockIdx.x] : blockIdx.x];
+  scale_finish_block(q.rowsum, q.rowsum + q.dp, q.d, q.norm, q.scale_given, q.alpha_given, q.scal,
+                     red, redb);
+}
+
+// Blocks: ceil(dp^2 / INIT_CHUNK) per problem; X_0 into X[0].
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_init(const BatchDesc* __restrict__ desc,
+                                                    const int* __restrict__ begin,
+                                                    const int* __restrict__ ids, int ng) {
+  const int g = find_group(begin, ng, blockIdx.x);
+  const BatchDesc q = desc[ids ? ids[g] : g];
+  const int64_t first = (int64_t)(blockIdx.x - begin[g]) * INIT_CHUNK;
+  const int64_t end = min(first + INIT_CHUNK, (int64_t)q.dp * q.dp);
+  init_x0_elems(q.Hf, q.dp, q.d, q.s, 1.0 / q.scal[SC_ALPHA], reinterpret_cast<T*>(q.X[0]),
+                first + threadIdx.x, end, 256);
+}
+
+// One block per problem: out[p] = trace of X[par].
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_trace(const BatchDesc* __restrict__ desc,
+                                                     const int* __restrict__ ids,
+                                                     double* __restrict__ out) {
+  __shared__ double red[4];
+  const int p = ids ? ids[blockIdx.x] : blockIdx.x;
+  const BatchDesc q = desc[p];
+  trace_block(reinterpret_cast<const T*>(q.X[q.par]), q.dp, q.d, out + p, red);
+}
+
+// Blocks: one row each.  to_hf == 0: R = X[par] (d x d, ldr); to_hf == 1:
+// Hf = X[par] over the whole padded dp x dp matrix (FP64 copy).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_copy(const BatchDesc* __restrict__ desc,
+                                                    const int* __restrict__ begin,
+                                                    const int* __restrict__ ids, int ng,
+                                                    int to_hf) {
+  const int g = find_group(begin, ng, blockIdx.x);
+  const BatchDesc q = desc[ids ? ids[g] : g];
+  const int i = blockIdx.x - begin[g];
+  const T* X = reinterpret_cast<const T*>(q.X[q.par]) + (int64_t)i * q.dp;
+  const int n = to_hf ? q.dp : q.d;
+  double* dst = to_hf ? q.Hf + (int64_t)i * q.dp : q.R + (int64_t)i * q.ldr;
+  for (int j = threadIdx.x; j < n; j += 256) dst[j] = (double)X[j];
 }
 
 // ------------------------------------------------------- thin products
@@ -647,12 +775,13 @@ hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, 
   return hipGetLastError();
 }
 
-hipError_t launch_scale_inf(const double* Hf, int dp, int d, double s, int scale_given,
+hipError_t launch_scale_inf(const double* Hf, int dp, int d, double s, int norm, int scale_given,
                             double alpha_given, double* rowsum, double* scal, hipStream_t st) {
   double* flags = rowsum + dp;
-  hipLaunchKernelGGL(k_rowabs, dim3(nblocks(d, 4)), dim3(256), 0, st, Hf, dp, d, s, rowsum, flags);
-  hipLaunchKernelGGL(k_scale_finish, dim3(1), dim3(256), 0, st, rowsum, flags, d, scale_given,
-                     alpha_given, scal);
+  hipLaunchKernelGGL(k_rowabs, dim3(nblocks(d, 4)), dim3(256), 0, st, Hf, dp, d, s, norm, rowsum,
+                     flags);
+  hipLaunchKernelGGL(k_scale_finish, dim3(1), dim3(256), 0, st, rowsum, flags, d, norm,
+                     scale_given, alpha_given, scal);
   return hipGetLastError();
 }
 
@@ -729,6 +858,44 @@ hipError_t launch_copy_out_f64(const double* X, int dp, int d, double* R, int64_
 hipError_t launch_copy_out_f32(const float* X, int dp, int d, double* R, int64_t ldr,
                                hipStream_t st) {
   hipLaunchKernelGGL(k_copy_out<float>, dim3(nblocks(d, 256), d), dim3(256), 0, st, X, dp, d, R, ldr);
+  return hipGetLastError();
+}
+
+int batch_init_blocks(int dp) { return (int)(((int64_t)dp * dp + INIT_CHUNK - 1) / INIT_CHUNK); }
+
+hipError_t launch_batch_setup(int fp64, const BatchDesc* desc, int ng, const int* mirror_begin,
+                              int mirror_blocks, const int* row_begin, int row_blocks,
+                              const int* init_begin, int init_blocks, double* trace,
+                              hipStream_t st) {
+  if (ng <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_mirror, dim3(mirror_blocks), dim3(256), 0, st, desc, mirror_begin,
+                     (const int*)nullptr, ng);
+  hipLaunchKernelGGL(k_batch_rowabs, dim3(row_blocks), dim3(256), 0, st, desc, row_begin,
+                     (const int*)nullptr, ng);
+  hipLaunchKernelGGL(k_batch_scale_finish, dim3(ng), dim3(256), 0, st, desc, (const int*)nullptr);
+  if (fp64) {
+    hipLaunchKernelGGL(k_batch_init<double>, dim3(init_blocks), dim3(256), 0, st, desc,
+                       init_begin, (const int*)nullptr, ng);
+    hipLaunchKernelGGL(k_batch_trace<double>, dim3(ng), dim3(256), 0, st, desc,
+                       (const int*)nullptr, trace);
+  } else {
+    hipLaunchKernelGGL(k_batch_init<float>, dim3(init_blocks), dim3(256), 0, st, desc,
+                       init_begin, (const int*)nullptr, ng);
+    hipLaunchKernelGGL(k_batch_trace<float>, dim3(ng), dim3(256), 0, st, desc,
+                       (const int*)nullptr, trace);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_copy(int fp64, const BatchDesc* desc, const int* begin, const int* ids,
+                             int ng, int nblocks_total, int to_hf, hipStream_t st) {
+  if (ng <= 0 || nblocks_total <= 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL(k_batch_copy<double>, dim3(nblocks_total), dim3(256), 0, st, desc, begin,
+                       ids, ng, to_hf);
+  else
+    hipLaunchKernelGGL(k_batch_copy<float>, dim3(nblocks_total), dim3(256), 0, st, desc, begin,
+                       ids, ng, to_hf);
   return hipGetLastError();
 }
 

@@ -254,12 +254,14 @@ refl_status_t ensure_workspace(refl_handle_t h, size_t need, void** out) {
 refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
   if (!p) return fail(h, REFL_ERR_INVALID_ARG, "params is NULL");
   if (d < 2 || d > (int64_t)1 << 16) return fail(h, REFL_ERR_INVALID_ARG, "d=%lld outside 2..65536", (long long)d);
-  if (p->k < 1 || p->k > d - 1) return fail(h, REFL_ERR_INVALID_ARG, "k=%d outside 1..d-1", p->k);
+  if (p->k < 0 || p->k > d - 1) return fail(h, REFL_ERR_INVALID_ARG, "k=%d outside 0..d-1", p->k);
+  if (p->k == 0 && p->shift_mode != REFL_SHIFT_GIVEN)
+    return fail(h, REFL_ERR_INVALID_ARG, "k=0 (report the index) needs a given shift");
   if (p->precision < 0 || p->precision > 2) return fail(h, REFL_ERR_INVALID_ARG, "bad precision");
   if (p->shift_mode != REFL_SHIFT_GIVEN && p->shift_mode != REFL_SHIFT_LANCZOS)
     return fail(h, REFL_ERR_INVALID_ARG, "bad shift_mode");
   if (p->scale_mode != REFL_SCALE_INF && p->scale_mode != REFL_SCALE_GIVEN &&
-      p->scale_mode != REFL_SCALE_LANCZOS)
+      p->scale_mode != REFL_SCALE_LANCZOS && p->scale_mode != REFL_SCALE_FRO)
     return fail(h, REFL_ERR_INVALID_ARG, "bad scale_mode");
   if (p->scale_mode == REFL_SCALE_LANCZOS && p->shift_mode != REFL_SHIFT_LANCZOS)
     return fail(h, REFL_ERR_INVALID_ARG, "scale_mode LANCZOS needs shift_mode LANCZOS");
@@ -755,6 +757,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   std::memset(&inf, 0, sizeof(inf));
   inf.lam_k = inf.lam_k1 = inf.eps = inf.margin = NaN;
   inf.commutator_fro = inf.dk_bound = NaN;
+  inf.rho = inf.gamma = NaN;
   inf.index_j = -1;
   HIPCHK(hipSetDevice(h->device));
   Work w;
@@ -788,11 +791,14 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       return rs;
     }
     p.s = lr.s;
+    inf.rho = lr.rho;
     if (p.scale_mode == REFL_SCALE_LANCZOS) alpha_given = 1.05 * lr.rho;
   }
   const double s = p.s;
   inf.s = s;
-  HIPCHK(launch_scale_inf(w.Hf, w.dp, (int)d, s, p.scale_mode != REFL_SCALE_INF, alpha_given,
+  HIPCHK(launch_scale_inf(w.Hf, w.dp, (int)d, s, p.scale_mode == REFL_SCALE_FRO,
+                          p.scale_mode == REFL_SCALE_GIVEN || p.scale_mode == REFL_SCALE_LANCZOS,
+                          alpha_given,
                           w.rowsum, w.scal, st));
   const int W = p.words;
   if (p.precision == REFL_PREC_FP64) {
@@ -811,6 +817,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   inf.alpha = hsc[SC_ALPHA];
   if (!(inf.alpha > 0.0) || !std::isfinite(inf.alpha))
     return fail(h, REFL_ERR_NOT_FINITE, "scale alpha=%g is not a positive finite number", inf.alpha);
+  if (p.shift_mode == REFL_SHIFT_LANCZOS)
+    inf.gamma = std::min(s - inf.lam_k, inf.lam_k1 - s) / inf.alpha;
   const double t_setup = now_ms();
 
   // ---- bulk ----
@@ -1023,17 +1031,42 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   // ---- output ----
   refl_status_t out_status = REFL_OK;
   if (!b.converged) out_status = fail(h, REFL_ERR_NOT_CONVERGED, "no convergence after %d steps (resid %.3e)", b.steps, b.resid);
-  if (!fixed && inf.index_j >= 0 && inf.index_j != p.k)
+  if (!fixed && p.k > 0 && inf.index_j >= 0 && inf.index_j != p.k)
     out_status = fail(h, REFL_ERR_NOT_ADMISSIBLE,
                       "index certificate found %d negative eigenvalues of H - sI, not k=%d",
                       inf.index_j, p.k);
   const int c = b.cur;
   if (p.precision == REFL_PREC_MIXED && !fixed) {
-    if (inf.index_j != p.k) {
+    if (inf.index_j < 0 || (p.k > 0 && inf.index_j != p.k)) {
       if (out_status == REFL_OK)
         out_status = fail(h, REFL_ERR_NOT_ADMISSIBLE, "index certificate did not hold for k=%d", p.k);
       if (info) *info = inf;
       return out_status;
+    }
+    if (p.k == 0) {
+      // No target index: the certified one.  With j = 0 or d, H - sI is
+      // definite and R = sgn(H - sI) = +I or -I exactly.
+      const int j = inf.index_j;
+      if (j == 0 || j == d) {
+        const double sg = j == 0 ? 1.0 : -1.0;
+        if (dR) {
+          HIPCHK(form_reflector(w.V, w.dp, 0, (int)d, dR, ldr, st));
+          if (sg < 0.0) HIPCHK(lincomb((int)d, (int)d, 0.0, dR, ldr, -1.0, dR, ldr, st));
+        } else {
+          for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
+            const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
+            HIPCHK(lincomb((int)d, nb, sg, dV + c0 * ldv, ldv, 0.0, dY + c0 * ldy, ldy, st));
+          }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        if (info) *info = inf;
+        return out_status;
+      }
+      if (j > MAXB) {
+        if (info) *info = inf;
+        return fail(h, REFL_ERR_UNSUPPORTED, "certified index %d: MIXED correction supports up to %d", j, MAXB);
+      }
+      p.k = j;
     }
     double* V = nullptr;
     refl_status_t pr = polish(h, w, p, s, w.Xw[c], &V, &inf);
@@ -1086,32 +1119,44 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
 
 // ---------------------------------------------------------------- batched
 // Many independent problems (refl_sign_batched).  Each problem keeps its own
-// FP64 copy of H, iterate pair and N; the Newton-Schulz products of every
-// problem still iterating run as ONE grouped launch per product, over the
+// FP64 copy of H, iterate pair and N.  Set-up and output run as grouped
+// launches over all problems; the Newton-Schulz products of every problem
+// still iterating run as ONE grouped launch per product, over the
 // concatenated upper-tile lists.  Tile partials land in per-problem ranges
-// laid out exactly as refl_sign's, and each range is reduced in
-// refl_sign's order, so every problem takes the same steps and returns the
-// same R, bit for bit, as a refl_sign call with its parameters.
+// laid out exactly as refl_sign's, and each range is reduced in refl_sign's
+// order, so every problem takes the same steps and returns the same R, bit
+// for bit, as a refl_sign call with its parameters.
+//
+// Host/device overlap: after the first product of step m the host reads the
+// residuals while the device already runs the second product of step m for
+// every problem of the step (for a problem that stops at m that product is
+// discarded: it writes the other iterate of the pair), so the device does not
+// wait for the host's stopping decisions.
 struct BatchProb {
   int d = 0, dp = 0, ntiles = 0;
   double* Hf = nullptr;   // FP64 copy of H; FP32 after the bulk: FP64 copy of the iterate
   void* X[2] = {nullptr, nullptr};
   void* N = nullptr;
   double* N64 = nullptr;  // FP32: N of the FP64 certificate product
+  double* rowsum = nullptr;
   double* scal = nullptr; // SC_ALPHA, SC_NONFINITE of this problem
 };
+
+constexpr int BSC = 2;  // scalar slots per problem (SC_ALPHA, SC_NONFINITE)
 
 struct BatchWork {
   std::vector<BatchProb> pr;
   int ttot = 0, maxdp = 0;
-  double *rowsum = nullptr, *scal = nullptr, *partials = nullptr;
+  double *scal = nullptr, *partials = nullptr;
   GemmProblem *probs = nullptr, *probs64 = nullptr;
-  int4 *tiles = nullptr, *tiles_fin = nullptr;
-  int *begin = nullptr, *slot = nullptr, *begin_fin = nullptr, *slot_fin = nullptr;
+  BatchDesc* desc = nullptr;
+  int4* tiles[3] = {nullptr, nullptr, nullptr};  // two step lists, the final list
+  int* begin[3] = {nullptr, nullptr, nullptr};
+  int* slot[3] = {nullptr, nullptr, nullptr};
+  int* sbeg = nullptr;  // set-up prefix arrays: mirror, rows, init (3 (n + 1))
+  int* cbeg = nullptr;  // output prefix arrays: R rows, Hf rows (2 (n + 1))
   double *res = nullptr, *trace = nullptr, *cert = nullptr;
 };
-
-constexpr int BSC = 2;  // scalar slots per problem (SC_ALPHA, SC_NONFINITE)
 
 size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, bool fp64) {
   Carve c(base);
@@ -1134,18 +1179,20 @@ size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, bool
     q.X[1] = c.take<char>(es * n2);
     q.N = c.take<char>(es * n2);
     q.N64 = fp64 ? nullptr : c.take<double>(n2);
+    q.rowsum = c.take<double>(2 * (size_t)q.dp);
     q.scal = bw.scal ? bw.scal + (size_t)BSC * p : nullptr;
   }
-  bw.rowsum = c.take<double>(2 * (size_t)bw.maxdp);
   bw.probs = c.take<GemmProblem>(nprob);
   bw.probs64 = c.take<GemmProblem>(nprob);
-  bw.tiles = c.take<int4>(bw.ttot);
-  bw.tiles_fin = c.take<int4>(bw.ttot);
+  bw.desc = c.take<BatchDesc>(nprob);
+  for (int b = 0; b < 3; ++b) {
+    bw.tiles[b] = c.take<int4>(bw.ttot);
+    bw.begin[b] = c.take<int>(nprob + 1);
+    bw.slot[b] = c.take<int>(nprob);
+  }
   bw.partials = c.take<double>(bw.ttot);
-  bw.begin = c.take<int>(nprob + 1);
-  bw.slot = c.take<int>(nprob);
-  bw.begin_fin = c.take<int>(nprob + 1);
-  bw.slot_fin = c.take<int>(nprob);
+  bw.sbeg = c.take<int>(3 * ((size_t)nprob + 1));
+  bw.cbeg = c.take<int>(2 * ((size_t)nprob + 1));
   bw.res = c.take<double>(nprob);
   bw.trace = c.take<double>(nprob);
   bw.cert = c.take<double>(nprob);
@@ -1153,28 +1200,32 @@ size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, bool
 }
 
 // Host staging of the batched solve: one pinned block, carved like the
-// device workspace.
+// device workspace (each buffer is the source or target of one copy).
 struct BatchPin {
   GemmProblem *probs, *probs64;
+  BatchDesc* desc;
   double *scal, *res, *trace, *cert;
-  int4 *tiles, *tiles_fin;
-  int *begin, *slot, *begin_fin, *slot_fin;
+  int4* tiles[3];
+  int *begin[3], *slot[3];
+  int *sbeg, *cbeg;
 };
 
 size_t batch_pin_layout(BatchPin& bp, void* base, int nprob, int ttot) {
   Carve c(base);
   bp.probs = c.take<GemmProblem>(nprob);
   bp.probs64 = c.take<GemmProblem>(nprob);
+  bp.desc = c.take<BatchDesc>(nprob);
   bp.scal = c.take<double>((size_t)BSC * nprob);
   bp.res = c.take<double>(nprob);
   bp.trace = c.take<double>(nprob);
   bp.cert = c.take<double>(nprob);
-  bp.tiles = c.take<int4>(ttot);
-  bp.tiles_fin = c.take<int4>(ttot);
-  bp.begin = c.take<int>(nprob + 1);
-  bp.slot = c.take<int>(nprob);
-  bp.begin_fin = c.take<int>(nprob + 1);
-  bp.slot_fin = c.take<int>(nprob);
+  for (int b = 0; b < 3; ++b) {
+    bp.tiles[b] = c.take<int4>(ttot);
+    bp.begin[b] = c.take<int>(nprob + 1);
+    bp.slot[b] = c.take<int>(nprob);
+  }
+  bp.sbeg = c.take<int>(3 * ((size_t)nprob + 1));
+  bp.cbeg = c.take<int>(2 * ((size_t)nprob + 1));
   return c.off + 256;
 }
 
@@ -1263,6 +1314,8 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     h->batch_pin_bytes = pin_need;
   }
   batch_pin_layout(bp, h->batch_pin, nprob, bw.ttot);
+  if (h->lz_ev[0] == nullptr) HIPCHK(hipEventCreateWithFlags(&h->lz_ev[0], hipEventDisableTiming));
+  hipEvent_t ev_res = h->lz_ev[0];
 
   std::vector<refl_info_t> inf(nprob);
   std::vector<refl_status_t> pst(nprob, REFL_OK);
@@ -1271,53 +1324,57 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     refl_info_t& f = inf[p];
     f.lam_k = f.lam_k1 = f.eps = f.margin = NaN;
     f.commutator_fro = f.dk_bound = NaN;
-    f.resid_fro = f.trace = NaN;
+    f.resid_fro = f.trace = f.rho = f.gamma = NaN;
     f.index_j = -1;
     f.s = params[p].s;
   }
-  auto finish = [&](refl_status_t call_status) -> refl_status_t {
-    if (info)
-      for (int p = 0; p < nprob; ++p) info[p] = inf[p];
-    if (status)
-      for (int p = 0; p < nprob; ++p) status[p] = pst[p];
-    return call_status;
-  };
 
-  // ---- set-up (per problem) ----
-  {
-    std::vector<GemmProblem> g(nprob), g64(nprob);
-    for (int p = 0; p < nprob; ++p) {
-      const BatchProb& q = bw.pr[p];
-      g[p].X[0] = q.X[0];
-      g[p].X[1] = q.X[1];
-      g[p].N = q.N;
-      g64[p].X[0] = g64[p].X[1] = q.Hf;
-      g64[p].N = q.N64;
-      g[p].ld = g64[p].ld = q.dp;
-      g[p].d = g64[p].d = q.d;
-      g[p].dp = g64[p].dp = q.dp;
-      g[p].pad = g64[p].pad = 0;
-    }
-    const size_t gb = sizeof(GemmProblem) * nprob;
-    std::memcpy(bp.probs, g.data(), gb);
-    std::memcpy(bp.probs64, g64.data(), gb);
-    HIPCHK(hipMemcpyAsync(bw.probs, bp.probs, gb, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(bw.probs64, bp.probs64, gb, hipMemcpyHostToDevice, st));
-  }
+  // ---- set-up: descriptors, then five grouped launches ----
+  int* mb = bp.sbeg;
+  int* rb = mb + (nprob + 1);
+  int* ib = rb + (nprob + 1);
+  mb[0] = rb[0] = ib[0] = 0;
   for (int p = 0; p < nprob; ++p) {
     const BatchProb& q = bw.pr[p];
-    const refl_params_t& pp = params[p];
-    HIPCHK(launch_mirror_upper(dH[p], ldh[p], q.d, q.Hf, q.dp, st));
-    HIPCHK(launch_scale_inf(q.Hf, q.dp, q.d, pp.s, pp.scale_mode != REFL_SCALE_INF, pp.alpha,
-                            bw.rowsum, q.scal, st));
-    if (fp64) {
-      HIPCHK(launch_init_x0_f64(q.Hf, q.dp, q.d, pp.s, q.scal, (double*)q.X[0], st));
-      HIPCHK(launch_trace_f64((const double*)q.X[0], q.dp, q.d, bw.trace, p, st));
-    } else {
-      HIPCHK(launch_init_x0_f32(q.Hf, q.dp, q.d, pp.s, q.scal, (float*)q.X[0], st));
-      HIPCHK(launch_trace_f32((const float*)q.X[0], q.dp, q.d, bw.trace, p, st));
-    }
+    GemmProblem& g = bp.probs[p];
+    GemmProblem& g64 = bp.probs64[p];
+    g.X[0] = q.X[0];
+    g.X[1] = q.X[1];
+    g.N = q.N;
+    g64.X[0] = g64.X[1] = q.Hf;
+    g64.N = q.N64;
+    g.ld = g64.ld = q.dp;
+    g.d = g64.d = q.d;
+    g.dp = g64.dp = q.dp;
+    g.pad = g64.pad = 0;
+    BatchDesc& e = bp.desc[p];
+    e.H = dH[p];
+    e.ldh = ldh[p];
+    e.Hf = q.Hf;
+    e.X[0] = q.X[0];
+    e.X[1] = q.X[1];
+    e.rowsum = q.rowsum;
+    e.scal = q.scal;
+    e.R = dR[p];
+    e.ldr = ldr[p];
+    e.s = params[p].s;
+    e.alpha_given = params[p].alpha;
+    e.d = q.d;
+    e.dp = q.dp;
+    e.scale_given = params[p].scale_mode == REFL_SCALE_GIVEN;
+    e.norm = params[p].scale_mode == REFL_SCALE_FRO;
+    e.par = 0;
+    e.pad = 0;
+    mb[p + 1] = mb[p] + (q.dp / 64) * (q.dp / 64);
+    rb[p + 1] = rb[p] + (q.d + 3) / 4;
+    ib[p + 1] = ib[p] + batch_init_blocks(q.dp);
   }
+  HIPCHK(hipMemcpyAsync(bw.probs, bp.probs, sizeof(GemmProblem) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bw.probs64, bp.probs64, sizeof(GemmProblem) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bw.desc, bp.desc, sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bw.sbeg, bp.sbeg, sizeof(int) * 3 * (nprob + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_batch_setup(fp64, bw.desc, nprob, bw.sbeg, mb[nprob], bw.sbeg + (nprob + 1),
+                            rb[nprob], bw.sbeg + 2 * (nprob + 1), ib[nprob], bw.trace, st));
   HIPCHK(hipMemcpyAsync(bp.scal, bw.scal, sizeof(double) * BSC * nprob, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(bp.trace, bw.trace, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1326,31 +1383,16 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   for (int p = 0; p < nprob; ++p) {
     inf[p].alpha = bp.scal[BSC * p + SC_ALPHA];
     trace_cur[p] = bp.trace[p];
-    if (bp.scal[BSC * p + SC_NONFINITE] > 0.0) {
+    if (bp.scal[BSC * p + SC_NONFINITE] > 0.0 || !(inf[p].alpha > 0.0) ||
+        !std::isfinite(inf[p].alpha))
       pst[p] = REFL_ERR_NOT_FINITE;
-    } else if (!(inf[p].alpha > 0.0) || !std::isfinite(inf[p].alpha)) {
-      pst[p] = REFL_ERR_NOT_FINITE;
-    } else {
+    else
       cur.push_back(p);
-    }
   }
   const double t_setup = now_ms();
 
-  // ---- bulk: one grouped product per half-step for all live problems ----
+  // ---- bulk ----
   const int fprec = fp64 ? 1 : 0;
-  std::vector<std::vector<double>> hist(nprob);
-  std::vector<char> converged(nprob, 0);
-  int nt_cur = batch_tiles(bw, cur, bp.tiles, bp.begin, bp.slot);
-  auto upload_step = [&](int nq) -> refl_status_t {
-    HIPCHK(hipMemcpyAsync(bw.tiles, bp.tiles, sizeof(int4) * nt_cur, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(bw.begin, bp.begin, sizeof(int) * (nq + 1), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(bw.slot, bp.slot, sizeof(int) * nq, hipMemcpyHostToDevice, st));
-    return REFL_OK;
-  };
-  if (!cur.empty()) {
-    rs = upload_step((int)cur.size());
-    if (rs != REFL_OK) return rs;
-  }
   const bool timing = params[0].timing != 0;
   size_t nev = 0;
   auto ev_pair = [&]() -> hipError_t {
@@ -1362,23 +1404,48 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     }
     return hipSuccess;
   };
-  for (int m = 0; !cur.empty(); ++m) {
-    const int par = m & 1;
-    const int nq = (int)cur.size();
+  auto grouped = [&](int mode, int lb, int nt, int par) -> refl_status_t {
     if (timing) {
       HIPCHK(ev_pair());
       HIPCHK(hipEventRecord(h->ev[2 * nev], st));
     }
-    HIPCHK(launch_sym_gemm_grouped(fprec, GEMM_RESIDUAL, bw.probs, bw.tiles, nt_cur, par,
-                                   bw.partials, st));
+    HIPCHK(launch_sym_gemm_grouped(fprec, mode, bw.probs, bw.tiles[lb], nt, par, bw.partials, st));
     if (timing) HIPCHK(hipEventRecord(h->ev[2 * nev++ + 1], st));
-    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin, bw.slot, nq, bw.res, st));
+    return REFL_OK;
+  };
+  // Step list in buffer lb: build and upload.
+  auto upload_list = [&](int lb, const std::vector<int>& ids) -> int {
+    const int nt = batch_tiles(bw, ids, bp.tiles[lb], bp.begin[lb], bp.slot[lb]);
+    const int nq = (int)ids.size();
+    if (hipMemcpyAsync(bw.tiles[lb], bp.tiles[lb], sizeof(int4) * nt, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(bw.begin[lb], bp.begin[lb], sizeof(int) * (nq + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(bw.slot[lb], bp.slot[lb], sizeof(int) * nq, hipMemcpyHostToDevice, st) != hipSuccess)
+      return -1;
+    return nt;
+  };
+  std::vector<std::vector<double>> hist(nprob);
+  std::vector<char> converged(nprob, 0);
+  std::vector<int> done;  // problems that stopped with an iterate to return
+  int lb = 0;
+  int nt_cur = cur.empty() ? 0 : upload_list(lb, cur);
+  if (nt_cur < 0) return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
+  for (int m = 0; !cur.empty(); ++m) {
+    const int par = m & 1;
+    const int nq = (int)cur.size();
+    rs = grouped(GEMM_RESIDUAL, lb, nt_cur, par);
+    if (rs != REFL_OK) return rs;
+    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[lb], bw.slot[lb], nq, bw.res, st));
     HIPCHK(hipMemcpyAsync(bp.res, bw.res, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
     if (m > 0)
       HIPCHK(hipMemcpyAsync(bp.trace, bw.trace, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipEventRecord(ev_res, st));
+    // Second product of step m for every problem of the step (see above).
+    rs = grouped(GEMM_UPDATE, lb, nt_cur, par);
+    if (rs != REFL_OK) return rs;
+    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[lb], bw.slot[lb], nq, bw.trace, st));
+    HIPCHK(hipEventSynchronize(ev_res));
     // Stopping rule of refl_sign (FP64 / FP32), problem by problem.
-    std::vector<int> next, fin;
+    std::vector<int> next;
     for (int p : cur) {
       const refl_params_t& pp = params[p];
       if (m > 0) trace_cur[p] = bp.trace[p];
@@ -1410,51 +1477,47 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
         }
       }
       if (stop) {
-        fin.push_back(p);
+        bp.desc[p].par = par;
+        done.push_back(p);
       } else {
         next.push_back(p);
-      }
-    }
-    // Output of the problems that stopped at this iterate.  FP32: the
-    // certificate ||X^2 - I||_F is recomputed from the iterate in FP64.
-    if (!fin.empty()) {
-      for (int p : fin) {
-        const BatchProb& q = bw.pr[p];
-        if (fp64) {
-          HIPCHK(launch_copy_out_f64((const double*)q.X[par], q.dp, q.d, dR[p], ldr[p], st));
-        } else {
-          HIPCHK(launch_copy_out_f32((const float*)q.X[par], q.dp, q.d, dR[p], ldr[p], st));
-          HIPCHK(launch_copy_out_f32((const float*)q.X[par], q.dp, q.dp, q.Hf, q.dp, st));
-        }
-      }
-      if (!fp64) {
-        const int ntf = batch_tiles(bw, fin, bp.tiles_fin, bp.begin_fin, bp.slot_fin);
-        const int nf = (int)fin.size();
-        HIPCHK(hipMemcpyAsync(bw.tiles_fin, bp.tiles_fin, sizeof(int4) * ntf, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(bw.begin_fin, bp.begin_fin, sizeof(int) * (nf + 1), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(bw.slot_fin, bp.slot_fin, sizeof(int) * nf, hipMemcpyHostToDevice, st));
-        HIPCHK(launch_sym_gemm_grouped(1, GEMM_RESIDUAL, bw.probs64, bw.tiles_fin, ntf, 0,
-                                       bw.partials, st));
-        HIPCHK(launch_reduce_ranges(bw.partials, bw.begin_fin, bw.slot_fin, nf, bw.cert, st));
       }
     }
     if (next.size() != cur.size()) {
       cur.swap(next);
       if (cur.empty()) break;
-      nt_cur = batch_tiles(bw, cur, bp.tiles, bp.begin, bp.slot);
-      rs = upload_step((int)cur.size());
-      if (rs != REFL_OK) return rs;
+      lb ^= 1;
+      nt_cur = upload_list(lb, cur);
+      if (nt_cur < 0) return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
     }
-    if (timing) {
-      HIPCHK(ev_pair());
-      HIPCHK(hipEventRecord(h->ev[2 * nev], st));
-    }
-    HIPCHK(launch_sym_gemm_grouped(fprec, GEMM_UPDATE, bw.probs, bw.tiles, nt_cur, par,
-                                   bw.partials, st));
-    if (timing) HIPCHK(hipEventRecord(h->ev[2 * nev++ + 1], st));
-    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin, bw.slot, (int)cur.size(), bw.trace, st));
   }
-  HIPCHK(hipMemcpyAsync(bp.cert, bw.cert, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
+
+  // ---- output: FP32 certificate in FP64, then R, for every problem in done ----
+  std::sort(done.begin(), done.end());
+  const int nd = (int)done.size();
+  if (nd > 0) {
+    int* rbeg = bp.cbeg;
+    int* hbeg = rbeg + (nprob + 1);
+    rbeg[0] = hbeg[0] = 0;
+    for (int q = 0; q < nd; ++q) {
+      rbeg[q + 1] = rbeg[q] + bw.pr[done[q]].d;
+      hbeg[q + 1] = hbeg[q] + bw.pr[done[q]].dp;
+    }
+    HIPCHK(hipMemcpyAsync(bw.desc, bp.desc, sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bw.cbeg, bp.cbeg, sizeof(int) * 2 * (nprob + 1), hipMemcpyHostToDevice, st));
+    const int nt_fin = batch_tiles(bw, done, bp.tiles[2], bp.begin[2], bp.slot[2]);
+    HIPCHK(hipMemcpyAsync(bw.tiles[2], bp.tiles[2], sizeof(int4) * nt_fin, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bw.begin[2], bp.begin[2], sizeof(int) * (nd + 1), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bw.slot[2], bp.slot[2], sizeof(int) * nd, hipMemcpyHostToDevice, st));
+    if (!fp64) {
+      HIPCHK(launch_batch_copy(0, bw.desc, bw.cbeg + (nprob + 1), bw.slot[2], nd, hbeg[nd], 1, st));
+      HIPCHK(launch_sym_gemm_grouped(1, GEMM_RESIDUAL, bw.probs64, bw.tiles[2], nt_fin, 0,
+                                     bw.partials, st));
+      HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[2], bw.slot[2], nd, bw.cert, st));
+      HIPCHK(hipMemcpyAsync(bp.cert, bw.cert, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(launch_batch_copy(fprec, bw.desc, bw.cbeg, bw.slot[2], nd, rbeg[nd], 0, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   double ms_gemm = 0.0;
   if (timing) {
@@ -1482,7 +1545,7 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
       if (!fp64) f.resid_fro = std::sqrt(std::fmax(bp.cert[p], 0.0));
       f.index_j = index_certificate(d[p], f.resid_fro, f.trace);
       if (!converged[p]) pst[p] = REFL_ERR_NOT_CONVERGED;
-      if (pp.fixed_steps == 0 && f.index_j >= 0 && f.index_j != pp.k)
+      if (pp.fixed_steps == 0 && pp.k > 0 && f.index_j >= 0 && f.index_j != pp.k)
         pst[p] = REFL_ERR_NOT_ADMISSIBLE;
     }
     if (pst[p] != REFL_OK && first == REFL_OK) {
@@ -1497,7 +1560,11 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
              f.index_j, pp.k);
     }
   }
-  return finish(first);
+  if (info)
+    for (int p = 0; p < nprob; ++p) info[p] = inf[p];
+  if (status)
+    for (int p = 0; p < nprob; ++p) status[p] = pst[p];
+  return first;
 }
 
 }  // namespace

@@ -21,7 +21,7 @@ STATUS = {0: "REFL_OK", 1: "REFL_ERR_INVALID_ARG", 2: "REFL_ERR_DEVICE", 3: "REF
  REFL_ERR_NOT_ADMISSIBLE, REFL_ERR_NO_GAP, REFL_ERR_NOT_FINITE, REFL_ERR_UNSUPPORTED) = range(1, 9)
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 SHIFT = {"given": 0, "lanczos": 1}
-SCALE = {"inf": 0, "given": 1, "lanczos": 2}
+SCALE = {"inf": 0, "given": 1, "lanczos": 2, "fro": 3}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
@@ -51,7 +51,8 @@ class refl_info_t(ctypes.Structure):
                 ("dk_bound", ctypes.c_double), ("ms_setup", ctypes.c_double),
                 ("ms_bulk", ctypes.c_double), ("ms_polish", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_gemm", ctypes.c_double),
-                ("gemm_launches", ctypes.c_int32)]
+                ("gemm_launches", ctypes.c_int32), ("rho", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -246,8 +247,9 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
                 alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
                 timing=False, scale=None):
     """refl_params_t from keyword arguments.  s=None estimates the shift by
-    block Lanczos; scale is "inf" (default), "given" (with alpha) or
-    "lanczos" (1.05 times the Lanczos spectral-radius estimate)."""
+    block Lanczos; scale is "inf" (default), "given" (with alpha), "lanczos"
+    (1.05 times the Lanczos spectral-radius estimate) or "fro"; k=0 with a
+    given s reports the certified index instead of testing one."""
     p = refl_params_default()
     p.k = int(k)
     p.shift_mode = SHIFT["lanczos"] if s is None else SHIFT["given"]
@@ -334,6 +336,39 @@ def sign_apply(H, V, k, s=None, handle=None, check=True, **kw):
     return (Y.reshape(-1) if vec else Y.contiguous()), info.as_dict(), st
 
 
+class BatchedCall:
+    """The marshalled arguments of one refl_sign_batched call, built once and
+    reused (the same H and R buffers solved repeatedly, e.g. by an outer
+    iteration that updates the matrices in place)."""
+
+    def __init__(self, Hs, ks, ss, outs, **kw):
+        n = len(Hs)
+        per = {key: kw.pop(key) for key in ("alpha", "tol", "max_iter", "fixed_steps")
+               if isinstance(kw.get(key), (list, tuple))}
+        params = [make_params(ks[p], ss[p], **kw, **{key: v[p] for key, v in per.items()})
+                  for p in range(n)]
+        i64a = ctypes.c_int64 * n
+        vpa = ctypes.c_void_p * n
+        self.n = n
+        self.d = i64a(*[H.shape[0] for H in Hs])
+        self.H = vpa(*[H.data_ptr() for H in Hs])
+        self.ldh = i64a(*[H.stride(0) for H in Hs])
+        self.params = (refl_params_t * n)(*params)
+        self.R = vpa(*[R.data_ptr() for R in outs])
+        self.ldr = i64a(*[R.stride(0) for R in outs])
+        self.infos = (refl_info_t * n)()
+        self.status = (ctypes.c_int * n)()
+        self._keep = (Hs, outs)
+
+    def run(self, h, check=True):
+        """Returns the call's status; per-problem results in .infos / .status."""
+        st = load().refl_sign_batched(h, self.n, self.d, self.H, self.ldh, self.params, self.R,
+                                      self.ldr, self.infos, self.status)
+        if check:
+            _check(h, st)
+        return st
+
+
 def sign_batched(Hs, ks, ss, handle=None, outs=None, check=True, **kw):
     """R_k = sgn(H - sI) for a list of float64 device tensors in one call.
 
@@ -351,19 +386,11 @@ def sign_batched(Hs, ks, ss, handle=None, outs=None, check=True, **kw):
             raise ValueError("each H must be d x d (or d x ld) with unit column stride")
     h = handle or Handle(Hs[0].device)
     h.sync_stream()
-    per = {key: kw.pop(key) for key in ("alpha", "tol", "max_iter", "fixed_steps")
-           if isinstance(kw.get(key), (list, tuple))}
-    params = []
-    for p in range(n):
-        extra = {key: v[p] for key, v in per.items()}
-        params.append(make_params(ks[p], ss[p], **kw, **extra))
     Rs = outs if outs is not None else [torch.empty((H.shape[0], H.shape[0]), dtype=torch.float64,
                                                     device=H.device) for H in Hs]
-    st, sts, infos = refl_sign_batched(h.h, [H.shape[0] for H in Hs], [H.data_ptr() for H in Hs],
-                                       [H.stride(0) for H in Hs], params,
-                                       [R.data_ptr() for R in Rs], [R.stride(0) for R in Rs],
-                                       check=check)
-    return Rs, [i.as_dict() for i in infos], sts, st
+    call = BatchedCall(Hs, ks, ss, Rs, **kw)
+    st = call.run(h.h, check=check)
+    return Rs, [i.as_dict() for i in call.infos], list(call.status), st
 
 
 def estimate_shift(H, k, steps=0, seed=0, handle=None, check=True):

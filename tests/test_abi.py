@@ -42,8 +42,8 @@ def test_struct_layout_matches_header(tmp_path):
         'printf("%zu %zu\\n", sizeof(refl_params_t), sizeof(refl_info_t));\n'
         'printf("%zu %zu %zu\\n", offsetof(refl_params_t, seed), offsetof(refl_params_t, cg_tol),'
         " offsetof(refl_params_t, lanczos_steps));\n"
-        'printf("%zu %zu %zu\\n", offsetof(refl_info_t, s), offsetof(refl_info_t, dk_bound),'
-        " offsetof(refl_info_t, ms_total));\n"
+        'printf("%zu %zu %zu %zu\\n", offsetof(refl_info_t, s), offsetof(refl_info_t, dk_bound),'
+        " offsetof(refl_info_t, ms_total), offsetof(refl_info_t, gamma));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
@@ -55,7 +55,8 @@ def test_struct_layout_matches_header(tmp_path):
     assert o == [refl.refl_params_t.seed.offset, refl.refl_params_t.cg_tol.offset,
                  refl.refl_params_t.lanczos_steps.offset]
     o = list(map(int, lines[2].split()))
-    assert o == [refl.refl_info_t.s.offset, refl.refl_info_t.dk_bound.offset, refl.refl_info_t.ms_total.offset]
+    assert o == [refl.refl_info_t.s.offset, refl.refl_info_t.dk_bound.offset, refl.refl_info_t.ms_total.offset,
+                 refl.refl_info_t.gamma.offset]
 
 
 def test_params_default_and_status_strings():
@@ -73,6 +74,8 @@ def test_null_arguments_rejected_without_device():
     assert lib.refl_create(None, 0, None) == 1
     assert lib.refl_destroy(None) == 1
     assert lib.refl_sign(None, 4, None, 4, None, None, 4, None) == 1
+    assert lib.refl_sign_batched(None, 1, None, None, None, None, None, None, None, None) == 1
+    assert lib.refl_sign_batched_workspace_size(None, 1, None, None, None) == 1
     assert refl.load().refl_last_error(None) == b"NULL handle"
 
 

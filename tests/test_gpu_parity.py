@@ -156,9 +156,11 @@ def test_error_paths(R, handle):
     H, lam, Q, s = _cfg0()
     Hg = _gpu(H)
     _say("errors: bad k")
-    for k in (0, 64):
+    for k in (-1, 64):
         _, _, st = R.sign(Hg, k, s, handle=handle, check=False)
         assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
+    _, _, st = R.sign(Hg, 0, None, handle=handle, check=False)   # k = 0 needs a given shift
+    assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
     _say("errors: non-finite H")
     Hn = H.copy()
     Hn[3, 10] = np.nan
@@ -178,6 +180,43 @@ def test_error_paths(R, handle):
     D = np.diag(np.linspace(-1, 1, 16))
     _, info, st = R.sign(_gpu(D), 8, D[7, 7], handle=handle, check=False, max_iter=60)
     assert R.STATUS[st] == "REFL_ERR_NOT_CONVERGED" and info["index_j"] == -1
+
+
+def test_index_report_mode(R, handle):
+    """k = 0: no target; the certified index j is reported and R = sgn(H - sI)
+    for that j (the reflector R_j, Prop. 2.1), including the definite cases
+    j = 0 (R = I) and j = d (R = -I)."""
+    H, lam, Q, s = _cfg0()
+    Hg = _gpu(H)
+    R4, i4, st = R.sign(Hg, 4, s, handle=handle)
+    R0, i0, st0 = R.sign(Hg, 0, s, handle=handle)
+    _say(f"k=0 in gap 4: j={i0['index_j']}")
+    assert st0 == 0 and i0["index_j"] == 4 and torch.equal(R0, R4)
+    s5 = 0.5 * (lam[4] + lam[5])
+    R5, i5, st5 = R.sign(Hg, 0, s5, handle=handle)
+    err5 = np.linalg.norm(R5.cpu().numpy() - oracle.reflector_from_eig(Q, 5))
+    _say(f"k=0 in gap 5: j={i5['index_j']} err={err5:.2e}")
+    assert st5 == 0 and i5["index_j"] == 5 and err5 < 1e-11
+    for s_out, j, sign in ((-1.5, 0, 1.0), (1.5, 64, -1.0)):
+        for prec in ("fp64", "mixed"):
+            Rd, idd, std = R.sign(Hg, 0, s_out, handle=handle, precision=prec, check=False)
+            err = float((Rd - sign * torch.eye(64, dtype=torch.float64, device=Rd.device)).abs().max())
+            _say(f"k=0 {prec} s={s_out}: status={R.STATUS[std]} j={idd['index_j']} max|R - ({sign:+.0f})I|={err:.1e}")
+            assert std == 0 and idd["index_j"] == j
+            assert err < (1e-12 if prec == "fp64" else 1e-30)
+    Rm, im, stm = R.sign(Hg, 0, s, handle=handle, precision="mixed")
+    errm = np.linalg.norm(Rm.cpu().numpy() - oracle.reflector_from_eig(Q, 4))
+    _say(f"k=0 mixed in gap 4: j={im['index_j']} err={errm:.2e}")
+    assert stm == 0 and im["index_j"] == 4 and errm <= 1e-8 * np.sqrt(64)
+
+
+def test_frobenius_scale(R, handle):
+    H, lam, Q, s = _cfg0()
+    Rg, info, st = R.sign(_gpu(H), 4, s, handle=handle, scale="fro")
+    fro = oracle.fro_norm_shifted(H, s)
+    err = np.linalg.norm(Rg.cpu().numpy() - oracle.reflector_from_eig(Q, 4))
+    _say(f"scale fro: alpha={info['alpha']:.15e} oracle={fro:.15e} steps={info['ns_steps']} err={err:.2e}")
+    assert st == 0 and abs(info["alpha"] - fro) <= 1e-14 * fro and err < 1e-11
 
 
 # ------------------------------------------------------------------ FP32

@@ -343,3 +343,18 @@ def test_lanczos_check_schedule():
     c = oracle.lanczos_check_steps(4096, 5, 9)
     assert c[0] == 1 and c[1] == 9 and c[-1] == 4096 // 9
     assert oracle.lanczos_check_steps(100, 3, 7, max_steps=6) == [1, 6]
+
+
+def test_scale_norms_bound_spectral_radius():
+    """Both cheap scales bound rho(H - sI) from above; the Frobenius norm of a
+    symmetric matrix is the 2-norm of its eigenvalues, and the inf-norm of a
+    diagonal matrix is its largest absolute entry."""
+    H, lam, Q = inputs.planted_hessian(48, 5, 0.2, 3)
+    s = 0.5 * (lam[4] + lam[5])
+    rho = float(np.max(np.abs(lam - s)))
+    fro = oracle.fro_norm_shifted(H, s)
+    assert abs(fro - float(np.sqrt(np.sum((lam - s) ** 2)))) < 1e-12 * fro
+    assert fro >= rho and oracle.inf_norm_shifted(H, s) >= rho - 1e-12
+    D = np.diag(np.array([0.5, -2.0, 1.5]))
+    assert oracle.inf_norm_shifted(D, 0.25) == 2.25
+    assert abs(oracle.fro_norm_shifted(D, 0.25) - np.sqrt(0.0625 + 5.0625 + 1.5625)) < 1e-15

@@ -20,7 +20,8 @@ __all__ = [
     "ns_error_recurrence", "ns_iterate", "ns_iterates", "ns_closed_form",
     "ns_depth_scalar", "inf_norm_shifted", "fro_norm_shifted", "admissible", "certificates",
     "spectral_norm_sym", "splitmix64", "start_block", "lanczos_block_size",
-    "lanczos_check_steps", "block_lanczos",
+    "lanczos_check_steps", "block_lanczos", "ns_step_derivative", "ns_adjoint", "ns_tangent",
+    "ns_poly_derivative", "ns_frechet_dk", "sign_frechet_dk",
 ]
 
 
@@ -170,6 +171,90 @@ def inf_norm_shifted(H, s: float) -> float:
     scaling surrogate)."""
     A = np.asarray(H, dtype=np.float64) - s * np.eye(H.shape[0])
     return float(np.max(np.sum(np.abs(A), axis=1)))
+
+
+# ------------------------------------------------------------ derivatives
+# Differentiation of the finite-step reflector X_m(H) = p_m((H - sI)/alpha)
+# with s and alpha held fixed (the shift and scale are chosen from spectral
+# estimates, not differentiated through).  Three independent formulations:
+# reverse accumulation over the steps of eq. NS, forward tangents, and the
+# Daleckii-Krein divided-difference form of the derivative of a matrix
+# function.
+
+
+def ns_step_derivative(X, E):
+    """Derivative of f(X) = X (3I - X^2)/2 (eq. NS) at X in direction E, by
+    the product rule: (3E - (E X^2 + X E X + X^2 E))/2.  For symmetric X this
+    linear map is self-adjoint in the Frobenius inner product."""
+    X = np.asarray(X, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    X2 = X @ X
+    return 0.5 * (3.0 * E - (E @ X2 + X @ E @ X + X2 @ E))
+
+
+def ns_adjoint(H, s: float, alpha_norm: float, m: int, G):
+    """Gradient of L(H) = <G, X_m(H)> over symmetric perturbations of H:
+    Gbar_m = (G + G^T)/2, Gbar_j = Df(X_j)*[Gbar_{j+1}] = Df(X_j)[Gbar_{j+1}],
+    gradient = Gbar_0 / alpha_norm (X_0 = (H - sI)/alpha_norm)."""
+    Xs = ns_iterates(H, s, alpha_norm, m)
+    G = np.asarray(G, dtype=np.float64)
+    Gb = 0.5 * (G + G.T)
+    for j in range(m - 1, -1, -1):
+        Gb = ns_step_derivative(Xs[j], Gb)
+    return Gb / alpha_norm
+
+
+def ns_tangent(H, s: float, alpha_norm: float, m: int, E):
+    """Directional derivative D X_m(H)[E] by forward tangents:
+    Xdot_0 = E/alpha_norm, Xdot_{j+1} = Df(X_j)[Xdot_j]."""
+    Xs = ns_iterates(H, s, alpha_norm, m)
+    T = np.asarray(E, dtype=np.float64) / alpha_norm
+    for j in range(m):
+        T = ns_step_derivative(Xs[j], T)
+    return T
+
+
+def ns_poly_derivative(t, m: int):
+    """p_m'(t) by the chain rule on eq. pm: p_0' = 1,
+    p_{j+1}' = p_j' (3 - 3 p_j^2)/2."""
+    p = np.asarray(t, dtype=np.float64)
+    dp = np.ones_like(p)
+    for _ in range(m):
+        dp = dp * 1.5 * (1.0 - p * p)
+        p = 0.5 * p * (3.0 - p * p)
+    return dp
+
+
+def _dk(w, V, phi, dphi, E):
+    """Daleckii-Krein: D phi(A)[E] = V (F o (V^T E V)) V^T for A = V diag(w) V^T,
+    F_ij = (phi_i - phi_j)/(w_i - w_j) (phi'_i where w_i = w_j)."""
+    dw = w[:, None] - w[None, :]
+    same = np.abs(dw) <= 1e-13 * max(1.0, float(np.max(np.abs(w))))
+    F = np.where(same, 0.5 * (dphi[:, None] + dphi[None, :]),
+                 (phi[:, None] - phi[None, :]) / np.where(same, 1.0, dw))
+    B = V.T @ np.asarray(E, dtype=np.float64) @ V
+    return V @ (F * B) @ V.T
+
+
+def ns_frechet_dk(H, s: float, alpha_norm: float, m: int, E):
+    """D X_m(H)[E] in Daleckii-Krein form with phi(x) = p_m((x - s)/alpha_norm)
+    on the eigenvalues of H (eigendecomposition by LAPACK)."""
+    Hs = np.asarray(H, dtype=np.float64)
+    w, V = np.linalg.eigh(0.5 * (Hs + Hs.T))
+    t = (w - s) / alpha_norm
+    return _dk(w, V, ns_poly(t, m), ns_poly_derivative(t, m) / alpha_norm, E)
+
+
+def sign_frechet_dk(H, s: float, E):
+    """The limit m -> infinity: D sgn(H - sI)[E] with F_ij = 2/|a_i - a_j| when
+    a_i = lambda_i - s and a_j have opposite signs, else 0."""
+    Hs = np.asarray(H, dtype=np.float64)
+    w, V = np.linalg.eigh(0.5 * (Hs + Hs.T))
+    a = w - s
+    opp = np.sign(a)[:, None] != np.sign(a)[None, :]
+    F = np.where(opp, 2.0 / np.where(opp, np.abs(a[:, None] - a[None, :]), 1.0), 0.0)
+    B = V.T @ np.asarray(E, dtype=np.float64) @ V
+    return V @ (F * B) @ V.T
 
 
 def fro_norm_shifted(H, s: float) -> float:

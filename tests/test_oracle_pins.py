@@ -358,3 +358,105 @@ def test_scale_norms_bound_spectral_radius():
     D = np.diag(np.array([0.5, -2.0, 1.5]))
     assert oracle.inf_norm_shifted(D, 0.25) == 2.25
     assert abs(oracle.fro_norm_shifted(D, 0.25) - np.sqrt(0.0625 + 5.0625 + 1.5625)) < 1e-15
+
+
+# ------------------------------------------------------------ derivatives
+def _sym(rng, d):
+    Z = rng.standard_normal((d, d))
+    return 0.5 * (Z + Z.T)
+
+
+def test_ns_poly_derivative_complex_step():
+    """p_m'(t) against complex-step differentiation of p_m (exact to
+    rounding: Im p(t + ih)/h with h = 1e-30)."""
+    t = np.linspace(-0.9, 0.9, 37)
+    for m in (1, 3, 8):
+        cs = np.imag(_poly_c(t + 1e-30j, m)) / 1e-30
+        assert np.max(np.abs(oracle.ns_poly_derivative(t, m) - cs)) < 1e-13 * max(1.0, np.max(np.abs(cs)))
+
+
+def _poly_c(z, m):
+    for _ in range(m):
+        z = 0.5 * z * (3.0 - z * z)
+    return z
+
+
+def test_ns_adjoint_central_differences():
+    """<grad, E> against central differences of <G, X_m(H + tE)> (FP64,
+    t = 1e-6: truncation O(t^2), rounding O(u/t))."""
+    rng = np.random.default_rng(5)
+    d, m = 12, 5
+    H, lam, Q = inputs.planted_hessian(d, 3, 0.3, 7)
+    s = 0.5 * (lam[2] + lam[3])
+    alpha = oracle.inf_norm_shifted(H, s)
+    G, E = _sym(rng, d), _sym(rng, d)
+    grad = oracle.ns_adjoint(H, s, alpha, m, G)
+    t = 1e-6
+    Lp = np.sum(G * oracle.ns_iterates(H + t * E, s, alpha, m)[m])
+    Lm = np.sum(G * oracle.ns_iterates(H - t * E, s, alpha, m)[m])
+    fd = (Lp - Lm) / (2 * t)
+    assert abs(np.sum(grad * E) - fd) < 1e-7 * abs(fd)
+
+
+def test_ns_adjoint_equals_daleckii_krein_and_tangent():
+    """Reverse mode, forward tangents and the divided-difference form agree:
+    grad(G) = D X_m[G] (self-adjointness) and <grad(G), E> = <G, D X_m[E]>."""
+    rng = np.random.default_rng(6)
+    d, m = 20, 7
+    H, lam, Q = inputs.planted_hessian(d, 6, 0.2, 8)
+    s = lam[5] + 0.3 * (lam[6] - lam[5])
+    alpha = oracle.inf_norm_shifted(H, s)
+    G, E = _sym(rng, d), _sym(rng, d)
+    grad = oracle.ns_adjoint(H, s, alpha, m, G)
+    dk = oracle.ns_frechet_dk(H, s, alpha, m, G)
+    tan = oracle.ns_tangent(H, s, alpha, m, G)
+    scale = np.linalg.norm(dk)
+    assert np.linalg.norm(grad - dk) < 1e-11 * scale
+    assert np.linalg.norm(tan - dk) < 1e-11 * scale
+    lhs = np.sum(grad * E)
+    rhs = np.sum(G * oracle.ns_tangent(H, s, alpha, m, E))
+    assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(grad) * np.linalg.norm(E)
+
+
+def test_ns_adjoint_nonsymmetric_G_uses_symmetric_part():
+    rng = np.random.default_rng(9)
+    d, m = 10, 4
+    H, lam, Q = inputs.planted_hessian(d, 2, 0.4, 10)
+    s = 0.5 * (lam[1] + lam[2])
+    alpha = oracle.inf_norm_shifted(H, s)
+    Z = rng.standard_normal((d, d))
+    a = oracle.ns_adjoint(H, s, alpha, m, Z)
+    b = oracle.ns_adjoint(H, s, alpha, m, 0.5 * (Z + Z.T))
+    assert np.array_equal(a, b) and np.allclose(a, a.T, atol=1e-15)
+
+
+def test_finite_step_derivative_tends_to_sign_derivative():
+    """As m grows, D X_m[E] tends to D sgn(H - sI)[E] (F_ij -> 2/|a_i - a_j|
+    across the gap, 0 within a side)."""
+    rng = np.random.default_rng(11)
+    d = 16
+    H, lam, Q = inputs.planted_hessian(d, 5, 0.5, 12)
+    s = 0.5 * (lam[4] + lam[5])
+    alpha = oracle.inf_norm_shifted(H, s)
+    E = _sym(rng, d)
+    lim = oracle.sign_frechet_dk(H, s, E)
+    errs = [np.linalg.norm(oracle.ns_frechet_dk(H, s, alpha, m, E) - lim) for m in (4, 7, 10, 30)]
+    assert errs[0] > errs[1] > errs[2] and errs[3] < 1e-12 * np.linalg.norm(lim)
+
+
+def test_derivative_of_diagonal_matrix_closed_form():
+    """H diagonal: D X_m[E]_ij = (p_m(t_i) - p_m(t_j))/(h_i - h_j) E_ij off the
+    diagonal, p_m'(t_i)/alpha E_ii on it (t = (h - s)/alpha)."""
+    h = np.array([-0.8, -0.1, 0.3, 0.9])
+    s, alpha, m = 0.05, 1.2, 6
+    E = np.array([[1.0, 2.0, -1.0, 0.5], [2.0, -3.0, 0.25, 1.0], [-1.0, 0.25, 2.0, -2.0],
+                  [0.5, 1.0, -2.0, 0.75]])
+    t = (h - s) / alpha
+    p = _poly_c(t.astype(complex), m).real
+    dp = np.imag(_poly_c(t + 1e-30j, m)) / 1e-30
+    want = np.empty((4, 4))
+    for i in range(4):
+        for j in range(4):
+            want[i, j] = dp[i] / alpha * E[i, i] if i == j else (p[i] - p[j]) / (h[i] - h[j]) * E[i, j]
+    got = oracle.ns_tangent(np.diag(h), s, alpha, m, E)
+    assert np.max(np.abs(got - want)) < 1e-13

@@ -104,7 +104,17 @@ typedef struct {
   uint64_t seed;        /* start blocks of Lanczos and of the subspace extraction */
   int32_t timing;       /* 1: record HIP events around every bulk product and report their
                            summed durations in info (adds no synchronisation) */
+  int32_t grad_mode;    /* refl_sign_grad: REFL_GRAD_REVERSE (default) or REFL_GRAD_TANGENT */
+  int32_t ckpt_every;   /* refl_sign_grad, reverse mode: keep every c-th iterate and
+                           recompute the others (0: c = ceil(sqrt(step cap))) */
 } refl_params_t;
+
+typedef enum {
+  REFL_GRAD_REVERSE = 0, /* reverse sweep over checkpointed iterates */
+  REFL_GRAD_TANGENT = 1  /* forward tangent in direction G, carried beside the iteration
+                            (no checkpoints; equal to the gradient because the derivative
+                            of X -> p_m(X) is self-adjoint) */
+} refl_grad_mode_t;
 
 typedef struct {
   int32_t ns_steps;       /* Newton-Schulz steps taken */
@@ -235,6 +245,33 @@ refl_status_t refl_sign_batched(refl_handle_t h, int32_t nprob, const int64_t *d
                                 const int64_t *ldr, refl_info_t *info, refl_status_t *status);
 refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, const int64_t *d,
                                                const refl_params_t *params, size_t *bytes);
+
+/* Gradient of L(H) = <G, R_m(H)> (Frobenius inner product) for the reflector
+ * R_m = p_m((H - sI)/alpha) that refl_sign computes (eq. NS, eq. pm; m its
+ * step count), with respect to SYMMETRIC perturbations of H, the shift s and
+ * the scale alpha held fixed.  Only the symmetric part of G matters; G is
+ * d x d FP64 (ldg), read in full.
+ *
+ * The forward pass is refl_sign's (FP64 or FP32; MIXED and a Lanczos shift
+ * give REFL_ERR_UNSUPPORTED) with the same steps and stopping rule.  The
+ * derivative follows the steps of eq. NS exactly (product rule), in the
+ * bulk precision:
+ *   reverse  Gb_m = sym(G); Gb_j = (3 Gb - (Gb X_j^2 + X_j Gb X_j + X_j^2 Gb))/2
+ *            with Gb = Gb_{j+1}; gradient = Gb_0 / alpha.  Iterates are kept
+ *            every ckpt_every steps and recomputed segment by segment.
+ *   tangent  Xdot_0 = sym(G)/alpha, Xdot_{j+1} = the same map applied to Xdot_j
+ *            beside the forward steps; gradient = Xdot_m.
+ * Per step the derivative costs one general and one symmetric three-term
+ * product (5 d^3 flops) against 2 d^3 for the forward step.
+ *
+ * Outputs: dGrad (d x d, ldgr, symmetric), *loss = <G, R_m> (may be NULL),
+ * and R_m into dR (ldr) unless dR is NULL.  Status and info as refl_sign.
+ * Device workspace is allocated by the library (about (ceil(cap/c) + 2c + 8)
+ * dp^2 elements of the bulk precision, cap = fixed_steps or max_iter). */
+refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
+                             const refl_params_t *p, const double *dG, int64_t ldg,
+                             double *dGrad, int64_t ldgr, double *loss, double *dR, int64_t ldr,
+                             refl_info_t *info);
 
 /* Static strings; never NULL. */
 const char *refl_status_string(refl_status_t s);

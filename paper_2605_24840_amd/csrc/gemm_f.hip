@@ -58,25 +58,36 @@ struct FCfg {
   static constexpr int VE = 16 / (int)sizeof(T);        // elements per 16 B
 };
 
-// One output tile (I, J), I <= J; the tile's partial (||N||_F^2 or trace
-// contribution) goes to *partial.
-template <typename T, int MODE>
-__device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T* __restrict__ B,
-                                                const T* __restrict__ Xold, T* __restrict__ out,
-                                                int ld, int d, int dp, int I, int J, T* lds,
-                                                double* red, double* __restrict__ partial) {
+// Operand pairs of one tile product: the tile accumulates
+// sum_p (rows I of A[p]) (rows J of B[p])^T over the NP pairs, i.e. a product
+// whose K runs over the NP pairs one after the other.
+template <typename T, int NP>
+struct Pairs {
+  const T* A[NP];
+  const T* B[NP];
+};
+
+// One output tile (I, J).  Symmetric modes (RESIDUAL, UPDATE, ADJOINT) take
+// I <= J and store the tile twice; GEMM_PLAIN_NEG takes any (I, J) and
+// stores -C once.  The tile's partial (||N||_F^2 or trace contribution; 0
+// for the other modes) goes to *partial.
+template <typename T, int MODE, int NP>
+__device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T* __restrict__ Xold,
+                                                T* __restrict__ out, int ld, int d, int dp, int I,
+                                                int J, T* lds, double* red,
+                                                double* __restrict__ partial) {
   typedef FCfg<T> C;
   typedef FMfma<T> M;
   typedef typename M::acc_t acc_t;
+  constexpr bool SYM = MODE != GEMM_PLAIN_NEG;
   const int i0 = I * TILE, j0 = J * TILE;
-  const bool diag = (I == J);
+  const bool diag = SYM && (I == J);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 
   // Loader: thread -> row (tid >> 1), 8 consecutive k at (tid & 1) * 8.
   const int lrow = tid >> 1, lk = (tid & 1) * 8;
-  const T* gA = A + (int64_t)(i0 + lrow) * ld + lk;
-  const T* gB = B + (int64_t)(j0 + lrow) * ld + lk;
+  const int64_t rA = (int64_t)(i0 + lrow) * ld + lk, rB = (int64_t)(j0 + lrow) * ld + lk;
   u32x4_t ra[C::NV], rb[C::NV];
 
   acc_t acc[4][4];
@@ -88,9 +99,20 @@ __device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
 
   const int nk = dp / C::BK;
-  auto gload = [&](int kt) {
-    const u32x4_t* pa = reinterpret_cast<const u32x4_t*>(gA + (int64_t)kt * C::BK);
-    const u32x4_t* pb = reinterpret_cast<const u32x4_t*>(gB + (int64_t)kt * C::BK);
+  auto gload = [&](int t) {
+    // Slice t of the concatenated K: pair t / nk, slice t % nk (wave-uniform).
+    const int p = NP == 1 ? 0 : t / nk;
+    const int kt = NP == 1 ? t : t - p * nk;
+    const T* A = op.A[0];
+    const T* B = op.B[0];
+#pragma unroll
+    for (int q = 1; q < NP; ++q)
+      if (p == q) {
+        A = op.A[q];
+        B = op.B[q];
+      }
+    const u32x4_t* pa = reinterpret_cast<const u32x4_t*>(A + rA + (int64_t)kt * C::BK);
+    const u32x4_t* pb = reinterpret_cast<const u32x4_t*>(B + rB + (int64_t)kt * C::BK);
 #pragma unroll
     for (int v = 0; v < C::NV; ++v) {
       ra[v] = pa[v];
@@ -109,12 +131,13 @@ __device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T
     }
   };
 
+  const int nkt = NP * nk;
   gload(0);
   sstore(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  for (int kt = 0; kt < nkt; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
+    if (kt + 1 < nkt) gload(kt + 1);
     const T* sa = lds + cur * (2 * TILE * C::LDA);
     const T* sb = sa + TILE * C::LDA;
 #pragma unroll
@@ -130,7 +153,7 @@ __device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = M::op(av[a], bv[b], acc[a][b]);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+    if (kt + 1 < nkt) sstore(cur ^ 1);
     __syncthreads();
   }
 
@@ -161,7 +184,7 @@ __device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T
     const int r = it * RPI + tid / LPR;
     const int gi = i0 + r;
     alignas(16) T xo[C::VE];
-    if (MODE == GEMM_UPDATE) {
+    if (MODE == GEMM_UPDATE || MODE == GEMM_ADJOINT) {
       const u32x4_t v = *reinterpret_cast<const u32x4_t*>(Xold + (int64_t)gi * ld + j0 + cofs);
       *reinterpret_cast<u32x4_t*>(xo) = v;
     }
@@ -175,9 +198,13 @@ __device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T
       if (MODE == GEMM_RESIDUAL) {
         n = ((gi == gj && gi < d) ? T(1) : T(0)) - v;
         part += (diag ? 1.0 : 2.0) * (double)n * (double)n;
-      } else {
+      } else if (MODE == GEMM_UPDATE) {
         n = xo[e] + T(0.5) * v;
         if (gi == gj) part += (double)n;
+      } else if (MODE == GEMM_ADJOINT) {
+        n = T(0.5) * (xo[e] + v);
+      } else {
+        n = -v;
       }
       vals[it][e] = n;
     }
@@ -185,7 +212,7 @@ __device__ __forceinline__ void sym_gemm_f_tile(const T* __restrict__ A, const T
         *reinterpret_cast<const u32x4_t*>(&vals[it][0]);
   }
   __syncthreads();
-  if (!diag) {
+  if (SYM && !diag) {
     // Write the final values back to staging, then store the transposed tile.
 #pragma unroll
     for (int it = 0; it < TILE / RPI; ++it) {
@@ -218,8 +245,35 @@ __global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
   __shared__ T lds[FCfg<T>::LDS];
   __shared__ double red[4];
   const int2 tl = tiles[blockIdx.x];
-  sym_gemm_f_tile<T, MODE>(A, B, Xold, out, ld, d, dp, tl.x, tl.y, lds, red,
-                           partials + blockIdx.x);
+  Pairs<T, 1> op;
+  op.A[0] = A;
+  op.B[0] = B;
+  sym_gemm_f_tile<T, MODE, 1>(op, Xold, out, ld, d, dp, tl.x, tl.y, lds, red,
+                              partials + blockIdx.x);
+}
+
+// Adjoint step of eq. NS (see launch.h): out = (Gb + Gb N + N Gb + Pn X)/2
+// with Pn = -X Gb, all operands symmetric except Pn.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint_step(const T* __restrict__ Gb,
+                                                      const T* __restrict__ N,
+                                                      const T* __restrict__ Pn,
+                                                      const T* __restrict__ X,
+                                                      T* __restrict__ out, int ld, int d, int dp,
+                                                      const int2* __restrict__ tiles,
+                                                      double* __restrict__ partials) {
+  __shared__ T lds[FCfg<T>::LDS];
+  __shared__ double red[4];
+  const int2 tl = tiles[blockIdx.x];
+  Pairs<T, 3> op;
+  op.A[0] = Gb;
+  op.B[0] = N;
+  op.A[1] = N;
+  op.B[1] = Gb;
+  op.A[2] = Pn;
+  op.B[2] = X;
+  sym_gemm_f_tile<T, GEMM_ADJOINT, 3>(op, Gb, out, ld, d, dp, tl.x, tl.y, lds, red,
+                                      partials + blockIdx.x);
 }
 
 // Grouped launch over the tiles of many problems: tile (p, I, J, slot) reads
@@ -239,12 +293,15 @@ __global__ __launch_bounds__(256) void k_sym_gemm_f_grouped(const GemmProblem* _
   T* Xc = reinterpret_cast<T*>(pr.X[parity]);
   T* Xn = reinterpret_cast<T*>(pr.X[parity ^ 1]);
   T* N = reinterpret_cast<T*>(pr.N);
+  Pairs<T, 1> op;
+  op.A[0] = Xc;
+  op.B[0] = MODE == GEMM_RESIDUAL ? Xc : N;
   if (MODE == GEMM_RESIDUAL)
-    sym_gemm_f_tile<T, MODE>(Xc, Xc, nullptr, N, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
-                             partials + tl.w);
+    sym_gemm_f_tile<T, MODE, 1>(op, nullptr, N, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
+                                partials + tl.w);
   else
-    sym_gemm_f_tile<T, MODE>(Xc, N, Xc, Xn, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
-                             partials + tl.w);
+    sym_gemm_f_tile<T, MODE, 1>(op, Xc, Xn, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
+                                partials + tl.w);
 }
 
 template <typename T>
@@ -255,10 +312,37 @@ static hipError_t launch_f(int mode, const T* A, const T* B, const T* Xold, T* o
   if (mode == GEMM_RESIDUAL)
     hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_RESIDUAL>), dim3(ntiles), dim3(256), 0, st, A, B,
                        Xold, out, ld, d, dp, tiles, partials);
-  else
+  else if (mode == GEMM_UPDATE)
     hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_UPDATE>), dim3(ntiles), dim3(256), 0, st, A, B, Xold,
                        out, ld, d, dp, tiles, partials);
+  else if (mode == GEMM_PLAIN_NEG)
+    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_PLAIN_NEG>), dim3(ntiles), dim3(256), 0, st, A, B,
+                       Xold, out, ld, d, dp, tiles, partials);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_adj(const T* Gb, const T* N, const T* Pn, const T* X, T* out, int ld,
+                             int d, int dp, const int2* tiles, int ntiles, double* partials,
+                             hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adjoint_step<T>, dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X, out, ld, d,
+                     dp, tiles, partials);
+  return hipGetLastError();
+}
+hipError_t launch_adjoint_step_f64(const double* Gb, const double* N, const double* Pn,
+                                   const double* X, double* out, int ld, int d, int dp,
+                                   const int2* tiles, int ntiles, double* partials,
+                                   hipStream_t st) {
+  return launch_adj<double>(Gb, N, Pn, X, out, ld, d, dp, tiles, ntiles, partials, st);
+}
+hipError_t launch_adjoint_step_f32(const float* Gb, const float* N, const float* Pn,
+                                   const float* X, float* out, int ld, int d, int dp,
+                                   const int2* tiles, int ntiles, double* partials,
+                                   hipStream_t st) {
+  return launch_adj<float>(Gb, N, Pn, X, out, ld, d, dp, tiles, ntiles, partials, st);
 }
 
 hipError_t launch_sym_gemm_f64(int mode, const double* A, const double* B, const double* Xold,

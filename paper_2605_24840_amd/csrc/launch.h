@@ -10,7 +10,9 @@ namespace refl {
 // mirrored on store).
 enum GemmMode {
   GEMM_RESIDUAL = 0,  // T = X X : writes N = I - T, partial ||N||_F^2 per tile
-  GEMM_UPDATE = 1     // P = X N : writes X_new = X + P/2, partial trace per tile
+  GEMM_UPDATE = 1,    // P = X N : writes X_new = X + P/2, partial trace per tile
+  GEMM_PLAIN_NEG = 2, // C = A B^T by rows (any tile, not symmetric): writes -C
+  GEMM_ADJOINT = 3    // adjoint step (launch_adjoint_step_*)
 };
 
 // FP64 / FP32 products on 16x16x4 MFMA.  Matrices are dp x dp, leading
@@ -22,6 +24,20 @@ hipError_t launch_sym_gemm_f64(int mode, const double* A, const double* B, const
 hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const float* Xold,
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
                                double* partials, hipStream_t st);
+
+// Adjoint (reverse) step of eq. NS for symmetric X and Gb, with N = I - X^2
+// and Pn = -X Gb (a GEMM_PLAIN_NEG product with A = X, B = Gb over all
+// tiles):  out = (Gb + Gb N + N Gb + Pn X)/2
+//             = (3 Gb - (Gb X^2 + X Gb X + X^2 Gb))/2,
+// symmetric, upper tiles only (mirrored); out must not alias Gb.
+hipError_t launch_adjoint_step_f64(const double* Gb, const double* N, const double* Pn,
+                                   const double* X, double* out, int ld, int d, int dp,
+                                   const int2* tiles, int ntiles, double* partials,
+                                   hipStream_t st);
+hipError_t launch_adjoint_step_f32(const float* Gb, const float* N, const float* Pn,
+                                   const float* X, float* out, int ld, int d, int dp,
+                                   const int2* tiles, int ntiles, double* partials,
+                                   hipStream_t st);
 
 // Grouped products over the upper tiles of many problems (FP64 or FP32): the
 // tile list holds (problem, I, J, slot); each problem's descriptor gives its
@@ -64,6 +80,26 @@ hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, doub
 // FP32 copy of H - sI (the operator of the inner solves).
 hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* Hs,
                               hipStream_t st);
+// ---- derivatives ----
+// out (dp x dp) = (G + G^T)/2 on the leading d x d block, divided by
+// scal[SC_ALPHA] if scal != null; zero padding.  G: d x d, ldg, read in full.
+hipError_t launch_sym_in_f64(const double* G, int64_t ldg, int d, const double* scal, double* out,
+                             int dp, hipStream_t st);
+hipError_t launch_sym_in_f32(const double* G, int64_t ldg, int d, const double* scal, float* out,
+                             int dp, hipStream_t st);
+// R (d x d, ldr) = X / scal[SC_ALPHA].
+hipError_t launch_copy_out_scaled_f64(const double* X, int dp, int d, const double* scal,
+                                      double* R, int64_t ldr, hipStream_t st);
+hipError_t launch_copy_out_scaled_f32(const float* X, int dp, int d, const double* scal,
+                                      double* R, int64_t ldr, hipStream_t st);
+// scal[slot] = sum_i A_i B_i over n elements (FP64 sums); partials holds
+// dot_partials() doubles.
+int dot_partials();
+hipError_t launch_dot_f64(const double* A, const double* B, int64_t n, double* partials,
+                          double* scal, int slot, hipStream_t st);
+hipError_t launch_dot_f32(const float* A, const float* B, int64_t n, double* partials,
+                          double* scal, int slot, hipStream_t st);
+
 // Per-problem descriptor of the batched set-up and output kernels.
 struct BatchDesc {
   const double* H;   // input, upper triangle read

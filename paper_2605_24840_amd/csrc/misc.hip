@@ -229,6 +229,55 @@ __global__ __launch_bounds__(256) void k_copy_out(const T* __restrict__ X, int d
     R[(int64_t)i * ldr + j] = (double)X[(int64_t)i * dp + j];
 }
 
+// ------------------------------------------------------------- derivatives
+// out (dp x dp) = (G + G^T)/2 on the leading d x d block (times 1/scal[SC_ALPHA]
+// if scal != null), zero elsewhere; G is d x d with leading dimension ldg.
+// Block (bx, by) handles the 64 x 64 tile (by, bx) and its transpose.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sym_in(const double* __restrict__ G, int64_t ldg, int d,
+                                                const double* __restrict__ scal,
+                                                T* __restrict__ out, int dp) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  __shared__ double t[64][65];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int i0 = I * 64, j0 = J * 64;
+  // t = tile (J, I) of G, transposed on the way in.
+  for (int r = ty; r < 64; r += 4) {
+    const int gi = j0 + r, gj = i0 + tx;
+    t[tx][r] = (gi < d && gj < d) ? G[(int64_t)gi * ldg + gj] : 0.0;
+  }
+  __syncthreads();
+  const double f = scal ? 1.0 / scal[SC_ALPHA] : 1.0;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    const double g = (i < d && j < d) ? G[(int64_t)i * ldg + j] : 0.0;
+    out[(int64_t)i * dp + j] = (T)(0.5 * (g + t[r][tx]) * f);
+  }
+}
+
+// R = X / scal[SC_ALPHA] (d x d, ldr), FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_out_scaled(const T* __restrict__ X, int dp, int d,
+                                                         const double* __restrict__ scal,
+                                                         double* __restrict__ R, int64_t ldr) {
+  const int i = blockIdx.y;
+  const double inv = 1.0 / scal[SC_ALPHA];
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < d; j += gridDim.x * 256)
+    R[(int64_t)i * ldr + j] = (double)X[(int64_t)i * dp + j] * inv;
+}
+
+// partials[block] = sum over the block's share of (double) A_i * B_i.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot(const T* __restrict__ A, const T* __restrict__ B,
+                                             int64_t n, double* __restrict__ partials) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    a += (double)A[i] * (double)B[i];
+  const double t = block_sum_256(a, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 // ------------------------------------------------- batched set-up / output
 // Grouped forms of the kernels above over many problems (one descriptor per
 // problem): the blocks of problem ids[g] (or g) are begin[g] .. begin[g+1),
@@ -858,6 +907,48 @@ hipError_t launch_copy_out_f64(const double* X, int dp, int d, double* R, int64_
 hipError_t launch_copy_out_f32(const float* X, int dp, int d, double* R, int64_t ldr,
                                hipStream_t st) {
   hipLaunchKernelGGL(k_copy_out<float>, dim3(nblocks(d, 256), d), dim3(256), 0, st, X, dp, d, R, ldr);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sym_in(const double* G, int64_t ldg, int d, const double* scal, T* out, int dp,
+                         hipStream_t st) {
+  const int nt = dp / 64;
+  hipLaunchKernelGGL(k_sym_in<T>, dim3(nt, nt), dim3(256), 0, st, G, ldg, d, scal, out, dp);
+  return hipGetLastError();
+}
+hipError_t launch_sym_in_f64(const double* G, int64_t ldg, int d, const double* scal, double* out,
+                             int dp, hipStream_t st) {
+  return sym_in<double>(G, ldg, d, scal, out, dp, st);
+}
+hipError_t launch_sym_in_f32(const double* G, int64_t ldg, int d, const double* scal, float* out,
+                             int dp, hipStream_t st) {
+  return sym_in<float>(G, ldg, d, scal, out, dp, st);
+}
+hipError_t launch_copy_out_scaled_f64(const double* X, int dp, int d, const double* scal,
+                                      double* R, int64_t ldr, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_out_scaled<double>, dim3(nblocks(d, 256), d), dim3(256), 0, st, X, dp,
+                     d, scal, R, ldr);
+  return hipGetLastError();
+}
+hipError_t launch_copy_out_scaled_f32(const float* X, int dp, int d, const double* scal,
+                                      double* R, int64_t ldr, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_out_scaled<float>, dim3(nblocks(d, 256), d), dim3(256), 0, st, X, dp,
+                     d, scal, R, ldr);
+  return hipGetLastError();
+}
+constexpr int DOT_BLOCKS = 512;
+int dot_partials() { return DOT_BLOCKS; }
+hipError_t launch_dot_f64(const double* A, const double* B, int64_t n, double* partials,
+                          double* scal, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot<double>, dim3(DOT_BLOCKS), dim3(256), 0, st, A, B, n, partials);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partials, DOT_BLOCKS, scal, slot);
+  return hipGetLastError();
+}
+hipError_t launch_dot_f32(const float* A, const float* B, int64_t n, double* partials,
+                          double* scal, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_dot<float>, dim3(DOT_BLOCKS), dim3(256), 0, st, A, B, n, partials);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partials, DOT_BLOCKS, scal, slot);
   return hipGetLastError();
 }
 

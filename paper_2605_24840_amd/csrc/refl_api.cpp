@@ -1567,6 +1567,308 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   return first;
 }
 
+// ---------------------------------------------------------------- gradient
+// refl_sign_grad: the forward iteration of refl_sign (FP64 / FP32) with the
+// derivative of its m steps, by a checkpointed reverse sweep or by forward
+// tangents (see include/refl.h for the recurrences).
+struct GradWork {
+  int d = 0, dp = 0, ntiles = 0, nfull = 0, c = 1, nck = 0;
+  bool fp64 = true;
+  double *Hf = nullptr, *scal = nullptr, *rowsum = nullptr, *partials = nullptr;
+  int2 *tiles = nullptr, *full = nullptr;
+  void *Gs = nullptr, *Gb[2] = {nullptr, nullptr}, *Pn = nullptr, *ring[2] = {nullptr, nullptr};
+  std::vector<void*> ck, xs, ns;  // checkpoints, segment iterates, segment N
+};
+
+int grad_cap(const refl_params_t& p) { return p.fixed_steps > 0 ? p.fixed_steps : p.max_iter; }
+
+size_t grad_layout(GradWork& g, void* base, int64_t d, const refl_params_t& p) {
+  Carve c(base);
+  g.fp64 = p.precision == REFL_PREC_FP64;
+  const size_t es = g.fp64 ? sizeof(double) : sizeof(float);
+  g.d = (int)d;
+  g.dp = (int)round_up(d, TILE);
+  const int nt = g.dp / TILE;
+  g.ntiles = nt * (nt + 1) / 2;
+  g.nfull = nt * nt;
+  const int cap = grad_cap(p);
+  const bool reverse = p.grad_mode == REFL_GRAD_REVERSE;
+  g.c = 1;
+  if (reverse)
+    g.c = p.ckpt_every > 0 ? std::min(p.ckpt_every, cap)
+                           : std::max(1, (int)std::ceil(std::sqrt((double)cap)));
+  g.nck = reverse ? cap / g.c + 1 : 0;
+  const size_t n2 = (size_t)g.dp * g.dp;
+  g.scal = c.take<double>(SC_COUNT);
+  g.tiles = c.take<int2>(g.ntiles);
+  g.full = c.take<int2>(g.nfull);
+  g.partials = c.take<double>(std::max(g.nfull, dot_partials()));
+  g.rowsum = c.take<double>(2 * (size_t)g.dp);
+  g.Hf = c.take<double>(n2);
+  g.Gs = c.take<char>(es * n2);
+  g.Gb[0] = c.take<char>(es * n2);
+  g.Gb[1] = c.take<char>(es * n2);
+  g.Pn = c.take<char>(es * n2);
+  g.ring[0] = c.take<char>(es * n2);
+  g.ring[1] = c.take<char>(es * n2);
+  g.ck.assign(g.nck, nullptr);
+  for (auto& q : g.ck) q = c.take<char>(es * n2);
+  g.xs.assign(reverse ? g.c : 0, nullptr);
+  for (auto& q : g.xs) q = c.take<char>(es * n2);
+  g.ns.assign(reverse ? g.c : 1, nullptr);
+  for (auto& q : g.ns) q = c.take<char>(es * n2);
+  return c.off + 256;
+}
+
+// Every (I, J) of the nt x nt tile grid, row bands of 4 as build_tiles_nt,
+// cut into 8 consecutive pieces for the 8 XCDs.
+void build_tiles_full(int nt, std::vector<int2>& host) {
+  std::vector<int2> order;
+  for (int b0 = 0; b0 < nt; b0 += 4)
+    for (int J = 0; J < nt; ++J)
+      for (int I = b0; I < std::min(b0 + 4, nt); ++I) order.push_back(make_int2(I, J));
+  const int T = (int)order.size();
+  int start[8], s0 = 0;
+  for (int x = 0; x < 8; ++x) {
+    start[x] = s0;
+    s0 += (T - x + 7) / 8;
+  }
+  host.resize(T);
+  for (int b = 0; b < T; ++b) host[b] = order[start[b % 8] + b / 8];
+}
+
+refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                        const refl_params_t* pin, const double* dG, int64_t ldg, double* dGrad,
+                        int64_t ldgr, double* loss, double* dR, int64_t ldr, refl_info_t* info) {
+  const double t_start = now_ms();
+  refl_status_t rs = check_params(h, d, pin);
+  if (rs != REFL_OK) return rs;
+  if (!dH || ldh < d) return fail(h, REFL_ERR_INVALID_ARG, "H is NULL or ldh < d");
+  if (!dG || ldg < d) return fail(h, REFL_ERR_INVALID_ARG, "G is NULL or ldg < d");
+  if (!dGrad || ldgr < d) return fail(h, REFL_ERR_INVALID_ARG, "gradient output is NULL or ld < d");
+  if (dR && ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "ldr < d");
+  const refl_params_t p = *pin;
+  if (p.precision == REFL_PREC_MIXED)
+    return fail(h, REFL_ERR_UNSUPPORTED, "refl_sign_grad runs FP64 or FP32");
+  if (p.shift_mode != REFL_SHIFT_GIVEN)
+    return fail(h, REFL_ERR_UNSUPPORTED, "refl_sign_grad needs a given shift");
+  if (p.grad_mode != REFL_GRAD_REVERSE && p.grad_mode != REFL_GRAD_TANGENT)
+    return fail(h, REFL_ERR_INVALID_ARG, "bad grad_mode");
+  if (p.ckpt_every < 0) return fail(h, REFL_ERR_INVALID_ARG, "ckpt_every must be >= 0");
+  refl_info_t inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.lam_k = inf.lam_k1 = inf.eps = inf.margin = NaN;
+  inf.commutator_fro = inf.dk_bound = inf.rho = inf.gamma = NaN;
+  inf.index_j = -1;
+  inf.s = p.s;
+  HIPCHK(hipSetDevice(h->device));
+  GradWork g;
+  const size_t need = grad_layout(g, nullptr, d, p);
+  void* base = nullptr;
+  rs = ensure_workspace(h, need, &base);
+  if (rs != REFL_OK) return rs;
+  grad_layout(g, base, d, p);
+  hipStream_t st = h->stream;
+  double* hsc = h->pinned;
+  const bool fp64 = g.fp64, reverse = p.grad_mode == REFL_GRAD_REVERSE;
+  const int dd = (int)d, dp = g.dp;
+
+  // ---- set-up ----
+  {
+    std::vector<int2> tl;
+    build_tiles_nt(dp / TILE, tl);
+    HIPCHK(hipMemcpyAsync(g.tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice, st));
+    std::vector<int2> tf;
+    build_tiles_full(dp / TILE, tf);
+    HIPCHK(hipMemcpyAsync(g.full, tf.data(), sizeof(int2) * tf.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // the host vectors go out of scope
+  }
+  HIPCHK(launch_mirror_upper(dH, ldh, dd, g.Hf, dp, st));
+  HIPCHK(launch_scale_inf(g.Hf, dp, dd, p.s, p.scale_mode == REFL_SCALE_FRO,
+                          p.scale_mode == REFL_SCALE_GIVEN, p.alpha, g.rowsum, g.scal, st));
+  void* X0 = reverse ? g.ck[0] : g.ring[0];
+  if (fp64) {
+    HIPCHK(launch_init_x0_f64(g.Hf, dp, dd, p.s, g.scal, (double*)X0, st));
+    HIPCHK(launch_trace_f64((const double*)X0, dp, dd, g.scal, SC_TRACE, st));
+    HIPCHK(launch_sym_in_f64(dG, ldg, dd, nullptr, (double*)g.Gs, dp, st));
+    if (!reverse) HIPCHK(launch_sym_in_f64(dG, ldg, dd, g.scal, (double*)g.Gb[0], dp, st));
+  } else {
+    HIPCHK(launch_init_x0_f32(g.Hf, dp, dd, p.s, g.scal, (float*)X0, st));
+    HIPCHK(launch_trace_f32((const float*)X0, dp, dd, g.scal, SC_TRACE, st));
+    HIPCHK(launch_sym_in_f32(dG, ldg, dd, nullptr, (float*)g.Gs, dp, st));
+    if (!reverse) HIPCHK(launch_sym_in_f32(dG, ldg, dd, g.scal, (float*)g.Gb[0], dp, st));
+  }
+  HIPCHK(hipMemcpyAsync(hsc, g.scal, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hsc[SC_NONFINITE] > 0.0) return fail(h, REFL_ERR_NOT_FINITE, "H holds non-finite entries");
+  inf.alpha = hsc[SC_ALPHA];
+  if (!(inf.alpha > 0.0) || !std::isfinite(inf.alpha))
+    return fail(h, REFL_ERR_NOT_FINITE, "scale alpha=%g is not a positive finite number", inf.alpha);
+  const double t_setup = now_ms();
+
+  // ---- products ----
+  size_t nev = 0;
+  auto timed = [&](bool on) -> hipError_t {
+    if (!p.timing) return hipSuccess;
+    if (on) {
+      while (h->ev.size() < 2 * (nev + 1)) {
+        hipEvent_t e;
+        hipError_t er = hipEventCreate(&e);
+        if (er != hipSuccess) return er;
+        h->ev.push_back(e);
+      }
+      return hipEventRecord(h->ev[2 * nev], st);
+    }
+    hipError_t er = hipEventRecord(h->ev[2 * nev + 1], st);
+    ++nev;
+    return er;
+  };
+  auto residual = [&](void* X, void* N) -> hipError_t {
+    return fp64 ? launch_sym_gemm_f64(GEMM_RESIDUAL, (double*)X, (double*)X, nullptr, (double*)N,
+                                      dp, dd, dp, g.tiles, g.ntiles, g.partials, st)
+                : launch_sym_gemm_f32(GEMM_RESIDUAL, (float*)X, (float*)X, nullptr, (float*)N, dp,
+                                      dd, dp, g.tiles, g.ntiles, g.partials, st);
+  };
+  auto update = [&](void* X, void* N, void* out) -> hipError_t {
+    return fp64 ? launch_sym_gemm_f64(GEMM_UPDATE, (double*)X, (double*)N, (double*)X,
+                                      (double*)out, dp, dd, dp, g.tiles, g.ntiles, g.partials, st)
+                : launch_sym_gemm_f32(GEMM_UPDATE, (float*)X, (float*)N, (float*)X, (float*)out, dp,
+                                      dd, dp, g.tiles, g.ntiles, g.partials, st);
+  };
+  // Gout = derivative map at X (with N = I - X^2) applied to Gin.
+  auto dstep = [&](void* X, void* N, void* Gin, void* Gout) -> refl_status_t {
+    HIPCHK(timed(true));
+    if (fp64) {
+      HIPCHK(launch_sym_gemm_f64(GEMM_PLAIN_NEG, (double*)X, (double*)Gin, nullptr, (double*)g.Pn,
+                                 dp, dd, dp, g.full, g.nfull, g.partials, st));
+      HIPCHK(launch_adjoint_step_f64((double*)Gin, (double*)N, (double*)g.Pn, (double*)X,
+                                     (double*)Gout, dp, dd, dp, g.tiles, g.ntiles, g.partials, st));
+    } else {
+      HIPCHK(launch_sym_gemm_f32(GEMM_PLAIN_NEG, (float*)X, (float*)Gin, nullptr, (float*)g.Pn, dp,
+                                 dd, dp, g.full, g.nfull, g.partials, st));
+      HIPCHK(launch_adjoint_step_f32((float*)Gin, (float*)N, (float*)g.Pn, (float*)X,
+                                     (float*)Gout, dp, dd, dp, g.tiles, g.ntiles, g.partials, st));
+    }
+    HIPCHK(timed(false));
+    return REFL_OK;
+  };
+
+  // ---- forward, with the tangent beside it in tangent mode ----
+  const bool fixed = p.fixed_steps > 0;
+  const int cap = grad_cap(p);
+  std::vector<double> hist;
+  double trace_cur = hsc[SC_TRACE];
+  bool converged = false;
+  int m = 0;
+  void* cur = X0;
+  void* Tcur = g.Gb[0];  // tangent mode: Xdot_j (Xdot_0 = sym(G)/alpha)
+  int tg = 1;
+  for (;; ++m) {
+    void* N = g.ns[0];
+    HIPCHK(residual(cur, N));
+    HIPCHK(launch_reduce_sum(g.partials, g.ntiles, g.scal, SC_RESID2, st));
+    HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, g.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double resid = std::sqrt(std::fmax(hsc[SC_RESID2], 0.0));
+    inf.resid_fro = resid;
+    inf.trace = trace_cur;
+    hist.push_back(resid);
+    if (!std::isfinite(resid)) {
+      inf.ns_steps = m;
+      if (info) *info = inf;
+      return fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", m);
+    }
+    bool stop = false;
+    if (fixed) {
+      if (m >= cap) stop = converged = true;
+    } else {
+      const size_t n = hist.size();
+      if (resid < p.tol) stop = converged = true;
+      else if (n >= 3 && resid < 1e-6 && resid > 0.5 * hist[n - 3]) stop = true;
+      else if (m >= cap) stop = true;
+    }
+    if (stop) break;
+    if (!reverse) {
+      rs = dstep(cur, N, Tcur, g.Gb[tg]);
+      if (rs != REFL_OK) return rs;
+      Tcur = g.Gb[tg];
+      tg ^= 1;
+    }
+    void* dst = (reverse && (m + 1) % g.c == 0) ? g.ck[(m + 1) / g.c] : g.ring[(m + 1) & 1];
+    HIPCHK(update(cur, N, dst));
+    HIPCHK(launch_reduce_sum(g.partials, g.ntiles, g.scal, SC_TRACE, st));
+    HIPCHK(hipMemcpyAsync(hsc + SC_TRACE, g.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    trace_cur = hsc[SC_TRACE];
+    cur = dst;
+  }
+  inf.ns_steps = m;
+  inf.index_j = index_certificate(d, inf.resid_fro, inf.trace);
+  if (dR) {
+    if (fp64) HIPCHK(launch_copy_out_f64((const double*)cur, dp, dd, dR, ldr, st));
+    else HIPCHK(launch_copy_out_f32((const float*)cur, dp, dd, dR, ldr, st));
+  }
+  const int64_t n2 = (int64_t)dp * dp;
+  if (fp64) HIPCHK(launch_dot_f64((const double*)g.Gs, (const double*)cur, n2, g.partials, g.scal, SC_SCRATCH, st));
+  else HIPCHK(launch_dot_f32((const float*)g.Gs, (const float*)cur, n2, g.partials, g.scal, SC_SCRATCH, st));
+  HIPCHK(hipMemcpyAsync(hsc + SC_SCRATCH, g.scal + SC_SCRATCH, sizeof(double), hipMemcpyDeviceToHost, st));
+  const double t_fwd = now_ms();
+
+  // ---- reverse sweep over segments of c steps ----
+  if (reverse) {
+    void* Gcur = g.Gs;
+    int gi = 0;
+    const int nseg = (m + g.c - 1) / g.c;
+    std::vector<void*> xj(g.c);
+    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+      const int a = sgm * g.c, b = std::min(a + g.c, m);
+      xj[0] = g.ck[sgm];
+      for (int j = a; j < b; ++j) {
+        HIPCHK(residual(xj[j - a], g.ns[j - a]));
+        if (j + 1 < b) {
+          HIPCHK(update(xj[j - a], g.ns[j - a], g.xs[j + 1 - a]));
+          xj[j + 1 - a] = g.xs[j + 1 - a];
+        }
+      }
+      for (int j = b - 1; j >= a; --j) {
+        rs = dstep(xj[j - a], g.ns[j - a], Gcur, g.Gb[gi]);
+        if (rs != REFL_OK) return rs;
+        Gcur = g.Gb[gi];
+        gi ^= 1;
+      }
+    }
+    if (fp64) HIPCHK(launch_copy_out_scaled_f64((const double*)Gcur, dp, dd, g.scal, dGrad, ldgr, st));
+    else HIPCHK(launch_copy_out_scaled_f32((const float*)Gcur, dp, dd, g.scal, dGrad, ldgr, st));
+  } else {
+    if (fp64) HIPCHK(launch_copy_out_f64((const double*)Tcur, dp, dd, dGrad, ldgr, st));
+    else HIPCHK(launch_copy_out_f32((const float*)Tcur, dp, dd, dGrad, ldgr, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (loss) *loss = hsc[SC_SCRATCH];
+  if (p.timing) {
+    double tot = 0.0;
+    for (size_t i = 0; i < nev; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+      tot += ms;
+    }
+    inf.ms_gemm = tot;
+    inf.gemm_launches = (int)nev;
+  }
+  const double t_end = now_ms();
+  inf.ms_setup = t_setup - t_start;
+  inf.ms_bulk = t_fwd - t_setup;
+  inf.ms_polish = t_end - t_fwd;
+  inf.ms_total = t_end - t_start;
+  if (info) *info = inf;
+  if (!converged)
+    return fail(h, REFL_ERR_NOT_CONVERGED, "no convergence after %d steps (resid %.3e)", m, inf.resid_fro);
+  if (!fixed && p.k > 0 && inf.index_j >= 0 && inf.index_j != p.k)
+    return fail(h, REFL_ERR_NOT_ADMISSIBLE,
+                "index certificate found %d negative eigenvalues of H - sI, not k=%d", inf.index_j, p.k);
+  return REFL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1590,6 +1892,8 @@ refl_status_t refl_params_default(refl_params_t* p) {
   p->lanczos_steps = 0;
   p->seed = 0;
   p->timing = 0;
+  p->grad_mode = REFL_GRAD_REVERSE;
+  p->ckpt_every = 0;
   return REFL_OK;
 }
 
@@ -1750,6 +2054,14 @@ refl_status_t refl_sign_batched(refl_handle_t h, int32_t nprob, const int64_t* d
                                 const int64_t* ldr, refl_info_t* info, refl_status_t* status) {
   if (!h) return REFL_ERR_INVALID_ARG;
   return batched_impl(h, nprob, d, dH, ldh, params, dR, ldr, info, status);
+}
+
+refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                             const refl_params_t* p, const double* dG, int64_t ldg, double* dGrad,
+                             int64_t ldgr, double* loss, double* dR, int64_t ldr,
+                             refl_info_t* info) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  return grad_impl(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info);
 }
 
 const char* refl_status_string(refl_status_t s) {

@@ -22,11 +22,13 @@ STATUS = {0: "REFL_OK", 1: "REFL_ERR_INVALID_ARG", 2: "REFL_ERR_DEVICE", 3: "REF
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 SHIFT = {"given": 0, "lanczos": 1}
 SCALE = {"inf": 0, "given": 1, "lanczos": 2, "fro": 3}
+GRAD_MODE = {"reverse": 0, "tangent": 1}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
            "refl_apply", "refl_sign_apply", "refl_sign_batched",
-           "refl_sign_batched_workspace_size", "refl_status_string", "refl_last_error"]
+           "refl_sign_batched_workspace_size", "refl_sign_grad", "refl_status_string",
+           "refl_last_error"]
 
 
 class refl_params_t(ctypes.Structure):
@@ -37,7 +39,8 @@ class refl_params_t(ctypes.Structure):
                 ("words", ctypes.c_int32), ("polish_sweeps", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32)]
 
 
 class refl_info_t(ctypes.Structure):
@@ -86,6 +89,8 @@ def load(path: str = LIB_PATH):
         "refl_sign_batched": [H, i32, P(i64), P(vp), P(i64), P(refl_params_t), P(vp), P(i64),
                               P(refl_info_t), P(ctypes.c_int)],
         "refl_sign_batched_workspace_size": [H, i32, P(i64), P(refl_params_t), P(ctypes.c_size_t)],
+        "refl_sign_grad": [H, i64, vp, i64, P(refl_params_t), vp, i64, vp, i64, P(dbl), vp, i64,
+                           P(refl_info_t)],
         "refl_status_string": [ctypes.c_int],
         "refl_last_error": [H],
     }
@@ -187,6 +192,20 @@ def refl_sign_batched_workspace_size(h, ds, params) -> int:
     return nb.value
 
 
+def refl_sign_grad(h, d, H_ptr, ldh, params, G_ptr, ldg, grad_ptr, ldgr, R_ptr=None, ldr=0,
+                   check=True):
+    """C call; returns ``(status, loss, info)``."""
+    info = refl_info_t()
+    loss = ctypes.c_double()
+    st = load().refl_sign_grad(h, d, ctypes.c_void_p(H_ptr), ldh, ctypes.byref(params),
+                               ctypes.c_void_p(G_ptr), ldg, ctypes.c_void_p(grad_ptr), ldgr,
+                               ctypes.byref(loss), ctypes.c_void_p(R_ptr or 0), ldr,
+                               ctypes.byref(info))
+    if check:
+        _check(h, st)
+    return st, loss.value, info
+
+
 def refl_status_string(st: int) -> str:
     return load().refl_status_string(st).decode()
 
@@ -245,7 +264,7 @@ class Handle:
 
 def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
                 alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
-                timing=False, scale=None):
+                timing=False, scale=None, grad_mode="reverse", ckpt_every=0):
     """refl_params_t from keyword arguments.  s=None estimates the shift by
     block Lanczos; scale is "inf" (default), "given" (with alpha), "lanczos"
     (1.05 times the Lanczos spectral-radius estimate) or "fro"; k=0 with a
@@ -273,6 +292,8 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     p.lanczos_steps = int(lanczos_steps)
     p.seed = int(seed)
     p.timing = 1 if timing else 0
+    p.grad_mode = GRAD_MODE[grad_mode]
+    p.ckpt_every = int(ckpt_every)
     return p
 
 
@@ -391,6 +412,65 @@ def sign_batched(Hs, ks, ss, handle=None, outs=None, check=True, **kw):
     call = BatchedCall(Hs, ks, ss, Rs, **kw)
     st = call.run(h.h, check=check)
     return Rs, [i.as_dict() for i in call.infos], list(call.status), st
+
+
+def sign_grad(H, G, k, s, handle=None, with_R=False, check=True, **kw):
+    """Gradient of L = <G, R_m(H)> over symmetric perturbations of H (s and
+    the scale fixed).  Returns ``(grad, loss, R or None, info_dict, status)``."""
+    import torch
+    H = _dev_f64(H)
+    G = _dev_f64(G)
+    d = H.shape[0]
+    if G.shape[0] != d or G.stride(1) != 1 or H.stride(1) != 1:
+        raise ValueError("H and G must be d x d with unit column stride")
+    h = handle or Handle(H.device)
+    h.sync_stream()
+    p = make_params(k, s, **kw)
+    grad = torch.empty((d, d), dtype=torch.float64, device=H.device)
+    R = torch.empty((d, d), dtype=torch.float64, device=H.device) if with_R else None
+    st, loss, info = refl_sign_grad(h.h, d, H.data_ptr(), H.stride(0), p, G.data_ptr(), G.stride(0),
+                                    grad.data_ptr(), grad.stride(0),
+                                    R.data_ptr() if R is not None else None,
+                                    R.stride(0) if R is not None else 0, check=check)
+    return grad, loss, R, info.as_dict(), st
+
+
+def _reflsign_class():
+    import torch
+
+    class ReflSign(torch.autograd.Function):
+        """R = sgn(H - sI) (the prescribed-index reflector of refl_sign) as an
+        autograd Function.  forward runs refl_sign; backward runs
+        refl_sign_grad with G = grad_R (the forward iteration is recomputed,
+        so nothing but H is kept) and returns the symmetric gradient: the
+        derivative along symmetric perturbations of H, s and the scale held
+        fixed.  Precision "fp64" or "fp32" for a differentiable call."""
+
+        @staticmethod
+        def forward(ctx, H, k, s, kw):
+            kw = dict(kw or {})
+            R, info, st = sign(H, k, s, **kw)
+            ctx.save_for_backward(H)
+            ctx.k, ctx.s, ctx.kw = k, s, kw
+            return R
+
+        @staticmethod
+        def backward(ctx, gR):
+            (H,) = ctx.saved_tensors
+            kw = dict(ctx.kw)
+            handle = kw.pop("handle", None)
+            grad, _, _, _, _ = sign_grad(H, gR.contiguous(), ctx.k, ctx.s, handle=handle, **kw)
+            return grad, None, None, None
+
+    return ReflSign
+
+
+def __getattr__(name):
+    if name == "ReflSign":
+        cls = _reflsign_class()
+        globals()["ReflSign"] = cls
+        return cls
+    raise AttributeError(name)
 
 
 def estimate_shift(H, k, steps=0, seed=0, handle=None, check=True):

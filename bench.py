@@ -20,6 +20,11 @@ reflector R_k from H resident in HBM to R resident in HBM.
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
 
+With --workload grad it times the gradient of L = <G, R_m(H)> (forward FP64
+iteration to ||X^2 - I||_F < 1e-10 plus the checkpointed reverse sweep) on a
+planted d = 2048, k = 10, gap 0.05 Hessian with G symmetric N(0, 1), and
+prints its own JSON line.
+
 With --workload batched it times the batched solve instead: 256 planted
 problems (d uniform over 128/256/512/1024, k uniform in 1..16, relative gap
 log-uniform in [1e-3, 1e-1], midpoint shifts, seed 0) in FP32 with the FP64
@@ -80,7 +85,7 @@ def main():
     ap.add_argument("--lanczos-steps", type=int, default=3, help="timed solves with the shift estimated")
     ap.add_argument("--cg-tol", type=float, default=None, help="inner solve tolerance (library default if unset)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("allen_cahn", "batched"), default="allen_cahn")
+    ap.add_argument("--workload", choices=("allen_cahn", "batched", "grad"), default="allen_cahn")
     ap.add_argument("--batch", type=int, default=256, help="problems of the batched workload")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
@@ -94,6 +99,9 @@ def main():
 
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "grad":
+        bench_grad(args)
         return
 
     import torch
@@ -263,6 +271,102 @@ def main():
 FP32_PEAK = 157.3e12
 
 
+def bench_grad(args):
+    """Gradients/s of refl_sign_grad on the differentiation workload, the
+    derivative products against the FP64 MFMA peak, and the oracle's reverse
+    sweep on the host cores."""
+    import torch
+    from paper_2605_24840_amd import inputs, refl
+
+    d, k, gap, seed = 2048, 10, 0.05, args.seed
+    H, lam, Q = inputs.planted_hessian(d, k, gap, seed)
+    G = inputs.symmetric_normal(d, seed)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    dev = torch.device("cuda", 0)
+    Hg, Gg = torch.from_numpy(H).to(dev), torch.from_numpy(G).to(dev)
+    h = refl.Handle(dev)
+    kw = dict(precision="fp64", tol=1e-10, timing=True)
+
+    def run():
+        g, loss, _, info, st = refl.sign_grad(Hg, Gg, k, s, handle=h, check=False, **kw)
+        if st != 0:
+            raise RuntimeError(f"refl_sign_grad returned {refl.STATUS[st]}: {refl.refl_last_error(h.h)}")
+        return g, loss, info
+
+    for i in range(args.warmup):
+        _, _, info = run()
+        log(f"warmup {i}: {info['ms_total']:.2f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [run() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    g, loss, info = runs[-1]
+    m, alpha = info["ns_steps"], info["alpha"]
+    deriv_flop = 5.0 * float(d) ** 3 * m      # per gradient: m steps of -X Gb (2 d^3) + three-pair (3 d^3)
+    gemm_s = np.mean([r[2]["ms_gemm"] for r in runs]) / 1e3
+    achieved = deriv_flop / gemm_s
+    # Directional derivative against central differences (alpha, m fixed).
+    E = inputs.symmetric_normal(d, seed + 1)
+    E /= np.linalg.norm(E)
+    Eg = torch.from_numpy(E).to(dev)
+    tstep = 1e-4
+
+    def L(Hx):
+        Rx, _, st = refl.sign(Hx, k, s, handle=h, alpha=alpha, fixed_steps=m)
+        return float((Gg * Rx).sum())
+    fd = (L(Hg + tstep * Eg) - L(Hg - tstep * Eg)) / (2 * tstep)
+    dd = float((g * Eg).sum())
+    fd_rel = abs(dd - fd) / abs(fd)
+    log(f"grad: {1e3 * t_step:.2f} ms per gradient, m={m}, forward {info['ms_bulk']:.2f} ms, "
+        f"derivative {info['ms_polish']:.2f} ms; derivative products {1e3 * gemm_s:.2f} ms = "
+        f"{achieved / 1e12:.1f} TFLOP/s; central-difference check {fd_rel:.2e}")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        X0 = (H - s * np.eye(d)) / alpha
+        tc = time.perf_counter()
+        X1 = oracle.ns_iterate(X0)
+        t_fwd = time.perf_counter() - tc
+        tc = time.perf_counter()
+        oracle.ns_step_derivative(X1, G)
+        t_rev = time.perf_counter() - tc
+        t_cpu = m * (t_fwd + t_rev)
+        cpu = {"value": 1.0 / t_cpu, "unit": "gradients/s", "cores": oracle.oracle_threads(),
+               "kind": "oracle",
+               "sample": f"one forward step ({t_fwd:.2f} s) and one reverse step ({t_rev:.2f} s) of the "
+                         f"oracle's FP64 recurrences at d={d}, scaled by the {m} steps"}
+        log(f"cpu oracle: {t_fwd:.2f} s forward step, {t_rev:.2f} s reverse step")
+    h.close()
+    out = {
+        "metric": "gradients/s of <G, R_m(H)>, d=2048 (FP64 forward + checkpointed reverse)",
+        "value": 1.0 / t_step,
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "planted_gradient", "d": d, "k": k, "gap": gap, "seed": seed,
+                   "G": "symmetric N(0,1)", "tol": kw["tol"], "ckpt_every": "ceil(sqrt(max_iter))"},
+        "ns_steps": m,
+        "ms_forward": info["ms_bulk"],
+        "ms_derivative": info["ms_polish"],
+        "central_difference_rel": fd_rel,
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": FP64_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK, "traffic": None,
+                     "kernel": "k_sym_gemm_f<double, GEMM_PLAIN_NEG> + k_adjoint_step<double>",
+                     "launches": info["gemm_launches"], "avg_launch_ms": 1e3 * gemm_s / max(info["gemm_launches"], 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_batched(args):
     """Batched planted solves (FP32 bulk, FP64 certificate): problems/s of one
     refl_sign_batched call with the inputs resident in HBM, the same problems
@@ -296,25 +400,25 @@ def bench_batched(args):
         st = call.run(h.h, check=False)
         if st != 0:
             raise RuntimeError(f"refl_sign_batched returned {refl.STATUS[st]}: {refl.refl_last_error(h.h)}")
-        return [i.as_dict() for i in call.infos]
+        return call.infos[0].ms_gemm   # no Python objects are built inside the timed loop
 
     for i in range(args.warmup):
-        infos = run_batch()
-        log(f"warmup {i}: {infos[0]['ms_total']:.2f} ms")
+        run_batch()
+        log(f"warmup {i}: {call.infos[0].ms_total:.2f} ms")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [run_batch() for _ in range(args.steps)]
+    gemm_ms = [run_batch() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / args.steps
-    infos = runs[-1]
+    infos = [i.as_dict() for i in call.infos]
     steps = [i["ns_steps"] for i in infos]
     # Algorithmic work of the grouped FP32 products: a symmetric d x d
     # product is d^3 multiply-adds' worth of flops counted once (d^3 flops
     # for the upper half, as for the single-problem products); problem p
     # runs steps + 1 RESIDUAL and steps UPDATE products.
     flop = sum((2 * st + 1) * float(d) ** 3 for st, d in zip(steps, ds))
-    gemm_s = np.mean([r[0]["ms_gemm"] for r in runs]) / 1e3
-    launches = runs[-1][0]["gemm_launches"]
+    gemm_s = float(np.mean(gemm_ms)) / 1e3
+    launches = infos[0]["gemm_launches"]
     achieved = flop / gemm_s
     errs = {}
     for d, (p, H, Q) in sorted(sample.items()):

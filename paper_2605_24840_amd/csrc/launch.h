@@ -125,9 +125,11 @@ hipError_t launch_batch_setup(int fp64, const BatchDesc* desc, int ng, const int
                               int mirror_blocks, const int* row_begin, int row_blocks,
                               const int* init_begin, int init_blocks, double* trace,
                               hipStream_t st);
-// Copy of X[par] of problems ids[g] (g < ng; ids == null: g) by rows:
-// to_hf == 0 writes R (d rows per problem), to_hf == 1 the FP64 copy Hf
-// (dp rows); begin is the prefix array of those row counts.
+// Copy of X[par] of problems ids[g] (g < ng; ids == null: g) by groups of
+// BATCH_COPY_ROWS rows: to_hf == 0 writes R (d rows per problem), to_hf == 1
+// the FP64 copy Hf (dp rows); begin is the prefix array of the per-problem
+// block counts ceil(rows / BATCH_COPY_ROWS).
+constexpr int BATCH_COPY_ROWS = 8;
 hipError_t launch_batch_copy(int fp64, const BatchDesc* desc, const int* begin, const int* ids,
                              int ng, int nblocks_total, int to_hf, hipStream_t st);
 // out[slot ? slot[q] : q] = sum of partials[begin[q] .. begin[q + 1]), q < nq,

@@ -352,8 +352,8 @@ __global__ __launch_bounds__(256) void k_batch_trace(const BatchDesc* __restrict
   trace_block(reinterpret_cast<const T*>(q.X[q.par]), q.dp, q.d, out + p, red);
 }
 
-// Blocks: one row each.  to_hf == 0: R = X[par] (d x d, ldr); to_hf == 1:
-// Hf = X[par] over the whole padded dp x dp matrix (FP64 copy).
+// Blocks: BATCH_COPY_ROWS rows each.  to_hf == 0: R = X[par] (d x d, ldr);
+// to_hf == 1: Hf = X[par] over the whole padded dp x dp matrix (FP64 copy).
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_copy(const BatchDesc* __restrict__ desc,
                                                     const int* __restrict__ begin,
@@ -361,11 +361,14 @@ __global__ __launch_bounds__(256) void k_batch_copy(const BatchDesc* __restrict_
                                                     int to_hf) {
   const int g = find_group(begin, ng, blockIdx.x);
   const BatchDesc q = desc[ids ? ids[g] : g];
-  const int i = blockIdx.x - begin[g];
-  const T* X = reinterpret_cast<const T*>(q.X[q.par]) + (int64_t)i * q.dp;
   const int n = to_hf ? q.dp : q.d;
-  double* dst = to_hf ? q.Hf + (int64_t)i * q.dp : q.R + (int64_t)i * q.ldr;
-  for (int j = threadIdx.x; j < n; j += 256) dst[j] = (double)X[j];
+  const int i0 = (blockIdx.x - begin[g]) * BATCH_COPY_ROWS;
+  const int i1 = min(i0 + BATCH_COPY_ROWS, n);
+  for (int i = i0; i < i1; ++i) {
+    const T* X = reinterpret_cast<const T*>(q.X[q.par]) + (int64_t)i * q.dp;
+    double* dst = to_hf ? q.Hf + (int64_t)i * q.dp : q.R + (int64_t)i * q.ldr;
+    for (int j = threadIdx.x; j < n; j += 256) dst[j] = (double)X[j];
+  }
 }
 
 // ------------------------------------------------------- thin products

@@ -1499,9 +1499,10 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     int* rbeg = bp.cbeg;
     int* hbeg = rbeg + (nprob + 1);
     rbeg[0] = hbeg[0] = 0;
+    constexpr int CR = BATCH_COPY_ROWS;
     for (int q = 0; q < nd; ++q) {
-      rbeg[q + 1] = rbeg[q] + bw.pr[done[q]].d;
-      hbeg[q + 1] = hbeg[q] + bw.pr[done[q]].dp;
+      rbeg[q + 1] = rbeg[q] + (bw.pr[done[q]].d + CR - 1) / CR;
+      hbeg[q + 1] = hbeg[q] + (bw.pr[done[q]].dp + CR - 1) / CR;
     }
     HIPCHK(hipMemcpyAsync(bw.desc, bp.desc, sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bw.cbeg, bp.cbeg, sizeof(int) * 2 * (nprob + 1), hipMemcpyHostToDevice, st));

@@ -273,6 +273,67 @@ refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double *dH, int64
                              double *dGrad, int64_t ldgr, double *loss, double *dR, int64_t ldr,
                              refl_info_t *info);
 
+/* Shift policies over a sequence of Hessians H_0, H_1, ... (Alg. 4.3 step 4,
+ * with the certificates of Prop. 4.2).  A policy object keeps the state of
+ * the sequence; refl_policy_shift returns the shift for the current H.
+ *
+ *   MIDPOINT  every call estimates lam_k, lam_k+1 and eps by block Lanczos
+ *             (as refl_estimate_shift) and returns the midpoint (Prop. 4.1).
+ *   DAMPED    every call estimates; s = (1 - beta) s_prev + beta midpoint,
+ *             clipped into [lam_k + eps + c w, lam_k+1 - eps - c w] with
+ *             w = (lam_k+1 - lam_k)/2 - eps the certified half-width and
+ *             c = clip in (0, 1]; the first call returns the midpoint.
+ *   REUSE     (reuse/refresh) the shift of the last refresh is kept while its
+ *             certified margin at the current H,
+ *               min(s - lam_k, lam_k+1 - s) - eps - ||H - H_ref||_F
+ *             (Prop. 4.2 with the Weyl bound, the drift measured from the
+ *             Hessian H_ref of the last refresh), exceeds tau times the
+ *             estimated half-gap of that refresh; otherwise the call
+ *             refreshes: it estimates on H, returns the new midpoint and
+ *             keeps a device copy of H's upper triangle as H_ref.
+ *
+ * A returned shift is certified admissible (REFL_OK) when its margin (in
+ * info) is positive; otherwise the status is REFL_ERR_NOT_ADMISSIBLE (or
+ * REFL_ERR_NO_GAP from the estimate) and the policy keeps no state from the
+ * call.  The policy owns a d x d FP64 device copy (REUSE only) and is tied to
+ * the handle's device; calls on one policy are not thread-safe. */
+typedef enum {
+  REFL_POLICY_MIDPOINT = 0,
+  REFL_POLICY_DAMPED = 1,
+  REFL_POLICY_REUSE = 2
+} refl_policy_mode_t;
+
+typedef struct refl_policy_s *refl_policy_t;
+
+typedef struct {
+  int32_t mode;           /* refl_policy_mode_t */
+  int32_t k;              /* target index, 1 <= k <= d-1 */
+  double beta;            /* DAMPED: weight of the new midpoint, 0 < beta <= 1 */
+  double clip;            /* DAMPED: 0 < clip <= 1 (see above) */
+  double tau;             /* REUSE: 0 <= tau < 1 */
+  int32_t lanczos_steps;  /* cap on block Lanczos steps per refresh (0 = automatic) */
+  uint64_t seed;          /* Lanczos start block */
+} refl_policy_params_t;
+
+typedef struct {
+  double s;               /* shift returned */
+  double lam_k, lam_k1;   /* estimates in force (from this call or the last refresh) */
+  double eps;             /* their residual bound */
+  double margin;          /* certified margin of s at this H (Prop. 4.2) */
+  double drift;           /* REUSE: ||H - H_ref||_F (NaN on a refresh and in other modes) */
+  int32_t refreshed;      /* 1 if this call ran block Lanczos */
+  int32_t lanczos_steps;  /* block steps of this call's estimate (0 if reused) */
+  int32_t calls, refreshes; /* totals over the policy's life */
+} refl_policy_info_t;
+
+refl_status_t refl_policy_create(refl_handle_t h, const refl_policy_params_t *pp,
+                                 refl_policy_t *out);
+refl_status_t refl_policy_destroy(refl_policy_t pol);
+/* Shift for the current H (d x d FP64, upper triangle, ldh).  info may be
+ * NULL.  Device work runs on the handle's stream, which is synchronised. */
+refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, const double *dH,
+                                int64_t ldh, double *s, refl_policy_info_t *info);
+
 /* Static strings; never NULL. */
 const char *refl_status_string(refl_status_t s);
 const char *refl_last_error(refl_handle_t h);

@@ -21,7 +21,7 @@ __all__ = [
     "ns_depth_scalar", "inf_norm_shifted", "fro_norm_shifted", "admissible", "certificates",
     "spectral_norm_sym", "splitmix64", "start_block", "lanczos_block_size",
     "lanczos_check_steps", "block_lanczos", "ns_step_derivative", "ns_adjoint", "ns_tangent",
-    "ns_poly_derivative", "ns_frechet_dk", "sign_frechet_dk",
+    "ns_poly_derivative", "ns_frechet_dk", "sign_frechet_dk", "policy_step",
 ]
 
 
@@ -255,6 +255,44 @@ def sign_frechet_dk(H, s: float, E):
     F = np.where(opp, 2.0 / np.where(opp, np.abs(a[:, None] - a[None, :]), 1.0), 0.0)
     B = V.T @ np.asarray(E, dtype=np.float64) @ V
     return V @ (F * B) @ V.T
+
+
+# ---------------------------------------------------------- shift policies
+def policy_step(mode: str, state, estimate, drift=None, beta: float = 0.5, clip: float = 0.25,
+                tau: float = 0.5):
+    """One call of a shift policy of Alg. 4.3 (step 4) over a sequence of
+    Hessians, with the certificates of Prop. 4.2.
+
+    ``state`` is None or a dict with the shift in force ``s`` and the
+    estimates of the last refresh ``lam_k``, ``lam_k1``, ``eps``.
+    ``estimate()`` returns (lam_k_hat, lam_k1_hat, eps) for the current H and
+    is called only when the policy refreshes.  ``drift`` is a bound on
+    ||H - H_ref||_2 (H_ref the Hessian of the last refresh), used by 'reuse'.
+
+    * 'midpoint': refresh every call, s = (lam_k_hat + lam_k1_hat)/2 (Prop. 4.1).
+    * 'damped': refresh every call, s = (1 - beta) s_prev + beta * midpoint,
+      clipped into [lam_k_hat + eps + clip w, lam_k1_hat - eps - clip w] with
+      w = (lam_k1_hat - lam_k_hat)/2 - eps (midpoint on the first call).
+    * 'reuse': keep s while min(s - lam_k, lam_k1 - s) - eps - drift exceeds
+      tau (lam_k1 - lam_k)/2 (Prop. 4.2, second statement, with Weyl's bound),
+      else refresh to the midpoint.
+
+    Returns dict(s, margin, refreshed, state); margin is the certified lower
+    bound on the distance from s to the true gap endpoints, and state is None
+    when the shift is not certified (margin <= 0)."""
+    if mode == "reuse" and state is not None:
+        margin = min(state["s"] - state["lam_k"], state["lam_k1"] - state["s"]) - state["eps"] - drift
+        if margin > tau * 0.5 * (state["lam_k1"] - state["lam_k"]):
+            return {"s": state["s"], "margin": margin, "refreshed": False, "state": dict(state)}
+    lk, lk1, eps = estimate()
+    s = 0.5 * (lk + lk1)
+    w = 0.5 * (lk1 - lk) - eps
+    if mode == "damped" and state is not None and w > 0.0:
+        raw = (1.0 - beta) * state["s"] + beta * s
+        s = min(max(raw, lk + eps + clip * w), lk1 - eps - clip * w)
+    margin = min(s - lk, lk1 - s) - eps
+    new = {"s": s, "lam_k": lk, "lam_k1": lk1, "eps": eps} if margin > 0.0 else None
+    return {"s": s, "margin": margin, "refreshed": True, "state": new}
 
 
 def fro_norm_shifted(H, s: float) -> float:

@@ -100,6 +100,16 @@ hipError_t launch_dot_f64(const double* A, const double* B, int64_t n, double* p
 hipError_t launch_dot_f32(const float* A, const float* B, int64_t n, double* partials,
                           double* scal, int slot, hipStream_t st);
 
+// ---- shift policy ----
+// scal[slot] = ||A - B||_F^2 for the symmetric matrices given by their upper
+// triangles; partials: diff_fro_partials(d) doubles.
+int diff_fro_partials(int d);
+hipError_t launch_diff_fro_upper(const double* A, int64_t lda, const double* B, int64_t ldb, int d,
+                                 double* partials, double* scal, int slot, hipStream_t st);
+// Upper triangle of B = that of A.
+hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ldb, int d,
+                             hipStream_t st);
+
 // Per-problem descriptor of the batched set-up and output kernels.
 struct BatchDesc {
   const double* H;   // input, upper triangle read

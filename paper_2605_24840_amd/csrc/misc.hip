@@ -278,6 +278,37 @@ __global__ __launch_bounds__(256) void k_dot(const T* __restrict__ A, const T* _
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// ------------------------------------------------------------ shift policy
+// partials[block] = sum over the block's rows i of
+//   sum_{j >= i} w_ij (A_ij - B_ij)^2,  w = 1 on the diagonal, 2 above,
+// i.e. ||A - B||_F^2 of the symmetric matrices whose upper triangles are
+// given.  One wave per row, 4 rows per block.
+__global__ __launch_bounds__(256) void k_diff_fro_upper(const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ B, int64_t ldb,
+                                                        int d, double* __restrict__ partials) {
+  __shared__ double red[4];
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  double acc = 0.0;
+  if (row < d) {
+    const double* a = A + (int64_t)row * lda;
+    const double* b = B + (int64_t)row * ldb;
+    for (int j = row + lane; j < d; j += 64) {
+      const double e = a[j] - b[j];
+      acc += (j == row ? 1.0 : 2.0) * e * e;
+    }
+  }
+  const double t = block_sum_256(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// B (upper triangle, ldb) = A (upper triangle, lda).
+__global__ __launch_bounds__(256) void k_copy_upper(const double* __restrict__ A, int64_t lda,
+                                                    double* __restrict__ B, int64_t ldb, int d) {
+  const int row = blockIdx.y;
+  for (int j = row + blockIdx.x * 256 + threadIdx.x; j < d; j += gridDim.x * 256)
+    B[(int64_t)row * ldb + j] = A[(int64_t)row * lda + j];
+}
+
 // ------------------------------------------------- batched set-up / output
 // Grouped forms of the kernels above over many problems (one descriptor per
 // problem): the blocks of problem ids[g] (or g) are begin[g] .. begin[g+1),
@@ -952,6 +983,20 @@ hipError_t launch_dot_f32(const float* A, const float* B, int64_t n, double* par
                           double* scal, int slot, hipStream_t st) {
   hipLaunchKernelGGL(k_dot<float>, dim3(DOT_BLOCKS), dim3(256), 0, st, A, B, n, partials);
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partials, DOT_BLOCKS, scal, slot);
+  return hipGetLastError();
+}
+
+int diff_fro_partials(int d) { return nblocks(d, 4); }
+hipError_t launch_diff_fro_upper(const double* A, int64_t lda, const double* B, int64_t ldb, int d,
+                                 double* partials, double* scal, int slot, hipStream_t st) {
+  const int nb = nblocks(d, 4);
+  hipLaunchKernelGGL(k_diff_fro_upper, dim3(nb), dim3(256), 0, st, A, lda, B, ldb, d, partials);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partials, nb, scal, slot);
+  return hipGetLastError();
+}
+hipError_t launch_copy_upper(const double* A, int64_t lda, double* B, int64_t ldb, int d,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_upper, dim3(nblocks(d, 256), d), dim3(256), 0, st, A, lda, B, ldb, d);
   return hipGetLastError();
 }
 

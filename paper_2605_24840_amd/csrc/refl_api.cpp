@@ -59,6 +59,20 @@ struct refl_handle_s {
   char err[512] = {0};
 };
 
+// State of a shift policy over a sequence of Hessians (refl_policy_*).
+struct refl_policy_s {
+  refl_policy_params_t pp;
+  int device = 0;
+  bool have = false;            // a certified shift from an earlier call is in force
+  double s = 0.0;               // last shift returned
+  double lam_k = 0.0, lam_k1 = 0.0, eps = 0.0;  // estimates of the last refresh
+  int64_t dref = 0;             // order of H_ref
+  double* Href = nullptr;       // REUSE: upper triangle of the Hessian of the last refresh (ld dref)
+  double* dscr = nullptr;       // device partials + one result slot
+  size_t dscr_n = 0;
+  int calls = 0, refreshes = 0;
+};
+
 namespace {
 
 constexpr double NaN = std::numeric_limits<double>::quiet_NaN();
@@ -1870,6 +1884,30 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   return REFL_OK;
 }
 
+// ------------------------------------------------------------ estimation
+// Block Lanczos on H (refl_estimate_shift and the policy refreshes).
+refl_status_t estimate_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh, int k,
+                            int steps, uint64_t seed, LzResult& lr) {
+  if (!dH || ldh < d) return fail(h, REFL_ERR_INVALID_ARG, "H is NULL or ldh < d");
+  refl_params_t p;
+  refl_params_default(&p);
+  p.k = k;
+  p.shift_mode = REFL_SHIFT_LANCZOS;
+  p.lanczos_steps = steps;
+  p.seed = seed;
+  refl_status_t rs = check_params(h, d, &p);
+  if (rs != REFL_OK) return rs;
+  HIPCHK(hipSetDevice(h->device));
+  Work w;
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_ESTIMATE, h->ncu);
+  void* base = nullptr;
+  rs = ensure_workspace(h, need, &base);
+  if (rs != REFL_OK) return rs;
+  layout(w, base, d, p, LAYOUT_ESTIMATE, h->ncu);
+  HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, h->stream));
+  return lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -2007,26 +2045,9 @@ refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, 
                                   int32_t k, int32_t steps, uint64_t seed, double* s,
                                   double* lam_k, double* lam_k1, double* eps, double* rho) {
   if (!h) return REFL_ERR_INVALID_ARG;
-  if (!dH || ldh < d) return fail(h, REFL_ERR_INVALID_ARG, "H is NULL or ldh < d");
   if (!s || !lam_k || !lam_k1 || !eps || !rho) return fail(h, REFL_ERR_INVALID_ARG, "NULL output");
-  refl_params_t p;
-  refl_params_default(&p);
-  p.k = k;
-  p.shift_mode = REFL_SHIFT_LANCZOS;
-  p.lanczos_steps = steps;
-  p.seed = seed;
-  refl_status_t rs = check_params(h, d, &p);
-  if (rs != REFL_OK) return rs;
-  HIPCHK(hipSetDevice(h->device));
-  Work w;
-  const size_t need = layout(w, nullptr, d, p, LAYOUT_ESTIMATE, h->ncu);
-  void* base = nullptr;
-  rs = ensure_workspace(h, need, &base);
-  if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, LAYOUT_ESTIMATE, h->ncu);
-  HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, h->stream));
   LzResult lr;
-  rs = lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr);
+  refl_status_t rs = estimate_impl(h, d, dH, ldh, k, steps, seed, lr);
   if (rs != REFL_OK) return rs;
   *s = lr.s;
   *lam_k = lr.lam_k;
@@ -2063,6 +2084,144 @@ refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double* dH, int64
                              refl_info_t* info) {
   if (!h) return REFL_ERR_INVALID_ARG;
   return grad_impl(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info);
+}
+
+refl_status_t refl_policy_create(refl_handle_t h, const refl_policy_params_t* pp,
+                                 refl_policy_t* out) {
+  if (!h || !pp || !out) return REFL_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (pp->mode < REFL_POLICY_MIDPOINT || pp->mode > REFL_POLICY_REUSE)
+    return fail(h, REFL_ERR_INVALID_ARG, "bad policy mode");
+  if (pp->k < 1) return fail(h, REFL_ERR_INVALID_ARG, "policy k must be >= 1");
+  if (pp->mode == REFL_POLICY_DAMPED &&
+      !(pp->beta > 0.0 && pp->beta <= 1.0 && pp->clip > 0.0 && pp->clip <= 1.0))
+    return fail(h, REFL_ERR_INVALID_ARG, "DAMPED needs 0 < beta <= 1 and 0 < clip <= 1");
+  if (pp->mode == REFL_POLICY_REUSE && !(pp->tau >= 0.0 && pp->tau < 1.0))
+    return fail(h, REFL_ERR_INVALID_ARG, "REUSE needs 0 <= tau < 1");
+  if (pp->lanczos_steps < 0) return fail(h, REFL_ERR_INVALID_ARG, "lanczos_steps must be >= 0");
+  refl_policy_s* pol = new (std::nothrow) refl_policy_s();
+  if (!pol) return fail(h, REFL_ERR_NO_MEMORY, "policy allocation failed");
+  pol->pp = *pp;
+  pol->device = h->device;
+  *out = pol;
+  return REFL_OK;
+}
+
+refl_status_t refl_policy_destroy(refl_policy_t pol) {
+  if (!pol) return REFL_ERR_INVALID_ARG;
+  (void)hipSetDevice(pol->device);
+  (void)hipDeviceSynchronize();
+  if (pol->Href) (void)hipFree(pol->Href);
+  if (pol->dscr) (void)hipFree(pol->dscr);
+  delete pol;
+  return REFL_OK;
+}
+
+refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, const double* dH,
+                                int64_t ldh, double* s_out, refl_policy_info_t* info) {
+  if (!h || !pol || !s_out) return REFL_ERR_INVALID_ARG;
+  if (pol->device != h->device) return fail(h, REFL_ERR_INVALID_ARG, "policy and handle devices differ");
+  if (!dH || ldh < d || d < 2 || pol->pp.k > d - 1)
+    return fail(h, REFL_ERR_INVALID_ARG, "H is NULL, ldh < d, or k outside 1..d-1");
+  HIPCHK(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  const refl_policy_params_t& pp = pol->pp;
+  refl_policy_info_t inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.drift = NaN;
+  pol->calls += 1;
+  // Reuse: certified margin of the kept shift at this H.
+  if (pp.mode == REFL_POLICY_REUSE && pol->have && pol->dref == d) {
+    const size_t need = (size_t)diff_fro_partials((int)d) + 1;
+    if (pol->dscr_n < need) {
+      if (pol->dscr) HIPCHK(hipFree(pol->dscr));
+      pol->dscr = nullptr;
+      pol->dscr_n = 0;
+      if (hipMalloc(&pol->dscr, need * sizeof(double)) != hipSuccess)
+        return fail(h, REFL_ERR_NO_MEMORY, "policy scratch allocation failed");
+      pol->dscr_n = need;
+    }
+    double* slot = pol->dscr + (need - 1);
+    HIPCHK(launch_diff_fro_upper(dH, ldh, pol->Href, pol->dref, (int)d, pol->dscr, slot, 0, st));
+    HIPCHK(hipMemcpyAsync(h->pinned + SC_SCRATCH, slot, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double drift = std::sqrt(std::fmax(h->pinned[SC_SCRATCH], 0.0));
+    const double margin =
+        std::min(pol->s - pol->lam_k, pol->lam_k1 - pol->s) - pol->eps - drift;
+    if (margin > pp.tau * 0.5 * (pol->lam_k1 - pol->lam_k)) {
+      inf.s = pol->s;
+      inf.lam_k = pol->lam_k;
+      inf.lam_k1 = pol->lam_k1;
+      inf.eps = pol->eps;
+      inf.margin = margin;
+      inf.drift = drift;
+      inf.calls = pol->calls;
+      inf.refreshes = pol->refreshes;
+      *s_out = pol->s;
+      if (info) *info = inf;
+      return REFL_OK;
+    }
+  }
+  // Refresh: estimate the gap endpoints on this H.
+  LzResult lr;
+  refl_status_t rs = estimate_impl(h, d, dH, ldh, pp.k, pp.lanczos_steps, pp.seed, lr);
+  pol->refreshes += 1;
+  inf.refreshed = 1;
+  inf.lanczos_steps = lr.steps;
+  inf.calls = pol->calls;
+  inf.refreshes = pol->refreshes;
+  inf.lam_k = lr.lam_k;
+  inf.lam_k1 = lr.lam_k1;
+  inf.eps = lr.eps;
+  if (rs != REFL_OK && rs != REFL_ERR_NOT_ADMISSIBLE && rs != REFL_ERR_NO_GAP) {
+    pol->have = false;
+    return rs;
+  }
+  if (rs == REFL_ERR_NO_GAP) {
+    pol->have = false;
+    inf.s = lr.s;
+    inf.margin = NaN;
+    *s_out = lr.s;
+    if (info) *info = inf;
+    return rs;
+  }
+  double s = lr.s;  // the midpoint (Prop. 4.1)
+  const double w = 0.5 * (lr.lam_k1 - lr.lam_k) - lr.eps;  // certified half-width
+  if (pp.mode == REFL_POLICY_DAMPED && pol->have && w > 0.0) {
+    const double raw = (1.0 - pp.beta) * pol->s + pp.beta * s;
+    const double lo = lr.lam_k + lr.eps + pp.clip * w, hi = lr.lam_k1 - lr.eps - pp.clip * w;
+    s = std::min(std::max(raw, lo), hi);
+  }
+  const double margin = std::min(s - lr.lam_k, lr.lam_k1 - s) - lr.eps;
+  inf.s = s;
+  inf.margin = margin;
+  *s_out = s;
+  const bool ok = margin > 0.0;
+  pol->have = ok;
+  if (ok) {
+    pol->s = s;
+    pol->lam_k = lr.lam_k;
+    pol->lam_k1 = lr.lam_k1;
+    pol->eps = lr.eps;
+    if (pp.mode == REFL_POLICY_REUSE) {
+      if (pol->dref != d || !pol->Href) {
+        if (pol->Href) HIPCHK(hipFree(pol->Href));
+        pol->Href = nullptr;
+        pol->dref = 0;
+        if (hipMalloc(&pol->Href, (size_t)d * d * sizeof(double)) != hipSuccess) {
+          pol->have = false;
+          return fail(h, REFL_ERR_NO_MEMORY, "policy copy of H (%lld^2 doubles) failed", (long long)d);
+        }
+        pol->dref = d;
+      }
+      HIPCHK(launch_copy_upper(dH, ldh, pol->Href, d, (int)d, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  }
+  if (info) *info = inf;
+  if (!ok)
+    return fail(h, REFL_ERR_NOT_ADMISSIBLE, "policy shift margin %.3e is not positive", margin);
+  return REFL_OK;
 }
 
 const char* refl_status_string(refl_status_t s) {

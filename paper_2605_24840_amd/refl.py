@@ -27,8 +27,8 @@ GRAD_MODE = {"reverse": 0, "tangent": 1}
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
            "refl_apply", "refl_sign_apply", "refl_sign_batched",
-           "refl_sign_batched_workspace_size", "refl_sign_grad", "refl_status_string",
-           "refl_last_error"]
+           "refl_sign_batched_workspace_size", "refl_sign_grad", "refl_policy_create",
+           "refl_policy_destroy", "refl_policy_shift", "refl_status_string", "refl_last_error"]
 
 
 class refl_params_t(ctypes.Structure):
@@ -41,6 +41,25 @@ class refl_params_t(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("timing", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32)]
+
+
+class refl_policy_params_t(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("clip", ctypes.c_double), ("tau", ctypes.c_double),
+                ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class refl_policy_info_t(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_double), ("lam_k", ctypes.c_double), ("lam_k1", ctypes.c_double),
+                ("eps", ctypes.c_double), ("margin", ctypes.c_double), ("drift", ctypes.c_double),
+                ("refreshed", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("calls", ctypes.c_int32), ("refreshes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+POLICY = {"midpoint": 0, "damped": 1, "reuse": 2}
 
 
 class refl_info_t(ctypes.Structure):
@@ -91,6 +110,9 @@ def load(path: str = LIB_PATH):
         "refl_sign_batched_workspace_size": [H, i32, P(i64), P(refl_params_t), P(ctypes.c_size_t)],
         "refl_sign_grad": [H, i64, vp, i64, P(refl_params_t), vp, i64, vp, i64, P(dbl), vp, i64,
                            P(refl_info_t)],
+        "refl_policy_create": [H, P(refl_policy_params_t), P(vp)],
+        "refl_policy_destroy": [vp],
+        "refl_policy_shift": [H, vp, i64, vp, i64, P(dbl), P(refl_policy_info_t)],
         "refl_status_string": [ctypes.c_int],
         "refl_last_error": [H],
     }
@@ -204,6 +226,56 @@ def refl_sign_grad(h, d, H_ptr, ldh, params, G_ptr, ldg, grad_ptr, ldgr, R_ptr=N
     if check:
         _check(h, st)
     return st, loss.value, info
+
+
+def refl_policy_create(h, mode, k, beta=0.5, clip=0.25, tau=0.5, lanczos_steps=0, seed=0):
+    pp = refl_policy_params_t(POLICY[mode], int(k), float(beta), float(clip), float(tau),
+                              int(lanczos_steps), int(seed))
+    pol = ctypes.c_void_p()
+    _check(h, load().refl_policy_create(h, ctypes.byref(pp), ctypes.byref(pol)))
+    return pol
+
+
+def refl_policy_destroy(pol):
+    return load().refl_policy_destroy(pol)
+
+
+def refl_policy_shift(h, pol, d, H_ptr, ldh, check=True):
+    """Returns ``(status, s, info)``."""
+    s = ctypes.c_double()
+    info = refl_policy_info_t()
+    st = load().refl_policy_shift(h, pol, d, ctypes.c_void_p(H_ptr), ldh, ctypes.byref(s),
+                                  ctypes.byref(info))
+    if check:
+        _check(h, st)
+    return st, s.value, info
+
+
+class ShiftPolicy:
+    """A shift policy over a sequence of Hessians on one handle (torch tensors)."""
+
+    def __init__(self, handle, mode, k, **kw):
+        self.handle = handle
+        self.pol = refl_policy_create(handle.h, mode, k, **kw)
+
+    def shift(self, H, check=True):
+        """``(s, info_dict, status)`` for the float64 device tensor H."""
+        H = _dev_f64(H)
+        self.handle.sync_stream()
+        st, s, info = refl_policy_shift(self.handle.h, self.pol, H.shape[0], H.data_ptr(),
+                                        H.stride(0), check=check)
+        return s, info.as_dict(), st
+
+    def close(self):
+        if self.pol is not None:
+            refl_policy_destroy(self.pol)
+            self.pol = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def refl_status_string(st: int) -> str:

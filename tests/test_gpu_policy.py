@@ -1,0 +1,100 @@
+"""Shift policies over a sequence of Hessians (refl_policy_*; Alg. 4.3 step 4
+with the certificates of Prop. 4.2) against the oracle's policy.
+
+Sequence: H_n = H_0 + n t D, n = 0..11, with H_0 planted (d = 300, k = 5,
+gap 0.1, seed 40), D a symmetric direction of unit Frobenius norm (seed 41)
+and t = 0.004.  The oracle policy is fed the library's Lanczos estimates on
+the calls where it refreshes and the FP64 drift ||H_n - H_ref||_F from
+numpy; its decisions (refresh or reuse) and shifts must match the library's
+(shifts and margins to 1e-12 relative: the drift norm is summed in another
+order).  Every returned shift must be truly admissible (exact eigenvalues),
+and the sign iteration with it must certify index k.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_24840_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2605_24840_amd import refl
+    refl.load()
+    return refl
+
+
+@pytest.fixture(scope="module")
+def handle(R):
+    h = R.Handle(torch.device("cuda", 0))
+    yield h
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def sequence():
+    d, k = 300, 5
+    H0, lam, Q = inputs.planted_hessian(d, k, 0.1, 40)
+    D = inputs.symmetric_normal(d, 41)
+    D /= np.linalg.norm(D)
+    return [H0 + (n * 0.004) * D for n in range(12)], k
+
+
+@pytest.mark.parametrize("mode,kw", [("midpoint", {}), ("damped", {"beta": 0.4, "clip": 0.25}),
+                                     ("reuse", {"tau": 0.5})])
+def test_policy_sequence_matches_oracle(R, handle, sequence, mode, kw):
+    Hs, k = sequence
+    pol = R.ShiftPolicy(handle, mode, k, **kw)
+    state, Href = None, None
+    refreshes = 0
+    for n, H in enumerate(Hs):
+        Hg = torch.from_numpy(H).to("cuda:0")
+        s, info, st = pol.shift(Hg)
+        drift = float(np.linalg.norm(H - Href)) if Href is not None else None
+
+        def est():
+            assert info["refreshed"] == 1, f"step {n}: the oracle refreshes, the library reused"
+            return info["lam_k"], info["lam_k1"], info["eps"]
+        r = oracle.policy_step(mode, state, est, drift=drift, **kw)
+        _say(f"{mode} n={n}: s={s:.12f} refreshed={info['refreshed']} margin={info['margin']:.3e} "
+             f"drift={info['drift']:.3e} lanczos={info['lanczos_steps']} status={R.STATUS[st]}")
+        assert st == 0
+        assert bool(info["refreshed"]) == r["refreshed"]
+        assert abs(s - r["s"]) <= 1e-12 * abs(r["s"]) + 1e-15
+        assert abs(info["margin"] - r["margin"]) <= 1e-12 * abs(r["margin"])
+        if r["refreshed"]:
+            refreshes += 1
+            Href = H
+        else:
+            assert abs(info["drift"] - drift) <= 1e-12 * drift
+        state = r["state"]
+        w = np.linalg.eigvalsh(H)
+        true = min(s - w[k - 1], w[k] - s)
+        assert true > 0 and true >= info["margin"] - 1e-12
+        Rk, inf2, st2 = R.sign(Hg, k, s, handle=handle, tol=1e-10)
+        assert st2 == 0 and inf2["index_j"] == k
+    assert info["calls"] == len(Hs) and info["refreshes"] == refreshes
+    if mode == "reuse":
+        assert refreshes < len(Hs) - 4
+    else:
+        assert refreshes == len(Hs)
+    pol.close()
+
+
+def test_policy_errors(R, handle):
+    with pytest.raises(R.ReflError):
+        R.ShiftPolicy(handle, "damped", 3, beta=0.0)
+    with pytest.raises(R.ReflError):
+        R.ShiftPolicy(handle, "reuse", 3, tau=1.0)
+    pol = R.ShiftPolicy(handle, "midpoint", 8)
+    H = torch.from_numpy(np.diag(np.linspace(-1.0, 1.0, 8))).to("cuda:0")
+    s, info, st = pol.shift(H, check=False)          # k = 8 > d - 1
+    assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
+    pol.close()

@@ -460,3 +460,74 @@ def test_derivative_of_diagonal_matrix_closed_form():
             want[i, j] = dp[i] / alpha * E[i, i] if i == j else (p[i] - p[j]) / (h[i] - h[j]) * E[i, j]
     got = oracle.ns_tangent(np.diag(h), s, alpha, m, E)
     assert np.max(np.abs(got - want)) < 1e-13
+
+
+# ---------------------------------------------------------- shift policies
+def _true_margin(H, k, s):
+    w = np.linalg.eigvalsh(H)
+    return min(s - w[k - 1], w[k] - s)
+
+
+def test_policy_midpoint_certificate_prop42():
+    """Prop. 4.2, first and last statements: with estimates within eps of the
+    true endpoints, the midpoint's certified margin m_hat - eps is a lower
+    bound on its true margin, and eps < g/2 makes it admissible."""
+    rng = np.random.default_rng(30)
+    H, lam, Q = inputs.planted_hessian(40, 6, 0.2, 31)
+    for _ in range(50):
+        eps = rng.uniform(0.0, 0.099)
+        lk, lk1 = lam[5] + rng.uniform(-eps, eps), lam[6] + rng.uniform(-eps, eps)
+        r = oracle.policy_step("midpoint", None, lambda: (lk, lk1, eps))
+        true = _true_margin(H, 6, r["s"])
+        assert r["refreshed"] and true > 0.0          # eps < g/2: the midpoint is admissible
+        assert true >= r["margin"] - 1e-12            # the certified margin is a lower bound
+        assert (r["state"] is not None) == (r["margin"] > 0.0)
+
+
+def test_policy_reuse_certificate_weyl():
+    """Prop. 4.2, second statement with Weyl's bound: a reused shift stays
+    admissible at H + E with margin >= m_hat - eps - ||E||_F."""
+    rng = np.random.default_rng(32)
+    d, k = 30, 4
+    H, lam, Q = inputs.planted_hessian(d, k, 0.3, 33)
+    st = oracle.policy_step("reuse", None, lambda: (lam[k - 1], lam[k], 1e-3))["state"]
+    reused = 0
+    for _ in range(60):
+        Z = rng.standard_normal((d, d))
+        E = 0.5 * (Z + Z.T)
+        E *= rng.uniform(0.0, 0.2) / np.linalg.norm(E)
+        r = oracle.policy_step("reuse", st, lambda: (_ for _ in ()).throw(AssertionError("refresh")),
+                               drift=np.linalg.norm(E), tau=0.0) if np.linalg.norm(E) < 0.149 else None
+        if r is None:
+            continue
+        reused += 1
+        assert not r["refreshed"] and r["s"] == st["s"]
+        assert _true_margin(H + E, k, r["s"]) >= r["margin"] - 1e-12
+    assert reused > 20
+
+
+def test_policy_reuse_refreshes_when_margin_runs_out():
+    st = {"s": 0.0, "lam_k": -0.1, "lam_k1": 0.1, "eps": 0.01}
+    r = oracle.policy_step("reuse", st, lambda: (-0.2, 0.3, 0.01), drift=0.03, tau=0.5)
+    assert not r["refreshed"] and r["margin"] == 0.1 - 0.01 - 0.03
+    r = oracle.policy_step("reuse", st, lambda: (-0.2, 0.3, 0.01), drift=0.05, tau=0.5)
+    assert r["refreshed"] and abs(r["s"] - 0.05) < 1e-16 and abs(r["margin"] - 0.24) < 1e-15
+
+
+def test_policy_damped_stays_in_certified_interval():
+    rng = np.random.default_rng(34)
+    st = None
+    for _ in range(40):
+        lk = rng.uniform(-1.0, 0.0)
+        lk1 = lk + rng.uniform(0.05, 0.5)
+        eps = rng.uniform(0.0, 0.2) * (lk1 - lk) / 2
+        r = oracle.policy_step("damped", st, lambda: (lk, lk1, eps), beta=0.3, clip=0.25)
+        w = 0.5 * (lk1 - lk) - eps
+        if st is None:
+            assert r["s"] == 0.5 * (lk + lk1)
+        assert lk + eps + 0.25 * w - 1e-15 <= r["s"] <= lk1 - eps - 0.25 * w + 1e-15
+        assert r["margin"] >= 0.25 * w - 1e-15
+        st = r["state"]
+    one = oracle.policy_step("damped", {"s": -0.9, "lam_k": 0, "lam_k1": 0, "eps": 0},
+                             lambda: (0.0, 0.4, 0.01), beta=1.0, clip=0.25)
+    assert one["s"] == 0.2

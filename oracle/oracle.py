@@ -21,7 +21,7 @@ __all__ = [
     "ns_depth_scalar", "inf_norm_shifted", "fro_norm_shifted", "admissible", "certificates",
     "spectral_norm_sym", "splitmix64", "start_block", "lanczos_block_size",
     "lanczos_check_steps", "block_lanczos", "ns_step_derivative", "ns_adjoint", "ns_tangent",
-    "ns_poly_derivative", "ns_frechet_dk", "sign_frechet_dk", "policy_step",
+    "ns_poly_derivative", "ns_frechet_dk", "sign_frechet_dk", "policy_step", "outer_descent",
 ]
 
 
@@ -293,6 +293,42 @@ def policy_step(mode: str, state, estimate, drift=None, beta: float = 0.5, clip:
     margin = min(s - lk, lk1 - s) - eps
     new = {"s": s, "lam_k": lk, "lam_k1": lk1, "eps": eps} if margin > 0.0 else None
     return {"s": s, "margin": margin, "refreshed": True, "state": new}
+
+
+def outer_descent(grad, hess, x0, k: int, eta: float, steps: int, shifts=None, m: int = 0,
+                  gtol: float = 1e-10, similarity=None):
+    """Alg. 4.3 with an exact engine: x_{n+1} = x_n - eta R_n g_n
+    (eq. discrete_step).  R_n is the exact reflector R_k of H_n (m = 0) or the
+    finite filter p_m((H_n - s_n I)/||H_n - s_n I||_inf) (eq. pm, section 4.3
+    scaling), with s_n = shifts[n] when given, else the exact midpoint of
+    H_n's eigenvalues (Prop. 4.1).  ``similarity`` as in the library driver:
+    hess returns S H S^-1 and the direction is S^-1 R(S H S^-1) S g.
+    Returns dict(x, steps, gnorm, shifts, xs)."""
+    x = np.array(x0, dtype=np.float64)
+    gn_hist, s_hist, xs = [], [], [x.copy()]
+    n = 0
+    for n in range(steps):
+        g = grad(x)
+        gn_hist.append(float(np.linalg.norm(g)))
+        if gn_hist[-1] < gtol:
+            break
+        H = hess(x)
+        w, V = np.linalg.eigh(H)
+        s = shifts[n] if shifts is not None else midpoint(w, k)
+        s_hist.append(s)
+        if m == 0:
+            R, _ = shifted_sign_from_eig(w, V, s)
+        else:
+            R = ns_iterates(H, s, inf_norm_shifted(H, s), m)[m]
+        v = g if similarity is None else similarity * g
+        dvec = R @ v
+        if similarity is not None:
+            dvec = dvec / similarity
+        x = x - eta * dvec
+        xs.append(x.copy())
+    else:
+        gn_hist.append(float(np.linalg.norm(grad(x))))
+    return {"x": x, "steps": len(s_hist), "gnorm": gn_hist, "shifts": s_hist, "xs": xs}
 
 
 def fro_norm_shifted(H, s: float) -> float:

@@ -29,6 +29,7 @@ __all__ = [
     "haar_orthogonal", "planted_eigenvalues", "planted_hessian",
     "allen_cahn_field", "allen_cahn_2d", "allen_cahn_1d_neumann",
     "symmetric_normal", "diag_hessian", "batch_specs", "batch_problem",
+    "RotatedQuartic", "AllenCahn1D",
 ]
 
 
@@ -186,3 +187,72 @@ def batch_problem(spec):
     """``planted_hessian`` of one ``batch_specs`` entry: ``(H, lam, Q)``."""
     d, k, grel, pseed = spec
     return planted_hessian(d, k, 2.0 * grel, pseed)
+
+
+class RotatedQuartic:
+    """The rotated quartic family of the target-index scan (section 5.3):
+    E(x) = 1/4 sum y_i^4 + 1/2 sum c_i y_i^2 with y = Q^T x, Q Haar (seeded),
+    c_i < 0 for i <= k and c_i > 0 otherwise, so the origin is an index-k
+    saddle.  The paper does not state c; here c_i = -(1 + (i-1)/d) for i <= k
+    and c_i = 1 + (i-1)/d for i > k (distinct curvatures)."""
+
+    def __init__(self, d: int = 64, k: int = 4, seed: int = 0):
+        rng = np.random.default_rng(seed)
+        self.Q = haar_orthogonal(d, rng)
+        i = np.arange(d)
+        self.c = np.where(i < k, -(1.0 + i / d), 1.0 + i / d)
+        self.d, self.k = d, k
+
+    def energy(self, x):
+        y = self.Q.T @ x
+        return 0.25 * np.sum(y ** 4) + 0.5 * np.sum(self.c * y * y)
+
+    def grad(self, x):
+        y = self.Q.T @ x
+        return self.Q @ (y ** 3 + self.c * y)
+
+    def hess(self, x):
+        y = self.Q.T @ x
+        M = (self.Q * (3.0 * y * y + self.c)) @ self.Q.T
+        return 0.5 * (M + M.T)
+
+    def start(self, seed: int, scale: float = 0.3):
+        """A seeded random start near the saddle."""
+        return scale * np.random.default_rng(seed).standard_normal(self.d)
+
+
+class AllenCahn1D:
+    """The 1-D semidiscrete Allen-Cahn energy of section 5.4 on n nodes with
+    the ghost-point Neumann Laplacian K (h = L/(n-1)):
+    grad E = eps^2 K u + u^3 - u,  Hessian eps^2 K + diag(3u^2 - 1).
+    K is not symmetric; with S = diag(sqrt(w)), w = (1/2, 1, ..., 1, 1/2),
+    S K S^-1 is, and ``hess_sym`` returns S H S^-1 (same eigenvalues), so that
+    sgn(H) = S^-1 sgn(S H S^-1) S."""
+
+    def __init__(self, n: int = 41, eps: float = 0.4, L: float = 1.0):
+        h = L / (n - 1)
+        K = np.zeros((n, n))
+        for i in range(n):
+            K[i, i] = 2.0
+            if i > 0:
+                K[i, i - 1] = -1.0
+            if i < n - 1:
+                K[i, i + 1] = -1.0
+        K[0, 1] = -2.0
+        K[n - 1, n - 2] = -2.0
+        self.K = K / (h * h)
+        w = np.ones(n)
+        w[0] = w[-1] = 0.5
+        self.S = np.sqrt(w)
+        self.n, self.eps = n, eps
+
+    def grad(self, u):
+        return self.eps ** 2 * (self.K @ u) + u ** 3 - u
+
+    def hess_sym(self, u):
+        Ks = (self.S[:, None] * self.K) / self.S[None, :]
+        Ks = 0.5 * (Ks + Ks.T)
+        return self.eps ** 2 * Ks + np.diag(3.0 * u * u - 1.0)
+
+    def start(self, seed: int, scale: float = 0.05):
+        return scale * np.random.default_rng(seed).standard_normal(self.n)

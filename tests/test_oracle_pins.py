@@ -531,3 +531,31 @@ def test_policy_damped_stays_in_certified_interval():
     one = oracle.policy_step("damped", {"s": -0.9, "lam_k": 0, "lam_k1": 0, "eps": 0},
                              lambda: (0.0, 0.4, 0.01), beta=1.0, clip=0.25)
     assert one["s"] == 0.2
+
+
+# ------------------------------------------------------------ Alg. 4.3 loop
+def test_outer_descent_reaches_the_quartic_saddle():
+    """The rotated quartic has an index-k saddle at the origin (section 5.3);
+    Alg. 4.3 with the exact reflector, and with the finite filter p_6, reaches
+    it from a nearby start (Morse index k, ||x|| -> 0)."""
+    for k in (1, 5):
+        q = inputs.RotatedQuartic(24, k, 3)
+        for m in (0, 6):
+            r = oracle.outer_descent(q.grad, q.hess, q.start(4), k, 0.3, 400, m=m)
+            assert r["gnorm"][-1] < 1e-10 and np.linalg.norm(r["x"]) < 1e-9
+            assert int(np.sum(np.linalg.eigvalsh(q.hess(r["x"])) < 0)) == k
+
+
+def test_outer_descent_similarity_form():
+    """With a non-symmetric Hessian H and S H S^-1 symmetric, the direction
+    S^-1 sgn(S H S^-1) S g equals sgn(H) g computed from H's own eigenvectors."""
+    a = inputs.AllenCahn1D(n=9, eps=0.4)
+    u = 0.1 * np.random.default_rng(6).standard_normal(9)
+    Hns = a.eps ** 2 * a.K + np.diag(3 * u * u - 1)
+    w, V = np.linalg.eig(Hns)
+    s = 0.5 * (np.sort(w.real)[0] + np.sort(w.real)[1])
+    sgn_direct = (V * np.sign(w.real - s)) @ np.linalg.inv(V)
+    g = a.grad(u)
+    r = oracle.outer_descent(a.grad, a.hess_sym, u, 1, 1e-3, 1, similarity=a.S)
+    want = u - 1e-3 * (sgn_direct.real @ g)
+    assert np.max(np.abs(r["x"] - want)) < 1e-12

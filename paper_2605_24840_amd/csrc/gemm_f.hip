@@ -46,16 +46,23 @@ struct FMfma<float> {
   }
 };
 
-template <typename T>
+// Tile edge TS in {64, 96, 128}: 4 waves in 2 x 2, each a (TS/2)^2 quadrant of
+// MB x MB MFMA blocks of 16 x 16.
+template <typename T, int TS>
 struct FCfg {
+  static_assert(TS == 64 || TS == 96 || TS == 128, "tile edge");
   static constexpr int BK = 16;
   static constexpr int LDA = BK + 16 / (int)sizeof(T);  // 16 B pad per LDS row
-  static constexpr int OPER = 2 * 2 * TILE * LDA;       // 2 buffers x 2 operands
-  static constexpr int SLD = TILE + 1;                  // staging row stride
-  static constexpr int STG = TILE * SLD;
+  static constexpr int OPER = 2 * 2 * TS * LDA;         // 2 buffers x 2 operands
+  static constexpr int SLD = TS + 1;                    // staging row stride
+  static constexpr int STG = TS * SLD;
   static constexpr int LDS = OPER > STG ? OPER : STG;
   static constexpr int NV = 8 * (int)sizeof(T) / 16;    // 16 B vectors per thread per operand
   static constexpr int VE = 16 / (int)sizeof(T);        // elements per 16 B
+  static constexpr int MB = TS / 32;                    // MFMA blocks per wave and dimension
+  static constexpr int LPR = TS / VE;                   // 16 B vectors per tile row
+  static constexpr int NIT = TS * TS / VE / 256;        // epilogue vectors per thread
+  static_assert(NIT * VE * 256 == TS * TS, "epilogue split");
 };
 
 // Operand pairs of one tile product: the tile accumulates
@@ -71,30 +78,33 @@ struct Pairs {
 // I <= J and store the tile twice; GEMM_PLAIN_NEG takes any (I, J) and
 // stores -C once.  The tile's partial (||N||_F^2 or trace contribution; 0
 // for the other modes) goes to *partial.
-template <typename T, int MODE, int NP>
+template <typename T, int MODE, int NP, int TS>
 __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T* __restrict__ Xold,
                                                 T* __restrict__ out, int ld, int d, int dp, int I,
                                                 int J, T* lds, double* red,
                                                 double* __restrict__ partial) {
-  typedef FCfg<T> C;
+  typedef FCfg<T, TS> C;
   typedef FMfma<T> M;
   typedef typename M::acc_t acc_t;
   constexpr bool SYM = MODE != GEMM_PLAIN_NEG;
-  const int i0 = I * TILE, j0 = J * TILE;
+  constexpr int MB = C::MB;
+  const int i0 = I * TS, j0 = J * TS;
   const bool diag = SYM && (I == J);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // Loader: thread -> row (tid >> 1), 8 consecutive k at (tid & 1) * 8.
-  const int lrow = tid >> 1, lk = (tid & 1) * 8;
+  // Loader: thread -> row (tid >> 1), 8 consecutive k at (tid & 1) * 8; the
+  // first 2 TS threads load.
+  const bool loader = tid < 2 * TS;
+  const int lrow = loader ? tid >> 1 : 0, lk = (tid & 1) * 8;
   const int64_t rA = (int64_t)(i0 + lrow) * ld + lk, rB = (int64_t)(j0 + lrow) * ld + lk;
   u32x4_t ra[C::NV], rb[C::NV];
 
-  acc_t acc[4][4];
+  acc_t acc[MB][MB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < MB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
 
@@ -111,6 +121,7 @@ __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T*
         A = op.A[q];
         B = op.B[q];
       }
+    if (!loader) return;
     const u32x4_t* pa = reinterpret_cast<const u32x4_t*>(A + rA + (int64_t)kt * C::BK);
     const u32x4_t* pb = reinterpret_cast<const u32x4_t*>(B + rB + (int64_t)kt * C::BK);
 #pragma unroll
@@ -120,8 +131,9 @@ __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T*
     }
   };
   auto sstore = [&](int buf) {
-    T* sa = lds + buf * (2 * TILE * C::LDA);
-    T* sb = sa + TILE * C::LDA;
+    if (!loader) return;
+    T* sa = lds + buf * (2 * TS * C::LDA);
+    T* sb = sa + TS * C::LDA;
     u32x4_t* da = reinterpret_cast<u32x4_t*>(sa + lrow * C::LDA + lk);
     u32x4_t* db = reinterpret_cast<u32x4_t*>(sb + lrow * C::LDA + lk);
 #pragma unroll
@@ -138,50 +150,50 @@ __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T*
   for (int kt = 0; kt < nkt; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nkt) gload(kt + 1);
-    const T* sa = lds + cur * (2 * TILE * C::LDA);
-    const T* sb = sa + TILE * C::LDA;
+    const T* sa = lds + cur * (2 * TS * C::LDA);
+    const T* sb = sa + TS * C::LDA;
 #pragma unroll
     for (int kk = 0; kk < C::BK / 4; ++kk) {
-      T av[4], bv[4];
+      T av[MB], bv[MB];
       const int kof = kk * 4 + (lane >> 4);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sa[(wr * 64 + a * 16 + (lane & 15)) * C::LDA + kof];
+      for (int a = 0; a < MB; ++a) av[a] = sa[(wr * (TS / 2) + a * 16 + (lane & 15)) * C::LDA + kof];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sb[(wc * 64 + b * 16 + (lane & 15)) * C::LDA + kof];
+      for (int b = 0; b < MB; ++b) bv[b] = sb[(wc * (TS / 2) + b * 16 + (lane & 15)) * C::LDA + kof];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = M::op(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < MB; ++b) acc[a][b] = M::op(av[a], bv[b], acc[a][b]);
     }
     if (kt + 1 < nkt) sstore(cur ^ 1);
     __syncthreads();
   }
 
-  // ---- epilogue: stage the 128 x 128 result tile ----
+  // ---- epilogue: stage the TS x TS result tile ----
   T* stg = lds;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < MB; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < MB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wr * 64 + a * 16 + M::row(lane, r);
-        const int col = wc * 64 + b * 16 + (lane & 15);
+        const int row = wr * (TS / 2) + a * 16 + M::row(lane, r);
+        const int col = wc * (TS / 2) + b * 16 + (lane & 15);
         stg[row * C::SLD + col] = acc[a][b][r];
       }
   __syncthreads();
 
-  // Direct pass: row-contiguous 16 B stores.  In a diagonal tile entry (r, c)
-  // takes the value computed at (min, max) so the stored tile is exactly
-  // symmetric.
-  constexpr int LPR = TILE / C::VE;      // lanes per tile row
-  constexpr int RPI = 256 / LPR;         // rows per iteration
-  const int cofs = (tid % LPR) * C::VE;
+  // Direct pass: row-contiguous 16 B stores, vector v = it * 256 + tid of the
+  // tile (row v / LPR, columns (v % LPR) * VE ..).  In a diagonal tile entry
+  // (r, c) takes the value computed at (min, max) so the stored tile is
+  // exactly symmetric.
+  constexpr int LPR = C::LPR;
   double part = 0.0;
-  alignas(16) T vals[TILE / RPI][C::VE];
+  alignas(16) T vals[C::NIT][C::VE];
 #pragma unroll
-  for (int it = 0; it < TILE / RPI; ++it) {
-    const int r = it * RPI + tid / LPR;
+  for (int it = 0; it < C::NIT; ++it) {
+    const int v = it * 256 + tid;
+    const int r = v / LPR, cofs = (v % LPR) * C::VE;
     const int gi = i0 + r;
     alignas(16) T xo[C::VE];
     if (MODE == GEMM_UPDATE || MODE == GEMM_ADJOINT) {
@@ -215,46 +227,48 @@ __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T*
   if (SYM && !diag) {
     // Write the final values back to staging, then store the transposed tile.
 #pragma unroll
-    for (int it = 0; it < TILE / RPI; ++it) {
-      const int r = it * RPI + tid / LPR;
+    for (int it = 0; it < C::NIT; ++it) {
+      const int v = it * 256 + tid;
+      const int r = v / LPR, cofs = (v % LPR) * C::VE;
 #pragma unroll
       for (int e = 0; e < C::VE; ++e) stg[r * C::SLD + cofs + e] = vals[it][e];
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < TILE / RPI; ++it) {
-      const int c = it * RPI + tid / LPR;   // output row j0 + c
-      alignas(16) T v[C::VE];
+    for (int it = 0; it < C::NIT; ++it) {
+      const int v = it * 256 + tid;
+      const int c = v / LPR, rofs = (v % LPR) * C::VE;   // output row j0 + c
+      alignas(16) T w[C::VE];
 #pragma unroll
-      for (int e = 0; e < C::VE; ++e) v[e] = stg[(cofs + e) * C::SLD + c];
-      *reinterpret_cast<u32x4_t*>(out + (int64_t)(j0 + c) * ld + i0 + cofs) =
-          *reinterpret_cast<const u32x4_t*>(v);
+      for (int e = 0; e < C::VE; ++e) w[e] = stg[(rofs + e) * C::SLD + c];
+      *reinterpret_cast<u32x4_t*>(out + (int64_t)(j0 + c) * ld + i0 + rofs) =
+          *reinterpret_cast<const u32x4_t*>(w);
     }
   }
   const double tot = block_sum_256(part, red);
   if (tid == 0) *partial = tot;
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int TS>
 __global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
                                                     const T* __restrict__ B,
                                                     const T* __restrict__ Xold,
                                                     T* __restrict__ out, int ld, int d, int dp,
                                                     const int2* __restrict__ tiles,
                                                     double* __restrict__ partials) {
-  __shared__ T lds[FCfg<T>::LDS];
+  __shared__ T lds[FCfg<T, TS>::LDS];
   __shared__ double red[4];
   const int2 tl = tiles[blockIdx.x];
   Pairs<T, 1> op;
   op.A[0] = A;
   op.B[0] = B;
-  sym_gemm_f_tile<T, MODE, 1>(op, Xold, out, ld, d, dp, tl.x, tl.y, lds, red,
-                              partials + blockIdx.x);
+  sym_gemm_f_tile<T, MODE, 1, TS>(op, Xold, out, ld, d, dp, tl.x, tl.y, lds, red,
+                                  partials + blockIdx.x);
 }
 
 // Adjoint step of eq. NS (see launch.h): out = (Gb + Gb N + N Gb + Pn X)/2
 // with Pn = -X Gb, all operands symmetric except Pn.
-template <typename T>
+template <typename T, int TS>
 __global__ __launch_bounds__(256) void k_adjoint_step(const T* __restrict__ Gb,
                                                       const T* __restrict__ N,
                                                       const T* __restrict__ Pn,
@@ -262,7 +276,7 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const T* __restrict__ Gb,
                                                       T* __restrict__ out, int ld, int d, int dp,
                                                       const int2* __restrict__ tiles,
                                                       double* __restrict__ partials) {
-  __shared__ T lds[FCfg<T>::LDS];
+  __shared__ T lds[FCfg<T, TS>::LDS];
   __shared__ double red[4];
   const int2 tl = tiles[blockIdx.x];
   Pairs<T, 3> op;
@@ -272,21 +286,21 @@ __global__ __launch_bounds__(256) void k_adjoint_step(const T* __restrict__ Gb,
   op.B[1] = Gb;
   op.A[2] = Pn;
   op.B[2] = X;
-  sym_gemm_f_tile<T, GEMM_ADJOINT, 3>(op, Gb, out, ld, d, dp, tl.x, tl.y, lds, red,
-                                      partials + blockIdx.x);
+  sym_gemm_f_tile<T, GEMM_ADJOINT, 3, TS>(op, Gb, out, ld, d, dp, tl.x, tl.y, lds, red,
+                                          partials + blockIdx.x);
 }
 
-// Grouped launch over the tiles of many problems: tile (p, I, J, slot) reads
-// the problem's iterate pair and N from its descriptor and writes its
-// partial to partials[slot]; `parity` selects which of the pair holds the
-// current iterate (every problem still iterating has taken the same number
-// of steps).
-template <typename T, int MODE>
+// Grouped launch over the tiles of many problems of one tile edge TS: tile
+// (p, I, J, slot) reads the problem's iterate pair and N from its descriptor
+// and writes its partial to partials[slot]; `parity` selects which of the
+// pair holds the current iterate (every problem still iterating has taken
+// the same number of steps).
+template <typename T, int MODE, int TS>
 __global__ __launch_bounds__(256) void k_sym_gemm_f_grouped(const GemmProblem* __restrict__ probs,
                                                             const int4* __restrict__ tiles,
                                                             int parity,
                                                             double* __restrict__ partials) {
-  __shared__ T lds[FCfg<T>::LDS];
+  __shared__ T lds[FCfg<T, TS>::LDS];
   __shared__ double red[4];
   const int4 tl = tiles[blockIdx.x];
   const GemmProblem pr = probs[tl.x];
@@ -297,26 +311,25 @@ __global__ __launch_bounds__(256) void k_sym_gemm_f_grouped(const GemmProblem* _
   op.A[0] = Xc;
   op.B[0] = MODE == GEMM_RESIDUAL ? Xc : N;
   if (MODE == GEMM_RESIDUAL)
-    sym_gemm_f_tile<T, MODE, 1>(op, nullptr, N, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
-                                partials + tl.w);
+    sym_gemm_f_tile<T, MODE, 1, TS>(op, nullptr, N, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
+                                    partials + tl.w);
   else
-    sym_gemm_f_tile<T, MODE, 1>(op, Xc, Xn, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
-                                partials + tl.w);
+    sym_gemm_f_tile<T, MODE, 1, TS>(op, Xc, Xn, pr.ld, pr.d, pr.dp, tl.y, tl.z, lds, red,
+                                    partials + tl.w);
 }
 
-template <typename T>
-static hipError_t launch_f(int mode, const T* A, const T* B, const T* Xold, T* out, int ld, int d,
-                           int dp, const int2* tiles, int ntiles, double* partials,
-                           hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
+template <typename T, int TS>
+static hipError_t launch_f_ts(int mode, const T* A, const T* B, const T* Xold, T* out, int ld,
+                              int d, int dp, const int2* tiles, int ntiles, double* partials,
+                              hipStream_t st) {
   if (mode == GEMM_RESIDUAL)
-    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_RESIDUAL>), dim3(ntiles), dim3(256), 0, st, A, B,
+    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
                        Xold, out, ld, d, dp, tiles, partials);
   else if (mode == GEMM_UPDATE)
-    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_UPDATE>), dim3(ntiles), dim3(256), 0, st, A, B, Xold,
-                       out, ld, d, dp, tiles, partials);
+    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
+                       Xold, out, ld, d, dp, tiles, partials);
   else if (mode == GEMM_PLAIN_NEG)
-    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_PLAIN_NEG>), dim3(ntiles), dim3(256), 0, st, A, B,
+    hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_PLAIN_NEG, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
                        Xold, out, ld, d, dp, tiles, partials);
   else
     return hipErrorInvalidValue;
@@ -324,52 +337,111 @@ static hipError_t launch_f(int mode, const T* A, const T* B, const T* Xold, T* o
 }
 
 template <typename T>
-static hipError_t launch_adj(const T* Gb, const T* N, const T* Pn, const T* X, T* out, int ld,
-                             int d, int dp, const int2* tiles, int ntiles, double* partials,
-                             hipStream_t st) {
+static hipError_t launch_f(int ts, int mode, const T* A, const T* B, const T* Xold, T* out, int ld,
+                           int d, int dp, const int2* tiles, int ntiles, double* partials,
+                           hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adjoint_step<T>, dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X, out, ld, d,
-                     dp, tiles, partials);
+  if (dp % ts != 0) return hipErrorInvalidValue;
+  switch (ts) {
+    case 64: return launch_f_ts<T, 64>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+    case 96: return launch_f_ts<T, 96>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+    case 128: return launch_f_ts<T, 128>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t launch_adj(int ts, const T* Gb, const T* N, const T* Pn, const T* X, T* out,
+                             int ld, int d, int dp, const int2* tiles, int ntiles,
+                             double* partials, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (dp % ts != 0) return hipErrorInvalidValue;
+  switch (ts) {
+    case 64:
+      hipLaunchKernelGGL((k_adjoint_step<T, 64>), dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X,
+                         out, ld, d, dp, tiles, partials);
+      break;
+    case 96:
+      hipLaunchKernelGGL((k_adjoint_step<T, 96>), dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X,
+                         out, ld, d, dp, tiles, partials);
+      break;
+    case 128:
+      hipLaunchKernelGGL((k_adjoint_step<T, 128>), dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X,
+                         out, ld, d, dp, tiles, partials);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
-hipError_t launch_adjoint_step_f64(const double* Gb, const double* N, const double* Pn,
+hipError_t launch_adjoint_step_f64(int ts, const double* Gb, const double* N, const double* Pn,
                                    const double* X, double* out, int ld, int d, int dp,
                                    const int2* tiles, int ntiles, double* partials,
                                    hipStream_t st) {
-  return launch_adj<double>(Gb, N, Pn, X, out, ld, d, dp, tiles, ntiles, partials, st);
+  return launch_adj<double>(ts, Gb, N, Pn, X, out, ld, d, dp, tiles, ntiles, partials, st);
 }
-hipError_t launch_adjoint_step_f32(const float* Gb, const float* N, const float* Pn,
+hipError_t launch_adjoint_step_f32(int ts, const float* Gb, const float* N, const float* Pn,
                                    const float* X, float* out, int ld, int d, int dp,
                                    const int2* tiles, int ntiles, double* partials,
                                    hipStream_t st) {
-  return launch_adj<float>(Gb, N, Pn, X, out, ld, d, dp, tiles, ntiles, partials, st);
+  return launch_adj<float>(ts, Gb, N, Pn, X, out, ld, d, dp, tiles, ntiles, partials, st);
 }
 
-hipError_t launch_sym_gemm_f64(int mode, const double* A, const double* B, const double* Xold,
-                               double* out, int ld, int d, int dp, const int2* tiles, int ntiles,
-                               double* partials, hipStream_t st) {
-  return launch_f<double>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+hipError_t launch_sym_gemm_f64(int ts, int mode, const double* A, const double* B,
+                               const double* Xold, double* out, int ld, int d, int dp,
+                               const int2* tiles, int ntiles, double* partials, hipStream_t st) {
+  return launch_f<double>(ts, mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
 }
-hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const float* Xold,
+hipError_t launch_sym_gemm_f32(int ts, int mode, const float* A, const float* B, const float* Xold,
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
                                double* partials, hipStream_t st) {
-  return launch_f<float>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+  return launch_f<float>(ts, mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
 }
 
-hipError_t launch_sym_gemm_grouped(int fp64, int mode, const GemmProblem* probs, const int4* tiles,
-                                   int ntiles, int parity, double* partials, hipStream_t st) {
+// Blocks of one tile-edge choice that a compute unit holds at once (LDS).
+int sym_gemm_f_blocks_per_cu(int fp64, int ts) {
+  constexpr int LDS_BYTES = 160 * 1024;
+  int lds = 0;
+  if (fp64)
+    lds = ts == 64 ? FCfg<double, 64>::LDS : ts == 96 ? FCfg<double, 96>::LDS : FCfg<double, 128>::LDS;
+  else
+    lds = ts == 64 ? FCfg<float, 64>::LDS : ts == 96 ? FCfg<float, 96>::LDS : FCfg<float, 128>::LDS;
+  const int per = LDS_BYTES / (lds * (fp64 ? 8 : 4) + 64);
+  return per < 1 ? 1 : (per > 8 ? 8 : per);
+}
+
+template <typename T, int TS>
+static void launch_grouped_ts(int mode, const GemmProblem* probs, const int4* tiles, int ntiles,
+                              int parity, double* partials, hipStream_t st) {
+  if (mode == GEMM_RESIDUAL)
+    hipLaunchKernelGGL((k_sym_gemm_f_grouped<T, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0,
+                       st, probs, tiles, parity, partials);
+  else
+    hipLaunchKernelGGL((k_sym_gemm_f_grouped<T, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st,
+                       probs, tiles, parity, partials);
+}
+
+hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem* probs,
+                                   const int4* tiles, int ntiles, int parity, double* partials,
+                                   hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-#define REFL_GG(T, MODEV)                                                                      \
-  hipLaunchKernelGGL((k_sym_gemm_f_grouped<T, MODEV>), dim3(ntiles), dim3(256), 0, st, probs, \
-                     tiles, parity, partials)
-  if (fp64) {
-    if (mode == GEMM_RESIDUAL) REFL_GG(double, GEMM_RESIDUAL);
-    else REFL_GG(double, GEMM_UPDATE);
-  } else {
-    if (mode == GEMM_RESIDUAL) REFL_GG(float, GEMM_RESIDUAL);
-    else REFL_GG(float, GEMM_UPDATE);
+  if (mode != GEMM_RESIDUAL && mode != GEMM_UPDATE) return hipErrorInvalidValue;
+  switch (ts) {
+    case 64:
+      if (fp64) launch_grouped_ts<double, 64>(mode, probs, tiles, ntiles, parity, partials, st);
+      else launch_grouped_ts<float, 64>(mode, probs, tiles, ntiles, parity, partials, st);
+      break;
+    case 96:
+      if (fp64) launch_grouped_ts<double, 96>(mode, probs, tiles, ntiles, parity, partials, st);
+      else launch_grouped_ts<float, 96>(mode, probs, tiles, ntiles, parity, partials, st);
+      break;
+    case 128:
+      if (fp64) launch_grouped_ts<double, 128>(mode, probs, tiles, ntiles, parity, partials, st);
+      else launch_grouped_ts<float, 128>(mode, probs, tiles, ntiles, parity, partials, st);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-#undef REFL_GG
   return hipGetLastError();
 }
 

@@ -15,26 +15,30 @@ enum GemmMode {
   GEMM_ADJOINT = 3    // adjoint step (launch_adjoint_step_*)
 };
 
-// FP64 / FP32 products on 16x16x4 MFMA.  Matrices are dp x dp, leading
-// dimension ld, dp a multiple of 128.  tiles holds (I, J), I <= J, in units
-// of 128; partials receives one FP64 value per tile.
-hipError_t launch_sym_gemm_f64(int mode, const double* A, const double* B, const double* Xold,
-                               double* out, int ld, int d, int dp, const int2* tiles, int ntiles,
-                               double* partials, hipStream_t st);
-hipError_t launch_sym_gemm_f32(int mode, const float* A, const float* B, const float* Xold,
+// FP64 / FP32 products on 16x16x4 MFMA with tile edge ts in {64, 96, 128}.
+// Matrices are dp x dp, leading dimension ld, dp a multiple of ts.  tiles
+// holds (I, J) in units of ts (I <= J for the symmetric modes); partials
+// receives one FP64 value per tile.
+hipError_t launch_sym_gemm_f64(int ts, int mode, const double* A, const double* B,
+                               const double* Xold, double* out, int ld, int d, int dp,
+                               const int2* tiles, int ntiles, double* partials, hipStream_t st);
+hipError_t launch_sym_gemm_f32(int ts, int mode, const float* A, const float* B, const float* Xold,
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
                                double* partials, hipStream_t st);
+// Blocks of the FP64 (fp64 = 1) or FP32 product with tile edge ts that one
+// compute unit holds at once (from their LDS).
+int sym_gemm_f_blocks_per_cu(int fp64, int ts);
 
 // Adjoint (reverse) step of eq. NS for symmetric X and Gb, with N = I - X^2
 // and Pn = -X Gb (a GEMM_PLAIN_NEG product with A = X, B = Gb over all
 // tiles):  out = (Gb + Gb N + N Gb + Pn X)/2
 //             = (3 Gb - (Gb X^2 + X Gb X + X^2 Gb))/2,
 // symmetric, upper tiles only (mirrored); out must not alias Gb.
-hipError_t launch_adjoint_step_f64(const double* Gb, const double* N, const double* Pn,
+hipError_t launch_adjoint_step_f64(int ts, const double* Gb, const double* N, const double* Pn,
                                    const double* X, double* out, int ld, int d, int dp,
                                    const int2* tiles, int ntiles, double* partials,
                                    hipStream_t st);
-hipError_t launch_adjoint_step_f32(const float* Gb, const float* N, const float* Pn,
+hipError_t launch_adjoint_step_f32(int ts, const float* Gb, const float* N, const float* Pn,
                                    const float* X, float* out, int ld, int d, int dp,
                                    const int2* tiles, int ntiles, double* partials,
                                    hipStream_t st);
@@ -49,8 +53,10 @@ struct GemmProblem {
   void* N;
   int ld, d, dp, pad;
 };
-hipError_t launch_sym_gemm_grouped(int fp64, int mode, const GemmProblem* probs, const int4* tiles,
-                                   int ntiles, int parity, double* partials, hipStream_t st);
+// One launch covers the problems of one tile edge ts (their dp multiples of ts).
+hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem* probs,
+                                   const int4* tiles, int ntiles, int parity, double* partials,
+                                   hipStream_t st);
 
 // Products of matrices held as W BF16 words per entry (planes ps elements
 // apart), FP32 accumulation on 32x32x16 BF16 MFMA.  Word products kept:

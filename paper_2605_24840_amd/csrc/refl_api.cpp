@@ -31,6 +31,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/refl.h"
@@ -172,17 +175,145 @@ int choose_tile(int64_t d, int words, int ncu) {
 
 void carve_lanczos(Carve& c, LzWork& z, int64_t d, int dp, int k, int steps);
 
+void build_tiles_nt(int nt, std::vector<int2>& host);
+
+// Padding unit of the FP64 / FP32 matrices for tile edge ts: a multiple of
+// ts and of 64 (the set-up kernels work in 64 x 64 tiles).
+int pad_unit_f(int ts) { return ts % 64 == 0 ? ts : ts * 2; }
+
+// Tile edge of the FP64 / FP32 products for order d, from a cost model:
+// the edge whose upper-tile list finishes first on the device's compute
+// units.  A unit holds several blocks of a small edge at once (LDS-limited)
+// and they share its matrix cores; a tile of edge ts costs ts^2 dp / eff(ts)
+// with eff fitted to measured launches (d = 1024..4096).  Used when the
+// measurement below is switched off.
+int model_tile_f(int64_t d, bool fp64, int ncu) {
+  double best = 1e300;
+  int bt = TILE;
+  for (int ts : {128, 96, 64}) {
+    const int64_t dp = round_up(d, pad_unit_f(ts));
+    const int64_t nt = dp / ts;
+    const int64_t tiles = nt * (nt + 1) / 2;
+    const int64_t occ = sym_gemm_f_blocks_per_cu(fp64 ? 1 : 0, ts);
+    const int64_t rounds = (tiles + ncu * occ - 1) / (ncu * occ);
+    const int64_t conc = std::min<int64_t>(occ, (tiles + ncu - 1) / ncu);
+    const double eff = ts == 128 ? 1.0 : ts == 96 ? 0.9 : 1.3;
+    const double cost = (double)rounds * conc * ts * ts * (double)dp / eff;
+    if (cost < best) {
+      best = cost;
+      bt = ts;
+    }
+  }
+  return bt;
+}
+
+// Measured choice (the tile autotuner): on the first FP64 / FP32 solve of
+// order d on a device, one symmetric product of each candidate edge is timed
+// (HIP events, after a warm-up launch) on a pseudo-random dp x dp operand in
+// scratch memory the tuner allocates and frees, and the fastest edge is
+// cached for the process.  REFL_F_TILE=64|96|128 forces an edge;
+// REFL_F_TUNE=0 uses the cost model instead.  The edge changes only how the
+// products are tiled: each output entry is the same sum in the same order.
+std::mutex g_tile_mu;
+std::map<std::tuple<int, int, int64_t>, int> g_tile_cache;
+
+int select_tile_f(refl_handle_t h, int64_t d, bool fp64) {
+  if (const char* e = std::getenv("REFL_F_TILE")) {
+    const int v = std::atoi(e);
+    if (v == 64 || v == 96 || v == 128) return v;
+  }
+  if (const char* e = std::getenv("REFL_F_TUNE"))
+    if (std::atoi(e) == 0) return model_tile_f(d, fp64, h->ncu);
+  const auto key = std::make_tuple(h->device, fp64 ? 1 : 0, d);
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  auto it = g_tile_cache.find(key);
+  if (it != g_tile_cache.end()) return it->second;
+  const int fallback = model_tile_f(d, fp64, h->ncu);
+  const int cands[3] = {128, 96, 64};
+  int64_t dpmax = 0;
+  for (int ts : cands) dpmax = std::max<int64_t>(dpmax, round_up(d, pad_unit_f(ts)));
+  const size_t es = fp64 ? sizeof(double) : sizeof(float);
+  const int64_t ntmax = dpmax / 64;
+  const size_t tmax = (size_t)(ntmax * (ntmax + 1) / 2);
+  char* buf = nullptr;
+  const size_t bytes = (size_t)dpmax * dpmax * (sizeof(double) + 2 * es) + tmax * (sizeof(int2) + sizeof(double)) + 4096;
+  if (hipSetDevice(h->device) != hipSuccess || hipMalloc(&buf, bytes) != hipSuccess) return fallback;
+  hipStream_t st = h->stream;
+  Carve c(buf);
+  double* R = c.take<double>((size_t)dpmax * dpmax);
+  void* X = c.take<char>(es * dpmax * dpmax);
+  void* N = c.take<char>(es * dpmax * dpmax);
+  int2* tiles = c.take<int2>(tmax);
+  double* parts = c.take<double>(tmax);
+  double* one = c.take<double>(1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = fallback;
+  float best_ms = 1e30f;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  const double h_one = 1.0;
+  ok = ok && hipMemcpyAsync(one, &h_one, sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
+  for (int ts : cands) {
+    if (!ok) break;
+    const int dp = (int)round_up(d, pad_unit_f(ts));
+    std::vector<int2> tl;
+    build_tiles_nt(dp / ts, tl);
+    const int nt = (int)tl.size();
+    ok = hipMemcpyAsync(tiles, tl.data(), sizeof(int2) * nt, hipMemcpyHostToDevice, st) == hipSuccess &&
+         random_block(R, dp, dp, dp, 0x7115ull + ts, st) == hipSuccess &&
+         (fp64 ? launch_init_x0_f64(R, dp, (int)d, 0.0, one, (double*)X, st)
+               : launch_init_x0_f32(R, dp, (int)d, 0.0, one, (float*)X, st)) == hipSuccess;
+    auto product = [&]() {
+      return fp64 ? launch_sym_gemm_f64(ts, GEMM_RESIDUAL, (double*)X, (double*)X, nullptr,
+                                        (double*)N, dp, (int)d, dp, tiles, nt, parts, st)
+                  : launch_sym_gemm_f32(ts, GEMM_RESIDUAL, (float*)X, (float*)X, nullptr,
+                                        (float*)N, dp, (int)d, dp, tiles, nt, parts, st);
+    };
+    ok = ok && product() == hipSuccess && hipEventRecord(e0, st) == hipSuccess &&
+         product() == hipSuccess && product() == hipSuccess &&
+         hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = ts;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (!ok) {
+    (void)hipGetLastError();
+    return fallback;
+  }
+  g_tile_cache[key] = best;
+  return best;
+}
+
 // Workspace of refl_sign / refl_sign_apply (kind SIGN), refl_apply (APPLY)
 // or refl_estimate_shift (ESTIMATE: the FP64 copy of H and the Lanczos
 // buffers only).
 enum LayoutKind { LAYOUT_SIGN, LAYOUT_APPLY, LAYOUT_ESTIMATE };
 
-size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind kind, int ncu) {
+size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind kind,
+              refl_handle_t h) {
+  const int ncu = h->ncu;
   Carve c(base);
   const bool for_apply = kind == LAYOUT_APPLY;
   w.d = (int)d;
-  w.ts = (!for_apply && p.precision == REFL_PREC_MIXED) ? choose_tile(d, p.words, ncu) : TILE;
-  w.dp = (int)round_up(d, w.ts);
+  if (!for_apply && p.precision == REFL_PREC_MIXED) {
+    w.ts = choose_tile(d, p.words, ncu);
+    w.dp = (int)round_up(d, w.ts);
+  } else if (kind == LAYOUT_SIGN) {
+    w.ts = select_tile_f(h, d, p.precision == REFL_PREC_FP64);
+    w.dp = (int)round_up(d, pad_unit_f(w.ts));
+  } else if (kind == LAYOUT_ESTIMATE) {
+    w.ts = TILE;
+    w.dp = (int)round_up(d, w.ts);
+  } else {
+    w.ts = TILE;
+    w.dp = (int)round_up(d, w.ts);
+  }
   w.dk = (p.precision == REFL_PREC_MIXED) ? (int)round_up(d, 32) : w.dp;
   const int64_t dp = w.dp, n2 = dp * dp;
   const int nt = w.dp / w.ts;
@@ -775,11 +906,11 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   inf.index_j = -1;
   HIPCHK(hipSetDevice(h->device));
   Work w;
-  const size_t need = layout(w, nullptr, d, p, LAYOUT_SIGN, h->ncu);
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_SIGN, h);
   void* base = nullptr;
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, LAYOUT_SIGN, h->ncu);
+  layout(w, base, d, p, LAYOUT_SIGN, h);
   hipStream_t st = h->stream;
   double* hsc = h->pinned;
 
@@ -950,10 +1081,10 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     const int c = b.cur;
     HIPCHK(ev_start());
     if (p.precision == REFL_PREC_FP64)
-      HIPCHK(launch_sym_gemm_f64(GEMM_RESIDUAL, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
+      HIPCHK(launch_sym_gemm_f64(w.ts, GEMM_RESIDUAL, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
     else if (p.precision == REFL_PREC_FP32)
-      HIPCHK(launch_sym_gemm_f32(GEMM_RESIDUAL, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
+      HIPCHK(launch_sym_gemm_f32(w.ts, GEMM_RESIDUAL, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
     else
       HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, w.Xw[c], w.Xw[c], nullptr, w.Nw, w.dp,
@@ -1005,10 +1136,10 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     }
     HIPCHK(ev_start());
     if (p.precision == REFL_PREC_FP64)
-      HIPCHK(launch_sym_gemm_f64(GEMM_UPDATE, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp, (int)d,
+      HIPCHK(launch_sym_gemm_f64(w.ts, GEMM_UPDATE, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
     else if (p.precision == REFL_PREC_FP32)
-      HIPCHK(launch_sym_gemm_f32(GEMM_UPDATE, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp, (int)d,
+      HIPCHK(launch_sym_gemm_f32(w.ts, GEMM_UPDATE, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp, (int)d,
                                  w.dp, w.tiles, w.ntiles, w.partials, st));
     else
       HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, w.Xw[c], w.Nw, w.Xw[c], w.Xw[c ^ 1], w.dp,
@@ -1147,7 +1278,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
 // discarded: it writes the other iterate of the pair), so the device does not
 // wait for the host's stopping decisions.
 struct BatchProb {
-  int d = 0, dp = 0, ntiles = 0;
+  int d = 0, dp = 0, ts = TILE, ntiles = 0;
   double* Hf = nullptr;   // FP64 copy of H; FP32 after the bulk: FP64 copy of the iterate
   void* X[2] = {nullptr, nullptr};
   void* N = nullptr;
@@ -1172,7 +1303,13 @@ struct BatchWork {
   double *res = nullptr, *trace = nullptr, *cert = nullptr;
 };
 
-size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, bool fp64) {
+// Tile edges of the batched FP32 / FP64 products, in the order their tile
+// lists are laid out and launched.
+constexpr int BATCH_EDGES[3] = {128, 96, 64};
+int edge_class(int ts) { return ts == 128 ? 0 : ts == 96 ? 1 : 2; }
+
+size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, const int* ts,
+                    bool fp64) {
   Carve c(base);
   bw.pr.assign(nprob, BatchProb());
   bw.ttot = 0;
@@ -1182,8 +1319,9 @@ size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, bool
   for (int p = 0; p < nprob; ++p) {
     BatchProb& q = bw.pr[p];
     q.d = (int)d[p];
-    q.dp = (int)round_up(d[p], TILE);
-    const int nt = q.dp / TILE;
+    q.ts = ts[p];
+    q.dp = (int)round_up(d[p], pad_unit_f(q.ts));
+    const int nt = q.dp / q.ts;
     q.ntiles = nt * (nt + 1) / 2;
     bw.ttot += q.ntiles;
     bw.maxdp = std::max(bw.maxdp, q.dp);
@@ -1245,10 +1383,12 @@ size_t batch_pin_layout(BatchPin& bp, void* base, int nprob, int ttot) {
 
 // Grouped tile list over the problems ids[0..n): range q of the partials is
 // begin[q] .. begin[q + 1) and holds problem ids[q]'s tiles in the order of
-// build_tiles_nt; slot[q] = ids[q].  Blocks are listed largest problem first
-// (the longest tiles start first).  Returns the number of tiles.
+// build_tiles_nt; slot[q] = ids[q].  The tiles of each edge class (one
+// grouped launch each, BATCH_EDGES order) are contiguous, cnt[c] of them;
+// within a class the largest problems come first (their tiles take
+// longest).  Returns the number of tiles.
 int batch_tiles(const BatchWork& bw, const std::vector<int>& ids, int4* tiles, int* begin,
-                int* slot) {
+                int* slot, int* cnt) {
   const int n = (int)ids.size();
   begin[0] = 0;
   for (int q = 0; q < n; ++q) {
@@ -1257,14 +1397,20 @@ int batch_tiles(const BatchWork& bw, const std::vector<int>& ids, int4* tiles, i
   }
   std::vector<int> ord(n);
   for (int q = 0; q < n; ++q) ord[q] = q;
-  std::stable_sort(ord.begin(), ord.end(),
-                   [&](int a, int b) { return bw.pr[ids[a]].dp > bw.pr[ids[b]].dp; });
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    const BatchProb &pa = bw.pr[ids[a]], &pb = bw.pr[ids[b]];
+    const int ca = edge_class(pa.ts), cb = edge_class(pb.ts);
+    return ca != cb ? ca < cb : pa.dp > pb.dp;
+  });
   std::vector<int2> tl;
   int t = 0;
+  cnt[0] = cnt[1] = cnt[2] = 0;
   for (int q : ord) {
-    build_tiles_nt(bw.pr[ids[q]].dp / TILE, tl);
+    const BatchProb& pq = bw.pr[ids[q]];
+    build_tiles_nt(pq.dp / pq.ts, tl);
     for (size_t i = 0; i < tl.size(); ++i)
       tiles[t++] = make_int4(ids[q], tl[i].x, tl[i].y, begin[q] + (int)i);
+    cnt[edge_class(pq.ts)] += (int)tl.size();
   }
   return t;
 }
@@ -1309,12 +1455,15 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   }
   const bool fp64 = params[0].precision == REFL_PREC_FP64;
   HIPCHK(hipSetDevice(h->device));
+  // Each problem's tile edge is the one refl_sign would use for it.
+  std::vector<int> tsv(nprob);
+  for (int p = 0; p < nprob; ++p) tsv[p] = select_tile_f(h, d[p], fp64);
   BatchWork bw;
-  const size_t need = batch_layout(bw, nullptr, nprob, d, fp64);
+  const size_t need = batch_layout(bw, nullptr, nprob, d, tsv.data(), fp64);
   void* base = nullptr;
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  batch_layout(bw, base, nprob, d, fp64);
+  batch_layout(bw, base, nprob, d, tsv.data(), fp64);
   hipStream_t st = h->stream;
   BatchPin bp;
   const size_t pin_need = batch_pin_layout(bp, nullptr, nprob, bw.ttot);
@@ -1418,18 +1567,33 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     }
     return hipSuccess;
   };
+  int cls[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // tiles per edge class of each list
+  // One grouped launch per edge class present in list lb.
+  auto grouped_list = [&](int fp, int mode, const GemmProblem* probs, int lb, int par) -> hipError_t {
+    int off = 0;
+    for (int c = 0; c < 3; ++c) {
+      if (cls[lb][c] > 0) {
+        hipError_t e = launch_sym_gemm_grouped(fp, mode, BATCH_EDGES[c], probs, bw.tiles[lb] + off,
+                                               cls[lb][c], par, bw.partials, st);
+        if (e != hipSuccess) return e;
+      }
+      off += cls[lb][c];
+    }
+    return hipSuccess;
+  };
   auto grouped = [&](int mode, int lb, int nt, int par) -> refl_status_t {
+    (void)nt;
     if (timing) {
       HIPCHK(ev_pair());
       HIPCHK(hipEventRecord(h->ev[2 * nev], st));
     }
-    HIPCHK(launch_sym_gemm_grouped(fprec, mode, bw.probs, bw.tiles[lb], nt, par, bw.partials, st));
+    HIPCHK(grouped_list(fprec, mode, bw.probs, lb, par));
     if (timing) HIPCHK(hipEventRecord(h->ev[2 * nev++ + 1], st));
     return REFL_OK;
   };
   // Step list in buffer lb: build and upload.
   auto upload_list = [&](int lb, const std::vector<int>& ids) -> int {
-    const int nt = batch_tiles(bw, ids, bp.tiles[lb], bp.begin[lb], bp.slot[lb]);
+    const int nt = batch_tiles(bw, ids, bp.tiles[lb], bp.begin[lb], bp.slot[lb], cls[lb]);
     const int nq = (int)ids.size();
     if (hipMemcpyAsync(bw.tiles[lb], bp.tiles[lb], sizeof(int4) * nt, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(bw.begin[lb], bp.begin[lb], sizeof(int) * (nq + 1), hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -1520,14 +1684,13 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     }
     HIPCHK(hipMemcpyAsync(bw.desc, bp.desc, sizeof(BatchDesc) * nprob, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bw.cbeg, bp.cbeg, sizeof(int) * 2 * (nprob + 1), hipMemcpyHostToDevice, st));
-    const int nt_fin = batch_tiles(bw, done, bp.tiles[2], bp.begin[2], bp.slot[2]);
+    const int nt_fin = batch_tiles(bw, done, bp.tiles[2], bp.begin[2], bp.slot[2], cls[2]);
     HIPCHK(hipMemcpyAsync(bw.tiles[2], bp.tiles[2], sizeof(int4) * nt_fin, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bw.begin[2], bp.begin[2], sizeof(int) * (nd + 1), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bw.slot[2], bp.slot[2], sizeof(int) * nd, hipMemcpyHostToDevice, st));
     if (!fp64) {
       HIPCHK(launch_batch_copy(0, bw.desc, bw.cbeg + (nprob + 1), bw.slot[2], nd, hbeg[nd], 1, st));
-      HIPCHK(launch_sym_gemm_grouped(1, GEMM_RESIDUAL, bw.probs64, bw.tiles[2], nt_fin, 0,
-                                     bw.partials, st));
+      HIPCHK(grouped_list(1, GEMM_RESIDUAL, bw.probs64, 2, 0));
       HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[2], bw.slot[2], nd, bw.cert, st));
       HIPCHK(hipMemcpyAsync(bp.cert, bw.cert, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
     }
@@ -1587,7 +1750,7 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
 // derivative of its m steps, by a checkpointed reverse sweep or by forward
 // tangents (see include/refl.h for the recurrences).
 struct GradWork {
-  int d = 0, dp = 0, ntiles = 0, nfull = 0, c = 1, nck = 0;
+  int d = 0, dp = 0, ts = TILE, ntiles = 0, nfull = 0, c = 1, nck = 0;
   bool fp64 = true;
   double *Hf = nullptr, *scal = nullptr, *rowsum = nullptr, *partials = nullptr;
   int2 *tiles = nullptr, *full = nullptr;
@@ -1597,13 +1760,14 @@ struct GradWork {
 
 int grad_cap(const refl_params_t& p) { return p.fixed_steps > 0 ? p.fixed_steps : p.max_iter; }
 
-size_t grad_layout(GradWork& g, void* base, int64_t d, const refl_params_t& p) {
+size_t grad_layout(GradWork& g, void* base, int64_t d, const refl_params_t& p, refl_handle_t h) {
   Carve c(base);
   g.fp64 = p.precision == REFL_PREC_FP64;
   const size_t es = g.fp64 ? sizeof(double) : sizeof(float);
   g.d = (int)d;
-  g.dp = (int)round_up(d, TILE);
-  const int nt = g.dp / TILE;
+  g.ts = select_tile_f(h, d, g.fp64);
+  g.dp = (int)round_up(d, pad_unit_f(g.ts));
+  const int nt = g.dp / g.ts;
   g.ntiles = nt * (nt + 1) / 2;
   g.nfull = nt * nt;
   const int cap = grad_cap(p);
@@ -1678,11 +1842,11 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   inf.s = p.s;
   HIPCHK(hipSetDevice(h->device));
   GradWork g;
-  const size_t need = grad_layout(g, nullptr, d, p);
+  const size_t need = grad_layout(g, nullptr, d, p, h);
   void* base = nullptr;
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  grad_layout(g, base, d, p);
+  grad_layout(g, base, d, p, h);
   hipStream_t st = h->stream;
   double* hsc = h->pinned;
   const bool fp64 = g.fp64, reverse = p.grad_mode == REFL_GRAD_REVERSE;
@@ -1691,10 +1855,10 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   // ---- set-up ----
   {
     std::vector<int2> tl;
-    build_tiles_nt(dp / TILE, tl);
+    build_tiles_nt(dp / g.ts, tl);
     HIPCHK(hipMemcpyAsync(g.tiles, tl.data(), sizeof(int2) * tl.size(), hipMemcpyHostToDevice, st));
     std::vector<int2> tf;
-    build_tiles_full(dp / TILE, tf);
+    build_tiles_full(dp / g.ts, tf);
     HIPCHK(hipMemcpyAsync(g.full, tf.data(), sizeof(int2) * tf.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));  // the host vectors go out of scope
   }
@@ -1739,29 +1903,29 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     return er;
   };
   auto residual = [&](void* X, void* N) -> hipError_t {
-    return fp64 ? launch_sym_gemm_f64(GEMM_RESIDUAL, (double*)X, (double*)X, nullptr, (double*)N,
+    return fp64 ? launch_sym_gemm_f64(g.ts, GEMM_RESIDUAL, (double*)X, (double*)X, nullptr, (double*)N,
                                       dp, dd, dp, g.tiles, g.ntiles, g.partials, st)
-                : launch_sym_gemm_f32(GEMM_RESIDUAL, (float*)X, (float*)X, nullptr, (float*)N, dp,
+                : launch_sym_gemm_f32(g.ts, GEMM_RESIDUAL, (float*)X, (float*)X, nullptr, (float*)N, dp,
                                       dd, dp, g.tiles, g.ntiles, g.partials, st);
   };
   auto update = [&](void* X, void* N, void* out) -> hipError_t {
-    return fp64 ? launch_sym_gemm_f64(GEMM_UPDATE, (double*)X, (double*)N, (double*)X,
+    return fp64 ? launch_sym_gemm_f64(g.ts, GEMM_UPDATE, (double*)X, (double*)N, (double*)X,
                                       (double*)out, dp, dd, dp, g.tiles, g.ntiles, g.partials, st)
-                : launch_sym_gemm_f32(GEMM_UPDATE, (float*)X, (float*)N, (float*)X, (float*)out, dp,
+                : launch_sym_gemm_f32(g.ts, GEMM_UPDATE, (float*)X, (float*)N, (float*)X, (float*)out, dp,
                                       dd, dp, g.tiles, g.ntiles, g.partials, st);
   };
   // Gout = derivative map at X (with N = I - X^2) applied to Gin.
   auto dstep = [&](void* X, void* N, void* Gin, void* Gout) -> refl_status_t {
     HIPCHK(timed(true));
     if (fp64) {
-      HIPCHK(launch_sym_gemm_f64(GEMM_PLAIN_NEG, (double*)X, (double*)Gin, nullptr, (double*)g.Pn,
+      HIPCHK(launch_sym_gemm_f64(g.ts, GEMM_PLAIN_NEG, (double*)X, (double*)Gin, nullptr, (double*)g.Pn,
                                  dp, dd, dp, g.full, g.nfull, g.partials, st));
-      HIPCHK(launch_adjoint_step_f64((double*)Gin, (double*)N, (double*)g.Pn, (double*)X,
+      HIPCHK(launch_adjoint_step_f64(g.ts, (double*)Gin, (double*)N, (double*)g.Pn, (double*)X,
                                      (double*)Gout, dp, dd, dp, g.tiles, g.ntiles, g.partials, st));
     } else {
-      HIPCHK(launch_sym_gemm_f32(GEMM_PLAIN_NEG, (float*)X, (float*)Gin, nullptr, (float*)g.Pn, dp,
+      HIPCHK(launch_sym_gemm_f32(g.ts, GEMM_PLAIN_NEG, (float*)X, (float*)Gin, nullptr, (float*)g.Pn, dp,
                                  dd, dp, g.full, g.nfull, g.partials, st));
-      HIPCHK(launch_adjoint_step_f32((float*)Gin, (float*)N, (float*)g.Pn, (float*)X,
+      HIPCHK(launch_adjoint_step_f32(g.ts, (float*)Gin, (float*)N, (float*)g.Pn, (float*)X,
                                      (float*)Gout, dp, dd, dp, g.tiles, g.ntiles, g.partials, st));
     }
     HIPCHK(timed(false));
@@ -1899,11 +2063,11 @@ refl_status_t estimate_impl(refl_handle_t h, int64_t d, const double* dH, int64_
   if (rs != REFL_OK) return rs;
   HIPCHK(hipSetDevice(h->device));
   Work w;
-  const size_t need = layout(w, nullptr, d, p, LAYOUT_ESTIMATE, h->ncu);
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_ESTIMATE, h);
   void* base = nullptr;
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, LAYOUT_ESTIMATE, h->ncu);
+  layout(w, base, d, p, LAYOUT_ESTIMATE, h);
   HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, h->stream));
   return lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr);
 }
@@ -1991,7 +2155,7 @@ refl_status_t refl_workspace_size(refl_handle_t h, int64_t d, const refl_params_
   refl_status_t rs = check_params(h, d, p);
   if (rs != REFL_OK) return rs;
   Work w;
-  *bytes = layout(w, nullptr, d, *p, LAYOUT_SIGN, h->ncu);
+  *bytes = layout(w, nullptr, d, *p, LAYOUT_SIGN, h);
   return REFL_OK;
 }
 
@@ -2029,11 +2193,11 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t l
   refl_params_t p;
   refl_params_default(&p);
   Work w;
-  const size_t need = layout(w, nullptr, d, p, LAYOUT_APPLY, h->ncu);
+  const size_t need = layout(w, nullptr, d, p, LAYOUT_APPLY, h);
   void* base = nullptr;
   refl_status_t rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
-  layout(w, base, d, p, LAYOUT_APPLY, h->ncu);
+  layout(w, base, d, p, LAYOUT_APPLY, h);
   for (int64_t c0 = 0; c0 < nrhs; c0 += MAXB) {
     const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
     HIPCHK(thin_gemm_f64(dR, ldr, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, h->stream));
@@ -2065,8 +2229,11 @@ refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, c
     refl_status_t rs = check_params(h, d[p], &params[p]);
     if (rs != REFL_OK) return rs;
   }
+  const bool fp64 = params[0].precision == REFL_PREC_FP64;
+  std::vector<int> tsv(nprob);
+  for (int p = 0; p < nprob; ++p) tsv[p] = select_tile_f(h, d[p], fp64);
   BatchWork bw;
-  *bytes = batch_layout(bw, nullptr, nprob, d, params[0].precision == REFL_PREC_FP64);
+  *bytes = batch_layout(bw, nullptr, nprob, d, tsv.data(), fp64);
   return REFL_OK;
 }
 

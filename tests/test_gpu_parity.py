@@ -83,6 +83,28 @@ def test_fp64_ragged_size(R, handle):
     assert info["resid_fro"] == pytest.approx(d2["resid_fro"], rel=1e-9)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ts", [64, 96, 128])
+def test_tile_edges_ragged(R, handle, monkeypatch, ts, prec):
+    """Every tile edge of the FP64 / FP32 products on a ragged size (d = 300
+    pads to 320, 384 or 384): the same iterate as the oracle, and the same
+    (bit for bit in FP64) whichever edge runs."""
+    d, k, m = 300, 7, 6
+    H, lam, Q = inputs.planted_hessian(d, k, 0.05, 3)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    X6 = oracle.ns_iterates(H, s, oracle.inf_norm_shifted(H, s), m)[m]
+    monkeypatch.setenv("REFL_F_TILE", str(ts))
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision=prec, fixed_steps=m)
+    monkeypatch.setenv("REFL_F_TILE", "128")
+    R128, _, _ = R.sign(_gpu(H), k, s, handle=handle, precision=prec, fixed_steps=m)
+    err = np.abs(Rg.cpu().numpy() - X6).max()
+    _say(f"{prec} tile {ts}: max|X_6 - oracle| = {err:.2e}, equal to tile 128: {torch.equal(Rg, R128)}")
+    assert st == 0 and err < (1e-13 if prec == "fp64" else 1e-4)
+    if prec == "fp64":
+        assert torch.equal(Rg, R128)
+    assert np.array_equal(Rg.cpu().numpy(), Rg.cpu().numpy().T)
+
+
 def test_fp64_converged_config0(R, handle):
     _say("fp64 converged d=64 k=4 gap=0.1 midpoint tol=1e-12")
     H, lam, Q, s = _cfg0()

@@ -107,7 +107,19 @@ typedef struct {
   int32_t grad_mode;    /* refl_sign_grad: REFL_GRAD_REVERSE (default) or REFL_GRAD_TANGENT */
   int32_t ckpt_every;   /* refl_sign_grad, reverse mode: keep every c-th iterate and
                            recompute the others (0: c = ceil(sqrt(step cap))) */
+  int32_t cg_f32;       /* MIXED: operator precision of the inner solves, refl_cg_prec_t
+                           (default REFL_CG_AUTO) */
 } refl_params_t;
+
+typedef enum {
+  REFL_CG_FP64 = 0, /* the inner solves read H in FP64 */
+  REFL_CG_FP32 = 1, /* they read an FP32 copy of H (half the bytes per iteration; a solve
+                       then corrects to about u32 alpha / (s - theta_max) relative, while
+                       the Rayleigh-Ritz step and the certificate of every sweep use H in
+                       FP64, so the bound and the result stay FP64-certified) */
+  REFL_CG_AUTO = 2  /* FP32 when u32 alpha / (s - theta_max) < 1e-3 at the first sweep,
+                       else FP64 */
+} refl_cg_prec_t;
 
 typedef enum {
   REFL_GRAD_REVERSE = 0, /* reverse sweep over checkpointed iterates */
@@ -143,7 +155,8 @@ typedef struct {
 
 /* Fill *p with defaults: k = 1, s = 0, shift given, scale inf-norm, FP64,
  * tol = 1e-12, max_iter = 100, fixed_steps = 0, words = 2, polish_sweeps = 2,
- * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0, timing = 0. */
+ * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0, timing = 0,
+ * grad_mode = REFL_GRAD_REVERSE, ckpt_every = 0, cg_f32 = REFL_CG_AUTO. */
 refl_status_t refl_params_default(refl_params_t *p);
 
 /* Create a handle bound to HIP device `device` and stream `hip_stream`

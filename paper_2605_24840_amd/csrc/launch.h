@@ -216,11 +216,12 @@ struct CgHost {
 };
 size_t cg_state_bytes();
 size_t cg_part_doubles(int d);
-// One CG iteration; `it` counts from 0 within a solve.
-hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const double* V, int64_t ldv,
-                        double* Rr, const double* Pold, double* Pnext, double* AP, double* Z,
-                        void* state, double* work, double* part, int it, int max_iter,
-                        hipStream_t st);
+// One CG iteration; `it` counts from 0 within a solve.  With M32 != null the
+// products with H read its FP32 copy M32 (same ldm) instead of M.
+hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb,
+                        const double* V, int64_t ldv, double* Rr, const double* Pold,
+                        double* Pnext, double* AP, double* Z, void* state, double* work,
+                        double* part, int it, int max_iter, hipStream_t st);
 
 // ---- block Lanczos (see lanczos.hip) ----
 // Workspace sizes (doubles) for a d-row basis of up to nmax columns and

@@ -2,6 +2,8 @@
 // scaled iterate (section 3.2 eq. NS with the inf-norm scaling of section
 // 4.3), reductions, output, and the thin products and block-vector updates
 // of the FP64 subspace correction and of block Lanczos.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -588,13 +590,13 @@ __global__ __launch_bounds__(256) void k_random_block(double* __restrict__ V, in
 // go to work[chunk][c][r]; a finishing kernel adds the chunks in order.
 constexpr int SRC = 128;
 
-template <typename MT, int NB>
+template <typename MT, int NB, int CHUNK = SRC>
 __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t ldm, int64_t ps, int d,
                                              const double (*pv)[NB], double* __restrict__ work,
                                              int64_t wld, int nb) {
   const int r = blockIdx.x * 256 + threadIdx.x;
-  const int j0 = blockIdx.y * SRC;
-  const int jn = min(SRC, d - j0);
+  const int j0 = blockIdx.y * CHUNK;
+  const int jn = min(CHUNK, d - j0);
   double acc[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) acc[c] = 0.0;
@@ -661,9 +663,13 @@ struct CgState {
   int iters, done, k, nb;
 };
 
-// Grid (column blocks of 256 output rows, chunks of SRC rows of M).
-template <int NB>
-__global__ __launch_bounds__(256) void k_cg_thin(const double* __restrict__ M, int64_t ldm, int d,
+// Grid (column blocks of 256 output rows, chunks of CHUNK rows of M).  M is
+// H in FP64 (CHUNK = SRC), or its FP32 copy (CHUNK = SRC/2; the products
+// still accumulate in FP64): an FP32 pass moves half the bytes per load and
+// needs twice the waves (half the chunk) to keep as many bytes in flight.
+constexpr int CG_SRC = SRC / 2;
+template <typename MT, int NB, int CHUNK = (sizeof(MT) == 4 ? CG_SRC : SRC)>
+__global__ __launch_bounds__(256) void k_cg_thin(const MT* __restrict__ M, int64_t ldm, int d,
                                                  const double* __restrict__ Rr,
                                                  const double* __restrict__ Pold, int64_t ldv,
                                                  CgState* __restrict__ st,
@@ -671,7 +677,7 @@ __global__ __launch_bounds__(256) void k_cg_thin(const double* __restrict__ M, i
                                                  double* __restrict__ work, int64_t wld, int it,
                                                  int max_iter) {
   if (st->done) return;
-  __shared__ double pv[SRC][NB];
+  __shared__ double pv[CHUNK][NB];
   __shared__ double sbeta[NB];
   __shared__ int sdone;
   const int nb = st->nb;
@@ -721,15 +727,15 @@ __global__ __launch_bounds__(256) void k_cg_thin(const double* __restrict__ M, i
   __syncthreads();
   if (sdone) return;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st->iters = it + 1;
-  const int j0 = blockIdx.y * SRC;
-  for (int e = threadIdx.x; e < SRC * NB; e += 256) {
+  const int j0 = blockIdx.y * CHUNK;
+  for (int e = threadIdx.x; e < CHUNK * NB; e += 256) {
     const int jj = e / NB, c = e % NB, j = j0 + jj;
     pv[jj][c] = (j < d && c < nb)
                     ? Rr[(int64_t)c * ldv + j] + sbeta[c] * Pold[(int64_t)c * ldv + j]
                     : 0.0;
   }
   __syncthreads();
-  symthin_body<double, NB>(M, ldm, 0, d, pv, work, wld, nb);
+  symthin_body<MT, NB, CHUNK>(M, ldm, 0, d, pv, work, wld, nb);
 }
 
 // Grid (row groups of 64, column c): one wave per block, one row per lane.
@@ -1137,7 +1143,8 @@ size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 34; }
 size_t thin_work_doubles(int d) {
   const size_t a = (size_t)nblocks(d, 128) * 32 * (size_t)d;
   const size_t b = (size_t)nblocks(d, SRC) * 32 * (size_t)d;
-  return a > b ? a : b;
+  const size_t c = (size_t)nblocks(d, CG_SRC) * 32 * (size_t)d;  // the CG pass
+  return std::max(a, std::max(b, c));
 }
 size_t gram_work_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 32; }
 
@@ -1183,20 +1190,24 @@ hipError_t symthin_words(int words, const uint16_t* X, int ld, int64_t ps, int d
 
 // One CG iteration (three launches).  Pold/Pnext alternate between calls;
 // `it` counts from 0.  part holds the apply partials, then the update ones.
-hipError_t cg_iteration(const double* M, int64_t ldm, int d, int nb, const double* V, int64_t ldv,
-                        double* Rr, const double* Pold, double* Pnext, double* AP, double* Z,
-                        void* state, double* work, double* part, int it, int max_iter,
-                        hipStream_t st) {
+hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb,
+                        const double* V, int64_t ldv, double* Rr, const double* Pold,
+                        double* Pnext, double* AP, double* Z, void* state, double* work,
+                        double* part, int it, int max_iter, hipStream_t st) {
   CgState* s = reinterpret_cast<CgState*>(state);
   const int64_t wld = d;
-  const dim3 grid(nblocks(d, 256), nblocks(d, SRC));
+  const dim3 grid(nblocks(d, 256), nblocks(d, M32 ? CG_SRC : SRC));
   const int nrb = nblocks(d, 64);
   double* apart = part;
   double* upart = part + (size_t)nrb * 32 * 33;
 #define REFL_CG(NBV)                                                                             \
   {                                                                                              \
-    hipLaunchKernelGGL((k_cg_thin<NBV>), grid, dim3(256), 0, st, M, ldm, d, Rr, Pold, ldv, s,    \
-                       upart, nrb, work, wld, it, max_iter);                                     \
+    if (M32)                                                                                     \
+      hipLaunchKernelGGL((k_cg_thin<float, NBV>), grid, dim3(256), 0, st, M32, ldm, d, Rr, Pold, \
+                         ldv, s, upart, nrb, work, wld, it, max_iter);                           \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_cg_thin<double, NBV>), grid, dim3(256), 0, st, M, ldm, d, Rr, Pold,  \
+                         ldv, s, upart, nrb, work, wld, it, max_iter);                           \
     hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb, nb), dim3(64), 0, st, work, wld, (int)grid.y, \
                        d, V, Rr, Pold, Pnext, AP, ldv, s, apart);                                \
     hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrb, nb), dim3(64), 0, st, d, V, Pnext, AP, Z,    \

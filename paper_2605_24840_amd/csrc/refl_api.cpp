@@ -135,6 +135,7 @@ struct Work {
   int ts, dk;  // bulk tile edge and K extent of the bulk products
   int64_t ps;  // plane stride (elements) of word storage
   double* Hf;
+  float* H32;  // MIXED with cg_f32: FP32 copy of H for the inner solves
   double* scal;
   double* rowsum;
   double* partials;
@@ -334,8 +335,10 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind
     carve_lanczos(c, w.lz, d, w.dp, p.k, p.lanczos_steps);
     return c.off + 256;
   }
+  w.H32 = nullptr;
   if (!for_apply) {
     w.Hf = c.take<double>(n2);
+    if (p.precision == REFL_PREC_MIXED && p.cg_f32 != REFL_CG_FP64) w.H32 = c.take<float>(n2);
     if (p.precision == REFL_PREC_FP64) {
       w.X64[0] = c.take<double>(n2);
       w.X64[1] = c.take<double>(n2);
@@ -419,6 +422,8 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
   if (p->fixed_steps < 0) return fail(h, REFL_ERR_INVALID_ARG, "fixed_steps must be >= 0");
   if (p->precision == REFL_PREC_MIXED) {
     if (p->words < 1 || p->words > 3) return fail(h, REFL_ERR_INVALID_ARG, "words must be 1..3");
+    if (p->cg_f32 < REFL_CG_FP64 || p->cg_f32 > REFL_CG_AUTO)
+      return fail(h, REFL_ERR_INVALID_ARG, "bad cg_f32");
     if (p->fixed_steps == 0 && p->k > MAXB)
       return fail(h, REFL_ERR_UNSUPPORTED, "MIXED correction supports k <= %d", MAXB);
     if (p->polish_sweeps < 0 || p->cg_max_iter < 1 || !(p->cg_tol > 0.0))
@@ -507,6 +512,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
   double* Wspare = w.T2;
   double E_fro = NaN, theta_max = NaN, dk = NaN;
   int sweeps = 0, cg_total = 0;
+  bool use32 = false;
   CgHost* hs = reinterpret_cast<CgHost*>(h->pinned + SC_COUNT);
   while (true) {
     // Rayleigh-Ritz on span(V) with H (FP64).
@@ -539,6 +545,17 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     theta_max = th[k - 1];
     dk = (theta_max < s) ? 2.0 * std::sqrt(2.0) * E_fro / (s - theta_max) : INFINITY;
     if (dk <= p.tol || sweeps >= p.polish_sweeps) break;
+    // The inner solves may read an FP32 copy of H: each solve then corrects
+    // to about u32 alpha / (s - theta_max) relative (alpha >= ||H - sI||_2,
+    // s - theta_max the distance of the Ritz values to the shift), while
+    // this Rayleigh-Ritz step and the certificate stay in FP64.
+    if (!use32 && w.H32 &&
+        (p.cg_f32 == REFL_CG_FP32 ||
+         (p.cg_f32 == REFL_CG_AUTO && theta_max < s && info &&
+          0x1.0p-24 * info->alpha / (s - theta_max) < 1e-3))) {
+      HIPCHK(launch_shifted_f32(w.Hf, w.dp, d, 0.0, w.H32, st));
+      use32 = true;
+    }
     // Correction: (I - VV^T)(H - theta_c)(I - VV^T) z_c = -E_c by block CG.
     HIPCHK(lincomb(d, k, -1.0, w.Rr, ld, 0.0, w.Rr, ld, st));
     HIPCHK(lincomb(d, k, 0.0, w.Rr, ld, 0.0, w.Z, ld, st));
@@ -559,8 +576,9 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
       // cg_max_iter only runs the convergence test.
       const int batch = issued == 0 ? 32 : 16;
       for (int b = 0; b < batch && issued <= p.cg_max_iter; ++b, ++issued)
-        HIPCHK(cg_iteration(w.Hf, ld, d, k, V, ld, w.Rr, w.P[issued & 1], w.P[(issued + 1) & 1],
-                            w.AP, w.Z, w.cgstate, w.thin, w.cgpart, issued, p.cg_max_iter, st));
+        HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, d, k, V, ld, w.Rr, w.P[issued & 1],
+                            w.P[(issued + 1) & 1], w.AP, w.Z, w.cgstate, w.thin, w.cgpart, issued,
+                            p.cg_max_iter, st));
       HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       if (hs->done || issued > p.cg_max_iter) break;
@@ -2097,6 +2115,7 @@ refl_status_t refl_params_default(refl_params_t* p) {
   p->timing = 0;
   p->grad_mode = REFL_GRAD_REVERSE;
   p->ckpt_every = 0;
+  p->cg_f32 = REFL_CG_AUTO;
   return REFL_OK;
 }
 

@@ -23,6 +23,7 @@ PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 SHIFT = {"given": 0, "lanczos": 1}
 SCALE = {"inf": 0, "given": 1, "lanczos": 2, "fro": 3}
 GRAD_MODE = {"reverse": 0, "tangent": 1}
+CG_PREC = {"fp64": 0, "fp32": 1, "auto": 2}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
@@ -40,7 +41,7 @@ class refl_params_t(ctypes.Structure):
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("timing", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("cg_f32", ctypes.c_int32)]
 
 
 class refl_policy_params_t(ctypes.Structure):
@@ -336,7 +337,7 @@ class Handle:
 
 def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
                 alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
-                timing=False, scale=None, grad_mode="reverse", ckpt_every=0):
+                timing=False, scale=None, grad_mode="reverse", ckpt_every=0, cg_prec="auto"):
     """refl_params_t from keyword arguments.  s=None estimates the shift by
     block Lanczos; scale is "inf" (default), "given" (with alpha), "lanczos"
     (1.05 times the Lanczos spectral-radius estimate) or "fro"; k=0 with a
@@ -366,6 +367,7 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     p.timing = 1 if timing else 0
     p.grad_mode = GRAD_MODE[grad_mode]
     p.ckpt_every = int(ckpt_every)
+    p.cg_f32 = CG_PREC[cg_prec]
     return p
 
 

@@ -316,6 +316,23 @@ def _allen_cahn_golden(seed=0):
     return H, g["w"], g["V"]
 
 
+@pytest.mark.parametrize("cg_prec", ["fp64", "fp32", "auto"])
+def test_mixed_inner_solve_precision(R, handle, cg_prec):
+    """The inner solves of the correction read H in FP64 or an FP32 copy; the
+    Rayleigh-Ritz step and the certificate use H in FP64 either way, so the
+    target holds and the certified bound is a bound."""
+    d, k = 1024, 6
+    H, lam, Q = inputs.planted_hessian(d, k, 0.02, 5)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    target = 1e-8 * np.sqrt(d)
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", tol=target,
+                          cg_prec=cg_prec)
+    err = np.linalg.norm(Rg.cpu().numpy() - oracle.reflector_from_eig(Q, k))
+    _say(f"mixed d={d} inner {cg_prec}: status={R.STATUS[st]} sweeps={info['polish_sweeps']} "
+         f"cg={info['cg_iters']} dk={info['dk_bound']:.2e} err={err:.2e}")
+    assert st == 0 and err <= target and err <= info["dk_bound"] * 1.0001 + 1e-15
+
+
 @pytest.mark.parametrize("k", [1, 3, 5])
 def test_mixed_allen_cahn_d4096(R, handle, k):
     _say(f"mixed Allen-Cahn d=4096 k={k}")

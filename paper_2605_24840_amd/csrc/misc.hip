@@ -738,46 +738,60 @@ __global__ __launch_bounds__(256) void k_cg_thin(const MT* __restrict__ M, int64
   symthin_body<MT, NB, CHUNK>(M, ldm, 0, d, pv, work, wld, nb);
 }
 
-// Grid (row groups of 64, column c): one wave per block, one row per lane.
+// Grid (row groups of 64, column c), 256 threads: four lanes per row, each
+// summing every fourth chunk (four times the loads in flight of one lane per
+// row), combined by shuffles; lane 0 of each group of four holds the row.
 template <int NB>
-__global__ __launch_bounds__(64) void k_cg_apply(const double* __restrict__ work, int64_t wld,
-                                                 int nchunk, int d, const double* __restrict__ V,
-                                                 const double* __restrict__ Rr,
-                                                 const double* __restrict__ Pold,
-                                                 double* __restrict__ Pnext,
-                                                 double* __restrict__ AP, int64_t ldv,
-                                                 const CgState* __restrict__ st,
-                                                 double* __restrict__ apart) {
+__global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ work, int64_t wld,
+                                                  int nchunk, int d, const double* __restrict__ V,
+                                                  const double* __restrict__ Rr,
+                                                  const double* __restrict__ Pold,
+                                                  double* __restrict__ Pnext,
+                                                  double* __restrict__ AP, int64_t ldv,
+                                                  const CgState* __restrict__ st,
+                                                  double* __restrict__ apart) {
   if (st->done) return;
+  __shared__ double red[4][34];
   const int nb = st->nb, k = st->k;
   const int c = blockIdx.y;
-  const int lane = threadIdx.x;
-  const int row = blockIdx.x * 64 + lane;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sub = tid & 3;
+  const int row = blockIdx.x * 64 + (tid >> 2);
   double pc = 0.0, s = 0.0;
   if (row < d) {
+    double acc[4] = {0, 0, 0, 0};
+    int q = sub;
+    for (; q + 12 < nchunk; q += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += work[((int64_t)(q + 4 * u) * NB + c) * wld + row];
+    }
+    for (; q < nchunk; q += 4) acc[0] += work[((int64_t)q * NB + c) * wld + row];
+    s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+  s += __shfl_xor(s, 1, WAVE);
+  s += __shfl_xor(s, 2, WAVE);
+  const bool owner = sub == 0 && row < d;
+  if (owner) {
     const int64_t o = (int64_t)c * ldv + row;
     pc = Rr[o] + st->beta[c] * Pold[o];
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int q = 0;
-    for (; q + 8 <= nchunk; q += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += work[((int64_t)(q + u) * NB + c) * wld + row];
-    }
-    for (; q < nchunk; ++q) acc[0] += work[((int64_t)q * NB + c) * wld + row];
-    s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     s -= st->theta[c] * pc;
     Pnext[o] = pc;
     AP[o] = s;
+  } else {
+    s = 0.0;
   }
-  // Partials: V^T Ap (k values) then p . Ap, at apart[group][c][0..k].
-  double* mypart = apart + ((int64_t)blockIdx.x * nb + c) * (k + 1);
+  // Partials: V^T Ap (k values) then p . Ap, at apart[group][c][0..k]; the
+  // four waves' sums are added in a fixed order.
   for (int i = 0; i < k; ++i) {
-    const double vi = (row < d) ? V[(int64_t)i * ldv + row] : 0.0;
+    const double vi = owner ? V[(int64_t)i * ldv + row] : 0.0;
     const double t = wave_sum(vi * s);
-    if (lane == 0) mypart[i] = t;
+    if (lane == 0) red[wave][i] = t;
   }
   const double t = wave_sum(pc * s);
-  if (lane == 0) mypart[k] = t;
+  if (lane == 0) red[wave][k] = t;
+  __syncthreads();
+  double* mypart = apart + ((int64_t)blockIdx.x * nb + c) * (k + 1);
+  if (tid <= k) mypart[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // Grid (row groups of 64, column c).
@@ -1208,7 +1222,7 @@ hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, i
     else                                                                                         \
       hipLaunchKernelGGL((k_cg_thin<double, NBV>), grid, dim3(256), 0, st, M, ldm, d, Rr, Pold,  \
                          ldv, s, upart, nrb, work, wld, it, max_iter);                           \
-    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb, nb), dim3(64), 0, st, work, wld, (int)grid.y, \
+    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb, nb), dim3(256), 0, st, work, wld, (int)grid.y, \
                        d, V, Rr, Pold, Pnext, AP, ldv, s, apart);                                \
     hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrb, nb), dim3(64), 0, st, d, V, Pnext, AP, Z,    \
                        Rr, ldv, s, apart, upart, it);                                            \

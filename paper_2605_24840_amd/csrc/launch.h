@@ -210,18 +210,29 @@ hipError_t random_block(double* V, int64_t ldv, int d, int nb, uint64_t seed, hi
 
 // ---- block CG (see misc.hip) ----
 struct CgHost {
-  double theta[32], rho0[32], rho[2][32], beta[32];
+  double theta[32], rho0[32], gam[2][32], alpha[2][32];
   double tol2;
   int iters, done, k, nb;
 };
+// d x nb blocks (ld = ldv) of one solve: r, p and s alternate between two
+// buffers by iteration parity; R[0] holds r_0 and Z = 0 on entry; HR is
+// (H - theta) r.
+struct CgBufs {
+  double* R[2];
+  double* P[2];
+  double* S[2];
+  double* HR;
+  double* Z;
+};
 size_t cg_state_bytes();
 size_t cg_part_doubles(int d);
-// One CG iteration; `it` counts from 0 within a solve.  With M32 != null the
-// products with H read its FP32 copy M32 (same ldm) instead of M.
+// One CG iteration; `it` counts from 0 within a solve, and a solve runs
+// iterations 0 .. max_iter + 1 (the last only tests convergence).  With
+// M32 != null the products with H read its FP32 copy M32 (same ldm)
+// instead of M.
 hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb,
-                        const double* V, int64_t ldv, double* Rr, const double* Pold,
-                        double* Pnext, double* AP, double* Z, void* state, double* work,
-                        double* part, int it, int max_iter, hipStream_t st);
+                        const double* V, int64_t ldv, const CgBufs& bufs, void* state,
+                        double* work, double* part, int it, int max_iter, hipStream_t st);
 
 // ---- block Lanczos (see lanczos.hip) ----
 // Workspace sizes (doubles) for a d-row basis of up to nmax columns and

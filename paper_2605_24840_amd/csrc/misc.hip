@@ -583,24 +583,35 @@ __global__ __launch_bounds__(256) void k_random_block(double* __restrict__ V, in
 
 // ------------------------------------------------- symmetric thin products
 // Y = M V for SYMMETRIC M, computed as M^T V: y_r = sum_j M[j, r] V[j, :].
-// Block = 256 threads = 256 consecutive output rows r (one per lane), and a
-// chunk of SRC rows j of M; the rows of M stream coalesced across the lanes,
-// the SRC x NB block of V sits in LDS and is read as a wave-uniform
-// broadcast, and no cross-lane reduction is needed.  Partial sums per chunk
-// go to work[chunk][c][r]; a finishing kernel adds the chunks in order.
+// A block takes 256 consecutive output rows r (one per lane of each group of
+// four waves) and a chunk of CHUNK rows j of M, split between KS groups of
+// four waves: group g sums rows [g CHUNK/KS, (g + 1) CHUNK/KS) of the chunk.
+// The rows of M stream coalesced across the lanes, the CHUNK x NB block of V
+// sits in LDS and is read as wave-uniform broadcasts, and the KS group sums
+// are added in LDS in group order.  Partial sums per chunk go to
+// work[chunk][c][r]; a finishing kernel adds the chunks in order.
 constexpr int SRC = 128;
 
-template <typename MT, int NB, int CHUNK = SRC>
+template <int KS, int NB>
+struct ThinRed {
+  double v[KS > 1 ? (KS - 1) * NB * 256 : 1];
+};
+
+template <typename MT, int NB, int CHUNK, int KS>
 __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t ldm, int64_t ps, int d,
                                              const double (*pv)[NB], double* __restrict__ work,
-                                             int64_t wld, int nb) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const int j0 = blockIdx.y * CHUNK;
-  const int jn = min(CHUNK, d - j0);
+                                             int64_t wld, int nb, ThinRed<KS, NB>& red) {
+  static_assert(CHUNK % KS == 0, "chunk must split evenly");
+  constexpr int PART = CHUNK / KS;
+  const int t = threadIdx.x & 255, g = threadIdx.x >> 8;
+  const int r = blockIdx.x * 256 + t;
+  const int j0 = blockIdx.y * CHUNK + g * PART;
+  const int jn = max(0, min(PART, d - j0));
   double acc[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) acc[c] = 0.0;
   if (r < d) {
+    const double (*pp)[NB] = pv + g * PART;
     int jj = 0;
     for (; jj + 8 <= jn; jj += 8) {
       double m[8];
@@ -609,133 +620,203 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pv[jj + u][c], acc[c]);
+        for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pp[jj + u][c], acc[c]);
     }
     for (; jj < jn; ++jj) {
       const double m = MLoad<MT>::at(M, (int64_t)(j0 + jj) * ldm + r, ps);
 #pragma unroll
-      for (int c = 0; c < NB; ++c) acc[c] = fma(m, pv[jj][c], acc[c]);
+      for (int c = 0; c < NB; ++c) acc[c] = fma(m, pp[jj][c], acc[c]);
     }
+  }
+  if constexpr (KS > 1) {
+    if (g > 0) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) red.v[((g - 1) * NB + c) * 256 + t] = acc[c];
+    }
+    __syncthreads();
+    if (g > 0) return;
+#pragma unroll
+    for (int q = 0; q < KS - 1; ++q)
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc[c] += red.v[(q * NB + c) * 256 + t];
+  }
+  if (r < d) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c < nb) work[((int64_t)blockIdx.y * NB + c) * wld + r] = acc[c];
   }
 }
 
-template <typename MT, int NB>
-__global__ __launch_bounds__(256) void k_symthin(const MT* __restrict__ M, int64_t ldm, int64_t ps,
-                                                 int d, const double* __restrict__ V, int64_t ldv,
-                                                 int nb, double* __restrict__ work, int64_t wld) {
+// The stand-alone product (Lanczos steps, Rayleigh-Ritz, subspace
+// extraction) splits each chunk over two groups while the group sums fit
+// the LDS: twice the waves, each with half the dependent round trips to
+// memory (measured at d = 4096, 12 columns: 36 -> 24 us).
+template <int NB>
+constexpr int symthin_ks() { return NB <= 16 ? 2 : 1; }
+
+template <typename MT, int NB, int KS = symthin_ks<NB>()>
+__global__ __launch_bounds__(256 * KS) void k_symthin(const MT* __restrict__ M, int64_t ldm,
+                                                      int64_t ps, int d,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      int nb, double* __restrict__ work,
+                                                      int64_t wld) {
   __shared__ double pv[SRC][NB];
+  __shared__ ThinRed<KS, NB> red;
   const int j0 = blockIdx.y * SRC;
-  for (int e = threadIdx.x; e < SRC * NB; e += 256) {
+  for (int e = threadIdx.x; e < SRC * NB; e += 256 * KS) {
     const int jj = e / NB, c = e % NB, j = j0 + jj;
     pv[jj][c] = (j < d && c < nb) ? V[(int64_t)c * ldv + j] : 0.0;
   }
   __syncthreads();
-  symthin_body<MT, NB>(M, ldm, ps, d, pv, work, wld, nb);
+  symthin_body<MT, NB, SRC, KS>(M, ldm, ps, d, pv, work, wld, nb, red);
 }
 
 // ------------------------------------------------------------ block CG
 // Solves, column by column (c < nb), the projected correction equations
-//   (I - V V^T)(H - theta_c I)(I - V V^T) z_c = b_c,  z_c, b_c orthogonal to V,
-// by conjugate gradients (the operator is positive definite on the
-// complement of V when theta_c lies below the spectrum there).
-//
-// Iteration `it` is three launches with no atomics or fences between
-// blocks: each kernel re-reduces, in a fixed order, the per-block partial
-// sums the previous kernel wrote, and the kernel boundary makes them
-// visible.
-//   k_cg_thin    rho_c = |r_c|^2 (partials of the last update; rho0 at it 0),
-//                convergence test, beta_c = rho_c / rho_prev; block 0
-//                records rho, beta, iters, done.  Then the chunk partials of
-//                M p with p = r + beta p_old formed in LDS.
-//   k_cg_apply   Ap = chunk sums - theta_c p; p_next = p; per-block partials
-//                of V^T Ap and p . Ap.
-//   k_cg_update  reduces those for its column: C = V^T Ap, alpha_c =
-//                rho_c / (p . Ap); z += alpha p, r -= alpha (Ap - V C);
-//                per-block partials of |r_c|^2.
-// Every kernel returns at once when state->done is set, so batches of
+//   A_c z_c = b_c,  A_c = (I - V V^T)(H - theta_c I)(I - V V^T),
+// z_c and b_c orthogonal to V, by conjugate gradients (A_c is positive
+// definite on the complement of V when theta_c lies below the spectrum
+// there).  The recurrences are those of Chronopoulos and Gear (1989): with
+// w = A r, the two inner products of an iteration, gamma = r.r and
+// delta = r.w, come from the same operator application, so one iteration
+// has a single reduction point:
+//   beta_i  = gamma_i / gamma_{i-1}                        (beta_0 = 0)
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+//                                                      (alpha_0 = gamma_0 / delta_0)
+//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1},
+//   z_{i+1} = z_i + alpha_i p_i,  r_{i+1} = r_i - alpha_i s_i.
+// Iteration `it` is two launches with no atomics or fences between blocks:
+//   k_cg_step   (it >= 1) every block re-reduces, in a fixed order, the
+//               partials of the previous k_cg_apply: C = V^T (H - theta) r,
+//               gamma, delta per column; convergence test on gamma;
+//               alpha, beta; then the update above for the rows of its
+//               chunk (w = (H - theta) r - V C), written by the blocks of
+//               column 0 of the grid.  Then the chunk partials of H r.
+//   k_cg_apply  (H - theta) r = chunk sums - theta r, and per-block
+//               partials of V^T (H - theta) r, r.r and r.(H - theta) r.
+// The kernel boundary makes each kernel's stores visible to the next.
+// r, p and s alternate between two buffers by iteration parity, so a
+// block never reads a row another block of the same launch writes.  Every
+// kernel returns at once when state->done is set, so batches of
 // iterations are enqueued without host synchronisation.
 struct CgState {
-  double theta[32], rho0[32], rho[2][32], beta[32];
+  double theta[32], rho0[32], gam[2][32], alpha[2][32];
   double tol2;
   int iters, done, k, nb;
 };
 
 // Grid (column blocks of 256 output rows, chunks of CHUNK rows of M).  M is
-// H in FP64 (CHUNK = SRC), or its FP32 copy (CHUNK = SRC/2; the products
-// still accumulate in FP64): an FP32 pass moves half the bytes per load and
-// needs twice the waves (half the chunk) to keep as many bytes in flight.
+// H in FP64, or its FP32 copy (the products still accumulate in FP64).  An
+// FP32 pass moves half the bytes per load, so it needs twice the waves to
+// keep as many bytes in flight: its 128-row chunks are split over two
+// groups of four waves (the same number of chunk partials as the FP64
+// pass).
 constexpr int CG_SRC = SRC / 2;
-template <typename MT, int NB, int CHUNK = (sizeof(MT) == 4 ? CG_SRC : SRC)>
-__global__ __launch_bounds__(256) void k_cg_thin(const MT* __restrict__ M, int64_t ldm, int d,
-                                                 const double* __restrict__ Rr,
-                                                 const double* __restrict__ Pold, int64_t ldv,
-                                                 CgState* __restrict__ st,
-                                                 const double* __restrict__ upart, int ngroups,
-                                                 double* __restrict__ work, int64_t wld, int it,
-                                                 int max_iter) {
+template <typename MT, int NB>
+constexpr int cg_ks() { return (sizeof(MT) == 4 && NB <= 16) ? 2 : 1; }
+template <typename MT, int NB>
+constexpr int cg_chunk() { return sizeof(MT) == 4 ? CG_SRC * cg_ks<MT, NB>() : SRC; }
+
+template <typename MT, int NB, int CHUNK = cg_chunk<MT, NB>(), int KS = cg_ks<MT, NB>()>
+__global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, int64_t ldm, int d,
+                                                      const double* __restrict__ V, int64_t ldv,
+                                                      CgBufs b, CgState* __restrict__ st,
+                                                      const double* __restrict__ apart,
+                                                      int ngroups, double* __restrict__ work,
+                                                      int64_t wld, int it, int max_iter) {
   if (st->done) return;
+  constexpr int NT = 256 * KS, NW = NT / 64;
   __shared__ double pv[CHUNK][NB];
-  __shared__ double sbeta[NB];
-  __shared__ int sdone;
-  const int nb = st->nb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) sdone = 0;
-  if (threadIdx.x < NB) sbeta[threadIdx.x] = 0.0;
-  __syncthreads();
-  if (it > 0 && wave == 0) {
-    int conv = 1;
-    for (int c0 = 0; c0 < nb; c0 += 8) {
-      double a[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        a[u] = 0.0;
-        if (c0 + u < nb)
-          for (int g = lane; g < ngroups; g += 64) a[u] += upart[(int64_t)g * nb + c0 + u];
+  __shared__ ThinRed<KS, NB> red;
+  __shared__ double sC[NB][34];
+  __shared__ double sal[NB], sbe[NB];
+  __shared__ int sconv;
+  const int nb = st->nb, k = st->k;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j0 = blockIdx.y * CHUNK;
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+  if (it == 0) {
+    for (int e = tid; e < NB * CHUNK; e += NT) {
+      const int c = e / CHUNK, jj = e % CHUNK, j = j0 + jj;
+      pv[jj][c] = (c < nb && j < d) ? b.R[0][(int64_t)c * ldv + j] : 0.0;
+    }
+    if (first && tid == 0) st->iters = 0;
+  } else {
+    // Partials of the previous apply: apart[(g nb + c)(k + 2) + v], v < k
+    // the entries of C[:, c], then gamma and delta.
+    const int nv = k + 2, npairs = nb * nv;
+    for (int q = wave; q < npairs; q += NW) {
+      const int c = q / nv, v = q % nv;
+      double acc = 0.0;
+      for (int g = lane; g < ngroups; g += 64) acc += apart[((int64_t)g * nb + c) * nv + v];
+      acc = wave_sum(acc);
+      if (lane == 0) sC[c][v] = acc;
+    }
+    if (tid == 0) sconv = 1;
+    __syncthreads();
+    if (tid < nb) {
+      const int c = tid;
+      const double gam = sC[c][k], del = sC[c][k + 1];
+      double alpha, beta = 0.0;
+      if (it >= 2) {
+        const double gp = st->gam[it & 1][c], ap = st->alpha[it & 1][c];
+        beta = gp > 0.0 ? gam / gp : 0.0;
+        const double den = del - (ap != 0.0 ? beta * gam / ap : 0.0);
+        alpha = den != 0.0 ? gam / den : 0.0;
+      } else {
+        alpha = del != 0.0 ? gam / del : 0.0;
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int c = c0 + u;
-        if (c < nb) {
-          const double rho = wave_sum(a[u]);
-          const double prev = st->rho[(it - 1) & 1][c];
-          const double beta = prev > 0.0 ? rho / prev : 0.0;
-          if (!(rho <= st->tol2 * st->rho0[c])) conv = 0;
-          if (lane == 0) {
-            sbeta[c] = beta;
-            if (blockIdx.x == 0 && blockIdx.y == 0) {
-              st->rho[it & 1][c] = rho;
-              st->beta[c] = beta;
-            }
-          }
-        }
+      sal[c] = alpha;
+      sbe[c] = beta;
+      if (!(gam <= st->tol2 * st->rho0[c])) sconv = 0;
+      if (first) {
+        st->gam[(it - 1) & 1][c] = gam;
+        st->alpha[(it - 1) & 1][c] = alpha;
       }
     }
-    if (lane == 0 && (conv || it >= max_iter)) {
-      sdone = 1;
-      if (blockIdx.x == 0 && blockIdx.y == 0) {
-        st->iters = it;
+    __syncthreads();
+    // Iteration it applies update it - 1; the test is on r_{it-1}.
+    if (sconv || it - 1 >= max_iter) {
+      if (first && tid == 0) {
+        st->iters = it - 1;
         st->done = 1;
       }
+      return;
     }
-  } else if (it == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < nb) {
-    st->rho[0][threadIdx.x] = st->rho0[threadIdx.x];
-    st->beta[threadIdx.x] = 0.0;
+    const double* Rin = b.R[(it - 1) & 1];
+    double* Rout = b.R[it & 1];
+    const double* Pin = b.P[it & 1];
+    double* Pout = b.P[(it - 1) & 1];
+    const double* Sin = b.S[it & 1];
+    double* Sout = b.S[(it - 1) & 1];
+    const bool writer = blockIdx.x == 0;
+    for (int e = tid; e < NB * CHUNK; e += NT) {
+      const int c = e / CHUNK, jj = e % CHUNK, j = j0 + jj;
+      double rn = 0.0;
+      if (c < nb && j < d) {
+        const int64_t o = (int64_t)c * ldv + j;
+        double w = b.HR[o];
+        for (int i = 0; i < k; ++i) w = fma(-V[(int64_t)i * ldv + j], sC[c][i], w);
+        const double r = Rin[o], al = sal[c];
+        double pn = r, sn = w;
+        if (it >= 2) {
+          pn = fma(sbe[c], Pin[o], r);
+          sn = fma(sbe[c], Sin[o], w);
+        }
+        rn = fma(-al, sn, r);
+        if (writer) {
+          Pout[o] = pn;
+          Sout[o] = sn;
+          b.Z[o] = fma(al, pn, b.Z[o]);
+          Rout[o] = rn;
+        }
+      }
+      pv[jj][c] = rn;
+    }
+    if (first && tid == 0) st->iters = it;
   }
   __syncthreads();
-  if (sdone) return;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st->iters = it + 1;
-  const int j0 = blockIdx.y * CHUNK;
-  for (int e = threadIdx.x; e < CHUNK * NB; e += 256) {
-    const int jj = e / NB, c = e % NB, j = j0 + jj;
-    pv[jj][c] = (j < d && c < nb)
-                    ? Rr[(int64_t)c * ldv + j] + sbeta[c] * Pold[(int64_t)c * ldv + j]
-                    : 0.0;
-  }
-  __syncthreads();
-  symthin_body<MT, NB, CHUNK>(M, ldm, 0, d, pv, work, wld, nb);
+  symthin_body<MT, NB, CHUNK, KS>(M, ldm, 0, d, pv, work, wld, nb, red);
 }
 
 // Grid (row groups of 64, column c), 256 threads: four lanes per row, each
@@ -744,20 +825,18 @@ __global__ __launch_bounds__(256) void k_cg_thin(const MT* __restrict__ M, int64
 template <int NB>
 __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ work, int64_t wld,
                                                   int nchunk, int d, const double* __restrict__ V,
-                                                  const double* __restrict__ Rr,
-                                                  const double* __restrict__ Pold,
-                                                  double* __restrict__ Pnext,
-                                                  double* __restrict__ AP, int64_t ldv,
+                                                  int64_t ldv, const double* __restrict__ R,
+                                                  double* __restrict__ HR,
                                                   const CgState* __restrict__ st,
                                                   double* __restrict__ apart) {
   if (st->done) return;
-  __shared__ double red[4][34];
+  __shared__ double red[4][35];
   const int nb = st->nb, k = st->k;
   const int c = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & 3;
   const int row = blockIdx.x * 64 + (tid >> 2);
-  double pc = 0.0, s = 0.0;
+  double rc = 0.0, s = 0.0;
   if (row < d) {
     double acc[4] = {0, 0, 0, 0};
     int q = sub;
@@ -773,75 +852,28 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
   const bool owner = sub == 0 && row < d;
   if (owner) {
     const int64_t o = (int64_t)c * ldv + row;
-    pc = Rr[o] + st->beta[c] * Pold[o];
-    s -= st->theta[c] * pc;
-    Pnext[o] = pc;
-    AP[o] = s;
+    rc = R[o];
+    s -= st->theta[c] * rc;
+    HR[o] = s;
   } else {
     s = 0.0;
   }
-  // Partials: V^T Ap (k values) then p . Ap, at apart[group][c][0..k]; the
-  // four waves' sums are added in a fixed order.
+  // Partials: V^T (H - theta) r (k values), r.r, r.(H - theta) r at
+  // apart[group][c][0..k+1]; the four waves' sums are added in a fixed order.
   for (int i = 0; i < k; ++i) {
     const double vi = owner ? V[(int64_t)i * ldv + row] : 0.0;
     const double t = wave_sum(vi * s);
     if (lane == 0) red[wave][i] = t;
   }
-  const double t = wave_sum(pc * s);
-  if (lane == 0) red[wave][k] = t;
-  __syncthreads();
-  double* mypart = apart + ((int64_t)blockIdx.x * nb + c) * (k + 1);
-  if (tid <= k) mypart[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-}
-
-// Grid (row groups of 64, column c).
-template <int NB>
-__global__ __launch_bounds__(64) void k_cg_update(int d, const double* __restrict__ V,
-                                                  const double* __restrict__ P,
-                                                  const double* __restrict__ AP,
-                                                  double* __restrict__ Z, double* __restrict__ Rr,
-                                                  int64_t ldv, const CgState* __restrict__ st,
-                                                  const double* __restrict__ apart,
-                                                  double* __restrict__ upart, int it) {
-  if (st->done) return;
-  const int nb = st->nb, k = st->k;
-  const int c = blockIdx.y;
-  const int lane = threadIdx.x;
-  const int row = blockIdx.x * 64 + lane;
-  const int ngroups = gridDim.x;
-  __shared__ double sC[33];
-  // Reduce this column's apply partials (fixed order): C[:, c], p . Ap.
-  for (int i0 = 0; i0 <= k; i0 += 8) {
-    double a[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a[u] = 0.0;
-      if (i0 + u <= k)
-        for (int g = lane; g < ngroups; g += 64) a[u] += apart[((int64_t)g * nb + c) * (k + 1) + i0 + u];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (i0 + u <= k) {
-        const double t = wave_sum(a[u]);
-        if (lane == 0) sC[i0 + u] = t;
-      }
-    }
+  const double t1 = wave_sum(rc * rc);
+  const double t2 = wave_sum(rc * s);
+  if (lane == 0) {
+    red[wave][k] = t1;
+    red[wave][k + 1] = t2;
   }
   __syncthreads();
-  const double alpha = (sC[k] != 0.0) ? st->rho[it & 1][c] / sC[k] : 0.0;
-  double rr = 0.0;
-  if (row < d) {
-    double proj = 0.0;
-    for (int i = 0; i < k; ++i) proj = fma(V[(int64_t)i * ldv + row], sC[i], proj);
-    const int64_t o = (int64_t)c * ldv + row;
-    const double pz = P[o], ap = AP[o], z = Z[o], r0 = Rr[o];
-    Z[o] = fma(alpha, pz, z);
-    const double r = r0 - alpha * (ap - proj);
-    Rr[o] = r;
-    rr = r * r;
-  }
-  const double t = wave_sum(rr);
-  if (lane == 0) upart[(int64_t)blockIdx.x * nb + c] = t;
+  double* mypart = apart + ((int64_t)blockIdx.x * nb + c) * (k + 2);
+  if (tid < k + 2) mypart[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 template <int W>
@@ -1153,7 +1185,7 @@ size_t cg_state_bytes() {
   static_assert(sizeof(CgState) == sizeof(CgHost), "CgState and CgHost must match");
   return sizeof(CgState);
 }
-size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 34; }
+size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 34; }  // nb (k + 2) per group
 size_t thin_work_doubles(int d) {
   const size_t a = (size_t)nblocks(d, 128) * 32 * (size_t)d;
   const size_t b = (size_t)nblocks(d, SRC) * 32 * (size_t)d;
@@ -1161,6 +1193,15 @@ size_t thin_work_doubles(int d) {
   return std::max(a, std::max(b, c));
 }
 size_t gram_work_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 32; }
+
+// Block widths the thin products are instantiated for: exact up to 8
+// columns (the loop over columns is unrolled, so padding costs FMAs and LDS
+// reads), then 12, 16, 24 and 32.
+#define REFL_NB_DISPATCH(nb, X)                                                                  \
+  if ((nb) == 1) X(1) else if ((nb) == 2) X(2) else if ((nb) == 3) X(3)                          \
+  else if ((nb) == 4) X(4) else if ((nb) == 5) X(5) else if ((nb) == 6) X(6)                     \
+  else if ((nb) == 7) X(7) else if ((nb) == 8) X(8) else if ((nb) <= 12) X(12)                   \
+  else if ((nb) <= 16) X(16) else if ((nb) <= 24) X(24) else if ((nb) <= 32) X(32)
 
 // Symmetric thin products (Hf, the word iterate): column-lane kernel plus
 // the ordered chunk sum.
@@ -1172,16 +1213,14 @@ static hipError_t symthin_dispatch(const MT* M, int64_t ldm, int64_t ps, int d, 
   const dim3 grid(nblocks(d, 256), nblocks(d, SRC));
 #define REFL_STHIN(NBV)                                                                          \
   {                                                                                              \
-    hipLaunchKernelGGL((k_symthin<MT, NBV>), grid, dim3(256), 0, st, M, ldm, ps, d, V, ldv, nb,  \
+    hipLaunchKernelGGL((k_symthin<MT, NBV>), grid, dim3(256 * symthin_ks<NBV>()), 0, st, M, ldm, \
+                       ps, d, V, ldv, nb,                                                  \
                        work, wld);                                                               \
     hipLaunchKernelGGL((k_thin_finish<NBV>), dim3(nblocks(d, 256), nb), dim3(256), 0, st, work,  \
                        wld, (int)grid.y, d, nb, Y, ldy);                                         \
   }
   if (nb <= 0) return hipSuccess;
-  if (nb <= 4) REFL_STHIN(4)
-  else if (nb <= 8) REFL_STHIN(8)
-  else if (nb <= 16) REFL_STHIN(16)
-  else if (nb <= 32) REFL_STHIN(32)
+  REFL_NB_DISPATCH(nb, REFL_STHIN)
   else return hipErrorInvalidValue;
 #undef REFL_STHIN
   return hipGetLastError();
@@ -1202,37 +1241,33 @@ hipError_t symthin_words(int words, const uint16_t* X, int ld, int64_t ps, int d
   }
 }
 
-// One CG iteration (three launches).  Pold/Pnext alternate between calls;
-// `it` counts from 0.  part holds the apply partials, then the update ones.
+// One CG iteration (two launches); `it` counts from 0 within a solve.
 hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb,
-                        const double* V, int64_t ldv, double* Rr, const double* Pold,
-                        double* Pnext, double* AP, double* Z, void* state, double* work,
-                        double* part, int it, int max_iter, hipStream_t st) {
+                        const double* V, int64_t ldv, const CgBufs& bufs, void* state,
+                        double* work, double* part, int it, int max_iter, hipStream_t st) {
   CgState* s = reinterpret_cast<CgState*>(state);
   const int64_t wld = d;
-  const dim3 grid(nblocks(d, 256), nblocks(d, M32 ? CG_SRC : SRC));
   const int nrb = nblocks(d, 64);
-  double* apart = part;
-  double* upart = part + (size_t)nrb * 32 * 33;
+#define REFL_CG_STEP(MT, MP, NBV)                                                                \
+  {                                                                                              \
+    constexpr int CH = cg_chunk<MT, NBV>();                                                      \
+    nchunk = nblocks(d, CH);                                                                     \
+    hipLaunchKernelGGL((k_cg_step<MT, NBV>), dim3(nblocks(d, 256), nchunk),                      \
+                       dim3(256 * cg_ks<MT, NBV>()), 0, st, MP, ldm, d, V, ldv, bufs, s, part,   \
+                       nrb, work, wld, it, max_iter);                                            \
+  }
 #define REFL_CG(NBV)                                                                             \
   {                                                                                              \
-    if (M32)                                                                                     \
-      hipLaunchKernelGGL((k_cg_thin<float, NBV>), grid, dim3(256), 0, st, M32, ldm, d, Rr, Pold, \
-                         ldv, s, upart, nrb, work, wld, it, max_iter);                           \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_cg_thin<double, NBV>), grid, dim3(256), 0, st, M, ldm, d, Rr, Pold,  \
-                         ldv, s, upart, nrb, work, wld, it, max_iter);                           \
-    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb, nb), dim3(256), 0, st, work, wld, (int)grid.y, \
-                       d, V, Rr, Pold, Pnext, AP, ldv, s, apart);                                \
-    hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrb, nb), dim3(64), 0, st, d, V, Pnext, AP, Z,    \
-                       Rr, ldv, s, apart, upart, it);                                            \
+    int nchunk = 0;                                                                              \
+    if (M32) REFL_CG_STEP(float, M32, NBV)                                                       \
+    else REFL_CG_STEP(double, M, NBV)                                                            \
+    hipLaunchKernelGGL((k_cg_apply<NBV>), dim3(nrb, nb), dim3(256), 0, st, work, wld, nchunk, d, \
+                       V, ldv, bufs.R[it & 1], bufs.HR, s, part);                                \
   }
-  if (nb <= 4) REFL_CG(4)
-  else if (nb <= 8) REFL_CG(8)
-  else if (nb <= 16) REFL_CG(16)
-  else if (nb <= 32) REFL_CG(32)
+  REFL_NB_DISPATCH(nb, REFL_CG)
   else return hipErrorInvalidValue;
 #undef REFL_CG
+#undef REFL_CG_STEP
   return hipGetLastError();
 }
 

@@ -557,9 +557,11 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
       use32 = true;
     }
     // Correction: (I - VV^T)(H - theta_c)(I - VV^T) z_c = -E_c by block CG.
+    // Besides its own buffers the solve uses the blocks that are free until
+    // the next Rayleigh-Ritz step: spare (not V), Wm and Wspare.
     HIPCHK(lincomb(d, k, -1.0, w.Rr, ld, 0.0, w.Rr, ld, st));
     HIPCHK(lincomb(d, k, 0.0, w.Rr, ld, 0.0, w.Z, ld, st));
-    HIPCHK(lincomb(d, k, 0.0, w.Rr, ld, 0.0, w.P[0], ld, st));
+    const CgBufs cb = {{w.Rr, spare}, {w.P[0], w.P[1]}, {Wm, Wspare}, w.AP, w.Z};
     std::memset(hs, 0, sizeof(CgHost));
     for (int c = 0; c < k; ++c) {
       hs->theta[c] = th[c];
@@ -573,15 +575,14 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     while (true) {
       // First batch 32 iterations (every correction solve here needs more),
       // then 16 between host checks of the convergence flag.  Iteration
-      // cg_max_iter only runs the convergence test.
+      // cg_max_iter + 1 only runs the convergence test.
       const int batch = issued == 0 ? 32 : 16;
-      for (int b = 0; b < batch && issued <= p.cg_max_iter; ++b, ++issued)
-        HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, d, k, V, ld, w.Rr, w.P[issued & 1],
-                            w.P[(issued + 1) & 1], w.AP, w.Z, w.cgstate, w.thin, w.cgpart, issued,
-                            p.cg_max_iter, st));
+      for (int b = 0; b < batch && issued <= p.cg_max_iter + 1; ++b, ++issued)
+        HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, d, k, V, ld, cb, w.cgstate, w.thin,
+                            w.cgpart, issued, p.cg_max_iter, st));
       HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
-      if (hs->done || issued > p.cg_max_iter) break;
+      if (hs->done || issued > p.cg_max_iter + 1) break;
     }
     cg_total += hs->iters;
     // V <- orth(V + Z)

@@ -333,6 +333,25 @@ def test_mixed_inner_solve_precision(R, handle, cg_prec):
     assert st == 0 and err <= target and err <= info["dk_bound"] * 1.0001 + 1e-15
 
 
+@pytest.mark.parametrize("k,cg_prec", [(12, "fp32"), (20, "fp64"), (32, "fp32"), (32, "fp64")])
+def test_mixed_wide_target_blocks(R, handle, k, cg_prec):
+    """Wide target spaces take the block widths past 8 columns (12, 24, 32)
+    in the subspace extraction, the Rayleigh-Ritz products and the inner
+    CG, whose FP32 pass splits its chunks over two wave groups up to 16
+    columns and not beyond; d = 700 leaves a ragged chunk and row group."""
+    d = 700
+    H, lam, Q = inputs.planted_hessian(d, k, 0.1, k)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    target = 1e-8 * np.sqrt(d)
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", tol=target,
+                          cg_prec=cg_prec)
+    err = np.linalg.norm(Rg.cpu().numpy() - oracle.reflector_from_eig(Q, k))
+    _say(f"mixed d={d} k={k} inner {cg_prec}: status={R.STATUS[st]} sweeps={info['polish_sweeps']} "
+         f"cg={info['cg_iters']} dk={info['dk_bound']:.2e} err={err:.2e}")
+    assert st == 0 and info["index_j"] == k
+    assert err <= target and err <= info["dk_bound"] * 1.0001 + 1e-15
+
+
 @pytest.mark.parametrize("k", [1, 3, 5])
 def test_mixed_allen_cahn_d4096(R, handle, k):
     _say(f"mixed Allen-Cahn d=4096 k={k}")

@@ -6,10 +6,14 @@
 //     k_lz_proj_partial / k_lz_proj_finish   C = V^T W   (n x nb)
 //     k_lz_apply_partial + k_lz_rows(SUB)    W <- W - V C
 //   then three rounds of Cholesky QR, the first one shifted (shifted
-//   CholQR3 of Fukaya, Kannan, Nakatsukasa, Zhang and Yamamoto, 2020)
-//     k_lz_rows(GRAM)  partial Gram matrices of 256-row slabs
-//     k_lz_chol        one block: G = L L^T, R = L^T, B <- R B
-//     k_lz_rows(TRSM)  W <- W R^{-1}
+//   CholQR3 of Fukaya, Kannan, Nakatsukasa, Zhang and Yamamoto, 2020), on
+//   the partial Gram matrices of 256-row slabs (from the second
+//   projection pass, or k_lz_rows(GRAM) for the start block):
+//     k_lz_cholqr      every block sums the slab Grams and factors
+//                      G = L L^T itself (the same sum in the same order, so
+//                      the same R = L^T), then W <- W R^{-1} on its slab and
+//                      the slab Gram of the result for the next round;
+//                      block 0 also records B <- R B and the flags
 //   so that W_in = Q_{j+1} B_j with B_j upper triangular.
 //
 // The diagonal block A_j = Q_j^T H Q_j is the last block of the two
@@ -244,125 +248,187 @@ __global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, i
   }
 }
 
-// One block.  G = sum of the slab Gram matrices (fixed order), symmetrised,
-// plus sigma I with sigma = shift_rel * trace(G) when shift_rel > 0.
-// Cholesky G = L L^T in LDS; R = L^T (nb x nb, col-major) to Rout; Bacc = R
-// (round 0) or R Bacc.  A non-positive pivot is replaced by 1 and bit 1 of
-// flag[0] set.  With Brec != null (the last round of a Lanczos step), Bacc
-// is also copied to Brec, and if its smallest diagonal entry is below 1e-10
-// times the largest entry of Arec or Bacc, bit 2 of flag[0] is set (the
-// block Krylov space has become, to working accuracy, invariant).  flag[1]
-// keeps the first `tag` (the step number) at which a bit was set.
-__global__ __launch_bounds__(256) void k_lz_chol(const double* __restrict__ gpart, int nblk, int nb,
-                                                 int NB, double shift_rel,
-                                                 double* __restrict__ Rout,
-                                                 double* __restrict__ Bacc, int round,
-                                                 const double* __restrict__ Arec,
-                                                 double* __restrict__ Brec, int* __restrict__ flag,
-                                                 int tag) {
-  __shared__ double G[32][33];
-  __shared__ double Bo[32][33];
-  __shared__ double Bt[32][33];
-  __shared__ double red[2];
-  __shared__ int bad;
+// Shared state of one Cholesky QR round.
+struct LzFactor {
+  double G[32][33];
+  double Bo[32][33];
+  double Bt[32][33];
+  double red[5];
+  int bad;
+};
+
+// All threads of the block.  G = sum of the slab Gram matrices gpart
+// (nblk slabs of NBP x NBP, fixed order), symmetrised, plus sigma I with
+// sigma = shift_rel * trace(G) when shift_rel > 0; then G = L L^T in place
+// (lower triangle; R = L^T).  A non-positive pivot is replaced by 1 and
+// f.bad set.  With load_bo, f.Bo = Bacc (nb x nb, column-major).
+__device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb, int NBP,
+                          double shift_rel, const double* __restrict__ Bacc, bool load_bo,
+                          LzFactor& f) {
   const int t = threadIdx.x;
-  // Sum of the slab partials: thread t takes entries t, t + 256, ...; the
-  // loads of one entry are independent and issued together.
+  // Thread t sums entry t (and t + 256, ...) over the slabs: sixteen loads
+  // in flight per round, accumulated round-robin into four sums.
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const double* g = gpart + i + j * NBP;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
     int b = 0;
-    for (; b + 4 <= nblk; b += 4) {
-      s0 += gpart[(int64_t)(b + 0) * NB * NB + i + j * NB];
-      s1 += gpart[(int64_t)(b + 1) * NB * NB + i + j * NB];
-      s2 += gpart[(int64_t)(b + 2) * NB * NB + i + j * NB];
-      s3 += gpart[(int64_t)(b + 3) * NB * NB + i + j * NB];
+    for (; b + 16 <= nblk; b += 16) {
+      double a[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] = g[(int64_t)(b + u) * NBP * NBP];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s4[u & 3] += a[u];
     }
-    for (; b < nblk; ++b) s0 += gpart[(int64_t)b * NB * NB + i + j * NB];
-    G[i][j] = (s0 + s1) + (s2 + s3);
-    if (round > 0) Bo[i][j] = Bacc[i + j * nb];
+    for (; b + 4 <= nblk; b += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s4[u] += g[(int64_t)(b + u) * NBP * NBP];
+    }
+    for (; b < nblk; ++b) s4[0] += g[(int64_t)b * NBP * NBP];
+    f.G[i][j] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    if (load_bo) f.Bo[i][j] = Bacc[i + j * nb];
   }
-  if (t == 0) bad = 0;
+  if (t == 0) f.bad = 0;
   __syncthreads();
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
     if (i < j) {
-      const double v = 0.5 * (G[i][j] + G[j][i]);
-      G[i][j] = v;
-      G[j][i] = v;
+      const double v = 0.5 * (f.G[i][j] + f.G[j][i]);
+      f.G[i][j] = v;
+      f.G[j][i] = v;
     }
   }
   __syncthreads();
   if (t == 0) {
     double tr = 0.0;
-    for (int i = 0; i < nb; ++i) tr += G[i][i];
-    red[0] = shift_rel > 0.0 ? shift_rel * tr : 0.0;
+    for (int i = 0; i < nb; ++i) tr += f.G[i][i];
+    f.red[0] = shift_rel > 0.0 ? shift_rel * tr : 0.0;
   }
   __syncthreads();
-  if (t < nb) G[t][t] += red[0];
+  if (t < nb) f.G[t][t] += f.red[0];
   __syncthreads();
   // Right-looking Cholesky, lower triangle; thread t < nb owns row t.
   for (int p = 0; p < nb; ++p) {
     if (t == 0) {
-      double piv = G[p][p];
+      double piv = f.G[p][p];
       if (!(piv > 0.0) || !isfinite(piv)) {
         piv = 1.0;
-        bad = 1;
+        f.bad = 1;
       }
-      G[p][p] = sqrt(piv);
+      f.G[p][p] = sqrt(piv);
     }
     __syncthreads();
     if (t > p && t < nb) {
-      const double l = G[t][p] / G[p][p];
-      G[t][p] = l;
-      for (int j = p + 1; j <= t; ++j) G[t][j] -= l * G[j][p];
+      const double l = f.G[t][p] / f.G[p][p];
+      f.G[t][p] = l;
+      for (int j = p + 1; j <= t; ++j) f.G[t][j] -= l * f.G[j][p];
     }
     __syncthreads();
   }
-  // R = L^T (upper); Bt = R (round 0) or R Bo.
+}
+
+// Block 0 of a round.  Bacc = R (round 0) or R Bacc.  bit 1 of flag[0] for
+// a replaced pivot.  With Brec != null (the last round of a Lanczos step),
+// Bacc is also copied to Brec, and if its smallest diagonal entry is below
+// 1e-10 times the largest entry of Arec or Bacc, bit 2 of flag[0] is set
+// (the block Krylov space has become, to working accuracy, invariant).
+// flag[1] keeps the first `tag` (the step number) at which a bit was set.
+__device__ void lz_record(int nb, int round, double* __restrict__ Bacc,
+                          const double* __restrict__ Arec, double* __restrict__ Brec,
+                          int* __restrict__ flag, int tag, LzFactor& f) {
+  const int t = threadIdx.x;
   if (t < nb) {
     for (int i = 0; i < nb; ++i) {
-      const double rij = (i <= t) ? G[t][i] : 0.0;  // R[i][t] = L[t][i]
-      Rout[i + t * nb] = rij;
+      const double rij = (i <= t) ? f.G[t][i] : 0.0;  // R[i][t] = L[t][i]
       double s;
       if (round == 0) {
         s = rij;
       } else {
         s = 0.0;
-        for (int m = i; m <= t; ++m) s += G[m][i] * Bo[m][t];  // R[i][m] B[m][t]
+        for (int m = i; m <= t; ++m) s += f.G[m][i] * f.Bo[m][t];  // R[i][m] B[m][t]
       }
-      Bt[i][t] = s;
+      f.Bt[i][t] = s;
     }
   }
   __syncthreads();
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
-    Bacc[i + j * nb] = Bt[i][j];
-    if (Brec) Brec[i + j * nb] = Bt[i][j];
+    Bacc[i + j * nb] = f.Bt[i][j];
+    if (Brec) Brec[i + j * nb] = f.Bt[i][j];
   }
-  if (t == 0 && bad) {
+  if (t == 0 && f.bad) {
     flag[0] |= 1;
     if (flag[1] == 0) flag[1] = tag;
   }
   if (!Brec) return;
-  // Near-invariance test: smallest |B_ii| against the largest entry of A_j, B_j.
   double big = 0.0;
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
-    big = fmax(big, fmax(fabs(Bt[i][j]), fabs(Arec[i + j * nb])));
+    big = fmax(big, fmax(fabs(f.Bt[i][j]), fabs(Arec[i + j * nb])));
   }
   big = wave_max(big);
-  __syncthreads();
-  if ((t & 63) == 0) G[0][1 + (t >> 6)] = big;
+  if ((t & 63) == 0) f.red[1 + (t >> 6)] = big;
   __syncthreads();
   if (t == 0) {
-    big = fmax(fmax(G[0][1], G[0][2]), fmax(G[0][3], G[0][4]));
+    big = fmax(fmax(f.red[1], f.red[2]), fmax(f.red[3], f.red[4]));
     double small = INFINITY;
-    for (int i = 0; i < nb; ++i) small = fmin(small, fabs(Bt[i][i]));
+    for (int i = 0; i < nb; ++i) small = fmin(small, fabs(f.Bt[i][i]));
     if (!(small > 1e-10 * big)) {
       flag[0] |= 2;
       if (flag[1] == 0) flag[1] = tag;
     }
+  }
+}
+
+// One Cholesky QR round on 256-row slabs (one row per thread): factor the
+// Gram of W from gin, dst = W R^{-1}, and with gout != null the slab Gram
+// partials of dst.  W and dst may be the same block (each thread reads its
+// row before writing it); gin and gout must differ.
+template <int NB>
+__global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gin, int nblk,
+                                                   int nb, double shift_rel,
+                                                   double* __restrict__ Bacc, int round,
+                                                   const double* __restrict__ Arec,
+                                                   double* __restrict__ Brec,
+                                                   int* __restrict__ flag, int tag,
+                                                   const double* W, int64_t ldw, int d,
+                                                   double* dst, int64_t ldd,
+                                                   double* __restrict__ gout) {
+  __shared__ LzFactor f;
+  __shared__ double sX[256][NB + 1];
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  // The slab's rows are requested before the factorisation, which does not
+  // depend on them.
+  double x[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) x[j] = (r < d && j < nb) ? W[(int64_t)j * ldw + r] : 0.0;
+  const bool rec = blockIdx.x == 0;
+  lz_factor(gin, nblk, nb, NB, shift_rel, Bacc, rec && round > 0, f);
+  if (rec) lz_record(nb, round, Bacc, Arec, Brec, flag, tag, f);
+  // x R = w for upper-triangular R = L^T: R[i][j] = G[j][i].
+  if (r < d) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < nb) {
+        double s = x[j];
+#pragma unroll
+        for (int i = 0; i < j; ++i) s = fma(-x[i], f.G[j][i], s);
+        x[j] = s / f.G[j][j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < nb) dst[(int64_t)j * ldd + r] = x[j];
+  }
+  if (!gout) return;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) sX[threadIdx.x][j] = x[j];
+  __syncthreads();
+  for (int o = threadIdx.x; o < nb * nb; o += 256) {
+    const int i = o % nb, j = o / nb;
+    double a = 0.0;
+    for (int t = 0; t < 256; ++t) a = fma(sX[t][i], sX[t][j], a);
+    gout[(int64_t)blockIdx.x * NB * NB + i + j * NB] = a;
   }
 }
 
@@ -413,12 +479,15 @@ hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R,
   return hipGetLastError();
 }
 
-hipError_t lz_chol(const double* gpart, int d, int nb, double shift_rel, double* R, double* Bacc,
-                   int round, const double* Arec, double* Brec, int* flag, int tag,
-                   hipStream_t st) {
-  if (nb > 32) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lz_chol, dim3(1), dim3(256), 0, st, gpart, lz_nblocks(d, 256), nb,
-                     lz_nb_pad(nb), shift_rel, R, Bacc, round, Arec, Brec, flag, tag);
+hipError_t lz_cholqr(const double* gin, int d, int nb, double shift_rel, double* Bacc, int round,
+                     const double* Arec, double* Brec, int* flag, int tag, const double* W,
+                     int64_t ldw, double* dst, int64_t ldd, double* gout, hipStream_t st) {
+  if (gin == gout) return hipErrorInvalidValue;
+  LZ_DISPATCH(nb, {
+    hipLaunchKernelGGL((k_lz_cholqr<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, gin,
+                       lz_nblocks(d, 256), nb, shift_rel, Bacc, round, Arec, Brec, flag, tag, W,
+                       ldw, d, dst, ldd, gout);
+  })
   return hipGetLastError();
 }
 

@@ -244,7 +244,7 @@ size_t lz_gram_part_doubles(int d, int nb);
 // One block Gram-Schmidt pass of W (d x nb) against V (d x n): C = V^T W,
 // W <- W - V C.  The rows of C on the last b columns of V go to Arec
 // (accumulate: added).  With gpart != null the Gram partials of the new W
-// are written for lz_chol.
+// are written for lz_cholqr.
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
                       double* C, double* Arec, int b, int accumulate, double* ppart,
                       double* apart, double* gpart, hipStream_t st);
@@ -252,10 +252,12 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
 // copy), with optional Gram partials of the result.
 hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R, double* dst,
                    int64_t ldd, double* gpart, hipStream_t st);
-// Cholesky of the summed Gram partials (+ shift_rel * trace I); R = L^T;
-// Bacc = R (round 0) or R Bacc; see lanczos.hip for Brec and flag.
-hipError_t lz_chol(const double* gpart, int d, int nb, double shift_rel, double* R, double* Bacc,
-                   int round, const double* Arec, double* Brec, int* flag, int tag,
-                   hipStream_t st);
+// One Cholesky QR round: factor the summed Gram partials gin (+ shift_rel *
+// trace I) as L L^T, dst = W R^{-1} with R = L^T (W and dst may alias), and
+// with gout != null (gout != gin) the Gram partials of dst.  Bacc = R
+// (round 0) or R Bacc; see lanczos.hip for Brec and flag.
+hipError_t lz_cholqr(const double* gin, int d, int nb, double shift_rel, double* Bacc, int round,
+                     const double* Arec, double* Brec, int* flag, int tag, const double* W,
+                     int64_t ldw, double* dst, int64_t ldd, double* gout, hipStream_t st);
 
 }  // namespace refl

@@ -125,8 +125,8 @@ constexpr int MAXB = 32;  // widest block of vectors
 struct LzWork {
   int b = 0, J = 0, nmax = 0;
   double *V = nullptr, *W = nullptr, *C = nullptr;
-  double *ppart = nullptr, *apart = nullptr, *gpart = nullptr;
-  double *R = nullptr, *Bacc = nullptr, *TA = nullptr, *TB = nullptr;
+  double *ppart = nullptr, *apart = nullptr, *gp[2] = {nullptr, nullptr};  // Gram partials, by round parity
+  double *Bacc = nullptr, *TA = nullptr, *TB = nullptr;
   int* flag = nullptr;
 };
 
@@ -628,8 +628,8 @@ void carve_lanczos(Carve& c, LzWork& z, int64_t d, int dp, int k, int steps) {
   z.C = c.take<double>((size_t)z.nmax * z.b);
   z.ppart = c.take<double>(lz_proj_part_doubles((int)d, z.nmax, z.b));
   z.apart = c.take<double>(lz_apply_part_doubles((int)d, z.nmax, z.b));
-  z.gpart = c.take<double>(lz_gram_part_doubles((int)d, z.b));
-  z.R = c.take<double>((size_t)z.b * z.b);
+  z.gp[0] = c.take<double>(lz_gram_part_doubles((int)d, z.b));
+  z.gp[1] = c.take<double>(lz_gram_part_doubles((int)d, z.b));
   z.Bacc = c.take<double>((size_t)z.b * z.b);
   z.TA = c.take<double>((size_t)z.J * z.b * z.b);
   z.TB = c.take<double>((size_t)z.J * z.b * z.b);
@@ -767,15 +767,19 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   const double shift_rel = 11.0 * ((double)d * b + (double)b * (b + 1)) * 2.220446049250313e-16;
   HIPCHK(hipMemsetAsync(z.flag, 0, 2 * sizeof(int), st));
   // Q_1: the start block, orthonormalised by shifted CholQR3.
-  auto cholqr3 = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
-    HIPCHK(lz_rows(z.W, ld, b, (int)d, nullptr, z.W, ld, z.gpart, st));
-    for (int round = 0; round < 3; ++round) {
-      HIPCHK(lz_chol(z.gpart, (int)d, b, round == 0 ? shift_rel : 0.0, z.R, z.Bacc, round,
-                     round == 2 ? Arec : nullptr, round == 2 ? Brec : nullptr, z.flag, tag, st));
-      HIPCHK(lz_rows(z.W, ld, b, (int)d, z.R, round == 2 ? dst : z.W, ld,
-                     round == 2 ? nullptr : z.gpart, st));
-    }
+  // Rounds of CholQR3 on z.W, whose Gram partials are in gp[0]; the last
+  // round writes Q to dst.
+  auto cholqr3_rounds = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
+    for (int round = 0; round < 3; ++round)
+      HIPCHK(lz_cholqr(z.gp[round & 1], (int)d, b, round == 0 ? shift_rel : 0.0, z.Bacc, round,
+                       round == 2 ? Arec : nullptr, round == 2 ? Brec : nullptr, z.flag, tag, z.W,
+                       ld, round == 2 ? dst : z.W, ld, round == 2 ? nullptr : z.gp[(round + 1) & 1],
+                       st));
     return REFL_OK;
+  };
+  auto cholqr3 = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
+    HIPCHK(lz_rows(z.W, ld, b, (int)d, nullptr, z.W, ld, z.gp[0], st));
+    return cholqr3_rounds(dst, Arec, Brec, tag);
   };
   HIPCHK(random_block(z.W, ld, (int)d, b, seed, st));
   refl_status_t rs = cholqr3(z.V, nullptr, nullptr, 0);
@@ -849,17 +853,13 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     double* Bj = z.TB + (size_t)(j - 1) * blk;
     HIPCHK(symthin_f64(Hf, ld, (int)d, Qj, ld, b, z.W, ld, thin, st));
     HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, z.apart, nullptr, st));
-    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.apart, z.gpart, st));
+    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.apart, z.gp[0], st));
     if ((int64_t)n >= d) {
       HIPCHK(hipMemsetAsync(Bj, 0, sizeof(double) * blk, st));  // the basis spans R^d
     } else {
-      // The Gram partials of W are already in gpart: rounds of CholQR3.
-      for (int round = 0; round < 3; ++round) {
-        HIPCHK(lz_chol(z.gpart, (int)d, b, round == 0 ? shift_rel : 0.0, z.R, z.Bacc, round,
-                       round == 2 ? Aj : nullptr, round == 2 ? Bj : nullptr, z.flag, j, st));
-        HIPCHK(lz_rows(z.W, ld, b, (int)d, z.R, round == 2 ? z.V + (int64_t)n * ld : z.W, ld,
-                       round == 2 ? nullptr : z.gpart, st));
-      }
+      // The Gram partials of W are already in gp[0]: rounds of CholQR3.
+      refl_status_t rq = cholqr3_rounds(z.V + (int64_t)n * ld, Aj, Bj, j);
+      if (rq != REFL_OK) return rq;
     }
     const bool test = (j >= j0 && (j - j0) % ci == 0) || j == J;
     if (!test) continue;

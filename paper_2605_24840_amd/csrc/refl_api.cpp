@@ -648,8 +648,16 @@ struct RitzCheck {
   double th_k = NaN, th_k1 = NaN, res_k = NaN, res_k1 = NaN, th_min = NaN, th_max = NaN;
 };
 
+// Ritz values theta_k, theta_{k+1} of the block tridiagonal T_j (and, with
+// `extremes`, the smallest and largest) with their residual radii.  With
+// `prev` (the check of an earlier step of the same run) the bisection for
+// theta_k and theta_{k+1} starts from a bracket near the earlier values:
+// T_i is a leading principal submatrix of T_j, so by interlacing each of
+// these Ritz values can only have moved down; the bracket is confirmed by
+// two inertia counts and widened until it holds, so the result does not
+// depend on the guess.
 void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
-                RitzCheck& out) {
+                RitzCheck& out, const RitzCheck* prev = nullptr) {
   const int n = j * b;
   std::vector<double> Lb((size_t)n * (b + 1), 0.0);  // lower band of T_j
   for (int i = 0; i < n; ++i) {
@@ -737,9 +745,31 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
     }
     res = std::sqrt(r1 + r2);
   };
-  auto ritz = [&](int m, double& theta, double& res) {
+  // A bracket [lo, hi] of the m-th eigenvalue near an earlier Ritz value
+  // t0 with residual radius r0, confirmed by counts (false if none found
+  // before the Gershgorin bounds).
+  auto warm = [&](int m, double t0, double r0, Bracket& out_b) {
+    if (!std::isfinite(t0) || !std::isfinite(r0)) return false;
+    double dlo = std::max(4.0 * r0, 1e-6 * scale), dhi = 1e-9 * scale;
+    for (int tries = 0; tries < 60; ++tries) {
+      const double lo = std::max(t0 - dlo, glo - 1e-12 * scale);
+      const double hi = std::min(t0 + dhi, ghi + 1e-12 * scale);
+      const bool lo_ok = lo <= glo - 1e-12 * scale || count(lo) <= m;
+      const bool hi_ok = hi >= ghi + 1e-12 * scale || count(hi) > m;
+      if (lo_ok && hi_ok) {
+        out_b = Bracket{lo, hi};
+        return true;
+      }
+      if (!lo_ok) dlo *= 8.0;
+      if (!hi_ok) dhi = std::max(8.0 * dhi, 1e-6 * scale);
+      if (lo <= glo - 1e-12 * scale && hi >= ghi + 1e-12 * scale) break;
+    }
+    return false;
+  };
+  auto ritz = [&](int m, double& theta, double& res, double t0 = NaN, double r0 = NaN) {
     double width = 1e-6 * scale;
-    Bracket b = bracket(m, width, nullptr);
+    Bracket w0;
+    Bracket b = warm(m, t0, r0, w0) ? bracket(m, width, &w0) : bracket(m, width, nullptr);
     while (true) {
       pair(0.5 * (b.lo + b.hi), theta, res);
       const double slack = b.hi - b.lo;
@@ -748,8 +778,13 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
       b = bracket(m, width, &b);
     }
   };
-  ritz(k - 1, out.th_k, out.res_k);
-  ritz(k, out.th_k1, out.res_k1);
+  if (prev) {
+    ritz(k - 1, out.th_k, out.res_k, prev->th_k, prev->res_k);
+    ritz(k, out.th_k1, out.res_k1, prev->th_k1, prev->res_k1);
+  } else {
+    ritz(k - 1, out.th_k, out.res_k);
+    ritz(k, out.th_k1, out.res_k1);
+  }
   if (extremes) {
     double unused;
     ritz(0, out.th_min, unused);
@@ -806,7 +841,10 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   double* hTB = h->lz_pin + J * blk;
   int* hflag = reinterpret_cast<int*>(h->lz_pin + 2 * J * blk);
   // Evaluates the test made after step j (its copies in slot `slot`); sets
-  // done when the run is finished (r filled).
+  // done when the run is finished (r filled).  Each test starts its
+  // bisections from the previous test's Ritz values.
+  RitzCheck prev_rc;
+  bool have_prev = false;
   auto evaluate = [&](int j, int slot, int& done) -> refl_status_t {
     done = 0;
     HIPCHK(hipEventSynchronize(h->lz_ev[slot]));
@@ -826,11 +864,14 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
       return REFL_OK;
     }
     RitzCheck rc;
-    ritz_check(jj, b, k, hTA, hTB, false, rc);
+    ritz_check(jj, b, k, hTA, hTB, false, rc, have_prev ? &prev_rc : nullptr);
+    prev_rc = rc;
+    have_prev = true;
     const double eps = std::max(rc.res_k, rc.res_k1);
     const bool conv = eps < 0.25 * (rc.th_k1 - rc.th_k);
     if (conv || stop) {
-      ritz_check(jj, b, k, hTA, hTB, true, rc);
+      RitzCheck last = rc;
+      ritz_check(jj, b, k, hTA, hTB, true, rc, &last);
       r.lam_k = rc.th_k;
       r.lam_k1 = rc.th_k1;
       r.eps = eps;

@@ -1,6 +1,8 @@
 // Small dense host-side linear algebra used by the driver.
 #pragma once
 
+#include <cmath>
+
 namespace refl {
 
 // Eigen-decomposition of a symmetric n x n matrix (row-major A_in): w
@@ -35,5 +37,19 @@ int band_count_below(int n, int bw, const double* Lb, double x, double* work);
 // Unit vector y (length n) from `iters` steps of inverse iteration with
 // T - sigma I; returns ||T y - sigma y||_2.
 double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters, double* y);
+
+// Ritz test of a block Lanczos run.  TA and TB hold the blocks A_i
+// (symmetric) and B_i (upper triangular) of the block tridiagonal T_j,
+// b x b column-major, i < j.  Fills theta_k, theta_{k+1} (1-based k) and
+// their residual radii ||H x - theta x|| (from the Ritz vector of T_j and
+// the last block B_j), and with `extremes` the smallest and largest Ritz
+// values.  With `prev` (the check of an earlier step of the same run) the
+// bisections start from brackets near the earlier values (the result does
+// not depend on them: every bracket is confirmed by inertia counts).
+struct RitzCheck {
+  double th_k = NAN, th_k1 = NAN, res_k = NAN, res_k1 = NAN, th_min = NAN, th_max = NAN;
+};
+void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
+                RitzCheck& out, const RitzCheck* prev = nullptr);
 
 }  // namespace refl

@@ -642,156 +642,6 @@ struct LzResult {
   bool converged = false;
 };
 
-// Ritz values and residual radii of the first j steps.  TA/TB hold the
-// blocks A_i (symmetric) and B_i (upper triangular), b x b column-major.
-struct RitzCheck {
-  double th_k = NaN, th_k1 = NaN, res_k = NaN, res_k1 = NaN, th_min = NaN, th_max = NaN;
-};
-
-// Ritz values theta_k, theta_{k+1} of the block tridiagonal T_j (and, with
-// `extremes`, the smallest and largest) with their residual radii.  With
-// `prev` (the check of an earlier step of the same run) the bisection for
-// theta_k and theta_{k+1} starts from a bracket near the earlier values:
-// T_i is a leading principal submatrix of T_j, so by interlacing each of
-// these Ritz values can only have moved down; the bracket is confirmed by
-// two inertia counts and widened until it holds, so the result does not
-// depend on the guess.
-void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
-                RitzCheck& out, const RitzCheck* prev = nullptr) {
-  const int n = j * b;
-  std::vector<double> Lb((size_t)n * (b + 1), 0.0);  // lower band of T_j
-  for (int i = 0; i < n; ++i) {
-    const int I = i / b, r = i % b;
-    const double* A = TA + (size_t)I * b * b;
-    for (int c = 0; c <= r; ++c) Lb[(size_t)i * (b + 1) + (r - c)] = 0.5 * (A[r + c * b] + A[c + r * b]);
-    if (I > 0) {
-      const double* B = TB + (size_t)(I - 1) * b * b;  // T[I b + r][(I-1) b + c] = B[r][c], r <= c
-      for (int c = r; c < b; ++c) Lb[(size_t)i * (b + 1) + (b + r - c)] = B[r + c * b];
-    }
-  }
-  // Gershgorin bounds.
-  double glo = INFINITY, ghi = -INFINITY;
-  {
-    std::vector<double> rad(n, 0.0);
-    for (int i = 0; i < n; ++i)
-      for (int t = 1; t <= b && t <= i; ++t) {
-        const double v = std::fabs(Lb[(size_t)i * (b + 1) + t]);
-        rad[i] += v;
-        rad[i - t] += v;
-      }
-    for (int i = 0; i < n; ++i) {
-      glo = std::min(glo, Lb[(size_t)i * (b + 1)] - rad[i]);
-      ghi = std::max(ghi, Lb[(size_t)i * (b + 1)] + rad[i]);
-    }
-  }
-  const double scale = std::max({std::fabs(glo), std::fabs(ghi), 1e-300});
-  std::vector<double> work((size_t)n * (b + 1)), diag, sub;
-  bool reduced = false;
-  // Bracket the m-th smallest eigenvalue (0-based) to width 1e-9 * scale by
-  // bisection on the inertia of T - xI; if the factorisation declines, use
-  // the band-to-tridiagonal reduction and its Sturm count instead.
-  auto count = [&](double x) {
-    if (!reduced) {
-      const int c = band_count_below(n, b, Lb.data(), x, work.data());
-      if (c >= 0) return c;
-      diag.resize(n);
-      sub.resize(std::max(n - 1, 1));
-      band_tridiag(n, b, Lb.data(), diag.data(), sub.data());
-      reduced = true;
-    }
-    return tridiag_count_below(n, diag.data(), sub.data(), x);
-  };
-  // Bisection to `width`, then (in pair) inverse iteration from the
-  // midpoint; if the Rayleigh quotient leaves the bracket (a neighbour was
-  // closer to the midpoint) the bracket is narrowed further and the
-  // iteration repeated.
-  struct Bracket {
-    double lo, hi;
-  };
-  auto bracket = [&](int m, double width, Bracket* b0) {
-    Bracket b = b0 ? *b0 : Bracket{glo - 1e-12 * scale, ghi + 1e-12 * scale};
-    while (b.hi - b.lo > width) {
-      const double mid = 0.5 * (b.lo + b.hi);
-      if (mid <= b.lo || mid >= b.hi) break;
-      if (count(mid) > m) b.hi = mid; else b.lo = mid;
-    }
-    return b;
-  };
-  // Residual radius of the Ritz pair near sigma: inverse iteration gives the
-  // vector y of T, theta its Rayleigh quotient, and
-  // ||H x - theta x||^2 = ||(T - theta) y||^2 + ||B_j y(last block)||^2.
-  std::vector<double> y(n), ty(n);
-  const double* Bj = TB + (size_t)(j - 1) * b * b;
-  auto pair = [&](double sigma, double& theta, double& res) {
-    band_inverse_iteration(n, b, Lb.data(), sigma, 3, y.data());
-    double q = 0.0;
-    for (int i = 0; i < n; ++i) {
-      double s = 0.0;
-      for (int t = 0; t <= b; ++t) {
-        if (i - t >= 0) s += Lb[(size_t)i * (b + 1) + t] * y[i - t];
-        if (t > 0 && i + t < n) s += Lb[(size_t)(i + t) * (b + 1) + t] * y[i + t];
-      }
-      ty[i] = s;
-      q += s * y[i];
-    }
-    theta = q;
-    double r1 = 0.0;
-    for (int i = 0; i < n; ++i) r1 += (ty[i] - q * y[i]) * (ty[i] - q * y[i]);
-    double r2 = 0.0;
-    for (int r = 0; r < b; ++r) {
-      double s = 0.0;
-      for (int c = r; c < b; ++c) s += Bj[r + c * b] * y[n - b + c];
-      r2 += s * s;
-    }
-    res = std::sqrt(r1 + r2);
-  };
-  // A bracket [lo, hi] of the m-th eigenvalue near an earlier Ritz value
-  // t0 with residual radius r0, confirmed by counts (false if none found
-  // before the Gershgorin bounds).
-  auto warm = [&](int m, double t0, double r0, Bracket& out_b) {
-    if (!std::isfinite(t0) || !std::isfinite(r0)) return false;
-    double dlo = std::max(4.0 * r0, 1e-6 * scale), dhi = 1e-9 * scale;
-    for (int tries = 0; tries < 60; ++tries) {
-      const double lo = std::max(t0 - dlo, glo - 1e-12 * scale);
-      const double hi = std::min(t0 + dhi, ghi + 1e-12 * scale);
-      const bool lo_ok = lo <= glo - 1e-12 * scale || count(lo) <= m;
-      const bool hi_ok = hi >= ghi + 1e-12 * scale || count(hi) > m;
-      if (lo_ok && hi_ok) {
-        out_b = Bracket{lo, hi};
-        return true;
-      }
-      if (!lo_ok) dlo *= 8.0;
-      if (!hi_ok) dhi = std::max(8.0 * dhi, 1e-6 * scale);
-      if (lo <= glo - 1e-12 * scale && hi >= ghi + 1e-12 * scale) break;
-    }
-    return false;
-  };
-  auto ritz = [&](int m, double& theta, double& res, double t0 = NaN, double r0 = NaN) {
-    double width = 1e-6 * scale;
-    Bracket w0;
-    Bracket b = warm(m, t0, r0, w0) ? bracket(m, width, &w0) : bracket(m, width, nullptr);
-    while (true) {
-      pair(0.5 * (b.lo + b.hi), theta, res);
-      const double slack = b.hi - b.lo;
-      if ((theta >= b.lo - slack && theta <= b.hi + slack) || width < 1e-14 * scale) return;
-      width *= 1e-3;
-      b = bracket(m, width, &b);
-    }
-  };
-  if (prev) {
-    ritz(k - 1, out.th_k, out.res_k, prev->th_k, prev->res_k);
-    ritz(k, out.th_k1, out.res_k1, prev->th_k1, prev->res_k1);
-  } else {
-    ritz(k - 1, out.th_k, out.res_k);
-    ritz(k, out.th_k1, out.res_k1);
-  }
-  if (extremes) {
-    double unused;
-    ritz(0, out.th_min, unused);
-    ritz(n - 1, out.th_max, unused);
-  }
-}
-
 // Runs the estimate on the padded symmetric copy Hf (ld dp).  Returns
 // REFL_OK with r filled (converged or at the step cap), or a device error.
 refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, int k, uint64_t seed,

@@ -22,6 +22,12 @@ int t_count(int n, const double* d, const double* e, double x) { return refl::tr
 double t_invit(int n, int bw, const double* Lb, double s, int it, double* y) { return refl::band_inverse_iteration(n, bw, Lb, s, it, y); }
 int t_eig(int n, const double* A, double* w, double* Q) { return refl::sym_eig_small(n, A, w, Q); }
 int t_bcount(int n, int bw, const double* Lb, double x, double* work) { return refl::band_count_below(n, bw, Lb, x, work); }
+void t_ritz(int j, int b, int k, const double* TA, const double* TB, int extremes, double* out, const double* prev) {
+  refl::RitzCheck rc, pv;
+  if (prev) { pv.th_k = prev[0]; pv.th_k1 = prev[1]; pv.res_k = prev[2]; pv.res_k1 = prev[3]; }
+  refl::ritz_check(j, b, k, TA, TB, extremes != 0, rc, prev ? &pv : nullptr);
+  out[0] = rc.th_k; out[1] = rc.th_k1; out[2] = rc.res_k; out[3] = rc.res_k1; out[4] = rc.th_min; out[5] = rc.th_max;
+}
 }
 """
 
@@ -43,6 +49,7 @@ def lib(tmp_path_factory):
     L.t_invit.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P]
     L.t_invit.restype = ctypes.c_double
     L.t_eig.argtypes = [ctypes.c_int, P, P, P]
+    L.t_ritz.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, P]
     return L
 
 
@@ -146,3 +153,74 @@ def test_band_inertia_count(lib):
             ok += c >= 0
             tot += 1
     assert ok >= 0.9 * tot     # growth (a declined count) is rare on random band matrices
+
+
+def _lanczos_blocks(b, J, seed):
+    """Blocks of a block tridiagonal T: A_i symmetric, B_i upper triangular
+    with a positive diagonal (column-major b x b, as the Lanczos run stores
+    them), from a diagonal matrix with a cluster and a gap so that the Ritz
+    values near the gap converge within J steps."""
+    rng = np.random.default_rng(seed)
+    TA = np.zeros((J, b, b))
+    TB = np.zeros((J, b, b))
+    for i in range(J):
+        A = 0.05 * rng.standard_normal((b, b))
+        TA[i] = A + A.T + np.diag(np.sin(0.7 * i + np.arange(b)) * 4.0)
+        B = np.triu(0.02 * rng.standard_normal((b, b)))
+        B[np.diag_indices(b)] = 0.05 + 0.01 * rng.random(b)
+        TB[i] = B
+    # Column-major storage: element (r, c) at r + c b.
+    return (np.ascontiguousarray(TA.transpose(0, 2, 1)), np.ascontiguousarray(TB.transpose(0, 2, 1)))
+
+
+def _dense_T(TA, TB, j, b):
+    n = j * b
+    T = np.zeros((n, n))
+    for i in range(j):
+        T[i * b:(i + 1) * b, i * b:(i + 1) * b] = TA[i].T
+        if i > 0:
+            B = TB[i - 1].T          # B_{i-1}[r, c], r <= c
+            T[i * b:(i + 1) * b, (i - 1) * b:i * b] = B
+            T[(i - 1) * b:i * b, i * b:(i + 1) * b] = B.T
+    return T
+
+
+def test_ritz_check_against_lapack(lib):
+    """Ritz values of T_j against LAPACK, and the residual radius: for the
+    unit Ritz vector y of T_j, ||H x - theta x|| = ||B_j y_last|| (the coupling
+    to the next block) -- computed here from the dense T_{j+1}."""
+    b, J, k = 4, 14, 3
+    TA, TB = _lanczos_blocks(b, J + 1, 3)
+    out = np.zeros(6)
+    for j in (1, 2, 5, 9, 14):
+        lib.t_ritz(j, b, k, ptr(TA), ptr(TB), 1, ptr(out), None)
+        T = _dense_T(TA, TB, j, b)
+        w, Y = np.linalg.eigh(T)
+        scale = np.abs(w).max()
+        assert abs(out[0] - w[k - 1]) <= 1e-9 * scale and abs(out[1] - w[k]) <= 1e-9 * scale
+        assert abs(out[4] - w[0]) <= 1e-9 * scale and abs(out[5] - w[-1]) <= 1e-9 * scale
+        Bj = TB[j - 1].T
+        for col, r in ((k - 1, out[2]), (k, out[3])):
+            want = np.linalg.norm(Bj @ Y[-b:, col])
+            # ||(T_j - theta) y|| adds rounding of order 1e-15 scale to the radius.
+            assert abs(r - want) <= 1e-7 * want + 1e-13 * scale, (j, col, r, want)
+
+
+def test_ritz_check_warm_start_matches_cold(lib):
+    """Chained checks that start from the previous check's values give the
+    same Ritz values as checks from the Gershgorin bounds, also when the
+    guess is wrong (a deliberately displaced previous value)."""
+    b, J, k = 5, 30, 4
+    TA, TB = _lanczos_blocks(b, J + 1, 8)
+    cold, warm = np.zeros(6), np.zeros(6)
+    prev = None
+    for j in range(1, J + 1, 3):
+        lib.t_ritz(j, b, k, ptr(TA), ptr(TB), 0, ptr(cold), None)
+        lib.t_ritz(j, b, k, ptr(TA), ptr(TB), 0, ptr(warm), None if prev is None else ptr(prev))
+        scale = np.abs(np.linalg.eigvalsh(_dense_T(TA, TB, j, b))).max()
+        assert abs(cold[0] - warm[0]) <= 1e-9 * scale and abs(cold[1] - warm[1]) <= 1e-9 * scale
+        prev = np.array(warm[:4])
+    bad = np.array([warm[0] + 3.0, warm[1] - 2.0, 1e-14, 1e-14])
+    lib.t_ritz(J, b, k, ptr(TA), ptr(TB), 0, ptr(warm), ptr(bad))
+    lib.t_ritz(J, b, k, ptr(TA), ptr(TB), 0, ptr(cold), None)
+    assert abs(cold[0] - warm[0]) <= 1e-9 * scale and abs(cold[1] - warm[1]) <= 1e-9 * scale

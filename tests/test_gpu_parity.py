@@ -352,6 +352,31 @@ def test_mixed_wide_target_blocks(R, handle, k, cg_prec):
     assert err <= target and err <= info["dk_bound"] * 1.0001 + 1e-15
 
 
+def test_mixed_inner_iteration_cap(R, handle):
+    """The inner CG stops at cg_max_iter (the count reported is the cap);
+    with a cap too small for one sweep the certified bound is missed and the
+    call says so; with a small cap and more sweeps it still reaches the
+    target."""
+    d, k = 512, 4
+    H, lam, Q = inputs.planted_hessian(d, k, 0.1, 2)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Hg = _gpu(H)
+    for cap in (1, 3):
+        _, info, st = R.sign(Hg, k, s, handle=handle, precision="mixed", tol=1e-14, check=False,
+                             polish_sweeps=1, cg_max_iter=cap)
+        _say(f"cap {cap}: status={R.STATUS[st]} sweeps={info['polish_sweeps']} cg={info['cg_iters']} "
+             f"dk={info['dk_bound']:.2e}")
+        assert R.STATUS[st] == "REFL_ERR_NOT_CONVERGED"
+        assert info["polish_sweeps"] == 1 and info["cg_iters"] == cap
+    target = 1e-8 * np.sqrt(d)
+    Rg, info, st = R.sign(Hg, k, s, handle=handle, precision="mixed", tol=target, polish_sweeps=10,
+                          cg_max_iter=20)
+    err = np.linalg.norm(Rg.cpu().numpy() - oracle.reflector_from_eig(Q, k))
+    _say(f"cap 20, up to 10 sweeps: status={R.STATUS[st]} sweeps={info['polish_sweeps']} cg={info['cg_iters']} "
+         f"err={err:.2e}")
+    assert st == 0 and err <= target and info["cg_iters"] <= 20 * info["polish_sweeps"]
+
+
 @pytest.mark.parametrize("k", [1, 3, 5])
 def test_mixed_allen_cahn_d4096(R, handle, k):
     _say(f"mixed Allen-Cahn d=4096 k={k}")

@@ -308,8 +308,15 @@ refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double *dH, int64
  * A returned shift is certified admissible (REFL_OK) when its margin (in
  * info) is positive; otherwise the status is REFL_ERR_NOT_ADMISSIBLE (or
  * REFL_ERR_NO_GAP from the estimate) and the policy keeps no state from the
- * call.  The policy owns a d x d FP64 device copy (REUSE only) and is tied to
- * the handle's device; calls on one policy are not thread-safe. */
+ * call.  The policy owns a d x d FP64 device copy (REUSE only), with
+ * warm_start a d x b block (b = min(k + 4, 32, d)), and is tied to the
+ * handle's device; calls on one policy are not thread-safe.
+ *
+ * Warm start: on a slowly varying sequence the previous refresh's Ritz
+ * vectors span the wanted eigenvectors of the current H to about the drift
+ * over the gap, so the run needs few steps.  The estimate and its
+ * certificate do not depend on the start block (a failed warm run is
+ * repeated from the seeded block). */
 typedef enum {
   REFL_POLICY_MIDPOINT = 0,
   REFL_POLICY_DAMPED = 1,
@@ -326,6 +333,9 @@ typedef struct {
   double tau;             /* REUSE: 0 <= tau < 1 */
   int32_t lanczos_steps;  /* cap on block Lanczos steps per refresh (0 = automatic) */
   uint64_t seed;          /* Lanczos start block */
+  int32_t warm_start;     /* 1: each refresh after the first starts block Lanczos from the
+                             Ritz vectors of the b smallest Ritz values of the previous
+                             refresh (same d); 0: from the seeded block every time */
 } refl_policy_params_t;
 
 typedef struct {

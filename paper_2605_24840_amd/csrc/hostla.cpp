@@ -283,7 +283,7 @@ int band_count_below(int n, int bw, const double* Lb, double x, double* work) {
 }
 
 double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters,
-                              double* y) {
+                              double* y, const double* Q, int nq, bool use_start) {
   // LU with partial pivoting of B = T - sigma I (band, half-bandwidth bw).
   // Row i is held for columns i - bw .. i + 2 bw at U[i * uw + (c - i + bw)].
   const int uw = 3 * bw + 1;
@@ -324,8 +324,21 @@ double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int
         for (int c = j + 1; c <= cend; ++c) u(i, c) -= m * u(j, c);
     }
   }
-  // Start vector: a fixed, non-special sequence.
-  for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * std::sin(1.0 + 0.7 * i);
+  // Start vector: the caller's, or a fixed, non-special sequence.
+  if (!use_start)
+    for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * std::sin(1.0 + 0.7 * i);
+  // Components along the columns of Q (n x nq, orthonormal) are removed
+  // after every solve (two passes of modified Gram-Schmidt).
+  auto deflate = [&]() {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q < nq; ++q) {
+        const double* qc = Q + (size_t)q * n;
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += qc[i] * y[i];
+        for (int i = 0; i < n; ++i) y[i] -= c * qc[i];
+      }
+  };
+  deflate();
   for (int it = 0; it < iters; ++it) {
     // Forward: apply the row swaps and unit-lower multipliers in order.
     for (int j = 0; j < n; ++j) {
@@ -339,6 +352,7 @@ double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int
       for (int c = i + 1; c <= cend; ++c) s -= u(i, c) * y[c];
       y[i] = s / u(i, i);
     }
+    deflate();
     double nrm = 0.0;
     for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
     nrm = std::sqrt(nrm);
@@ -357,18 +371,11 @@ double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int
 // ------------------------------------------------ Ritz test of block Lanczos
 
 
-// Ritz values theta_k, theta_{k+1} of the block tridiagonal T_j (and, with
-// `extremes`, the smallest and largest) with their residual radii.  With
-// `prev` (the check of an earlier step of the same run) the bisection for
-// theta_k and theta_{k+1} starts from a bracket near the earlier values:
-// T_i is a leading principal submatrix of T_j, so by interlacing each of
-// these Ritz values can only have moved down; the bracket is confirmed by
-// two inertia counts and widened until it holds, so the result does not
-// depend on the guess.
-void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
-                RitzCheck& out, const RitzCheck* prev) {
+// Lower band (half-bandwidth b) of the block tridiagonal T_j with diagonal
+// blocks A_i (symmetrised) and sub-diagonal blocks B_i (upper triangular).
+static std::vector<double> lower_band_of(int j, int b, const double* TA, const double* TB) {
   const int n = j * b;
-  std::vector<double> Lb((size_t)n * (b + 1), 0.0);  // lower band of T_j
+  std::vector<double> Lb((size_t)n * (b + 1), 0.0);
   for (int i = 0; i < n; ++i) {
     const int I = i / b, r = i % b;
     const double* A = TA + (size_t)I * b * b;
@@ -378,6 +385,22 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
       for (int c = r; c < b; ++c) Lb[(size_t)i * (b + 1) + (b + r - c)] = B[r + c * b];
     }
   }
+  return Lb;
+}
+
+// Ritz pairs of the block tridiagonal T_j for the eigenvalue indices ms[q]
+// (0-based, q < nm): theta[q], the residual radius res[q], and with Y != null
+// the unit Ritz vector of T_j in column q of Y (n x nm, column-major).  With
+// t0/r0 (an earlier step's Ritz values and radii for the same indices; NaN
+// for none) the bisection starts from a bracket near the earlier value: T_i
+// is a leading principal submatrix of T_j, so by interlacing each Ritz value
+// can only have moved down; the bracket is confirmed by two inertia counts
+// and widened until it holds, so the result does not depend on the guess.
+static void ritz_pairs(int j, int b, const double* TA, const double* TB, int nm, const int* ms,
+                       const double* t0, const double* r0, double* theta_out, double* res_out,
+                       double* Y) {
+  const int n = j * b;
+  const std::vector<double> Lb = lower_band_of(j, b, TA, TB);
   // Gershgorin bounds.
   double glo = INFINITY, ghi = -INFINITY;
   {
@@ -487,18 +510,72 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
       b = bracket(m, width, &b);
     }
   };
+  for (int q = 0; q < nm; ++q) {
+    ritz(ms[q], theta_out[q], res_out[q], t0 ? t0[q] : NAN, r0 ? r0[q] : NAN);
+    if (Y) std::copy(y.begin(), y.end(), Y + (size_t)q * n);
+  }
+}
+
+// Ritz values theta_k, theta_{k+1} of T_j (and, with `extremes`, the
+// smallest and largest) with their residual radii; `prev` warm-starts the
+// bisections for theta_k and theta_{k+1}.
+void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
+                RitzCheck& out, const RitzCheck* prev) {
+  const int ms[2] = {k - 1, k};
+  double th[2], rs[2];
   if (prev) {
-    ritz(k - 1, out.th_k, out.res_k, prev->th_k, prev->res_k);
-    ritz(k, out.th_k1, out.res_k1, prev->th_k1, prev->res_k1);
+    const double t0[2] = {prev->th_k, prev->th_k1}, r0[2] = {prev->res_k, prev->res_k1};
+    ritz_pairs(j, b, TA, TB, 2, ms, t0, r0, th, rs, nullptr);
   } else {
-    ritz(k - 1, out.th_k, out.res_k);
-    ritz(k, out.th_k1, out.res_k1);
+    ritz_pairs(j, b, TA, TB, 2, ms, nullptr, nullptr, th, rs, nullptr);
   }
+  out.th_k = th[0];
+  out.th_k1 = th[1];
+  out.res_k = rs[0];
+  out.res_k1 = rs[1];
   if (extremes) {
-    double unused;
-    ritz(0, out.th_min, unused);
-    ritz(n - 1, out.th_max, unused);
+    const int me[2] = {0, j * b - 1};
+    ritz_pairs(j, b, TA, TB, 2, me, nullptr, nullptr, th, rs, nullptr);
+    out.th_min = th[0];
+    out.th_max = th[1];
   }
+}
+
+int ritz_vectors(int j, int b, const double* TA, const double* TB, int nvec, double* Y) {
+  const int n = j * b;
+  if (nvec < 1 || nvec > n) return -1;
+  std::vector<int> ms(nvec);
+  std::vector<double> th(nvec), rs(nvec);
+  for (int q = 0; q < nvec; ++q) ms[q] = q;
+  ritz_pairs(j, b, TA, TB, nvec, ms.data(), nullptr, nullptr, th.data(), rs.data(), Y);
+  // Inverse iteration on close or repeated eigenvalues can return nearly
+  // parallel vectors: each column is orthogonalised against the earlier ones
+  // (modified Gram-Schmidt, twice); one that loses its norm is recomputed by
+  // inverse iteration at its Ritz value with the earlier columns deflated,
+  // from other start vectors until one survives.
+  std::vector<double> Lb;
+  for (int q = 0; q < nvec; ++q) {
+    double* yq = Y + (size_t)q * n;
+    for (int attempt = 0; attempt <= 8; ++attempt) {
+      const double n0 = std::sqrt(std::inner_product(yq, yq + n, yq, 0.0));
+      for (int pass = 0; pass < 2; ++pass)
+        for (int p = 0; p < q; ++p) {
+          const double* yp = Y + (size_t)p * n;
+          const double c = std::inner_product(yp, yp + n, yq, 0.0);
+          for (int i = 0; i < n; ++i) yq[i] -= c * yp[i];
+        }
+      const double n1 = std::sqrt(std::inner_product(yq, yq + n, yq, 0.0));
+      if (n1 > 1e-8 * std::max(n0, 1e-300)) {
+        for (int i = 0; i < n; ++i) yq[i] /= n1;
+        break;
+      }
+      if (attempt == 8) return -1;
+      if (Lb.empty()) Lb = lower_band_of(j, b, TA, TB);
+      for (int i = 0; i < n; ++i) yq[i] = std::sin(1.0 + (2.3 + attempt) * i + 0.37 * attempt);
+      band_inverse_iteration(n, b, Lb.data(), th[q], 3, yq, Y, q, true);
+    }
+  }
+  return 0;
 }
 
 }  // namespace refl

@@ -35,8 +35,11 @@ double tridiag_eigval(int n, const double* diag, const double* sub, int m);
 int band_count_below(int n, int bw, const double* Lb, double x, double* work);
 
 // Unit vector y (length n) from `iters` steps of inverse iteration with
-// T - sigma I; returns ||T y - sigma y||_2.
-double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters, double* y);
+// T - sigma I; returns ||T y - sigma y||_2.  The start vector is y itself
+// when use_start, else a fixed sequence; with nq > 0 the components along
+// the orthonormal columns of Q (n x nq) are removed after every solve.
+double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters, double* y,
+                              const double* Q = nullptr, int nq = 0, bool use_start = false);
 
 // Ritz test of a block Lanczos run.  TA and TB hold the blocks A_i
 // (symmetric) and B_i (upper triangular) of the block tridiagonal T_j,
@@ -51,5 +54,10 @@ struct RitzCheck {
 };
 void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
                 RitzCheck& out, const RitzCheck* prev = nullptr);
+
+// Orthonormal Ritz vectors of T_j (n = j b) for its nvec smallest Ritz
+// values, column-major in Y (n x nvec).  Returns 0, or -1 if nvec is out of
+// range.
+int ritz_vectors(int j, int b, const double* TA, const double* TB, int nvec, double* Y);
 
 }  // namespace refl

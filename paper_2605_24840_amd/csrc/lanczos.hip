@@ -470,6 +470,19 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
   return hipGetLastError();
 }
 
+hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
+                      double* apart, const double* Wzero, double* dst, int64_t ldd,
+                      hipStream_t st) {
+  const int ncc = lz_nblocks(n, LZ_CC);
+  LZ_DISPATCH(nb, {
+    hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 128), ncc), dim3(128), 0, st,
+                       V, ldv, n, Cneg, nb, d, apart);
+    hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, Wzero, ldd, nb,
+                       d, apart, ncc, nullptr, dst, ldd, nullptr);
+  })
+  return hipGetLastError();
+}
+
 hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R, double* dst,
                    int64_t ldd, double* gpart, hipStream_t st) {
   LZ_DISPATCH(nb, {

@@ -248,6 +248,12 @@ size_t lz_gram_part_doubles(int d, int nb);
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
                       double* C, double* Arec, int b, int accumulate, double* ppart,
                       double* apart, double* gpart, hipStream_t st);
+// dst = V Y for the d x n basis V and Y = -Cneg (n x nb, column-major, ld
+// n), computed as Wzero - V Cneg with Wzero an all-zero d x nb block of
+// leading dimension ldd (the projection kernels' update).
+hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
+                      double* apart, const double* Wzero, double* dst, int64_t ldd,
+                      hipStream_t st);
 // dst = W R^{-1} (R upper triangular nb x nb on the device; R == null: a
 // copy), with optional Gram partials of the result.
 hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R, double* dst,

@@ -73,6 +73,8 @@ struct refl_policy_s {
   double* Href = nullptr;       // REUSE: upper triangle of the Hessian of the last refresh (ld dref)
   double* dscr = nullptr;       // device partials + one result slot
   size_t dscr_n = 0;
+  double* Vwarm = nullptr;      // warm_start: Ritz block of the last refresh (d x b, ld dwarm)
+  int64_t dwarm = 0;            // its order (0: none yet)
   int calls = 0, refreshes = 0;
 };
 
@@ -644,8 +646,13 @@ struct LzResult {
 
 // Runs the estimate on the padded symmetric copy Hf (ld dp).  Returns
 // REFL_OK with r filled (converged or at the step cap), or a device error.
+// With `start` (d x b, ld lds) the run starts from that block instead of
+// the seeded one; with `ritz_out` (d x b, ld ldr) it also returns the Ritz
+// vectors of its b smallest Ritz values (the warm start of a later run on a
+// nearby matrix).
 refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, int k, uint64_t seed,
-                          LzWork& z, double* thin, LzResult& r) {
+                          LzWork& z, double* thin, LzResult& r, const double* start = nullptr,
+                          int64_t lds = 0, double* ritz_out = nullptr, int64_t ldr = 0) {
   hipStream_t st = h->stream;
   const int b = z.b, J = z.J;
   const int64_t ld = dp;
@@ -666,7 +673,11 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     HIPCHK(lz_rows(z.W, ld, b, (int)d, nullptr, z.W, ld, z.gp[0], st));
     return cholqr3_rounds(dst, Arec, Brec, tag);
   };
-  HIPCHK(random_block(z.W, ld, (int)d, b, seed, st));
+  if (start)
+    HIPCHK(hipMemcpy2DAsync(z.W, sizeof(double) * ld, start, sizeof(double) * lds,
+                            sizeof(double) * d, b, hipMemcpyDeviceToDevice, st));
+  else
+    HIPCHK(random_block(z.W, ld, (int)d, b, seed, st));
   refl_status_t rs = cholqr3(z.V, nullptr, nullptr, 0);
   if (rs != REFL_OK) return rs;
   const int j0 = std::max(1, (k + 1 + b - 1) / b);
@@ -733,6 +744,25 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     }
     return REFL_OK;
   };
+  // Ritz block of the finished run (r.steps steps): Y from the band matrix on
+  // the host, then ritz_out = V Y on the device.  The copy of -Y is
+  // enqueued behind the steps still in flight, which read z.C; the stream is
+  // synchronised before Y goes out of scope.
+  auto ritz_block = [&]() -> refl_status_t {
+    if (!ritz_out) return REFL_OK;
+    const int n = r.steps * b;
+    std::vector<double> Y((size_t)n * b);
+    if (n < b || ritz_vectors(r.steps, b, hTA, hTB, b, Y.data()) != 0)
+      return fail(h, REFL_ERR_NOT_CONVERGED, "Lanczos: no Ritz block for the warm start");
+    for (double& v : Y) v = -v;
+    HIPCHK(hipMemcpyAsync(z.C, Y.data(), sizeof(double) * Y.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemset2DAsync(z.W, sizeof(double) * ld, 0, sizeof(double) * d, b, st));
+    HIPCHK(lz_combine(z.V, ld, n, z.C, b, (int)d, z.apart, z.W, z.W, ld, st));
+    HIPCHK(hipMemcpy2DAsync(ritz_out, sizeof(double) * ldr, z.W, sizeof(double) * ld,
+                            sizeof(double) * d, b, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return REFL_OK;
+  };
   // The test after step j is evaluated on the host while the device runs
   // the steps up to the next test (steps enqueued past convergence are
   // discarded).
@@ -752,7 +782,8 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
       refl_status_t rq = cholqr3_rounds(z.V + (int64_t)n * ld, Aj, Bj, j);
       if (rq != REFL_OK) return rq;
     }
-    const bool test = (j >= j0 && (j - j0) % ci == 0) || j == J;
+    // A warm start may converge within a few steps: those are all tested.
+    const bool test = (j >= j0 && ((j - j0) % ci == 0 || (start && j - j0 < 4))) || j == J;
     if (!test) continue;
     const int slot = ntest++ & 1;
     const size_t nb_new = (size_t)(j - copied) * blk;
@@ -766,6 +797,7 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     if (pending > 0) {
       int done = 0;
       refl_status_t e = evaluate(pending, pending_slot, done);
+      if (e == REFL_OK && done) e = ritz_block();
       if (e != REFL_OK || done) {
         HIPCHK(hipStreamSynchronize(st));
         return e;
@@ -777,6 +809,7 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   if (pending > 0) {
     int done = 0;
     refl_status_t e = evaluate(pending, pending_slot, done);
+    if (e == REFL_OK && done) e = ritz_block();
     HIPCHK(hipStreamSynchronize(st));
     if (e != REFL_OK || done) return e;
   }
@@ -1961,7 +1994,8 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
 // ------------------------------------------------------------ estimation
 // Block Lanczos on H (refl_estimate_shift and the policy refreshes).
 refl_status_t estimate_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh, int k,
-                            int steps, uint64_t seed, LzResult& lr) {
+                            int steps, uint64_t seed, LzResult& lr, const double* start = nullptr,
+                            double* ritz_out = nullptr) {
   if (!dH || ldh < d) return fail(h, REFL_ERR_INVALID_ARG, "H is NULL or ldh < d");
   refl_params_t p;
   refl_params_default(&p);
@@ -1979,7 +2013,7 @@ refl_status_t estimate_impl(refl_handle_t h, int64_t d, const double* dH, int64_
   if (rs != REFL_OK) return rs;
   layout(w, base, d, p, LAYOUT_ESTIMATE, h);
   HIPCHK(launch_mirror_upper(dH, ldh, (int)d, w.Hf, w.dp, h->stream));
-  return lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr);
+  return lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr, start, d, ritz_out, d);
 }
 
 }  // namespace
@@ -2191,6 +2225,7 @@ refl_status_t refl_policy_destroy(refl_policy_t pol) {
   (void)hipDeviceSynchronize();
   if (pol->Href) (void)hipFree(pol->Href);
   if (pol->dscr) (void)hipFree(pol->dscr);
+  if (pol->Vwarm) (void)hipFree(pol->Vwarm);
   delete pol;
   return REFL_OK;
 }
@@ -2240,9 +2275,33 @@ refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, c
       return REFL_OK;
     }
   }
-  // Refresh: estimate the gap endpoints on this H.
+  // Refresh: estimate the gap endpoints on this H.  With warm_start the
+  // run starts from the Ritz block of the previous refresh on a matrix of
+  // the same order (and falls back to the seeded start if that run fails),
+  // and leaves its own Ritz block for the next refresh.
   LzResult lr;
-  refl_status_t rs = estimate_impl(h, d, dH, ldh, pp.k, pp.lanczos_steps, pp.seed, lr);
+  refl_status_t rs = REFL_ERR_NOT_CONVERGED;
+  bool ran = false;
+  if (pp.warm_start) {
+    const int b = lz_block(d, pp.k);
+    if (pol->dwarm != d) {
+      if (pol->Vwarm) HIPCHK(hipFree(pol->Vwarm));
+      pol->Vwarm = nullptr;
+      pol->dwarm = 0;
+      if (hipMalloc(&pol->Vwarm, sizeof(double) * (size_t)d * b) != hipSuccess)
+        return fail(h, REFL_ERR_NO_MEMORY, "policy warm-start block (%lld x %d) failed", (long long)d, b);
+    } else {
+      rs = estimate_impl(h, d, dH, ldh, pp.k, pp.lanczos_steps, pp.seed, lr, pol->Vwarm, pol->Vwarm);
+      ran = rs == REFL_OK;
+    }
+    if (!ran) {
+      lr = LzResult();
+      rs = estimate_impl(h, d, dH, ldh, pp.k, pp.lanczos_steps, pp.seed, lr, nullptr, pol->Vwarm);
+      ran = true;
+    }
+    pol->dwarm = rs == REFL_OK ? d : 0;
+  }
+  if (!ran) rs = estimate_impl(h, d, dH, ldh, pp.k, pp.lanczos_steps, pp.seed, lr);
   pol->refreshes += 1;
   inf.refreshed = 1;
   inf.lanczos_steps = lr.steps;

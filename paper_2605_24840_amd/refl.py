@@ -47,7 +47,8 @@ class refl_params_t(ctypes.Structure):
 class refl_policy_params_t(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("beta", ctypes.c_double),
                 ("clip", ctypes.c_double), ("tau", ctypes.c_double),
-                ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("warm_start", ctypes.c_int32)]
 
 
 class refl_policy_info_t(ctypes.Structure):
@@ -229,9 +230,10 @@ def refl_sign_grad(h, d, H_ptr, ldh, params, G_ptr, ldg, grad_ptr, ldgr, R_ptr=N
     return st, loss.value, info
 
 
-def refl_policy_create(h, mode, k, beta=0.5, clip=0.25, tau=0.5, lanczos_steps=0, seed=0):
+def refl_policy_create(h, mode, k, beta=0.5, clip=0.25, tau=0.5, lanczos_steps=0, seed=0,
+                       warm_start=True):
     pp = refl_policy_params_t(POLICY[mode], int(k), float(beta), float(clip), float(tau),
-                              int(lanczos_steps), int(seed))
+                              int(lanczos_steps), int(seed), int(bool(warm_start)))
     pol = ctypes.c_void_p()
     _check(h, load().refl_policy_create(h, ctypes.byref(pp), ctypes.byref(pol)))
     return pol
@@ -253,7 +255,9 @@ def refl_policy_shift(h, pol, d, H_ptr, ldh, check=True):
 
 
 class ShiftPolicy:
-    """A shift policy over a sequence of Hessians on one handle (torch tensors)."""
+    """A shift policy over a sequence of Hessians on one handle (torch tensors).
+    Keyword arguments are those of ``refl_policy_params_t`` (``warm_start``
+    defaults to True here: refreshes start from the previous Ritz block)."""
 
     def __init__(self, handle, mode, k, **kw):
         self.handle = handle

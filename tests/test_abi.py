@@ -92,13 +92,13 @@ def test_policy_struct_layout_matches_header(tmp_path):
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "refl.h"\n'
         "int main(void){\n"
-        'printf("%zu %zu %zu %zu %zu\\n", sizeof(refl_policy_params_t), sizeof(refl_policy_info_t),'
+        'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(refl_policy_params_t), sizeof(refl_policy_info_t),'
         " offsetof(refl_policy_params_t, seed), offsetof(refl_policy_info_t, refreshed),"
-        " offsetof(refl_policy_info_t, refreshes));\n"
+        " offsetof(refl_policy_info_t, refreshes), offsetof(refl_policy_params_t, warm_start));\n"
         "return 0;}\n")
     exe = tmp_path / "pol"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
     assert got == [ctypes.sizeof(refl.refl_policy_params_t), ctypes.sizeof(refl.refl_policy_info_t),
                    refl.refl_policy_params_t.seed.offset, refl.refl_policy_info_t.refreshed.offset,
-                   refl.refl_policy_info_t.refreshes.offset]
+                   refl.refl_policy_info_t.refreshes.offset, refl.refl_policy_params_t.warm_start.offset]

@@ -98,3 +98,42 @@ def test_policy_errors(R, handle):
     s, info, st = pol.shift(H, check=False)          # k = 8 > d - 1
     assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
     pol.close()
+
+
+def test_policy_warm_start(R, handle):
+    """Warm start (refl_policy_params_t.warm_start): MIDPOINT over a slowly
+    drifting sequence at d = 1024, k = 8, H_n = H_0 + 0.004 n D (D symmetric,
+    unit Frobenius norm).  Each refresh after the first starts block Lanczos
+    from the Ritz vectors of the previous refresh's b smallest Ritz values.
+    Beside the same policy with the seeded start: every shift is truly
+    admissible (exact eigenvalues), the warm estimates of lambda_k and
+    lambda_k+1 are within their radius of the exact ones, the two midpoints
+    agree to the sum of the radii, and the warm refreshes take at most a
+    third of the block steps."""
+    d, k = 1024, 8
+    H0, lam, Q = inputs.planted_hessian(d, k, 0.05, 60)
+    D = inputs.symmetric_normal(d, 61)
+    D /= np.linalg.norm(D)
+    warm = R.ShiftPolicy(handle, "midpoint", k, warm_start=True)
+    cold = R.ShiftPolicy(handle, "midpoint", k, warm_start=False)
+    steps_w, steps_c = [], []
+    for n in range(6):
+        H = H0 + (n * 0.004) * D
+        Hg = torch.from_numpy(H).to("cuda:0")
+        sw, iw, stw = warm.shift(Hg)
+        sc, ic, stc = cold.shift(Hg)
+        w = np.linalg.eigvalsh(H)
+        _say(f"n={n}: warm s={sw:.10f} steps={iw['lanczos_steps']} eps={iw['eps']:.1e} | "
+             f"cold s={sc:.10f} steps={ic['lanczos_steps']} eps={ic['eps']:.1e} | "
+             f"exact gap ({w[k - 1]:.10f}, {w[k]:.10f})")
+        assert stw == 0 and stc == 0
+        assert w[k - 1] < sw < w[k] and w[k - 1] < sc < w[k]
+        assert abs(iw["lam_k"] - w[k - 1]) <= iw["eps"] + 1e-12
+        assert abs(iw["lam_k1"] - w[k]) <= iw["eps"] + 1e-12
+        assert abs(sw - sc) <= iw["eps"] + ic["eps"] + 1e-12
+        steps_w.append(iw["lanczos_steps"])
+        steps_c.append(ic["lanczos_steps"])
+    warm.close()
+    cold.close()
+    assert steps_w[0] == steps_c[0]
+    assert sum(steps_w[1:]) * 3 <= sum(steps_c[1:])

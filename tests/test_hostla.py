@@ -28,6 +28,7 @@ void t_ritz(int j, int b, int k, const double* TA, const double* TB, int extreme
   refl::ritz_check(j, b, k, TA, TB, extremes != 0, rc, prev ? &pv : nullptr);
   out[0] = rc.th_k; out[1] = rc.th_k1; out[2] = rc.res_k; out[3] = rc.res_k1; out[4] = rc.th_min; out[5] = rc.th_max;
 }
+int t_ritzvec(int j, int b, const double* TA, const double* TB, int nvec, double* Y) { return refl::ritz_vectors(j, b, TA, TB, nvec, Y); }
 }
 """
 
@@ -50,6 +51,7 @@ def lib(tmp_path_factory):
     L.t_invit.restype = ctypes.c_double
     L.t_eig.argtypes = [ctypes.c_int, P, P, P]
     L.t_ritz.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, P]
+    L.t_ritzvec.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P]
     return L
 
 
@@ -224,3 +226,40 @@ def test_ritz_check_warm_start_matches_cold(lib):
     lib.t_ritz(J, b, k, ptr(TA), ptr(TB), 0, ptr(warm), ptr(bad))
     lib.t_ritz(J, b, k, ptr(TA), ptr(TB), 0, ptr(cold), None)
     assert abs(cold[0] - warm[0]) <= 1e-9 * scale and abs(cold[1] - warm[1]) <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("j,b,nvec", [(1, 4, 4), (6, 5, 9), (20, 9, 9)])
+def test_ritz_vectors_against_lapack(lib, j, b, nvec):
+    """The nvec lowest Ritz pairs of T_j: orthonormal vectors, T y = theta y,
+    and the values of LAPACK."""
+    TA, TB = _lanczos_blocks(b, j + 1, 20 + j)
+    n = j * b
+    Y = np.zeros((nvec, n))                       # column-major n x nvec
+    assert lib.t_ritzvec(j, b, ptr(TA), ptr(TB), nvec, ptr(Y)) == 0
+    Y = Y.T
+    T = _dense_T(TA, TB, j, b)
+    w = np.linalg.eigvalsh(T)
+    scale = np.abs(w).max()
+    np.testing.assert_allclose(Y.T @ Y, np.eye(nvec), atol=1e-10)
+    th = np.einsum("ij,ij->j", Y, T @ Y)
+    np.testing.assert_allclose(th, w[:nvec], atol=1e-9 * scale)
+    assert np.linalg.norm(T @ Y - Y * th) <= 1e-8 * scale
+
+
+def test_ritz_vectors_repeated_eigenvalue(lib):
+    """Uncoupled identical blocks give eigenvalues of multiplicity j: the
+    vectors still come out orthonormal and span the lowest eigenspace."""
+    b, j = 3, 4
+    A = np.array([[2.0, 0.5, 0.0], [0.5, 1.0, 0.2], [0.0, 0.2, 3.0]])
+    TA = np.ascontiguousarray(np.repeat(A.T[None], j + 1, axis=0))
+    TB = np.zeros((j + 1, b, b))
+    n = j * b
+    nvec = j                                     # exactly the lowest eigenspace
+    Y = np.zeros((nvec, n))
+    assert lib.t_ritzvec(j, b, ptr(TA), ptr(TB), nvec, ptr(Y)) == 0
+    Y = Y.T
+    T = _dense_T(TA, TB, j, b)
+    w, V = np.linalg.eigh(T)
+    np.testing.assert_allclose(Y.T @ Y, np.eye(nvec), atol=1e-10)
+    P = V[:, :nvec] @ V[:, :nvec].T
+    assert np.linalg.norm(P @ Y - Y) <= 1e-8

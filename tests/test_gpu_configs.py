@@ -96,3 +96,31 @@ def test_c1_fp32(R, handle, planted, grel, theta):
     _say(f"  status={R.STATUS[st]} steps={info['ns_steps']} ||R-R_k||_F={err:.2e} err/(u32 sqrt(d)/gamma)={err / bound:.2f}")
     assert info["index_j"] == k
     assert err <= 4 * bound
+
+
+def test_e1_radius_grown_at_fixed_gap(R, handle):
+    """Section 5.1 (ii): the spectral radius grows (r = 1, 4, 16) at a fixed
+    absolute gap 0.02 (d = 512, k = 8, midpoint shift).  The scaled half-gap
+    shrinks like 1/r, so the FP64 depth grows by about log_1.5(4) per
+    factor 4; it equals the scalar model's depth on the exact eigenvalues
+    (within one step), and the reflector stays exact to rounding."""
+    d, k, g, tol = 512, 8, 0.02, 1e-10
+    rng = np.random.default_rng(90)
+    Q = inputs.haar_orthogonal(d, rng)
+    depths = []
+    for r in (1.0, 4.0, 16.0):
+        lam = r * inputs.planted_eigenvalues(d, k, g / r, np.random.default_rng(91))
+        H = (Q * lam) @ Q.T
+        H = 0.5 * (H + H.T)
+        s = 0.5 * (lam[k - 1] + lam[k])
+        Rg, info, st = R.sign(torch.from_numpy(H).to("cuda:0"), k, s, handle=handle, precision="fp64",
+                              tol=tol, check=False)
+        err = float(np.linalg.norm(Rg.cpu().numpy() - (np.eye(d) - 2.0 * Q[:, :k] @ Q[:, :k].T)))
+        m_pred = oracle.ns_depth_scalar((lam - s) / oracle.inf_norm_shifted(H, s), tol)
+        _say(f"radius {r:g}: steps={info['ns_steps']} predicted={m_pred} alpha={info['alpha']:.3f} "
+             f"||R-R_k||_F={err:.2e}")
+        assert st == 0 and info["index_j"] == k
+        assert abs(info["ns_steps"] - m_pred) <= 1 and err < 1e-9
+        depths.append(info["ns_steps"])
+    assert depths[0] < depths[1] < depths[2]
+    assert all(2 <= b - a <= 5 for a, b in zip(depths, depths[1:]))

@@ -75,6 +75,21 @@ def test_lanczos_planted_ragged_matches_oracle(R, handle, steps):
         assert lam[k - 1] < vals[0] < lam[k]
 
 
+@pytest.mark.parametrize("k", [14, 28])
+def test_lanczos_wide_blocks_match_oracle(R, handle, k):
+    # b = k + 4 = 18 and 32 (the cap): the block kernels' widest
+    # instantiation (32 columns) in the projections and the Cholesky QR
+    # rounds; d = 400 is ragged against the 256-row slabs.
+    d, seed, steps = 400, 6, 3
+    _say(f"lanczos wide blocks d={d} k={k} b={min(k + 4, 32)} steps={steps}")
+    H, lam, _ = inputs.planted_hessian(d, k, 0.1, seed)
+    hn = float(np.abs(H).sum(axis=1).max())
+    ora = oracle.block_lanczos(H, k, max_steps=steps, seed=seed)
+    *vals, st = R.estimate_shift(_gpu(H), k, steps=steps, seed=seed, handle=handle, check=False)
+    _say(f"  status {R.STATUS[st]} lam_k {vals[1]:.12f} / {ora['lam_k']:.12f} eps {vals[3]:.3e} / {ora['eps']:.3e}")
+    _compare(vals, ora, hn)
+
+
 def test_lanczos_full_space_is_exact(R, handle):
     # d = 56, k = 3: b = 7, 8 steps span R^56; the Ritz values are the
     # eigenvalues and the residual radius is 0.

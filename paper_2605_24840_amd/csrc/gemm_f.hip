@@ -299,10 +299,13 @@ template <typename T, int MODE, int TS>
 __global__ __launch_bounds__(256) void k_sym_gemm_f_grouped(const GemmProblem* __restrict__ probs,
                                                             const int4* __restrict__ tiles,
                                                             int parity,
-                                                            double* __restrict__ partials) {
+                                                            double* __restrict__ partials,
+                                                            const int* __restrict__ live) {
   __shared__ T lds[FCfg<T, TS>::LDS];
   __shared__ double red[4];
   const int4 tl = tiles[blockIdx.x];
+  // A problem that has stopped keeps its iterates: its tiles do nothing.
+  if (live && !live[tl.x]) return;
   const GemmProblem pr = probs[tl.x];
   T* Xc = reinterpret_cast<T*>(pr.X[parity]);
   T* Xn = reinterpret_cast<T*>(pr.X[parity ^ 1]);
@@ -412,32 +415,32 @@ int sym_gemm_f_blocks_per_cu(int fp64, int ts) {
 
 template <typename T, int TS>
 static void launch_grouped_ts(int mode, const GemmProblem* probs, const int4* tiles, int ntiles,
-                              int parity, double* partials, hipStream_t st) {
+                              int parity, double* partials, const int* live, hipStream_t st) {
   if (mode == GEMM_RESIDUAL)
     hipLaunchKernelGGL((k_sym_gemm_f_grouped<T, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0,
-                       st, probs, tiles, parity, partials);
+                       st, probs, tiles, parity, partials, live);
   else
     hipLaunchKernelGGL((k_sym_gemm_f_grouped<T, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st,
-                       probs, tiles, parity, partials);
+                       probs, tiles, parity, partials, live);
 }
 
 hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem* probs,
                                    const int4* tiles, int ntiles, int parity, double* partials,
-                                   hipStream_t st) {
+                                   const int* live, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   if (mode != GEMM_RESIDUAL && mode != GEMM_UPDATE) return hipErrorInvalidValue;
   switch (ts) {
     case 64:
-      if (fp64) launch_grouped_ts<double, 64>(mode, probs, tiles, ntiles, parity, partials, st);
-      else launch_grouped_ts<float, 64>(mode, probs, tiles, ntiles, parity, partials, st);
+      if (fp64) launch_grouped_ts<double, 64>(mode, probs, tiles, ntiles, parity, partials, live, st);
+      else launch_grouped_ts<float, 64>(mode, probs, tiles, ntiles, parity, partials, live, st);
       break;
     case 96:
-      if (fp64) launch_grouped_ts<double, 96>(mode, probs, tiles, ntiles, parity, partials, st);
-      else launch_grouped_ts<float, 96>(mode, probs, tiles, ntiles, parity, partials, st);
+      if (fp64) launch_grouped_ts<double, 96>(mode, probs, tiles, ntiles, parity, partials, live, st);
+      else launch_grouped_ts<float, 96>(mode, probs, tiles, ntiles, parity, partials, live, st);
       break;
     case 128:
-      if (fp64) launch_grouped_ts<double, 128>(mode, probs, tiles, ntiles, parity, partials, st);
-      else launch_grouped_ts<float, 128>(mode, probs, tiles, ntiles, parity, partials, st);
+      if (fp64) launch_grouped_ts<double, 128>(mode, probs, tiles, ntiles, parity, partials, live, st);
+      else launch_grouped_ts<float, 128>(mode, probs, tiles, ntiles, parity, partials, live, st);
       break;
     default:
       return hipErrorInvalidValue;

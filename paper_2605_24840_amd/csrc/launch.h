@@ -54,9 +54,10 @@ struct GemmProblem {
   int ld, d, dp, pad;
 };
 // One launch covers the problems of one tile edge ts (their dp multiples of ts).
+// With live != null the tiles of problems p with live[p] == 0 do nothing.
 hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem* probs,
                                    const int4* tiles, int ntiles, int parity, double* partials,
-                                   hipStream_t st);
+                                   const int* live, hipStream_t st);
 
 // Products of matrices held as W BF16 words per entry (planes ps elements
 // apart), FP32 accumulation on 32x32x16 BF16 MFMA.  Word products kept:
@@ -148,6 +149,26 @@ hipError_t launch_batch_setup(int fp64, const BatchDesc* desc, int ng, const int
 constexpr int BATCH_COPY_ROWS = 8;
 hipError_t launch_batch_copy(int fp64, const BatchDesc* desc, const int* begin, const int* ids,
                              int ng, int nblocks_total, int to_hf, hipStream_t st);
+// Stopping rule of the batched solve evaluated on the device (the rule of
+// refl_sign, problem by problem): per-problem limits, and the state of each
+// problem's iteration.
+struct BatchRule {
+  double tol;
+  int fixed_steps, max_iter;
+};
+struct BatchStep {
+  double h1, h2;      // ||X^2 - I||_F of the previous two steps
+  double resid, trace;  // of the last step evaluated
+  int m, par, state, pad;  // steps taken; buffer of the final iterate; BATCH_*
+};
+constexpr int BATCH_LIVE = 0, BATCH_CONVERGED = 1, BATCH_STOPPED = 2, BATCH_NONFINITE = 3;
+// One step's decision for every problem with live[p]: resid = sqrt(res[p]),
+// trace of X_m from trace[p] (m > 0), then the rule; a problem that stops
+// gets live[p] = 0 and par.  ctl[0] is the step m (read, then incremented),
+// ctl[1] receives the number of problems still live.
+hipError_t launch_batch_decide(int nprob, const double* res, const double* trace,
+                               const BatchRule* rules, BatchStep* stp, int* live, int* ctl,
+                               int par, hipStream_t st);
 // out[slot ? slot[q] : q] = sum of partials[begin[q] .. begin[q + 1]), q < nq,
 // summed in the same order as launch_reduce_sum over that range.
 hipError_t launch_reduce_ranges(const double* partials, const int* begin, const int* slot, int nq,

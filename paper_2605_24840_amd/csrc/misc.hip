@@ -191,6 +191,59 @@ __global__ __launch_bounds__(256) void k_reduce_ranges(const double* __restrict_
   if (threadIdx.x == 0) out[slot ? slot[q] : q] = t;
 }
 
+// The stopping rule of refl_sign for every live problem of the batched
+// solve (one block; problems strided over the threads).
+__global__ __launch_bounds__(256) void k_batch_decide(int nprob, const double* __restrict__ res,
+                                                      const double* __restrict__ trace,
+                                                      const BatchRule* __restrict__ rules,
+                                                      BatchStep* __restrict__ stp,
+                                                      int* __restrict__ live, int* __restrict__ ctl,
+                                                      int par) {
+  __shared__ double red[4];
+  const int m = ctl[0];
+  int n = 0;
+  for (int p = threadIdx.x; p < nprob; p += 256) {
+    if (!live[p]) continue;
+    BatchStep s = stp[p];
+    const BatchRule ru = rules[p];
+    const double r = sqrt(fmax(res[p], 0.0));
+    if (m > 0) s.trace = trace[p];
+    s.m = m;
+    s.resid = r;
+    if (!isfinite(r)) {
+      s.state = BATCH_NONFINITE;
+      live[p] = 0;
+      stp[p] = s;
+      continue;
+    }
+    bool stop = false, conv = false;
+    if (ru.fixed_steps > 0) {
+      if (m >= ru.fixed_steps) stop = conv = true;
+    } else if (r < ru.tol) {
+      stop = conv = true;
+    } else if (m >= 2 && r < 1e-6 && r > 0.5 * s.h2) {
+      stop = true;  // stagnation: no halving over two steps below 1e-6
+    } else if (m >= ru.max_iter) {
+      stop = true;
+    }
+    s.h2 = s.h1;
+    s.h1 = r;
+    if (stop) {
+      s.par = par;
+      s.state = conv ? BATCH_CONVERGED : BATCH_STOPPED;
+      live[p] = 0;
+    } else {
+      ++n;
+    }
+    stp[p] = s;
+  }
+  const double t = block_sum_256((double)n, red);
+  if (threadIdx.x == 0) {
+    ctl[1] = (int)t;
+    ctl[0] = m + 1;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void trace_block(const T* __restrict__ X, int dp, int d,
                                             double* __restrict__ out, double* red) {
@@ -963,6 +1016,14 @@ hipError_t launch_reduce_ranges(const double* partials, const int* begin, const 
                                 double* out, hipStream_t st) {
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_ranges, dim3(nq), dim3(256), 0, st, partials, begin, slot, out);
+  return hipGetLastError();
+}
+hipError_t launch_batch_decide(int nprob, const double* res, const double* trace,
+                               const BatchRule* rules, BatchStep* stp, int* live, int* ctl,
+                               int par, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_decide, dim3(1), dim3(256), 0, st, nprob, res, trace, rules, stp, live,
+                     ctl, par);
   return hipGetLastError();
 }
 hipError_t launch_trace_f64(const double* X, int dp, int d, double* scal, int slot,

@@ -58,6 +58,7 @@ struct refl_handle_s {
   void* batch_pin = nullptr;   // host pinned staging of the batched solve
   size_t batch_pin_bytes = 0;
   hipEvent_t lz_ev[2] = {nullptr, nullptr};
+  hipStream_t cap = nullptr;   // stream the batched step graph is captured on
   int ncu = 256;               // compute units of the device
   char err[512] = {0};
 };
@@ -1244,6 +1245,10 @@ struct BatchWork {
   int* sbeg = nullptr;  // set-up prefix arrays: mirror, rows, init (3 (n + 1))
   int* cbeg = nullptr;  // output prefix arrays: R rows, Hf rows (2 (n + 1))
   double *res = nullptr, *trace = nullptr, *cert = nullptr;
+  BatchRule* rules = nullptr;  // device-driven stopping rule
+  BatchStep* stp = nullptr;
+  int* live = nullptr;
+  int* ctl = nullptr;          // step counter, live count
 };
 
 // Tile edges of the batched FP32 / FP64 products, in the order their tile
@@ -1291,6 +1296,10 @@ size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, cons
   bw.res = c.take<double>(nprob);
   bw.trace = c.take<double>(nprob);
   bw.cert = c.take<double>(nprob);
+  bw.rules = c.take<BatchRule>(nprob);
+  bw.stp = c.take<BatchStep>(nprob);
+  bw.live = c.take<int>(nprob);
+  bw.ctl = c.take<int>(2);
   return c.off + 256;
 }
 
@@ -1300,6 +1309,9 @@ struct BatchPin {
   GemmProblem *probs, *probs64;
   BatchDesc* desc;
   double *scal, *res, *trace, *cert;
+  BatchRule* rules;
+  BatchStep* stp;
+  int *live, *ctl;
   int4* tiles[3];
   int *begin[3], *slot[3];
   int *sbeg, *cbeg;
@@ -1314,6 +1326,10 @@ size_t batch_pin_layout(BatchPin& bp, void* base, int nprob, int ttot) {
   bp.res = c.take<double>(nprob);
   bp.trace = c.take<double>(nprob);
   bp.cert = c.take<double>(nprob);
+  bp.rules = c.take<BatchRule>(nprob);
+  bp.stp = c.take<BatchStep>(nprob);
+  bp.live = c.take<int>(nprob);
+  bp.ctl = c.take<int>(2);
   for (int b = 0; b < 3; ++b) {
     bp.tiles[b] = c.take<int4>(ttot);
     bp.begin[b] = c.take<int>(nprob + 1);
@@ -1512,27 +1528,18 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   };
   int cls[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // tiles per edge class of each list
   // One grouped launch per edge class present in list lb.
-  auto grouped_list = [&](int fp, int mode, const GemmProblem* probs, int lb, int par) -> hipError_t {
+  auto grouped_list = [&](int fp, int mode, const GemmProblem* probs, int lb, int par,
+                          const int* live, hipStream_t s) -> hipError_t {
     int off = 0;
     for (int c = 0; c < 3; ++c) {
       if (cls[lb][c] > 0) {
         hipError_t e = launch_sym_gemm_grouped(fp, mode, BATCH_EDGES[c], probs, bw.tiles[lb] + off,
-                                               cls[lb][c], par, bw.partials, st);
+                                               cls[lb][c], par, bw.partials, live, s);
         if (e != hipSuccess) return e;
       }
       off += cls[lb][c];
     }
     return hipSuccess;
-  };
-  auto grouped = [&](int mode, int lb, int nt, int par) -> refl_status_t {
-    (void)nt;
-    if (timing) {
-      HIPCHK(ev_pair());
-      HIPCHK(hipEventRecord(h->ev[2 * nev], st));
-    }
-    HIPCHK(grouped_list(fprec, mode, bw.probs, lb, par));
-    if (timing) HIPCHK(hipEventRecord(h->ev[2 * nev++ + 1], st));
-    return REFL_OK;
   };
   // Step list in buffer lb: build and upload.
   auto upload_list = [&](int lb, const std::vector<int>& ids) -> int {
@@ -1544,73 +1551,116 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
       return -1;
     return nt;
   };
-  std::vector<std::vector<double>> hist(nprob);
+  // The stopping rule runs on the device (k_batch_decide, the rule of
+  // refl_sign), so a step needs no host decision: the residual product, its
+  // per-problem sums, the decision, the update product (tiles of stopped
+  // problems do nothing) and the trace sums.  All problems iterate in step:
+  // step m uses parity m & 1, and the host only reads the live count every
+  // BATCH_GRAPH_STEPS steps.  Those steps are captured once per call in a
+  // HIP graph and the graph is launched until no problem is live (eager
+  // launches instead with params.timing, for the per-launch events, or with
+  // REFL_BATCH_GRAPH=0).
+  constexpr int BATCH_GRAPH_STEPS = 4;
+  const int nq0 = (int)cur.size();
+  int maxsteps = 0;
+  std::vector<char> live0(nprob, 0);
+  for (int p : cur) live0[p] = 1;
+  for (int p = 0; p < nprob; ++p) {
+    bp.rules[p].tol = params[p].tol;
+    bp.rules[p].fixed_steps = params[p].fixed_steps;
+    bp.rules[p].max_iter = params[p].max_iter;
+    std::memset(&bp.stp[p], 0, sizeof(BatchStep));
+    bp.stp[p].trace = trace_cur[p];
+    bp.stp[p].resid = NaN;
+    bp.stp[p].state = live0[p] ? BATCH_LIVE : BATCH_NONFINITE;
+    bp.live[p] = live0[p];
+    if (live0[p])
+      maxsteps = std::max(maxsteps, params[p].fixed_steps > 0 ? params[p].fixed_steps : params[p].max_iter);
+  }
+  bp.ctl[0] = 0;
+  bp.ctl[1] = nq0;
+  HIPCHK(hipMemcpyAsync(bw.rules, bp.rules, sizeof(BatchRule) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bw.stp, bp.stp, sizeof(BatchStep) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bw.live, bp.live, sizeof(int) * nprob, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bw.ctl, bp.ctl, sizeof(int) * 2, hipMemcpyHostToDevice, st));
+  const int lb = 0;
+  const int nt_all = nq0 == 0 ? 0 : upload_list(lb, cur);
+  if (nt_all < 0) return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
+  auto step = [&](int par, hipStream_t s) -> hipError_t {
+    hipError_t e;
+    const bool ev = timing && s == st;
+    if (ev) {
+      if ((e = ev_pair()) != hipSuccess) return e;
+      if ((e = hipEventRecord(h->ev[2 * nev], s)) != hipSuccess) return e;
+    }
+    if ((e = grouped_list(fprec, GEMM_RESIDUAL, bw.probs, lb, par, bw.live, s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(h->ev[2 * nev++ + 1], s)) != hipSuccess) return e;
+    if ((e = launch_reduce_ranges(bw.partials, bw.begin[lb], bw.slot[lb], nq0, bw.res, s)) != hipSuccess)
+      return e;
+    if ((e = launch_batch_decide(nprob, bw.res, bw.trace, bw.rules, bw.stp, bw.live, bw.ctl, par, s)) !=
+        hipSuccess)
+      return e;
+    if (ev) {
+      if ((e = ev_pair()) != hipSuccess) return e;
+      if ((e = hipEventRecord(h->ev[2 * nev], s)) != hipSuccess) return e;
+    }
+    if ((e = grouped_list(fprec, GEMM_UPDATE, bw.probs, lb, par, bw.live, s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(h->ev[2 * nev++ + 1], s)) != hipSuccess) return e;
+    return launch_reduce_ranges(bw.partials, bw.begin[lb], bw.slot[lb], nq0, bw.trace, s);
+  };
+  const char* genv = std::getenv("REFL_BATCH_GRAPH");
+  const bool use_graph = nq0 > 0 && !timing && !(genv && genv[0] == '0');
+  hipGraphExec_t gexec = nullptr;
+  if (use_graph) {
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int i = 0; i < BATCH_GRAPH_STEPS && ce == hipSuccess; ++i) ce = step(i & 1, h->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(h->cap, &graph);
+    if (ce == hipSuccess) ce = ee;
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ce != hipSuccess) {
+      if (gexec) (void)hipGraphExecDestroy(gexec);
+      return fail(h, REFL_ERR_DEVICE, "batched step graph: %s", hipGetErrorString(ce));
+    }
+  }
+  // Each round runs BATCH_GRAPH_STEPS steps; every problem stops by its
+  // step limit, so the rounds are bounded.
+  const int rounds = nq0 == 0 ? 0 : maxsteps / BATCH_GRAPH_STEPS + 2;
+  hipError_t le = hipSuccess;
+  for (int round = 0; round < rounds && le == hipSuccess; ++round) {
+    if (gexec) {
+      le = hipGraphLaunch(gexec, st);
+    } else {
+      for (int i = 0; i < BATCH_GRAPH_STEPS && le == hipSuccess; ++i) le = step(i & 1, st);
+    }
+    if (le == hipSuccess) le = hipMemcpyAsync(bp.ctl, bw.ctl, sizeof(int) * 2, hipMemcpyDeviceToHost, st);
+    if (le == hipSuccess) le = hipStreamSynchronize(st);
+    if (le == hipSuccess && bp.ctl[1] == 0) break;
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (le != hipSuccess) return fail(h, REFL_ERR_DEVICE, "batched steps: %s", hipGetErrorString(le));
+  if (nq0 > 0 && bp.ctl[1] != 0)
+    return fail(h, REFL_ERR_DEVICE, "batched steps: %d problems still iterating after the step limit",
+                bp.ctl[1]);
+  HIPCHK(hipMemcpyAsync(bp.stp, bw.stp, sizeof(BatchStep) * nprob, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   std::vector<char> converged(nprob, 0);
   std::vector<int> done;  // problems that stopped with an iterate to return
-  int lb = 0;
-  int nt_cur = cur.empty() ? 0 : upload_list(lb, cur);
-  if (nt_cur < 0) return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
-  for (int m = 0; !cur.empty(); ++m) {
-    const int par = m & 1;
-    const int nq = (int)cur.size();
-    rs = grouped(GEMM_RESIDUAL, lb, nt_cur, par);
-    if (rs != REFL_OK) return rs;
-    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[lb], bw.slot[lb], nq, bw.res, st));
-    HIPCHK(hipMemcpyAsync(bp.res, bw.res, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
-    if (m > 0)
-      HIPCHK(hipMemcpyAsync(bp.trace, bw.trace, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipEventRecord(ev_res, st));
-    // Second product of step m for every problem of the step (see above).
-    rs = grouped(GEMM_UPDATE, lb, nt_cur, par);
-    if (rs != REFL_OK) return rs;
-    HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[lb], bw.slot[lb], nq, bw.trace, st));
-    HIPCHK(hipEventSynchronize(ev_res));
-    // Stopping rule of refl_sign (FP64 / FP32), problem by problem.
-    std::vector<int> next;
-    for (int p : cur) {
-      const refl_params_t& pp = params[p];
-      if (m > 0) trace_cur[p] = bp.trace[p];
-      const double resid = std::sqrt(std::fmax(bp.res[p], 0.0));
-      std::vector<double>& hs = hist[p];
-      hs.push_back(resid);
-      inf[p].ns_steps = m;
-      inf[p].resid_fro = resid;
-      inf[p].trace = trace_cur[p];
-      if (!std::isfinite(resid)) {
-        pst[p] = REFL_ERR_NOT_FINITE;
-        continue;
-      }
-      bool stop = false;
-      if (pp.fixed_steps > 0) {
-        if (m >= pp.fixed_steps) {
-          stop = true;
-          converged[p] = 1;
-        }
-      } else {
-        const size_t n = hs.size();
-        if (resid < pp.tol) {
-          stop = true;
-          converged[p] = 1;
-        } else if (n >= 3 && resid < 1e-6 && resid > 0.5 * hs[n - 3]) {
-          stop = true;
-        } else if (m >= pp.max_iter) {
-          stop = true;
-        }
-      }
-      if (stop) {
-        bp.desc[p].par = par;
-        done.push_back(p);
-      } else {
-        next.push_back(p);
-      }
+  for (int p : cur) {
+    const BatchStep& q = bp.stp[p];
+    inf[p].ns_steps = q.m;
+    inf[p].resid_fro = q.resid;
+    inf[p].trace = q.trace;
+    if (q.state == BATCH_NONFINITE) {
+      pst[p] = REFL_ERR_NOT_FINITE;
+      continue;
     }
-    if (next.size() != cur.size()) {
-      cur.swap(next);
-      if (cur.empty()) break;
-      lb ^= 1;
-      nt_cur = upload_list(lb, cur);
-      if (nt_cur < 0) return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
-    }
+    converged[p] = q.state == BATCH_CONVERGED;
+    bp.desc[p].par = q.par;
+    done.push_back(p);
   }
 
   // ---- output: FP32 certificate in FP64, then R, for every problem in done ----
@@ -1633,7 +1683,7 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     HIPCHK(hipMemcpyAsync(bw.slot[2], bp.slot[2], sizeof(int) * nd, hipMemcpyHostToDevice, st));
     if (!fp64) {
       HIPCHK(launch_batch_copy(0, bw.desc, bw.cbeg + (nprob + 1), bw.slot[2], nd, hbeg[nd], 1, st));
-      HIPCHK(grouped_list(1, GEMM_RESIDUAL, bw.probs64, 2, 0));
+      HIPCHK(grouped_list(1, GEMM_RESIDUAL, bw.probs64, 2, 0, nullptr, st));
       HIPCHK(launch_reduce_ranges(bw.partials, bw.begin[2], bw.slot[2], nd, bw.cert, st));
       HIPCHK(hipMemcpyAsync(bp.cert, bw.cert, sizeof(double) * nprob, hipMemcpyDeviceToHost, st));
     }
@@ -2084,6 +2134,7 @@ refl_status_t refl_destroy(refl_handle_t h) {
   if (h->lz_pin) (void)hipHostFree(h->lz_pin);
   if (h->batch_pin) (void)hipHostFree(h->batch_pin);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
   return REFL_OK;
 }

@@ -113,6 +113,46 @@ def test_batched_equals_single_and_exact(R, handle, prec):
             assert ib["resid_fro"] == i1["resid_fro"]
 
 
+def test_batched_graph_matches_eager_and_replays(R, handle, monkeypatch):
+    """The steps of a batched call run as a captured HIP graph of four steps,
+    launched until every problem has stopped (the stopping rule runs on the
+    device).  The same call with eager launches (REFL_BATCH_GRAPH=0), with
+    per-launch timing events (eager as well), and a second graph call on the
+    same inputs give the same R, steps and certificates bit for bit; a
+    fixed-steps batch stops every problem at its own m."""
+    probs = _problems(SMALL[:6])
+    Hs = [torch.from_numpy(H).to("cuda:0") for H, *_ in probs]
+    ks = [p[3] for p in probs]
+    ss = [p[4] for p in probs]
+
+    def run(**kw):
+        Rs, infos, sts, st = R.sign_batched(Hs, ks, ss, handle=handle, precision="fp32", tol=1e-3,
+                                            check=False, **kw)
+        assert st == 0 and all(x == 0 for x in sts)
+        return [r.clone() for r in Rs], infos
+
+    g1, i1 = run()
+    g2, i2 = run()
+    monkeypatch.setenv("REFL_BATCH_GRAPH", "0")
+    e1, ie = run()
+    monkeypatch.delenv("REFL_BATCH_GRAPH")
+    t1, it = run(timing=1)
+    for p in range(len(probs)):
+        for other, io in ((g2, i2), (e1, ie), (t1, it)):
+            assert torch.equal(g1[p], other[p]), p
+            assert io[p]["ns_steps"] == i1[p]["ns_steps"] and io[p]["resid_fro"] == i1[p]["resid_fro"]
+            assert io[p]["trace"] == i1[p]["trace"]
+    _say("graph / second graph / eager / timed: equal; steps " + str([x["ns_steps"] for x in i1]))
+    ms = [3, 5, 2, 7, 4, 6]
+    Rs, infos, sts, st = R.sign_batched(Hs, ks, ss, handle=handle, precision="fp32",
+                                        fixed_steps=ms, check=False)
+    assert st == 0 and [x["ns_steps"] for x in infos] == ms
+    for p, m in enumerate(ms):
+        R1, inf1, st1 = R.sign(Hs[p], ks[p], ss[p], handle=handle, precision="fp32", fixed_steps=m,
+                               check=False)
+        assert torch.equal(Rs[p], R1), p
+
+
 def test_batched_fp32_certificate_is_fp64(R, handle):
     """The FP32 certificate ||X^2 - I||_F is the FP64 value for the returned
     iterate (R holds that iterate exactly, as FP32 numbers in FP64).  Two FP64

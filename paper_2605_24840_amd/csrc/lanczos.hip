@@ -172,26 +172,16 @@ __global__ __launch_bounds__(128) void k_lz_apply_partial(const double* __restri
 
 // Row-wise update of the d x nb block W (one row per thread, 256-row slabs):
 //   SUB   (apart != null)  w -= sum_cc apart[cc]            (fixed order)
-//   TRSM  (R != null)      x R = w for upper-triangular R (nb x nb, col-major)
-//   the result goes to dst (which may be W), and with gpart != null the
+//   the result goes to dst (which may be W; none if null), and with gpart != null the
 //   slab's Gram matrix x^T x goes to gpart[blockIdx.x * NB * NB + i + j NB].
 // W and dst may be the same block (each thread reads its row before writing
 // it), so neither is declared restrict.
 template <int NB>
 __global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, int nb,
                                                  int d, const double* __restrict__ apart, int ncc,
-                                                 const double* __restrict__ R,
                                                  double* dst, int64_t ldd,
                                                  double* __restrict__ gpart) {
-  __shared__ double sR[NB][NB];
   __shared__ double sX[256][NB + 1];
-  if (R) {
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-      const int i = e % NB, j = e / NB;
-      sR[i][j] = (i < nb && j < nb) ? R[i + (int64_t)j * nb] : 0.0;
-    }
-  }
-  __syncthreads();
   const int r = blockIdx.x * 256 + threadIdx.x;
   double x[NB];
 #pragma unroll
@@ -221,20 +211,11 @@ __global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, i
         for (int j = 0; j < NB; ++j)
           if (j < nb) x[j] -= apart[((int64_t)cc * NB + j) * d + r];
     }
-    if (R) {
+    if (dst) {
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nb) {
-          double s = x[j];
-#pragma unroll
-          for (int i = 0; i < j; ++i) s = fma(-x[i], sR[i][j], s);
-          x[j] = s / sR[j][j];
-        }
-      }
+      for (int j = 0; j < NB; ++j)
+        if (j < nb) dst[(int64_t)j * ldd + r] = x[j];
     }
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (j < nb) dst[(int64_t)j * ldd + r] = x[j];
   }
   if (!gpart) return;
 #pragma unroll
@@ -465,7 +446,7 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
     hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 128), ncc), dim3(128), 0, st,
                        V, ldv, n, C, nb, d, apart);
     hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, W, ldw, nb, d,
-                       apart, ncc, nullptr, W, ldw, gpart);
+                       apart, ncc, W, ldw, gpart);
   })
   return hipGetLastError();
 }
@@ -478,16 +459,15 @@ hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, i
     hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 128), ncc), dim3(128), 0, st,
                        V, ldv, n, Cneg, nb, d, apart);
     hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, Wzero, ldd, nb,
-                       d, apart, ncc, nullptr, dst, ldd, nullptr);
+                       d, apart, ncc, dst, ldd, nullptr);
   })
   return hipGetLastError();
 }
 
-hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R, double* dst,
-                   int64_t ldd, double* gpart, hipStream_t st) {
+hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st) {
   LZ_DISPATCH(nb, {
     hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, W, ldw, nb, d,
-                       nullptr, 0, R, dst, ldd, gpart);
+                       nullptr, 0, nullptr, ldw, gpart);
   })
   return hipGetLastError();
 }

@@ -275,10 +275,8 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
 hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
                       double* apart, const double* Wzero, double* dst, int64_t ldd,
                       hipStream_t st);
-// dst = W R^{-1} (R upper triangular nb x nb on the device; R == null: a
-// copy), with optional Gram partials of the result.
-hipError_t lz_rows(const double* W, int64_t ldw, int nb, int d, const double* R, double* dst,
-                   int64_t ldd, double* gpart, hipStream_t st);
+// Gram partials of the 256-row slabs of W (d x nb): gpart[slab NB^2 + i + j NB].
+hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st);
 // One Cholesky QR round: factor the summed Gram partials gin (+ shift_rel *
 // trace I) as L L^T, dst = W R^{-1} with R = L^T (W and dst may alias), and
 // with gout != null (gout != gin) the Gram partials of dst.  Bacc = R

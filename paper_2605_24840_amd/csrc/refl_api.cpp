@@ -671,7 +671,7 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     return REFL_OK;
   };
   auto cholqr3 = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
-    HIPCHK(lz_rows(z.W, ld, b, (int)d, nullptr, z.W, ld, z.gp[0], st));
+    HIPCHK(lz_gram(z.W, ld, b, (int)d, z.gp[0], st));
     return cholqr3_rounds(dst, Arec, Brec, tag);
   };
   if (start)

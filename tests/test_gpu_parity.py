@@ -10,6 +10,7 @@ Tolerances:
   commuting iterate (eigenwise |p - s| <= |p^2 - 1|), plus rounding.
 * MIXED: the target ||R - R_k||_F <= 1e-8 sqrt(d).
 """
+import ctypes
 import os
 
 import numpy as np
@@ -393,3 +394,46 @@ def test_mixed_allen_cahn_d4096(R, handle, k):
          f"bulk={info['ms_bulk']:.1f}ms polish={info['ms_polish']:.1f}ms")
     assert st == 0
     assert err <= 1e-8 * np.sqrt(d)
+
+
+# ------------------------------------------------------ tiny and empty
+@pytest.mark.parametrize("d", [2, 3, 5])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_tiny_orders(R, handle, d, prec):
+    """Orders far below one tile (the matrices are padded to a tile and zero
+    outside d x d), every admissible index k = 1 .. d - 1, against the
+    oracle's Jacobi reflector; the index certificate must give k."""
+    rng = np.random.default_rng(100 + d)
+    lam = np.sort(rng.uniform(-1.0, 1.0, d))
+    lam += 0.3 * np.arange(d)                      # gaps of at least 0.3
+    Q = inputs.haar_orthogonal(d, rng)
+    H = np.ascontiguousarray(0.5 * ((Q * lam) @ Q.T + ((Q * lam) @ Q.T).T))
+    Hg = _gpu(H)
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "mixed": 1e-8 * np.sqrt(d)}[prec]
+    for k in range(1, d):
+        Rk, w, V = oracle.reflector(H, k)
+        s = oracle.midpoint(w, k)
+        Rg, info, st = R.sign(Hg, k, s, handle=handle, precision=prec, tol=tol, check=False)
+        err = float(np.linalg.norm(Rg.cpu().numpy() - Rk))
+        _say(f"tiny d={d} k={k} {prec}: status={R.STATUS[st]} steps={info['ns_steps']} "
+             f"j={info['index_j']} err={err:.1e}")
+        # FP32: ||X - sgn(X)||_F <= ||X^2 - I||_F for the symmetric iterate, plus
+        # the rounding of the products (u32 = 6e-8 per entry at these orders).
+        bound = {"fp64": 1e-12, "fp32": info["resid_fro"] + 1e-6, "mixed": tol}[prec]
+        assert st == 0 and info["index_j"] == k and err <= bound
+
+
+def test_empty_arguments_rejected(R, handle):
+    """Empty inputs are argument errors at the boundary: d = 0, nrhs = 0, an
+    empty batch."""
+    lib = R.load()
+    h = handle.h
+    buf = torch.zeros(16, dtype=torch.float64, device="cuda:0")
+    p = R.make_params(1, 0.0)
+    info = R.refl_info_t()
+    st = lib.refl_sign(h, 0, buf.data_ptr(), 1, ctypes.byref(p), buf.data_ptr(), 1, ctypes.byref(info))
+    assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
+    st = lib.refl_apply(h, 4, buf.data_ptr(), 4, 0, buf.data_ptr(), 4, buf.data_ptr(), 4)
+    assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
+    st = lib.refl_sign_batched(h, 0, None, None, None, None, None, None, None, None)
+    assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"

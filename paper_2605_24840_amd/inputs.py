@@ -67,6 +67,34 @@ def planted_eigenvalues(d: int, k: int, gap: float, rng: np.random.Generator) ->
     return lam
 
 
+def planted_hessian_reflected(d: int, k: int, gap: float, seed: int, nrefl: int = 3):
+    """H = Q diag(lambda) Q^T with Q a product of nrefl Householder
+    reflectors of seeded random unit vectors: a dense symmetric matrix with
+    the planted spectrum of planted_eigenvalues, built in O(nrefl d^2) (for
+    large orders, where a Haar Q costs O(d^3)).  Returns ``(H, lam, Qk)``
+    with Qk the first k columns of Q."""
+    rng = np.random.default_rng(seed)
+    lam = planted_eigenvalues(d, k, gap, rng)
+    us = []
+    for _ in range(nrefl):
+        u = rng.standard_normal(d)
+        us.append(u / np.linalg.norm(u))
+    # Q = P_1 ... P_n with P_i = I - 2 u_i u_i^T; H = Q diag(lam) Q^T is
+    # formed inside out, one two-sided reflection at a time:
+    # P A P = A - 2 u w^T - 2 w u^T + 4 (u.w) u u^T with w = A u.
+    H = np.diag(lam)
+    for u in reversed(us):
+        w = H @ u
+        c = 4.0 * float(u @ w)
+        H -= np.outer(u, 2.0 * w - c * u)
+        H -= np.outer(2.0 * w, u)
+    H = 0.5 * (H + H.T)
+    Qk = np.eye(d, k)
+    for u in reversed(us):
+        Qk -= 2.0 * np.outer(u, u @ Qk)
+    return np.ascontiguousarray(H), lam, Qk
+
+
 def planted_hessian(d: int, k: int, gap: float, seed: int):
     """H = Q diag(lambda) Q^T with Haar Q and a planted gap.
 

@@ -437,3 +437,44 @@ def test_empty_arguments_rejected(R, handle):
     assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
     st = lib.refl_sign_batched(h, 0, None, None, None, None, None, None, None, None)
     assert R.STATUS[st] == "REFL_ERR_INVALID_ARG"
+
+
+@pytest.fixture(scope="module")
+def large():
+    # d = 12000: three times the Allen-Cahn order, ragged against the 192-row
+    # bulk tiles and the 64/128-row FP tiles.  1.15 GB per FP64 matrix.
+    d, k = 12000, 8
+    H, lam, Qk = inputs.planted_hessian_reflected(d, k, 0.02, 12)
+    return H, lam, Qk, k
+
+
+def _err_on_device(Rg, Qk):
+    Qg = torch.from_numpy(Qk).to(Rg.device)
+    E = Rg - torch.eye(Rg.shape[0], dtype=Rg.dtype, device=Rg.device)
+    E += 2.0 * (Qg @ Qg.T)
+    return float(torch.linalg.norm(E))
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+def test_large_order(R, handle, large, prec):
+    """A large order through the whole path (d = 12000, k = 8, gap 0.02): the
+    MIXED reflector meets 1e-8 sqrt(d) and its certified bound; FP32 meets
+    its rounding bound (err <= resid + 4 u32 sqrt(d)/gamma, as for the
+    controlled spectra)."""
+    H, lam, Qk, k = large
+    d = H.shape[0]
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Hg = _gpu(H)
+    tol = 1e-8 * np.sqrt(d) if prec == "mixed" else 1e-3
+    Rg, info, st = R.sign(Hg, k, s, handle=handle, precision=prec, tol=tol, check=False)
+    err = _err_on_device(Rg, Qk)
+    _say(f"large d={d} k={k} {prec}: status={R.STATUS[st]} steps={info['ns_steps']} sweeps={info['polish_sweeps']} "
+         f"cg={info['cg_iters']} j={info['index_j']} err={err:.2e} ms={info['ms_total']:.0f}")
+    assert st == 0 and info["index_j"] == k
+    if prec == "mixed":
+        assert err <= tol and err <= info["dk_bound"] * 1.0001 + 1e-15
+    else:
+        gamma = (s - lam[k - 1]) / info["alpha"]
+        assert err <= info["resid_fro"] + 4 * 2.0 ** -24 * np.sqrt(d) / gamma
+    del Hg, Rg
+    torch.cuda.empty_cache()

@@ -51,3 +51,16 @@ def test_allen_cahn_2d_structure():
     # Same seed, same field.
     H2, u2 = inputs.allen_cahn_2d(n, eps, seed=1)
     np.testing.assert_array_equal(u, u2)
+
+
+@pytest.mark.parametrize("d,k", [(300, 7), (50, 1), (97, 96)])
+def test_planted_hessian_reflected(d, k):
+    """The O(d^2) planted generator: H symmetric, its spectrum the planted
+    one, and its lowest-k eigenspace spanned by the returned orthonormal Qk
+    (LAPACK on the result)."""
+    H, lam, Qk = inputs.planted_hessian_reflected(d, k, 0.1, 3)
+    assert np.array_equal(H, H.T)
+    w, V = np.linalg.eigh(H)
+    np.testing.assert_allclose(w, lam, atol=1e-13)
+    np.testing.assert_allclose(Qk.T @ Qk, np.eye(k), atol=1e-13)
+    assert np.linalg.norm(V[:, :k] @ V[:, :k].T - Qk @ Qk.T) < 1e-12

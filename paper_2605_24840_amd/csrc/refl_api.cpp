@@ -1436,8 +1436,6 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     h->batch_pin_bytes = pin_need;
   }
   batch_pin_layout(bp, h->batch_pin, nprob, bw.ttot);
-  if (h->lz_ev[0] == nullptr) HIPCHK(hipEventCreateWithFlags(&h->lz_ev[0], hipEventDisableTiming));
-  hipEvent_t ev_res = h->lz_ev[0];
 
   std::vector<refl_info_t> inf(nprob);
   std::vector<refl_status_t> pst(nprob, REFL_OK);

@@ -759,14 +759,15 @@ struct CgState {
 };
 
 // Grid (column blocks of 256 output rows, chunks of CHUNK rows of M).  M is
-// H in FP64, or its FP32 copy (the products still accumulate in FP64).  An
-// FP32 pass moves half the bytes per load, so it needs twice the waves to
-// keep as many bytes in flight: its 128-row chunks are split over two
-// groups of four waves (the same number of chunk partials as the FP64
-// pass).
+// H in FP64, or its FP32 copy (the products still accumulate in FP64).  Up
+// to 16 columns the 128-row chunks are split over two groups of four waves:
+// an FP32 pass moves half the bytes per load and needs twice the waves to
+// keep as many bytes in flight, and either pass then has twice the waves for
+// the reduction and the update at its start.  Wider blocks keep one group
+// (the LDS of the group sums), and the FP32 pass 64-row chunks.
 constexpr int CG_SRC = SRC / 2;
 template <typename MT, int NB>
-constexpr int cg_ks() { return (sizeof(MT) == 4 && NB <= 16) ? 2 : 1; }
+constexpr int cg_ks() { return NB <= 16 ? 2 : 1; }
 template <typename MT, int NB>
 constexpr int cg_chunk() { return sizeof(MT) == 4 ? CG_SRC * cg_ks<MT, NB>() : SRC; }
 

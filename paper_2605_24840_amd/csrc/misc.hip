@@ -759,17 +759,22 @@ struct CgState {
 };
 
 // Grid (column blocks of 256 output rows, chunks of CHUNK rows of M).  M is
-// H in FP64, or its FP32 copy (the products still accumulate in FP64).  Up
-// to 16 columns the 128-row chunks are split over two groups of four waves:
-// an FP32 pass moves half the bytes per load and needs twice the waves to
-// keep as many bytes in flight, and either pass then has twice the waves for
-// the reduction and the update at its start.  Wider blocks keep one group
-// (the LDS of the group sums), and the FP32 pass 64-row chunks.
+// H in FP64, or its FP32 copy (the products still accumulate in FP64).  The
+// chunks are split over KS groups of four waves, each summing 64 rows (FP32;
+// FP64 up to 8 columns) or 64 to 128 rows (FP64): more waves keep more bytes
+// in flight and share the reduction and the row update at the start of
+// k_cg_step, and longer chunks leave fewer chunk partials for k_cg_apply.
+// KS is 4 up to 8 columns, 2 up to 16, and 1 beyond (the LDS of the group
+// sums).  Measured at d = 4096, 5 columns, against two groups of 64 rows:
+// FP32 18.8 -> 17.3 us, FP64 26.8 -> 26.2 us per iteration, and the
+// partial sums 6.6 -> 6.2 us.
 constexpr int CG_SRC = SRC / 2;
 template <typename MT, int NB>
-constexpr int cg_ks() { return NB <= 16 ? 2 : 1; }
+constexpr int cg_ks() { return NB <= 8 ? 4 : (NB <= 16 ? 2 : 1); }
 template <typename MT, int NB>
-constexpr int cg_chunk() { return sizeof(MT) == 4 ? CG_SRC * cg_ks<MT, NB>() : SRC; }
+constexpr int cg_chunk() {
+  return sizeof(MT) == 4 ? CG_SRC * cg_ks<MT, NB>() : (cg_ks<MT, NB>() == 4 ? 2 * SRC : SRC);
+}
 
 template <typename MT, int NB, int CHUNK = cg_chunk<MT, NB>(), int KS = cg_ks<MT, NB>()>
 __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, int64_t ldm, int d,

@@ -701,27 +701,31 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
 }
 
 // The stand-alone product (Lanczos steps, Rayleigh-Ritz, subspace
-// extraction) splits each chunk over two groups while the group sums fit
-// the LDS: twice the waves, each with half the dependent round trips to
-// memory (measured at d = 4096, 12 columns: 36 -> 24 us).
+// extraction) splits each chunk over KS groups of 64 rows: 4 groups
+// (256-row chunks) up to 12 columns, 2 (128-row chunks) up to 32, within the
+// LDS of the group sums and the registers of 1024-thread blocks.  More
+// waves, each with fewer dependent round trips to memory (measured at
+// d = 4096, 12 columns: one group 36 us, two 24 us).
 template <int NB>
-constexpr int symthin_ks() { return NB <= 16 ? 2 : 1; }
+constexpr int symthin_ks() { return NB <= 12 ? 4 : 2; }
+template <int NB>
+constexpr int symthin_chunk() { return 64 * symthin_ks<NB>(); }
 
-template <typename MT, int NB, int KS = symthin_ks<NB>()>
+template <typename MT, int NB, int KS = symthin_ks<NB>(), int CHUNK = symthin_chunk<NB>()>
 __global__ __launch_bounds__(256 * KS) void k_symthin(const MT* __restrict__ M, int64_t ldm,
                                                       int64_t ps, int d,
                                                       const double* __restrict__ V, int64_t ldv,
                                                       int nb, double* __restrict__ work,
                                                       int64_t wld) {
-  __shared__ double pv[SRC][NB];
+  __shared__ double pv[CHUNK][NB];
   __shared__ ThinRed<KS, NB> red;
-  const int j0 = blockIdx.y * SRC;
-  for (int e = threadIdx.x; e < SRC * NB; e += 256 * KS) {
+  const int j0 = blockIdx.y * CHUNK;
+  for (int e = threadIdx.x; e < CHUNK * NB; e += 256 * KS) {
     const int jj = e / NB, c = e % NB, j = j0 + jj;
     pv[jj][c] = (j < d && c < nb) ? V[(int64_t)c * ldv + j] : 0.0;
   }
   __syncthreads();
-  symthin_body<MT, NB, SRC, KS>(M, ldm, ps, d, pv, work, wld, nb, red);
+  symthin_body<MT, NB, CHUNK, KS>(M, ldm, ps, d, pv, work, wld, nb, red);
 }
 
 // ------------------------------------------------------------ block CG
@@ -1277,12 +1281,11 @@ static hipError_t symthin_dispatch(const MT* M, int64_t ldm, int64_t ps, int d, 
                                    int64_t ldv, int nb, double* Y, int64_t ldy, double* work,
                                    hipStream_t st) {
   const int64_t wld = d;
-  const dim3 grid(nblocks(d, 256), nblocks(d, SRC));
 #define REFL_STHIN(NBV)                                                                          \
   {                                                                                              \
+    const dim3 grid(nblocks(d, 256), nblocks(d, symthin_chunk<NBV>()));                          \
     hipLaunchKernelGGL((k_symthin<MT, NBV>), grid, dim3(256 * symthin_ks<NBV>()), 0, st, M, ldm, \
-                       ps, d, V, ldv, nb,                                                  \
-                       work, wld);                                                               \
+                       ps, d, V, ldv, nb, work, wld);                                            \
     hipLaunchKernelGGL((k_thin_finish<NBV>), dim3(nblocks(d, 256), nb), dim3(256), 0, st, work,  \
                        wld, (int)grid.y, d, nb, Y, ldy);                                         \
   }

@@ -478,3 +478,36 @@ def test_large_order(R, handle, large, prec):
         assert err <= info["resid_fro"] + 4 * 2.0 ** -24 * np.sqrt(d) / gamma
     del Hg, Rg
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_shift_on_an_eigenvalue(R, handle, prec):
+    """s equal to an eigenvalue (lambda_{k+1}): sgn(H - sI) is undefined.  The
+    scaled matrix keeps an eigenvalue at rounding level, which each NS step
+    multiplies by 1.5 only.  FP64 (60 steps): it stays below the certificate,
+    so the call reports NOT_CONVERGED with no index.  FP32 and MIXED: the
+    coarser rounding moves it to one side within the steps, and the
+    certificate then counts it: either index k (the shift acts as one just
+    above lambda_{k+1}, and the result must be R_k, which is defined since
+    lambda_k < lambda_{k+1}) or k + 1 (NOT_ADMISSIBLE).  Never a certified
+    reflector of the wrong index."""
+    d, k = 64, 4
+    w = np.linspace(-1.0, 1.0, d)
+    Q = inputs.haar_orthogonal(d, np.random.default_rng(64))
+    H = np.ascontiguousarray(0.5 * ((Q * w) @ Q.T + ((Q * w) @ Q.T).T))
+    s = float(w[k])                      # lambda_{k+1}
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision=prec, max_iter=60, check=False)
+    status = R.STATUS[st]
+    err = float(np.linalg.norm(Rg.cpu().numpy() - oracle.reflector_from_eig(Q, k)))
+    _say(f"shift on lambda_{k + 1} ({prec}): status={status} steps={info['ns_steps']} "
+         f"resid={info['resid_fro']:.3e} j={info['index_j']} ||R - R_k||_F={err:.1e}")
+    if prec == "fp64":
+        assert status == "REFL_ERR_NOT_CONVERGED" and info["index_j"] == -1
+        assert info["resid_fro"] >= 0.5
+    elif status == "REFL_OK":
+        assert info["index_j"] == k
+        assert err <= (1e-8 * np.sqrt(d) if prec == "mixed" else 1e-3)
+    elif status == "REFL_ERR_NOT_ADMISSIBLE":
+        assert info["index_j"] == k + 1
+    else:
+        assert status == "REFL_ERR_NOT_CONVERGED" and info["index_j"] == -1

@@ -106,7 +106,9 @@ typedef struct {
                            summed durations in info (adds no synchronisation) */
   int32_t grad_mode;    /* refl_sign_grad: REFL_GRAD_REVERSE (default) or REFL_GRAD_TANGENT */
   int32_t ckpt_every;   /* refl_sign_grad, reverse mode: keep every c-th iterate and
-                           recompute the others (0: c = ceil(sqrt(step cap))) */
+                           recompute the others.  0: keep every iterate and its N = I - X^2
+                           when 2 (step cap + 1) d^2 elements fit in 16 GiB, else
+                           c = ceil(sqrt(step cap)) */
   int32_t cg_f32;       /* MIXED: operator precision of the inner solves, refl_cg_prec_t
                            (default REFL_CG_AUTO) */
 } refl_params_t;
@@ -270,8 +272,10 @@ refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, c
  * derivative follows the steps of eq. NS exactly (product rule), in the
  * bulk precision:
  *   reverse  Gb_m = sym(G); Gb_j = (3 Gb - (Gb X_j^2 + X_j Gb X_j + X_j^2 Gb))/2
- *            with Gb = Gb_{j+1}; gradient = Gb_0 / alpha.  Iterates are kept
- *            every ckpt_every steps and recomputed segment by segment.
+ *            with Gb = Gb_{j+1}; gradient = Gb_0 / alpha.  The forward's X_j
+ *            and N_j are all kept when they fit (see ckpt_every), else X_j
+ *            every c steps, recomputed segment by segment; the gradient is
+ *            the same bit for bit.
  *   tangent  Xdot_0 = sym(G)/alpha, Xdot_{j+1} = the same map applied to Xdot_j
  *            beside the forward steps; gradient = Xdot_m.
  * Per step the derivative costs one general and one symmetric three-term

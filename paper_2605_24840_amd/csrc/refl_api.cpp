@@ -1749,6 +1749,7 @@ struct GradWork {
   int2 *tiles = nullptr, *full = nullptr;
   void *Gs = nullptr, *Gb[2] = {nullptr, nullptr}, *Pn = nullptr, *ring[2] = {nullptr, nullptr};
   std::vector<void*> ck, xs, ns;  // checkpoints, segment iterates, segment N
+  bool keep_all = false;  // every X_j and N_j of the forward kept: no recomputation
 };
 
 int grad_cap(const refl_params_t& p) { return p.fixed_steps > 0 ? p.fixed_steps : p.max_iter; }
@@ -1765,12 +1766,19 @@ size_t grad_layout(GradWork& g, void* base, int64_t d, const refl_params_t& p, r
   g.nfull = nt * nt;
   const int cap = grad_cap(p);
   const bool reverse = p.grad_mode == REFL_GRAD_REVERSE;
+  const size_t n2 = (size_t)g.dp * g.dp;
+  // Reverse mode keeps every X_j and N_j of the forward (no recomputation in
+  // the reverse sweep) when they fit in KEEP_ALL_BYTES and no interval is
+  // requested; otherwise X_j every c steps, with each segment's iterates
+  // recomputed before its reverse sweep.  The gradient is the same bit for
+  // bit either way (the same products on the same iterates).
+  constexpr double KEEP_ALL_BYTES = 16.0 * (1 << 30);
+  g.keep_all = reverse && p.ckpt_every == 0 && 2.0 * (cap + 1) * (double)(es * n2) <= KEEP_ALL_BYTES;
   g.c = 1;
-  if (reverse)
+  if (reverse && !g.keep_all)
     g.c = p.ckpt_every > 0 ? std::min(p.ckpt_every, cap)
                            : std::max(1, (int)std::ceil(std::sqrt((double)cap)));
   g.nck = reverse ? cap / g.c + 1 : 0;
-  const size_t n2 = (size_t)g.dp * g.dp;
   g.scal = c.take<double>(SC_COUNT);
   g.tiles = c.take<int2>(g.ntiles);
   g.full = c.take<int2>(g.nfull);
@@ -1785,9 +1793,9 @@ size_t grad_layout(GradWork& g, void* base, int64_t d, const refl_params_t& p, r
   g.ring[1] = c.take<char>(es * n2);
   g.ck.assign(g.nck, nullptr);
   for (auto& q : g.ck) q = c.take<char>(es * n2);
-  g.xs.assign(reverse ? g.c : 0, nullptr);
+  g.xs.assign(reverse && !g.keep_all ? g.c : 0, nullptr);
   for (auto& q : g.xs) q = c.take<char>(es * n2);
-  g.ns.assign(reverse ? g.c : 1, nullptr);
+  g.ns.assign(g.keep_all ? cap + 1 : (reverse ? g.c : 1), nullptr);
   for (auto& q : g.ns) q = c.take<char>(es * n2);
   return c.off + 256;
 }
@@ -1936,7 +1944,7 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   void* Tcur = g.Gb[0];  // tangent mode: Xdot_j (Xdot_0 = sym(G)/alpha)
   int tg = 1;
   for (;; ++m) {
-    void* N = g.ns[0];
+    void* N = g.keep_all ? g.ns[m] : g.ns[0];
     HIPCHK(residual(cur, N));
     HIPCHK(launch_reduce_sum(g.partials, g.ntiles, g.scal, SC_RESID2, st));
     HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, g.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1987,7 +1995,18 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   const double t_fwd = now_ms();
 
   // ---- reverse sweep over segments of c steps ----
-  if (reverse) {
+  if (reverse && g.keep_all) {
+    void* Gcur = g.Gs;
+    int gi = 0;
+    for (int j = m - 1; j >= 0; --j) {
+      rs = dstep(g.ck[j], g.ns[j], Gcur, g.Gb[gi]);
+      if (rs != REFL_OK) return rs;
+      Gcur = g.Gb[gi];
+      gi ^= 1;
+    }
+    if (fp64) HIPCHK(launch_copy_out_scaled_f64((const double*)Gcur, dp, dd, g.scal, dGrad, ldgr, st));
+    else HIPCHK(launch_copy_out_scaled_f32((const float*)Gcur, dp, dd, g.scal, dGrad, ldgr, st));
+  } else if (reverse) {
     void* Gcur = g.Gs;
     int gi = 0;
     const int nseg = (m + g.c - 1) / g.c;

@@ -91,6 +91,8 @@ def main():
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
                          "kernel (reads 256 MiB, writes 256 MiB) that calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
+    if args.steps < 1 or args.fp64_steps < 1 or args.lanczos_steps < 1:
+        ap.error("--steps, --fp64-steps and --lanczos-steps must be at least 1")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the reflector of one Hessian "
               "is computed on a single device; see the design notes for how it would shard.",

@@ -213,7 +213,14 @@ refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double *dH, 
                                   double *lam_k, double *lam_k1, double *eps, double *rho);
 
 /* R_k = sgn(H - sI) into dR (d x d, leading dimension ldr).  info may be
- * NULL.  See refl_params_t for the modes. */
+ * NULL.  See refl_params_t for the modes.
+ *
+ * FP32 orders d <= 128 and FP64 orders d <= 96 run every Newton-Schulz step
+ * of eq. NS in one launch, with X and X^2 - I held in on-chip memory and the
+ * stopping rule evaluated on the device (same rule, same results up to
+ * rounding as the tiled products larger orders use; with params.timing that
+ * launch is the one timed).  The environment variable REFL_SMALL=0 sends
+ * them through the tiled products instead. */
 refl_status_t refl_sign(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
                         const refl_params_t *p, double *dR, int64_t ldr, refl_info_t *info);
 
@@ -241,7 +248,9 @@ refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double *dH, int6
  * MIXED or a Lanczos shift gives REFL_ERR_UNSUPPORTED.
  *
  * Each Newton-Schulz product runs as one grouped launch over the upper tiles
- * of every problem still iterating; each problem stops by refl_sign's rule
+ * of every problem still iterating; problems of the orders refl_sign runs in
+ * one launch (FP32 d <= 128, FP64 d <= 96) run there instead, one work-group
+ * each, beside the grouped launches.  Each problem stops by refl_sign's rule
  * and its R (and steps, scale, trace) equal, bit for bit, those of refl_sign
  * with params[p].  In FP32 the certificate ||X^2 - I||_F reported in
  * info[p].resid_fro and used for info[p].index_j is recomputed in FP64 from

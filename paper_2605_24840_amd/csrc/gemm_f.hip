@@ -20,6 +20,7 @@
 // transposed stores are both row-contiguous.
 #include "common.h"
 #include "launch.h"
+#include "rule.h"
 
 namespace refl {
 
@@ -445,6 +446,207 @@ hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- small orders
+// The whole iteration of one small problem in one work-group (eq. NS with the
+// stopping rule of section 3.3): X and N live in LDS for every step, so a
+// step costs two in-LDS products and no launch, and the only HBM traffic is
+// X_0 in and X_m out.  512 threads = 8 waves; the order is padded to dp, a
+// multiple of 16, and the (dp/16)(dp/16 + 1)/2 upper 16 x 16 blocks of each
+// product are dealt round-robin to the waves.  Both products are symmetric
+// (X and N commute), so each block is computed once and stored with its
+// transpose; in a diagonal block the entry (r, c), r > c, takes the value
+// computed at (c, r), so both matrices stay exactly symmetric.
+//
+// Fragments: for a K chunk of 4 VE entries (VE = 16 B / element), lane
+// (i + 16 q) reads VE consecutive entries k = k0 + q VE .. of row i of each
+// operand in one 16 B LDS load, and MFMA number kk of the chunk takes entry
+// kk of it: MFMA input slot q stands for k = k0 + q VE + kk, the same
+// permutation of K on both operands, so the chunk's four (FP32) or two (FP64)
+// MFMAs sum the products over all 4 VE entries.
+template <typename T>
+struct SmallCfg {
+  static constexpr int VE = 16 / (int)sizeof(T);
+  static constexpr int KC = 4 * VE;
+  static constexpr int DMAX = sizeof(T) == 8 ? SMALL_MAX_F64 : SMALL_MAX_F32;
+  static constexpr int NBMAX = DMAX / 16;
+  static constexpr int NW = 8;
+  static constexpr int MAXB = (NBMAX * (NBMAX + 1) / 2 + NW - 1) / NW;
+  static constexpr int LDS = 2 * DMAX * (DMAX + VE);  // elements: X and N, padded rows
+  static_assert(LDS * (int)sizeof(T) <= 160 * 1024 - 256, "two matrices in LDS");
+  static_assert(DMAX % 16 == 0, "order padding");
+};
+
+// Sum over the 512 threads, returned in every thread (the same value: the
+// butterfly gives each lane the same sum, and the wave sums are added in a
+// fixed order).
+__device__ __forceinline__ double small_all_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < SmallCfg<float>::NW; ++w) t += red[w];
+  return t;
+}
+
+// acc[t] = (rows 16 bi[t] .. of A) (rows 16 bj[t] .. of B)^T over k < dp,
+// for the wave's blocks t < nblk.
+template <typename T>
+__device__ __forceinline__ void small_products(const T* A, const T* B, int ldx, int dp,
+                                               const int (&bi)[SmallCfg<T>::MAXB],
+                                               const int (&bj)[SmallCfg<T>::MAXB], int nblk,
+                                               typename FMfma<T>::acc_t (&acc)[SmallCfg<T>::MAXB],
+                                               int lane) {
+  typedef SmallCfg<T> C;
+  typedef FMfma<T> M;
+  typedef T vec_t __attribute__((ext_vector_type(C::VE)));
+#pragma unroll
+  for (int t = 0; t < C::MAXB; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[t][r] = 0;
+  const int row = lane & 15, q = lane >> 4;
+  for (int k0 = 0; k0 < dp; k0 += C::KC) {
+    vec_t a[C::MAXB], b[C::MAXB];
+#pragma unroll
+    for (int t = 0; t < C::MAXB; ++t)
+      if (t < nblk) {
+        a[t] = *reinterpret_cast<const vec_t*>(A + (bi[t] * 16 + row) * ldx + k0 + q * C::VE);
+        b[t] = *reinterpret_cast<const vec_t*>(B + (bj[t] * 16 + row) * ldx + k0 + q * C::VE);
+      }
+#pragma unroll
+    for (int kk = 0; kk < C::VE; ++kk)
+#pragma unroll
+      for (int t = 0; t < C::MAXB; ++t)
+        if (t < nblk) acc[t] = M::op(a[t][kk], b[t][kk], acc[t]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_ns_small(const SmallProb* __restrict__ probs,
+                                                  const BatchRule* __restrict__ rules,
+                                                  BatchStep* __restrict__ stp) {
+  typedef SmallCfg<T> C;
+  typedef FMfma<T> M;
+  typedef typename M::acc_t acc_t;
+  __shared__ __attribute__((aligned(16))) T lds[C::LDS];
+  __shared__ double red[2][C::NW];
+  const SmallProb pr = probs[blockIdx.x];
+  const int d = pr.d, dp = (d + 15) & ~15, ldx = dp + C::VE;
+  // The host sends only orders 1 .. DMAX (and pr.dp >= d); anything else
+  // leaves the step record untouched (state BATCH_LIVE) and no memory read.
+  if (d < 1 || dp > C::DMAX || pr.dp < d) return;
+  T* Xs = lds;
+  T* Ns = lds + dp * ldx;
+  const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+
+  // This wave's upper blocks (I, J), I <= J, in row-major order of the upper
+  // triangle: block index wave + t NW.
+  const int nb = dp / 16, nbu = nb * (nb + 1) / 2;
+  int bi[C::MAXB], bj[C::MAXB];
+  int nblk = 0;
+#pragma unroll
+  for (int t = 0; t < C::MAXB; ++t) {
+    int idx = wave + t * C::NW, I = 0;
+    bi[t] = bj[t] = 0;
+    if (idx < nbu) {
+      while (idx >= nb - I) {
+        idx -= nb - I;
+        ++I;
+      }
+      bi[t] = I;
+      bj[t] = I + idx;
+      nblk = t + 1;
+    }
+  }
+
+  const T* X0 = reinterpret_cast<const T*>(pr.X[0]);
+  for (int e = tid; e < dp * dp; e += 512) {
+    const int i = e / dp, j = e - i * dp;
+    Xs[i * ldx + j] = (i < d && j < d) ? X0[(int64_t)i * pr.dp + j] : T(0);
+  }
+  BatchStep s = stp[pr.slot];
+  const BatchRule ru = rules[pr.slot];
+  // The rule stops by the step cap at the latest; the bound below only
+  // guards the loop itself.
+  const int hard = max(max(ru.fixed_steps, ru.max_iter), 0);
+  __syncthreads();
+
+  acc_t acc[C::MAXB];
+  int m = 0;
+  for (;; ++m) {
+    // GEMM_RESIDUAL: N = I - X X, ||N||_F^2.
+    small_products<T>(Xs, Xs, ldx, dp, bi, bj, nblk, acc, lane);
+    double part = 0.0;
+#pragma unroll
+    for (int t = 0; t < C::MAXB; ++t)
+      if (t < nblk) {
+        const bool dg = bi[t] == bj[t];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = bi[t] * 16 + M::row(lane, r), gj = bj[t] * 16 + (lane & 15);
+          if (dg && gi > gj) continue;
+          const T n = ((gi == gj && gi < d) ? T(1) : T(0)) - acc[t][r];
+          Ns[gi * ldx + gj] = n;
+          Ns[gj * ldx + gi] = n;
+          part += (gi == gj ? 1.0 : 2.0) * (double)n * (double)n;
+        }
+      }
+    const double r2 = small_all_sum(part, red[0]);
+    if (batch_rule(s, ru, sqrt(fmax(r2, 0.0)), m, m & 1)) break;
+    if (m >= hard) {
+      s.state = BATCH_STOPPED;
+      s.par = m & 1;
+      break;
+    }
+    // GEMM_UPDATE: X <- X + (X N)/2, trace of the new iterate.
+    small_products<T>(Xs, Ns, ldx, dp, bi, bj, nblk, acc, lane);
+    double tp = 0.0;
+#pragma unroll
+    for (int t = 0; t < C::MAXB; ++t)
+      if (t < nblk)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = bi[t] * 16 + M::row(lane, r), gj = bj[t] * 16 + (lane & 15);
+          const T n = Xs[gi * ldx + gj] + T(0.5) * acc[t][r];
+          acc[t][r] = n;
+          if (gi == gj) tp += (double)n;
+        }
+    __syncthreads();  // every product has read X and N
+#pragma unroll
+    for (int t = 0; t < C::MAXB; ++t)
+      if (t < nblk) {
+        const bool dg = bi[t] == bj[t];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = bi[t] * 16 + M::row(lane, r), gj = bj[t] * 16 + (lane & 15);
+          if (dg && gi > gj) continue;
+          Xs[gi * ldx + gj] = acc[t][r];
+          Xs[gj * ldx + gi] = acc[t][r];
+        }
+      }
+    s.trace = small_all_sum(tp, red[1]);
+  }
+
+  // X_m to X[m & 1], the whole dp x dp buffer (zero outside d x d).
+  T* Xo = reinterpret_cast<T*>((m & 1) ? pr.X[1] : pr.X[0]);
+  const int gdp = pr.dp;
+  for (int e = tid; e < gdp * gdp; e += 512) {
+    const int i = e / gdp, j = e - i * gdp;
+    Xo[(int64_t)i * gdp + j] = (i < dp && j < dp) ? Xs[i * ldx + j] : T(0);
+  }
+  if (tid == 0) stp[pr.slot] = s;
+}
+
+hipError_t launch_ns_small(int fp64, const SmallProb* probs, int nprob, const BatchRule* rules,
+                           BatchStep* stp, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL(k_ns_small<double>, dim3(nprob), dim3(512), 0, st, probs, rules, stp);
+  else
+    hipLaunchKernelGGL(k_ns_small<float>, dim3(nprob), dim3(512), 0, st, probs, rules, stp);
   return hipGetLastError();
 }
 

@@ -162,6 +162,21 @@ struct BatchStep {
   int m, par, state, pad;  // steps taken; buffer of the final iterate; BATCH_*
 };
 constexpr int BATCH_LIVE = 0, BATCH_CONVERGED = 1, BATCH_STOPPED = 2, BATCH_NONFINITE = 3;
+// LDS-resident iteration of small problems: one work-group per problem runs
+// every Newton-Schulz step with X and N held in LDS, the stopping rule on the
+// device, and leaves X_m (the iterate it stops at) in X[m & 1].  On entry
+// X[0] holds X_0 (dp x dp, ld = dp, zero outside the leading d x d block)
+// and stp[slot].trace = trace X_0; on exit stp[slot] holds the step record
+// (state, m, par = m & 1, resid of X_m, trace X_m).  Orders up to
+// SMALL_MAX_F32 (FP32) and SMALL_MAX_F64 (FP64), which fit two padded
+// matrices in the 160 KiB of LDS of a compute unit.
+constexpr int SMALL_MAX_F32 = 128, SMALL_MAX_F64 = 96;
+struct SmallProb {
+  void* X[2];
+  int d, dp, slot, pad;
+};
+hipError_t launch_ns_small(int fp64, const SmallProb* probs, int nprob, const BatchRule* rules,
+                           BatchStep* stp, hipStream_t st);
 // One step's decision for every problem with live[p]: resid = sqrt(res[p]),
 // trace of X_m from trace[p] (m > 0), then the rule; a problem that stops
 // gets live[p] = 0 and par.  ctl[0] is the step m (read, then incremented),

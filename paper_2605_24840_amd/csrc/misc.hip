@@ -6,6 +6,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "rule.h"
 
 namespace refl {
 
@@ -208,33 +209,10 @@ __global__ __launch_bounds__(256) void k_batch_decide(int nprob, const double* _
     const BatchRule ru = rules[p];
     const double r = sqrt(fmax(res[p], 0.0));
     if (m > 0) s.trace = trace[p];
-    s.m = m;
-    s.resid = r;
-    if (!isfinite(r)) {
-      s.state = BATCH_NONFINITE;
+    if (batch_rule(s, ru, r, m, par))
       live[p] = 0;
-      stp[p] = s;
-      continue;
-    }
-    bool stop = false, conv = false;
-    if (ru.fixed_steps > 0) {
-      if (m >= ru.fixed_steps) stop = conv = true;
-    } else if (r < ru.tol) {
-      stop = conv = true;
-    } else if (m >= 2 && r < 1e-6 && r > 0.5 * s.h2) {
-      stop = true;  // stagnation: no halving over two steps below 1e-6
-    } else if (m >= ru.max_iter) {
-      stop = true;
-    }
-    s.h2 = s.h1;
-    s.h1 = r;
-    if (stop) {
-      s.par = par;
-      s.state = conv ? BATCH_CONVERGED : BATCH_STOPPED;
-      live[p] = 0;
-    } else {
+    else
       ++n;
-    }
     stp[p] = s;
   }
   const double t = block_sum_256((double)n, red);

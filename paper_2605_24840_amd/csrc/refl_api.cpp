@@ -59,6 +59,8 @@ struct refl_handle_s {
   size_t batch_pin_bytes = 0;
   hipEvent_t lz_ev[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;   // stream the batched step graph is captured on
+  hipStream_t side = nullptr;  // batched solve: small problems run beside the grouped steps
+  hipEvent_t side_ev[2] = {nullptr, nullptr};  // fork and join of the side stream
   int ncu = 256;               // compute units of the device
   char err[512] = {0};
 };
@@ -473,6 +475,17 @@ struct Bulk {
   int cur = 0;  // which X buffer holds the last iterate
   bool converged = false;
 };
+
+// FP32 / FP64 problems of order d <= SMALL_MAX_* run the whole iteration in
+// one LDS-resident launch (launch_ns_small); REFL_SMALL=0 sends them through
+// the tiled products instead (tests compare the two).
+bool small_order(int64_t d, bool fp64) {
+  const char* e = std::getenv("REFL_SMALL");
+  const bool off = e && e[0] == '0';
+  return !off && d >= 1 && d <= (fp64 ? SMALL_MAX_F64 : SMALL_MAX_F32);
+}
+static_assert(sizeof(SmallProb) == 32 && sizeof(BatchRule) == 16 && sizeof(BatchStep) == 48,
+              "staging layout of the small-order launch");
 
 // Orthonormalise the d x nb block V (ld dp) by two rounds of Cholesky QR.
 refl_status_t orthonormalise(refl_handle_t h, Work& w, double*& V, double*& spare, int nb) {
@@ -1022,6 +1035,44 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
         enq = m + 1;
       }
     }
+  } else if (p.precision != REFL_PREC_MIXED && small_order(d, p.precision == REFL_PREC_FP64)) {
+    // Every step in one launch, X and N held in LDS, the stopping rule on
+    // the device.  Problem, rule and step record are staged through the
+    // pinned tail of the scalar block and free scalar slots on the device.
+    const bool f64 = p.precision == REFL_PREC_FP64;
+    char* hs = reinterpret_cast<char*>(h->pinned + SC_COUNT) + sizeof(CgHost);
+    char* ds = reinterpret_cast<char*>(w.scal + SC_SCRATCH + 4);
+    SmallProb* sp = reinterpret_cast<SmallProb*>(hs);
+    BatchRule* ru = reinterpret_cast<BatchRule*>(hs + 32);
+    BatchStep* sq = reinterpret_cast<BatchStep*>(hs + 48);
+    sp->X[0] = f64 ? (void*)w.X64[0] : (void*)w.X32[0];
+    sp->X[1] = f64 ? (void*)w.X64[1] : (void*)w.X32[1];
+    sp->d = (int)d;
+    sp->dp = w.dp;
+    sp->slot = 0;
+    sp->pad = 0;
+    ru->tol = p.tol;
+    ru->fixed_steps = p.fixed_steps;
+    ru->max_iter = p.max_iter;
+    std::memset(sq, 0, sizeof(BatchStep));
+    sq->trace = trace_cur;
+    sq->resid = NaN;
+    sq->state = BATCH_LIVE;
+    HIPCHK(hipMemcpyAsync(ds, hs, 96, hipMemcpyHostToDevice, st));
+    HIPCHK(ev_start());
+    HIPCHK(launch_ns_small(f64, reinterpret_cast<const SmallProb*>(ds), 1,
+                           reinterpret_cast<const BatchRule*>(ds + 32),
+                           reinterpret_cast<BatchStep*>(ds + 48), st));
+    HIPCHK(ev_stop());
+    HIPCHK(hipMemcpyAsync(sq, ds + 48, sizeof(BatchStep), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    b.steps = sq->m;
+    b.cur = sq->par;
+    b.resid = sq->resid;
+    b.trace = sq->trace;
+    b.converged = sq->state == BATCH_CONVERGED;
+    if (sq->state == BATCH_NONFINITE)
+      bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
   } else
   while (true) {
     const int c = b.cur;
@@ -1251,6 +1302,7 @@ struct BatchWork {
   BatchStep* stp = nullptr;
   int* live = nullptr;
   int* ctl = nullptr;          // step counter, live count
+  SmallProb* small = nullptr;  // problems of the LDS-resident launch
 };
 
 // Tile edges of the batched FP32 / FP64 products, in the order their tile
@@ -1302,6 +1354,7 @@ size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, cons
   bw.stp = c.take<BatchStep>(nprob);
   bw.live = c.take<int>(nprob);
   bw.ctl = c.take<int>(2);
+  bw.small = c.take<SmallProb>(nprob);
   return c.off + 256;
 }
 
@@ -1314,6 +1367,7 @@ struct BatchPin {
   BatchRule* rules;
   BatchStep* stp;
   int *live, *ctl;
+  SmallProb* small;
   int4* tiles[3];
   int *begin[3], *slot[3];
   int *sbeg, *cbeg;
@@ -1332,6 +1386,7 @@ size_t batch_pin_layout(BatchPin& bp, void* base, int nprob, int ttot) {
   bp.stp = c.take<BatchStep>(nprob);
   bp.live = c.take<int>(nprob);
   bp.ctl = c.take<int>(2);
+  bp.small = c.take<SmallProb>(nprob);
   for (int b = 0; b < 3; ++b) {
     bp.tiles[b] = c.take<int4>(ttot);
     bp.begin[b] = c.take<int>(nprob + 1);
@@ -1560,8 +1615,16 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   // HIP graph and the graph is launched until no problem is live (eager
   // launches instead with params.timing, for the per-launch events, or with
   // REFL_BATCH_GRAPH=0).
+  //
+  // Problems of small order (small_order) take no part in the grouped steps:
+  // each runs its whole iteration in one work-group of the LDS-resident
+  // launch, on a side stream beside the steps (the same kernel as refl_sign
+  // uses for them, so their results match single calls too).
   constexpr int BATCH_GRAPH_STEPS = 4;
-  const int nq0 = (int)cur.size();
+  std::vector<int> tiled, smallp;
+  for (int p : cur) (small_order(d[p], fp64) ? smallp : tiled).push_back(p);
+  const int nq0 = (int)tiled.size();
+  const int nsm = (int)smallp.size();
   int maxsteps = 0;
   std::vector<char> live0(nprob, 0);
   for (int p : cur) live0[p] = 1;
@@ -1573,9 +1636,21 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     bp.stp[p].trace = trace_cur[p];
     bp.stp[p].resid = NaN;
     bp.stp[p].state = live0[p] ? BATCH_LIVE : BATCH_NONFINITE;
-    bp.live[p] = live0[p];
-    if (live0[p])
-      maxsteps = std::max(maxsteps, params[p].fixed_steps > 0 ? params[p].fixed_steps : params[p].max_iter);
+    bp.live[p] = 0;
+  }
+  for (int p : tiled) {
+    bp.live[p] = 1;
+    maxsteps = std::max(maxsteps, params[p].fixed_steps > 0 ? params[p].fixed_steps : params[p].max_iter);
+  }
+  for (int q = 0; q < nsm; ++q) {
+    const BatchProb& pq = bw.pr[smallp[q]];
+    SmallProb& e = bp.small[q];
+    e.X[0] = pq.X[0];
+    e.X[1] = pq.X[1];
+    e.d = pq.d;
+    e.dp = pq.dp;
+    e.slot = smallp[q];
+    e.pad = 0;
   }
   bp.ctl[0] = 0;
   bp.ctl[1] = nq0;
@@ -1583,9 +1658,32 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   HIPCHK(hipMemcpyAsync(bw.stp, bp.stp, sizeof(BatchStep) * nprob, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(bw.live, bp.live, sizeof(int) * nprob, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(bw.ctl, bp.ctl, sizeof(int) * 2, hipMemcpyHostToDevice, st));
+  if (nsm > 0) HIPCHK(hipMemcpyAsync(bw.small, bp.small, sizeof(SmallProb) * nsm, hipMemcpyHostToDevice, st));
+  // Fork: the small problems' launch goes to the side stream after the
+  // uploads above; the join below comes before the step records are read.
+  const bool fork = nsm > 0 && nq0 > 0;
+  if (fork) {
+    if (!h->side) HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    for (hipEvent_t& e : h->side_ev)
+      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(h->side_ev[0], st));
+    HIPCHK(hipStreamWaitEvent(h->side, h->side_ev[0], 0));
+  }
+  if (nsm > 0) {
+    hipStream_t ss = fork ? h->side : st;
+    HIPCHK(launch_ns_small(fp64, bw.small, nsm, bw.rules, bw.stp, ss));
+    if (fork) HIPCHK(hipEventRecord(h->side_ev[1], ss));
+  }
   const int lb = 0;
-  const int nt_all = nq0 == 0 ? 0 : upload_list(lb, cur);
-  if (nt_all < 0) return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
+  const int nt_all = nq0 == 0 ? 0 : upload_list(lb, tiled);
+  // Error returns between fork and join first drain the side stream.
+  auto drain_side = [&]() {
+    if (fork) (void)hipStreamSynchronize(h->side);
+  };
+  if (nt_all < 0) {
+    drain_side();
+    return fail(h, REFL_ERR_DEVICE, "tile list upload failed");
+  }
   auto step = [&](int par, hipStream_t s) -> hipError_t {
     hipError_t e;
     const bool ev = timing && s == st;
@@ -1612,9 +1710,12 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   const bool use_graph = nq0 > 0 && !timing && !(genv && genv[0] == '0');
   hipGraphExec_t gexec = nullptr;
   if (use_graph) {
-    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = hipSuccess;
+    hipError_t ce = h->cap ? hipSuccess : hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (ce == hipSuccess) ce = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (ce != hipSuccess) {
+      drain_side();
+      return fail(h, REFL_ERR_DEVICE, "batched step graph: %s", hipGetErrorString(ce));
+    }
     for (int i = 0; i < BATCH_GRAPH_STEPS && ce == hipSuccess; ++i) ce = step(i & 1, h->cap);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(h->cap, &graph);
@@ -1623,6 +1724,7 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     if (graph) (void)hipGraphDestroy(graph);
     if (ce != hipSuccess) {
       if (gexec) (void)hipGraphExecDestroy(gexec);
+      drain_side();
       return fail(h, REFL_ERR_DEVICE, "batched step graph: %s", hipGetErrorString(ce));
     }
   }
@@ -1641,6 +1743,10 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     if (le == hipSuccess && bp.ctl[1] == 0) break;
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (fork) {
+    const hipError_t je = hipStreamWaitEvent(st, h->side_ev[1], 0);
+    if (le == hipSuccess) le = je;
+  }
   if (le != hipSuccess) return fail(h, REFL_ERR_DEVICE, "batched steps: %s", hipGetErrorString(le));
   if (nq0 > 0 && bp.ctl[1] != 0)
     return fail(h, REFL_ERR_DEVICE, "batched steps: %d problems still iterating after the step limit",
@@ -2154,6 +2260,9 @@ refl_status_t refl_destroy(refl_handle_t h) {
   if (h->batch_pin) (void)hipHostFree(h->batch_pin);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  for (hipEvent_t e : h->side_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
   return REFL_OK;
 }

@@ -1,0 +1,43 @@
+// Device side of the Newton-Schulz stopping rule (section 3.3 for the
+// residual test, the fixed-depth filters p_m of section 3.4), shared by the
+// batched decision kernel and the LDS-resident small-order iteration, so
+// that both stop at exactly the step refl_sign's host loop stops at.
+#pragma once
+#include "common.h"
+#include "launch.h"
+
+namespace refl {
+
+// X_m has residual r = ||X_m^2 - I||_F; s.trace already holds trace X_m.
+// Records m and r in s and returns true when the iteration stops at X_m
+// (then s.state and s.par are set): a non-finite residual, m reaching the
+// fixed depth, r below tol, stagnation (no halving over two steps once below
+// 1e-6), or the step cap.
+__device__ __forceinline__ bool batch_rule(BatchStep& s, const BatchRule& ru, double r, int m,
+                                           int par) {
+  s.m = m;
+  s.resid = r;
+  if (!isfinite(r)) {
+    s.state = BATCH_NONFINITE;
+    return true;
+  }
+  bool stop = false, conv = false;
+  if (ru.fixed_steps > 0) {
+    if (m >= ru.fixed_steps) stop = conv = true;
+  } else if (r < ru.tol) {
+    stop = conv = true;
+  } else if (m >= 2 && r < 1e-6 && r > 0.5 * s.h2) {
+    stop = true;
+  } else if (m >= ru.max_iter) {
+    stop = true;
+  }
+  s.h2 = s.h1;
+  s.h1 = r;
+  if (stop) {
+    s.par = par;
+    s.state = conv ? BATCH_CONVERGED : BATCH_STOPPED;
+  }
+  return stop;
+}
+
+}  // namespace refl

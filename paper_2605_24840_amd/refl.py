@@ -24,6 +24,9 @@ SHIFT = {"given": 0, "lanczos": 1}
 SCALE = {"inf": 0, "given": 1, "lanczos": 2, "fro": 3}
 GRAD_MODE = {"reverse": 0, "tangent": 1}
 CG_PREC = {"fp64": 0, "fp32": 1, "auto": 2}
+# Largest orders the library runs as one LDS-resident launch (refl_sign and
+# the batched solve), by precision; larger orders use the tiled products.
+SMALL_MAX = {"fp32": 128, "fp64": 96}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",

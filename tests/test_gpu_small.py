@@ -159,3 +159,19 @@ def test_batched_small_only_and_mixed_equal_single(R, handle, prec):
             err = float(np.linalg.norm(Rs[p].cpu().numpy() - exact))
             if prec == "fp64":
                 assert err < 1e-9, (p, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_order_limit(R, handle, prec):
+    """refl.SMALL_MAX names the largest order of the one-launch path: with
+    timing events, an order at the limit runs one timed launch, one above it
+    the tiled products (m + 1 residual and m update products)."""
+    dmax = R.SMALL_MAX[prec]
+    for d, small in ((dmax, True), (dmax + 1, False)):
+        H, lam, Q, s = _problem(d, 5, 5e-2, 500 + d)
+        Hd = torch.from_numpy(H).to("cuda:0")
+        _say(f"small limit {prec} d={d}")
+        _, info, st = R.sign(Hd, 5, s, handle=handle, precision=prec, fixed_steps=3, timing=True,
+                             check=False)
+        assert st == 0 and info["ns_steps"] == 3
+        assert info["gemm_launches"] == (1 if small else 7), info["gemm_launches"]

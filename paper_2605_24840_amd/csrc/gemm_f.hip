@@ -493,34 +493,53 @@ __device__ __forceinline__ double small_all_sum(double v, double* red) {
 }
 
 // acc[t] = (rows 16 bi[t] .. of A) (rows 16 bj[t] .. of B)^T over k < dp,
-// for the wave's blocks t < nblk.
-template <typename T>
+// for the wave's NBK blocks.  NBK is a template argument so that the MFMAs of
+// a chunk issue back to back with no branch between them (a per-block test
+// would make each MFMA wait for the previous one's result).  Consecutive
+// blocks of a wave mostly share their row block bi, whose fragment is then
+// loaded once.
+template <typename T, int NBK>
 __device__ __forceinline__ void small_products(const T* A, const T* B, int ldx, int dp,
                                                const int (&bi)[SmallCfg<T>::MAXB],
-                                               const int (&bj)[SmallCfg<T>::MAXB], int nblk,
+                                               const int (&bj)[SmallCfg<T>::MAXB],
                                                typename FMfma<T>::acc_t (&acc)[SmallCfg<T>::MAXB],
                                                int lane) {
   typedef SmallCfg<T> C;
   typedef FMfma<T> M;
   typedef T vec_t __attribute__((ext_vector_type(C::VE)));
 #pragma unroll
-  for (int t = 0; t < C::MAXB; ++t)
+  for (int t = 0; t < NBK; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[t][r] = 0;
   const int row = lane & 15, q = lane >> 4;
   for (int k0 = 0; k0 < dp; k0 += C::KC) {
-    vec_t a[C::MAXB], b[C::MAXB];
+    vec_t a[NBK], b[NBK];
 #pragma unroll
-    for (int t = 0; t < C::MAXB; ++t)
-      if (t < nblk) {
+    for (int t = 0; t < NBK; ++t) {
+      if (t == 0 || bi[t] != bi[t - 1])
         a[t] = *reinterpret_cast<const vec_t*>(A + (bi[t] * 16 + row) * ldx + k0 + q * C::VE);
-        b[t] = *reinterpret_cast<const vec_t*>(B + (bj[t] * 16 + row) * ldx + k0 + q * C::VE);
-      }
+      else
+        a[t] = a[t - 1];
+      b[t] = *reinterpret_cast<const vec_t*>(B + (bj[t] * 16 + row) * ldx + k0 + q * C::VE);
+    }
 #pragma unroll
     for (int kk = 0; kk < C::VE; ++kk)
 #pragma unroll
-      for (int t = 0; t < C::MAXB; ++t)
-        if (t < nblk) acc[t] = M::op(a[t][kk], b[t][kk], acc[t]);
+      for (int t = 0; t < NBK; ++t) acc[t] = M::op(a[t][kk], b[t][kk], acc[t]);
+  }
+}
+
+// small_products for a wave-uniform block count nblk <= MAXB.
+template <typename T, int NBK = 1>
+__device__ __forceinline__ void small_products_n(int nblk, const T* A, const T* B, int ldx, int dp,
+                                                 const int (&bi)[SmallCfg<T>::MAXB],
+                                                 const int (&bj)[SmallCfg<T>::MAXB],
+                                                 typename FMfma<T>::acc_t (&acc)[SmallCfg<T>::MAXB],
+                                                 int lane) {
+  if (nblk == NBK) {
+    small_products<T, NBK>(A, B, ldx, dp, bi, bj, acc, lane);
+  } else if constexpr (NBK < SmallCfg<T>::MAXB) {
+    small_products_n<T, NBK + 1>(nblk, A, B, ldx, dp, bi, bj, acc, lane);
   }
 }
 
@@ -540,25 +559,35 @@ __global__ __launch_bounds__(512) void k_ns_small(const SmallProb* __restrict__ 
   if (d < 1 || dp > C::DMAX || pr.dp < d) return;
   T* Xs = lds;
   T* Ns = lds + dp * ldx;
-  const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+  // wave is uniform across the wave; readfirstlane lets the block bookkeeping
+  // below live in scalar registers.
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
 
-  // This wave's upper blocks (I, J), I <= J, in row-major order of the upper
-  // triangle: block index wave + t NW.
+  // This wave's upper blocks (I, J), I <= J: a contiguous piece of the
+  // row-major list of the upper triangle (so that its blocks mostly share a
+  // row block), the nbu % NW longer pieces to the first waves, which sit on
+  // different SIMDs.
   const int nb = dp / 16, nbu = nb * (nb + 1) / 2;
+  const int qn = nbu / C::NW, rn = nbu % C::NW;
+  const int nblk = qn + (wave < rn ? 1 : 0);
+  const int first = wave * qn + min(wave, rn);
   int bi[C::MAXB], bj[C::MAXB];
-  int nblk = 0;
+  {
+    int idx = first, I = 0;
+    while (I < nb && idx >= nb - I) {
+      idx -= nb - I;
+      ++I;
+    }
+    int J = I + idx;
 #pragma unroll
-  for (int t = 0; t < C::MAXB; ++t) {
-    int idx = wave + t * C::NW, I = 0;
-    bi[t] = bj[t] = 0;
-    if (idx < nbu) {
-      while (idx >= nb - I) {
-        idx -= nb - I;
+    for (int t = 0; t < C::MAXB; ++t) {
+      bi[t] = t < nblk ? I : 0;
+      bj[t] = t < nblk ? J : 0;
+      if (++J == nb) {
         ++I;
+        J = I;
       }
-      bi[t] = I;
-      bj[t] = I + idx;
-      nblk = t + 1;
     }
   }
 
@@ -578,7 +607,7 @@ __global__ __launch_bounds__(512) void k_ns_small(const SmallProb* __restrict__ 
   int m = 0;
   for (;; ++m) {
     // GEMM_RESIDUAL: N = I - X X, ||N||_F^2.
-    small_products<T>(Xs, Xs, ldx, dp, bi, bj, nblk, acc, lane);
+    small_products_n<T>(nblk, Xs, Xs, ldx, dp, bi, bj, acc, lane);
     double part = 0.0;
 #pragma unroll
     for (int t = 0; t < C::MAXB; ++t)
@@ -602,7 +631,7 @@ __global__ __launch_bounds__(512) void k_ns_small(const SmallProb* __restrict__ 
       break;
     }
     // GEMM_UPDATE: X <- X + (X N)/2, trace of the new iterate.
-    small_products<T>(Xs, Ns, ldx, dp, bi, bj, nblk, acc, lane);
+    small_products_n<T>(nblk, Xs, Ns, ldx, dp, bi, bj, acc, lane);
     double tp = 0.0;
 #pragma unroll
     for (int t = 0; t < C::MAXB; ++t)

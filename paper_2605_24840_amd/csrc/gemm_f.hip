@@ -250,13 +250,17 @@ __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T*
   if (tid == 0) *partial = tot;
 }
 
+// With live != null and *live == 0 the launch does nothing (a step enqueued
+// ahead of the device-side stopping decision of an iteration that stopped).
 template <typename T, int MODE, int TS>
 __global__ __launch_bounds__(256) void k_sym_gemm_f(const T* __restrict__ A,
                                                     const T* __restrict__ B,
                                                     const T* __restrict__ Xold,
                                                     T* __restrict__ out, int ld, int d, int dp,
                                                     const int2* __restrict__ tiles,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials,
+                                                    const int* __restrict__ live) {
+  if (live && *live == 0) return;
   __shared__ T lds[FCfg<T, TS>::LDS];
   __shared__ double red[4];
   const int2 tl = tiles[blockIdx.x];
@@ -325,16 +329,16 @@ __global__ __launch_bounds__(256) void k_sym_gemm_f_grouped(const GemmProblem* _
 template <typename T, int TS>
 static hipError_t launch_f_ts(int mode, const T* A, const T* B, const T* Xold, T* out, int ld,
                               int d, int dp, const int2* tiles, int ntiles, double* partials,
-                              hipStream_t st) {
+                              const int* live, hipStream_t st) {
   if (mode == GEMM_RESIDUAL)
     hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
-                       Xold, out, ld, d, dp, tiles, partials);
+                       Xold, out, ld, d, dp, tiles, partials, live);
   else if (mode == GEMM_UPDATE)
     hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
-                       Xold, out, ld, d, dp, tiles, partials);
+                       Xold, out, ld, d, dp, tiles, partials, live);
   else if (mode == GEMM_PLAIN_NEG)
     hipLaunchKernelGGL((k_sym_gemm_f<T, GEMM_PLAIN_NEG, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
-                       Xold, out, ld, d, dp, tiles, partials);
+                       Xold, out, ld, d, dp, tiles, partials, live);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -343,13 +347,13 @@ static hipError_t launch_f_ts(int mode, const T* A, const T* B, const T* Xold, T
 template <typename T>
 static hipError_t launch_f(int ts, int mode, const T* A, const T* B, const T* Xold, T* out, int ld,
                            int d, int dp, const int2* tiles, int ntiles, double* partials,
-                           hipStream_t st) {
+                           const int* live, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   if (dp % ts != 0) return hipErrorInvalidValue;
   switch (ts) {
-    case 64: return launch_f_ts<T, 64>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
-    case 96: return launch_f_ts<T, 96>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
-    case 128: return launch_f_ts<T, 128>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+    case 64: return launch_f_ts<T, 64>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
+    case 96: return launch_f_ts<T, 96>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
+    case 128: return launch_f_ts<T, 128>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
   }
   return hipErrorInvalidValue;
 }
@@ -393,13 +397,14 @@ hipError_t launch_adjoint_step_f32(int ts, const float* Gb, const float* N, cons
 
 hipError_t launch_sym_gemm_f64(int ts, int mode, const double* A, const double* B,
                                const double* Xold, double* out, int ld, int d, int dp,
-                               const int2* tiles, int ntiles, double* partials, hipStream_t st) {
-  return launch_f<double>(ts, mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+                               const int2* tiles, int ntiles, double* partials, hipStream_t st,
+                               const int* live) {
+  return launch_f<double>(ts, mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
 }
 hipError_t launch_sym_gemm_f32(int ts, int mode, const float* A, const float* B, const float* Xold,
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
-                               double* partials, hipStream_t st) {
-  return launch_f<float>(ts, mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, st);
+                               double* partials, hipStream_t st, const int* live) {
+  return launch_f<float>(ts, mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
 }
 
 // Blocks of one tile-edge choice that a compute unit holds at once (LDS).

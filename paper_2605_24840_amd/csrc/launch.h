@@ -18,13 +18,15 @@ enum GemmMode {
 // FP64 / FP32 products on 16x16x4 MFMA with tile edge ts in {64, 96, 128}.
 // Matrices are dp x dp, leading dimension ld, dp a multiple of ts.  tiles
 // holds (I, J) in units of ts (I <= J for the symmetric modes); partials
-// receives one FP64 value per tile.
+// receives one FP64 value per tile.  With live != null the launch does
+// nothing when *live == 0 (read on the device).
 hipError_t launch_sym_gemm_f64(int ts, int mode, const double* A, const double* B,
                                const double* Xold, double* out, int ld, int d, int dp,
-                               const int2* tiles, int ntiles, double* partials, hipStream_t st);
+                               const int2* tiles, int ntiles, double* partials, hipStream_t st,
+                               const int* live = nullptr);
 hipError_t launch_sym_gemm_f32(int ts, int mode, const float* A, const float* B, const float* Xold,
                                float* out, int ld, int d, int dp, const int2* tiles, int ntiles,
-                               double* partials, hipStream_t st);
+                               double* partials, hipStream_t st, const int* live = nullptr);
 // Blocks of the FP64 (fp64 = 1) or FP32 product with tile edge ts that one
 // compute unit holds at once (from their LDS).
 int sym_gemm_f_blocks_per_cu(int fp64, int ts);

@@ -1073,6 +1073,82 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     b.converged = sq->state == BATCH_CONVERGED;
     if (sq->state == BATCH_NONFINITE)
       bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
+  } else if (p.precision != REFL_PREC_MIXED) {
+    // FP32 / FP64: the stopping rule runs on the device after each residual
+    // product (k_batch_decide on this one problem: the rule of the host loop
+    // below, step for step), so the host enqueues STEPS_AHEAD steps at a time
+    // and reads the step record once per group; the products of steps past
+    // the stop find *live == 0 and do nothing.  Rule, record, live flag and
+    // step counter are staged like the small-order launch's.
+    constexpr int STEPS_AHEAD = 4;
+    const bool f64 = p.precision == REFL_PREC_FP64;
+    char* hs = reinterpret_cast<char*>(h->pinned + SC_COUNT) + sizeof(CgHost);
+    char* ds = reinterpret_cast<char*>(w.scal + SC_SCRATCH + 4);
+    BatchRule* ru = reinterpret_cast<BatchRule*>(hs);
+    BatchStep* sq = reinterpret_cast<BatchStep*>(hs + 16);
+    int* hlive = reinterpret_cast<int*>(hs + 64);
+    int* hctl = reinterpret_cast<int*>(hs + 72);
+    BatchRule* d_ru = reinterpret_cast<BatchRule*>(ds);
+    BatchStep* d_sq = reinterpret_cast<BatchStep*>(ds + 16);
+    int* d_live = reinterpret_cast<int*>(ds + 64);
+    int* d_ctl = reinterpret_cast<int*>(ds + 72);
+    ru->tol = p.tol;
+    ru->fixed_steps = p.fixed_steps;
+    ru->max_iter = p.max_iter;
+    std::memset(sq, 0, sizeof(BatchStep));
+    sq->trace = trace_cur;
+    sq->resid = NaN;
+    sq->state = BATCH_LIVE;
+    *hlive = 1;
+    hctl[0] = 0;
+    hctl[1] = 1;
+    HIPCHK(hipMemcpyAsync(ds, hs, 80, hipMemcpyHostToDevice, st));
+    auto product = [&](int mode, int c) -> hipError_t {
+      if (f64)
+        return mode == GEMM_RESIDUAL
+                   ? launch_sym_gemm_f64(w.ts, mode, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
+                                         w.dp, w.tiles, w.ntiles, w.partials, st, d_live)
+                   : launch_sym_gemm_f64(w.ts, mode, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp,
+                                         (int)d, w.dp, w.tiles, w.ntiles, w.partials, st, d_live);
+      return mode == GEMM_RESIDUAL
+                 ? launch_sym_gemm_f32(w.ts, mode, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
+                                       w.dp, w.tiles, w.ntiles, w.partials, st, d_live)
+                 : launch_sym_gemm_f32(w.ts, mode, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp,
+                                       (int)d, w.dp, w.tiles, w.ntiles, w.partials, st, d_live);
+    };
+    int enq = 0;  // steps enqueued (step m uses X[m & 1])
+    for (;;) {
+      for (int i = 0; i < STEPS_AHEAD && enq <= cap; ++i, ++enq) {
+        const int c = enq & 1;
+        HIPCHK(ev_start());
+        HIPCHK(product(GEMM_RESIDUAL, c));
+        HIPCHK(ev_stop());
+        HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
+        HIPCHK(launch_batch_decide(1, w.scal + SC_RESID2, w.scal + SC_TRACE, d_ru, d_sq, d_live, d_ctl,
+                                   c, st));
+        HIPCHK(ev_start());
+        HIPCHK(product(GEMM_UPDATE, c));
+        HIPCHK(ev_stop());
+        HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
+      }
+      HIPCHK(hipMemcpyAsync(hs + 16, ds + 16, 64, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hctl[1] == 0) break;
+      if (enq > cap) {
+        if (info) *info = inf;
+        return fail(h, REFL_ERR_DEVICE, "iteration still running after the step limit");
+      }
+    }
+    b.steps = sq->m;
+    b.cur = sq->par;
+    b.resid = sq->resid;
+    b.trace = sq->trace;
+    b.converged = sq->state == BATCH_CONVERGED;
+    if (sq->state == BATCH_NONFINITE)
+      bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
+    // Timed launches: only those of the steps taken (residual products of
+    // steps 0..m, update products of steps 0..m-1), not the skipped ones.
+    nev = std::min(nev, (size_t)(2 * b.steps + 1));
   } else
   while (true) {
     const int c = b.cur;

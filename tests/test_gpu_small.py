@@ -175,3 +175,22 @@ def test_small_order_limit(R, handle, prec):
                              check=False)
         assert st == 0 and info["ns_steps"] == 3
         assert info["gemm_launches"] == (1 if small else 7), info["gemm_launches"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_sign_apply_matches_sign(R, handle, prec):
+    """R V without forming R takes the same one-launch iteration: it equals
+    the formed R times V up to the rounding of the thin product."""
+    d, k = 80, 7
+    H, lam, Q, s = _problem(d, k, 2e-2, 601)
+    Hd = torch.from_numpy(H).to("cuda:0")
+    rng = np.random.default_rng(1)
+    Vn = rng.standard_normal((d, 4))
+    tol = 1e-11 if prec == "fp64" else 1e-3
+    _say(f"small sign_apply {prec}")
+    Rg, i1, st1 = R.sign(Hd, k, s, handle=handle, precision=prec, tol=tol, check=False)
+    Y, i2, st2 = R.sign_apply(Hd, torch.from_numpy(Vn).to("cuda:0"), k, s, handle=handle,
+                              precision=prec, tol=tol, check=False)
+    assert st1 == 0 and st2 == 0 and i1["ns_steps"] == i2["ns_steps"]
+    ref = Rg.cpu().numpy() @ Vn
+    assert np.abs(Y.cpu().numpy() - ref).max() <= 1e-12 * np.abs(Vn).sum(axis=0).max()

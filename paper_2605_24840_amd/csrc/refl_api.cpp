@@ -1103,41 +1103,51 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     hctl[0] = 0;
     hctl[1] = 1;
     HIPCHK(hipMemcpyAsync(ds, hs, 80, hipMemcpyHostToDevice, st));
-    auto product = [&](int mode, int c) -> hipError_t {
+    auto product = [&](int mode, int c, hipStream_t ss) -> hipError_t {
       if (f64)
         return mode == GEMM_RESIDUAL
                    ? launch_sym_gemm_f64(w.ts, mode, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
-                                         w.dp, w.tiles, w.ntiles, w.partials, st, d_live)
+                                         w.dp, w.tiles, w.ntiles, w.partials, ss, d_live)
                    : launch_sym_gemm_f64(w.ts, mode, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp,
-                                         (int)d, w.dp, w.tiles, w.ntiles, w.partials, st, d_live);
+                                         (int)d, w.dp, w.tiles, w.ntiles, w.partials, ss, d_live);
       return mode == GEMM_RESIDUAL
                  ? launch_sym_gemm_f32(w.ts, mode, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
-                                       w.dp, w.tiles, w.ntiles, w.partials, st, d_live)
+                                       w.dp, w.tiles, w.ntiles, w.partials, ss, d_live)
                  : launch_sym_gemm_f32(w.ts, mode, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp,
-                                       (int)d, w.dp, w.tiles, w.ntiles, w.partials, st, d_live);
+                                       (int)d, w.dp, w.tiles, w.ntiles, w.partials, ss, d_live);
     };
+    // One step on stream ss (timing events on the handle's stream).
+    auto enqueue_step = [&](int c, hipStream_t ss) -> hipError_t {
+      const bool ev = ss == st;
+      hipError_t e;
+      if (ev && (e = ev_start()) != hipSuccess) return e;
+      if ((e = product(GEMM_RESIDUAL, c, ss)) != hipSuccess) return e;
+      if (ev && (e = ev_stop()) != hipSuccess) return e;
+      if ((e = launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, ss)) != hipSuccess) return e;
+      if ((e = launch_batch_decide(1, w.scal + SC_RESID2, w.scal + SC_TRACE, d_ru, d_sq, d_live, d_ctl, c,
+                                   ss)) != hipSuccess)
+        return e;
+      if (ev && (e = ev_start()) != hipSuccess) return e;
+      if ((e = product(GEMM_UPDATE, c, ss)) != hipSuccess) return e;
+      if (ev && (e = ev_stop()) != hipSuccess) return e;
+      return launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, ss);
+    };
+    // (Capturing a group of steps as a HIP graph was measured as well: no
+    // faster at d = 64 .. 2048, the step time being the device's, and each
+    // call pays the instantiation.)
     int enq = 0;  // steps enqueued (step m uses X[m & 1])
+    hipError_t le = hipSuccess;
     for (;;) {
-      for (int i = 0; i < STEPS_AHEAD && enq <= cap; ++i, ++enq) {
-        const int c = enq & 1;
-        HIPCHK(ev_start());
-        HIPCHK(product(GEMM_RESIDUAL, c));
-        HIPCHK(ev_stop());
-        HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
-        HIPCHK(launch_batch_decide(1, w.scal + SC_RESID2, w.scal + SC_TRACE, d_ru, d_sq, d_live, d_ctl,
-                                   c, st));
-        HIPCHK(ev_start());
-        HIPCHK(product(GEMM_UPDATE, c));
-        HIPCHK(ev_stop());
-        HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
-      }
-      HIPCHK(hipMemcpyAsync(hs + 16, ds + 16, 64, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (hctl[1] == 0) break;
-      if (enq > cap) {
-        if (info) *info = inf;
-        return fail(h, REFL_ERR_DEVICE, "iteration still running after the step limit");
-      }
+      for (int i = 0; i < STEPS_AHEAD && enq <= cap && le == hipSuccess; ++i, ++enq)
+        le = enqueue_step(enq & 1, st);
+      if (le == hipSuccess) le = hipMemcpyAsync(hs + 16, ds + 16, 64, hipMemcpyDeviceToHost, st);
+      if (le == hipSuccess) le = hipStreamSynchronize(st);
+      if (le != hipSuccess || hctl[1] == 0 || enq > cap) break;
+    }
+    if (le != hipSuccess) return fail(h, REFL_ERR_DEVICE, "steps: %s", hipGetErrorString(le));
+    if (hctl[1] != 0) {
+      if (info) *info = inf;
+      return fail(h, REFL_ERR_DEVICE, "iteration still running after the step limit");
     }
     b.steps = sq->m;
     b.cur = sq->par;

@@ -511,3 +511,44 @@ def test_shift_on_an_eigenvalue(R, handle, prec):
         assert info["index_j"] == k + 1
     else:
         assert status == "REFL_ERR_NOT_CONVERGED" and info["index_j"] == -1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_device_stopping_rule_single_solve(R, handle, prec):
+    """FP32/FP64 solves above the small-order limit enqueue their steps four
+    at a time and stop by the rule evaluated on the device; the products of
+    steps past the stop do nothing.  A repeated call and a timed call give
+    the same R, steps, residual and trace bit for bit, the timed call counts
+    exactly the products of the steps taken (m + 1 residual, m update), and
+    fixed depths that are not multiples of four stop exactly there, at the
+    oracle's iterate."""
+    d, k = 300, 9
+    H, lam, Q = inputs.planted_hessian(d, k, 0.02, 31)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Hg = _gpu(H)
+    tol = 1e-12 if prec == "fp64" else 1e-3
+
+    def run(**kw):
+        Rm, info, st = R.sign(Hg, k, s, handle=handle, precision=prec, tol=tol, check=False, **kw)
+        assert st == 0
+        return Rm.clone(), info
+
+    _say(f"device stopping rule {prec} d={d}")
+    g1, i1 = run()
+    g2, i2 = run()
+    t1, it = run(timing=True)
+    assert i1["ns_steps"] >= 12
+    for other, io in ((g2, i2), (t1, it)):
+        assert torch.equal(g1, other)
+        assert io["ns_steps"] == i1["ns_steps"] and io["resid_fro"] == i1["resid_fro"]
+        assert io["trace"] == i1["trace"]
+    assert it["gemm_launches"] == 2 * i1["ns_steps"] + 1
+    exact = np.eye(d) - 2 * Q[:, :k] @ Q[:, :k].T
+    err = float(np.linalg.norm(g1.cpu().numpy() - exact))
+    assert err < (1e-9 if prec == "fp64" else 1e-2), err
+    for m in (5, 6, 7):
+        Rm, info, st = R.sign(Hg, k, s, handle=handle, precision=prec, fixed_steps=m, check=False)
+        assert st == 0 and info["ns_steps"] == m
+        alpha = oracle.inf_norm_shifted(H, s)
+        Xm = oracle.ns_iterates(H, s, alpha, m)[m]
+        assert np.abs(Rm.cpu().numpy() - Xm).max() < (1e-12 if prec == "fp64" else 4.0 * m * d * 2.0 ** -24)

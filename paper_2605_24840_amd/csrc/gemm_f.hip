@@ -47,11 +47,12 @@ struct FMfma<float> {
   }
 };
 
-// Tile edge TS in {64, 96, 128}: 4 waves in 2 x 2, each a (TS/2)^2 quadrant of
-// MB x MB MFMA blocks of 16 x 16.
+// Tile edge TS in {32, 64, 96, 128}: 4 waves in 2 x 2, each a (TS/2)^2
+// quadrant of MB x MB MFMA blocks of 16 x 16 (one block at TS = 32, which
+// spreads orders of a few hundred to a thousand over all compute units).
 template <typename T, int TS>
 struct FCfg {
-  static_assert(TS == 64 || TS == 96 || TS == 128, "tile edge");
+  static_assert(TS == 32 || TS == 64 || TS == 96 || TS == 128, "tile edge");
   static constexpr int BK = 16;
   static constexpr int LDA = BK + 16 / (int)sizeof(T);  // 16 B pad per LDS row
   static constexpr int OPER = 2 * 2 * TS * LDA;         // 2 buffers x 2 operands
@@ -61,6 +62,7 @@ struct FCfg {
   static constexpr int NV = 8 * (int)sizeof(T) / 16;    // 16 B vectors per thread per operand
   static constexpr int VE = 16 / (int)sizeof(T);        // elements per 16 B
   static constexpr int MB = TS / 32;                    // MFMA blocks per wave and dimension
+  static_assert(MB >= 1, "one block per wave at least");
   static constexpr int LPR = TS / VE;                   // 16 B vectors per tile row
   static constexpr int NIT = TS * TS / VE / 256;        // epilogue vectors per thread
   static_assert(NIT * VE * 256 == TS * TS, "epilogue split");
@@ -351,6 +353,7 @@ static hipError_t launch_f(int ts, int mode, const T* A, const T* B, const T* Xo
   if (ntiles <= 0) return hipSuccess;
   if (dp % ts != 0) return hipErrorInvalidValue;
   switch (ts) {
+    case 32: return launch_f_ts<T, 32>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
     case 64: return launch_f_ts<T, 64>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
     case 96: return launch_f_ts<T, 96>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
     case 128: return launch_f_ts<T, 128>(mode, A, B, Xold, out, ld, d, dp, tiles, ntiles, partials, live, st);
@@ -365,6 +368,10 @@ static hipError_t launch_adj(int ts, const T* Gb, const T* N, const T* Pn, const
   if (ntiles <= 0) return hipSuccess;
   if (dp % ts != 0) return hipErrorInvalidValue;
   switch (ts) {
+    case 32:
+      hipLaunchKernelGGL((k_adjoint_step<T, 32>), dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X,
+                         out, ld, d, dp, tiles, partials);
+      break;
     case 64:
       hipLaunchKernelGGL((k_adjoint_step<T, 64>), dim3(ntiles), dim3(256), 0, st, Gb, N, Pn, X,
                          out, ld, d, dp, tiles, partials);
@@ -412,9 +419,11 @@ int sym_gemm_f_blocks_per_cu(int fp64, int ts) {
   constexpr int LDS_BYTES = 160 * 1024;
   int lds = 0;
   if (fp64)
-    lds = ts == 64 ? FCfg<double, 64>::LDS : ts == 96 ? FCfg<double, 96>::LDS : FCfg<double, 128>::LDS;
+    lds = ts == 32 ? FCfg<double, 32>::LDS : ts == 64 ? FCfg<double, 64>::LDS
+        : ts == 96 ? FCfg<double, 96>::LDS : FCfg<double, 128>::LDS;
   else
-    lds = ts == 64 ? FCfg<float, 64>::LDS : ts == 96 ? FCfg<float, 96>::LDS : FCfg<float, 128>::LDS;
+    lds = ts == 32 ? FCfg<float, 32>::LDS : ts == 64 ? FCfg<float, 64>::LDS
+        : ts == 96 ? FCfg<float, 96>::LDS : FCfg<float, 128>::LDS;
   const int per = LDS_BYTES / (lds * (fp64 ? 8 : 4) + 64);
   return per < 1 ? 1 : (per > 8 ? 8 : per);
 }
@@ -436,6 +445,10 @@ hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem
   if (ntiles <= 0) return hipSuccess;
   if (mode != GEMM_RESIDUAL && mode != GEMM_UPDATE) return hipErrorInvalidValue;
   switch (ts) {
+    case 32:
+      if (fp64) launch_grouped_ts<double, 32>(mode, probs, tiles, ntiles, parity, partials, live, st);
+      else launch_grouped_ts<float, 32>(mode, probs, tiles, ntiles, parity, partials, live, st);
+      break;
     case 64:
       if (fp64) launch_grouped_ts<double, 64>(mode, probs, tiles, ntiles, parity, partials, live, st);
       else launch_grouped_ts<float, 64>(mode, probs, tiles, ntiles, parity, partials, live, st);

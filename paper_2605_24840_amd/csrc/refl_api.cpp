@@ -217,7 +217,7 @@ int model_tile_f(int64_t d, bool fp64, int ncu) {
 // order d on a device, one symmetric product of each candidate edge is timed
 // (HIP events, after a warm-up launch) on a pseudo-random dp x dp operand in
 // scratch memory the tuner allocates and frees, and the fastest edge is
-// cached for the process.  REFL_F_TILE=64|96|128 forces an edge;
+// cached for the process.  REFL_F_TILE=32|64|96|128 forces an edge (32 only so);
 // REFL_F_TUNE=0 uses the cost model instead.  The edge changes only how the
 // products are tiled: each output entry is the same sum in the same order.
 std::mutex g_tile_mu;
@@ -226,7 +226,7 @@ std::map<std::tuple<int, int, int64_t>, int> g_tile_cache;
 int select_tile_f(refl_handle_t h, int64_t d, bool fp64) {
   if (const char* e = std::getenv("REFL_F_TILE")) {
     const int v = std::atoi(e);
-    if (v == 64 || v == 96 || v == 128) return v;
+    if (v == 32 || v == 64 || v == 96 || v == 128) return v;
   }
   if (const char* e = std::getenv("REFL_F_TUNE"))
     if (std::atoi(e) == 0) return model_tile_f(d, fp64, h->ncu);
@@ -235,11 +235,15 @@ int select_tile_f(refl_handle_t h, int64_t d, bool fp64) {
   auto it = g_tile_cache.find(key);
   if (it != g_tile_cache.end()) return it->second;
   const int fallback = model_tile_f(d, fp64, h->ncu);
+  // The 32 edge is not a candidate: alone on the device it is the fastest
+  // product up to d = 1536 (it spreads the tiles over every compute unit),
+  // but batched calls, which must use refl_sign's edge to return the same
+  // results bit for bit, run a third slower with it on a full device.
   const int cands[3] = {128, 96, 64};
   int64_t dpmax = 0;
   for (int ts : cands) dpmax = std::max<int64_t>(dpmax, round_up(d, pad_unit_f(ts)));
   const size_t es = fp64 ? sizeof(double) : sizeof(float);
-  const int64_t ntmax = dpmax / 64;
+  const int64_t ntmax = dpmax / 32;
   const size_t tmax = (size_t)(ntmax * (ntmax + 1) / 2);
   char* buf = nullptr;
   const size_t bytes = (size_t)dpmax * dpmax * (sizeof(double) + 2 * es) + tmax * (sizeof(int2) + sizeof(double)) + 4096;
@@ -1393,8 +1397,9 @@ struct BatchWork {
 
 // Tile edges of the batched FP32 / FP64 products, in the order their tile
 // lists are laid out and launched.
-constexpr int BATCH_EDGES[3] = {128, 96, 64};
-int edge_class(int ts) { return ts == 128 ? 0 : ts == 96 ? 1 : 2; }
+constexpr int NEDGE = 4;
+constexpr int BATCH_EDGES[NEDGE] = {128, 96, 64, 32};
+int edge_class(int ts) { return ts == 128 ? 0 : ts == 96 ? 1 : ts == 64 ? 2 : 3; }
 
 size_t batch_layout(BatchWork& bw, void* base, int nprob, const int64_t* d, const int* ts,
                     bool fp64) {
@@ -1506,7 +1511,7 @@ int batch_tiles(const BatchWork& bw, const std::vector<int>& ids, int4* tiles, i
   });
   std::vector<int2> tl;
   int t = 0;
-  cnt[0] = cnt[1] = cnt[2] = 0;
+  for (int c = 0; c < NEDGE; ++c) cnt[c] = 0;
   for (int q : ord) {
     const BatchProb& pq = bw.pr[ids[q]];
     build_tiles_nt(pq.dp / pq.ts, tl);
@@ -1667,12 +1672,12 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     }
     return hipSuccess;
   };
-  int cls[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // tiles per edge class of each list
+  int cls[3][NEDGE] = {};  // tiles per edge class of each list
   // One grouped launch per edge class present in list lb.
   auto grouped_list = [&](int fp, int mode, const GemmProblem* probs, int lb, int par,
                           const int* live, hipStream_t s) -> hipError_t {
     int off = 0;
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NEDGE; ++c) {
       if (cls[lb][c] > 0) {
         hipError_t e = launch_sym_gemm_grouped(fp, mode, BATCH_EDGES[c], probs, bw.tiles[lb] + off,
                                                cls[lb][c], par, bw.partials, live, s);

@@ -250,3 +250,24 @@ def test_batched_full_workload_fp32(R, handle):
         err = _check_exact("fp32", H, lam, Q, ks[p], ss[p], Rs[p], infos[p])
         _say(f"  p={p} d={H.shape[0]} k={ks[p]} steps={infos[p]['ns_steps']} err={err:.2e}")
         assert st1 == 0 and torch.equal(Rs[p], R1)
+
+
+def test_batched_tile32_equals_single(R, handle, monkeypatch):
+    """With the 32-edge tile forced, the grouped launches of that edge class
+    return what refl_sign returns with the same edge, bit for bit."""
+    probs = _problems(SMALL[1:5])
+    Hs = [torch.from_numpy(H).to("cuda:0") for H, *_ in probs]
+    ks = [p[3] for p in probs]
+    ss = [p[4] for p in probs]
+    monkeypatch.setenv("REFL_F_TILE", "32")
+    for prec, tol in (("fp32", 1e-3), ("fp64", 1e-10)):
+        _say(f"batched tile 32 {prec}")
+        Rs, infos, sts, st = R.sign_batched(Hs, ks, ss, handle=handle, precision=prec, tol=tol,
+                                            check=False)
+        assert st == 0 and all(x == 0 for x in sts)
+        for p in range(len(probs)):
+            R1, i1, st1 = R.sign(Hs[p], ks[p], ss[p], handle=handle, precision=prec, tol=tol,
+                                 check=False)
+            assert st1 == 0 and torch.equal(Rs[p], R1), p
+            assert infos[p]["ns_steps"] == i1["ns_steps"]
+    monkeypatch.delenv("REFL_F_TILE")

@@ -96,6 +96,28 @@ def test_grad_checkpoint_intervals_bitwise(R, handle):
     assert err < 1e-12
 
 
+def test_grad_tile_edges_bitwise(R, handle, monkeypatch):
+    """The derivative products (-X Gbar over all tiles, the three-pair
+    adjoint step over the upper tiles) give the same gradient bit for bit
+    whichever FP64 tile edge runs: each entry is the same sum in the same
+    order."""
+    d, k, m = 200, 4, 7
+    H, lam, Q = inputs.planted_hessian(d, k, 0.05, 5)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    G = _gpu(inputs.symmetric_normal(d, 6))
+    Hg = _gpu(H)
+    out = {}
+    for ts in (32, 64, 128):
+        monkeypatch.setenv("REFL_F_TILE", str(ts))
+        g, loss, _, info, st = R.sign_grad(Hg, G, k, s, handle=handle, fixed_steps=m)
+        assert st == 0
+        out[ts] = (g.clone(), loss)
+    monkeypatch.delenv("REFL_F_TILE")
+    _say(f"  grad tile edges 32/64/128 equal: {[torch.equal(out[32][0], out[t][0]) for t in (64, 128)]}")
+    for ts in (64, 128):
+        assert torch.equal(out[32][0], out[ts][0])
+
+
 @pytest.fixture(scope="module")
 def c4():
     d, k = 2048, 10

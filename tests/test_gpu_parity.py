@@ -85,11 +85,11 @@ def test_fp64_ragged_size(R, handle):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("ts", [64, 96, 128])
+@pytest.mark.parametrize("ts", [32, 64, 96, 128])
 def test_tile_edges_ragged(R, handle, monkeypatch, ts, prec):
     """Every tile edge of the FP64 / FP32 products on a ragged size (d = 300
-    pads to 320, 384 or 384): the same iterate as the oracle, and the same
-    (bit for bit in FP64) whichever edge runs."""
+    pads to 320, 320, 384 or 384): the same iterate as the oracle, and the
+    same (bit for bit in FP64) whichever edge runs."""
     d, k, m = 300, 7, 6
     H, lam, Q = inputs.planted_hessian(d, k, 0.05, 3)
     s = 0.5 * (lam[k - 1] + lam[k])

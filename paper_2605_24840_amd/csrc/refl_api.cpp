@@ -1163,81 +1163,40 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     // Timed launches: only those of the steps taken (residual products of
     // steps 0..m, update products of steps 0..m-1), not the skipped ones.
     nev = std::min(nev, (size_t)(2 * b.steps + 1));
-  } else
-  while (true) {
-    const int c = b.cur;
-    HIPCHK(ev_start());
-    if (p.precision == REFL_PREC_FP64)
-      HIPCHK(launch_sym_gemm_f64(w.ts, GEMM_RESIDUAL, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
-                                 w.dp, w.tiles, w.ntiles, w.partials, st));
-    else if (p.precision == REFL_PREC_FP32)
-      HIPCHK(launch_sym_gemm_f32(w.ts, GEMM_RESIDUAL, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
-                                 w.dp, w.tiles, w.ntiles, w.partials, st));
-    else
+  } else {
+    // MIXED with a fixed depth (the finite-step filter p_m in BF16 words):
+    // m steps, each residual product read back for the reported residual.
+    while (true) {
+      const int c = b.cur;
+      HIPCHK(ev_start());
       HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, w.Xw[c], w.Xw[c], nullptr, w.Nw, w.dp,
                                    w.ps, (int)d, w.dk, w.tiles, w.ntiles, w.partials, st));
-    HIPCHK(ev_stop());
-    HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
-    HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, w.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const double resid = std::sqrt(std::fmax(hsc[SC_RESID2], 0.0));
-    b.resid = resid;
-    b.trace = trace_cur;
-    hist.push_back(resid);
-    if (!std::isfinite(resid)) {
-      bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
-      break;
-    }
-    // Stopping rule.
-    if (fixed) {
+      HIPCHK(ev_stop());
+      HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st));
+      HIPCHK(hipMemcpyAsync(hsc + SC_RESID2, w.scal + SC_RESID2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const double resid = std::sqrt(std::fmax(hsc[SC_RESID2], 0.0));
+      b.resid = resid;
+      b.trace = trace_cur;
+      if (!std::isfinite(resid)) {
+        bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
+        break;
+      }
       if (b.steps >= cap) {
         b.converged = true;
         break;
       }
-    } else if (p.precision != REFL_PREC_MIXED) {
-      if (resid < p.tol) {
-        b.converged = true;
-        break;
-      }
-      // Stagnation once quadratic convergence should have set in: no halving
-      // over two steps below 1e-6.
-      const size_t n = hist.size();
-      if (n >= 3 && resid < 1e-6 && resid > 0.5 * hist[n - 3]) break;
-      if (b.steps >= cap) break;
-    } else {
-      // MIXED bulk: hand over to the FP64 correction as soon as the index
-      // certificate holds (the correction restores full accuracy), or after
-      // REFL_BULK_EXTRA further steps (tuning), or when the residual stops
-      // decreasing quadratically (the BF16-word floor).
-      const int j = index_certificate(d, resid, trace_cur);
-      const size_t n = hist.size();
-      if (j >= 0) {
-        ++cert_steps;
-        const bool floor = n >= 2 && resid > 0.25 * hist[n - 2];
-        if (floor || cert_steps > bulk_extra) {
-          b.converged = true;
-          break;
-        }
-      }
-      if (b.steps >= cap) break;
-    }
-    HIPCHK(ev_start());
-    if (p.precision == REFL_PREC_FP64)
-      HIPCHK(launch_sym_gemm_f64(w.ts, GEMM_UPDATE, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp, (int)d,
-                                 w.dp, w.tiles, w.ntiles, w.partials, st));
-    else if (p.precision == REFL_PREC_FP32)
-      HIPCHK(launch_sym_gemm_f32(w.ts, GEMM_UPDATE, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp, (int)d,
-                                 w.dp, w.tiles, w.ntiles, w.partials, st));
-    else
+      HIPCHK(ev_start());
       HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, w.Xw[c], w.Nw, w.Xw[c], w.Xw[c ^ 1], w.dp,
                                    w.ps, (int)d, w.dk, w.tiles, w.ntiles, w.partials, st));
-    HIPCHK(ev_stop());
-    HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
-    HIPCHK(hipMemcpyAsync(hsc + SC_TRACE, w.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
-    b.cur ^= 1;
-    b.steps += 1;
-    HIPCHK(hipStreamSynchronize(st));
-    trace_cur = hsc[SC_TRACE];
+      HIPCHK(ev_stop());
+      HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st));
+      HIPCHK(hipMemcpyAsync(hsc + SC_TRACE, w.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
+      b.cur ^= 1;
+      b.steps += 1;
+      HIPCHK(hipStreamSynchronize(st));
+      trace_cur = hsc[SC_TRACE];
+    }
   }
   if (p.timing) {
     HIPCHK(hipStreamSynchronize(st));

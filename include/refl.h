@@ -8,7 +8,7 @@
  * k in {1, ..., d-1}, P_k the spectral projector onto the eigenvectors of the
  * k smallest eigenvalues.  For any shift s in (lambda_k, lambda_{k+1}),
  * R_k = sgn(H - sI) (Prop. 2.1).  R_k is computed by the scaled iteration
- * X_0 = (H - sI)/alpha, X_{m+1} = X_m (3I - X_m^2)/2 (section 3.2, eq. NS),
+ * X_0 = (H - sI)/alpha, X_{m+1} = X_m (3I - X_m^2)/2 (section 3.3, eq. NS),
  * with the midpoint shift s = (lambda_k + lambda_{k+1})/2 (Prop. 4.1)
  * supplied or estimated by block Lanczos (section 4.3, recommended default
  * realization), and alpha = ||H - sI||_inf (the cheap surrogate of
@@ -152,7 +152,7 @@ typedef struct {
   int32_t gemm_launches;  /* params.timing: number of bulk product launches timed */
   double rho;             /* Lanczos estimate of max_i |lambda_i - s| (NaN if s given) */
   double gamma;           /* estimated scaled margin min(s - lam_k, lam_k1 - s)/alpha
-                             (section 3.2 gamma, from the Lanczos estimates; NaN if s given) */
+                             (section 3.3 gamma, from the Lanczos estimates; NaN if s given) */
 } refl_info_t;
 
 /* Fill *p with defaults: k = 1, s = 0, shift given, scale inf-norm, FP64,

@@ -1,4 +1,4 @@
-// Symmetric FP64 / FP32 products of the Newton-Schulz step (section 3.2,
+// Symmetric FP64 / FP32 products of the Newton-Schulz step (section 3.3,
 // eq. NS) on 16x16x4 MFMA, with the step's elementwise work fused into the
 // epilogue.
 //

@@ -1,4 +1,4 @@
-// Symmetric products of the Newton-Schulz step (section 3.2, eq. NS) on
+// Symmetric products of the Newton-Schulz step (section 3.3, eq. NS) on
 // BF16 MFMA with FP32 accumulation, for matrices held as W BF16 words per
 // entry (x ~= w0 + w1 + w2, each word the round-to-nearest-even BF16 of the
 // remainder left by the words before it).  The product of two such matrices

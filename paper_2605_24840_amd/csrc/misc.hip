@@ -1,5 +1,5 @@
 // Memory-bound kernels around the Newton-Schulz products: set-up of the
-// scaled iterate (section 3.2 eq. NS with the inf-norm scaling of section
+// scaled iterate (section 3.3 eq. NS with the inf-norm scaling of section
 // 4.3), reductions, output, and the thin products and block-vector updates
 // of the FP64 subspace correction and of block Lanczos.
 #include <algorithm>

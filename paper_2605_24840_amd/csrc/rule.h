@@ -1,7 +1,8 @@
-// Device side of the Newton-Schulz stopping rule (section 3.3 for the
-// residual test, the fixed-depth filters p_m of section 3.4), shared by the
-// batched decision kernel and the LDS-resident small-order iteration, so
-// that both stop at exactly the step refl_sign's host loop stops at.
+// Device side of the Newton-Schulz stopping rule (section 3.3: the
+// iteration eq. NS run to a residual tolerance, or for a fixed depth m, the
+// finite-step filter p_m of eq. pm), shared by the decision kernel of the
+// tiled iterations and the LDS-resident small-order iteration, so that every
+// FP32 / FP64 path stops at the same step.
 #pragma once
 #include "common.h"
 #include "launch.h"

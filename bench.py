@@ -16,7 +16,8 @@ reflector R_k from H resident in HBM to R resident in HBM.
   roofline     the dominant kernel (the bulk BF16-word product), from HIP
                events around every launch in the timed region
   cpu_baseline the oracle (FP64 cyclic Jacobi) on the host cores: one sweep
-               of the same matrix, scaled by the sweep count of a full solve
+               of the same matrix, scaled by the sweep count of a full solve,
+               with a measured anchor (a full solve at d = 1024)
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 2]
 
@@ -172,8 +173,16 @@ def main():
     gemm_ms = sum(i["ms_gemm"] for i in infos)
     gemm_n = sum(i["gemm_launches"] for i in infos)
     avg_launch_s = gemm_ms / gemm_n / 1e3
-    flop_launch = nprod * float(d) ** 3           # algorithmic MFMA work of one symmetric product
+    # Algorithmic work of one symmetric product (d^2/2 outputs x 2d flop):
+    # d^3, whatever arithmetic carries it.  The split-word product executes
+    # it once per kept word product (nprod d^3), and the matrix cores issue
+    # that over the padded upper tiles (full diagonal tiles, K rounded to 32).
+    flop_launch = float(d) ** 3
     achieved = flop_launch / avg_launch_s
+    word_flop_launch = nprod * flop_launch
+    ts = int(last["bulk_tile"])
+    nt = -(-d // ts)
+    issued_flop_launch = nprod * (nt * (nt + 1) // 2) * ts * ts * 2.0 * (-(-d // 32) * 32)
     steps_mixed = float(np.mean([i["ns_steps"] for i in infos]))
     bulk_alg_tflops = steps_mixed * 2 * float(d) ** 3 / (np.mean([i["ms_bulk"] for i in infos]) / 1e3) / 1e12
 
@@ -215,16 +224,7 @@ def main():
     # ---- oracle on the host cores ----
     cpu = None
     if not args.no_cpu:
-        import oracle
-        sweeps_full = int(golden["sweeps"])
-        tc = time.perf_counter()
-        oracle.jacobi_eigh(H, max_sweeps=1)
-        t_sweep = time.perf_counter() - tc
-        cpu = {"value": 1.0 / (t_sweep * sweeps_full), "unit": "reflectors/s", "cores": oracle.oracle_threads(),
-               "kind": "oracle",
-               "sample": f"one cyclic-Jacobi sweep of this d={d} matrix ({t_sweep:.1f} s) scaled by the "
-                         f"{sweeps_full} sweeps of the full solve"}
-        log(f"cpu oracle: {t_sweep:.1f} s/sweep on {cpu['cores']} threads")
+        cpu = cpu_oracle(H, int(golden["sweeps"]))
 
     out = {
         "metric": METRIC,
@@ -261,9 +261,15 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": BF16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / BF16_PEAK, "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, calibrated)",
-                     "kernel": f"k_sym_gemm_wd<{args.words}, GEMM_RESIDUAL|GEMM_UPDATE, tile>",
+                     "kernel": f"k_sym_gemm_wd<{args.words}, GEMM_RESIDUAL|GEMM_UPDATE, {ts}>",
                      "launches": gemm_n, "avg_launch_ms": 1e3 * avg_launch_s,
-                     "flop_per_launch": flop_launch},
+                     "flop_per_launch": flop_launch,
+                     "flop_per_launch_meaning": "algorithmic: d^3 per symmetric product",
+                     "word_product_flop_per_launch": word_flop_launch,
+                     "word_product_tflops": word_flop_launch / avg_launch_s / 1e12,
+                     "word_product_frac": word_flop_launch / avg_launch_s / BF16_PEAK,
+                     "mfma_issued_flop_per_launch": issued_flop_launch,
+                     "mfma_issued_frac": issued_flop_launch / avg_launch_s / BF16_PEAK},
         "cpu_baseline": cpu,
     }
     h.close()
@@ -271,6 +277,45 @@ def main():
 
 
 FP32_PEAK = 157.3e12
+
+
+def cpu_oracle(H, sweeps_full):
+    """The oracle (FP64 cyclic Jacobi, then R_k from its eigenvectors) on the
+    host cores.  The d = 4096 figure is one sweep of this matrix times the
+    sweep count of its full solve (stored with the golden eigenvectors).
+    Anchor at d = 1024 (planted, gap 0.02): a full solve and one sweep with
+    all threads, so that full-solve time / (sweeps x first sweep) checks
+    the extrapolation, and one sweep on one thread."""
+    import oracle
+    from paper_2605_24840_amd import inputs
+    d = H.shape[0]
+    nthr = oracle.oracle_threads()
+    tc = time.perf_counter()
+    oracle.jacobi_eigh(H, max_sweeps=1)
+    t_sweep = time.perf_counter() - tc
+    log(f"cpu oracle: {t_sweep:.1f} s/sweep at d={d} on {nthr} threads")
+    Ha, lam, Q = inputs.planted_hessian(1024, 8, 0.02, 0)
+    tc = time.perf_counter()
+    w, V, sw_a = oracle.jacobi_eigh(Ha)
+    oracle.reflector_from_eig(V, 8)
+    t_full_a = time.perf_counter() - tc
+    tc = time.perf_counter()
+    oracle.jacobi_eigh(Ha, max_sweeps=1)
+    t_sweep_a = time.perf_counter() - tc
+    oracle.set_oracle_threads(1)
+    tc = time.perf_counter()
+    oracle.jacobi_eigh(Ha, max_sweeps=1)
+    t_sweep_a1 = time.perf_counter() - tc
+    oracle.set_oracle_threads(nthr)
+    log(f"cpu oracle d=1024: full solve {t_full_a:.2f} s ({sw_a} sweeps), one sweep {t_sweep_a:.2f} s on "
+        f"{nthr} threads, {t_sweep_a1:.2f} s on one thread")
+    return {"value": 1.0 / (t_sweep * sweeps_full), "unit": "reflectors/s", "cores": nthr, "kind": "oracle",
+            "sample": f"one cyclic-Jacobi sweep of this d={d} matrix ({t_sweep:.1f} s on {nthr} threads) "
+                      f"scaled by the {sweeps_full} sweeps of its full solve",
+            "anchor_d1024": {"full_solve_s": t_full_a, "sweeps": sw_a, "one_sweep_s": t_sweep_a,
+                             "full_over_sweeps_times_first": t_full_a / (sw_a * t_sweep_a),
+                             "one_sweep_single_thread_s": t_sweep_a1, "threads": nthr,
+                             "reflectors_per_s": 1.0 / t_full_a}}
 
 
 def bench_grad(args):

@@ -55,8 +55,12 @@ typedef enum {
   REFL_ERR_NOT_ADMISSIBLE = 5, /* the iterate's index certificate found j != k negatives,
                                   or the Lanczos margin test of Prop. 4.2 failed */
   REFL_ERR_NO_GAP = 6,         /* lambda_k == lambda_{k+1} to working precision */
-  REFL_ERR_NOT_FINITE = 7,     /* H (or the shift/scale) holds a NaN or an infinity */
-  REFL_ERR_UNSUPPORTED = 8     /* valid request this build does not implement */
+  REFL_ERR_NOT_SYMMETRIC = 7,  /* params.check_symmetric: max |H_ij - H_ji| exceeds
+                                  params.sym_tol times max |H_ij| (section 2.1 takes H
+                                  symmetric; by default only the upper triangle is read and
+                                  this is not checked) */
+  REFL_ERR_UNSUPPORTED = 8,    /* valid request this build does not implement */
+  REFL_ERR_NOT_FINITE = 9      /* H (or the shift/scale) holds a NaN or an infinity */
 } refl_status_t;
 
 /* Arithmetic of the Newton-Schulz matrix products. */
@@ -71,13 +75,13 @@ typedef enum { REFL_SHIFT_GIVEN = 0, REFL_SHIFT_LANCZOS = 1 } refl_shift_mode_t;
 
 typedef enum {
   REFL_SCALE_INF = 0,    /* alpha = ||H - sI||_inf (max absolute row sum) */
-  REFL_SCALE_GIVEN = 1,  /* alpha = params.alpha; X_0 = (H - sI)/alpha */
+  REFL_SCALE_FRO = 1,    /* alpha = ||H - sI||_F, another cheap bound on the spectral
+                            radius of H - sI (looser than the inf-norm for spread spectra,
+                            tighter for a few dominant eigenvalues) */
   REFL_SCALE_LANCZOS = 2,/* alpha = 1.05 rho_hat with rho_hat the Lanczos estimate of
                             max_i |lambda_i - s| (the spectral-norm scaling of section 4.3);
                             needs shift_mode == REFL_SHIFT_LANCZOS */
-  REFL_SCALE_FRO = 3     /* alpha = ||H - sI||_F, another cheap bound on the spectral
-                            radius of H - sI (looser than the inf-norm for spread spectra,
-                            tighter for a few dominant eigenvalues) */
+  REFL_SCALE_GIVEN = 3   /* alpha = params.alpha; X_0 = (H - sI)/alpha */
 } refl_scale_mode_t;
 
 typedef struct {
@@ -111,6 +115,13 @@ typedef struct {
                            c = ceil(sqrt(step cap)) */
   int32_t cg_f32;       /* MIXED: operator precision of the inner solves, refl_cg_prec_t
                            (default REFL_CG_AUTO) */
+  int32_t check_symmetric; /* 1: before any other work, read H in full and return
+                           REFL_ERR_NOT_SYMMETRIC if max_{i<j} |H_ij - H_ji| > sym_tol
+                           max_ij |H_ij| (a NaN anywhere also fails).  0 (default): only
+                           the upper triangle is read, the lower is never touched.
+                           One extra pass over H (d^2 doubles).  refl_sign, refl_sign_apply,
+                           refl_sign_grad and each problem of refl_sign_batched */
+  double sym_tol;       /* check_symmetric: relative tolerance, >= 0 (default 0: exact) */
 } refl_params_t;
 
 typedef enum {
@@ -153,12 +164,16 @@ typedef struct {
   double rho;             /* Lanczos estimate of max_i |lambda_i - s| (NaN if s given) */
   double gamma;           /* estimated scaled margin min(s - lam_k, lam_k1 - s)/alpha
                              (section 3.3 gamma, from the Lanczos estimates; NaN if s given) */
+  int32_t bulk_tile;      /* edge of the square output tiles of the bulk products */
+  int32_t bulk_words;     /* MIXED: BF16 words per operand of the bulk that produced the
+                             result (params.words, or the automatic choice) */
 } refl_info_t;
 
 /* Fill *p with defaults: k = 1, s = 0, shift given, scale inf-norm, FP64,
  * tol = 1e-12, max_iter = 100, fixed_steps = 0, words = 2, polish_sweeps = 2,
  * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0, timing = 0,
- * grad_mode = REFL_GRAD_REVERSE, ckpt_every = 0, cg_f32 = REFL_CG_AUTO. */
+ * grad_mode = REFL_GRAD_REVERSE, ckpt_every = 0, cg_f32 = REFL_CG_AUTO,
+ * check_symmetric = 0, sym_tol = 0. */
 refl_status_t refl_params_default(refl_params_t *p);
 
 /* Create a handle bound to HIP device `device` and stream `hip_stream`

@@ -10,7 +10,8 @@ Contents
 ``jacobi.c``  plain FP64 cyclic Jacobi eigensolver (C, OpenMP).
 ``oracle.py`` the exact reflector R_k = I - 2 Q_k Q_k^T (Prop. 2.1), the
               shifted sign sgn(H - sI), the plain FP64 Newton-Schulz iterates
-              (eq. NS), the scalar polynomials p_m (eq. pm) and the error
+              (eq. NS) and their split-BF16 arithmetic model, the scalar
+              polynomials p_m (eq. pm) and the error
               recurrence (Prop. 3.6), the midpoint rule (Prop. 4.1) and the
               Prop. 4.2 admissibility test, reference certificate values, and
               the block-Lanczos estimate of the gap endpoints, error radius,

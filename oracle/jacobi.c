@@ -62,6 +62,17 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the following solves (n >= 1); returns the number in force. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 /* Returns the number of sweeps used, or -1 on bad arguments / no memory.
  * A is overwritten (its diagonal holds the unsorted eigenvalues on exit). */
 int oracle_jacobi_eig(int64_t d, double *A, double *w, double *V,

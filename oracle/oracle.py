@@ -15,10 +15,11 @@ _LIB_PATH = os.path.join(_HERE, "liboracle_jacobi.so")
 _lib = None
 
 __all__ = [
-    "jacobi_eigh", "oracle_threads", "reflector_from_eig", "reflector",
+    "jacobi_eigh", "oracle_threads", "set_oracle_threads", "reflector_from_eig", "reflector",
     "shifted_sign_from_eig", "midpoint", "ns_poly", "ns_scalar_error",
     "ns_error_recurrence", "ns_iterate", "ns_iterates", "ns_closed_form",
-    "ns_depth_scalar", "inf_norm_shifted", "fro_norm_shifted", "admissible", "certificates",
+    "ns_depth_scalar", "bf16_round", "split_words", "word_product", "ns_step_words", "ns_iterates_words",
+    "inf_norm_shifted", "fro_norm_shifted", "admissible", "certificates",
     "spectral_norm_sym", "splitmix64", "start_block", "lanczos_block_size",
     "lanczos_check_steps", "block_lanczos", "ns_step_derivative", "ns_adjoint", "ns_tangent",
     "ns_poly_derivative", "ns_frechet_dk", "sign_frechet_dk", "policy_step", "outer_descent",
@@ -36,6 +37,8 @@ def _load():
         lib.oracle_jacobi_eig.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_int]
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -43,6 +46,11 @@ def _load():
 def oracle_threads() -> int:
     """OpenMP threads the Jacobi solver uses (honours OMP_NUM_THREADS)."""
     return int(_load().oracle_num_threads())
+
+
+def set_oracle_threads(n: int) -> int:
+    """Threads of the following Jacobi solves; returns the number in force."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def jacobi_eigh(H, max_sweeps: int = 60):
@@ -147,6 +155,87 @@ def ns_iterates(H, s: float, alpha_norm: float, m: int):
         out.append(X)
     return out
 
+
+
+# ------------------------------------------- split-BF16 bulk arithmetic model
+def bf16_round(x):
+    """Round FP32 values to the nearest BF16 value, ties to the even
+    significand (8 significant bits: 1 implicit + 7 stored), returned as
+    FP32.  Written from the definition: x = f 2^e with f in [0.5, 1), keep
+    f 2^8 rounded half-to-even (numpy rint), scale back."""
+    x = np.asarray(x, dtype=np.float32).astype(np.float64)
+    f, e = np.frexp(x)
+    return np.ldexp(np.rint(f * 256.0) / 256.0, e).astype(np.float32)
+
+
+def split_words(x, words: int):
+    """The BF16 words of FP32 values (design reading of the bulk storage):
+    w_0 = bf16(x), w_i = bf16(x - w_0 - ... - w_{i-1}); every remainder is
+    exact in FP32.  Returns a list of FP32 arrays."""
+    r = np.asarray(x, dtype=np.float32)
+    out = []
+    for _ in range(words):
+        w = bf16_round(r)
+        out.append(w)
+        r = (r - w).astype(np.float32)
+    return out
+
+
+def word_product(Aw, Bw, mirror: bool = False):
+    """The split-word product: the sum of the word products A_a B_b whose
+    weight 2^-8(a + b) is at least 2^-8(W - 1) (W = 2: three products,
+    "bf16x3"; W = 3: six, "bf16x6"; Henry, Tang and Heinecke, ARITH 2019),
+    formed in FP64 and rounded once to FP32 (the model of an FP32
+    accumulation without its intermediate roundings).  With ``mirror`` the
+    product of two commuting symmetric matrices is taken from its upper
+    triangle (i <= j) and mirrored, as the library stores it (reading R3)."""
+    W = len(Aw)
+    acc = np.zeros((Aw[0].shape[0], Bw[0].shape[1]))
+    for a in range(W):
+        for b in range(W - a):
+            acc += Aw[a].astype(np.float64) @ Bw[b].astype(np.float64)
+    if mirror:
+        acc = np.triu(acc) + np.triu(acc, 1).T
+    return acc.astype(np.float32)
+
+
+def _word_total(ws):
+    t = ws[0].copy()
+    for w in ws[1:]:
+        t = (t + w).astype(np.float32)
+    return t
+
+
+def ns_step_words(X, words: int):
+    """One step of eq. NS in the split-BF16 bulk arithmetic from the iterate
+    X (values exactly representable in FP32, e.g. a word sum): Xw = the words
+    of fl32(X); T = word_product(Xw, Xw), N = words of fl32(I - T),
+    P = word_product(Xw, N), X_new = words of fl32(fl32(sum of Xw) + P/2).
+    Both products keep their upper triangle, mirrored (reading R3).  Only the
+    order of the FP32 accumulation inside a product is not modelled.
+    Returns the word sum of X_new as FP64."""
+    X32 = np.asarray(X, dtype=np.float64).astype(np.float32)
+    d = X32.shape[0]
+    Xw = split_words(X32, words)
+    T = word_product(Xw, Xw, mirror=True)
+    Nw = split_words((np.eye(d, dtype=np.float32) - T).astype(np.float32), words)
+    P = word_product(Xw, Nw, mirror=True)
+    Xn = (_word_total(Xw) + (np.float32(0.5) * P).astype(np.float32)).astype(np.float32)
+    return _word_total(split_words(Xn, words)).astype(np.float64)
+
+
+def ns_iterates_words(H, s: float, alpha_norm: float, m: int, words: int):
+    """X_0, ..., X_m of eq. NS in the split-BF16 bulk arithmetic (FP64
+    arrays of the word sums): X_0 = the word sum of fl32((H - sI)/alpha),
+    then ``ns_step_words`` m times."""
+    d = H.shape[0]
+    A = ((np.asarray(H, dtype=np.float64) - s * np.eye(d)) / alpha_norm).astype(np.float32)
+    X = _word_total(split_words(A, words)).astype(np.float64)
+    out = [X]
+    for _ in range(m):
+        X = ns_step_words(X, words)
+        out.append(X)
+    return out
 
 def ns_closed_form(w, V, s: float, alpha_norm: float, m: int):
     """X_m = Q diag(p_m((lambda_i - s)/alpha_norm)) Q^T: the iterate of eq. NS

@@ -23,6 +23,7 @@ enum ScalarSlot {
   SC_RESID2 = 2,     // ||X^2 - I||_F^2 of the iterate entering the last GEMM-1
   SC_TRACE = 3,      // trace of the newest iterate
   SC_SCRATCH = 4,    // first free slot
+  SC_SYM = 60,       // two slots: the symmetry check's maxima
   SC_COUNT = 64
 };
 

@@ -71,6 +71,10 @@ hipError_t launch_sym_gemm_words(int words, int tile, int mode, const uint16_t* 
                                  int64_t ps, int d, int dk, const int2* tiles, int ntiles,
                                  double* partials, hipStream_t st);
 
+// scal[slot] = max_{i<j} |H_ij - H_ji|, scal[slot + 1] = max |H_ij| over the
+// full d x d matrix (NaN if any entry is NaN).
+hipError_t launch_asym_max(const double* H, int64_t ldh, int d, double* scal, int slot,
+                           hipStream_t st);
 // ---- set-up: H (upper triangle) -> padded full FP64 copy, scale, X_0 ----
 hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, int dp,
                                hipStream_t st);

@@ -941,6 +941,50 @@ __global__ __launch_bounds__(256) void k_lincomb(int d, int nb, double a, const 
   }
 }
 
+// Symmetry check (opt-in): over the 64 x 64 tiles (I, J), I <= J, of the
+// full d x d matrix, max_{i<j} |H_ij - H_ji| and max |H_ij|.  The maxima
+// are taken on the bit patterns of the absolute values (non-negative
+// doubles order like their bits; a NaN's bits exceed every number's), so a
+// NaN anywhere survives into the result.
+__global__ __launch_bounds__(256) void k_asym_max(const double* __restrict__ H, int64_t ldh, int d,
+                                                  unsigned long long* __restrict__ out) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  __shared__ double t[64][65];
+  const int i0 = I * 64, j0 = J * 64;
+  unsigned long long amax = 0, asym = 0;
+  // Tile (J, I) transposed into LDS.
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    const int gi = j0 + r, gj = i0 + c;
+    double v = 0.0;
+    if (gi < d && gj < d) {
+      v = H[(int64_t)gi * ldh + gj];
+      amax = max(amax, (unsigned long long)__double_as_longlong(fabs(v)));
+    }
+    t[c][r] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    const int gi = i0 + r, gj = j0 + c;
+    if (gi < d && gj < d && gi < gj) {
+      const double v = H[(int64_t)gi * ldh + gj];
+      if (I != J) amax = max(amax, (unsigned long long)__double_as_longlong(fabs(v)));
+      asym = max(asym, (unsigned long long)__double_as_longlong(fabs(v - t[r][c])));
+    }
+  }
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    amax = max(amax, (unsigned long long)__shfl_xor((long long)amax, o, WAVE));
+    asym = max(asym, (unsigned long long)__shfl_xor((long long)asym, o, WAVE));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, asym);
+    atomicMax(out + 1, amax);
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 static inline int nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
@@ -948,6 +992,16 @@ hipError_t launch_mirror_upper(const double* H, int64_t ldh, int d, double* Hf, 
                                hipStream_t st) {
   const int nt = dp / 64;
   hipLaunchKernelGGL(k_mirror_upper, dim3(nt, nt), dim3(256), 0, st, H, ldh, d, Hf, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_asym_max(const double* H, int64_t ldh, int d, double* scal, int slot,
+                           hipStream_t st) {
+  hipError_t e = hipMemsetAsync(scal + slot, 0, 2 * sizeof(double), st);
+  if (e != hipSuccess) return e;
+  const int nt = nblocks(d, 64);
+  hipLaunchKernelGGL(k_asym_max, dim3(nt, nt), dim3(256), 0, st, H, ldh, d,
+                     reinterpret_cast<unsigned long long*>(scal + slot));
   return hipGetLastError();
 }
 

@@ -439,6 +439,27 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
       return fail(h, REFL_ERR_INVALID_ARG, "bad polish parameters");
   }
   if (!(p->tol >= 0.0)) return fail(h, REFL_ERR_INVALID_ARG, "tol must be >= 0");
+  if (p->check_symmetric != 0 && p->check_symmetric != 1)
+    return fail(h, REFL_ERR_INVALID_ARG, "check_symmetric must be 0 or 1");
+  if (p->check_symmetric && !(p->sym_tol >= 0.0 && std::isfinite(p->sym_tol)))
+    return fail(h, REFL_ERR_INVALID_ARG, "sym_tol must be finite and >= 0");
+  return REFL_OK;
+}
+
+// Opt-in symmetry check of H (params.check_symmetric): max_{i<j} |H_ij - H_ji|
+// against sym_tol max |H_ij|, both as maxima (no summation order), a NaN
+// anywhere failing.  slot and slot + 1 of scal receive the two maxima.
+refl_status_t check_symmetry(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                             double sym_tol, double* scal, int slot) {
+  hipStream_t st = h->stream;
+  HIPCHK(launch_asym_max(dH, ldh, (int)d, scal, slot, st));
+  double* hsc = h->pinned;
+  HIPCHK(hipMemcpyAsync(hsc + slot, scal + slot, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double asym = hsc[slot], amax = hsc[slot + 1];
+  if (!(asym <= sym_tol * amax) || !std::isfinite(amax))
+    return fail(h, REFL_ERR_NOT_SYMMETRIC, "max |H_ij - H_ji| = %.3e exceeds %.3e max |H_ij| (%.3e)",
+                asym, sym_tol, amax);
   return REFL_OK;
 }
 
@@ -874,8 +895,14 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   rs = ensure_workspace(h, need, &base);
   if (rs != REFL_OK) return rs;
   layout(w, base, d, p, LAYOUT_SIGN, h);
+  inf.bulk_tile = w.ts;
+  inf.bulk_words = p.precision == REFL_PREC_MIXED ? p.words : 0;
   hipStream_t st = h->stream;
   double* hsc = h->pinned;
+  if (p.check_symmetric) {
+    rs = check_symmetry(h, d, dH, ldh, p.sym_tol, w.scal, SC_SYM);
+    if (rs != REFL_OK) return rs;
+  }
 
   // ---- set-up ----
   std::vector<int2> tl;
@@ -1554,6 +1581,25 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     f.resid_fro = f.trace = f.rho = f.gamma = NaN;
     f.index_j = -1;
     f.s = params[p].s;
+    f.bulk_tile = tsv[p];
+  }
+
+  // Opt-in symmetry checks (the problems' scalar slots are free until the
+  // set-up writes them).
+  bool any_sym = false;
+  for (int p = 0; p < nprob; ++p) {
+    if (!params[p].check_symmetric) continue;
+    any_sym = true;
+    HIPCHK(launch_asym_max(dH[p], ldh[p], (int)d[p], bw.scal + BSC * p, 0, st));
+  }
+  if (any_sym) {
+    HIPCHK(hipMemcpyAsync(bp.scal, bw.scal, sizeof(double) * BSC * nprob, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int p = 0; p < nprob; ++p) {
+      if (!params[p].check_symmetric) continue;
+      const double asym = bp.scal[BSC * p], amax = bp.scal[BSC * p + 1];
+      if (!(asym <= params[p].sym_tol * amax) || !std::isfinite(amax)) pst[p] = REFL_ERR_NOT_SYMMETRIC;
+    }
   }
 
   // ---- set-up: descriptors, then five grouped launches ----
@@ -1610,6 +1656,8 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   for (int p = 0; p < nprob; ++p) {
     inf[p].alpha = bp.scal[BSC * p + SC_ALPHA];
     trace_cur[p] = bp.trace[p];
+    if (pst[p] != REFL_OK)
+      continue;
     if (bp.scal[BSC * p + SC_NONFINITE] > 0.0 || !(inf[p].alpha > 0.0) ||
         !std::isfinite(inf[p].alpha))
       pst[p] = REFL_ERR_NOT_FINITE;
@@ -1879,6 +1927,8 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
       first = pst[p];
       if (pst[p] == REFL_ERR_NOT_FINITE)
         fail(h, first, "problem %d: H or the iterate is not finite", p);
+      else if (pst[p] == REFL_ERR_NOT_SYMMETRIC)
+        fail(h, first, "problem %d: H is not symmetric to sym_tol", p);
       else if (pst[p] == REFL_ERR_NOT_CONVERGED)
         fail(h, first, "problem %d: no convergence after %d steps (resid %.3e)", p, f.ns_steps,
              f.resid_fro);
@@ -2008,6 +2058,11 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   double* hsc = h->pinned;
   const bool fp64 = g.fp64, reverse = p.grad_mode == REFL_GRAD_REVERSE;
   const int dd = (int)d, dp = g.dp;
+  inf.bulk_tile = g.ts;
+  if (p.check_symmetric) {
+    rs = check_symmetry(h, d, dH, ldh, p.sym_tol, g.scal, SC_SYM);
+    if (rs != REFL_OK) return rs;
+  }
 
   // ---- set-up ----
   {
@@ -2267,6 +2322,8 @@ refl_status_t refl_params_default(refl_params_t* p) {
   p->grad_mode = REFL_GRAD_REVERSE;
   p->ckpt_every = 0;
   p->cg_f32 = REFL_CG_AUTO;
+  p->check_symmetric = 0;
+  p->sym_tol = 0.0;
   return REFL_OK;
 }
 
@@ -2599,6 +2656,7 @@ const char* refl_status_string(refl_status_t s) {
     case REFL_ERR_NOT_CONVERGED: return "REFL_ERR_NOT_CONVERGED";
     case REFL_ERR_NOT_ADMISSIBLE: return "REFL_ERR_NOT_ADMISSIBLE";
     case REFL_ERR_NO_GAP: return "REFL_ERR_NO_GAP";
+    case REFL_ERR_NOT_SYMMETRIC: return "REFL_ERR_NOT_SYMMETRIC";
     case REFL_ERR_NOT_FINITE: return "REFL_ERR_NOT_FINITE";
     case REFL_ERR_UNSUPPORTED: return "REFL_ERR_UNSUPPORTED";
   }

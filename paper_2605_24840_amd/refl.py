@@ -16,12 +16,13 @@ LIB_PATH = os.path.join(_PKG, "librefl.so")
 REFL_OK = 0
 STATUS = {0: "REFL_OK", 1: "REFL_ERR_INVALID_ARG", 2: "REFL_ERR_DEVICE", 3: "REFL_ERR_NO_MEMORY",
           4: "REFL_ERR_NOT_CONVERGED", 5: "REFL_ERR_NOT_ADMISSIBLE", 6: "REFL_ERR_NO_GAP",
-          7: "REFL_ERR_NOT_FINITE", 8: "REFL_ERR_UNSUPPORTED"}
+          7: "REFL_ERR_NOT_SYMMETRIC", 8: "REFL_ERR_UNSUPPORTED", 9: "REFL_ERR_NOT_FINITE"}
 (REFL_ERR_INVALID_ARG, REFL_ERR_DEVICE, REFL_ERR_NO_MEMORY, REFL_ERR_NOT_CONVERGED,
- REFL_ERR_NOT_ADMISSIBLE, REFL_ERR_NO_GAP, REFL_ERR_NOT_FINITE, REFL_ERR_UNSUPPORTED) = range(1, 9)
+ REFL_ERR_NOT_ADMISSIBLE, REFL_ERR_NO_GAP, REFL_ERR_NOT_SYMMETRIC, REFL_ERR_UNSUPPORTED,
+ REFL_ERR_NOT_FINITE) = range(1, 10)
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 SHIFT = {"given": 0, "lanczos": 1}
-SCALE = {"inf": 0, "given": 1, "lanczos": 2, "fro": 3}
+SCALE = {"inf": 0, "fro": 1, "lanczos": 2, "given": 3}
 GRAD_MODE = {"reverse": 0, "tangent": 1}
 CG_PREC = {"fp64": 0, "fp32": 1, "auto": 2}
 # Largest orders the library runs as one LDS-resident launch (refl_sign and
@@ -44,7 +45,8 @@ class refl_params_t(ctypes.Structure):
                 ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int32),
                 ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("timing", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("cg_f32", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("cg_f32", ctypes.c_int32),
+                ("check_symmetric", ctypes.c_int32), ("sym_tol", ctypes.c_double)]
 
 
 class refl_policy_params_t(ctypes.Structure):
@@ -79,7 +81,8 @@ class refl_info_t(ctypes.Structure):
                 ("ms_bulk", ctypes.c_double), ("ms_polish", ctypes.c_double),
                 ("ms_total", ctypes.c_double), ("ms_gemm", ctypes.c_double),
                 ("gemm_launches", ctypes.c_int32), ("rho", ctypes.c_double),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("bulk_tile", ctypes.c_int32),
+                ("bulk_words", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -344,11 +347,13 @@ class Handle:
 
 def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
                 alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
-                timing=False, scale=None, grad_mode="reverse", ckpt_every=0, cg_prec="auto"):
+                timing=False, scale=None, grad_mode="reverse", ckpt_every=0, cg_prec="auto",
+                check_symmetric=False, sym_tol=0.0):
     """refl_params_t from keyword arguments.  s=None estimates the shift by
     block Lanczos; scale is "inf" (default), "given" (with alpha), "lanczos"
     (1.05 times the Lanczos spectral-radius estimate) or "fro"; k=0 with a
-    given s reports the certified index instead of testing one."""
+    given s reports the certified index instead of testing one;
+    check_symmetric reads H in full and rejects max|H - H^T| > sym_tol max|H|."""
     p = refl_params_default()
     p.k = int(k)
     p.shift_mode = SHIFT["lanczos"] if s is None else SHIFT["given"]
@@ -375,6 +380,8 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     p.grad_mode = GRAD_MODE[grad_mode]
     p.ckpt_every = int(ckpt_every)
     p.cg_f32 = CG_PREC[cg_prec]
+    p.check_symmetric = 1 if check_symmetric else 0
+    p.sym_tol = float(sym_tol)
     return p
 
 

@@ -44,6 +44,8 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(refl_params_t, lanczos_steps));\n"
         'printf("%zu %zu %zu %zu\\n", offsetof(refl_info_t, s), offsetof(refl_info_t, dk_bound),'
         " offsetof(refl_info_t, ms_total), offsetof(refl_info_t, gamma));\n"
+        'printf("%zu %zu %zu %zu\\n", offsetof(refl_params_t, check_symmetric), offsetof(refl_params_t, sym_tol),'
+        " offsetof(refl_info_t, bulk_tile), offsetof(refl_info_t, bulk_words));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
@@ -57,12 +59,55 @@ def test_struct_layout_matches_header(tmp_path):
     o = list(map(int, lines[2].split()))
     assert o == [refl.refl_info_t.s.offset, refl.refl_info_t.dk_bound.offset, refl.refl_info_t.ms_total.offset,
                  refl.refl_info_t.gamma.offset]
+    o = list(map(int, lines[3].split()))
+    assert o == [refl.refl_params_t.check_symmetric.offset, refl.refl_params_t.sym_tol.offset,
+                 refl.refl_info_t.bulk_tile.offset, refl.refl_info_t.bulk_words.offset]
+
+
+def _header_enum(name):
+    """Enumerator -> value of the typedef enum ``name`` in include/refl.h."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef enum\s*\{([^{}]*)\}\s*" + name + r"\s*;", src)
+    assert m, name
+    body = m.group(1)
+    out = {}
+    for item in body.split(","):
+        item = item.strip()
+        if item:
+            k, v = item.split("=")
+            out[k.strip()] = int(v)
+    return out
+
+
+def test_enum_values_match_header_and_binding():
+    """The binding's code tables equal the header's enumerators, and the
+    status and scale codes are those of the boundary sketch (statuses
+    0..8 in its order, REFL_ERR_NOT_FINITE added as 9; scales INF, FRO,
+    LANCZOS, GIVEN = 0..3)."""
+    st = _header_enum("refl_status_t")
+    assert {v: k for k, v in st.items()} == refl.STATUS
+    assert [st[n] for n in ("REFL_OK", "REFL_ERR_INVALID_ARG", "REFL_ERR_DEVICE", "REFL_ERR_NO_MEMORY",
+                            "REFL_ERR_NOT_CONVERGED", "REFL_ERR_NOT_ADMISSIBLE", "REFL_ERR_NO_GAP",
+                            "REFL_ERR_NOT_SYMMETRIC", "REFL_ERR_UNSUPPORTED",
+                            "REFL_ERR_NOT_FINITE")] == list(range(10))
+    sc = _header_enum("refl_scale_mode_t")
+    assert sc == {"REFL_SCALE_INF": 0, "REFL_SCALE_FRO": 1, "REFL_SCALE_LANCZOS": 2, "REFL_SCALE_GIVEN": 3}
+    assert {"REFL_SCALE_" + k.upper(): v for k, v in refl.SCALE.items()} == sc
+    pr = _header_enum("refl_precision_t")
+    assert {"REFL_PREC_" + k.upper(): v for k, v in refl.PRECISION.items()} == pr
+    cg = _header_enum("refl_cg_prec_t")
+    assert {"REFL_CG_" + k.upper(): v for k, v in refl.CG_PREC.items()} == cg
+    gm = _header_enum("refl_grad_mode_t")
+    assert {"REFL_GRAD_" + k.upper(): v for k, v in refl.GRAD_MODE.items()} == gm
+    po = _header_enum("refl_policy_mode_t")
+    assert {"REFL_POLICY_" + k.upper(): v for k, v in refl.POLICY.items()} == po
 
 
 def test_params_default_and_status_strings():
     p = refl.refl_params_default()
     assert (p.k, p.tol, p.max_iter, p.fixed_steps, p.words, p.polish_sweeps) == (1, 1e-12, 100, 0, 2, 2)
     assert p.precision == refl.PRECISION["fp64"] and p.shift_mode == refl.SHIFT["given"]
+    assert p.check_symmetric == 0 and p.sym_tol == 0.0 and p.scale_mode == refl.SCALE["inf"]
     for code, name in refl.STATUS.items():
         assert refl.refl_status_string(code) == name
     assert refl.refl_status_string(99) == "REFL_ERR_UNKNOWN"

@@ -220,11 +220,12 @@ def test_batched_argument_errors(R, handle):
 def test_batched_full_workload_fp32(R, handle):
     """The 256-problem workload (d uniform over 128/256/512/1024, k in 1..16,
     relative gap log-uniform in [1e-3, 1e-1], midpoint shifts) in FP32: every
-    problem certifies index k; a sample equals single solves bit for bit and
-    meets the bound against the exact R_k."""
+    problem certifies index k and meets the bound against its exact R_k
+    (checked on the device for all 256); a sample equals single solves bit
+    for bit."""
     specs = inputs.batch_specs(256, seed=0)
     _say("generating 256 planted problems")
-    Hs, ks, ss, keep = [], [], [], {}
+    Hs, ks, ss, exact = [], [], [], []
     sample = {0, 1, 37, 100, 200, 255}
     for p, spec in enumerate(specs):
         H, lam, Q = inputs.batch_problem(spec)
@@ -233,8 +234,7 @@ def test_batched_full_workload_fp32(R, handle):
         Hs.append(torch.from_numpy(H).to("cuda:0"))
         ks.append(k)
         ss.append(s)
-        if p in sample:
-            keep[p] = (H, lam, Q)
+        exact.append((np.ascontiguousarray(Q[:, :k]), float(s - lam[k - 1])))
     _say("batched fp32 solve of 256 problems")
     Rs, infos, sts, st = R.sign_batched(Hs, ks, ss, handle=handle, precision="fp32", tol=1e-3,
                                         check=False)
@@ -243,12 +243,23 @@ def test_batched_full_workload_fp32(R, handle):
     assert all(infos[p]["index_j"] == ks[p] for p in range(256))
     steps = [i["ns_steps"] for i in infos]
     _say(f"  steps min={min(steps)} max={max(steps)} batch ms={infos[0]['ms_total']:.1f}")
+    worst = 0.0
+    for p in range(256):
+        Qk, half_gap = exact[p]
+        d = Qk.shape[0]
+        Qg = torch.from_numpy(Qk).to("cuda:0")
+        E = Rs[p] - torch.eye(d, dtype=torch.float64, device="cuda:0")
+        E += 2.0 * (Qg @ Qg.T)
+        err = float(torch.linalg.norm(E))
+        gamma = half_gap / infos[p]["alpha"]
+        bound = infos[p]["resid_fro"] + 4 * U32 * np.sqrt(d) / gamma
+        worst = max(worst, err / bound)
+        assert err <= bound, (p, d, ks[p], err, bound)
+    _say(f"  all 256 against the exact R_k: worst err/bound = {worst:.3f}")
     for p in sorted(sample):
-        H, lam, Q = keep[p]
         R1, i1, st1 = R.sign(Hs[p], ks[p], ss[p], handle=handle, precision="fp32", tol=1e-3,
                              check=False)
-        err = _check_exact("fp32", H, lam, Q, ks[p], ss[p], Rs[p], infos[p])
-        _say(f"  p={p} d={H.shape[0]} k={ks[p]} steps={infos[p]['ns_steps']} err={err:.2e}")
+        _say(f"  p={p} d={Hs[p].shape[0]} k={ks[p]} steps={infos[p]['ns_steps']}")
         assert st1 == 0 and torch.equal(Rs[p], R1)
 
 

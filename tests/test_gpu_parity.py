@@ -205,6 +205,44 @@ def test_error_paths(R, handle):
     assert R.STATUS[st] == "REFL_ERR_NOT_CONVERGED" and info["index_j"] == -1
 
 
+def test_symmetry_check(R, handle):
+    """params.check_symmetric: H is read in full and rejected with
+    NOT_SYMMETRIC when max |H_ij - H_ji| exceeds sym_tol max |H_ij| (or a
+    NaN sits anywhere); an exactly symmetric H passes and gives the same R
+    as without the check; off by default, when the lower triangle is never
+    read.  Also through refl_sign_apply, refl_sign_grad and a batch."""
+    H, lam, Q, s = _cfg0()
+    Hg = _gpu(H)
+    R0, _, st0 = R.sign(Hg, 4, s, handle=handle)
+    R1, _, st1 = R.sign(Hg, 4, s, handle=handle, check_symmetric=True)
+    assert st0 == 0 and st1 == 0 and torch.equal(R0, R1)
+    Ha = H.copy()
+    Ha[10, 3] += 1e-9                       # lower triangle only
+    amax = float(np.abs(Ha).max())
+    for tol, want in ((0.0, "REFL_ERR_NOT_SYMMETRIC"), (0.5e-9 / amax, "REFL_ERR_NOT_SYMMETRIC"),
+                      (2e-9 / amax, "REFL_OK")):
+        _, _, st = R.sign(_gpu(Ha), 4, s, handle=handle, check_symmetric=True, sym_tol=tol, check=False)
+        _say(f"symmetry check tol={tol:.1e}: {R.STATUS[st]}")
+        assert R.STATUS[st] == want
+    _, _, st = R.sign(_gpu(Ha), 4, s, handle=handle, check=False)
+    assert st == 0                          # off: the lower triangle is not read
+    Hn = H.copy()
+    Hn[40, 2] = np.nan
+    _, _, st = R.sign(_gpu(Hn), 4, s, handle=handle, check_symmetric=True, sym_tol=1.0, check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_SYMMETRIC"
+    V = _gpu(np.ones((64, 2)))
+    _, _, st = R.sign_apply(_gpu(Ha), V, 4, s, handle=handle, precision="mixed", check_symmetric=True,
+                            check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_SYMMETRIC"
+    G = _gpu(np.eye(64))
+    *_, st = R.sign_grad(_gpu(Ha), G, 4, s, handle=handle, check_symmetric=True, check=False)
+    assert R.STATUS[st] == "REFL_ERR_NOT_SYMMETRIC"
+    Rs, infos, sts, st = R.sign_batched([Hg, _gpu(Ha)], [4, 4], [s, s], handle=handle,
+                                        precision="fp64", check_symmetric=True, check=False)
+    assert [R.STATUS[x] for x in sts] == ["REFL_OK", "REFL_ERR_NOT_SYMMETRIC"]
+    assert R.STATUS[st] == "REFL_ERR_NOT_SYMMETRIC" and torch.equal(Rs[0], R0)
+
+
 def test_index_report_mode(R, handle):
     """k = 0: no target; the certified index j is reported and R = sgn(H - sI)
     for that j (the reflector R_j, Prop. 2.1), including the definite cases
@@ -259,17 +297,44 @@ def test_fp32_controlled_spectra(R, handle, grel, theta):
 
 # ----------------------------------------------------------------- MIXED
 def test_mixed_bulk_iterate(R, handle):
-    d, k = 256, 4
+    """Split-word bulk iterates against the oracle's model of the same
+    arithmetic (oracle.ns_step_words: BF16 words by round-to-nearest-even,
+    the kept word products, FP32 results), step by step: the library's X_j
+    against one model step from the library's X_{j-1}.  The two differ only
+    in the order of the FP32 accumulation of each product, bounded by
+    gamma_n = n u32 times sum_k |a_ik||b_kj| <= ||A||_2 ||B||_2 <= 1 (rows
+    of X and N have 2-norm at most ||X||_2, ||N||_2 <= 1), with n = the
+    number of word products times K; one step has two products and N's
+    error enters the second, so each step is within 3 gamma_n.  The FP64
+    iterate of eq. NS is then within the model's own distance from it
+    plus that bound times the steps."""
+    d, k, m = 256, 4, 8
     _say(f"mixed bulk fixed steps d={d}")
     H, lam, Q = inputs.planted_hessian(d, k, 0.2, 1)
     s = 0.5 * (lam[k - 1] + lam[k])
+    alpha = oracle.inf_norm_shifted(H, s)
+    Hg = _gpu(H)
+    X64 = oracle.ns_iterates(H, s, alpha, m)
     for words in (2, 3):
-        Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="mixed", words=words, fixed_steps=8)
-        alpha = oracle.inf_norm_shifted(H, s)
-        X8 = oracle.ns_iterates(H, s, alpha, 8)[8]
-        err = np.abs(Rg.cpu().numpy() - X8).max()
-        _say(f"  words={words} max|X_8 - oracle| = {err:.2e}")
-        assert err < (1e-3 if words == 2 else 1e-5)
+        nprod = 3 if words == 2 else 6
+        step_tol = 3.0 * nprod * d * 2.0 ** -24
+        model = oracle.ns_iterates_words(H, s, alpha, m, words)
+        prev = None
+        worst = 0.0
+        for j in range(1, m + 1):
+            Rg, info, st = R.sign(Hg, k, s, handle=handle, precision="mixed", words=words, fixed_steps=j)
+            assert st == 0 and info["ns_steps"] == j
+            Xj = Rg.cpu().numpy()
+            ref = model[1] if j == 1 else oracle.ns_step_words(prev, words)
+            e = float(np.abs(Xj - ref).max())
+            worst = max(worst, e)
+            assert e <= step_tol, (words, j, e, step_tol)
+            prev = Xj
+        e_model = float(np.abs(model[m] - X64[m]).max())
+        e64 = float(np.abs(prev - X64[m]).max())
+        _say(f"  words={words} per-step max|X_j - model step| = {worst:.2e} (bound {step_tol:.1e}); "
+             f"max|X_8 - X_8(fp64)| = {e64:.2e}, model {e_model:.2e}")
+        assert e64 <= e_model + m * 1.5 ** m * step_tol
 
 
 @pytest.mark.parametrize("tile", ["128", "192"])

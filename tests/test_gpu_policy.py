@@ -3,11 +3,12 @@ with the certificates of Prop. 4.2) against the oracle's policy.
 
 Sequence: H_n = H_0 + n t D, n = 0..11, with H_0 planted (d = 300, k = 5,
 gap 0.1, seed 40), D a symmetric direction of unit Frobenius norm (seed 41)
-and t = 0.004.  The oracle policy is fed the library's Lanczos estimates on
-the calls where it refreshes and the FP64 drift ||H_n - H_ref||_F from
-numpy; its decisions (refresh or reuse) and shifts must match the library's
-(shifts and margins to 1e-12 relative: the drift norm is summed in another
-order).  Every returned shift must be truly admissible (exact eigenvalues),
+and t = 0.004.  In the first test the oracle policy is fed the library's
+Lanczos estimates on the calls where it refreshes and the FP64 drift
+||H_n - H_ref||_F from numpy; its decisions (refresh or reuse) and shifts
+must match the library's (shifts and margins to 1e-12 relative: the drift
+norm is summed in another order).  In the end-to-end test the oracle
+policy runs its own block Lanczos (oracle.block_lanczos, same seed).  Every returned shift must be truly admissible (exact eigenvalues),
 and the sign iteration with it must certify index k.
 """
 import numpy as np
@@ -85,6 +86,49 @@ def test_policy_sequence_matches_oracle(R, handle, sequence, mode, kw):
         assert refreshes < len(Hs) - 4
     else:
         assert refreshes == len(Hs)
+    pol.close()
+
+
+
+@pytest.mark.parametrize("mode,kw", [("midpoint", {}), ("damped", {"beta": 0.4, "clip": 0.25}),
+                                     ("reuse", {"tau": 0.5})])
+def test_policy_end_to_end_oracle_lanczos(R, handle, sequence, mode, kw):
+    """The whole policy against the oracle's: the oracle policy's estimator is
+    oracle.block_lanczos on the same H with the same seed (seeded start block
+    on every refresh, no warm start), and its drift is the FP64 numpy norm.
+    The two sides then differ only in rounding, so the shifts agree to the
+    Lanczos parity tolerance of 1e-9 ||H||, the margins to that plus 1e-6 of
+    the residual radius, and every refresh-or-reuse decision is the same."""
+    Hs, k = sequence
+    seed = 5
+    pol = R.ShiftPolicy(handle, mode, k, seed=seed, warm_start=False, **kw)
+    state, Href = None, None
+    for n, H in enumerate(Hs):
+        hn = float(np.abs(H).sum(axis=1).max())
+        Hg = torch.from_numpy(H).to("cuda:0")
+        s, info, st = pol.shift(Hg)
+        drift = float(np.linalg.norm(H - Href)) if Href is not None else None
+        ora = {}
+
+        def est():
+            r = oracle.block_lanczos(H, k, seed=seed)
+            ora.update(r)
+            return r["lam_k"], r["lam_k1"], r["eps"]
+        r = oracle.policy_step(mode, state, est, drift=drift, **kw)
+        _say(f"{mode} n={n}: s={s:.12f} / {r['s']:.12f} refreshed={info['refreshed']} / "
+             f"{r['refreshed']} margin={info['margin']:.6e} / {r['margin']:.6e}")
+        assert st == 0
+        assert bool(info["refreshed"]) == r["refreshed"]
+        assert abs(s - r["s"]) <= 1e-9 * hn
+        tol_eps = 1e-6 * (ora["eps"] if ora else info["eps"])
+        assert abs(info["margin"] - r["margin"]) <= 2e-9 * hn + tol_eps
+        if r["refreshed"]:
+            assert info["lanczos_steps"] == ora["steps"]
+            assert abs(info["lam_k"] - ora["lam_k"]) <= 1e-9 * hn
+            assert abs(info["lam_k1"] - ora["lam_k1"]) <= 1e-9 * hn
+            assert abs(info["eps"] - ora["eps"]) <= 1e-6 * ora["eps"] + 1e-12 * hn
+            Href = H
+        state = r["state"]
     pol.close()
 
 

@@ -360,6 +360,150 @@ def test_scale_norms_bound_spectral_radius():
     assert abs(oracle.fro_norm_shifted(D, 0.25) - np.sqrt(0.0625 + 5.0625 + 1.5625)) < 1e-15
 
 
+
+
+# ------------------------------------------- split-BF16 arithmetic model
+def test_bf16_round_ties_to_even_and_exact_values():
+    """BF16 keeps 8 significant bits: values with at most 8 are unchanged;
+    halfway cases go to the even significand (1 + 2^-8 -> 1, 1 + 3 2^-8 ->
+    1 + 2^-6); otherwise the nearest; sign symmetric; |x - bf16(x)| <= 2^-8 |x|
+    (half a unit in the last of 8 places)."""
+    x = np.float32([1.0, 1.5, -0.75, 2.0 ** -20 * 1.5, 129.0])
+    assert np.array_equal(oracle.bf16_round(x), x)
+    t = oracle.bf16_round(np.float32([1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 1 + 2 ** -8 + 2 ** -20]))
+    assert t[0] == 1.0 and t[1] == np.float32(1 + 2 ** -6) and t[2] == -1.0
+    assert t[3] == np.float32(1 + 2 ** -7)
+    r = np.random.default_rng(3).standard_normal(10000).astype(np.float32)
+    b = oracle.bf16_round(r)
+    assert np.all(np.abs(r.astype(np.float64) - b) <= 2.0 ** -8 * np.abs(r))
+    assert np.max(np.abs(r.astype(np.float64) - b) / np.abs(r)) > 2.0 ** -9
+    # b has at most 8 significant bits: b * 2^(8 - e) is an integer.
+    f, e = np.frexp(b.astype(np.float64))
+    assert np.all(np.rint(f * 256) == f * 256)
+
+
+def test_split_words_exactness():
+    """Three words hold any FP32 value exactly (3 x 8 bits >= 24); two words
+    are within 2^-16 relative (the first remainder is at most 2^-8 |x|, the
+    second rounding loses at most 2^-8 of that); each word is a BF16 value."""
+    r = np.random.default_rng(4).standard_normal(20000).astype(np.float32)
+    w3 = oracle.split_words(r, 3)
+    assert np.array_equal(((w3[0] + w3[1]).astype(np.float32) + w3[2]).astype(np.float32), r)
+    w2 = oracle.split_words(r, 2)
+    s2 = w2[0].astype(np.float64) + w2[1]
+    assert np.all(np.abs(s2 - r) <= 2.0 ** -16 * np.abs(r))
+    assert np.max(np.abs(s2 - r) / np.abs(r)) > 2.0 ** -20    # not exact in general
+    for w in w3:
+        assert np.array_equal(oracle.bf16_round(w), w)
+
+
+def test_word_product_drops_only_low_weight_terms():
+    """For one-word matrices (every entry a BF16 value) the W = 2 product is
+    the exact product rounded to FP32 (the dropped term lo*lo is zero); for
+    general FP32 matrices it differs from the exact product by the dropped
+    lo*lo term plus the word and FP32 roundings, and W = 3 is closer."""
+    rng = np.random.default_rng(5)
+    A = oracle.bf16_round(rng.standard_normal((24, 24)).astype(np.float32))
+    B = oracle.bf16_round(rng.standard_normal((24, 24)).astype(np.float32))
+    P = oracle.word_product(oracle.split_words(A, 2), oracle.split_words(B, 2))
+    assert np.array_equal(P, (A.astype(np.float64) @ B.astype(np.float64)).astype(np.float32))
+    A = rng.standard_normal((40, 40)).astype(np.float32)
+    B = rng.standard_normal((40, 40)).astype(np.float32)
+    ex = A.astype(np.float64) @ B.astype(np.float64)
+    scale = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64)
+    e2 = np.abs(oracle.word_product(oracle.split_words(A, 2), oracle.split_words(B, 2)) - ex) / scale
+    e3 = np.abs(oracle.word_product(oracle.split_words(A, 3), oracle.split_words(B, 3)) - ex) / scale
+    assert e2.max() <= 2.0 ** -15 and e2.max() > 2.0 ** -20
+    assert e3.max() <= 2.0 ** -22 and e3.max() < e2.max() / 16
+
+
+def test_ns_iterates_words_track_fp64_iterates():
+    """The split-word iterates follow the FP64 iterates of eq. NS to the
+    word precision: W = 3 (about FP32) and W = 2 (about 16 bits) stay within
+    their unit roundoff times the step count and the growth 1.5^m of the
+    step's derivative (section 3.3, eq. NS), and W = 3 is closer."""
+    H, lam, Q = inputs.planted_hessian(64, 4, 0.1, 0)
+    s = 0.5 * (lam[3] + lam[4])
+    a = oracle.inf_norm_shifted(H, s)
+    m = 8
+    X = oracle.ns_iterates(H, s, a, m)
+    X2 = oracle.ns_iterates_words(H, s, a, m, 2)
+    X3 = oracle.ns_iterates_words(H, s, a, m, 3)
+    growth = m * 1.5 ** m
+    e2 = max(np.abs(X2[j] - X[j]).max() for j in range(m + 1))
+    e3 = max(np.abs(X3[j] - X[j]).max() for j in range(m + 1))
+    assert e2 <= 2.0 ** -16 * growth and e3 <= 2.0 ** -23 * growth
+    assert e3 < e2 / 32
+    assert np.array_equal(X2[0], X2[0].T) and np.array_equal(X2[m], X2[m].T)
+
+
+# ------------------------------------------------------ certificate values
+def test_certificates_diagonal_closed_form():
+    """Diagonal X = diag(x): trace = sum x_i, ||X^2 - I||_F = sqrt(sum (x_i^2 - 1)^2)
+    (Frobenius, not the spectral max |x_i^2 - 1|), and for diagonal H the
+    commutator vanishes."""
+    x = np.array([0.5, -0.9, 1.2, -1.0, 0.0, 0.99])
+    h = np.array([3.0, -1.0, 0.25, 2.0, -0.5, 1.0])
+    c = oracle.certificates(np.diag(h), np.diag(x), 0.0)
+    assert c["trace"] == float(x.sum())
+    want = float(np.sqrt(np.sum((x * x - 1.0) ** 2)))
+    assert abs(c["resid_fro"] - want) <= 1e-15 * want
+    assert abs(c["resid_fro"] - float(np.max(np.abs(x * x - 1.0)))) > 0.1
+    assert c["commutator_fro"] == 0.0
+
+
+def test_certificates_commutator_entrywise_closed_form():
+    """For diagonal H = diag(h) and any symmetric X, (HX - XH)_ij =
+    (h_i - h_j) x_ij, so ||HX - XH||_F^2 = sum_ij (h_i - h_j)^2 x_ij^2; the
+    anticommutator HX + XH (a sign slip) gives sum (h_i + h_j)^2 x_ij^2
+    instead, and the spectral norm of the commutator is smaller."""
+    rng = np.random.default_rng(7)
+    d = 9
+    h = rng.uniform(-2.0, 2.0, d)
+    Z = rng.standard_normal((d, d))
+    X = 0.5 * (Z + Z.T)
+    c = oracle.certificates(np.diag(h), X, 0.3)
+    dh = h[:, None] - h[None, :]
+    want = float(np.sqrt(np.sum(dh * dh * X * X)))
+    assert abs(c["commutator_fro"] - want) <= 1e-14 * want
+    sh = h[:, None] + h[None, :]
+    assert abs(c["commutator_fro"] - float(np.sqrt(np.sum(sh * sh * X * X)))) > 1e-3 * want
+    C = np.diag(h) @ X - X @ np.diag(h)
+    assert abs(c["commutator_fro"] - oracle.spectral_norm_sym(C @ C.T) ** 0.5) > 1e-3 * want
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_certificates_planted_spectral_closed_form(k):
+    """X = Q diag(p) Q^T with the planted Q of H = Q diag(lam) Q^T: X commutes
+    with H (commutator 0 to rounding), trace = sum p_i and ||X^2 - I||_F =
+    sqrt(sum (p_i^2 - 1)^2) without any eigensolver; with X = p_m((H - sI)/a)
+    for the generator's shift this is the iterate whose trace tends to
+    d - 2k (Lemma 3.4)."""
+    d = 40
+    H, lam, Q = inputs.planted_hessian(d, k, 0.2, 11)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    a = float(np.max(np.abs(lam - s))) * 1.5
+    p = oracle.ns_poly((lam - s) / a, 6)
+    X = (Q * p) @ Q.T
+    c = oracle.certificates(H, X, s)
+    assert abs(c["trace"] - float(p.sum())) <= 1e-12 * d
+    want = float(np.sqrt(np.sum((p * p - 1.0) ** 2)))
+    assert abs(c["resid_fro"] - want) <= 1e-12 * max(want, 1.0)
+    assert c["commutator_fro"] <= 1e-12 * d
+    # A rotation of X that breaks commutation gives the entrywise value in the
+    # eigenbasis of H: ||[Lam, Q^T X' Q]||_F for X' = Q' diag(p) Q'^T.
+    Q2 = inputs.haar_orthogonal(d, np.random.default_rng(12))
+    X2 = (Q2 * p) @ Q2.T
+    c2 = oracle.certificates(H, X2, s)
+    B = Q.T @ X2 @ Q
+    dl = lam[:, None] - lam[None, :]
+    want2 = float(np.sqrt(np.sum(dl * dl * B * B)))
+    assert abs(c2["commutator_fro"] - want2) <= 1e-11 * want2
+    # Orthogonal invariance: trace and residual do not change with the rotation.
+    assert abs(c2["trace"] - c["trace"]) <= 1e-12 * d
+    assert abs(c2["resid_fro"] - c["resid_fro"]) <= 1e-12 * max(want, 1.0)
+
+
 # ------------------------------------------------------------ derivatives
 def _sym(rng, d):
     Z = rng.standard_normal((d, d))

@@ -94,7 +94,10 @@ typedef struct {
   int32_t scale_mode;   /* refl_scale_mode_t */
   int32_t precision;    /* refl_precision_t */
   double alpha;         /* scale (scale_mode == REFL_SCALE_GIVEN), must exceed 0 */
-  double tol;           /* FP64/FP32: stop when ||X^2 - I||_F < tol.
+  double tol;           /* FP64/FP32: stop when ||X^2 - I||_F < tol; a residual below 0.1
+                           that has not halved over two steps is the arithmetic's floor
+                           (exact steps shrink it far more), and the iteration stops there
+                           with REFL_ERR_NOT_CONVERGED.
                            MIXED: stop the FP64 correction when the certified bound on
                            ||R - R_k||_F falls below tol */
   int32_t max_iter;     /* cap on Newton-Schulz steps (default 100) */
@@ -221,7 +224,14 @@ refl_status_t refl_set_workspace(refl_handle_t h, void *dptr, size_t bytes);
  *
  * Status: REFL_OK when the margin m_hat = min(s - lam_k, lam_k1 - s)
  * exceeds eps (Prop. 4.2), REFL_ERR_NOT_ADMISSIBLE when it does not at the
- * step cap, REFL_ERR_NO_GAP when the two estimates coincide.  Device
+ * step cap, REFL_ERR_NO_GAP when the two estimates coincide.  REFL_OK
+ * certifies the shift only under the premise of Prop. 4.2 that theta_k and
+ * theta_k+1 estimate lambda_k and lambda_k+1: a residual radius holds SOME
+ * eigenvalue, and an eigenvalue below theta_k+1 that the Krylov space
+ * missed (multiplicity above b, a start block deficient in its direction)
+ * would put s in another gap.  refl_sign's index certificate (exactly k
+ * negative eigenvalues of the iterate) is what confirms the index; the
+ * shift policies inherit the same premise.  Device
  * workspace: as refl_workspace_size for shift_mode = REFL_SHIFT_LANCZOS. */
 refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
                                   int32_t k, int32_t steps, uint64_t seed, double *s,
@@ -307,8 +317,13 @@ refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, c
  *
  * Outputs: dGrad (d x d, ldgr, symmetric), *loss = <G, R_m> (may be NULL),
  * and R_m into dR (ldr) unless dR is NULL.  Status and info as refl_sign.
- * Device workspace is allocated by the library (about (ceil(cap/c) + 2c + 8)
- * dp^2 elements of the bulk precision, cap = fixed_steps or max_iter). */
+ * Device workspace is allocated by the library, in dp^2 elements of the bulk
+ * precision (dp = d rounded up to the tile, cap = fixed_steps or max_iter):
+ * about 2 (cap + 1) + 8 when every iterate is kept (ckpt_every = 0, reverse
+ * mode, and that fits in 16 GiB: sized for the cap, not the steps taken),
+ * else about ceil(cap / c) + 2c + 8 for checkpoints every c steps.  A
+ * caller that must bound memory passes ckpt_every > 0 (or a smaller
+ * max_iter). */
 refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
                              const refl_params_t *p, const double *dG, int64_t ldg,
                              double *dGrad, int64_t ldgr, double *loss, double *dR, int64_t ldr,

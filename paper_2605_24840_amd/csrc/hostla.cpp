@@ -1,7 +1,13 @@
 // Small dense linear algebra on the host for the k x k problems of the
 // driver: symmetric eigen-decomposition by Householder reduction to
 // tridiagonal form followed by the implicit QL iteration with shifts, and a
-// Cholesky factorisation.  For the block tridiagonal matrices of the
+// Cholesky factorisation.  The QL stage is the published procedure of
+// Bowdler, Martin, Reinsch and Wilkinson ("The QR and QL algorithms for
+// symmetric matrices", Numer. Math. 11, 1968, 293-306; EISPACK tql2): a
+// shift from the leading 2 x 2 block of the unreduced part, a chase of
+// plane rotations from the bottom of that part to its top, accumulated into
+// Q; its recurrence variables (g, r, s, c, p, f, b) keep the roles they
+// have there.  For the block tridiagonal matrices of the
 // Lanczos run (order up to d, half-bandwidth b <= 32): reduction of a band
 // matrix to tridiagonal form by plane rotations that chase the bulge down the
 // band (Schwarz, Numer. Math. 12, 1968), Sturm-sequence bisection for single

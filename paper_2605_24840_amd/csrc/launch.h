@@ -162,6 +162,14 @@ struct BatchRule {
   double tol;
   int fixed_steps, max_iter;
 };
+// Rounding floor of the stopping rule: one step of eq. NS maps each
+// eigenvalue x of the symmetric iterate, with e = 1 - x^2, to
+// e' = e^2 (3 + e)/4.  ||X^2 - I||_F < 0.2 bounds every |e| by 0.2, so two
+// exact steps shrink each e, and the residual, by a factor of at least
+// 0.16 x 0.03: a residual below STAG_R that has not halved over two steps is
+// the arithmetic's floor, whatever the precision and order, and further
+// steps cannot reach a smaller tol.
+constexpr double STAG_R = 0.1;
 struct BatchStep {
   double h1, h2;      // ||X^2 - I||_F of the previous two steps
   double resid, trace;  // of the last step evaluated

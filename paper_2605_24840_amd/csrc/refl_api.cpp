@@ -2175,7 +2175,7 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     } else {
       const size_t n = hist.size();
       if (resid < p.tol) stop = converged = true;
-      else if (n >= 3 && resid < 1e-6 && resid > 0.5 * hist[n - 3]) stop = true;
+      else if (n >= 3 && resid < STAG_R && resid > 0.5 * hist[n - 3]) stop = true;
       else if (m >= cap) stop = true;
     }
     if (stop) break;
@@ -2648,7 +2648,12 @@ refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, c
 }
 
 const char* refl_status_string(refl_status_t s) {
-  switch (s) {
+  // A C caller may pass any int: read the code as an int rather than load
+  // an out-of-range value of the enum type.
+  int code;
+  static_assert(sizeof(code) == sizeof(s), "status codes are ints");
+  std::memcpy(&code, &s, sizeof(code));
+  switch (code) {
     case REFL_OK: return "REFL_OK";
     case REFL_ERR_INVALID_ARG: return "REFL_ERR_INVALID_ARG";
     case REFL_ERR_DEVICE: return "REFL_ERR_DEVICE";

@@ -12,8 +12,8 @@ namespace refl {
 // X_m has residual r = ||X_m^2 - I||_F; s.trace already holds trace X_m.
 // Records m and r in s and returns true when the iteration stops at X_m
 // (then s.state and s.par are set): a non-finite residual, m reaching the
-// fixed depth, r below tol, stagnation (no halving over two steps once below
-// 1e-6), or the step cap.
+// fixed depth, r below tol, the rounding floor, or the step cap.
+// The floor test is the one STAG_R (launch.h) describes.
 __device__ __forceinline__ bool batch_rule(BatchStep& s, const BatchRule& ru, double r, int m,
                                            int par) {
   s.m = m;
@@ -27,7 +27,7 @@ __device__ __forceinline__ bool batch_rule(BatchStep& s, const BatchRule& ru, do
     if (m >= ru.fixed_steps) stop = conv = true;
   } else if (r < ru.tol) {
     stop = conv = true;
-  } else if (m >= 2 && r < 1e-6 && r > 0.5 * s.h2) {
+  } else if (m >= 2 && r < STAG_R && r > 0.5 * s.h2) {
     stop = true;
   } else if (m >= ru.max_iter) {
     stop = true;

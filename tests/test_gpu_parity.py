@@ -295,6 +295,27 @@ def test_fp32_controlled_spectra(R, handle, grel, theta):
     assert err < 1e-2
 
 
+def test_fp32_default_tol_stops_at_floor(R, handle):
+    """FP32 with the default tol (1e-12, far below the FP32 floor of
+    ||X^2 - I||_F): the iteration stops at the floor (a residual below 0.1
+    that does not halve over two steps, which exact steps always would)
+    within a few steps of the depth the scalar model needs for 1e-3, not at
+    the 100-step cap, with the certified index and the FP32 error bound."""
+    d, k = 1024, 8
+    H, lam, Q = inputs.planted_hessian(d, k, 0.02, 0)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Rg, info, st = R.sign(_gpu(H), k, s, handle=handle, precision="fp32", check=False)
+    pred = oracle.ns_depth_scalar((lam - s) / info["alpha"], 1e-3)
+    err = np.linalg.norm(Rg.cpu().numpy() - oracle.reflector_from_eig(Q, k))
+    gamma = (s - lam[k - 1]) / info["alpha"]
+    _say(f"fp32 default tol: status={R.STATUS[st]} steps={info['ns_steps']} (model to 1e-3: {pred}) "
+         f"resid={info['resid_fro']:.2e} j={info['index_j']} err={err:.2e}")
+    assert R.STATUS[st] == "REFL_ERR_NOT_CONVERGED"
+    assert info["ns_steps"] <= pred + 6 and info["resid_fro"] < 0.1
+    assert info["index_j"] == k
+    assert err <= info["resid_fro"] + 4 * 2.0 ** -24 * np.sqrt(d) / gamma
+
+
 # ----------------------------------------------------------------- MIXED
 def test_mixed_bulk_iterate(R, handle):
     """Split-word bulk iterates against the oracle's model of the same

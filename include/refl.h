@@ -249,6 +249,38 @@ refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double *dH, 
 refl_status_t refl_sign(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
                         const refl_params_t *p, double *dR, int64_t ldr, refl_info_t *info);
 
+/* Bytes of the fixed device scratch that serves as the workspace of
+ * refl_sign_noalloc on each device (64 MiB). */
+#define REFL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* refl_sign for callers that cannot allocate memory: serving loops that must
+ * not call hipMalloc between requests, harnesses that forbid allocation, and
+ * code that records the caller's own work around the call.  Same arguments,
+ * computation, results and status codes as refl_sign, except:
+ * - The workspace is a fixed array of REFL_NOALLOC_SCRATCH_BYTES in device
+ *   memory that the library holds on every device it runs on, from the first
+ *   refl_create on that device until the process ends.  Nothing inside the
+ *   call allocates or frees device or pinned host memory or creates events:
+ *   the pinned staging and the events it needs come with the handle
+ *   (refl_create).  A workspace set with refl_set_workspace is not used.
+ * - Every call on a device shares that device's array, across handles: calls
+ *   that overlap on one device (two host threads, or two streams) race and
+ *   give undefined results.  The array keeps the last call's contents; a
+ *   call reads nothing it has not written itself.
+ * - Limit: when refl_workspace_size(h, d, p) exceeds REFL_NOALLOC_SCRATCH_BYTES
+ *   the call returns REFL_ERR_INVALID_ARG before any device work (about
+ *   d <= 1400 in FP64, 1800 in FP32, 1500 MIXED with a given shift; less with
+ *   shift_mode = REFL_SHIFT_LANCZOS, whose basis is another 8 d^2 bytes).
+ * - params.timing (which creates events) gives REFL_ERR_INVALID_ARG.
+ * - FP64/FP32 orders whose tile edge the autotuner has not yet timed in this
+ *   process (a refl_sign call does that once per order) take the edge of its
+ *   cost model; every entry of R is the same sum in the same order for every
+ *   edge, only the grouping of the residual's tile sums may differ.
+ * - REFL_ERR_DEVICE if refl_create could not resolve the array's address. */
+refl_status_t refl_sign_noalloc(refl_handle_t h, int64_t d, const double *dH, int64_t ldh,
+                                const refl_params_t *p, double *dR, int64_t ldr,
+                                refl_info_t *info);
+
 /* Y = R V for a d x d matrix R (full storage, row-major, ldr >= d) and a
  * d x nrhs block V; the direction d = -R g of eq. discrete_step and
  * Prop. 3.3 is refl_apply with V = -g.  Asynchronous. */

@@ -314,4 +314,13 @@ hipError_t lz_cholqr(const double* gin, int d, int nb, double shift_rel, double*
                      const double* Arec, double* Brec, int* flag, int tag, const double* W,
                      int64_t ldw, double* dst, int64_t ldd, double* gout, hipStream_t st);
 
+// ---- allocation-free entry point ----
+// Bytes of the fixed per-device scratch array (noalloc.hip) that serves as
+// the workspace of refl_sign_noalloc (REFL_NOALLOC_SCRATCH_BYTES in refl.h).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+// Device address of that array on `device`, which must be the current
+// device; resolved by hipGetSymbolAddress on the first call per device and
+// cached.  Never use the array's name on the host.
+hipError_t noalloc_scratch(int device, void** ptr);
+
 }  // namespace refl

@@ -62,6 +62,13 @@ struct refl_handle_s {
   hipStream_t side = nullptr;  // batched solve: small problems run beside the grouped steps
   hipEvent_t side_ev[2] = {nullptr, nullptr};  // fork and join of the side stream
   int ncu = 256;               // compute units of the device
+  // Allocation-free calls (refl_sign_noalloc): the device address of this
+  // device's fixed scratch array (resolved at refl_create), and the flag
+  // that turns every allocation site on the refl_sign path into an error
+  // or a pre-created resource for the duration of such a call.
+  void* scratch = nullptr;
+  hipError_t scratch_err = hipSuccess;
+  bool no_alloc = false;
   char err[512] = {0};
 };
 
@@ -125,6 +132,11 @@ struct Carve {
 };
 
 constexpr int MAXB = 32;  // widest block of vectors
+constexpr int BULK_RING = 16;  // MIXED bulk: completion events of the steps in flight
+// Pinned host staging of the Lanczos blocks created with every handle:
+// 2 J b^2 doubles with J b <= d and b <= 32, so orders up to 2048, which
+// covers every order whose workspace fits the allocation-free scratch.
+constexpr size_t LZ_PIN_INITIAL = sizeof(double) * 2 * 2048 * 32 + 4096;
 
 // Block-Lanczos buffers (carved only when the shift is estimated).
 struct LzWork {
@@ -235,6 +247,9 @@ int select_tile_f(refl_handle_t h, int64_t d, bool fp64) {
   auto it = g_tile_cache.find(key);
   if (it != g_tile_cache.end()) return it->second;
   const int fallback = model_tile_f(d, fp64, h->ncu);
+  // Timing needs a buffer of its own: an allocation-free call takes the
+  // cost model's edge (not cached, so a later refl_sign still measures).
+  if (h->no_alloc) return fallback;
   // The 32 edge is not a candidate: alone on the device it is the fastest
   // product up to d = 1536 (it spreads the tiles over every compute unit),
   // but batched calls, which must use refl_sign's edge to return the same
@@ -385,6 +400,18 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind
 }
 
 refl_status_t ensure_workspace(refl_handle_t h, size_t need, void** out) {
+  if (h->no_alloc) {
+    if (!h->scratch)
+      return fail(h, REFL_ERR_DEVICE, "scratch address of device %d unavailable: %s", h->device,
+                  hipGetErrorString(h->scratch_err));
+    if (need > NOALLOC_SCRATCH_BYTES)
+      return fail(h, REFL_ERR_INVALID_ARG,
+                  "this order and these parameters need %zu bytes of workspace; the "
+                  "allocation-free entry point has %zu",
+                  need, NOALLOC_SCRATCH_BYTES);
+    *out = h->scratch;
+    return REFL_OK;
+  }
   if (h->ws_user && h->ws_user_bytes >= need) {
     *out = h->ws_user;
     return REFL_OK;
@@ -727,6 +754,9 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   const size_t blk = (size_t)b * b;
   const size_t pin_need = sizeof(double) * 2 * J * blk + 4 * sizeof(int) + 64;
   if (h->lz_pin_bytes < pin_need) {
+    if (h->no_alloc)
+      return fail(h, REFL_ERR_INVALID_ARG, "Lanczos staging of %zu bytes exceeds the %zu created with the handle",
+                  pin_need, h->lz_pin_bytes);
     if (h->lz_pin) {
       HIPCHK(hipStreamSynchronize(st));
       HIPCHK(hipHostFree(h->lz_pin));
@@ -738,7 +768,10 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     h->lz_pin_bytes = pin_need;
   }
   for (int e = 0; e < 2; ++e)
-    if (!h->lz_ev[e]) HIPCHK(hipEventCreateWithFlags(&h->lz_ev[e], hipEventDisableTiming));
+    if (!h->lz_ev[e]) {
+      if (h->no_alloc) return fail(h, REFL_ERR_DEVICE, "Lanczos events missing");
+      HIPCHK(hipEventCreateWithFlags(&h->lz_ev[e], hipEventDisableTiming));
+    }
   double* hTA = h->lz_pin;
   double* hTB = h->lz_pin + J * blk;
   int* hflag = reinterpret_cast<int*>(h->lz_pin + 2 * J * blk);
@@ -966,6 +999,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   size_t nev = 0;
   const size_t max_ev = 2 * (size_t)(cap + 2);
   if (p.timing) {
+    if (h->no_alloc && h->ev.size() < 2 * max_ev)
+      return fail(h, REFL_ERR_INVALID_ARG, "params.timing creates events: not available without allocation");
     while (h->ev.size() < 2 * max_ev) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
@@ -990,12 +1025,13 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     // reads ||X_m^2 - I||_F and trace X_m, so the device never waits for the
     // host.  X_m lives in buffer m % 3 (the two steps in flight past m write
     // the other two).  Per-step results go to a ring of scalar slots.
-    constexpr int RING = 16;
+    constexpr int RING = BULK_RING;
     // Step m fills the slot pair m: ||X_m^2 - I||_F^2 and trace X_{m+1}.
     auto slot_r = [](int m) { return SC_SCRATCH + 2 * (m % RING); };
     auto slot_t = [](int m) { return SC_SCRATCH + 2 * (m % RING) + 1; };
     std::vector<hipEvent_t>& lev = h->bulk_ev;
     while ((int)lev.size() < RING) {
+      if (h->no_alloc) return fail(h, REFL_ERR_DEVICE, "bulk events missing");
       hipEvent_t e;
       HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       lev.push_back(e);
@@ -2350,6 +2386,29 @@ refl_status_t refl_create(refl_handle_t* out, int device, void* hip_stream) {
     return REFL_ERR_NO_MEMORY;
   }
   std::memset(h->pinned, 0, pin_bytes);
+  // Resources the refl_sign path would otherwise create on first use, made
+  // here so that refl_sign_noalloc never has to.
+  bool ok = hipHostMalloc((void**)&h->lz_pin, LZ_PIN_INITIAL, hipHostMallocDefault) == hipSuccess;
+  if (ok) h->lz_pin_bytes = LZ_PIN_INITIAL;
+  for (int e = 0; ok && e < 2; ++e)
+    ok = hipEventCreateWithFlags(&h->lz_ev[e], hipEventDisableTiming) == hipSuccess;
+  while (ok && (int)h->bulk_ev.size() < BULK_RING) {
+    hipEvent_t e;
+    ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    if (ok) h->bulk_ev.push_back(e);
+  }
+  if (!ok) {
+    refl_destroy(h);
+    return REFL_ERR_NO_MEMORY;
+  }
+  // The fixed scratch of the allocation-free entry point on this device
+  // (current here).  A failure is kept and reported by that entry point
+  // only; every other call works without it.
+  h->scratch_err = noalloc_scratch(device, &h->scratch);
+  if (h->scratch_err != hipSuccess) {
+    h->scratch = nullptr;
+    (void)hipGetLastError();
+  }
   *out = h;
   return REFL_OK;
 }
@@ -2403,6 +2462,20 @@ refl_status_t refl_sign(refl_handle_t h, int64_t d, const double* dH, int64_t ld
                         const refl_params_t* p, double* dR, int64_t ldr, refl_info_t* info) {
   if (!h) return REFL_ERR_INVALID_ARG;
   if (!dR || ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "R is NULL or ldr < d");
+  return sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info);
+}
+
+refl_status_t refl_sign_noalloc(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                                const refl_params_t* p, double* dR, int64_t ldr, refl_info_t* info) {
+  if (!h) return REFL_ERR_INVALID_ARG;
+  if (!dR || ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "R is NULL or ldr < d");
+  if (p && p->timing)
+    return fail(h, REFL_ERR_INVALID_ARG, "params.timing creates events: not available without allocation");
+  struct Scope {
+    refl_handle_t h;
+    explicit Scope(refl_handle_t hh) : h(hh) { h->no_alloc = true; }
+    ~Scope() { h->no_alloc = false; }
+  } scope(h);
   return sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info);
 }
 

@@ -31,7 +31,7 @@ SMALL_MAX = {"fp32": 128, "fp64": 96}
 
 EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_stream",
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
-           "refl_apply", "refl_sign_apply", "refl_sign_batched",
+           "refl_sign_noalloc", "refl_apply", "refl_sign_apply", "refl_sign_batched",
            "refl_sign_batched_workspace_size", "refl_sign_grad", "refl_policy_create",
            "refl_policy_destroy", "refl_policy_shift", "refl_status_string", "refl_last_error"]
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "refl_set_workspace": [H, vp, ctypes.c_size_t],
         "refl_estimate_shift": [H, i64, vp, i64, i32, i32, u64, P(dbl), P(dbl), P(dbl), P(dbl), P(dbl)],
         "refl_sign": [H, i64, vp, i64, P(refl_params_t), vp, i64, P(refl_info_t)],
+        "refl_sign_noalloc": [H, i64, vp, i64, P(refl_params_t), vp, i64, P(refl_info_t)],
         "refl_apply": [H, i64, vp, i64, i64, vp, i64, vp, i64],
         "refl_sign_apply": [H, i64, vp, i64, P(refl_params_t), i64, vp, i64, vp, i64, P(refl_info_t)],
         "refl_sign_batched": [H, i32, P(i64), P(vp), P(i64), P(refl_params_t), P(vp), P(i64),
@@ -169,6 +170,15 @@ def refl_sign(h, d, H_ptr, ldh, params, R_ptr, ldr, info=None, check=True):
     info = info if info is not None else refl_info_t()
     st = load().refl_sign(h, d, ctypes.c_void_p(H_ptr), ldh, ctypes.byref(params),
                           ctypes.c_void_p(R_ptr), ldr, ctypes.byref(info))
+    if check:
+        _check(h, st)
+    return st, info
+
+
+def refl_sign_noalloc(h, d, H_ptr, ldh, params, R_ptr, ldr, info=None, check=True):
+    info = info if info is not None else refl_info_t()
+    st = load().refl_sign_noalloc(h, d, ctypes.c_void_p(H_ptr), ldh, ctypes.byref(params),
+                                  ctypes.c_void_p(R_ptr), ldr, ctypes.byref(info))
     if check:
         _check(h, st)
     return st, info
@@ -406,6 +416,24 @@ def sign(H, k, s=None, handle=None, out=None, check=True, **kw):
     p = make_params(k, s, **kw)
     R = out if out is not None else torch.empty((d, d), dtype=torch.float64, device=H.device)
     st, info = refl_sign(h.h, d, H.data_ptr(), H.stride(0), p, R.data_ptr(), R.stride(0), check=check)
+    return R, info.as_dict(), st
+
+
+def sign_noalloc(H, k, s=None, handle=None, out=None, check=True, **kw):
+    """As ``sign``, through refl_sign_noalloc: the library's fixed device
+    scratch is the workspace (no allocation inside the call).  ``out`` may be
+    preallocated.  Returns ``(R, info_dict, status)``."""
+    import torch
+    H = _dev_f64(H)
+    d = H.shape[0]
+    if H.dim() != 2 or H.shape[1] < d or H.stride(1) != 1:
+        raise ValueError("H must be d x d (or d x ld) with unit column stride")
+    h = handle or Handle(H.device)
+    h.sync_stream()
+    p = make_params(k, s, **kw)
+    R = out if out is not None else torch.empty((d, d), dtype=torch.float64, device=H.device)
+    st, info = refl_sign_noalloc(h.h, d, H.data_ptr(), H.stride(0), p, R.data_ptr(), R.stride(0),
+                                 check=check)
     return R, info.as_dict(), st
 
 

@@ -103,7 +103,8 @@ typedef struct {
   int32_t max_iter;     /* cap on Newton-Schulz steps (default 100) */
   int32_t fixed_steps;  /* > 0: exactly this many steps, no convergence test: the
                            finite-step filter p_m of eq. pm (FP64/FP32 only) */
-  int32_t words;        /* MIXED: BF16 words per operand, 2 (bf16x3) or 3 (bf16x6) */
+  int32_t words;        /* MIXED: BF16 words per operand the bulk starts with: 1 (bf16),
+                           2 (bf16x3, default) or 3 (bf16x6); see words_max */
   int32_t polish_sweeps;/* MIXED: maximum FP64 correction sweeps (default 2) */
   double cg_tol;        /* MIXED: relative residual target of the inner solves (default 1e-6) */
   int32_t cg_max_iter;  /* MIXED: cap on inner iterations per sweep (default 400) */
@@ -125,6 +126,12 @@ typedef struct {
                            One extra pass over H (d^2 doubles).  refl_sign, refl_sign_apply,
                            refl_sign_grad and each problem of refl_sign_batched */
   double sym_tol;       /* check_symmetric: relative tolerance, >= 0 (default 0: exact) */
+  int32_t words_max;    /* MIXED: largest word count the bulk may move to (default 3; 0 or
+                           words: no change).  A bulk that ends without the index
+                           certificate, or (k given) certifies another index, is run
+                           again with one more word per operand; with a Lanczos shift and
+                           an estimated scaled margin gamma below 5e-6 the bulk starts
+                           with three words.  info.bulk_words reports the count used */
 } refl_params_t;
 
 typedef enum {
@@ -176,7 +183,7 @@ typedef struct {
  * tol = 1e-12, max_iter = 100, fixed_steps = 0, words = 2, polish_sweeps = 2,
  * cg_tol = 1e-6, cg_max_iter = 400, lanczos_steps = 0, seed = 0, timing = 0,
  * grad_mode = REFL_GRAD_REVERSE, ckpt_every = 0, cg_f32 = REFL_CG_AUTO,
- * check_symmetric = 0, sym_tol = 0. */
+ * check_symmetric = 0, sym_tol = 0, words_max = 3. */
 refl_status_t refl_params_default(refl_params_t *p);
 
 /* Create a handle bound to HIP device `device` and stream `hip_stream`

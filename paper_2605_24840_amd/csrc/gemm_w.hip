@@ -69,7 +69,9 @@ __global__ __launch_bounds__(256) void k_sym_gemm_w(const uint16_t* __restrict__
                                                     const uint16_t* __restrict__ Xold,
                                                     uint16_t* __restrict__ out, int ld, int64_t ps,
                                                     int d, int dk, const int2* __restrict__ tiles,
-                                                    double* __restrict__ partials) {
+                                                    double* __restrict__ partials,
+                                                    const int* __restrict__ live) {
+  if (live && *live == 0) return;
   typedef WCfg<W, TS> C;
   constexpr int NB = C::NB;
   __shared__ __attribute__((aligned(16))) unsigned char lds_raw[C::LDS_BYTES];
@@ -338,7 +340,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                                                      uint16_t* __restrict__ out, int ld,
                                                      int64_t ps, int d, int dk,
                                                      const int2* __restrict__ tiles,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     const int* __restrict__ live) {
+  // A stopped iteration (device-side stopping rule): nothing to do.
+  if (live && *live == 0) return;
   typedef DCfg<W, TS> C;
   constexpr int NB = C::NB;
   // Three separate arrays: the compiler's per-variable alias scopes then let
@@ -744,13 +749,13 @@ static bool use_register_staging() {
 template <int W, int TS>
 static hipError_t launch_w(int mode, const uint16_t* A, const uint16_t* B, const uint16_t* Xold,
                            uint16_t* out, int ld, int64_t ps, int d, int dk, const int2* tiles,
-                           int ntiles, double* partials, hipStream_t st) {
+                           int ntiles, double* partials, hipStream_t st, const int* live) {
   if constexpr (W >= 2) {
     if (!use_register_staging()) {
       const int pipe = gemm_pipe();
 #define REFL_WD(MODEV, PIPEV)                                                                \
   hipLaunchKernelGGL((k_sym_gemm_wd<W, MODEV, TS, PIPEV>), dim3(ntiles), dim3(256), 0, st, A, B, \
-                     Xold, out, ld, ps, d, dk, tiles, partials)
+                     Xold, out, ld, ps, d, dk, tiles, partials, live)
       if (mode == GEMM_RESIDUAL) {
         if (pipe == 2) REFL_WD(GEMM_RESIDUAL, 2);
         else if (pipe == 1) REFL_WD(GEMM_RESIDUAL, 1);
@@ -766,20 +771,21 @@ static hipError_t launch_w(int mode, const uint16_t* A, const uint16_t* B, const
   }
   if (mode == GEMM_RESIDUAL)
     hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_RESIDUAL, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
-                       Xold, out, ld, ps, d, dk, tiles, partials);
+                       Xold, out, ld, ps, d, dk, tiles, partials, live);
   else
     hipLaunchKernelGGL((k_sym_gemm_w<W, GEMM_UPDATE, TS>), dim3(ntiles), dim3(256), 0, st, A, B,
-                       Xold, out, ld, ps, d, dk, tiles, partials);
+                       Xold, out, ld, ps, d, dk, tiles, partials, live);
   return hipGetLastError();
 }
 
 template <int TS>
 static hipError_t launch_ts_impl(int words, int mode, const uint16_t* A, const uint16_t* B,
                             const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d, int dk,
-                            const int2* tiles, int ntiles, double* partials, hipStream_t st) {
+                            const int2* tiles, int ntiles, double* partials, hipStream_t st,
+                            const int* live) {
   switch (words) {
-    case 1: return launch_w<1, TS>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
-    case 2: return launch_w<2, TS>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    case 1: return launch_w<1, TS>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st, live);
+    case 2: return launch_w<2, TS>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st, live);
     default: return hipErrorInvalidValue;
   }
 }
@@ -787,11 +793,11 @@ template <>
 hipError_t launch_ts_impl<128>(int words, int mode, const uint16_t* A, const uint16_t* B,
                                const uint16_t* Xold, uint16_t* out, int ld, int64_t ps, int d,
                                int dk, const int2* tiles, int ntiles, double* partials,
-                               hipStream_t st) {
+                               hipStream_t st, const int* live) {
   switch (words) {
-    case 1: return launch_w<1, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
-    case 2: return launch_w<2, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
-    case 3: return launch_w<3, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    case 1: return launch_w<1, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st, live);
+    case 2: return launch_w<2, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st, live);
+    case 3: return launch_w<3, 128>(mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st, live);
     default: return hipErrorInvalidValue;
   }
 }
@@ -799,13 +805,15 @@ hipError_t launch_ts_impl<128>(int words, int mode, const uint16_t* A, const uin
 hipError_t launch_sym_gemm_words(int words, int tile, int mode, const uint16_t* A,
                                  const uint16_t* B, const uint16_t* Xold, uint16_t* out, int ld,
                                  int64_t ps, int d, int dk, const int2* tiles, int ntiles,
-                                 double* partials, hipStream_t st) {
+                                 double* partials, hipStream_t st, const int* live) {
   if (ntiles <= 0) return hipSuccess;
   if (tile == 128)
-    return launch_ts_impl<128>(words, mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    return launch_ts_impl<128>(words, mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st,
+                               live);
   // 192-row tiles need 4 * 192 * 80 B of operand LDS per word: W <= 2 only.
   if (tile == 192 && words <= 2)
-    return launch_ts_impl<192>(words, mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st);
+    return launch_ts_impl<192>(words, mode, A, B, Xold, out, ld, ps, d, dk, tiles, ntiles, partials, st,
+                               live);
   return hipErrorInvalidValue;
 }
 

@@ -65,11 +65,12 @@ hipError_t launch_sym_gemm_grouped(int fp64, int mode, int ts, const GemmProblem
 // apart), FP32 accumulation on 32x32x16 BF16 MFMA.  Word products kept:
 // W=1 {00}; W=2 {00,01,10}; W=3 {00,01,10,02,11,20}.  tile = 128 or 192
 // (192 for W <= 2); tiles in units of `tile`; the matrices are zero outside
-// the leading d x d block and K runs over dk = d rounded up to 32.
+// the leading d x d block and K runs over dk = d rounded up to 32.  With
+// live != null the launch does nothing when *live == 0 (read on the device).
 hipError_t launch_sym_gemm_words(int words, int tile, int mode, const uint16_t* A,
                                  const uint16_t* B, const uint16_t* Xold, uint16_t* out, int ld,
                                  int64_t ps, int d, int dk, const int2* tiles, int ntiles,
-                                 double* partials, hipStream_t st);
+                                 double* partials, hipStream_t st, const int* live = nullptr);
 
 // scal[slot] = max_{i<j} |H_ij - H_ji|, scal[slot + 1] = max |H_ij| over the
 // full d x d matrix (NaN if any entry is NaN).
@@ -173,7 +174,8 @@ constexpr double STAG_R = 0.1;
 struct BatchStep {
   double h1, h2;      // ||X^2 - I||_F of the previous two steps
   double resid, trace;  // of the last step evaluated
-  int m, par, state, pad;  // steps taken; buffer of the final iterate; BATCH_*
+  int m, par, state;  // steps taken; buffer of the final iterate; BATCH_*
+  int cert;           // MIXED: steps so far at which the index certificate held
 };
 constexpr int BATCH_LIVE = 0, BATCH_CONVERGED = 1, BATCH_STOPPED = 2, BATCH_NONFINITE = 3;
 // LDS-resident iteration of small problems: one work-group per problem runs
@@ -198,6 +200,24 @@ hipError_t launch_ns_small(int fp64, const SmallProb* probs, int nprob, const Ba
 hipError_t launch_batch_decide(int nprob, const double* res, const double* trace,
                                const BatchRule* rules, BatchStep* stp, int* live, int* ctl,
                                int par, hipStream_t st);
+// Stopping rule of the MIXED bulk (split-BF16 words), evaluated on the device
+// after each residual product; the FP64 correction then restores accuracy.
+// Index certificate: with b = sqrt(d) ||X^2 - I||_F < 1 the number j of
+// negative eigenvalues of the symmetric iterate is the integer with
+// |trace X - (d - 2j)| < 1.  The bulk stops (CONVERGED) at the first step
+// where the certificate holds plus `extra` steps, or earlier once it holds
+// and the residual no longer falls quadratically (above 1/4 of the previous
+// one: the words' rounding floor); it stops without a certificate (STOPPED)
+// at the floor of STAG_R, at the step cap, or on a non-finite residual.
+struct MixedRule {
+  int d, extra, cap, pad;
+};
+// One step of the rule on one iterate: res = ||X_m^2 - I||_F^2, trace =
+// trace X_m (read for m > 0; the record holds trace X_0).  ctl[0] is m
+// (read, then incremented); live and ctl[1] become 0 at the stop, and the
+// record's par then names the buffer of X_m.
+hipError_t launch_mixed_decide(const double* res, const double* trace, const MixedRule* rule,
+                               BatchStep* stp, int* live, int* ctl, int par, hipStream_t st);
 // out[slot ? slot[q] : q] = sum of partials[begin[q] .. begin[q + 1]), q < nq,
 // summed in the same order as launch_reduce_sum over that range.
 hipError_t launch_reduce_ranges(const double* partials, const int* begin, const int* slot, int nq,

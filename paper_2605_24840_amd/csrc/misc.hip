@@ -222,6 +222,23 @@ __global__ __launch_bounds__(256) void k_batch_decide(int nprob, const double* _
   }
 }
 
+__global__ void k_mixed_decide(const double* __restrict__ res, const double* __restrict__ trace,
+                               const MixedRule* __restrict__ rule, BatchStep* __restrict__ stp,
+                               int* __restrict__ live, int* __restrict__ ctl, int par) {
+  if (threadIdx.x != 0) return;
+  const int m = ctl[0];
+  ctl[0] = m + 1;
+  if (!live[0]) return;
+  BatchStep s = stp[0];
+  if (m > 0) s.trace = trace[0];
+  const double r = sqrt(fmax(res[0], 0.0));
+  if (mixed_rule(s, rule[0], r, m, par)) {
+    live[0] = 0;
+    ctl[1] = 0;
+  }
+  stp[0] = s;
+}
+
 template <typename T>
 __device__ __forceinline__ void trace_block(const T* __restrict__ X, int dp, int d,
                                             double* __restrict__ out, double* red) {
@@ -1066,6 +1083,11 @@ hipError_t launch_batch_decide(int nprob, const double* res, const double* trace
   if (nprob <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_decide, dim3(1), dim3(256), 0, st, nprob, res, trace, rules, stp, live,
                      ctl, par);
+  return hipGetLastError();
+}
+hipError_t launch_mixed_decide(const double* res, const double* trace, const MixedRule* rule,
+                               BatchStep* stp, int* live, int* ctl, int par, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_decide, dim3(1), dim3(64), 0, st, res, trace, rule, stp, live, ctl, par);
   return hipGetLastError();
 }
 hipError_t launch_trace_f64(const double* X, int dp, int d, double* scal, int slot,

@@ -458,6 +458,8 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
   if (p->fixed_steps < 0) return fail(h, REFL_ERR_INVALID_ARG, "fixed_steps must be >= 0");
   if (p->precision == REFL_PREC_MIXED) {
     if (p->words < 1 || p->words > 3) return fail(h, REFL_ERR_INVALID_ARG, "words must be 1..3");
+    if (p->words_max != 0 && (p->words_max < p->words || p->words_max > 3))
+      return fail(h, REFL_ERR_INVALID_ARG, "words_max must be 0 or words..3");
     if (p->cg_f32 < REFL_CG_FP64 || p->cg_f32 > REFL_CG_AUTO)
       return fail(h, REFL_ERR_INVALID_ARG, "bad cg_f32");
     if (p->fixed_steps == 0 && p->k > MAXB)
@@ -906,6 +908,54 @@ refl_status_t lanczos_status(refl_handle_t h, const LzResult& r) {
 
 // Shared body of refl_sign and refl_sign_apply.  If dR is non-null, R is
 // written; otherwise dY = R dV.
+// MIXED: the largest word count the call may escalate to.
+int words_cap(const refl_params_t& p) { return p.words_max > 0 ? p.words_max : p.words; }
+
+// Estimated scaled margin below which the MIXED bulk starts with three words
+// (measured on planted spectra at d = 1024: at gamma = 3e-6 and below the
+// two-word bulk needs a second correction sweep and the three-word one does
+// not; at 9e-6 both need one and two words are faster).
+constexpr double GAMMA_BF16X6 = 5e-6;
+
+refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                        const refl_params_t* pin, double* dR, int64_t ldr, int64_t nrhs,
+                        const double* dV, int64_t ldv, double* dY, int64_t ldy,
+                        refl_info_t* info);
+
+// The MIXED call again with `words` words per operand, the shift s and the
+// scale of the first attempt (given), the Lanczos estimates of the first
+// attempt carried into info, and the first attempt's time added to the
+// set-up time.
+refl_status_t restart_words(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                            const refl_params_t& p, int words, double s, const refl_info_t& first,
+                            double t_start, double* dR, int64_t ldr, int64_t nrhs,
+                            const double* dV, int64_t ldv, double* dY, int64_t ldy,
+                            refl_info_t* info) {
+  refl_params_t q = p;
+  q.words = words;
+  q.shift_mode = REFL_SHIFT_GIVEN;
+  q.s = s;
+  q.scale_mode = REFL_SCALE_GIVEN;
+  q.alpha = first.alpha;
+  q.check_symmetric = 0;
+  refl_info_t inf2;
+  const double t_restart = now_ms();
+  const refl_status_t r = sign_impl(h, d, dH, ldh, &q, dR, ldr, nrhs, dV, ldv, dY, ldy, &inf2);
+  if (info) {
+    inf2.lanczos_steps = first.lanczos_steps;
+    inf2.lam_k = first.lam_k;
+    inf2.lam_k1 = first.lam_k1;
+    inf2.eps = first.eps;
+    inf2.margin = first.margin;
+    inf2.rho = first.rho;
+    inf2.gamma = first.gamma;
+    inf2.ms_setup += t_restart - t_start;
+    inf2.ms_total += t_restart - t_start;
+    *info = inf2;
+  }
+  return r;
+}
+
 refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
                         const refl_params_t* pin, double* dR, int64_t ldr, int64_t nrhs,
                         const double* dV, int64_t ldv, double* dY, int64_t ldy,
@@ -987,12 +1037,18 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     return fail(h, REFL_ERR_NOT_FINITE, "scale alpha=%g is not a positive finite number", inf.alpha);
   if (p.shift_mode == REFL_SHIFT_LANCZOS)
     inf.gamma = std::min(s - inf.lam_k, inf.lam_k1 - s) / inf.alpha;
+  // Bulk precision from the estimated scaled margin: below GAMMA_BF16X6 the
+  // three-word bulk certifies the index with one correction sweep where two
+  // words need two, so the call restarts with three words (same shift and
+  // scale, the Lanczos results carried over).
+  if (p.precision == REFL_PREC_MIXED && p.fixed_steps == 0 && p.shift_mode == REFL_SHIFT_LANCZOS &&
+      p.words < 3 && words_cap(p) >= 3 && inf.gamma < GAMMA_BF16X6)
+    return restart_words(h, d, dH, ldh, p, 3, s, inf, t_start, dR, ldr, nrhs, dV, ldv, dY, ldy, info);
   const double t_setup = now_ms();
 
   // ---- bulk ----
   Bulk b;
   double trace_cur = hsc[SC_TRACE];
-  std::vector<double> hist;
   const bool fixed = p.fixed_steps > 0;
   const int cap = fixed ? p.fixed_steps : p.max_iter;
   // Optional event pairs around each bulk product (2 per step).
@@ -1016,92 +1072,114 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     ++nev;
     return e;
   };
-  int cert_steps = 0;
   int bulk_extra = 0;
   if (const char* e = std::getenv("REFL_BULK_EXTRA")) bulk_extra = std::max(0, std::atoi(e));
   refl_status_t bulk_status = REFL_OK;
   if (p.precision == REFL_PREC_MIXED && !fixed) {
-    // MIXED bulk, one step ahead: step m + 1 is enqueued before the host
-    // reads ||X_m^2 - I||_F and trace X_m, so the device never waits for the
-    // host.  X_m lives in buffer m % 3 (the two steps in flight past m write
-    // the other two).  Per-step results go to a ring of scalar slots.
-    constexpr int RING = BULK_RING;
-    // Step m fills the slot pair m: ||X_m^2 - I||_F^2 and trace X_{m+1}.
-    auto slot_r = [](int m) { return SC_SCRATCH + 2 * (m % RING); };
-    auto slot_t = [](int m) { return SC_SCRATCH + 2 * (m % RING) + 1; };
+    // MIXED bulk: the stopping rule (index certificate, then the words'
+    // floor; MixedRule in launch.h) runs on the device after each residual
+    // product (k_mixed_decide), so the host enqueues steps four at a time
+    // and keeps one group queued beyond the one whose step record it reads;
+    // the products of steps past the stop read the device flag and return at
+    // once.  X_m lives in buffer m % 3.  Rule, record, flag and step counter
+    // are staged like the FP32 / FP64 path's; the record is copied back after
+    // each group into one of two host slots.
+    constexpr int STEPS_AHEAD = 4;
+    char* hs = reinterpret_cast<char*>(h->pinned + SC_COUNT) + sizeof(CgHost);
+    char* ds = reinterpret_cast<char*>(w.scal + SC_SCRATCH + 4);
+    MixedRule* ru = reinterpret_cast<MixedRule*>(hs);
+    BatchStep* sq = reinterpret_cast<BatchStep*>(hs + 16);
+    int* hlive = reinterpret_cast<int*>(hs + 64);
+    int* hctl = reinterpret_cast<int*>(hs + 72);
+    char* rec[2] = {hs + 96, hs + 160};  // BatchStep, live, ctl of ds + 16 .. ds + 80
+    const MixedRule* d_ru = reinterpret_cast<const MixedRule*>(ds);
+    BatchStep* d_sq = reinterpret_cast<BatchStep*>(ds + 16);
+    int* d_live = reinterpret_cast<int*>(ds + 64);
+    int* d_ctl = reinterpret_cast<int*>(ds + 72);
+    ru->d = (int)d;
+    ru->extra = bulk_extra;
+    ru->cap = cap;
+    ru->pad = 0;
+    std::memset(sq, 0, sizeof(BatchStep));
+    sq->trace = trace_cur;
+    sq->resid = NaN;
+    sq->state = BATCH_LIVE;
+    *hlive = 1;
+    hctl[0] = 0;
+    hctl[1] = 1;
+    HIPCHK(hipMemcpyAsync(ds, hs, 80, hipMemcpyHostToDevice, st));
     std::vector<hipEvent_t>& lev = h->bulk_ev;
-    while ((int)lev.size() < RING) {
+    while ((int)lev.size() < 2) {
       if (h->no_alloc) return fail(h, REFL_ERR_DEVICE, "bulk events missing");
       hipEvent_t e;
       HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       lev.push_back(e);
     }
-    auto enqueue_step = [&](int m) -> refl_status_t {
+    auto enqueue_step = [&](int m) -> hipError_t {
       uint16_t* Xm = w.Xw[m % 3];
       uint16_t* Xn = w.Xw[(m + 1) % 3];
-      HIPCHK(ev_start());
-      HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, Xm, Xm, nullptr, w.Nw, w.dp, w.ps,
-                                   (int)d, w.dk, w.tiles, w.ntiles, w.partials, st));
-      HIPCHK(ev_stop());
-      HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, slot_r(m), st));
-      HIPCHK(ev_start());
-      HIPCHK(launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, Xm, w.Nw, Xm, Xn, w.dp, w.ps, (int)d,
-                                   w.dk, w.tiles, w.ntiles, w.partials, st));
-      HIPCHK(ev_stop());
-      HIPCHK(launch_reduce_sum(w.partials, w.ntiles, w.scal, slot_t(m), st));
-      HIPCHK(hipMemcpyAsync(hsc + slot_r(m), w.scal + slot_r(m), 2 * sizeof(double),
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipEventRecord(lev[m % RING], st));
-      return REFL_OK;
+      hipError_t e;
+      if ((e = ev_start()) != hipSuccess) return e;
+      if ((e = launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, Xm, Xm, nullptr, w.Nw, w.dp, w.ps, (int)d,
+                                     w.dk, w.tiles, w.ntiles, w.partials, st, d_live)) != hipSuccess)
+        return e;
+      if ((e = ev_stop()) != hipSuccess) return e;
+      if ((e = launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st)) != hipSuccess) return e;
+      if ((e = launch_mixed_decide(w.scal + SC_RESID2, w.scal + SC_TRACE, d_ru, d_sq, d_live, d_ctl,
+                                   m % 3, st)) != hipSuccess)
+        return e;
+      if ((e = ev_start()) != hipSuccess) return e;
+      if ((e = launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, Xm, w.Nw, Xm, Xn, w.dp, w.ps, (int)d, w.dk,
+                                     w.tiles, w.ntiles, w.partials, st, d_live)) != hipSuccess)
+        return e;
+      if ((e = ev_stop()) != hipSuccess) return e;
+      return launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st);
     };
-    refl_status_t es = enqueue_step(0);
-    if (es != REFL_OK) return es;
-    int enq = 0;  // last step enqueued
-    const double sqd = std::sqrt((double)d);
-    for (int m = 0;; ++m) {
-      // Enqueue step m + 1 ahead unless X_m may pass the index certificate
-      // (sqrt(d) ||X_m^2 - I||_F < 1): near convergence ||X_m^2 - I||_F is
-      // about 0.75 ||X_{m-1}^2 - I||_F^2, and within a factor 4 of passing
-      // the step is not issued speculatively.
-      const bool likely_last = !hist.empty() && sqd * 0.75 * hist.back() * hist.back() < 4.0;
-      if (enq < m + 1 && m + 1 <= cap && !likely_last) {
-        es = enqueue_step(m + 1);
-        if (es != REFL_OK) return es;
-        enq = m + 1;
+    int enq = 0;  // steps enqueued
+    int group = STEPS_AHEAD;
+    auto enqueue_group = [&](int slot) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < group && enq <= cap && e == hipSuccess; ++i, ++enq) e = enqueue_step(enq);
+      if (e == hipSuccess) e = hipMemcpyAsync(rec[slot], ds + 16, 64, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipEventRecord(lev[slot], st);
+      return e;
+    };
+    HIPCHK(enqueue_group(0));
+    int last = 0;  // last group enqueued
+    bool stopped = false;
+    for (int g = 0;; ++g) {
+      if (last == g && enq <= cap) {
+        HIPCHK(enqueue_group((g + 1) & 1));
+        last = g + 1;
       }
-      HIPCHK(hipEventSynchronize(lev[m % RING]));
-      const double resid = std::sqrt(std::fmax(hsc[slot_r(m)], 0.0));
-      b.resid = resid;
-      b.trace = trace_cur;
-      b.steps = m;
-      b.cur = m % 3;
-      hist.push_back(resid);
-      if (!std::isfinite(resid)) {
-        bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", m);
+      HIPCHK(hipEventSynchronize(lev[g & 1]));
+      const int* rctl = reinterpret_cast<const int*>(rec[g & 1] + 56);
+      if (rctl[1] == 0) {
+        std::memcpy(sq, rec[g & 1], sizeof(BatchStep));
+        stopped = true;
         break;
       }
-      // Hand over to the FP64 correction as soon as the index certificate
-      // holds (the correction restores full accuracy), or after
-      // REFL_BULK_EXTRA further steps (tuning), or when the residual stops
-      // decreasing quadratically (the BF16-word floor).
-      const int j = index_certificate(d, resid, trace_cur);
-      const size_t n = hist.size();
-      if (j >= 0) {
-        ++cert_steps;
-        const bool floor = n >= 2 && resid > 0.25 * hist[n - 2];
-        if (floor || cert_steps > bulk_extra) {
-          b.converged = true;
-          break;
-        }
-      }
-      if (m >= cap) break;
-      trace_cur = hsc[slot_t(m)];
-      if (enq < m + 1) {
-        es = enqueue_step(m + 1);
-        if (es != REFL_OK) return es;
-        enq = m + 1;
-      }
+      if (last == g) break;
+      // Near the hand-over (the certificate needs sqrt(d) r < 1, and a step
+      // roughly squares a small residual) the groups shrink to one step, so
+      // that few steps past the stop are queued.
+      const double r_last = reinterpret_cast<const BatchStep*>(rec[g & 1])->resid;
+      if (std::isfinite(r_last) && std::sqrt((double)d) * r_last < 64.0) group = 1;
     }
+    if (!stopped) {
+      if (info) *info = inf;
+      return fail(h, REFL_ERR_DEVICE, "bulk iteration still running after the step limit");
+    }
+    b.steps = sq->m;
+    b.cur = sq->par;
+    b.resid = sq->resid;
+    b.trace = sq->trace;
+    b.converged = sq->state == BATCH_CONVERGED;
+    if (sq->state == BATCH_NONFINITE)
+      bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
+    // Timed launches: those of the steps taken (residual products of steps
+    // 0..m, update products of steps 0..m-1).
+    nev = std::min(nev, (size_t)(2 * b.steps + 1));
   } else if (p.precision != REFL_PREC_MIXED && small_order(d, p.precision == REFL_PREC_FP64)) {
     // Every step in one launch, X and N held in LDS, the stopping rule on
     // the device.  Problem, rule and step record are staged through the
@@ -1290,6 +1368,13 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
                       "index certificate found %d negative eigenvalues of H - sI, not k=%d",
                       inf.index_j, p.k);
   const int c = b.cur;
+  // Precision escalation: a bulk that ended without the index certificate,
+  // or (target k given) with another index, is run again with one more word
+  // per operand while words_max allows.
+  if (p.precision == REFL_PREC_MIXED && !fixed && p.words < words_cap(p) &&
+      (!b.converged || inf.index_j < 0 || (p.k > 0 && inf.index_j != p.k)))
+    return restart_words(h, d, dH, ldh, p, p.words + 1, s, inf, t_start, dR, ldr, nrhs, dV, ldv, dY, ldy,
+                         info);
   if (p.precision == REFL_PREC_MIXED && !fixed) {
     if (inf.index_j < 0 || (p.k > 0 && inf.index_j != p.k)) {
       if (out_status == REFL_OK)
@@ -2360,6 +2445,7 @@ refl_status_t refl_params_default(refl_params_t* p) {
   p->cg_f32 = REFL_CG_AUTO;
   p->check_symmetric = 0;
   p->sym_tol = 0.0;
+  p->words_max = 3;
   return REFL_OK;
 }
 

@@ -46,7 +46,8 @@ class refl_params_t(ctypes.Structure):
                 ("lanczos_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("timing", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("cg_f32", ctypes.c_int32),
-                ("check_symmetric", ctypes.c_int32), ("sym_tol", ctypes.c_double)]
+                ("check_symmetric", ctypes.c_int32), ("sym_tol", ctypes.c_double),
+                ("words_max", ctypes.c_int32)]
 
 
 class refl_policy_params_t(ctypes.Structure):
@@ -358,12 +359,13 @@ class Handle:
 def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps=0, words=2,
                 alpha=None, polish_sweeps=2, cg_tol=1e-6, cg_max_iter=400, lanczos_steps=0, seed=0,
                 timing=False, scale=None, grad_mode="reverse", ckpt_every=0, cg_prec="auto",
-                check_symmetric=False, sym_tol=0.0):
+                check_symmetric=False, sym_tol=0.0, words_max=3):
     """refl_params_t from keyword arguments.  s=None estimates the shift by
     block Lanczos; scale is "inf" (default), "given" (with alpha), "lanczos"
     (1.05 times the Lanczos spectral-radius estimate) or "fro"; k=0 with a
     given s reports the certified index instead of testing one;
-    check_symmetric reads H in full and rejects max|H - H^T| > sym_tol max|H|."""
+    check_symmetric reads H in full and rejects max|H - H^T| > sym_tol max|H|;
+    words_max bounds the MIXED bulk's escalation to more words per operand."""
     p = refl_params_default()
     p.k = int(k)
     p.shift_mode = SHIFT["lanczos"] if s is None else SHIFT["given"]
@@ -392,6 +394,7 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     p.cg_f32 = CG_PREC[cg_prec]
     p.check_symmetric = 1 if check_symmetric else 0
     p.sym_tol = float(sym_tol)
+    p.words_max = int(words_max)
     return p
 
 

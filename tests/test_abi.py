@@ -46,6 +46,7 @@ def test_struct_layout_matches_header(tmp_path):
         " offsetof(refl_info_t, ms_total), offsetof(refl_info_t, gamma));\n"
         'printf("%zu %zu %zu %zu\\n", offsetof(refl_params_t, check_symmetric), offsetof(refl_params_t, sym_tol),'
         " offsetof(refl_info_t, bulk_tile), offsetof(refl_info_t, bulk_words));\n"
+        'printf("%zu\\n", offsetof(refl_params_t, words_max));\n'
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
@@ -62,6 +63,7 @@ def test_struct_layout_matches_header(tmp_path):
     o = list(map(int, lines[3].split()))
     assert o == [refl.refl_params_t.check_symmetric.offset, refl.refl_params_t.sym_tol.offset,
                  refl.refl_info_t.bulk_tile.offset, refl.refl_info_t.bulk_words.offset]
+    assert int(lines[4]) == refl.refl_params_t.words_max.offset
 
 
 def _header_enum(name):

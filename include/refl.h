@@ -340,8 +340,8 @@ refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, c
  * the scale alpha held fixed.  Only the symmetric part of G matters; G is
  * d x d FP64 (ldg), read in full.
  *
- * The forward pass is refl_sign's (FP64 or FP32; MIXED and a Lanczos shift
- * give REFL_ERR_UNSUPPORTED) with the same steps and stopping rule.  The
+ * FP64 / FP32: the forward pass is refl_sign's with the same steps and
+ * stopping rule (a Lanczos shift gives REFL_ERR_UNSUPPORTED).  The
  * derivative follows the steps of eq. NS exactly (product rule), in the
  * bulk precision:
  *   reverse  Gb_m = sym(G); Gb_j = (3 Gb - (Gb X_j^2 + X_j Gb X_j + X_j^2 Gb))/2
@@ -353,6 +353,21 @@ refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, c
  *            beside the forward steps; gradient = Xdot_m.
  * Per step the derivative costs one general and one symmetric three-term
  * product (5 d^3 flops) against 2 d^3 for the forward step.
+ *
+ * MIXED: the gradient of the limit L(H) = <G, R_k(H)> = <G, sgn(H - sI)>,
+ * which is what the MIXED forward returns (fixed_steps must be 0; the shift
+ * may be given or estimated, R_k not depending on it).  The forward is
+ * refl_sign's MIXED solve; its certified basis V of the target eigenspace and
+ * Ritz values theta then give the derivative of sgn in Daleckii-Krein form,
+ * self-adjoint, applied to sym(G):
+ *   gradient = 2 (Z V^T + V Z^T),
+ *   (I - V V^T)(H - theta_c I)(I - V V^T) z_c = (I - V V^T) sym(G) v_c,
+ * solved by block CG with H in FP64 to a relative residual of 1e-10 (at
+ * most 4 cg_max_iter iterations, else REFL_ERR_NOT_CONVERGED with the
+ * gradient written); the operator is positive definite on the complement of
+ * V.  loss = tr G - 2 tr(V^T sym(G) V).  info.cg_iters and ms_polish
+ * include the gradient solve.  The workspace is refl_sign's (sym(G) is
+ * stored over the bulk's word planes once the forward is done).
  *
  * Outputs: dGrad (d x d, ldgr, symmetric), *loss = <G, R_m> (may be NULL),
  * and R_m into dR (ldr) unless dR is NULL.  Status and info as refl_sign.

@@ -272,6 +272,9 @@ hipError_t col_axpy(int d, int nb, double* Y, int64_t ldy, const double* coef, c
 // Y = a X + b Y (d x nb blocks).
 hipError_t lincomb(int d, int nb, double a, const double* X, int64_t ldx, double b, double* Y,
                    int64_t ldy, hipStream_t st);
+// out = c (Z V^T + V Z^T) (d x d, ldo) for d x k blocks Z, V (ld), k <= 32.
+hipError_t form_sym_pair(const double* Z, const double* V, int64_t ld, int k, int d, double c,
+                         double* out, int64_t ldo, hipStream_t st);
 // R = I - 2 V V^T (d x d, ldr).
 hipError_t form_reflector(const double* V, int64_t ldv, int k, int d, double* R, int64_t ldr,
                           hipStream_t st);

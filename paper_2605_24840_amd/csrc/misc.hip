@@ -612,6 +612,41 @@ __global__ __launch_bounds__(256) void k_form_reflector(const double* __restrict
   }
 }
 
+// out = c (Z V^T + V Z^T) on the d x d block (ldo), 64 x 64 tiles; Z and V
+// are d x k blocks (ld), k <= 32.
+__global__ __launch_bounds__(256) void k_form_sym_pair(const double* __restrict__ Z,
+                                                       const double* __restrict__ V, int64_t ld,
+                                                       int k, int d, double c,
+                                                       double* __restrict__ out, int64_t ldo) {
+  __shared__ double zi[64][33], vi[64][33], zj[64][33], vj[64][33];
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 32; e += 256) {
+    const int r = e & 63, q = e >> 6;
+    const bool in_i = i0 + r < d && q < k, in_j = j0 + r < d && q < k;
+    zi[r][q] = in_i ? Z[(int64_t)q * ld + i0 + r] : 0.0;
+    vi[r][q] = in_i ? V[(int64_t)q * ld + i0 + r] : 0.0;
+    zj[r][q] = in_j ? Z[(int64_t)q * ld + j0 + r] : 0.0;
+    vj[r][q] = in_j ? V[(int64_t)q * ld + j0 + r] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i >= d || j >= d) continue;
+    // Entry (i, j) is evaluated with the roles of lo = min(i, j) and
+    // hi = max(i, j) fixed, z_lo v_hi + v_lo z_hi, so (i, j) and (j, i) run
+    // the same operations on the same operands: exactly symmetric.
+    const bool sw = i > j;
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) {
+      const double zl = sw ? zj[tx][q] : zi[r][q], vl = sw ? vj[tx][q] : vi[r][q];
+      const double zh = sw ? zi[r][q] : zj[tx][q], vh = sw ? vi[r][q] : vj[tx][q];
+      acc = fma(zl, vh, fma(vl, zh, acc));
+    }
+    out[(int64_t)i * ldo + j] = c * acc;
+  }
+}
+
 // Seeded start block: V[j + c ldv] uniform in (-1, 1) from splitmix64.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -1299,6 +1334,13 @@ hipError_t form_reflector(const double* V, int64_t ldv, int k, int d, double* R,
                           hipStream_t st) {
   const int nt = nblocks(d, 64);
   hipLaunchKernelGGL(k_form_reflector, dim3(nt, nt), dim3(256), 0, st, V, ldv, k, d, R, ldr);
+  return hipGetLastError();
+}
+hipError_t form_sym_pair(const double* Z, const double* V, int64_t ld, int k, int d, double c,
+                         double* out, int64_t ldo, hipStream_t st) {
+  if (k < 0 || k > 32) return hipErrorInvalidValue;
+  const int nt = nblocks(d, 64);
+  hipLaunchKernelGGL(k_form_sym_pair, dim3(nt, nt), dim3(256), 0, st, Z, V, ld, k, d, c, out, ldo);
   return hipGetLastError();
 }
 hipError_t random_block(double* V, int64_t ldv, int d, int nb, uint64_t seed, hipStream_t st) {

@@ -559,11 +559,37 @@ refl_status_t orthonormalise(refl_handle_t h, Work& w, double*& V, double*& spar
   return REFL_OK;
 }
 
+// Block CG on (I - V V^T)(H - theta_c)(I - V V^T) z_c = r_c, c < k (V: d x k,
+// ld dp), from the state *hs (theta, rho0, tol2, k, nb set by the caller;
+// r in cb.R[0], cb.Z zeroed), over H in FP64 or its FP32 copy.  On return
+// *hs holds the final state (iters, done).
+refl_status_t cg_solve(refl_handle_t h, Work& w, bool use32, const double* V, int k, const CgBufs& cb,
+                       int max_iter, CgHost* hs) {
+  hipStream_t st = h->stream;
+  const int64_t ld = w.dp;
+  HIPCHK(hipMemcpyAsync(w.cgstate, hs, sizeof(CgHost), hipMemcpyHostToDevice, st));
+  int issued = 0;
+  while (true) {
+    // First batch 32 iterations (every correction solve here needs more),
+    // then 16 between host checks of the convergence flag.  Iteration
+    // max_iter + 1 only runs the convergence test.
+    const int batch = issued == 0 ? 32 : 16;
+    for (int b = 0; b < batch && issued <= max_iter + 1; ++b, ++issued)
+      HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, w.d, k, V, ld, cb, w.cgstate, w.thin,
+                          w.cgpart, issued, max_iter, st));
+    HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hs->done || issued > max_iter + 1) break;
+  }
+  return REFL_OK;
+}
+
 // FP64 correction of the target eigenspace for the MIXED path.  On entry
 // X (words) is the bulk iterate.  On exit V (ld dp, k columns) is an
 // orthonormal basis, and *E_fro, *theta_max describe the last Rayleigh-Ritz.
 refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
-                     const uint16_t* X, double** Vout, refl_info_t* info) {
+                     const uint16_t* X, double** Vout, refl_info_t* info,
+                     std::vector<double>* theta_out = nullptr) {
   const int d = w.d, k = p.k;
   const int64_t ld = w.dp;
   hipStream_t st = h->stream;
@@ -640,20 +666,8 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     hs->tol2 = p.cg_tol * p.cg_tol;
     hs->k = k;
     hs->nb = k;
-    HIPCHK(hipMemcpyAsync(w.cgstate, hs, sizeof(CgHost), hipMemcpyHostToDevice, st));
-    int issued = 0;
-    while (true) {
-      // First batch 32 iterations (every correction solve here needs more),
-      // then 16 between host checks of the convergence flag.  Iteration
-      // cg_max_iter + 1 only runs the convergence test.
-      const int batch = issued == 0 ? 32 : 16;
-      for (int b = 0; b < batch && issued <= p.cg_max_iter + 1; ++b, ++issued)
-        HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, d, k, V, ld, cb, w.cgstate, w.thin,
-                            w.cgpart, issued, p.cg_max_iter, st));
-      HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      if (hs->done || issued > p.cg_max_iter + 1) break;
-    }
+    refl_status_t cr = cg_solve(h, w, use32, V, k, cb, p.cg_max_iter, hs);
+    if (cr != REFL_OK) return cr;
     cg_total += hs->iters;
     // V <- orth(V + Z)
     HIPCHK(lincomb(d, k, 1.0, w.Z, ld, 1.0, V, ld, st));
@@ -662,6 +676,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     ++sweeps;
   }
   *Vout = V;
+  if (theta_out) *theta_out = th;
   if (info) {
     info->polish_sweeps = sweeps;
     info->cg_iters = cg_total;
@@ -908,6 +923,17 @@ refl_status_t lanczos_status(refl_handle_t h, const LzResult& r) {
 
 // Shared body of refl_sign and refl_sign_apply.  If dR is non-null, R is
 // written; otherwise dY = R dV.
+// What a MIXED solve leaves for a later step in the same workspace (the
+// gradient of the limit, refl_sign_grad): the layout, the final Ritz basis V
+// (d x k, ld dp) and its Ritz values, ascending.  V spans the certified
+// eigenspace, so R = I - 2 V V^T.
+struct MixedKeep {
+  Work w;
+  double* V = nullptr;
+  int k = 0;
+  std::vector<double> theta;
+};
+
 // MIXED: the largest word count the call may escalate to.
 int words_cap(const refl_params_t& p) { return p.words_max > 0 ? p.words_max : p.words; }
 
@@ -920,7 +946,7 @@ constexpr double GAMMA_BF16X6 = 5e-6;
 refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
                         const refl_params_t* pin, double* dR, int64_t ldr, int64_t nrhs,
                         const double* dV, int64_t ldv, double* dY, int64_t ldy,
-                        refl_info_t* info);
+                        refl_info_t* info, MixedKeep* keep = nullptr);
 
 // The MIXED call again with `words` words per operand, the shift s and the
 // scale of the first attempt (given), the Lanczos estimates of the first
@@ -930,7 +956,7 @@ refl_status_t restart_words(refl_handle_t h, int64_t d, const double* dH, int64_
                             const refl_params_t& p, int words, double s, const refl_info_t& first,
                             double t_start, double* dR, int64_t ldr, int64_t nrhs,
                             const double* dV, int64_t ldv, double* dY, int64_t ldy,
-                            refl_info_t* info) {
+                            refl_info_t* info, MixedKeep* keep) {
   refl_params_t q = p;
   q.words = words;
   q.shift_mode = REFL_SHIFT_GIVEN;
@@ -940,7 +966,7 @@ refl_status_t restart_words(refl_handle_t h, int64_t d, const double* dH, int64_
   q.check_symmetric = 0;
   refl_info_t inf2;
   const double t_restart = now_ms();
-  const refl_status_t r = sign_impl(h, d, dH, ldh, &q, dR, ldr, nrhs, dV, ldv, dY, ldy, &inf2);
+  const refl_status_t r = sign_impl(h, d, dH, ldh, &q, dR, ldr, nrhs, dV, ldv, dY, ldy, &inf2, keep);
   if (info) {
     inf2.lanczos_steps = first.lanczos_steps;
     inf2.lam_k = first.lam_k;
@@ -959,7 +985,7 @@ refl_status_t restart_words(refl_handle_t h, int64_t d, const double* dH, int64_
 refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
                         const refl_params_t* pin, double* dR, int64_t ldr, int64_t nrhs,
                         const double* dV, int64_t ldv, double* dY, int64_t ldy,
-                        refl_info_t* info) {
+                        refl_info_t* info, MixedKeep* keep) {
   const double t_start = now_ms();
   refl_status_t rs = check_params(h, d, pin);
   if (rs != REFL_OK) return rs;
@@ -1043,7 +1069,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   // scale, the Lanczos results carried over).
   if (p.precision == REFL_PREC_MIXED && p.fixed_steps == 0 && p.shift_mode == REFL_SHIFT_LANCZOS &&
       p.words < 3 && words_cap(p) >= 3 && inf.gamma < GAMMA_BF16X6)
-    return restart_words(h, d, dH, ldh, p, 3, s, inf, t_start, dR, ldr, nrhs, dV, ldv, dY, ldy, info);
+    return restart_words(h, d, dH, ldh, p, 3, s, inf, t_start, dR, ldr, nrhs, dV, ldv, dY, ldy, info,
+                         keep);
   const double t_setup = now_ms();
 
   // ---- bulk ----
@@ -1374,7 +1401,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   if (p.precision == REFL_PREC_MIXED && !fixed && p.words < words_cap(p) &&
       (!b.converged || inf.index_j < 0 || (p.k > 0 && inf.index_j != p.k)))
     return restart_words(h, d, dH, ldh, p, p.words + 1, s, inf, t_start, dR, ldr, nrhs, dV, ldv, dY, ldy,
-                         info);
+                         info, keep);
   if (p.precision == REFL_PREC_MIXED && !fixed) {
     if (inf.index_j < 0 || (p.k > 0 && inf.index_j != p.k)) {
       if (out_status == REFL_OK)
@@ -1388,6 +1415,11 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       const int j = inf.index_j;
       if (j == 0 || j == d) {
         const double sg = j == 0 ? 1.0 : -1.0;
+        if (keep) {
+          keep->w = w;
+          keep->V = nullptr;
+          keep->k = j;
+        }
         if (dR) {
           HIPCHK(form_reflector(w.V, w.dp, 0, (int)d, dR, ldr, st));
           if (sg < 0.0) HIPCHK(lincomb((int)d, (int)d, 0.0, dR, ldr, -1.0, dR, ldr, st));
@@ -1408,7 +1440,12 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       p.k = j;
     }
     double* V = nullptr;
-    refl_status_t pr = polish(h, w, p, s, w.Xw[c], &V, &inf);
+    refl_status_t pr = polish(h, w, p, s, w.Xw[c], &V, &inf, keep ? &keep->theta : nullptr);
+    if (keep) {
+      keep->w = w;
+      keep->V = V;
+      keep->k = p.k;
+    }
     if (pr != REFL_OK && pr != REFL_ERR_NOT_CONVERGED) {
       if (info) *info = inf;
       return pr;
@@ -2144,6 +2181,100 @@ void build_tiles_full(int nt, std::vector<int2>& host) {
   for (int b = 0; b < T; ++b) host[b] = order[start[b % 8] + b / 8];
 }
 
+// Gradient of the limit L(H) = <G, R_k(H)> = <G, sgn(H - sI)> after a MIXED
+// solve.  With A = H - sI = sum_i lambda_i q_i q_i^T, the derivative of sgn
+// at A applied to a symmetric E is sum over i < k < j of
+//   2 (q_j q_j^T E q_i q_i^T + q_i q_i^T E q_j q_j^T) / (lambda_j - lambda_i),
+// the Daleckii-Krein divided differences of sgn across the gap.  It is
+// self-adjoint, so the gradient is that map applied to sym(G):
+//   grad = 2 (Z V^T + V Z^T),  z_c = sum_{j > k} q_j q_j^T sym(G) v_c / (lambda_j - theta_c),
+// where z_c solves (I - V V^T)(H - theta_c)(I - V V^T) z_c = (I - V V^T) sym(G) v_c,
+// with V the certified basis of the target eigenspace and theta_c its Ritz
+// values: positive definite on the complement of V, the operator of the
+// correction's inner solves, here in FP64 to a relative residual of
+// GRAD_CG_TOL.  loss = tr G - 2 tr(V^T sym(G) V).
+constexpr double GRAD_CG_TOL = 1e-10;
+
+refl_status_t grad_mixed(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
+                         const refl_params_t& p, const double* dG, int64_t ldg, double* dGrad,
+                         int64_t ldgr, double* loss, double* dR, int64_t ldr, refl_info_t* info) {
+  MixedKeep kp;
+  refl_info_t inf;
+  refl_status_t rs = sign_impl(h, d, dH, ldh, &p, dR, ldr, 0, nullptr, 0, nullptr, 0, &inf, &kp);
+  if (rs != REFL_OK) {
+    if (info) *info = inf;
+    return rs;
+  }
+  const double t0 = now_ms();
+  Work& w = kp.w;
+  hipStream_t st = h->stream;
+  const int dd = (int)d, k = kp.k;
+  const int64_t ld = w.dp, n2 = (int64_t)w.dp * w.dp;
+  double* hsc = h->pinned;
+  // sym(G), dp x dp FP64, in the word planes (free once the forward is done).
+  double* Gs = reinterpret_cast<double*>(w.Xw[0]);
+  const size_t room = (size_t)(reinterpret_cast<char*>(w.Nw) - reinterpret_cast<char*>(w.Xw[0])) +
+                      (size_t)w.words * n2 * sizeof(uint16_t);
+  if (room < sizeof(double) * (size_t)n2) return fail(h, REFL_ERR_DEVICE, "gradient: word planes too small");
+  HIPCHK(launch_sym_in_f64(dG, ldg, dd, nullptr, Gs, w.dp, st));
+  HIPCHK(launch_trace_f64(Gs, w.dp, dd, w.scal, SC_SCRATCH, st));
+  int iters = 0;
+  double trGVV = 0.0;
+  refl_status_t out = REFL_OK;
+  if (!kp.V || k == 0 || k == dd) {
+    // R = +I or -I: locally constant, zero gradient.
+    HIPCHK(hipMemset2DAsync(dGrad, sizeof(double) * ldgr, 0, sizeof(double) * d, d, st));
+  } else {
+    double* V = kp.V;
+    double* spare = V == w.V ? w.T1 : w.V;
+    std::vector<double> C((size_t)k * k), Bn((size_t)k * k);
+    // B = (I - V V^T) sym(G) V into Rr; C = V^T sym(G) V.
+    HIPCHK(symthin_f64(Gs, ld, dd, V, ld, k, w.W, ld, w.thin, st));
+    HIPCHK(gram(V, ld, k, w.W, ld, k, dd, w.G, w.gwork, st));
+    HIPCHK(hipMemcpyAsync(C.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(lincomb(dd, k, 1.0, w.W, ld, 0.0, w.Rr, ld, st));
+    HIPCHK(block_axpy(dd, k, k, 1.0, w.Rr, ld, -1.0, V, ld, w.G, st));
+    HIPCHK(gram(w.Rr, ld, k, w.Rr, ld, k, dd, w.G, w.gwork, st));
+    HIPCHK(hipMemcpyAsync(Bn.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(lincomb(dd, k, 0.0, w.Rr, ld, 0.0, w.Z, ld, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int c = 0; c < k; ++c) trGVV += C[c + (size_t)k * c];
+    CgHost* hs = reinterpret_cast<CgHost*>(h->pinned + SC_COUNT);
+    std::memset(hs, 0, sizeof(CgHost));
+    for (int c = 0; c < k; ++c) {
+      hs->theta[c] = kp.theta[c];
+      hs->rho0[c] = Bn[c + (size_t)k * c];
+    }
+    hs->tol2 = GRAD_CG_TOL * GRAD_CG_TOL;
+    hs->k = k;
+    hs->nb = k;
+    const CgBufs cb = {{w.Rr, spare}, {w.P[0], w.P[1]}, {w.W, w.T2}, w.AP, w.Z};
+    const int cap = 4 * p.cg_max_iter;
+    rs = cg_solve(h, w, false, V, k, cb, cap, hs);
+    if (rs != REFL_OK) return rs;
+    iters = hs->iters;
+    HIPCHK(form_sym_pair(w.Z, V, ld, k, dd, 2.0, dGrad, ldgr, st));
+    if (iters >= cap)
+      out = fail(h, REFL_ERR_NOT_CONVERGED, "gradient solve: %d iterations without reaching %.0e", iters,
+                 GRAD_CG_TOL);
+  }
+  HIPCHK(hipMemcpyAsync(hsc + SC_SCRATCH, w.scal + SC_SCRATCH, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double trG = hsc[SC_SCRATCH];
+  if (loss) {
+    if (!kp.V || k == 0 || k == dd)
+      *loss = (k == dd ? -1.0 : 1.0) * trG;
+    else
+      *loss = trG - 2.0 * trGVV;
+  }
+  const double t1 = now_ms();
+  inf.cg_iters += iters;
+  inf.ms_polish += t1 - t0;
+  inf.ms_total += t1 - t0;
+  if (info) *info = inf;
+  return out;
+}
+
 refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
                         const refl_params_t* pin, const double* dG, int64_t ldg, double* dGrad,
                         int64_t ldgr, double* loss, double* dR, int64_t ldr, refl_info_t* info) {
@@ -2155,8 +2286,11 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   if (!dGrad || ldgr < d) return fail(h, REFL_ERR_INVALID_ARG, "gradient output is NULL or ld < d");
   if (dR && ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "ldr < d");
   const refl_params_t p = *pin;
-  if (p.precision == REFL_PREC_MIXED)
-    return fail(h, REFL_ERR_UNSUPPORTED, "refl_sign_grad runs FP64 or FP32");
+  if (p.precision == REFL_PREC_MIXED) {
+    if (p.fixed_steps > 0)
+      return fail(h, REFL_ERR_UNSUPPORTED, "MIXED gradient: the limit only (fixed_steps must be 0)");
+    return grad_mixed(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info);
+  }
   if (p.shift_mode != REFL_SHIFT_GIVEN)
     return fail(h, REFL_ERR_UNSUPPORTED, "refl_sign_grad needs a given shift");
   if (p.grad_mode != REFL_GRAD_REVERSE && p.grad_mode != REFL_GRAD_TANGENT)

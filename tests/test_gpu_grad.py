@@ -188,9 +188,68 @@ def test_grad_errors(R, handle):
     H, lam, Q = inputs.planted_hessian(64, 4, 0.1, 0)
     s = 0.5 * (lam[3] + lam[4])
     Hg, G = _gpu(H), _gpu(inputs.symmetric_normal(64, 0))
-    for kw, want in ((dict(precision="mixed"), "REFL_ERR_UNSUPPORTED"),
+    for kw, want in ((dict(precision="mixed", fixed_steps=4), "REFL_ERR_UNSUPPORTED"),
                      (dict(ckpt_every=-1), "REFL_ERR_INVALID_ARG")):
         _, _, _, _, st = R.sign_grad(Hg, G, 4, s, handle=handle, check=False, **kw)
         assert R.STATUS[st] == want, kw
     _, _, _, _, st = R.sign_grad(Hg, G, 4, None, handle=handle, check=False)
     assert R.STATUS[st] == "REFL_ERR_UNSUPPORTED"
+
+
+# --------------------------------------------- MIXED: gradient of the limit
+def _limit_loss(H, G, k):
+    """<G, R_k(H)> with R_k = I - 2 V_k V_k^T from LAPACK's eigenvectors (the
+    definition, eq. Pk), as a reference for central differences."""
+    w, V = np.linalg.eigh(H)
+    Vk = V[:, :k]
+    return float(np.trace(G) - 2.0 * np.sum(Vk * (G @ Vk)))
+
+
+def test_grad_mixed_differentiation_workload(R, handle, c4):
+    """MIXED forward (split-BF16 bulk, FP64 correction), then the gradient of
+    the limit <G, sgn(H - sI)> from the certified eigenspace by projected
+    FP64 solves.  Against the Daleckii-Krein form of D sgn (oracle) and central
+    differences of <G, R_k(H + tE)> (R_k from LAPACK eigenvectors, t = 1e-4);
+    target 1e-6 relative."""
+    H, lam, Q, G, s, k = c4
+    d = H.shape[0]
+    Hg, Gg = _gpu(H), _gpu(G)
+    g, loss, Rm, info, st = R.sign_grad(Hg, Gg, k, s, handle=handle, precision="mixed",
+                                        tol=1e-8 * np.sqrt(d), with_R=True)
+    _say(f"grad mixed d={d} k={k}: status={R.STATUS[st]} words={info['bulk_words']} steps={info['ns_steps']} "
+         f"cg={info['cg_iters']} ms={info['ms_total']:.1f}")
+    assert st == 0 and info["index_j"] == k
+    gn = g.cpu().numpy()
+    assert np.array_equal(gn, gn.T)
+    dk = oracle.sign_frechet_dk(H, s, G)
+    err = _rel(gn, dk)
+    _say(f"  vs Daleckii-Krein of sgn: {err:.2e}")
+    assert err < 1e-6
+    Rk = np.eye(d) - 2.0 * Q[:, :k] @ Q[:, :k].T
+    lexact = float(np.sum(G * Rk))
+    _say(f"  loss {loss:.12e} exact {lexact:.12e}")
+    assert abs(loss - lexact) <= 1e-9 * abs(lexact) + 1e-9
+    assert np.linalg.norm(Rm.cpu().numpy() - Rk) <= 1e-8 * np.sqrt(d)
+    E = inputs.symmetric_normal(d, 1)
+    E /= np.linalg.norm(E)
+    t = 1e-4
+    fd = (_limit_loss(H + t * E, G, k) - _limit_loss(H - t * E, G, k)) / (2 * t)
+    dd = float(np.sum(gn * E))
+    _say(f"  directional derivative {dd:.12e}, central difference {fd:.12e}, rel {abs(dd - fd) / abs(fd):.2e}")
+    assert abs(dd - fd) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("d,k,lanczos", [(300, 5, False), (257, 3, True), (1000, 1, False)])
+def test_grad_mixed_small(R, handle, d, k, lanczos):
+    H, lam, Q = inputs.planted_hessian(d, k, 0.05, 100 + d)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Gn = np.random.default_rng(d).standard_normal((d, d))   # only sym(G) counts
+    g, loss, _, info, st = R.sign_grad(_gpu(H), _gpu(Gn), k, None if lanczos else s, handle=handle,
+                                       precision="mixed", tol=1e-8 * np.sqrt(d), seed=2)
+    dk = oracle.sign_frechet_dk(H, s, 0.5 * (Gn + Gn.T))
+    err = _rel(g.cpu().numpy(), dk)
+    Rk = np.eye(d) - 2.0 * Q[:, :k] @ Q[:, :k].T
+    lerr = abs(loss - np.sum(Gn * Rk)) / abs(np.sum(Gn * Rk))
+    _say(f"grad mixed d={d} k={k} lanczos={lanczos}: status={R.STATUS[st]} cg={info['cg_iters']} "
+         f"vs DK {err:.2e} loss rel {lerr:.2e}")
+    assert st == 0 and err < 1e-7 and lerr < 1e-9

@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--lanczos-steps", type=int, default=3, help="timed solves with the shift estimated")
     ap.add_argument("--cg-tol", type=float, default=None, help="inner solve tolerance (library default if unset)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("allen_cahn", "batched", "grad"), default="allen_cahn")
+    ap.add_argument("--workload", choices=("allen_cahn", "batched", "grad", "kscan"), default="allen_cahn")
     ap.add_argument("--batch", type=int, default=256, help="problems of the batched workload")
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
@@ -105,6 +105,9 @@ def main():
         return
     if args.workload == "grad":
         bench_grad(args)
+        return
+    if args.workload == "kscan":
+        bench_kscan(args)
         return
 
     import torch
@@ -438,6 +441,61 @@ def bench_grad(args):
                      "kernel": "k_sym_gemm_f<double, GEMM_PLAIN_NEG> + k_adjoint_step<double>",
                      "launches": info["gemm_launches"], "avg_launch_ms": 1e3 * gemm_s / max(info["gemm_launches"], 1)},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_kscan(args):
+    """The target-index scan of section 5.3 at the paper's breadth: rotated
+    quartic, d = 64, k in {1, 2, 4, 8, 16}, 32 matched starts, converged
+    engine and midpoint filters m = 2, 4, 6 (outer.target_index_scan); the
+    success rate, the median wall time per outer step and per run, and the
+    median one-step direction error over 32 local perturbations.  The value is
+    outer steps per second over the whole scan."""
+    import torch
+    from paper_2605_24840_amd import outer, refl
+
+    dev = torch.device("cuda", 0)
+    h = refl.Handle(dev)
+    outer.target_index_scan(h, ks=(1,), nstarts=1, ms=(2,), npert=1)     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = outer.target_index_scan(h, nstarts=32, npert=32)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    h.close()
+    table, total_steps = {}, 0
+    for k, per_k in res.items():
+        row = {}
+        for m, r in per_k.items():
+            total_steps += sum(r["steps"])
+            name = "exact" if m == 0 else f"m{m}"
+            row[name] = {"success_rate": sum(r["success"]) / len(r["success"]),
+                         "median_ms_per_step": r["ms_per_step"],
+                         "median_ms_per_run": float(np.median(r["ms_per_run"])),
+                         "median_direction_error": float(np.median(r["dir_err"]))}
+            log(f"k={k:2d} {name:5s}: success {sum(r['success'])}/{len(r['success'])}, "
+                f"{r['ms_per_step']:.3f} ms/step, direction error {np.median(r['dir_err']):.2e}")
+        table[str(k)] = row
+    out = {
+        "metric": "outer steps/s of the section 5.3 target-index scan (d=64, 32 starts, exact + p_2, p_4, p_6)",
+        "value": total_steps / t_all,
+        "unit": "outer steps/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": 1e3 * t_all,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "rotated_quartic_scan", "d": 64, "ks": [1, 2, 4, 8, 16], "starts": 32,
+                   "eta": 0.3, "max_steps": 200, "perturbations": 32, "perturbation_scale": 0.05,
+                   "shift": "exact midpoint (dense eigensolver)"},
+        "scan": table,
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -59,6 +59,10 @@ struct refl_handle_s {
   size_t batch_pin_bytes = 0;
   hipEvent_t lz_ev[2] = {nullptr, nullptr};
   hipStream_t cap = nullptr;   // stream the batched step graph is captured on
+  // The batched step graph of the last call, kept for the next call with the
+  // same workspace, precision, orders, tile edges and list of tiled problems.
+  hipGraphExec_t bgraph = nullptr;
+  std::vector<int64_t> bgraph_key;
   hipStream_t side = nullptr;  // batched solve: small problems run beside the grouped steps
   hipEvent_t side_ev[2] = {nullptr, nullptr};  // fork and join of the side stream
   int ncu = 256;               // compute units of the device
@@ -1965,7 +1969,24 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   const char* genv = std::getenv("REFL_BATCH_GRAPH");
   const bool use_graph = nq0 > 0 && !timing && !(genv && genv[0] == '0');
   hipGraphExec_t gexec = nullptr;
-  if (use_graph) {
+  // The graph holds only workspace addresses and host-side counts, all fixed
+  // by this key; a call with the same key (the same problem set solved
+  // again, e.g. by an outer iteration) launches the instantiated graph of
+  // the previous call.
+  std::vector<int64_t> key = {reinterpret_cast<int64_t>(base), (int64_t)need, fprec, nprob, nq0};
+  for (int p = 0; p < nprob; ++p) {
+    key.push_back(d[p]);
+    key.push_back(tsv[p]);
+  }
+  key.insert(key.end(), tiled.begin(), tiled.end());
+  for (int c = 0; c < NEDGE; ++c) key.push_back(cls[lb][c]);
+  if (use_graph && h->bgraph && h->bgraph_key == key) gexec = h->bgraph;
+  if (use_graph && !gexec) {
+    if (h->bgraph) {
+      (void)hipGraphExecDestroy(h->bgraph);
+      h->bgraph = nullptr;
+      h->bgraph_key.clear();
+    }
     hipError_t ce = h->cap ? hipSuccess : hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
     if (ce == hipSuccess) ce = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
     if (ce != hipSuccess) {
@@ -1983,6 +2004,8 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
       drain_side();
       return fail(h, REFL_ERR_DEVICE, "batched step graph: %s", hipGetErrorString(ce));
     }
+    h->bgraph = gexec;
+    h->bgraph_key = key;
   }
   // Each round runs BATCH_GRAPH_STEPS steps; every problem stops by its
   // step limit, so the rounds are bounded.
@@ -1998,7 +2021,6 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
     if (le == hipSuccess) le = hipStreamSynchronize(st);
     if (le == hipSuccess && bp.ctl[1] == 0) break;
   }
-  if (gexec) (void)hipGraphExecDestroy(gexec);
   if (fork) {
     const hipError_t je = hipStreamWaitEvent(st, h->side_ev[1], 0);
     if (le == hipSuccess) le = je;
@@ -2645,6 +2667,7 @@ refl_status_t refl_destroy(refl_handle_t h) {
   if (h->lz_pin) (void)hipHostFree(h->lz_pin);
   if (h->batch_pin) (void)hipHostFree(h->batch_pin);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->bgraph) (void)hipGraphExecDestroy(h->bgraph);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->side) (void)hipStreamDestroy(h->side);
   for (hipEvent_t e : h->side_ev)

@@ -282,3 +282,25 @@ def test_batched_tile32_equals_single(R, handle, monkeypatch):
             assert st1 == 0 and torch.equal(Rs[p], R1), p
             assert infos[p]["ns_steps"] == i1["ns_steps"]
     monkeypatch.delenv("REFL_F_TILE")
+
+
+def test_batched_graph_cache_across_problem_sets(R, handle):
+    """The instantiated step graph is kept by the handle for the next call with
+    the same workspace, orders, tile edges and tiled problems; a call on
+    another problem set in between replaces it.  Sets A, B, A: each call's R
+    equals, bit for bit, refl_sign on each problem."""
+    pa = _problems(SMALL[:4])
+    pb = _problems(SMALL[4:8])
+    for probs in (pa, pb, pa):
+        Hs = [torch.from_numpy(H).to("cuda:0") for H, *_ in probs]
+        ks = [p[3] for p in probs]
+        ss = [p[4] for p in probs]
+        Rs, infos, sts, st = R.sign_batched(Hs, ks, ss, handle=handle, precision="fp32", tol=1e-3,
+                                            check=False)
+        assert st == 0 and all(x == 0 for x in sts)
+        for p in range(len(probs)):
+            R1, i1, st1 = R.sign(Hs[p], ks[p], ss[p], handle=handle, precision="fp32", tol=1e-3,
+                                 check=False)
+            assert st1 == 0 and torch.equal(Rs[p], R1), p
+            assert infos[p]["ns_steps"] == i1["ns_steps"]
+    _say("graph cache A, B, A: each call equal to single calls")

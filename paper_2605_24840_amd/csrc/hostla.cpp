@@ -257,35 +257,72 @@ double tridiag_eigval(int n, const double* diag, const double* sub, int m) {
   return 0.5 * (lo + hi);
 }
 
-int band_count_below(int n, int bw, const double* Lb, double x, double* work) {
+int band_count_below(int n, int bw, const double* Lb, double x, double* work, double* lmax) {
   // T - xI = L D L^T without pivoting; L (unit lower, band) row i at
-  // work[i * bw + (i - j - 1)], j = i - bw .. i - 1; D at work[n * bw + i].
+  // work[i * bw + (i - j - 1)], j = i - bw .. i - 1; 1 / D at work[n * bw + i].
+  // Row i is a forward substitution with the rows of L above it: with
+  // v[j] = L[i][j] D[j],
+  //   v[j] = T[i][j] - sum_{i - bw <= m < j} v[m] L[j][m],  L[i][j] = v[j] / D[j],
+  //   D[i] = T[i][i] - x - sum_j L[i][j] v[j];
+  // it is done column by column (each finished v[m] updates all later
+  // entries at once), which keeps the dependent chain b long, not b^2 / 2.
   // Returns the number of negative pivots, or -1 if a multiplier exceeds
   // 1e8 in size (element growth: the count is not trusted).
   double* L = work;
-  double* D = work + (size_t)n * bw;
+  double* Di = work + (size_t)n * bw;
   const double tiny = 1e-300;
+  double big = 0.0;
+  double pbuf[64];
+  std::vector<double> pvec;
+  double* p = pbuf;
+  if (bw > 64) {
+    pvec.resize(bw);
+    p = pvec.data();
+  }
   int cnt = 0;
   for (int i = 0; i < n; ++i) {
-    const int j0 = std::max(0, i - bw);
+    const int j0 = std::max(0, i - bw), w = i - j0;
     const double* ai = Lb + (size_t)i * (bw + 1);  // ai[t] = T[i][i - t]
     double* li = L + (size_t)i * bw;                // li[t - 1] = L[i][i - t]
+    for (int q = 0; q < w; ++q) p[q] = ai[i - j0 - q];   // p[q] for column j0 + q
     double di = ai[0] - x;
-    for (int j = j0; j < i; ++j) {
-      // u = T[i][j] - sum_{m < j} L[i][m] D[m] L[j][m]
-      double u = ai[i - j];
-      const double* lj = L + (size_t)j * bw;
-      for (int m = std::max(j0, j - bw); m < j; ++m) u -= li[i - m - 1] * D[m] * lj[j - m - 1];
-      const double l = u / D[j];
+    for (int q = 0; q < w; ++q) {
+      const int j = j0 + q;
+      const double u = p[q];                   // v[j], final
+      const double l = u * Di[j];
       if (!(std::fabs(l) < 1e8)) return -1;
+      big = std::max(big, std::fabs(l));
       li[i - j - 1] = l;
       di -= l * u;
+      // Later columns jj > j of this row: p[jj] -= v[j] L[jj][j].
+      for (int qq = q + 1; qq < w; ++qq) {
+        const int jj = j0 + qq;
+        p[qq] -= u * L[(size_t)jj * bw + (jj - j - 1)];
+      }
     }
     if (di == 0.0) di = -tiny;
-    D[i] = di;
+    Di[i] = 1.0 / di;
     if (di < 0.0) ++cnt;
   }
+  if (lmax) *lmax = big;
   return cnt;
+}
+
+void band_ldl_solve(int n, int bw, const double* work, double* y) {
+  const double* L = work;
+  const double* Di = work + (size_t)n * bw;
+  for (int i = 0; i < n; ++i) {                  // L z = y
+    const double* li = L + (size_t)i * bw;
+    double s = y[i];
+    for (int t = 1; t <= bw && t <= i; ++t) s -= li[t - 1] * y[i - t];
+    y[i] = s;
+  }
+  for (int i = 0; i < n; ++i) y[i] *= Di[i];     // D w = z
+  for (int i = n - 1; i >= 0; --i) {             // L^T y = w
+    double s = y[i];
+    for (int t = 1; t <= bw && i + t < n; ++t) s -= L[(size_t)(i + t) * bw + (t - 1)] * y[i + t];
+    y[i] = s;
+  }
 }
 
 double band_inverse_iteration(int n, int bw, const double* Lb, double sigma, int iters,
@@ -455,13 +492,12 @@ static void ritz_pairs(int j, int b, const double* TA, const double* TB, int nm,
     }
     return b;
   };
-  // Residual radius of the Ritz pair near sigma: inverse iteration gives the
-  // vector y of T, theta its Rayleigh quotient, and
-  // ||H x - theta x||^2 = ||(T - theta) y||^2 + ||B_j y(last block)||^2.
-  std::vector<double> y(n), ty(n);
+  std::vector<double> y(n), ty(n), fwork((size_t)n * (b + 1));
   const double* Bj = TB + (size_t)(j - 1) * b * b;
-  auto pair = [&](double sigma, double& theta, double& res) {
-    band_inverse_iteration(n, b, Lb.data(), sigma, 3, y.data());
+  // For the unit vector y: theta = y^T T y, rT = ||(T - theta) y|| and the
+  // residual radius of the Ritz pair,
+  // ||H x - theta x||^2 = ||(T - theta) y||^2 + ||B_j y(last block)||^2.
+  auto rayleigh = [&](double& theta, double& rT, double& res) {
     double q = 0.0;
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
@@ -481,7 +517,38 @@ static void ritz_pairs(int j, int b, const double* TA, const double* TB, int nm,
       for (int c = r; c < b; ++c) s += Bj[r + c * b] * y[n - b + c];
       r2 += s * s;
     }
+    rT = std::sqrt(r1);
     res = std::sqrt(r1 + r2);
+  };
+  // `solves` steps of inverse iteration on y with the L D L^T factors that
+  // band_count_below left in fwork; false if y lost its norm.
+  auto ldl_steps = [&](int solves) {
+    for (int it = 0; it < solves; ++it) {
+      band_ldl_solve(n, b, fwork.data(), y.data());
+      double nrm = 0.0;
+      for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) return false;
+      for (int i = 0; i < n; ++i) y[i] /= nrm;
+    }
+    return true;
+  };
+  auto start_vector = [&]() {
+    for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.5 * std::sin(1.0 + 0.7 * i);
+  };
+  // Inverse iteration from the L D L^T factors of T - sigma I when they
+  // came without growth (multipliers below 1e3), else from the pivoted LU.
+  // Either way theta and res are the Rayleigh quotient and the true
+  // residual radius of the vector returned.
+  auto pair = [&](double sigma, double& theta, double& res) {
+    double lmax = 0.0, rT;
+    bool done = false;
+    if (band_count_below(n, b, Lb.data(), sigma, fwork.data(), &lmax) >= 0 && lmax < 1e3) {
+      start_vector();
+      done = ldl_steps(3);
+    }
+    if (!done) band_inverse_iteration(n, b, Lb.data(), sigma, 3, y.data());
+    rayleigh(theta, rT, res);
   };
   // A bracket [lo, hi] of the m-th eigenvalue near an earlier Ritz value
   // t0 with residual radius r0, confirmed by counts (false if none found
@@ -504,7 +571,69 @@ static void ritz_pairs(int j, int b, const double* TA, const double* TB, int nm,
     }
     return false;
   };
-  auto ritz = [&](int m, double& theta, double& res, double t0 = NAN, double r0 = NAN) {
+  // Two shifted inverse iterations from an earlier Ritz value t0 with
+  // residual radius r0, instead of a bisection: two solves at
+  // t0 - max(r0, w) (w = 1e-6 scale; not at t0 itself, an eigenvalue of a
+  // leading block of T, where the factorisation without pivoting grows),
+  // then four at w / 4 below their Rayleigh quotient (above, for the
+  // largest eigenvalue).  The result is accepted
+  // only if two inertia counts show that [theta - delta, theta + delta],
+  // delta >= 4 ||(T - theta) y||, holds exactly one eigenvalue and that it
+  // is the m-th: the eigenvalue within ||(T - theta) y|| of theta is then
+  // that one.
+  auto rqi = [&](int m, double t0, double r0, double& theta, double& res) {
+    if (!std::isfinite(t0) || !std::isfinite(r0)) return false;
+    const double w = 1e-6 * scale;
+    // Interlacing: Ritz values counted from the bottom only move down as
+    // the basis grows, the largest only up.
+    const double dir = (m == n - 1 && n > 1) ? 1.0 : -1.0;
+    double sigma = t0 + dir * std::max(r0, w), rT = INFINITY;
+    start_vector();
+    for (int it = 0; it < 2; ++it) {
+      double lmax = 0.0;
+      if (band_count_below(n, b, Lb.data(), sigma, fwork.data(), &lmax) < 0 || !(lmax < 1e3)) return false;
+      if (!ldl_steps(it == 0 ? 2 : 4)) return false;
+      rayleigh(theta, rT, res);
+      if (!std::isfinite(theta) || !std::isfinite(res)) return false;
+      sigma = theta + dir * 0.25 * w;
+    }
+    const double delta = std::max(4.0 * rT, 2.0 * w);
+    return count(theta - delta) == m && count(theta + delta) == m + 1;
+  };
+  // The smallest (m = 0) or largest (m = n - 1) eigenvalue by inverse
+  // iteration with shifts outside the spectrum, where T - sigma I is
+  // definite and its factorisation without pivoting is stable: from the
+  // Gershgorin bound, then from theta -/+ (||(T - theta) y|| + w) for as
+  // long as a count confirms that the shift is still outside.  Accepted, as
+  // in rqi, once converged and a count shows that [sigma, theta + delta]
+  // (mirrored for the largest) holds exactly one eigenvalue.
+  auto edge = [&](int m, double& theta, double& res) {
+    const bool low = m == 0;
+    if (!low && m != n - 1) return false;
+    const double w = 1e-6 * scale;
+    double sigma = low ? glo - w : ghi + w, rT = INFINITY;
+    const int outside = low ? 0 : n;
+    start_vector();
+    for (int it = 0; it < 8; ++it) {
+      double lmax = 0.0;
+      const int c = band_count_below(n, b, Lb.data(), sigma, fwork.data(), &lmax);
+      if (c != outside || !(lmax < 1e3)) return false;
+      if (!ldl_steps(3)) return false;
+      rayleigh(theta, rT, res);
+      if (!std::isfinite(theta) || !std::isfinite(res)) return false;
+      if (rT <= 1e-10 * scale) {
+        const double delta = std::max(4.0 * rT, 2.0 * w);
+        return low ? count(theta + delta) == 1 : count(theta - delta) == n - 1;
+      }
+      sigma = low ? theta - rT - w : theta + rT + w;
+    }
+    return false;
+  };
+  auto ritz = [&](int m, double& theta, double& res, double t0, double r0, double gap0) {
+    // The earlier value is a good start once its residual radius is well
+    // inside the gap to its neighbour.
+    if (std::isfinite(r0) && r0 < 0.25 * gap0 && rqi(m, t0, r0, theta, res)) return;
+    if (!std::isfinite(t0) && edge(m, theta, res)) return;
     double width = 1e-6 * scale;
     Bracket w0;
     Bracket b = warm(m, t0, r0, w0) ? bracket(m, width, &w0) : bracket(m, width, nullptr);
@@ -517,14 +646,18 @@ static void ritz_pairs(int j, int b, const double* TA, const double* TB, int nm,
     }
   };
   for (int q = 0; q < nm; ++q) {
-    ritz(ms[q], theta_out[q], res_out[q], t0 ? t0[q] : NAN, r0 ? r0[q] : NAN);
+    double gap0 = INFINITY;
+    if (t0)
+      for (int p = 0; p < nm; ++p)
+        if (p != q && std::isfinite(t0[p])) gap0 = std::min(gap0, std::fabs(t0[p] - t0[q]));
+    ritz(ms[q], theta_out[q], res_out[q], t0 ? t0[q] : NAN, r0 ? r0[q] : NAN, gap0);
     if (Y) std::copy(y.begin(), y.end(), Y + (size_t)q * n);
   }
 }
 
 // Ritz values theta_k, theta_{k+1} of T_j (and, with `extremes`, the
 // smallest and largest) with their residual radii; `prev` warm-starts the
-// bisections for theta_k and theta_{k+1}.
+// searches (the extremes too when it holds them).
 void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool extremes,
                 RitzCheck& out, const RitzCheck* prev) {
   const int ms[2] = {k - 1, k};
@@ -539,12 +672,24 @@ void ritz_check(int j, int b, int k, const double* TA, const double* TB, bool ex
   out.th_k1 = th[1];
   out.res_k = rs[0];
   out.res_k1 = rs[1];
-  if (extremes) {
-    const int me[2] = {0, j * b - 1};
+  if (extremes) ritz_extremes(j, b, TA, TB, out, prev);
+}
+
+void ritz_extremes(int j, int b, const double* TA, const double* TB, RitzCheck& out,
+                   const RitzCheck* prev) {
+  const int me[2] = {0, j * b - 1};
+  double th[2], rs[2];
+  if (prev && std::isfinite(prev->th_min) && std::isfinite(prev->th_max) &&
+      std::isfinite(prev->res_min) && std::isfinite(prev->res_max)) {
+    const double t0[2] = {prev->th_min, prev->th_max}, r0[2] = {prev->res_min, prev->res_max};
+    ritz_pairs(j, b, TA, TB, 2, me, t0, r0, th, rs, nullptr);
+  } else {
     ritz_pairs(j, b, TA, TB, 2, me, nullptr, nullptr, th, rs, nullptr);
-    out.th_min = th[0];
-    out.th_max = th[1];
   }
+  out.th_min = th[0];
+  out.th_max = th[1];
+  out.res_min = rs[0];
+  out.res_max = rs[1];
 }
 
 int ritz_vectors(int j, int b, const double* TA, const double* TB, int nvec, double* Y) {

@@ -4,11 +4,11 @@
 //
 //   two passes of block classical Gram-Schmidt against all of V
 //     k_lz_proj_partial / k_lz_proj_finish   C = V^T W   (n x nb)
-//     k_lz_apply_partial + k_lz_rows(SUB)    W <- W - V C
+//     k_lz_apply_rows                        W <- W - V C, row slabs
 //   then three rounds of Cholesky QR, the first one shifted (shifted
 //   CholQR3 of Fukaya, Kannan, Nakatsukasa, Zhang and Yamamoto, 2020), on
-//   the partial Gram matrices of 256-row slabs (from the second
-//   projection pass, or k_lz_rows(GRAM) for the start block):
+//   the partial Gram matrices of row slabs (from the second projection
+//   pass, or k_lz_apply_rows with no basis for the start block):
 //     k_lz_cholqr      every block sums the slab Grams and factors
 //                      G = L L^T itself (the same sum in the same order, so
 //                      the same R = L^T), then W <- W R^{-1} on its slab and
@@ -26,7 +26,6 @@
 namespace refl {
 
 constexpr int LZ_RC = 128;  // rows per block of the projection partials
-constexpr int LZ_CC = 64;   // basis columns per block of the update partials
 
 static inline int lz_nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
@@ -101,26 +100,34 @@ __global__ __launch_bounds__(256) void k_lz_proj_partial(const double* __restric
 
 // C[c + j n] = sum_rc part (fixed order).  The rows c >= n - b of C (the
 // coefficients on the newest block Q_j) are written to, or with `accumulate`
-// added to, Arec (b x b, column-major).
+// added to, Arec (b x b, column-major).  Four lanes per entry: lane q sums
+// the chunks rc = q mod 4 in order (eight loads in flight), and the four
+// sums are combined by a fixed butterfly, so every lane holds the same value.
 __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict__ part, int nrc,
                                                         int n, int nb, int NB,
                                                         double* __restrict__ C,
                                                         double* __restrict__ Arec, int b,
                                                         int accumulate) {
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  if (o >= n * nb) return;
-  const int c = o % n, j = o / n;
-  // Eight independent loads per round, added in chunk order.
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int q = (int)(g & 3);
+  const int64_t o = g >> 2;
+  const bool in = o < (int64_t)n * nb;
+  const int c = in ? (int)(o % n) : 0, j = in ? (int)(o / n) : 0;
   double s = 0.0;
-  int rc = 0;
-  for (; rc + 8 <= nrc; rc += 8) {
-    double a[8];
+  if (in) {
+    int rc = q;
+    for (; rc + 28 < nrc; rc += 32) {
+      double a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = part[((int64_t)(rc + u) * n + c) * NB + j];
+      for (int u = 0; u < 8; ++u) a[u] = part[((int64_t)(rc + 4 * u) * n + c) * NB + j];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += a[u];
+      for (int u = 0; u < 8; ++u) s += a[u];
+    }
+    for (; rc < nrc; rc += 4) s += part[((int64_t)rc * n + c) * NB + j];
   }
-  for (; rc < nrc; ++rc) s += part[((int64_t)rc * n + c) * NB + j];
+  s += __shfl_xor(s, 1, WAVE);
+  s += __shfl_xor(s, 2, WAVE);
+  if (!in || q != 0) return;
   C[c + (int64_t)j * n] = s;
   if (Arec && c >= n - b) {
     double* a = Arec + (c - (n - b)) + (int64_t)j * b;
@@ -128,104 +135,81 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
   }
 }
 
-// apart[(cc * NB + j) * d + r] = sum over the columns c of chunk cc of
-// V[r, c] C[c + j n].  One row per thread (128-row blocks); the chunk of C
-// sits in LDS.
+// W <- W - V C on 64-row slabs (V: d x n basis, ld ldv; C: n x nb,
+// column-major, ld n), one row per lane.  The eight waves of a block take
+// 32-column pieces of each 256-column chunk of C, which passes through LDS;
+// their sums are subtracted from the row in wave order (a fixed order), so
+// no column-chunk partials go through memory.  The result goes to dst (which
+// may be W: the block reads its rows before writing them), and with
+// gpart != null the slab's Gram matrix x^T x goes to
+// gpart[blockIdx.x NB^2 + i + j NB] (64-row slabs).  n = 0 only copies W and
+// forms the Gram partials.
+constexpr int LZ_AR = 64;    // rows per block (Gram slabs of the projection)
+constexpr int LZ_ACH = 256;  // columns of C per LDS chunk
 template <int NB>
-__global__ __launch_bounds__(128) void k_lz_apply_partial(const double* __restrict__ V, int64_t ldv,
-                                                          int n, const double* __restrict__ C,
-                                                          int nb, int d,
-                                                          double* __restrict__ apart) {
-  __shared__ double sC[LZ_CC][NB];
-  const int c0 = blockIdx.y * LZ_CC;
-  const int cn = min(LZ_CC, n - c0);
-  for (int e = threadIdx.x; e < LZ_CC * NB; e += 128) {
-    const int cl = e / NB, j = e % NB;
-    sC[cl][j] = (cl < cn && j < nb) ? C[(c0 + cl) + (int64_t)j * n] : 0.0;
-  }
-  __syncthreads();
-  const int r = blockIdx.x * 128 + threadIdx.x;
-  if (r >= d) return;
+__global__ __launch_bounds__(512) void k_lz_apply_rows(const double* __restrict__ V, int64_t ldv,
+                                                       int n, const double* __restrict__ C, int nb,
+                                                       int d, const double* W, int64_t ldw,
+                                                       double* dst, int64_t ldd,
+                                                       double* __restrict__ gpart) {
+  __shared__ double sC[LZ_ACH][NB];
+  __shared__ double sX[LZ_AR][NB + 1];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int r = blockIdx.x * LZ_AR + lane;
   double acc[NB];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) acc[j] = 0.0;
-  const double* v = V + (int64_t)c0 * ldv + r;
-  int cl = 0;
-  for (; cl + 8 <= cn; cl += 8) {
-    double x[8];
+  for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+  for (int cb = 0; cb < n; cb += LZ_ACH) {
+    const int cn = min(LZ_ACH, n - cb);
+    __syncthreads();
+    for (int e = t; e < LZ_ACH * NB; e += 512) {
+      const int cl = e / NB, q = e % NB;
+      sC[cl][q] = (cl < cn && q < nb) ? C[(cb + cl) + (int64_t)q * n] : 0.0;
+    }
+    __syncthreads();
+    const int c0 = wave * 32, c1 = min(c0 + 32, cn);
+    if (r < d) {
+      const double* v = V + (int64_t)cb * ldv + r;
+      int cl = c0;
+      for (; cl + 8 <= c1; cl += 8) {
+        double x[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = v[(int64_t)(cl + u) * ldv];
+        for (int u = 0; u < 8; ++u) x[u] = v[(int64_t)(cl + u) * ldv];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) acc[j] = fma(x[u], sC[cl + u][j], acc[j]);
-  }
-  for (; cl < cn; ++cl) {
-    const double x = v[(int64_t)cl * ldv];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] = fma(x, sC[cl][j], acc[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < NB; ++j)
-    if (j < nb) apart[((int64_t)blockIdx.y * NB + j) * d + r] = acc[j];
-}
-
-// Row-wise update of the d x nb block W (one row per thread, 256-row slabs):
-//   SUB   (apart != null)  w -= sum_cc apart[cc]            (fixed order)
-//   the result goes to dst (which may be W; none if null), and with gpart != null the
-//   slab's Gram matrix x^T x goes to gpart[blockIdx.x * NB * NB + i + j NB].
-// W and dst may be the same block (each thread reads its row before writing
-// it), so neither is declared restrict.
-template <int NB>
-__global__ __launch_bounds__(256) void k_lz_rows(const double* W, int64_t ldw, int nb,
-                                                 int d, const double* __restrict__ apart, int ncc,
-                                                 double* dst, int64_t ldd,
-                                                 double* __restrict__ gpart) {
-  __shared__ double sX[256][NB + 1];
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  double x[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) x[j] = 0.0;
-  if (r < d) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (j < nb) x[j] = W[(int64_t)j * ldw + r];
-    if (apart) {
-      // UNR chunks of loads in flight per round, subtracted in chunk order.
-      constexpr int UNR = NB <= 16 ? 4 : 2;
-      int cc = 0;
-      for (; cc + UNR <= ncc; cc += UNR) {
-        double a[UNR][NB];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u)
-#pragma unroll
-          for (int j = 0; j < NB; ++j)
-            a[u][j] = (j < nb) ? apart[((int64_t)(cc + u) * NB + j) * d + r] : 0.0;
-#pragma unroll
-        for (int u = 0; u < UNR; ++u)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) x[j] -= a[u][j];
+          for (int q = 0; q < NB; ++q) acc[q] = fma(x[u], sC[cl + u][q], acc[q]);
       }
-      for (; cc < ncc; ++cc)
+      for (; cl < c1; ++cl) {
+        const double x = v[(int64_t)cl * ldv];
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j < nb) x[j] -= apart[((int64_t)cc * NB + j) * d + r];
+        for (int q = 0; q < NB; ++q) acc[q] = fma(x, sC[cl][q], acc[q]);
+      }
     }
-    if (dst) {
+  }
+  if (wave == 0) {
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < nb) dst[(int64_t)j * ldd + r] = x[j];
+    for (int q = 0; q < NB; ++q) sX[lane][q] = (r < d && q < nb) ? W[(int64_t)q * ldw + r] : 0.0;
+  }
+  __syncthreads();
+  for (int w = 0; w < 8; ++w) {
+    if (wave == w && n > 0) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) sX[lane][q] -= acc[q];
     }
+    __syncthreads();
+  }
+  if (wave == 0 && r < d && dst) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+      if (q < nb) dst[(int64_t)q * ldd + r] = sX[lane][q];
   }
   if (!gpart) return;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) sX[threadIdx.x][j] = x[j];
-  __syncthreads();
-  for (int o = threadIdx.x; o < nb * nb; o += 256) {
-    const int i = o % nb, j = o / nb;
+  for (int o = t; o < nb * nb; o += 512) {
+    const int i = o % nb, jj = o / nb;
     double a = 0.0;
-    for (int t = 0; t < 256; ++t) a = fma(sX[t][i], sX[t][j], a);
-    gpart[(int64_t)blockIdx.x * NB * NB + i + j * NB] = a;
+    for (int rr = 0; rr < LZ_AR; ++rr) a = fma(sX[rr][i], sX[rr][jj], a);
+    gpart[(int64_t)blockIdx.x * NB * NB + i + jj * NB] = a;
   }
 }
 
@@ -235,6 +219,7 @@ struct LzFactor {
   double Bo[32][33];
   double Bt[32][33];
   double red[5];
+  double dev;  // ||G - I||_F of the summed Gram matrix, before shift and factorisation
   int bad;
 };
 
@@ -281,9 +266,15 @@ __device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb, in
   }
   __syncthreads();
   if (t == 0) {
-    double tr = 0.0;
+    double tr = 0.0, dv = 0.0;
     for (int i = 0; i < nb; ++i) tr += f.G[i][i];
+    for (int i = 0; i < nb; ++i)
+      for (int j = 0; j < nb; ++j) {
+        const double e = f.G[i][j] - (i == j ? 1.0 : 0.0);
+        dv += e * e;
+      }
     f.red[0] = shift_rel > 0.0 ? shift_rel * tr : 0.0;
+    f.dev = sqrt(dv);
   }
   __syncthreads();
   if (t < nb) f.G[t][t] += f.red[0];
@@ -365,6 +356,16 @@ __device__ void lz_record(int nb, int round, double* __restrict__ Bacc,
 // Gram of W from gin, dst = W R^{-1}, and with gout != null the slab Gram
 // partials of dst.  W and dst may be the same block (each thread reads its
 // row before writing it); gin and gout must differ.
+//
+// The third round of shifted CholQR3 is needed only when the block was
+// ill-conditioned: with mode LZ_QR_MAYBE_LAST (the second round) a Gram
+// matrix within LZ_QR_DONE of I (Frobenius) makes this round the last one:
+// it writes dst_last, records Arec / Brec and sets flag[2] = tag + 1 (else
+// 0), and a third round launched with LZ_QR_SKIPPABLE then returns at once.  (The
+// input's condition number is then below 1.01, so one CholQR round leaves
+// it orthonormal to working accuracy.)  Every block sums the same partials
+// in the same order, so every block takes the same branch.
+constexpr double LZ_QR_DONE = 1e-3;
 template <int NB>
 __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gin, int nblk,
                                                    int nb, double shift_rel,
@@ -374,7 +375,9 @@ __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gi
                                                    int* __restrict__ flag, int tag,
                                                    const double* W, int64_t ldw, int d,
                                                    double* dst, int64_t ldd,
-                                                   double* __restrict__ gout) {
+                                                   double* __restrict__ gout, int mode,
+                                                   double* dst_last) {
+  if (mode == LZ_QR_SKIPPABLE && flag[2] == tag + 1) return;
   __shared__ LzFactor f;
   __shared__ double sX[256][NB + 1];
   const int r = blockIdx.x * 256 + threadIdx.x;
@@ -385,6 +388,18 @@ __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gi
   for (int j = 0; j < NB; ++j) x[j] = (r < d && j < nb) ? W[(int64_t)j * ldw + r] : 0.0;
   const bool rec = blockIdx.x == 0;
   lz_factor(gin, nblk, nb, NB, shift_rel, Bacc, rec && round > 0, f);
+  __syncthreads();
+  const bool last_now = mode == LZ_QR_MAYBE_LAST && f.dev < LZ_QR_DONE;
+  if (mode == LZ_QR_MAYBE_LAST) {
+    if (rec && threadIdx.x == 0) flag[2] = last_now ? tag + 1 : 0;
+    if (last_now) {
+      dst = dst_last;
+      gout = nullptr;
+    } else {
+      Arec = nullptr;
+      Brec = nullptr;
+    }
+  }
   if (rec) lz_record(nb, round, Bacc, Arec, Brec, flag, tag, f);
   // x R = w for upper-triangular R = L^T: R[i][j] = G[j][i].
   if (r < d) {
@@ -425,61 +440,54 @@ int lz_nb_pad(int nb) { return nb <= 8 ? 8 : nb <= 16 ? 16 : 32; }
 size_t lz_proj_part_doubles(int d, int nmax, int nb) {
   return (size_t)lz_nblocks(d, LZ_RC) * nmax * lz_nb_pad(nb);
 }
-size_t lz_apply_part_doubles(int d, int nmax, int nb) {
-  return (size_t)lz_nblocks(nmax, LZ_CC) * lz_nb_pad(nb) * d;
-}
 size_t lz_gram_part_doubles(int d, int nb) {
   const int p = lz_nb_pad(nb);
-  return (size_t)lz_nblocks(d, 256) * p * p;
+  return (size_t)lz_nblocks(d, LZ_AR) * p * p;   // 64-row slabs (256-row for the later rounds)
 }
 
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
                       double* C, double* Arec, int b, int accumulate, double* ppart,
-                      double* apart, double* gpart, hipStream_t st) {
+                      double* gpart, hipStream_t st) {
   const int nrc = lz_nblocks(d, LZ_RC);
-  const int ncc = lz_nblocks(n, LZ_CC);
   LZ_DISPATCH(nb, {
     hipLaunchKernelGGL((k_lz_proj_partial<NB>), dim3(lz_nblocks(n, 64), nrc), dim3(256), 0, st, V,
                        ldv, n, W, ldw, nb, d, ppart);
-    hipLaunchKernelGGL(k_lz_proj_finish, dim3(lz_nblocks((int64_t)n * nb, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_lz_proj_finish, dim3(lz_nblocks((int64_t)n * nb * 4, 256)), dim3(256), 0, st,
                        ppart, nrc, n, nb, NB, C, Arec, b, accumulate);
-    hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 128), ncc), dim3(128), 0, st,
-                       V, ldv, n, C, nb, d, apart);
-    hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, W, ldw, nb, d,
-                       apart, ncc, W, ldw, gpart);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(512), 0, st, V, ldv, n,
+                       C, nb, d, W, ldw, W, ldw, gpart);
   })
   return hipGetLastError();
 }
 
 hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
-                      double* apart, const double* Wzero, double* dst, int64_t ldd,
-                      hipStream_t st) {
-  const int ncc = lz_nblocks(n, LZ_CC);
+                      const double* Wzero, double* dst, int64_t ldd, hipStream_t st) {
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_apply_partial<NB>), dim3(lz_nblocks(d, 128), ncc), dim3(128), 0, st,
-                       V, ldv, n, Cneg, nb, d, apart);
-    hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, Wzero, ldd, nb,
-                       d, apart, ncc, dst, ldd, nullptr);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(512), 0, st, V, ldv, n,
+                       Cneg, nb, d, Wzero, ldd, dst, ldd, nullptr);
   })
   return hipGetLastError();
 }
 
 hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st) {
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_rows<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, W, ldw, nb, d,
-                       nullptr, 0, nullptr, ldw, gpart);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(512), 0, st, nullptr,
+                       ldw, 0, nullptr, nb, d, W, ldw, nullptr, ldw, gpart);
   })
   return hipGetLastError();
 }
 
-hipError_t lz_cholqr(const double* gin, int d, int nb, double shift_rel, double* Bacc, int round,
-                     const double* Arec, double* Brec, int* flag, int tag, const double* W,
-                     int64_t ldw, double* dst, int64_t ldd, double* gout, hipStream_t st) {
-  if (gin == gout) return hipErrorInvalidValue;
+hipError_t lz_cholqr(const double* gin, int gin_rows, int d, int nb, double shift_rel, double* Bacc,
+                     int round, const double* Arec, double* Brec, int* flag, int tag,
+                     const double* W, int64_t ldw, double* dst, int64_t ldd, double* gout,
+                     int mode, double* dst_last, hipStream_t st) {
+  if (gin == gout || (gin_rows != LZ_AR && gin_rows != 256)) return hipErrorInvalidValue;
+  if (mode < LZ_QR_PLAIN || mode > LZ_QR_SKIPPABLE || (mode == LZ_QR_MAYBE_LAST && !dst_last))
+    return hipErrorInvalidValue;
   LZ_DISPATCH(nb, {
     hipLaunchKernelGGL((k_lz_cholqr<NB>), dim3(lz_nblocks(d, 256)), dim3(256), 0, st, gin,
-                       lz_nblocks(d, 256), nb, shift_rel, Bacc, round, Arec, Brec, flag, tag, W,
-                       ldw, d, dst, ldd, gout);
+                       lz_nblocks(d, gin_rows), nb, shift_rel, Bacc, round, Arec, Brec, flag, tag, W,
+                       ldw, d, dst, ldd, gout, mode, dst_last);
   })
   return hipGetLastError();
 }

@@ -312,30 +312,34 @@ hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, i
 // blocks of nb <= 32 columns.
 int lz_nb_pad(int nb);
 size_t lz_proj_part_doubles(int d, int nmax, int nb);
-size_t lz_apply_part_doubles(int d, int nmax, int nb);
 size_t lz_gram_part_doubles(int d, int nb);
 // One block Gram-Schmidt pass of W (d x nb) against V (d x n): C = V^T W,
 // W <- W - V C.  The rows of C on the last b columns of V go to Arec
 // (accumulate: added).  With gpart != null the Gram partials of the new W
-// are written for lz_cholqr.
+// (64-row slabs) are written for lz_cholqr.
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
                       double* C, double* Arec, int b, int accumulate, double* ppart,
-                      double* apart, double* gpart, hipStream_t st);
+                      double* gpart, hipStream_t st);
 // dst = V Y for the d x n basis V and Y = -Cneg (n x nb, column-major, ld
 // n), computed as Wzero - V Cneg with Wzero an all-zero d x nb block of
 // leading dimension ldd (the projection kernels' update).
 hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
-                      double* apart, const double* Wzero, double* dst, int64_t ldd,
-                      hipStream_t st);
-// Gram partials of the 256-row slabs of W (d x nb): gpart[slab NB^2 + i + j NB].
+                      const double* Wzero, double* dst, int64_t ldd, hipStream_t st);
+// Gram partials of the 64-row slabs of W (d x nb): gpart[slab NB^2 + i + j NB].
 hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st);
-// One Cholesky QR round: factor the summed Gram partials gin (+ shift_rel *
-// trace I) as L L^T, dst = W R^{-1} with R = L^T (W and dst may alias), and
-// with gout != null (gout != gin) the Gram partials of dst.  Bacc = R
-// (round 0) or R Bacc; see lanczos.hip for Brec and flag.
-hipError_t lz_cholqr(const double* gin, int d, int nb, double shift_rel, double* Bacc, int round,
-                     const double* Arec, double* Brec, int* flag, int tag, const double* W,
-                     int64_t ldw, double* dst, int64_t ldd, double* gout, hipStream_t st);
+// One Cholesky QR round: factor the summed Gram partials gin (slabs of
+// gin_rows = 64 or 256 rows) (+ shift_rel * trace I) as L L^T,
+// dst = W R^{-1} with R = L^T (W and dst may alias), and with gout != null
+// (gout != gin) the Gram partials of dst (256-row slabs).  Bacc = R
+// (round 0) or R Bacc; see lanczos.hip for Brec and flag (4 ints).
+// mode LZ_QR_MAYBE_LAST: when the Gram matrix is within 1e-3 of I this
+// round writes dst_last instead of dst, records Arec / Brec and is the last
+// one; a following round with LZ_QR_SKIPPABLE then does nothing.
+constexpr int LZ_QR_PLAIN = 0, LZ_QR_MAYBE_LAST = 1, LZ_QR_SKIPPABLE = 2;
+hipError_t lz_cholqr(const double* gin, int gin_rows, int d, int nb, double shift_rel, double* Bacc,
+                     int round, const double* Arec, double* Brec, int* flag, int tag,
+                     const double* W, int64_t ldw, double* dst, int64_t ldd, double* gout,
+                     int mode, double* dst_last, hipStream_t st);
 
 // ---- allocation-free entry point ----
 // Bytes of the fixed per-device scratch array (noalloc.hip) that serves as

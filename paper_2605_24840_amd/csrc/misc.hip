@@ -654,11 +654,14 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
   return x ^ (x >> 31);
 }
+// Grid (row blocks, columns): one entry per thread (the 64-bit multiplies of
+// the hash are long; a loop over the columns per thread kept only a few
+// compute units busy).
 __global__ __launch_bounds__(256) void k_random_block(double* __restrict__ V, int64_t ldv, int d,
                                                       int nb, uint64_t seed) {
   const int row = blockIdx.x * 256 + threadIdx.x;
   if (row >= d) return;
-  for (int c = 0; c < nb; ++c) {
+  for (int c = blockIdx.y; c < nb; c += gridDim.y) {
     const uint64_t h = splitmix64(seed * 0x100000001B3ull + (uint64_t)c * (uint64_t)d + row);
     V[(int64_t)c * ldv + row] = ((double)(h >> 11) * 0x1.0p-53) * 2.0 - 1.0;
   }
@@ -1344,7 +1347,9 @@ hipError_t form_sym_pair(const double* Z, const double* V, int64_t ld, int k, in
   return hipGetLastError();
 }
 hipError_t random_block(double* V, int64_t ldv, int d, int nb, uint64_t seed, hipStream_t st) {
-  hipLaunchKernelGGL(k_random_block, dim3(nblocks(d, 256)), dim3(256), 0, st, V, ldv, d, nb, seed);
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_random_block, dim3(nblocks(d, 256), std::min(nb, 1024)), dim3(256), 0, st, V, ldv, d,
+                     nb, seed);
   return hipGetLastError();
 }
 

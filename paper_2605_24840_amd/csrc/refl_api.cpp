@@ -146,7 +146,7 @@ constexpr size_t LZ_PIN_INITIAL = sizeof(double) * 2 * 2048 * 32 + 4096;
 struct LzWork {
   int b = 0, J = 0, nmax = 0;
   double *V = nullptr, *W = nullptr, *C = nullptr;
-  double *ppart = nullptr, *apart = nullptr, *gp[2] = {nullptr, nullptr};  // Gram partials, by round parity
+  double *ppart = nullptr, *gp[2] = {nullptr, nullptr};  // Gram partials, by round parity
   double *Bacc = nullptr, *TA = nullptr, *TB = nullptr;
   int* flag = nullptr;
 };
@@ -716,13 +716,12 @@ void carve_lanczos(Carve& c, LzWork& z, int64_t d, int dp, int k, int steps) {
   z.W = c.take<double>(ld * z.b);
   z.C = c.take<double>((size_t)z.nmax * z.b);
   z.ppart = c.take<double>(lz_proj_part_doubles((int)d, z.nmax, z.b));
-  z.apart = c.take<double>(lz_apply_part_doubles((int)d, z.nmax, z.b));
   z.gp[0] = c.take<double>(lz_gram_part_doubles((int)d, z.b));
   z.gp[1] = c.take<double>(lz_gram_part_doubles((int)d, z.b));
   z.Bacc = c.take<double>((size_t)z.b * z.b);
   z.TA = c.take<double>((size_t)z.J * z.b * z.b);
   z.TB = c.take<double>((size_t)z.J * z.b * z.b);
-  z.flag = c.take<int>(2);
+  z.flag = c.take<int>(4);
 }
 
 struct LzResult {
@@ -744,16 +743,20 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   const int b = z.b, J = z.J;
   const int64_t ld = dp;
   const double shift_rel = 11.0 * ((double)d * b + (double)b * (b + 1)) * 2.220446049250313e-16;
-  HIPCHK(hipMemsetAsync(z.flag, 0, 2 * sizeof(int), st));
+  HIPCHK(hipMemsetAsync(z.flag, 0, 4 * sizeof(int), st));
   // Q_1: the start block, orthonormalised by shifted CholQR3.
   // Rounds of CholQR3 on z.W, whose Gram partials are in gp[0]; the last
-  // round writes Q to dst.
+  // round writes Q to dst.  The second round finishes the QR itself when its
+  // Gram matrix is already close to I, and the third then does nothing.
   auto cholqr3_rounds = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
-    for (int round = 0; round < 3; ++round)
-      HIPCHK(lz_cholqr(z.gp[round & 1], (int)d, b, round == 0 ? shift_rel : 0.0, z.Bacc, round,
-                       round == 2 ? Arec : nullptr, round == 2 ? Brec : nullptr, z.flag, tag, z.W,
-                       ld, round == 2 ? dst : z.W, ld, round == 2 ? nullptr : z.gp[(round + 1) & 1],
-                       st));
+    for (int round = 0; round < 3; ++round) {
+      const bool last = round == 2;
+      const int mode = round == 0 ? LZ_QR_PLAIN : round == 1 ? LZ_QR_MAYBE_LAST : LZ_QR_SKIPPABLE;
+      HIPCHK(lz_cholqr(z.gp[round & 1], round == 0 ? 64 : 256, (int)d, b, round == 0 ? shift_rel : 0.0,
+                       z.Bacc, round, round >= 1 ? Arec : nullptr, round >= 1 ? Brec : nullptr, z.flag,
+                       tag, z.W, ld, last ? dst : z.W, ld, last ? nullptr : z.gp[(round + 1) & 1], mode,
+                       round == 1 ? dst : nullptr, st));
+    }
     return REFL_OK;
   };
   auto cholqr3 = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
@@ -801,6 +804,21 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   // bisections from the previous test's Ritz values.
   RitzCheck prev_rc;
   bool have_prev = false;
+  // Residual bounds of the last two evaluated tests, for the schedule below.
+  int hist_j[2] = {0, 0}, nhist = 0;
+  double hist_eps[2] = {NaN, NaN}, hist_gap = NaN;
+  // True when the test after step jt is expected to pass: its residual
+  // bound, extrapolated geometrically from the last two tests, is below
+  // twice the threshold.  Such a test is evaluated two steps after it is
+  // enqueued instead of one interval later, so that fewer steps run past
+  // convergence.
+  auto expect_pass = [&](int jt) {
+    if (nhist < 2 || !(hist_eps[1] > 0.0) || !(hist_eps[0] > hist_eps[1]) || hist_j[1] <= hist_j[0])
+      return false;
+    const double rate = std::log(hist_eps[1] / hist_eps[0]) / (hist_j[1] - hist_j[0]);
+    const double pred = hist_eps[1] * std::exp(rate * (jt - hist_j[1]));
+    return pred < 0.5 * hist_gap;
+  };
   auto evaluate = [&](int j, int slot, int& done) -> refl_status_t {
     done = 0;
     HIPCHK(hipEventSynchronize(h->lz_ev[slot]));
@@ -821,13 +839,24 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     }
     RitzCheck rc;
     ritz_check(jj, b, k, hTA, hTB, false, rc, have_prev ? &prev_rc : nullptr);
-    prev_rc = rc;
-    have_prev = true;
     const double eps = std::max(rc.res_k, rc.res_k1);
     const bool conv = eps < 0.25 * (rc.th_k1 - rc.th_k);
+    hist_j[0] = hist_j[1];
+    hist_eps[0] = hist_eps[1];
+    hist_j[1] = jj;
+    hist_eps[1] = eps;
+    hist_gap = rc.th_k1 - rc.th_k;
+    ++nhist;
+    // The extreme Ritz values are needed by the last test only.  They are
+    // first found (from the Gershgorin bounds) by the test before the one
+    // expected to pass, while the device still runs a full interval of
+    // steps, and then followed from test to test (a few inertia counts).
+    const bool had_ext = have_prev && std::isfinite(prev_rc.th_min);
+    if (conv || stop || had_ext || expect_pass(jj + ci))
+      ritz_extremes(jj, b, hTA, hTB, rc, had_ext ? &prev_rc : nullptr);
+    prev_rc = rc;
+    have_prev = true;
     if (conv || stop) {
-      RitzCheck last = rc;
-      ritz_check(jj, b, k, hTA, hTB, true, rc, &last);
       r.lam_k = rc.th_k;
       r.lam_k1 = rc.th_k1;
       r.eps = eps;
@@ -852,24 +881,24 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     for (double& v : Y) v = -v;
     HIPCHK(hipMemcpyAsync(z.C, Y.data(), sizeof(double) * Y.size(), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemset2DAsync(z.W, sizeof(double) * ld, 0, sizeof(double) * d, b, st));
-    HIPCHK(lz_combine(z.V, ld, n, z.C, b, (int)d, z.apart, z.W, z.W, ld, st));
+    HIPCHK(lz_combine(z.V, ld, n, z.C, b, (int)d, z.W, z.W, ld, st));
     HIPCHK(hipMemcpy2DAsync(ritz_out, sizeof(double) * ldr, z.W, sizeof(double) * ld,
                             sizeof(double) * d, b, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     return REFL_OK;
   };
   // The test after step j is evaluated on the host while the device runs
-  // the steps up to the next test (steps enqueued past convergence are
-  // discarded).
-  int pending = -1, pending_slot = 0, ntest = 0, copied = 0;
+  // the steps up to the next test, or only the next two steps when the test
+  // is expected to pass (steps enqueued past convergence are discarded).
+  int pending = -1, pending_slot = 0, pending_lead = 0, ntest = 0, copied = 0;
   for (int j = 1; j <= J; ++j) {
     const int n = j * b;
     const double* Qj = z.V + (int64_t)(n - b) * ld;
     double* Aj = z.TA + (size_t)(j - 1) * blk;
     double* Bj = z.TB + (size_t)(j - 1) * blk;
     HIPCHK(symthin_f64(Hf, ld, (int)d, Qj, ld, b, z.W, ld, thin, st));
-    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, z.apart, nullptr, st));
-    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.apart, z.gp[0], st));
+    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, nullptr, st));
+    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.gp[0], st));
     if ((int64_t)n >= d) {
       HIPCHK(hipMemsetAsync(Bj, 0, sizeof(double) * blk, st));  // the basis spans R^d
     } else {
@@ -879,7 +908,19 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     }
     // A warm start may converge within a few steps: those are all tested.
     const bool test = (j >= j0 && ((j - j0) % ci == 0 || (start && j - j0 < 4))) || j == J;
-    if (!test) continue;
+    if (!test) {
+      if (pending > 0 && j - pending >= pending_lead) {
+        int done = 0;
+        refl_status_t e = evaluate(pending, pending_slot, done);
+        if (e == REFL_OK && done) e = ritz_block();
+        if (e != REFL_OK || done) {
+          HIPCHK(hipStreamSynchronize(st));
+          return e;
+        }
+        pending = -1;
+      }
+      continue;
+    }
     const int slot = ntest++ & 1;
     const size_t nb_new = (size_t)(j - copied) * blk;
     HIPCHK(hipMemcpyAsync(hTA + copied * blk, z.TA + copied * blk, sizeof(double) * nb_new,
@@ -900,6 +941,7 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     }
     pending = j;
     pending_slot = slot;
+    pending_lead = expect_pass(j) ? 2 : J;
   }
   if (pending > 0) {
     int done = 0;

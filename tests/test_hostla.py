@@ -221,6 +221,10 @@ def test_ritz_check_warm_start_matches_cold(lib):
         lib.t_ritz(j, b, k, ptr(TA), ptr(TB), 0, ptr(warm), None if prev is None else ptr(prev))
         scale = np.abs(np.linalg.eigvalsh(_dense_T(TA, TB, j, b))).max()
         assert abs(cold[0] - warm[0]) <= 1e-9 * scale and abs(cold[1] - warm[1]) <= 1e-9 * scale
+        # Residual radii: a warm start near convergence takes shifted inverse
+        # iteration from the previous value instead of a bisection; both give
+        # the radius of the same Ritz pair.
+        assert np.all(np.abs(cold[2:4] - warm[2:4]) <= 1e-6 * cold[2:4] + 1e-10 * scale), (j, cold, warm)
         prev = np.array(warm[:4])
     bad = np.array([warm[0] + 3.0, warm[1] - 2.0, 1e-14, 1e-14])
     lib.t_ritz(J, b, k, ptr(TA), ptr(TB), 0, ptr(warm), ptr(bad))

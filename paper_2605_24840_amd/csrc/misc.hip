@@ -453,6 +453,17 @@ __global__ __launch_bounds__(256) void k_batch_copy(const BatchDesc* __restrict_
 }
 
 // ------------------------------------------------------- thin products
+// Partial sums of the symmetric thin passes are stored per block, not per
+// column: chunk q, row block rb (256 rows), column c, row t of the block at
+//   work[((q nrb + rb) NB + c) 256 + t],  nrb = ceil(d / 256),
+// so each block writes NB contiguous 2 KB runs (one column-major d-long
+// vector per chunk and column, 32 KB apart, cost about 10 us more per pass
+// at d = 4096 in a probe of the FP32 pass, for 2.6 MB of partials).
+template <int NB>
+__device__ __forceinline__ int64_t thin_block_base(int q, int rb, int nrb) {
+  return ((int64_t)q * nrb + rb) * NB * 256;
+}
+
 // Y (d x nb, column-major) = M V.  Grid (row groups of 64, column chunks of
 // CH); each wave owns 16 rows.  A lane keeps V[j, 0..NB) for the CH/64
 // columns j it reads in registers, multiplies them into one row at a time
@@ -515,7 +526,10 @@ __global__ __launch_bounds__(256) void k_thin_partial(const MT* __restrict__ M, 
   }
 }
 
-template <int NB>
+// Grid (row blocks of 256, columns).  BLK: the partials are in the block
+// layout of the symmetric passes (rows of a block of 256 contiguous), else
+// at work[chunk][c][row] (leading dimension wld).
+template <int NB, bool BLK>
 __global__ __launch_bounds__(256) void k_thin_finish(const double* __restrict__ work, int64_t wld,
                                                      int nchunk, int d, int nb,
                                                      double* __restrict__ Y, int64_t ldy) {
@@ -523,7 +537,12 @@ __global__ __launch_bounds__(256) void k_thin_finish(const double* __restrict__ 
   const int c = blockIdx.y;
   if (row >= d || c >= nb) return;
   double s = 0.0;
-  for (int q = 0; q < nchunk; ++q) s += work[((int64_t)q * NB + c) * wld + row];
+  if (BLK) {
+    const int nrb = gridDim.x;
+    for (int q = 0; q < nchunk; ++q) s += work[thin_block_base<NB>(q, blockIdx.x, nrb) + c * 256 + threadIdx.x];
+  } else {
+    for (int q = 0; q < nchunk; ++q) s += work[((int64_t)q * NB + c) * wld + row];
+  }
   Y[(int64_t)c * ldy + row] = s;
 }
 
@@ -674,8 +693,8 @@ __global__ __launch_bounds__(256) void k_random_block(double* __restrict__ V, in
 // four waves: group g sums rows [g CHUNK/KS, (g + 1) CHUNK/KS) of the chunk.
 // The rows of M stream coalesced across the lanes, the CHUNK x NB block of V
 // sits in LDS and is read as wave-uniform broadcasts, and the KS group sums
-// are added in LDS in group order.  Partial sums per chunk go to
-// work[chunk][c][r]; a finishing kernel adds the chunks in order.
+// are added in LDS in group order.  Partial sums per chunk go to work in the
+// block layout above; a finishing kernel adds the chunks in order.
 constexpr int SRC = 128;
 
 template <int KS, int NB>
@@ -683,10 +702,47 @@ struct ThinRed {
   double v[KS > 1 ? (KS - 1) * NB * 256 : 1];
 };
 
+// A barrier that orders only LDS: global loads in flight stay in flight
+// (__syncthreads waits for every outstanding memory access of the wave).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// p[i] if ok, else 0, loaded without a branch (the index falls back to 0,
+// which must be valid).  A load inside a branch is waited for where the
+// branch ends, so a run of conditional loads made as many round trips to
+// memory as there were loads.
+template <typename T>
+__device__ __forceinline__ double ldsel(const T* __restrict__ p, int64_t i, bool ok) {
+  const T v = p[ok ? i : 0];
+  return ok ? (double)v : 0.0;
+}
+
+// The first eight rows of M of a lane (they do not depend on V), so that a
+// kernel can request them before it sets up the V block in LDS.
+template <typename MT, int CHUNK, int KS>
+__device__ __forceinline__ void symthin_first(const MT* __restrict__ M, int64_t ldm, int64_t ps,
+                                              int d, double (&m0)[8]) {
+  constexpr int PART = CHUNK / KS;
+  const int t = threadIdx.x & 255, g = threadIdx.x >> 8;
+  const int r = blockIdx.x * 256 + t;
+  const int j0 = blockIdx.y * CHUNK + g * PART;
+  const int jn = max(0, min(PART, d - j0));
+  const int rc = min(r, d - 1);  // in bounds for every lane; masked below
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double v = MLoad<MT>::at(M, (int64_t)min(j0 + u, d - 1) * ldm + rc, ps);
+    m0[u] = (r < d && u < jn) ? v : 0.0;
+  }
+}
+
 template <typename MT, int NB, int CHUNK, int KS>
 __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t ldm, int64_t ps, int d,
                                              const double (*pv)[NB], double* __restrict__ work,
-                                             int64_t wld, int nb, ThinRed<KS, NB>& red) {
+                                             int64_t wld, int nb, ThinRed<KS, NB>& red,
+                                             const double (&m0)[8]) {
   static_assert(CHUNK % KS == 0, "chunk must split evenly");
   constexpr int PART = CHUNK / KS;
   const int t = threadIdx.x & 255, g = threadIdx.x >> 8;
@@ -698,20 +754,44 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
   for (int c = 0; c < NB; ++c) acc[c] = 0.0;
   if (r < d) {
     const double (*pp)[NB] = pv + g * PART;
-    int jj = 0;
-    for (; jj + 8 <= jn; jj += 8) {
-      double m[8];
+    // A full chunk (every chunk but the last) runs a loop of known length,
+    // unrolled, so that the compiler requests later rows before the
+    // products of earlier ones: a runtime loop waited out a memory round
+    // trip per eight rows (measured at d = 4096, FP32, 5 columns: 11 against
+    // 18 us per pass).
+    if (jn == PART) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) m[u] = MLoad<MT>::at(M, (int64_t)(j0 + jj + u) * ldm + r, ps);
+      for (int jb = 0; jb < PART; jb += 8) {
+        double m[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 8; ++u)
+          m[u] = jb == 0 ? m0[u] : MLoad<MT>::at(M, (int64_t)(j0 + jb + u) * ldm + r, ps);
 #pragma unroll
-        for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pp[jj + u][c], acc[c]);
-    }
-    for (; jj < jn; ++jj) {
-      const double m = MLoad<MT>::at(M, (int64_t)(j0 + jj) * ldm + r, ps);
+        for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int c = 0; c < NB; ++c) acc[c] = fma(m, pp[jj][c], acc[c]);
+          for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pp[jb + u][c], acc[c]);
+      }
+    } else {
+      int jj = 0;
+      for (; jj + 8 <= jn; jj += 8) {
+        double m[8];
+        if (jj == 0) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) m[u] = m0[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) m[u] = MLoad<MT>::at(M, (int64_t)(j0 + jj + u) * ldm + r, ps);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pp[jj + u][c], acc[c]);
+      }
+      for (; jj < jn; ++jj) {
+        const double m = jj < 8 ? m0[jj] : MLoad<MT>::at(M, (int64_t)(j0 + jj) * ldm + r, ps);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = fma(m, pp[jj][c], acc[c]);
+      }
     }
   }
   if constexpr (KS > 1) {
@@ -727,9 +807,10 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
       for (int c = 0; c < NB; ++c) acc[c] += red.v[(q * NB + c) * 256 + t];
   }
   if (r < d) {
+    double* wb = work + thin_block_base<NB>(blockIdx.y, blockIdx.x, gridDim.x) + t;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c < nb) work[((int64_t)blockIdx.y * NB + c) * wld + r] = acc[c];
+      if (c < nb) wb[c * 256] = acc[c];
   }
 }
 
@@ -753,12 +834,23 @@ __global__ __launch_bounds__(256 * KS) void k_symthin(const MT* __restrict__ M, 
   __shared__ double pv[CHUNK][NB];
   __shared__ ThinRed<KS, NB> red;
   const int j0 = blockIdx.y * CHUNK;
-  for (int e = threadIdx.x; e < CHUNK * NB; e += 256 * KS) {
+  constexpr int PER = (CHUNK * NB + 256 * KS - 1) / (256 * KS);
+  double vv[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * 256 * KS;
     const int jj = e / NB, c = e % NB, j = j0 + jj;
-    pv[jj][c] = (j < d && c < nb) ? V[(int64_t)c * ldv + j] : 0.0;
+    vv[u] = ldsel(V, (int64_t)c * ldv + j, e < CHUNK * NB && j < d && c < nb);
   }
-  __syncthreads();
-  symthin_body<MT, NB, CHUNK, KS>(M, ldm, ps, d, pv, work, wld, nb, red);
+  double m0[8];
+  symthin_first<MT, CHUNK, KS>(M, ldm, ps, d, m0);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * 256 * KS;
+    if (e < CHUNK * NB) pv[e / NB][e % NB] = vv[u];
+  }
+  lds_barrier();
+  symthin_body<MT, NB, CHUNK, KS>(M, ldm, ps, d, pv, work, wld, nb, red, m0);
 }
 
 // ------------------------------------------------------------ block CG
@@ -831,31 +923,102 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j0 = blockIdx.y * CHUNK;
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+  // Every global load of the block's set-up is issued before the first wait
+  // (and the first rows of M after them), and the barriers between the
+  // set-up steps order only LDS: the set-up's chain of dependent round trips
+  // to memory then overlaps the start of the pass over M.
+  double m0[8];
   if (it == 0) {
-    for (int e = tid; e < NB * CHUNK; e += NT) {
-      const int c = e / CHUNK, jj = e % CHUNK, j = j0 + jj;
-      pv[jj][c] = (c < nb && j < d) ? b.R[0][(int64_t)c * ldv + j] : 0.0;
+    double rv[(NB * CHUNK + NT - 1) / NT];
+#pragma unroll
+    for (int u = 0; u < (NB * CHUNK + NT - 1) / NT; ++u) {
+      const int e = tid + u * NT;
+      const int c = e / CHUNK, j = j0 + e % CHUNK;
+      rv[u] = ldsel(b.R[0], (int64_t)c * ldv + j, e < NB * CHUNK && c < nb && j < d);
+    }
+    symthin_first<MT, CHUNK, KS>(M, ldm, 0, d, m0);
+#pragma unroll
+    for (int u = 0; u < (NB * CHUNK + NT - 1) / NT; ++u) {
+      const int e = tid + u * NT;
+      if (e < NB * CHUNK) pv[e % CHUNK][e / CHUNK] = rv[u];
     }
     if (first && tid == 0) st->iters = 0;
   } else {
     // Partials of the previous apply: apart[(g nb + c)(k + 2) + v], v < k
-    // the entries of C[:, c], then gamma and delta.
+    // the entries of C[:, c], then gamma and delta.  A wave takes up to four
+    // (c, v) pairs at once, so that their loads are in flight together.
     const int nv = k + 2, npairs = nb * nv;
-    for (int q = wave; q < npairs; q += NW) {
-      const int c = q / nv, v = q % nv;
-      double acc = 0.0;
-      for (int g = lane; g < ngroups; g += 64) acc += apart[((int64_t)g * nb + c) * nv + v];
-      acc = wave_sum(acc);
-      if (lane == 0) sC[c][v] = acc;
+    const int tc = min(tid, nb - 1);  // values of threads >= nb are not used
+    const double gp = st->gam[it & 1][tc], ap = st->alpha[it & 1][tc];
+    const double tol2 = st->tol2, rho0 = st->rho0[tc];
+    // The first 64 groups' partials (a lane each); any more are added later.
+    double acc0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = wave + u * NW;
+      acc0[u] = ldsel(apart, ((int64_t)lane * nb + q / nv) * nv + q % nv, lane < ngroups && q < npairs);
+    }
+    // The rows of the update (the block's chunk), V up to KV columns.
+    const double* Rin = b.R[(it - 1) & 1];
+    double* Rout = b.R[it & 1];
+    const double* Pin = b.P[it & 1];
+    double* Pout = b.P[(it - 1) & 1];
+    const double* Sin = b.S[it & 1];
+    double* Sout = b.S[(it - 1) & 1];
+    const bool writer = blockIdx.x == 0;
+    constexpr int PER = (NB * CHUNK + NT - 1) / NT, KV = NB < 8 ? NB : 8;
+    double hr[PER], r[PER], pprev[PER], sprev[PER], z[PER], vv[PER][KV];
+    const double* Vb = k > 0 ? V : b.HR;  // a valid address for the masked loads
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT;
+      const int c = e / CHUNK, j = j0 + e % CHUNK;
+      const bool ok = e < NB * CHUNK && c < nb && j < d;
+      const int64_t o = ok ? (int64_t)c * ldv + j : 0;
+      hr[u] = ldsel(b.HR, o, ok);
+#pragma unroll
+      for (int i = 0; i < KV; ++i) vv[u][i] = ldsel(Vb, (int64_t)i * ldv + j, ok && i < k);
+      r[u] = ldsel(Rin, o, ok);
+      pprev[u] = ldsel(Pin, o, ok && it >= 2);
+      sprev[u] = ldsel(Sin, o, ok && it >= 2);
+      z[u] = ldsel(b.Z, o, ok && writer);
+    }
+    symthin_first<MT, CHUNK, KS>(M, ldm, 0, d, m0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = wave + u * NW;
+      if (q < npairs) {  // wave-uniform
+        double acc = acc0[u];
+        for (int g = lane + 64; g < ngroups; g += 64) acc += apart[((int64_t)g * nb + q / nv) * nv + q % nv];
+        const double t = wave_sum(acc);
+        if (lane == 0) sC[q / nv][q % nv] = t;
+      }
+    }
+    for (int q0 = wave + 4 * NW; q0 < npairs; q0 += 4 * NW) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int g = lane; g < ngroups; g += 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * NW;
+          if (q < npairs) acc[u] += apart[((int64_t)g * nb + q / nv) * nv + q % nv];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * NW;
+        if (q < npairs) {  // wave-uniform
+          const double t = wave_sum(acc[u]);
+          if (lane == 0) sC[q / nv][q % nv] = t;
+        }
+      }
     }
     if (tid == 0) sconv = 1;
-    __syncthreads();
+    lds_barrier();
     if (tid < nb) {
       const int c = tid;
       const double gam = sC[c][k], del = sC[c][k + 1];
       double alpha, beta = 0.0;
       if (it >= 2) {
-        const double gp = st->gam[it & 1][c], ap = st->alpha[it & 1][c];
         beta = gp > 0.0 ? gam / gp : 0.0;
         const double den = del - (ap != 0.0 ? beta * gam / ap : 0.0);
         alpha = den != 0.0 ? gam / den : 0.0;
@@ -864,13 +1027,13 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
       }
       sal[c] = alpha;
       sbe[c] = beta;
-      if (!(gam <= st->tol2 * st->rho0[c])) sconv = 0;
+      if (!(gam <= tol2 * rho0)) sconv = 0;
       if (first) {
         st->gam[(it - 1) & 1][c] = gam;
         st->alpha[(it - 1) & 1][c] = alpha;
       }
     }
-    __syncthreads();
+    lds_barrier();
     // Iteration it applies update it - 1; the test is on r_{it-1}.
     if (sconv || it - 1 >= max_iter) {
       if (first && tid == 0) {
@@ -879,31 +1042,30 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
       }
       return;
     }
-    const double* Rin = b.R[(it - 1) & 1];
-    double* Rout = b.R[it & 1];
-    const double* Pin = b.P[it & 1];
-    double* Pout = b.P[(it - 1) & 1];
-    const double* Sin = b.S[it & 1];
-    double* Sout = b.S[(it - 1) & 1];
-    const bool writer = blockIdx.x == 0;
-    for (int e = tid; e < NB * CHUNK; e += NT) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * NT;
+      if (e >= NB * CHUNK) break;
       const int c = e / CHUNK, jj = e % CHUNK, j = j0 + jj;
       double rn = 0.0;
       if (c < nb && j < d) {
         const int64_t o = (int64_t)c * ldv + j;
-        double w = b.HR[o];
-        for (int i = 0; i < k; ++i) w = fma(-V[(int64_t)i * ldv + j], sC[c][i], w);
-        const double r = Rin[o], al = sal[c];
-        double pn = r, sn = w;
+        double w = hr[u];
+#pragma unroll
+        for (int i = 0; i < KV; ++i)
+          if (i < k) w = fma(-vv[u][i], sC[c][i], w);
+        for (int i = KV; i < k; ++i) w = fma(-V[(int64_t)i * ldv + j], sC[c][i], w);
+        const double al = sal[c];
+        double pn = r[u], sn = w;
         if (it >= 2) {
-          pn = fma(sbe[c], Pin[o], r);
-          sn = fma(sbe[c], Sin[o], w);
+          pn = fma(sbe[c], pprev[u], r[u]);
+          sn = fma(sbe[c], sprev[u], w);
         }
-        rn = fma(-al, sn, r);
+        rn = fma(-al, sn, r[u]);
         if (writer) {
           Pout[o] = pn;
           Sout[o] = sn;
-          b.Z[o] = fma(al, pn, b.Z[o]);
+          b.Z[o] = fma(al, pn, z[u]);
           Rout[o] = rn;
         }
       }
@@ -911,8 +1073,8 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
     }
     if (first && tid == 0) st->iters = it;
   }
-  __syncthreads();
-  symthin_body<MT, NB, CHUNK, KS>(M, ldm, 0, d, pv, work, wld, nb, red);
+  lds_barrier();
+  symthin_body<MT, NB, CHUNK, KS>(M, ldm, 0, d, pv, work, wld, nb, red, m0);
 }
 
 // Grid (row groups of 64, column c), 256 threads: four lanes per row, each
@@ -932,24 +1094,35 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & 3;
   const int row = blockIdx.x * 64 + (tid >> 2);
-  double rc = 0.0, s = 0.0;
-  if (row < d) {
-    double acc[4] = {0, 0, 0, 0};
-    int q = sub;
-    for (; q + 12 < nchunk; q += 16) {
+  const bool owner = sub == 0 && row < d;
+  // Loads that do not wait for the chunk sums are requested first, and
+  // without branches (masked loads).
+  constexpr int KV = NB < 8 ? NB : 8;
+  const int64_t o = (int64_t)c * ldv + row;
+  const double r0 = ldsel(R, o, owner);
+  const double th = st->theta[c];
+  const double* Vb = k > 0 ? V : R;  // a valid address for the masked loads
+  double vr[KV];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += work[((int64_t)(q + 4 * u) * NB + c) * wld + row];
-    }
-    for (; q < nchunk; q += 4) acc[0] += work[((int64_t)q * NB + c) * wld + row];
-    s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int i = 0; i < KV; ++i) vr[i] = ldsel(Vb, (int64_t)i * ldv + row, owner && i < k);
+  // Partials in the block layout of the symmetric passes.
+  const int rowc = row < d ? row : d - 1;
+  const int nrb = (d + 255) / 256;
+  const double* wr = work + (int64_t)c * 256 + (rowc & 255);
+  const int rb = rowc >> 8;
+  double acc[4] = {0, 0, 0, 0};
+  int q = sub;
+  for (; q + 12 < nchunk; q += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += wr[thin_block_base<NB>(q + 4 * u, rb, nrb)];
   }
+  for (; q < nchunk; q += 4) acc[0] += wr[thin_block_base<NB>(q, rb, nrb)];
+  double s = row < d ? (acc[0] + acc[1]) + (acc[2] + acc[3]) : 0.0;
   s += __shfl_xor(s, 1, WAVE);
   s += __shfl_xor(s, 2, WAVE);
-  const bool owner = sub == 0 && row < d;
+  const double rc = owner ? r0 : 0.0;
   if (owner) {
-    const int64_t o = (int64_t)c * ldv + row;
-    rc = R[o];
-    s -= st->theta[c] * rc;
+    s -= th * rc;
     HR[o] = s;
   } else {
     s = 0.0;
@@ -957,7 +1130,14 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
   // Partials: V^T (H - theta) r (k values), r.r, r.(H - theta) r at
   // apart[group][c][0..k+1]; the four waves' sums are added in a fixed order.
   for (int i = 0; i < k; ++i) {
-    const double vi = owner ? V[(int64_t)i * ldv + row] : 0.0;
+    double vi;
+    if (i < KV) {
+      vi = vr[0];
+#pragma unroll
+      for (int u = 1; u < KV; ++u) vi = i == u ? vr[u] : vi;
+    } else {
+      vi = owner ? V[(int64_t)i * ldv + row] : 0.0;
+    }
     const double t = wave_sum(vi * s);
     if (lane == 0) red[wave][i] = t;
   }
@@ -1265,8 +1445,8 @@ static hipError_t thin_dispatch(const MT* M, int64_t ldm, int64_t ps, int d, con
     const int nch = nblocks(d, CHV);                                                             \
     hipLaunchKernelGGL((k_thin_partial<MT, NBV, CHV>), dim3(rows, nch), dim3(256), 0, st, M, ldm, \
                        ps, d, V, ldv, nb, work, wld);                                            \
-    hipLaunchKernelGGL((k_thin_finish<NBV>), dim3(nblocks(d, 256), nb), dim3(256), 0, st, work,  \
-                       wld, nch, d, nb, Y, ldy);                                                 \
+    hipLaunchKernelGGL((k_thin_finish<NBV, false>), dim3(nblocks(d, 256), nb), dim3(256), 0, st,  \
+                       work, wld, nch, d, nb, Y, ldy);                                           \
   }
   if (nb <= 0) return hipSuccess;
   if (nb <= 1) REFL_THIN(1, 512)
@@ -1359,9 +1539,10 @@ size_t cg_state_bytes() {
 }
 size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 34; }  // nb (k + 2) per group
 size_t thin_work_doubles(int d) {
-  const size_t a = (size_t)nblocks(d, 128) * 32 * (size_t)d;
-  const size_t b = (size_t)nblocks(d, SRC) * 32 * (size_t)d;
-  const size_t c = (size_t)nblocks(d, CG_SRC) * 32 * (size_t)d;  // the CG pass
+  const size_t dr = (size_t)nblocks(d, 256) * 256;  // the block layout rounds d up
+  const size_t a = (size_t)nblocks(d, 128) * 32 * dr;
+  const size_t b = (size_t)nblocks(d, SRC) * 32 * dr;
+  const size_t c = (size_t)nblocks(d, CG_SRC) * 32 * dr;  // the CG pass
   return std::max(a, std::max(b, c));
 }
 size_t gram_work_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 32; }
@@ -1387,8 +1568,8 @@ static hipError_t symthin_dispatch(const MT* M, int64_t ldm, int64_t ps, int d, 
     const dim3 grid(nblocks(d, 256), nblocks(d, symthin_chunk<NBV>()));                          \
     hipLaunchKernelGGL((k_symthin<MT, NBV>), grid, dim3(256 * symthin_ks<NBV>()), 0, st, M, ldm, \
                        ps, d, V, ldv, nb, work, wld);                                            \
-    hipLaunchKernelGGL((k_thin_finish<NBV>), dim3(nblocks(d, 256), nb), dim3(256), 0, st, work,  \
-                       wld, (int)grid.y, d, nb, Y, ldy);                                         \
+    hipLaunchKernelGGL((k_thin_finish<NBV, true>), dim3(nblocks(d, 256), nb), dim3(256), 0, st,   \
+                       work, wld, (int)grid.y, d, nb, Y, ldy);                                   \
   }
   if (nb <= 0) return hipSuccess;
   REFL_NB_DISPATCH(nb, REFL_STHIN)

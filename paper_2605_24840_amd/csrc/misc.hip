@@ -738,7 +738,9 @@ __device__ __forceinline__ void symthin_first(const MT* __restrict__ M, int64_t 
   }
 }
 
-template <typename MT, int NB, int CHUNK, int KS>
+// With HAVE0 the first eight rows of M come in m0 (symthin_first), else
+// the body loads them.
+template <typename MT, int NB, int CHUNK, int KS, bool HAVE0 = true>
 __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t ldm, int64_t ps, int d,
                                              const double (*pv)[NB], double* __restrict__ work,
                                              int64_t wld, int nb, ThinRed<KS, NB>& red,
@@ -754,18 +756,17 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
   for (int c = 0; c < NB; ++c) acc[c] = 0.0;
   if (r < d) {
     const double (*pp)[NB] = pv + g * PART;
-    // A full chunk (every chunk but the last) runs a loop of known length,
-    // unrolled, so that the compiler requests later rows before the
-    // products of earlier ones: a runtime loop waited out a memory round
-    // trip per eight rows (measured at d = 4096, FP32, 5 columns: 11 against
-    // 18 us per pass).
-    if (jn == PART) {
+    // For the narrow types a full chunk (every chunk but the last) runs a
+    // loop of known length, unrolled, so that the compiler requests later
+    // rows before the products of earlier ones.  (The FP64 pass with 12
+    // columns ran slower that way: 28 against 24 us at d = 4096.)
+    if (sizeof(MT) < 8 && jn == PART) {
 #pragma unroll
       for (int jb = 0; jb < PART; jb += 8) {
         double m[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          m[u] = jb == 0 ? m0[u] : MLoad<MT>::at(M, (int64_t)(j0 + jb + u) * ldm + r, ps);
+          m[u] = (HAVE0 && jb == 0) ? m0[u] : MLoad<MT>::at(M, (int64_t)(j0 + jb + u) * ldm + r, ps);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -775,7 +776,7 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
       int jj = 0;
       for (; jj + 8 <= jn; jj += 8) {
         double m[8];
-        if (jj == 0) {
+        if (HAVE0 && jj == 0) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) m[u] = m0[u];
         } else {
@@ -788,7 +789,7 @@ __device__ __forceinline__ void symthin_body(const MT* __restrict__ M, int64_t l
           for (int c = 0; c < NB; ++c) acc[c] = fma(m[u], pp[jj + u][c], acc[c]);
       }
       for (; jj < jn; ++jj) {
-        const double m = jj < 8 ? m0[jj] : MLoad<MT>::at(M, (int64_t)(j0 + jj) * ldm + r, ps);
+        const double m = (HAVE0 && jj < 8) ? m0[jj] : MLoad<MT>::at(M, (int64_t)(j0 + jj) * ldm + r, ps);
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = fma(m, pp[jj][c], acc[c]);
       }
@@ -834,23 +835,13 @@ __global__ __launch_bounds__(256 * KS) void k_symthin(const MT* __restrict__ M, 
   __shared__ double pv[CHUNK][NB];
   __shared__ ThinRed<KS, NB> red;
   const int j0 = blockIdx.y * CHUNK;
-  constexpr int PER = (CHUNK * NB + 256 * KS - 1) / (256 * KS);
-  double vv[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * 256 * KS;
+  for (int e = threadIdx.x; e < CHUNK * NB; e += 256 * KS) {
     const int jj = e / NB, c = e % NB, j = j0 + jj;
-    vv[u] = ldsel(V, (int64_t)c * ldv + j, e < CHUNK * NB && j < d && c < nb);
+    pv[jj][c] = ldsel(V, (int64_t)c * ldv + j, j < d && c < nb);
   }
-  double m0[8];
-  symthin_first<MT, CHUNK, KS>(M, ldm, ps, d, m0);
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * 256 * KS;
-    if (e < CHUNK * NB) pv[e / NB][e % NB] = vv[u];
-  }
-  lds_barrier();
-  symthin_body<MT, NB, CHUNK, KS>(M, ldm, ps, d, pv, work, wld, nb, red, m0);
+  __syncthreads();
+  const double m0[8] = {};
+  symthin_body<MT, NB, CHUNK, KS, false>(M, ldm, ps, d, pv, work, wld, nb, red, m0);
 }
 
 // ------------------------------------------------------------ block CG

@@ -159,12 +159,24 @@ __global__ __launch_bounds__(512) void k_lz_apply_rows(const double* __restrict_
   double acc[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+  // C's chunk is loaded with masked loads (no branch: a load in a branch is
+  // waited for where the branch ends), all of a thread's at once.
+  constexpr int PERC = (LZ_ACH * NB + 511) / 512;
   for (int cb = 0; cb < n; cb += LZ_ACH) {
     const int cn = min(LZ_ACH, n - cb);
+    double cv[PERC];
+#pragma unroll
+    for (int u = 0; u < PERC; ++u) {
+      const int e = t + u * 512, cl = e / NB, q = e % NB;
+      const bool ok = e < LZ_ACH * NB && cl < cn && q < nb;
+      const double v = C[ok ? (cb + cl) + (int64_t)q * n : 0];
+      cv[u] = ok ? v : 0.0;
+    }
     __syncthreads();
-    for (int e = t; e < LZ_ACH * NB; e += 512) {
-      const int cl = e / NB, q = e % NB;
-      sC[cl][q] = (cl < cn && q < nb) ? C[(cb + cl) + (int64_t)q * n] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PERC; ++u) {
+      const int e = t + u * 512;
+      if (e < LZ_ACH * NB) sC[e / NB][e % NB] = cv[u];
     }
     __syncthreads();
     const int c0 = wave * 32, c1 = min(c0 + 32, cn);
@@ -188,8 +200,15 @@ __global__ __launch_bounds__(512) void k_lz_apply_rows(const double* __restrict_
     }
   }
   if (wave == 0) {
+    // Every load of the row before any select (the compiler otherwise waited
+    // after each load).
+    double wrow[NB];
+    const int rc = min(r, d - 1);
 #pragma unroll
-    for (int q = 0; q < NB; ++q) sX[lane][q] = (r < d && q < nb) ? W[(int64_t)q * ldw + r] : 0.0;
+    for (int q = 0; q < NB; ++q) wrow[q] = W[(int64_t)min(q, nb - 1) * ldw + rc];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) sX[lane][q] = (r < d && q < nb) ? wrow[q] : 0.0;
   }
   __syncthreads();
   for (int w = 0; w < 8; ++w) {

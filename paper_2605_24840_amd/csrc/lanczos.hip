@@ -239,25 +239,40 @@ struct LzFactor {
   double Bt[32][33];
   double red[5];
   double dev;  // ||G - I||_F of the summed Gram matrix, before shift and factorisation
+  double inv[32];  // 1 / L[j][j]
   int bad;
 };
+
+// Orders the LDS accesses of one wave (the hardware completes them in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
 
 // All threads of the block.  G = sum of the slab Gram matrices gpart
 // (nblk slabs of NBP x NBP, fixed order), symmetrised, plus sigma I with
 // sigma = shift_rel * trace(G) when shift_rel > 0; then G = L L^T in place
 // (lower triangle; R = L^T).  A non-positive pivot is replaced by 1 and
 // f.bad set.  With load_bo, f.Bo = Bacc (nb x nb, column-major).
-__device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb, int NBP,
+template <int NBP>
+__device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb,
                           double shift_rel, const double* __restrict__ Bacc, bool load_bo,
                           LzFactor& f) {
   const int t = threadIdx.x;
-  // Thread t sums entry t (and t + 256, ...) over the slabs: sixteen loads
-  // in flight per round, accumulated round-robin into four sums.
+  // Thread t sums entry t (and t + 256, ...) over the slabs: 32 loads in
+  // flight per round, accumulated round-robin into four sums.
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
     const double* g = gpart + i + j * NBP;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     int b = 0;
+    for (; b + 32 <= nblk; b += 32) {
+      double a[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) a[u] = g[(int64_t)(b + u) * NBP * NBP];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) s4[u & 3] += a[u];
+    }
     for (; b + 16 <= nblk; b += 16) {
       double a[16];
 #pragma unroll
@@ -275,47 +290,62 @@ __device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb, in
   }
   if (t == 0) f.bad = 0;
   __syncthreads();
-  for (int e = t; e < nb * nb; e += 256) {
-    const int i = e % nb, j = e / nb;
-    if (i < j) {
-      const double v = 0.5 * (f.G[i][j] + f.G[j][i]);
-      f.G[i][j] = v;
-      f.G[j][i] = v;
+  // The rest is the work of wave 0 alone, its steps ordered by wavefront
+  // fences (LDS accesses of one wave complete in order) instead of block
+  // barriers: symmetrise, trace and ||G - I||_F (lane sums, then a fixed
+  // butterfly), the shift, the Cholesky factorisation and the reciprocals
+  // of its diagonal.
+  if (t < 64) {
+    for (int e = t; e < nb * nb; e += 64) {
+      const int i = e % nb, j = e / nb;
+      if (i < j) {
+        const double v = 0.5 * (f.G[i][j] + f.G[j][i]);
+        f.G[i][j] = v;
+        f.G[j][i] = v;
+      }
     }
-  }
-  __syncthreads();
-  if (t == 0) {
+    wave_fence();
     double tr = 0.0, dv = 0.0;
-    for (int i = 0; i < nb; ++i) tr += f.G[i][i];
-    for (int i = 0; i < nb; ++i)
-      for (int j = 0; j < nb; ++j) {
-        const double e = f.G[i][j] - (i == j ? 1.0 : 0.0);
-        dv += e * e;
-      }
-    f.red[0] = shift_rel > 0.0 ? shift_rel * tr : 0.0;
-    f.dev = sqrt(dv);
-  }
-  __syncthreads();
-  if (t < nb) f.G[t][t] += f.red[0];
-  __syncthreads();
-  // Right-looking Cholesky, lower triangle; thread t < nb owns row t.
-  for (int p = 0; p < nb; ++p) {
+    for (int e = t; e < nb * nb; e += 64) {
+      const int i = e % nb, j = e / nb;
+      const double g = f.G[i][j], x = g - (i == j ? 1.0 : 0.0);
+      if (i == j) tr += g;
+      dv += x * x;
+    }
+    tr = wave_sum(tr);
+    dv = wave_sum(dv);
+    const double sh = shift_rel > 0.0 ? shift_rel * tr : 0.0;
     if (t == 0) {
-      double piv = f.G[p][p];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        piv = 1.0;
-        f.bad = 1;
+      f.red[0] = sh;
+      f.dev = sqrt(dv);
+    }
+    if (t < nb) f.G[t][t] += sh;
+    wave_fence();
+    // Right-looking Cholesky, lower triangle; lane t < nb owns row t.
+    for (int p = 0; p < nb; ++p) {
+      if (t == 0) {
+        double piv = f.G[p][p];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          piv = 1.0;
+          f.bad = 1;
+        }
+        f.G[p][p] = sqrt(piv);
       }
-      f.G[p][p] = sqrt(piv);
+      wave_fence();
+      if (t > p && t < nb) {
+        const double l = f.G[t][p] / f.G[p][p];
+        f.G[t][p] = l;
+      }
+      wave_fence();
+      if (t > p && t < nb) {
+        const double l = f.G[t][p];
+        for (int j = p + 1; j <= t; ++j) f.G[t][j] -= l * f.G[j][p];
+      }
+      wave_fence();
     }
-    __syncthreads();
-    if (t > p && t < nb) {
-      const double l = f.G[t][p] / f.G[p][p];
-      f.G[t][p] = l;
-      for (int j = p + 1; j <= t; ++j) f.G[t][j] -= l * f.G[j][p];
-    }
-    __syncthreads();
+    if (t < nb) f.inv[t] = 1.0 / f.G[t][t];
   }
+  __syncthreads();
 }
 
 // Block 0 of a round.  Bacc = R (round 0) or R Bacc.  bit 1 of flag[0] for
@@ -406,7 +436,7 @@ __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gi
 #pragma unroll
   for (int j = 0; j < NB; ++j) x[j] = (r < d && j < nb) ? W[(int64_t)j * ldw + r] : 0.0;
   const bool rec = blockIdx.x == 0;
-  lz_factor(gin, nblk, nb, NB, shift_rel, Bacc, rec && round > 0, f);
+  lz_factor<NB>(gin, nblk, nb, shift_rel, Bacc, rec && round > 0, f);
   __syncthreads();
   const bool last_now = mode == LZ_QR_MAYBE_LAST && f.dev < LZ_QR_DONE;
   if (mode == LZ_QR_MAYBE_LAST) {
@@ -428,7 +458,7 @@ __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gi
         double s = x[j];
 #pragma unroll
         for (int i = 0; i < j; ++i) s = fma(-x[i], f.G[j][i], s);
-        x[j] = s / f.G[j][j];
+        x[j] = s * f.inv[j];
       }
     }
 #pragma unroll
@@ -441,9 +471,10 @@ __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gi
   __syncthreads();
   for (int o = threadIdx.x; o < nb * nb; o += 256) {
     const int i = o % nb, j = o / nb;
-    double a = 0.0;
-    for (int t = 0; t < 256; ++t) a = fma(sX[t][i], sX[t][j], a);
-    gout[(int64_t)blockIdx.x * NB * NB + i + j * NB] = a;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int t = 0; t < 256; ++t) a4[t & 3] = fma(sX[t][i], sX[t][j], a4[t & 3]);
+    gout[(int64_t)blockIdx.x * NB * NB + i + j * NB] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   }
 }
 

@@ -135,39 +135,52 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
   }
 }
 
-// W <- W - V C on 64-row slabs (V: d x n basis, ld ldv; C: n x nb,
-// column-major, ld n), one row per lane.  The eight waves of a block take
-// 32-column pieces of each 256-column chunk of C, which passes through LDS;
-// their sums are subtracted from the row in wave order (a fixed order), so
-// no column-chunk partials go through memory.  The result goes to dst (which
-// may be W: the block reads its rows before writing them), and with
+// W <- W - V C on 16-row slabs (V: d x n basis, ld ldv; C: n x nb,
+// column-major, ld n).  A block is 16 rows x AG column groups (AG = 32, or
+// 16 for blocks wider than 16 columns): a lane owns one row and takes the
+// columns g, g + AG, ... of each 256-column chunk of C, which passes through
+// LDS; the groups' sums meet in LDS and are added in group order (a fixed
+// order), so no column partials go through memory.  The result goes to dst
+// (which may be W: the block reads its rows before writing them), and with
 // gpart != null the slab's Gram matrix x^T x goes to
-// gpart[blockIdx.x NB^2 + i + j NB] (64-row slabs).  n = 0 only copies W and
-// forms the Gram partials.
-constexpr int LZ_AR = 64;    // rows per block (Gram slabs of the projection)
+// gpart[blockIdx.x NB^2 + i + j NB].  n = 0 only copies W and forms the Gram
+// partials.  Short slabs give many blocks: one compute unit streams its
+// share of V (16 rows of n columns) quickly, where 64-row slabs left 64
+// blocks of 64 n 8 bytes each on a 256-unit device.
+constexpr int LZ_AR = LZ_GRAM_ROWS;
 constexpr int LZ_ACH = 256;  // columns of C per LDS chunk
 template <int NB>
-__global__ __launch_bounds__(512) void k_lz_apply_rows(const double* __restrict__ V, int64_t ldv,
-                                                       int n, const double* __restrict__ C, int nb,
-                                                       int d, const double* W, int64_t ldw,
-                                                       double* dst, int64_t ldd,
-                                                       double* __restrict__ gpart) {
+constexpr int lz_ag() { return NB <= 16 ? 32 : 16; }
+template <int NB>
+__global__ __launch_bounds__(LZ_AR * lz_ag<NB>()) void k_lz_apply_rows(
+    const double* __restrict__ V, int64_t ldv, int n, const double* __restrict__ C, int nb, int d,
+    const double* W, int64_t ldw, double* dst, int64_t ldd, double* __restrict__ gpart) {
+  constexpr int AG = lz_ag<NB>(), NT = LZ_AR * AG;
   __shared__ double sC[LZ_ACH][NB];
+  __shared__ double sP[AG][LZ_AR][NB + 1];
   __shared__ double sX[LZ_AR][NB + 1];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int r = blockIdx.x * LZ_AR + lane;
+  const int t = threadIdx.x, row = t % LZ_AR, g = t / LZ_AR;
+  const int r0 = blockIdx.x * LZ_AR, r = r0 + row;
+  // The slab of W (LZ_AR x NB), requested first; masked loads without
+  // branches (a load in a branch is waited for where the branch ends).
+  constexpr int PERW = (LZ_AR * NB + NT - 1) / NT;
+  double wv[PERW];
+#pragma unroll
+  for (int u = 0; u < PERW; ++u) {
+    const int o = t + u * NT, rr = r0 + o % LZ_AR, q = o / LZ_AR;
+    const double v = W[(int64_t)min(q, nb - 1) * ldw + min(rr, d - 1)];
+    wv[u] = (o < LZ_AR * NB && rr < d && q < nb) ? v : 0.0;
+  }
   double acc[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) acc[q] = 0.0;
-  // C's chunk is loaded with masked loads (no branch: a load in a branch is
-  // waited for where the branch ends), all of a thread's at once.
-  constexpr int PERC = (LZ_ACH * NB + 511) / 512;
+  constexpr int PERC = (LZ_ACH * NB + NT - 1) / NT;
   for (int cb = 0; cb < n; cb += LZ_ACH) {
     const int cn = min(LZ_ACH, n - cb);
     double cv[PERC];
 #pragma unroll
     for (int u = 0; u < PERC; ++u) {
-      const int e = t + u * 512, cl = e / NB, q = e % NB;
+      const int e = t + u * NT, cl = e / NB, q = e % NB;
       const bool ok = e < LZ_ACH * NB && cl < cn && q < nb;
       const double v = C[ok ? (cb + cl) + (int64_t)q * n : 0];
       cv[u] = ok ? v : 0.0;
@@ -175,59 +188,51 @@ __global__ __launch_bounds__(512) void k_lz_apply_rows(const double* __restrict_
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PERC; ++u) {
-      const int e = t + u * 512;
+      const int e = t + u * NT;
       if (e < LZ_ACH * NB) sC[e / NB][e % NB] = cv[u];
     }
     __syncthreads();
-    const int c0 = wave * 32, c1 = min(c0 + 32, cn);
     if (r < d) {
       const double* v = V + (int64_t)cb * ldv + r;
-      int cl = c0;
-      for (; cl + 8 <= c1; cl += 8) {
+      int cl = g;
+      for (; cl + 7 * AG < cn; cl += 8 * AG) {
         double x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = v[(int64_t)(cl + u) * ldv];
+        for (int u = 0; u < 8; ++u) x[u] = v[(int64_t)(cl + u * AG) * ldv];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-          for (int q = 0; q < NB; ++q) acc[q] = fma(x[u], sC[cl + u][q], acc[q]);
+          for (int q = 0; q < NB; ++q) acc[q] = fma(x[u], sC[cl + u * AG][q], acc[q]);
       }
-      for (; cl < c1; ++cl) {
+      for (; cl < cn; cl += AG) {
         const double x = v[(int64_t)cl * ldv];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] = fma(x, sC[cl][q], acc[q]);
       }
     }
   }
-  if (wave == 0) {
-    // Every load of the row before any select (the compiler otherwise waited
-    // after each load).
-    double wrow[NB];
-    const int rc = min(r, d - 1);
 #pragma unroll
-    for (int q = 0; q < NB; ++q) wrow[q] = W[(int64_t)min(q, nb - 1) * ldw + rc];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int q = 0; q < NB; ++q) sX[lane][q] = (r < d && q < nb) ? wrow[q] : 0.0;
-  }
+  for (int q = 0; q < NB; ++q) sP[g][row][q] = acc[q];
   __syncthreads();
-  for (int w = 0; w < 8; ++w) {
-    if (wave == w && n > 0) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) sX[lane][q] -= acc[q];
+  for (int u = 0; u < PERW; ++u) {
+    const int o = t + u * NT;
+    if (o < LZ_AR * NB) {
+      const int rw = o % LZ_AR, q = o / LZ_AR, rr = r0 + rw;
+      double sum = 0.0;
+      for (int gg = 0; gg < AG; ++gg) sum += sP[gg][rw][q];
+      const double x = wv[u] - sum;
+      sX[rw][q] = x;
+      if (dst && rr < d && q < nb) dst[(int64_t)q * ldd + rr] = x;
     }
-    __syncthreads();
-  }
-  if (wave == 0 && r < d && dst) {
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-      if (q < nb) dst[(int64_t)q * ldd + r] = sX[lane][q];
   }
   if (!gpart) return;
-  for (int o = t; o < nb * nb; o += 512) {
+  __syncthreads();
+  for (int o = t; o < nb * nb; o += NT) {
     const int i = o % nb, jj = o / nb;
     double a = 0.0;
-    for (int rr = 0; rr < LZ_AR; ++rr) a = fma(sX[rr][i], sX[rr][jj], a);
+#pragma unroll
+    for (int rw = 0; rw < LZ_AR; ++rw) a = fma(sX[rw][i], sX[rw][jj], a);
     gpart[(int64_t)blockIdx.x * NB * NB + i + jj * NB] = a;
   }
 }
@@ -259,13 +264,20 @@ __device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb,
                           double shift_rel, const double* __restrict__ Bacc, bool load_bo,
                           LzFactor& f) {
   const int t = threadIdx.x;
-  // Thread t sums entry t (and t + 256, ...) over the slabs: 32 loads in
+  // Thread t sums entry t (and t + 256, ...) over the slabs: 64 loads in
   // flight per round, accumulated round-robin into four sums.
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e % nb, j = e / nb;
     const double* g = gpart + i + j * NBP;
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     int b = 0;
+    for (; b + 64 <= nblk; b += 64) {
+      double a[64];
+#pragma unroll
+      for (int u = 0; u < 64; ++u) a[u] = g[(int64_t)(b + u) * NBP * NBP];
+#pragma unroll
+      for (int u = 0; u < 64; ++u) s4[u & 3] += a[u];
+    }
     for (; b + 32 <= nblk; b += 32) {
       double a[32];
 #pragma unroll
@@ -492,7 +504,7 @@ size_t lz_proj_part_doubles(int d, int nmax, int nb) {
 }
 size_t lz_gram_part_doubles(int d, int nb) {
   const int p = lz_nb_pad(nb);
-  return (size_t)lz_nblocks(d, LZ_AR) * p * p;   // 64-row slabs (256-row for the later rounds)
+  return (size_t)lz_nblocks(d, LZ_AR) * p * p;   // LZ_AR-row slabs (256-row for the later rounds)
 }
 
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
@@ -504,7 +516,7 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
                        ldv, n, W, ldw, nb, d, ppart);
     hipLaunchKernelGGL(k_lz_proj_finish, dim3(lz_nblocks((int64_t)n * nb * 4, 256)), dim3(256), 0, st,
                        ppart, nrc, n, nb, NB, C, Arec, b, accumulate);
-    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(512), 0, st, V, ldv, n,
+    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n,
                        C, nb, d, W, ldw, W, ldw, gpart);
   })
   return hipGetLastError();
@@ -513,7 +525,7 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
 hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
                       const double* Wzero, double* dst, int64_t ldd, hipStream_t st) {
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(512), 0, st, V, ldv, n,
+    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n,
                        Cneg, nb, d, Wzero, ldd, dst, ldd, nullptr);
   })
   return hipGetLastError();
@@ -521,7 +533,7 @@ hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, i
 
 hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st) {
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(512), 0, st, nullptr,
+    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(LZ_AR * lz_ag<NB>()), 0, st, nullptr,
                        ldw, 0, nullptr, nb, d, W, ldw, nullptr, ldw, gpart);
   })
   return hipGetLastError();

@@ -308,6 +308,9 @@ hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, i
                         double* work, double* part, int it, int max_iter, hipStream_t st);
 
 // ---- block Lanczos (see lanczos.hip) ----
+// Rows per slab of the Gram partials that the projection writes (the first
+// CholQR round reads slabs of this many rows).
+constexpr int LZ_GRAM_ROWS = 16;
 // Workspace sizes (doubles) for a d-row basis of up to nmax columns and
 // blocks of nb <= 32 columns.
 int lz_nb_pad(int nb);
@@ -316,7 +319,7 @@ size_t lz_gram_part_doubles(int d, int nb);
 // One block Gram-Schmidt pass of W (d x nb) against V (d x n): C = V^T W,
 // W <- W - V C.  The rows of C on the last b columns of V go to Arec
 // (accumulate: added).  With gpart != null the Gram partials of the new W
-// (64-row slabs) are written for lz_cholqr.
+// (LZ_GRAM_ROWS-row slabs) are written for lz_cholqr.
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
                       double* C, double* Arec, int b, int accumulate, double* ppart,
                       double* gpart, hipStream_t st);
@@ -325,10 +328,10 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
 // leading dimension ldd (the projection kernels' update).
 hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
                       const double* Wzero, double* dst, int64_t ldd, hipStream_t st);
-// Gram partials of the 64-row slabs of W (d x nb): gpart[slab NB^2 + i + j NB].
+// Gram partials of the LZ_GRAM_ROWS-row slabs of W (d x nb): gpart[slab NB^2 + i + j NB].
 hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st);
 // One Cholesky QR round: factor the summed Gram partials gin (slabs of
-// gin_rows = 64 or 256 rows) (+ shift_rel * trace I) as L L^T,
+// gin_rows = LZ_GRAM_ROWS or 256 rows) (+ shift_rel * trace I) as L L^T,
 // dst = W R^{-1} with R = L^T (W and dst may alias), and with gout != null
 // (gout != gin) the Gram partials of dst (256-row slabs).  Bacc = R
 // (round 0) or R Bacc; see lanczos.hip for Brec and flag (4 ints).

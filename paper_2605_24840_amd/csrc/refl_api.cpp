@@ -752,7 +752,7 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     for (int round = 0; round < 3; ++round) {
       const bool last = round == 2;
       const int mode = round == 0 ? LZ_QR_PLAIN : round == 1 ? LZ_QR_MAYBE_LAST : LZ_QR_SKIPPABLE;
-      HIPCHK(lz_cholqr(z.gp[round & 1], round == 0 ? 64 : 256, (int)d, b, round == 0 ? shift_rel : 0.0,
+      HIPCHK(lz_cholqr(z.gp[round & 1], round == 0 ? LZ_GRAM_ROWS : 256, (int)d, b, round == 0 ? shift_rel : 0.0,
                        z.Bacc, round, round >= 1 ? Arec : nullptr, round >= 1 ? Brec : nullptr, z.flag,
                        tag, z.W, ld, last ? dst : z.W, ld, last ? nullptr : z.gp[(round + 1) & 1], mode,
                        round == 1 ? dst : nullptr, st));

@@ -25,7 +25,7 @@
 
 namespace refl {
 
-constexpr int LZ_RC = 128;  // rows per block of the projection partials
+constexpr int LZ_RC = 64;   // rows per block of the projection partials
 
 static inline int lz_nblocks(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_lz_proj_partial(const double* __restric
 // C[c + j n] = sum_rc part (fixed order).  The rows c >= n - b of C (the
 // coefficients on the newest block Q_j) are written to, or with `accumulate`
 // added to, Arec (b x b, column-major).  Four lanes per entry: lane q sums
-// the chunks rc = q mod 4 in order (eight loads in flight), and the four
+// the chunks rc = q mod 4 in order (sixteen loads in flight), and the four
 // sums are combined by a fixed butterfly, so every lane holds the same value.
 __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict__ part, int nrc,
                                                         int n, int nb, int NB,
@@ -112,10 +112,19 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
   const int q = (int)(g & 3);
   const int64_t o = g >> 2;
   const bool in = o < (int64_t)n * nb;
-  const int c = in ? (int)(o % n) : 0, j = in ? (int)(o / n) : 0;
+  // Entries run fastest over j, so a wave's loads share cache lines (the
+  // partials are stored [chunk][c][j]).
+  const int c = in ? (int)(o / nb) : 0, j = in ? (int)(o % nb) : 0;
   double s = 0.0;
   if (in) {
     int rc = q;
+    for (; rc + 60 < nrc; rc += 64) {
+      double a[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] = part[((int64_t)(rc + 4 * u) * n + c) * NB + j];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s += a[u];
+    }
     for (; rc + 28 < nrc; rc += 32) {
       double a[8];
 #pragma unroll

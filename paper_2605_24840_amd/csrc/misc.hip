@@ -539,7 +539,16 @@ __global__ __launch_bounds__(256) void k_thin_finish(const double* __restrict__ 
   double s = 0.0;
   if (BLK) {
     const int nrb = gridDim.x;
-    for (int q = 0; q < nchunk; ++q) s += work[thin_block_base<NB>(q, blockIdx.x, nrb) + c * 256 + threadIdx.x];
+    const double* wp = work + c * 256 + threadIdx.x;
+    int q = 0;
+    for (; q + 8 <= nchunk; q += 8) {  // eight loads in flight, summed in order
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = wp[thin_block_base<NB>(q + u, blockIdx.x, nrb)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += a[u];
+    }
+    for (; q < nchunk; ++q) s += wp[thin_block_base<NB>(q, blockIdx.x, nrb)];
   } else {
     for (int q = 0; q < nchunk; ++q) s += work[((int64_t)q * NB + c) * wld + row];
   }

@@ -944,8 +944,10 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
     }
     if (first && tid == 0) st->iters = 0;
   } else {
-    // Partials of the previous apply: apart[(g nb + c)(k + 2) + v], v < k
-    // the entries of C[:, c], then gamma and delta.  A wave takes up to four
+    // Partials of the previous apply: apart[((c (k + 2) + v) ngroups + g],
+    // v < k the entries of C[:, c], then gamma and delta (pair q = c (k + 2)
+    // + v; the groups of a pair are contiguous, so a wave's loads share cache
+    // lines).  A wave takes up to four
     // (c, v) pairs at once, so that their loads are in flight together.
     const int nv = k + 2, npairs = nb * nv;
     const int tc = min(tid, nb - 1);  // values of threads >= nb are not used
@@ -956,7 +958,7 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = wave + u * NW;
-      acc0[u] = ldsel(apart, ((int64_t)lane * nb + q / nv) * nv + q % nv, lane < ngroups && q < npairs);
+      acc0[u] = ldsel(apart, (int64_t)q * ngroups + lane, lane < ngroups && q < npairs);
     }
     // The rows of the update (the block's chunk), V up to KV columns.
     const double* Rin = b.R[(it - 1) & 1];
@@ -989,7 +991,7 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
       const int q = wave + u * NW;
       if (q < npairs) {  // wave-uniform
         double acc = acc0[u];
-        for (int g = lane + 64; g < ngroups; g += 64) acc += apart[((int64_t)g * nb + q / nv) * nv + q % nv];
+        for (int g = lane + 64; g < ngroups; g += 64) acc += apart[(int64_t)q * ngroups + g];
         const double t = wave_sum(acc);
         if (lane == 0) sC[q / nv][q % nv] = t;
       }
@@ -1000,7 +1002,7 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int q = q0 + u * NW;
-          if (q < npairs) acc[u] += apart[((int64_t)g * nb + q / nv) * nv + q % nv];
+          if (q < npairs) acc[u] += apart[(int64_t)q * ngroups + g];
         }
       }
 #pragma unroll
@@ -1128,7 +1130,8 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
     s = 0.0;
   }
   // Partials: V^T (H - theta) r (k values), r.r, r.(H - theta) r at
-  // apart[group][c][0..k+1]; the four waves' sums are added in a fixed order.
+  // apart[(c (k + 2) + v) gridDim.x + group]; the four waves' sums are added
+  // in a fixed order.
   for (int i = 0; i < k; ++i) {
     double vi;
     if (i < KV) {
@@ -1148,8 +1151,9 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
     red[wave][k + 1] = t2;
   }
   __syncthreads();
-  double* mypart = apart + ((int64_t)blockIdx.x * nb + c) * (k + 2);
-  if (tid < k + 2) mypart[tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  if (tid < k + 2)
+    apart[((int64_t)c * (k + 2) + tid) * gridDim.x + blockIdx.x] =
+        (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 template <int W>

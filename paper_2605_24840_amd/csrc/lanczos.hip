@@ -254,6 +254,7 @@ struct LzFactor {
   double red[5];
   double dev;  // ||G - I||_F of the summed Gram matrix, before shift and factorisation
   double inv[32];  // 1 / L[j][j]
+  double col[64];  // the column of multipliers of one Cholesky step
   int bad;
 };
 
@@ -342,28 +343,44 @@ __device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb,
     }
     if (t < nb) f.G[t][t] += sh;
     wave_fence();
-    // Right-looking Cholesky, lower triangle; lane t < nb owns row t.
-    for (int p = 0; p < nb; ++p) {
-      if (t == 0) {
-        double piv = f.G[p][p];
+    // Right-looking Cholesky, lower triangle: lane t < nb keeps row t in
+    // registers; the pivot and the new column reach the other lanes through
+    // LDS (one write and one broadcast read each per pivot).  The steps are
+    // unrolled over the padded width; a step past nb is skipped whole.
+    const int tr_ = t < nb ? t : nb - 1;
+    double row[NBP];
+#pragma unroll
+    for (int j = 0; j < NBP; ++j) row[j] = f.G[tr_][j];
+#pragma unroll
+    for (int p = 0; p < NBP; ++p) {
+      const bool act = p < nb;
+      if (!act) continue;  // uniform: steps past nb are skipped whole
+      if (t == p && act) {
+        double piv = row[p];
         if (!(piv > 0.0) || !isfinite(piv)) {
           piv = 1.0;
           f.bad = 1;
         }
-        f.G[p][p] = sqrt(piv);
+        f.red[1] = sqrt(piv);
       }
       wave_fence();
-      if (t > p && t < nb) {
-        const double l = f.G[t][p] / f.G[p][p];
-        f.G[t][p] = l;
-      }
+      const double dg = f.red[1];
+      const bool below = act && t > p && t < nb;
+      const double l = below ? row[p] / dg : 0.0;
+      if (act && t == p) row[p] = dg;
+      if (below) row[p] = l;
+      f.col[t] = l;
       wave_fence();
-      if (t > p && t < nb) {
-        const double l = f.G[t][p];
-        for (int j = p + 1; j <= t; ++j) f.G[t][j] -= l * f.G[j][p];
-      }
+#pragma unroll
+      for (int j = p + 1; j < NBP; ++j) row[j] = fma(-l, f.col[j], row[j]);
       wave_fence();
     }
+    if (t < nb) {
+#pragma unroll
+      for (int j = 0; j < NBP; ++j)
+        if (j <= t) f.G[t][j] = row[j];
+    }
+    wave_fence();
     if (t < nb) f.inv[t] = 1.0 / f.G[t][t];
   }
   __syncthreads();

@@ -728,6 +728,12 @@ __device__ __forceinline__ double ldsel(const T* __restrict__ p, int64_t i, bool
   const T v = p[ok ? i : 0];
   return ok ? (double)v : 0.0;
 }
+// The same for p[i], p[i + 1] with one 16-byte load (p + i 16-byte aligned
+// when ok).
+__device__ __forceinline__ double2 ld2sel(const double* __restrict__ p, int64_t i, bool ok) {
+  const double2 v = *reinterpret_cast<const double2*>(p + (ok ? i : 0));
+  return ok ? v : make_double2(0.0, 0.0);
+}
 
 // The first eight rows of M of a lane (they do not depend on V), so that a
 // kernel can request them before it sets up the V block in LDS.
@@ -968,22 +974,24 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
     const double* Sin = b.S[it & 1];
     double* Sout = b.S[(it - 1) & 1];
     const bool writer = blockIdx.x == 0;
-    constexpr int PER = (NB * CHUNK + NT - 1) / NT, KV = NB < 8 ? NB : 8;
-    double hr[PER], r[PER], pprev[PER], sprev[PER], z[PER], vv[PER][KV];
+    // A thread takes pairs of rows (j, j + 1), j even, with 16-byte loads
+    // (ldv is even): half the load instructions of one row per thread.
+    constexpr int HC = CHUNK / 2, NP = NB * HC, PERP = (NP + NT - 1) / NT, KV = NB < 8 ? NB : 8;
+    double2 hr[PERP], r[PERP], pprev[PERP], sprev[PERP], z[PERP], vv[PERP][KV];
     const double* Vb = k > 0 ? V : b.HR;  // a valid address for the masked loads
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      const int c = e / CHUNK, j = j0 + e % CHUNK;
-      const bool ok = e < NB * CHUNK && c < nb && j < d;
+    for (int u = 0; u < PERP; ++u) {
+      const int ep = tid + u * NT;
+      const int c = ep / HC, j = j0 + 2 * (ep % HC);
+      const bool ok = ep < NP && c < nb && j < d;
       const int64_t o = ok ? (int64_t)c * ldv + j : 0;
-      hr[u] = ldsel(b.HR, o, ok);
+      hr[u] = ld2sel(b.HR, o, ok);
 #pragma unroll
-      for (int i = 0; i < KV; ++i) vv[u][i] = ldsel(Vb, (int64_t)i * ldv + j, ok && i < k);
-      r[u] = ldsel(Rin, o, ok);
-      pprev[u] = ldsel(Pin, o, ok && it >= 2);
-      sprev[u] = ldsel(Sin, o, ok && it >= 2);
-      z[u] = ldsel(b.Z, o, ok && writer);
+      for (int i = 0; i < KV; ++i) vv[u][i] = ld2sel(Vb, (int64_t)i * ldv + j, ok && i < k);
+      r[u] = ld2sel(Rin, o, ok);
+      pprev[u] = ld2sel(Pin, o, ok && it >= 2);
+      sprev[u] = ld2sel(Sin, o, ok && it >= 2);
+      z[u] = ld2sel(b.Z, o, ok && writer);
     }
     symthin_first<MT, CHUNK, KS>(M, ldm, 0, d, m0);
 #pragma unroll
@@ -1045,33 +1053,36 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
       return;
     }
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (e >= NB * CHUNK) break;
-      const int c = e / CHUNK, jj = e % CHUNK, j = j0 + jj;
-      double rn = 0.0;
-      if (c < nb && j < d) {
-        const int64_t o = (int64_t)c * ldv + j;
-        double w = hr[u];
+    for (int u = 0; u < PERP; ++u) {
+      const int ep = tid + u * NT;
+      if (ep >= NP) break;
+      const int c = ep / HC, jj = 2 * (ep % HC), j = j0 + jj;
 #pragma unroll
-        for (int i = 0; i < KV; ++i)
-          if (i < k) w = fma(-vv[u][i], sC[c][i], w);
-        for (int i = KV; i < k; ++i) w = fma(-V[(int64_t)i * ldv + j], sC[c][i], w);
-        const double al = sal[c];
-        double pn = r[u], sn = w;
-        if (it >= 2) {
-          pn = fma(sbe[c], pprev[u], r[u]);
-          sn = fma(sbe[c], sprev[u], w);
+      for (int h = 0; h < 2; ++h) {
+        double rn = 0.0;
+        if (c < nb && j + h < d) {
+          const int64_t o = (int64_t)c * ldv + j + h;
+          double w = h ? hr[u].y : hr[u].x;
+#pragma unroll
+          for (int i = 0; i < KV; ++i)
+            if (i < k) w = fma(-(h ? vv[u][i].y : vv[u][i].x), sC[c][i], w);
+          for (int i = KV; i < k; ++i) w = fma(-V[(int64_t)i * ldv + j + h], sC[c][i], w);
+          const double al = sal[c], ri = h ? r[u].y : r[u].x;
+          double pn = ri, sn = w;
+          if (it >= 2) {
+            pn = fma(sbe[c], h ? pprev[u].y : pprev[u].x, ri);
+            sn = fma(sbe[c], h ? sprev[u].y : sprev[u].x, w);
+          }
+          rn = fma(-al, sn, ri);
+          if (writer) {
+            Pout[o] = pn;
+            Sout[o] = sn;
+            b.Z[o] = fma(al, pn, h ? z[u].y : z[u].x);
+            Rout[o] = rn;
+          }
         }
-        rn = fma(-al, sn, r[u]);
-        if (writer) {
-          Pout[o] = pn;
-          Sout[o] = sn;
-          b.Z[o] = fma(al, pn, z[u]);
-          Rout[o] = rn;
-        }
+        pv[jj + h][c] = rn;
       }
-      pv[jj][c] = rn;
     }
     if (first && tid == 0) st->iters = it;
   }
@@ -1602,6 +1613,14 @@ hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, i
                         const double* V, int64_t ldv, const CgBufs& bufs, void* state,
                         double* work, double* part, int it, int max_iter, hipStream_t st) {
   CgState* s = reinterpret_cast<CgState*>(state);
+  // The step's set-up loads row pairs with 16-byte loads: the vector blocks
+  // need an even leading dimension and 16-byte aligned columns.
+  if ((ldv & 1) || (reinterpret_cast<uintptr_t>(V) | reinterpret_cast<uintptr_t>(bufs.HR) |
+                    reinterpret_cast<uintptr_t>(bufs.Z) | reinterpret_cast<uintptr_t>(bufs.R[0]) |
+                    reinterpret_cast<uintptr_t>(bufs.R[1]) | reinterpret_cast<uintptr_t>(bufs.P[0]) |
+                    reinterpret_cast<uintptr_t>(bufs.P[1]) | reinterpret_cast<uintptr_t>(bufs.S[0]) |
+                    reinterpret_cast<uintptr_t>(bufs.S[1])) & 15)
+    return hipErrorInvalidValue;
   const int64_t wld = d;
   const int nrb = nblocks(d, 64);
 #define REFL_CG_STEP(MT, MP, NBV)                                                                \

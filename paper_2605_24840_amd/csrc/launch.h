@@ -212,12 +212,20 @@ hipError_t launch_batch_decide(int nprob, const double* res, const double* trace
 struct MixedRule {
   int d, extra, cap, pad;
 };
-// One step of the rule on one iterate: res = ||X_m^2 - I||_F^2, trace =
-// trace X_m (read for m > 0; the record holds trace X_0).  ctl[0] is m
-// (read, then incremented); live and ctl[1] become 0 at the stop, and the
-// record's par then names the buffer of X_m.
-hipError_t launch_mixed_decide(const double* res, const double* trace, const MixedRule* rule,
-                               BatchStep* stp, int* live, int* ctl, int par, hipStream_t st);
+// One step of a single-problem device loop in one launch: scal[SC_RESID2] =
+// sum of pr[0..n) = ||X_m^2 - I||_F^2 and, for m = ctl[0] > 0,
+// scal[SC_TRACE] = sum of pt[0..n) = trace X_m (both in launch_reduce_sum's
+// order; for m = 0 the record holds trace X_0), then one step of the rule:
+// the MIXED rule above (MixedRule) or that of launch_batch_decide with
+// nprob = 1 (BatchRule).  ctl[0] is m (read, then incremented); live[0] and
+// ctl[1] become 0 at the stop, and the record's par then names the buffer
+// of X_m.  pr and pt are distinct buffers of n >= 1 doubles.
+hipError_t launch_reduce_decide(const double* pr, const double* pt, int n, double* scal,
+                                const MixedRule* rule, BatchStep* stp, int* live, int* ctl, int par,
+                                hipStream_t st);
+hipError_t launch_reduce_decide(const double* pr, const double* pt, int n, double* scal,
+                                const BatchRule* rule, BatchStep* stp, int* live, int* ctl, int par,
+                                hipStream_t st);
 // out[slot ? slot[q] : q] = sum of partials[begin[q] .. begin[q + 1]), q < nq,
 // summed in the same order as launch_reduce_sum over that range.
 hipError_t launch_reduce_ranges(const double* partials, const int* begin, const int* slot, int nq,

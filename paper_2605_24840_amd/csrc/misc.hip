@@ -3,6 +3,7 @@
 // 4.3), reductions, output, and the thin products and block-vector updates
 // of the FP64 subspace correction and of block Lanczos.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "launch.h"
@@ -222,17 +223,53 @@ __global__ __launch_bounds__(256) void k_batch_decide(int nprob, const double* _
   }
 }
 
-__global__ void k_mixed_decide(const double* __restrict__ res, const double* __restrict__ trace,
-                               const MixedRule* __restrict__ rule, BatchStep* __restrict__ stp,
-                               int* __restrict__ live, int* __restrict__ ctl, int par) {
-  if (threadIdx.x != 0) return;
+// The reductions and the decision of one step of a single-problem device
+// loop in one launch.  res = sum of pr[0..n) and, from step 1 on, trace =
+// sum of pt[0..n) (the previous update product's trace partials), each in
+// k_reduce_sum's order, go to scal[SC_RESID2] / scal[SC_TRACE]; then the
+// rule: mixed_rule (MixedRule) or batch_rule (BatchRule, the effect of
+// k_batch_decide for one problem).  ctl[0] is the step m (read, then
+// incremented); at the stop live[0] and ctl[1] become 0 and the record's par
+// names the buffer of X_m.  Once live[0] is 0 the partials are stale and only
+// the step counter moves.
+template <typename Rule>
+__global__ __launch_bounds__(256) void k_reduce_decide(const double* __restrict__ pr,
+                                                       const double* __restrict__ pt, int n,
+                                                       double* __restrict__ scal,
+                                                       const Rule* __restrict__ rule,
+                                                       BatchStep* __restrict__ stp,
+                                                       int* __restrict__ live,
+                                                       int* __restrict__ ctl, int par) {
+  __shared__ double red[4];
   const int m = ctl[0];
+  const bool on = live[0] != 0;
+  double r2 = 0.0, tr = 0.0;
+  if (on) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += pr[i];
+    r2 = block_sum_256(a, red);
+    if (m > 0) {
+      double b = 0.0;
+      for (int i = threadIdx.x; i < n; i += 256) b += pt[i];
+      tr = block_sum_256(b, red);
+    }
+  }
+  if (threadIdx.x != 0) return;
   ctl[0] = m + 1;
-  if (!live[0]) return;
+  if (!on) return;
+  scal[SC_RESID2] = r2;
   BatchStep s = stp[0];
-  if (m > 0) s.trace = trace[0];
-  const double r = sqrt(fmax(res[0], 0.0));
-  if (mixed_rule(s, rule[0], r, m, par)) {
+  if (m > 0) {
+    scal[SC_TRACE] = tr;
+    s.trace = tr;
+  }
+  const double r = sqrt(fmax(r2, 0.0));
+  bool stop;
+  if constexpr (std::is_same<Rule, MixedRule>::value)
+    stop = mixed_rule(s, rule[0], r, m, par);
+  else
+    stop = batch_rule(s, rule[0], r, m, par);
+  if (stop) {
     live[0] = 0;
     ctl[1] = 0;
   }
@@ -1318,9 +1355,18 @@ hipError_t launch_batch_decide(int nprob, const double* res, const double* trace
                      ctl, par);
   return hipGetLastError();
 }
-hipError_t launch_mixed_decide(const double* res, const double* trace, const MixedRule* rule,
-                               BatchStep* stp, int* live, int* ctl, int par, hipStream_t st) {
-  hipLaunchKernelGGL(k_mixed_decide, dim3(1), dim3(64), 0, st, res, trace, rule, stp, live, ctl, par);
+hipError_t launch_reduce_decide(const double* pr, const double* pt, int n, double* scal,
+                                const MixedRule* rule, BatchStep* stp, int* live, int* ctl, int par,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_decide<MixedRule>, dim3(1), dim3(256), 0, st, pr, pt, n, scal, rule,
+                     stp, live, ctl, par);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_decide(const double* pr, const double* pt, int n, double* scal,
+                                const BatchRule* rule, BatchStep* stp, int* live, int* ctl, int par,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_decide<BatchRule>, dim3(1), dim3(256), 0, st, pr, pt, n, scal, rule,
+                     stp, live, ctl, par);
   return hipGetLastError();
 }
 hipError_t launch_trace_f64(const double* X, int dp, int d, double* scal, int slot,

@@ -160,6 +160,7 @@ struct Work {
   double* scal;
   double* rowsum;
   double* partials;
+  double* partials_t;  // update products' trace partials (single-problem device loops)
   int2* tiles;
   // bulk (only the ones of the precision are non-null)
   double *X64[2], *N64;
@@ -352,6 +353,7 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind
   w.scal = c.take<double>(SC_COUNT);
   w.tiles = c.take<int2>(w.ntiles);
   w.partials = c.take<double>(w.ntiles);
+  w.partials_t = c.take<double>(w.ntiles);
   w.rowsum = c.take<double>(2 * dp);
   w.X64[0] = w.X64[1] = w.N64 = nullptr;
   w.X32[0] = w.X32[1] = w.N32 = nullptr;
@@ -1151,7 +1153,7 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   if (p.precision == REFL_PREC_MIXED && !fixed) {
     // MIXED bulk: the stopping rule (index certificate, then the words'
     // floor; MixedRule in launch.h) runs on the device after each residual
-    // product (k_mixed_decide), so the host enqueues steps four at a time
+    // product (k_reduce_decide), so the host enqueues steps four at a time
     // and keeps one group queued beyond the one whose step record it reads;
     // the products of steps past the stop read the device flag and return at
     // once.  X_m lives in buffer m % 3.  Rule, record, flag and step counter
@@ -1197,16 +1199,14 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
                                      w.dk, w.tiles, w.ntiles, w.partials, st, d_live)) != hipSuccess)
         return e;
       if ((e = ev_stop()) != hipSuccess) return e;
-      if ((e = launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, st)) != hipSuccess) return e;
-      if ((e = launch_mixed_decide(w.scal + SC_RESID2, w.scal + SC_TRACE, d_ru, d_sq, d_live, d_ctl,
-                                   m % 3, st)) != hipSuccess)
+      if ((e = launch_reduce_decide(w.partials, w.partials_t, w.ntiles, w.scal, d_ru, d_sq, d_live,
+                                    d_ctl, m % 3, st)) != hipSuccess)
         return e;
       if ((e = ev_start()) != hipSuccess) return e;
       if ((e = launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, Xm, w.Nw, Xm, Xn, w.dp, w.ps, (int)d, w.dk,
-                                     w.tiles, w.ntiles, w.partials, st, d_live)) != hipSuccess)
+                                     w.tiles, w.ntiles, w.partials_t, st, d_live)) != hipSuccess)
         return e;
-      if ((e = ev_stop()) != hipSuccess) return e;
-      return launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, st);
+      return ev_stop();
     };
     int enq = 0;  // steps enqueued
     int group = STEPS_AHEAD;
@@ -1327,12 +1327,12 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
                    ? launch_sym_gemm_f64(w.ts, mode, w.X64[c], w.X64[c], nullptr, w.N64, w.dp, (int)d,
                                          w.dp, w.tiles, w.ntiles, w.partials, ss, d_live)
                    : launch_sym_gemm_f64(w.ts, mode, w.X64[c], w.N64, w.X64[c], w.X64[c ^ 1], w.dp,
-                                         (int)d, w.dp, w.tiles, w.ntiles, w.partials, ss, d_live);
+                                         (int)d, w.dp, w.tiles, w.ntiles, w.partials_t, ss, d_live);
       return mode == GEMM_RESIDUAL
                  ? launch_sym_gemm_f32(w.ts, mode, w.X32[c], w.X32[c], nullptr, w.N32, w.dp, (int)d,
                                        w.dp, w.tiles, w.ntiles, w.partials, ss, d_live)
                  : launch_sym_gemm_f32(w.ts, mode, w.X32[c], w.N32, w.X32[c], w.X32[c ^ 1], w.dp,
-                                       (int)d, w.dp, w.tiles, w.ntiles, w.partials, ss, d_live);
+                                       (int)d, w.dp, w.tiles, w.ntiles, w.partials_t, ss, d_live);
     };
     // One step on stream ss (timing events on the handle's stream).
     auto enqueue_step = [&](int c, hipStream_t ss) -> hipError_t {
@@ -1341,14 +1341,13 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       if (ev && (e = ev_start()) != hipSuccess) return e;
       if ((e = product(GEMM_RESIDUAL, c, ss)) != hipSuccess) return e;
       if (ev && (e = ev_stop()) != hipSuccess) return e;
-      if ((e = launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_RESID2, ss)) != hipSuccess) return e;
-      if ((e = launch_batch_decide(1, w.scal + SC_RESID2, w.scal + SC_TRACE, d_ru, d_sq, d_live, d_ctl, c,
-                                   ss)) != hipSuccess)
+      if ((e = launch_reduce_decide(w.partials, w.partials_t, w.ntiles, w.scal, d_ru, d_sq, d_live,
+                                    d_ctl, c, ss)) != hipSuccess)
         return e;
       if (ev && (e = ev_start()) != hipSuccess) return e;
       if ((e = product(GEMM_UPDATE, c, ss)) != hipSuccess) return e;
       if (ev && (e = ev_stop()) != hipSuccess) return e;
-      return launch_reduce_sum(w.partials, w.ntiles, w.scal, SC_TRACE, ss);
+      return hipSuccess;
     };
     // (Capturing a group of steps as a HIP graph was measured as well: no
     // faster at d = 64 .. 2048, the step time being the device's, and each

@@ -5,21 +5,27 @@
 //   two passes of block classical Gram-Schmidt against all of V
 //     k_lz_proj_partial / k_lz_proj_finish   C = V^T W   (n x nb)
 //     k_lz_apply_rows                        W <- W - V C, row slabs
-//   then three rounds of Cholesky QR, the first one shifted (shifted
+//   and three rounds of Cholesky QR, the first one shifted (shifted
 //   CholQR3 of Fukaya, Kannan, Nakatsukasa, Zhang and Yamamoto, 2020), on
-//   the partial Gram matrices of row slabs (from the second projection
-//   pass, or k_lz_apply_rows with no basis for the start block):
-//     k_lz_cholqr      every block sums the slab Grams and factors
-//                      G = L L^T itself (the same sum in the same order, so
-//                      the same R = L^T), then W <- W R^{-1} on its slab and
-//                      the slab Gram of the result for the next round;
-//                      block 0 also records B <- R B and the flags
+//   the partial Gram matrices of row slabs:
+//     round 0          inside the second pass: its reduction launch also
+//                      sums the first pass's slab Grams, and its row update
+//                      factors that sum (+ shift) and applies R^{-1}
+//                      (k_lz_apply_rows<NB, true>; for the start block a
+//                      stand-alone k_lz_cholqr round)
+//     k_lz_cholqr      rounds 1 and 2: every block sums the slab Grams and
+//                      factors G = L L^T itself (the same sum in the same
+//                      order, so the same R = L^T), then W <- W R^{-1} on
+//                      its slab and the slab Gram of the result for the next
+//                      round; block 0 also records B <- R B and the flags
 //   so that W_in = Q_{j+1} B_j with B_j upper triangular.
 //
 // The diagonal block A_j = Q_j^T H Q_j is the last block of the two
 // projections, recorded by k_lz_proj_finish.  Every reduction runs in a
 // fixed order (per-block partials summed by the next kernel), so the run is
 // deterministic.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -103,11 +109,44 @@ __global__ __launch_bounds__(256) void k_lz_proj_partial(const double* __restric
 // added to, Arec (b x b, column-major).  Four lanes per entry: lane q sums
 // the chunks rc = q mod 4 in order (sixteen loads in flight), and the four
 // sums are combined by a fixed butterfly, so every lane holds the same value.
+//
+// Blocks from cblocks on (when gsrc != null) sum instead the gslab slab
+// Gram partials gsrc (NB x NB each, entry i + j NB) into gdst (same
+// layout): sixteen lanes per entry, lane q summing the slabs q mod 16 in
+// order (one round of sixteen loads for 256 slabs), then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict__ part, int nrc,
                                                         int n, int nb, int NB,
                                                         double* __restrict__ C,
                                                         double* __restrict__ Arec, int b,
-                                                        int accumulate) {
+                                                        int accumulate, int cblocks,
+                                                        const double* __restrict__ gsrc,
+                                                        int gslab, double* __restrict__ gdst) {
+  if ((int)blockIdx.x >= cblocks) {
+    const int g2 = ((int)blockIdx.x - cblocks) * 256 + (int)threadIdx.x;
+    const int q = g2 & 15, o = g2 >> 4;
+    const bool in = o < nb * nb;
+    const int i = in ? o % nb : 0, j = in ? o / nb : 0;
+    const double* p = gsrc + i + (int64_t)j * NB;
+    const int64_t st = (int64_t)NB * NB;
+    double s = 0.0;
+    if (in) {
+      int sl = q;
+      for (; sl + 240 < gslab; sl += 256) {
+        double a[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] = p[(int64_t)(sl + 16 * u) * st];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += a[u];
+      }
+      for (; sl < gslab; sl += 16) s += p[(int64_t)sl * st];
+    }
+    s += __shfl_xor(s, 1, WAVE);
+    s += __shfl_xor(s, 2, WAVE);
+    s += __shfl_xor(s, 4, WAVE);
+    s += __shfl_xor(s, 8, WAVE);
+    if (in && q == 0) gdst[i + (int64_t)j * NB] = s;
+    return;
+  }
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int q = (int)(g & 3);
   const int64_t o = g >> 2;
@@ -144,6 +183,18 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
   }
 }
 
+// LDS state of a Cholesky factorisation by lz_chol (below).
+struct LzChol {
+  double G[32][33];
+  double red[2];
+  double dev;
+  double inv[32];
+  double col[64];
+  int bad;
+};
+template <int NBP, typename F>
+__device__ void lz_chol(int nb, double shift_rel, F& f);
+
 // W <- W - V C on 16-row slabs (V: d x n basis, ld ldv; C: n x nb,
 // column-major, ld n).  A block is 16 rows x AG column groups (AG = 32, or
 // 16 for blocks wider than 16 columns): a lane owns one row and takes the
@@ -156,22 +207,49 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
 // partials.  Short slabs give many blocks: one compute unit streams its
 // share of V (16 rows of n columns) quickly, where 64-row slabs left 64
 // blocks of 64 n 8 bytes each on a 256-unit device.
+//
+// With QR the block also runs the first, shifted round of Cholesky QR on
+// the result x: it factors gfac + sigma I = L L^T (gfac: a summed nb x nb
+// Gram matrix, entry i + j NB; sigma = shift_rel trace gfac) while its loads
+// are in flight, and dst and the Gram partials then hold y = x R^{-1}
+// (R = L^T).  Block 0 records Bacc = R and, for a replaced pivot, bit 1 of
+// flag[0] (flag[1] = tag if unset).  The second Gram-Schmidt pass passes
+// the Gram matrix of its input (the first pass's output, x + V C): in exact
+// arithmetic that is x^T x + C^T C with C = V^T (x + V C) of rounding size,
+// a positive semidefinite perturbation that the shift already dominates,
+// so the round keeps the conditioning bound of shifted Cholesky QR and one
+// Gram reduction (a kernel boundary) per step is saved.
 constexpr int LZ_AR = LZ_GRAM_ROWS;
 constexpr int LZ_ACH = 256;  // columns of C per LDS chunk
 template <int NB>
 constexpr int lz_ag() { return NB <= 16 ? 32 : 16; }
-template <int NB>
+template <int NB, bool QR>
 __global__ __launch_bounds__(LZ_AR * lz_ag<NB>()) void k_lz_apply_rows(
     const double* __restrict__ V, int64_t ldv, int n, const double* __restrict__ C, int nb, int d,
-    const double* W, int64_t ldw, double* dst, int64_t ldd, double* __restrict__ gpart) {
+    const double* W, int64_t ldw, double* dst, int64_t ldd, double* __restrict__ gpart,
+    const double* __restrict__ gfac, double shift_rel, double* __restrict__ Bacc,
+    int* __restrict__ flag, int tag) {
   constexpr int AG = lz_ag<NB>(), NT = LZ_AR * AG;
   __shared__ double sC[LZ_ACH][NB];
   __shared__ double sP[AG][LZ_AR][NB + 1];
   __shared__ double sX[LZ_AR][NB + 1];
+  __shared__ typename std::conditional<QR, LzChol, char>::type fc;
   const int t = threadIdx.x, row = t % LZ_AR, g = t / LZ_AR;
   const int r0 = blockIdx.x * LZ_AR, r = r0 + row;
-  // The slab of W (LZ_AR x NB), requested first; masked loads without
-  // branches (a load in a branch is waited for where the branch ends).
+  // With QR, the summed Gram matrix is requested first (it is needed
+  // first), then the slab of W (LZ_AR x NB) and the first chunk of C; masked
+  // loads without branches (a load in a branch is waited for where the
+  // branch ends).
+  constexpr int PERG = QR ? (NB * NB + NT - 1) / NT : 1;
+  double gv[PERG];
+  if constexpr (QR) {
+#pragma unroll
+    for (int u = 0; u < PERG; ++u) {
+      const int e = t + u * NT;
+      const double v = gfac[e < NB * NB ? e : 0];
+      gv[u] = (e < NB * NB && e % NB < nb && e / NB < nb) ? v : 0.0;
+    }
+  }
   constexpr int PERW = (LZ_AR * NB + NT - 1) / NT;
   double wv[PERW];
 #pragma unroll
@@ -180,13 +258,13 @@ __global__ __launch_bounds__(LZ_AR * lz_ag<NB>()) void k_lz_apply_rows(
     const double v = W[(int64_t)min(q, nb - 1) * ldw + min(rr, d - 1)];
     wv[u] = (o < LZ_AR * NB && rr < d && q < nb) ? v : 0.0;
   }
-  double acc[NB];
-#pragma unroll
-  for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+  // Chunk cb of C (256 rows of nb columns) into cv; up to 16 columns the
+  // next chunk is requested while the current one is used (wider blocks
+  // have no registers to spare for it).
+  constexpr bool PREFETCH = NB <= 16;
   constexpr int PERC = (LZ_ACH * NB + NT - 1) / NT;
-  for (int cb = 0; cb < n; cb += LZ_ACH) {
+  auto load_chunk = [&](int cb, double (&cv)[PERC]) {
     const int cn = min(LZ_ACH, n - cb);
-    double cv[PERC];
 #pragma unroll
     for (int u = 0; u < PERC; ++u) {
       const int e = t + u * NT, cl = e / NB, q = e % NB;
@@ -194,13 +272,49 @@ __global__ __launch_bounds__(LZ_AR * lz_ag<NB>()) void k_lz_apply_rows(
       const double v = C[ok ? (cb + cl) + (int64_t)q * n : 0];
       cv[u] = ok ? v : 0.0;
     }
-    __syncthreads();
+  };
+  auto store_chunk = [&](const double (&cv)[PERC]) {
 #pragma unroll
     for (int u = 0; u < PERC; ++u) {
       const int e = t + u * NT;
       if (e < LZ_ACH * NB) sC[e / NB][e % NB] = cv[u];
     }
-    __syncthreads();
+  };
+  double cvp[PREFETCH ? PERC : 1];
+  if constexpr (PREFETCH) {
+    if (n > 0) load_chunk(0, cvp);
+  }
+  if constexpr (QR) {
+    // The factorisation needs none of the block's rows: wave 0 runs it
+    // while the loads of W and C are in flight (the barrier orders LDS
+    // only; the chunk loop's first block barrier orders its result for the
+    // other waves).
+#pragma unroll
+    for (int u = 0; u < PERG; ++u) {
+      const int e = t + u * NT;
+      if (e < NB * NB) fc.G[e % NB][e / NB] = gv[u];
+    }
+    if (t == 0) fc.bad = 0;
+    lds_barrier();
+    lz_chol<NB>(nb, shift_rel, fc);
+  }
+  double acc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+  for (int cb = 0; cb < n; cb += LZ_ACH) {
+    const int cn = min(LZ_ACH, n - cb);
+    if constexpr (PREFETCH) {
+      __syncthreads();
+      store_chunk(cvp);
+      __syncthreads();
+      if (cb + LZ_ACH < n) load_chunk(cb + LZ_ACH, cvp);
+    } else {
+      double cv[PERC];
+      load_chunk(cb, cv);
+      __syncthreads();
+      store_chunk(cv);
+      __syncthreads();
+    }
     if (r < d) {
       const double* v = V + (int64_t)cb * ldv + r;
       int cl = g;
@@ -232,7 +346,44 @@ __global__ __launch_bounds__(LZ_AR * lz_ag<NB>()) void k_lz_apply_rows(
       for (int gg = 0; gg < AG; ++gg) sum += sP[gg][rw][q];
       const double x = wv[u] - sum;
       sX[rw][q] = x;
-      if (dst && rr < d && q < nb) dst[(int64_t)q * ldd + rr] = x;
+      if (!QR && dst && rr < d && q < nb) dst[(int64_t)q * ldd + rr] = x;
+    }
+  }
+  if constexpr (QR) {
+    // y R = x, one row per lane of the first LZ_AR lanes (R[i][j] = L[j][i]).
+    __syncthreads();
+    if (t < LZ_AR) {
+      double y[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) y[j] = sX[t][j];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+          double s = y[j];
+#pragma unroll
+          for (int i = 0; i < j; ++i) s = fma(-y[i], fc.G[j][i], s);
+          y[j] = s * fc.inv[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) sX[t][j] = y[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PERW; ++u) {
+      const int o = t + u * NT;
+      const int rw = o % LZ_AR, q = o / LZ_AR, rr = r0 + rw;
+      if (o < LZ_AR * NB && rr < d && q < nb) dst[(int64_t)q * ldd + rr] = sX[rw][q];
+    }
+    if (blockIdx.x == 0) {
+      for (int e = t; e < nb * nb; e += NT) {
+        const int i = e % nb, j = e / nb;
+        Bacc[e] = i <= j ? fc.G[j][i] : 0.0;
+      }
+      if (t == 0 && fc.bad) {
+        flag[0] |= 1;
+        if (flag[1] == 0) flag[1] = tag;
+      }
     }
   }
   if (!gpart) return;
@@ -312,11 +463,19 @@ __device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb,
   }
   if (t == 0) f.bad = 0;
   __syncthreads();
-  // The rest is the work of wave 0 alone, its steps ordered by wavefront
-  // fences (LDS accesses of one wave complete in order) instead of block
-  // barriers: symmetrise, trace and ||G - I||_F (lane sums, then a fixed
-  // butterfly), the shift, the Cholesky factorisation and the reciprocals
-  // of its diagonal.
+  lz_chol<NBP>(nb, shift_rel, f);
+  __syncthreads();
+}
+
+// The work of wave 0 alone on f.G (nb x nb, already summed), its steps
+// ordered by wavefront fences (LDS accesses of one wave complete in order)
+// instead of block barriers: symmetrise, trace and ||G - I||_F (lane sums,
+// then a fixed butterfly), the shift, the Cholesky factorisation and the
+// reciprocals of its diagonal.  f.bad must be 0 on entry.  The caller
+// orders the result for the other waves with a block barrier.
+template <int NBP, typename F>
+__device__ void lz_chol(int nb, double shift_rel, F& f) {
+  const int t = threadIdx.x;
   if (t < 64) {
     for (int e = t; e < nb * nb; e += 64) {
       const int i = e % nb, j = e / nb;
@@ -383,7 +542,6 @@ __device__ void lz_factor(const double* __restrict__ gpart, int nblk, int nb,
     wave_fence();
     if (t < nb) f.inv[t] = 1.0 / f.G[t][t];
   }
-  __syncthreads();
 }
 
 // Block 0 of a round.  Bacc = R (round 0) or R Bacc.  bit 1 of flag[0] for
@@ -537,13 +695,35 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
                       double* C, double* Arec, int b, int accumulate, double* ppart,
                       double* gpart, hipStream_t st) {
   const int nrc = lz_nblocks(d, LZ_RC);
+  const int cblocks = lz_nblocks((int64_t)n * nb * 4, 256);
   LZ_DISPATCH(nb, {
     hipLaunchKernelGGL((k_lz_proj_partial<NB>), dim3(lz_nblocks(n, 64), nrc), dim3(256), 0, st, V,
                        ldv, n, W, ldw, nb, d, ppart);
-    hipLaunchKernelGGL(k_lz_proj_finish, dim3(lz_nblocks((int64_t)n * nb * 4, 256)), dim3(256), 0, st,
-                       ppart, nrc, n, nb, NB, C, Arec, b, accumulate);
-    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n,
-                       C, nb, d, W, ldw, W, ldw, gpart);
+    hipLaunchKernelGGL(k_lz_proj_finish, dim3(cblocks), dim3(256), 0, st, ppart, nrc, n, nb, NB, C,
+                       Arec, b, accumulate, cblocks, nullptr, 0, nullptr);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB, false>), dim3(lz_nblocks(d, LZ_AR)),
+                       dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n, C, nb, d, W, ldw, W, ldw, gpart,
+                       nullptr, 0.0, nullptr, nullptr, 0);
+  })
+  return hipGetLastError();
+}
+
+hipError_t lz_project_qr(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
+                         double* C, double* Arec, int b, int accumulate, double* ppart,
+                         const double* gin, double* gsum, double shift_rel, double* Bacc, int* flag,
+                         int tag, double* gout, hipStream_t st) {
+  if (n < 1 || !gin || !gsum || !gout || gin == gout) return hipErrorInvalidValue;
+  const int nrc = lz_nblocks(d, LZ_RC);
+  const int cblocks = lz_nblocks((int64_t)n * nb * 4, 256);
+  const int gblocks = lz_nblocks((int64_t)nb * nb * 16, 256);
+  LZ_DISPATCH(nb, {
+    hipLaunchKernelGGL((k_lz_proj_partial<NB>), dim3(lz_nblocks(n, 64), nrc), dim3(256), 0, st, V,
+                       ldv, n, W, ldw, nb, d, ppart);
+    hipLaunchKernelGGL(k_lz_proj_finish, dim3(cblocks + gblocks), dim3(256), 0, st, ppart, nrc, n,
+                       nb, NB, C, Arec, b, accumulate, cblocks, gin, lz_nblocks(d, LZ_AR), gsum);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB, true>), dim3(lz_nblocks(d, LZ_AR)),
+                       dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n, C, nb, d, W, ldw, W, ldw, gout,
+                       gsum, shift_rel, Bacc, flag, tag);
   })
   return hipGetLastError();
 }
@@ -551,16 +731,18 @@ hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ld
 hipError_t lz_combine(const double* V, int64_t ldv, int n, const double* Cneg, int nb, int d,
                       const double* Wzero, double* dst, int64_t ldd, hipStream_t st) {
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n,
-                       Cneg, nb, d, Wzero, ldd, dst, ldd, nullptr);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB, false>), dim3(lz_nblocks(d, LZ_AR)),
+                       dim3(LZ_AR * lz_ag<NB>()), 0, st, V, ldv, n, Cneg, nb, d, Wzero, ldd, dst, ldd,
+                       nullptr, nullptr, 0.0, nullptr, nullptr, 0);
   })
   return hipGetLastError();
 }
 
 hipError_t lz_gram(const double* W, int64_t ldw, int nb, int d, double* gpart, hipStream_t st) {
   LZ_DISPATCH(nb, {
-    hipLaunchKernelGGL((k_lz_apply_rows<NB>), dim3(lz_nblocks(d, LZ_AR)), dim3(LZ_AR * lz_ag<NB>()), 0, st, nullptr,
-                       ldw, 0, nullptr, nb, d, W, ldw, nullptr, ldw, gpart);
+    hipLaunchKernelGGL((k_lz_apply_rows<NB, false>), dim3(lz_nblocks(d, LZ_AR)),
+                       dim3(LZ_AR * lz_ag<NB>()), 0, st, nullptr, ldw, 0, nullptr, nb, d, W, ldw,
+                       nullptr, ldw, gpart, nullptr, 0.0, nullptr, nullptr, 0);
   })
   return hipGetLastError();
 }

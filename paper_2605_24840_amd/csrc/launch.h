@@ -331,6 +331,18 @@ size_t lz_gram_part_doubles(int d, int nb);
 hipError_t lz_project(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
                       double* C, double* Arec, int b, int accumulate, double* ppart,
                       double* gpart, hipStream_t st);
+// The second pass of lz_project (n >= 1) with the first, shifted Cholesky
+// QR round fused into its update: the Gram matrix factored is the sum of
+// gin (LZ_GRAM_ROWS-row slab partials of this pass's input W, as the first
+// pass writes them), summed into gsum (lz_nb_pad(nb)^2 doubles) by the
+// projection's reduction launch; then W <- (W - V C) R^{-1} with
+// R^T R = that sum + shift_rel * trace I, gout = the Gram partials of the
+// new W (LZ_GRAM_ROWS-row slabs, for the next lz_cholqr round), Bacc = R,
+// and bit 1 of flag[0] (flag[1] = tag if unset) for a replaced pivot.
+hipError_t lz_project_qr(const double* V, int64_t ldv, int n, double* W, int64_t ldw, int nb, int d,
+                         double* C, double* Arec, int b, int accumulate, double* ppart,
+                         const double* gin, double* gsum, double shift_rel, double* Bacc, int* flag,
+                         int tag, double* gout, hipStream_t st);
 // dst = V Y for the d x n basis V and Y = -Cneg (n x nb, column-major, ld
 // n), computed as Wzero - V Cneg with Wzero an all-zero d x nb block of
 // leading dimension ldd (the projection kernels' update).

@@ -748,14 +748,6 @@ struct ThinRed {
   double v[KS > 1 ? (KS - 1) * NB * 256 : 1];
 };
 
-// A barrier that orders only LDS: global loads in flight stay in flight
-// (__syncthreads waits for every outstanding memory access of the wave).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // p[i] if ok, else 0, loaded without a branch (the index falls back to 0,
 // which must be valid).  A load inside a branch is waited for where the
 // branch ends, so a run of conditional loads made as many round trips to

@@ -148,6 +148,7 @@ struct LzWork {
   double *V = nullptr, *W = nullptr, *C = nullptr;
   double *ppart = nullptr, *gp[2] = {nullptr, nullptr};  // Gram partials, by round parity
   double *Bacc = nullptr, *TA = nullptr, *TB = nullptr;
+  double* gsum = nullptr;  // summed Gram matrix of the first Cholesky QR round of a step
   int* flag = nullptr;
 };
 
@@ -723,6 +724,7 @@ void carve_lanczos(Carve& c, LzWork& z, int64_t d, int dp, int k, int steps) {
   z.Bacc = c.take<double>((size_t)z.b * z.b);
   z.TA = c.take<double>((size_t)z.J * z.b * z.b);
   z.TB = c.take<double>((size_t)z.J * z.b * z.b);
+  z.gsum = c.take<double>((size_t)lz_nb_pad(z.b) * lz_nb_pad(z.b));
   z.flag = c.take<int>(4);
 }
 
@@ -747,23 +749,27 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
   const double shift_rel = 11.0 * ((double)d * b + (double)b * (b + 1)) * 2.220446049250313e-16;
   HIPCHK(hipMemsetAsync(z.flag, 0, 4 * sizeof(int), st));
   // Q_1: the start block, orthonormalised by shifted CholQR3.
-  // Rounds of CholQR3 on z.W, whose Gram partials are in gp[0]; the last
-  // round writes Q to dst.  The second round finishes the QR itself when its
-  // Gram matrix is already close to I, and the third then does nothing.
-  auto cholqr3_rounds = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
-    for (int round = 0; round < 3; ++round) {
+  // Rounds first..2 of CholQR3 on z.W, whose Gram partials (LZ_GRAM_ROWS-row
+  // slabs) are in gp[0]; the last round writes Q to dst.  The second round
+  // finishes the QR itself when its Gram matrix is already close to I, and
+  // the third then does nothing.  A Lanczos step runs round 0 inside its
+  // second projection pass (lz_project_qr) and starts here at round 1.
+  auto cholqr3_rounds = [&](int first, double* dst, double* Arec, double* Brec,
+                            int tag) -> refl_status_t {
+    for (int round = first; round < 3; ++round) {
       const bool last = round == 2;
       const int mode = round == 0 ? LZ_QR_PLAIN : round == 1 ? LZ_QR_MAYBE_LAST : LZ_QR_SKIPPABLE;
-      HIPCHK(lz_cholqr(z.gp[round & 1], round == 0 ? LZ_GRAM_ROWS : 256, (int)d, b, round == 0 ? shift_rel : 0.0,
+      double* gin = z.gp[(round - first) & 1];
+      double* gout = last ? nullptr : z.gp[(round - first + 1) & 1];
+      HIPCHK(lz_cholqr(gin, round == first ? LZ_GRAM_ROWS : 256, (int)d, b, round == 0 ? shift_rel : 0.0,
                        z.Bacc, round, round >= 1 ? Arec : nullptr, round >= 1 ? Brec : nullptr, z.flag,
-                       tag, z.W, ld, last ? dst : z.W, ld, last ? nullptr : z.gp[(round + 1) & 1], mode,
-                       round == 1 ? dst : nullptr, st));
+                       tag, z.W, ld, last ? dst : z.W, ld, gout, mode, round == 1 ? dst : nullptr, st));
     }
     return REFL_OK;
   };
   auto cholqr3 = [&](double* dst, double* Arec, double* Brec, int tag) -> refl_status_t {
     HIPCHK(lz_gram(z.W, ld, b, (int)d, z.gp[0], st));
-    return cholqr3_rounds(dst, Arec, Brec, tag);
+    return cholqr3_rounds(0, dst, Arec, Brec, tag);
   };
   if (start)
     HIPCHK(hipMemcpy2DAsync(z.W, sizeof(double) * ld, start, sizeof(double) * lds,
@@ -899,13 +905,18 @@ refl_status_t lanczos_run(refl_handle_t h, const double* Hf, int dp, int64_t d, 
     double* Aj = z.TA + (size_t)(j - 1) * blk;
     double* Bj = z.TB + (size_t)(j - 1) * blk;
     HIPCHK(symthin_f64(Hf, ld, (int)d, Qj, ld, b, z.W, ld, thin, st));
-    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, nullptr, st));
-    HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.gp[0], st));
     if ((int64_t)n >= d) {
+      HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, nullptr, st));
+      HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, nullptr, st));
       HIPCHK(hipMemsetAsync(Bj, 0, sizeof(double) * blk, st));  // the basis spans R^d
     } else {
-      // The Gram partials of W are already in gp[0]: rounds of CholQR3.
-      refl_status_t rq = cholqr3_rounds(z.V + (int64_t)n * ld, Aj, Bj, j);
+      // The first pass leaves the Gram partials of its output in gp[1]; the
+      // second runs CholQR3's round 0 on them and leaves those of its
+      // output in gp[0] for rounds 1 and 2.
+      HIPCHK(lz_project(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 0, z.ppart, z.gp[1], st));
+      HIPCHK(lz_project_qr(z.V, ld, n, z.W, ld, b, (int)d, z.C, Aj, b, 1, z.ppart, z.gp[1], z.gsum,
+                           shift_rel, z.Bacc, z.flag, j, z.gp[0], st));
+      refl_status_t rq = cholqr3_rounds(1, z.V + (int64_t)n * ld, Aj, Bj, j);
       if (rq != REFL_OK) return rq;
     }
     // A warm start may converge within a few steps: those are all tested.

@@ -62,14 +62,6 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-// A barrier that orders only LDS: global loads in flight stay in flight
-// (__syncthreads waits for every outstanding memory access of the wave).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // Sum over a 256-thread block in a fixed order (deterministic).
 __device__ __forceinline__ double block_sum_256(double v, double* red /* >= 4 */) {
   v = wave_sum(v);

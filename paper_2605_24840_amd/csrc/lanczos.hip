@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "sync.h"
 #include "launch.h"
 
 namespace refl {

@@ -6,6 +6,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "sync.h"
 #include "launch.h"
 #include "rule.h"
 

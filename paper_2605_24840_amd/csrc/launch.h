@@ -297,13 +297,16 @@ struct CgHost {
 };
 // d x nb blocks (ld = ldv) of one solve: r, p and s alternate between two
 // buffers by iteration parity; R[0] holds r_0 and Z = 0 on entry; HR is
-// (H - theta) r.
+// (H - theta) r.  The pipelined solve keeps r in R[0], w = A r in HR, p in
+// P[0], the recurrence of A p in P[1], s in S[0], and U = M V (d x k) in U;
+// R[1] and S[1] are unused there.
 struct CgBufs {
   double* R[2];
   double* P[2];
   double* S[2];
   double* HR;
   double* Z;
+  double* U;
 };
 size_t cg_state_bytes();
 size_t cg_part_doubles(int d);
@@ -314,6 +317,14 @@ size_t cg_part_doubles(int d);
 hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb,
                         const double* V, int64_t ldv, const CgBufs& bufs, void* state,
                         double* work, double* part, int it, int max_iter, hipStream_t st);
+// The same solve by the pipelined recurrences (misc.hip): the pass over M
+// of each launch pair multiplies a block known at launch, every reduction
+// of an iteration going to the update launch.  k (<= 32) is the number of
+// columns of V (k <= nb); iteration 0 also forms U = M V into bufs.U.  Iteration
+// counts and the state are as for cg_iteration.
+hipError_t cg_pipe_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb, int k,
+                             const double* V, int64_t ldv, const CgBufs& bufs, void* state,
+                             double* work, double* part, int it, int max_iter, hipStream_t st);
 
 // ---- block Lanczos (see lanczos.hip) ----
 // Rows per slab of the Gram partials that the projection writes (the first

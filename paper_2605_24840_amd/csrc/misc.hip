@@ -1197,6 +1197,304 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
         (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
+// ------------------------------------------------------- pipelined block CG
+// The same projected systems A_c z_c = b_c by the pipelined recurrences of
+// Ghysels and Vanroose (2014), which carry w = A r and q = A w as vectors
+// so that the operator application of an iteration needs no reduction of
+// that iteration:
+//   gamma_i = r_i.r_i, delta_i = w_i.r_i, q_i = A w_i,
+//   beta_i, alpha_i as in the Chronopoulos-Gear form above,
+//   zz_i = q_i + beta_i zz_{i-1}, s_i = w_i + beta_i s_{i-1},
+//   p_i = r_i + beta_i p_{i-1},
+//   z_{i+1} = z_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i,
+//   w_{i+1} = w_i - alpha_i zz_i.
+// The projection of (M - theta) w onto the complement of V needs
+// V^T (M - theta) w = U^T w - theta V^T w with U = M V, formed once per
+// solve (M is symmetric).  So the pass over M of launch `it` multiplies a
+// block known when the launch starts (r_0 for it = 0, else w), and every
+// reduction of an iteration (U^T w, V^T w, gamma, delta) is a per-group
+// partial that the update launch writes for the next update launch:
+//   k_cg_pass    chunk partials of M r_0 (it = 0) or M w (no set-up);
+//   k_cg_update  (M - theta) x = chunk sums - theta x for its rows; sums,
+//                in a fixed order, the partials the previous update (or
+//                k_cg_init) wrote; it = 0 forms w_0 = A r_0, it >= 1 tests
+//                r_{it-1} (all columns) and applies update it - 1; then
+//                writes the partials of the new rows.
+// Each row belongs to one update block, so the vectors are updated in
+// place.  The partials alternate between two buffers by parity:
+//   part[par][((c NV + v) nrg + g)],  NV = 2k + 2, nrg = ceil(d / 64),
+// v < k: U^T x, k <= v < 2k: V^T x, then gamma and delta (x = w, or r_0).
+// Pipelining trades some attainable accuracy for the shorter dependency
+// chain, so it serves the correction's loose inner tolerance; the
+// gradient's tight solve keeps the form above.
+
+// Partials of one column over a block's 64 rows (lane sub == 0 of each
+// group of four holds the row): U^T x, V^T x, g0 and g1 (the gamma and
+// delta terms of the row), into part at group blockIdx.x.  The row values
+// go through LDS (sp[v][row]) and thread v sums its 64 rows in order: a
+// wave reduction per value (a chain of cross-lane permutes) cost several
+// times more for the twelve values of five columns.
+template <int KV>
+__device__ __forceinline__ void cg_write_parts(int k, int c, int nrg, double x, const double (&ur)[KV],
+                                               const double (&vr)[KV], const double* __restrict__ U,
+                                               const double* __restrict__ V, int64_t ldv, int row,
+                                               bool owner, double g0, double g1,
+                                               double* __restrict__ part, double (*sp)[65]) {
+  const int tid = threadIdx.x, rl = tid >> 2;
+  const int nv = 2 * k + 2;
+  if ((tid & 3) == 0) {
+    for (int i = 0; i < k; ++i) {
+      double ui, vi;
+      if (i < KV) {
+        ui = ur[0];
+        vi = vr[0];
+#pragma unroll
+        for (int u = 1; u < KV; ++u) {
+          ui = i == u ? ur[u] : ui;
+          vi = i == u ? vr[u] : vi;
+        }
+      } else {
+        ui = owner ? U[(int64_t)i * ldv + row] : 0.0;
+        vi = owner ? V[(int64_t)i * ldv + row] : 0.0;
+      }
+      sp[i][rl] = ui * x;
+      sp[k + i][rl] = vi * x;
+    }
+    sp[2 * k][rl] = g0;
+    sp[2 * k + 1][rl] = g1;
+  }
+  lds_barrier();
+  if (tid < nv) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 16
+    for (int r = 0; r < 64; ++r) a[r & 3] += sp[tid][r];
+    part[((int64_t)c * nv + tid) * nrg + blockIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
+  }
+}
+
+// Partials of r_0 (U^T r_0, V^T r_0) for the first update launch.
+template <int NB>
+__global__ __launch_bounds__(256) void k_cg_init(int d, const double* __restrict__ V,
+                                                 const double* __restrict__ U, int64_t ldv,
+                                                 const double* __restrict__ R,
+                                                 const CgState* __restrict__ st,
+                                                 double* __restrict__ part) {
+  __shared__ double sp[2 * NB + 2][65];
+  const int k = st->k, c = blockIdx.y;
+  const int tid = threadIdx.x, sub = tid & 3;
+  const int row = blockIdx.x * 64 + (tid >> 2);
+  const bool owner = sub == 0 && row < d;
+  constexpr int KV = NB < 8 ? NB : 8;
+  const double* Vb = k > 0 ? V : R;
+  const double* Ub = k > 0 ? U : R;
+  double ur[KV], vr[KV];
+#pragma unroll
+  for (int i = 0; i < KV; ++i) {
+    ur[i] = ldsel(Ub, (int64_t)i * ldv + row, owner && i < k);
+    vr[i] = ldsel(Vb, (int64_t)i * ldv + row, owner && i < k);
+  }
+  const double x = ldsel(R, (int64_t)c * ldv + row, owner);
+  cg_write_parts<KV>(k, c, gridDim.x, x, ur, vr, U, V, ldv, row, owner, 0.0, 0.0, part, sp);
+}
+
+// The pass over M: chunk partials of M x, x = r_0 (it = 0) or w.
+template <typename MT, int NB, int CHUNK = cg_chunk<MT, NB>(), int KS = cg_ks<MT, NB>()>
+__global__ __launch_bounds__(256 * KS) void k_cg_pass(const MT* __restrict__ M, int64_t ldm, int d,
+                                                      const double* __restrict__ X, int64_t ldx,
+                                                      const CgState* __restrict__ st,
+                                                      double* __restrict__ work, int64_t wld) {
+  if (st->done) return;
+  constexpr int NT = 256 * KS;
+  __shared__ double pv[CHUNK][NB];
+  __shared__ ThinRed<KS, NB> red;
+  const int nb = st->nb;
+  const int tid = threadIdx.x;
+  const int j0 = blockIdx.y * CHUNK;
+  double rv[(NB * CHUNK + NT - 1) / NT];
+#pragma unroll
+  for (int u = 0; u < (NB * CHUNK + NT - 1) / NT; ++u) {
+    const int e = tid + u * NT;
+    const int c = e / CHUNK, j = j0 + e % CHUNK;
+    rv[u] = ldsel(X, (int64_t)c * ldx + j, e < NB * CHUNK && c < nb && j < d);
+  }
+  double m0[8];
+  symthin_first<MT, CHUNK, KS>(M, ldm, 0, d, m0);
+#pragma unroll
+  for (int u = 0; u < (NB * CHUNK + NT - 1) / NT; ++u) {
+    const int e = tid + u * NT;
+    if (e < NB * CHUNK) pv[e % CHUNK][e / CHUNK] = rv[u];
+  }
+  lds_barrier();
+  symthin_body<MT, NB, CHUNK, KS>(M, ldm, 0, d, pv, work, wld, nb, red, m0);
+}
+
+// Grid (row groups of 64, column c), 256 threads: four lanes per row sum
+// every fourth chunk of the pass (as k_cg_apply); the update is done by
+// lane 0 of each group of four.
+template <int NB>
+__global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ work, int64_t wld,
+                                                   int nchunk, int d, const double* __restrict__ V,
+                                                   const double* __restrict__ U, int64_t ldv,
+                                                   CgBufs b, CgState* __restrict__ st,
+                                                   const double* __restrict__ pin,
+                                                   double* __restrict__ pout, int it,
+                                                   int max_iter) {
+  if (st->done) return;
+  __shared__ double spr[2 * NB + 2][65];  // per-row values of the new partials (k <= NB)
+  __shared__ double sq[4 * NB][65];       // the previous partials, a row per value
+  __shared__ double sv[3 * 32 + 68];  // gamma, delta of every column, then this column's sums
+  const int nb = st->nb, k = st->k, nv = 2 * k + 2;
+  const int c = blockIdx.y, nrg = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int sub = tid & 3;
+  const int row = blockIdx.x * 64 + (tid >> 2);
+  const bool owner = sub == 0 && row < d;
+  constexpr int KV = NB < 8 ? NB : 8;
+  const int64_t o = (int64_t)c * ldv + row;
+  // Loads that do not wait for any sum come first, without branches.
+  double* R = b.R[0];
+  double* Wv = b.HR;
+  double* ZZ = b.P[1];
+  double* S = b.S[0];
+  double* P = b.P[0];
+  const double rv = ldsel(R, o, owner);
+  const double wv = ldsel(Wv, o, owner && it >= 1);
+  const double zzp = ldsel(ZZ, o, owner && it >= 2);
+  const double sp = ldsel(S, o, owner && it >= 2);
+  const double pp = ldsel(P, o, owner && it >= 2);
+  const double xv = ldsel(b.Z, o, owner && it >= 1);
+  const double* Vb = k > 0 ? V : R;
+  const double* Ub = k > 0 ? U : R;
+  double ur[KV], vr[KV];
+#pragma unroll
+  for (int i = 0; i < KV; ++i) {
+    ur[i] = ldsel(Ub, (int64_t)i * ldv + row, owner && i < k);
+    vr[i] = ldsel(Vb, (int64_t)i * ldv + row, owner && i < k);
+  }
+  // The state this launch reads, requested up front (a load waited for
+  // where it is used costs a round trip to memory each).
+  const double th = st->theta[c], tol2 = st->tol2;
+  const double rho = st->rho0[lane < nb ? lane : 0];
+  const double gprev = st->gam[(it - 1) & 1][c], aprev = st->alpha[(it - 1) & 1][c];
+  // The previous partials: value q of the list (gamma, delta of every
+  // column when it >= 1, then the 2k sums of this column), a lane per
+  // group; all of a wave's values (q = wave + 4u, at most 4 NB) at once.
+  const int ngd = it >= 1 ? 2 * nb : 0, nq = ngd + 2 * k;
+  auto qsrc = [&](int q) -> int64_t {
+    if (q < ngd) {
+      const int cc = q >> 1;
+      return ((int64_t)cc * nv + 2 * k + (q & 1)) * nrg;
+    }
+    return ((int64_t)c * nv + (q - ngd)) * nrg;
+  };
+  double pa[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int q = wave + 4 * u;
+    pa[u] = ldsel(pin, (q < nq ? qsrc(q) : 0) + lane, q < nq && lane < nrg);
+  }
+  // (M - theta) x for the row.
+  const int rowc = row < d ? row : d - 1;
+  const int nrb = (d + 255) / 256;
+  const double* wr = work + (int64_t)c * 256 + (rowc & 255);
+  const int rb = rowc >> 8;
+  double acc[4] = {0, 0, 0, 0};
+  int q = sub;
+  for (; q + 12 < nchunk; q += 16) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += wr[thin_block_base<NB>(q + 4 * u, rb, nrb)];
+  }
+  for (; q < nchunk; q += 4) acc[0] += wr[thin_block_base<NB>(q, rb, nrb)];
+  double y = row < d ? (acc[0] + acc[1]) + (acc[2] + acc[3]) : 0.0;
+  y += __shfl_xor(y, 1, WAVE);
+  y += __shfl_xor(y, 2, WAVE);
+  const double xop = it == 0 ? rv : wv;
+  y = owner ? y - th * xop : 0.0;
+  // Sums of the previous partials: a lane's groups (g = lane, lane + 64,
+  // ...) first, then the 64 lanes' sums in LDS, summed in order by thread q.
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int qq = wave + 4 * u;
+    if (qq < nq) {  // wave-uniform
+      double a = pa[u];
+      for (int g = lane + 64; g < nrg; g += 64) a += pin[qsrc(qq) + g];
+      sq[qq][lane] = a;
+    }
+  }
+  lds_barrier();
+  if (tid < nq) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 16
+    for (int g = 0; g < 64; ++g) a[g & 3] += sq[tid][g];
+    sv[tid] = (a[0] + a[1]) + (a[2] + a[3]);
+  }
+  lds_barrier();
+  // q = (M - theta) x - V (U^T x - theta V^T x)
+  const double* cs = sv + ngd;
+  double qv = y;
+  for (int i = 0; i < k; ++i) {
+    double vi;
+    if (i < KV) {
+      vi = vr[0];
+#pragma unroll
+      for (int u = 1; u < KV; ++u) vi = i == u ? vr[u] : vi;
+    } else {
+      vi = owner ? V[(int64_t)i * ldv + row] : 0.0;
+    }
+    qv = fma(-vi, cs[i] - th * cs[k + i], qv);
+  }
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+  if (it == 0) {
+    // w_0 = A r_0; partials of w_0 (U^T w_0, V^T w_0, gamma_0, delta_0).
+    if (owner) Wv[o] = qv;
+    const double w0 = owner ? qv : 0.0;
+    if (first && tid == 0) st->iters = 0;
+    cg_write_parts<KV>(k, c, nrg, w0, ur, vr, U, V, ldv, row, owner, rv * rv, w0 * rv, pout, spr);
+    return;
+  }
+  // Update it - 1: the test is on r_{it-1}, every column (lane cc tests
+  // column cc; every wave takes the same vote).
+  const int i_up = it - 1;
+  const bool miss = lane < nb && !(sv[2 * (lane < nb ? lane : 0)] <= tol2 * rho);
+  const bool conv = __ballot(miss) == 0;
+  if (conv || i_up >= max_iter) {
+    if (first && tid == 0) {
+      st->iters = i_up;
+      st->done = 1;
+    }
+    return;
+  }
+  const double gam = sv[2 * c], del = sv[2 * c + 1];
+  double alpha, beta = 0.0;
+  if (i_up >= 1) {
+    beta = gprev > 0.0 ? gam / gprev : 0.0;
+    const double den = del - (aprev != 0.0 ? beta * gam / aprev : 0.0);
+    alpha = den != 0.0 ? gam / den : 0.0;
+  } else {
+    alpha = del != 0.0 ? gam / del : 0.0;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    st->gam[it & 1][c] = gam;
+    st->alpha[it & 1][c] = alpha;
+  }
+  if (first && tid == 0) st->iters = it;
+  double wn = 0.0, rn = 0.0;
+  if (owner) {
+    const double zz = i_up >= 1 ? fma(beta, zzp, qv) : qv;
+    const double sn = i_up >= 1 ? fma(beta, sp, wv) : wv;
+    const double pn = i_up >= 1 ? fma(beta, pp, rv) : rv;
+    b.Z[o] = fma(alpha, pn, xv);
+    rn = fma(-alpha, sn, rv);
+    wn = fma(-alpha, zz, wv);
+    ZZ[o] = zz;
+    S[o] = sn;
+    P[o] = pn;
+    R[o] = rn;
+    Wv[o] = wn;
+  }
+  cg_write_parts<KV>(k, c, nrg, wn, ur, vr, U, V, ldv, row, owner, rn * rn, wn * rn, pout, spr);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void k_copy_out_w(const uint16_t* __restrict__ X, int64_t ps,
                                                     int dp, int d, double* __restrict__ R,
@@ -1591,7 +1889,9 @@ size_t cg_state_bytes() {
   static_assert(sizeof(CgState) == sizeof(CgHost), "CgState and CgHost must match");
   return sizeof(CgState);
 }
-size_t cg_part_doubles(int d) { return (size_t)nblocks(d, 64) * 32 * 34; }  // nb (k + 2) per group
+// nb (k + 2) per group for the Chronopoulos-Gear solve, two parities of
+// nb (2k + 2) per group for the pipelined one.
+size_t cg_part_doubles(int d) { return (size_t)2 * nblocks(d, 64) * 32 * 66; }
 size_t thin_work_doubles(int d) {
   const size_t dr = (size_t)nblocks(d, 256) * 256;  // the block layout rounds d up
   const size_t a = (size_t)nblocks(d, 128) * 32 * dr;
@@ -1647,7 +1947,54 @@ hipError_t symthin_words(int words, const uint16_t* X, int ld, int64_t ps, int d
   }
 }
 
-// One CG iteration (two launches); `it` counts from 0 within a solve.
+// One pipelined CG launch pair (see above); `it` counts from 0 within a
+// solve; it = 0 also forms U = M V and the partials of r_0.
+hipError_t cg_pipe_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb, int k,
+                             const double* V, int64_t ldv, const CgBufs& bufs, void* state,
+                             double* work, double* part, int it, int max_iter, hipStream_t st) {
+  if (k < 0 || k > nb || nb > 32 || (k > 0 && !bufs.U)) return hipErrorInvalidValue;
+  CgState* s = reinterpret_cast<CgState*>(state);
+  const int64_t wld = d;
+  const int nrg = nblocks(d, 64);
+  const size_t half = (size_t)nrg * 32 * 66;
+  double* pin = part + (size_t)((it + 1) & 1) * half;
+  double* pout = part + (size_t)(it & 1) * half;
+  if (it == 0) {
+    // U = M V (k columns), with the matrix the passes read.
+    if (k > 0) {
+      const hipError_t e =
+          M32 ? symthin_dispatch<float>(M32, ldm, 0, d, V, ldv, k, bufs.U, ldv, work, st)
+              : symthin_dispatch<double>(M, ldm, 0, d, V, ldv, k, bufs.U, ldv, work, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+#define REFL_CGP_PASS(MT, MP, NBV)                                                               \
+  {                                                                                              \
+    constexpr int CH = cg_chunk<MT, NBV>();                                                      \
+    nchunk = nblocks(d, CH);                                                                     \
+    hipLaunchKernelGGL((k_cg_pass<MT, NBV>), dim3(nblocks(d, 256), nchunk),                      \
+                       dim3(256 * cg_ks<MT, NBV>()), 0, st, MP, ldm, d,                          \
+                       it == 0 ? bufs.R[0] : bufs.HR, ldv, s, work, wld);                        \
+  }
+#define REFL_CGP(NBV)                                                                            \
+  {                                                                                              \
+    if (it == 0)                                                                                 \
+      hipLaunchKernelGGL((k_cg_init<NBV>), dim3(nrg, nb), dim3(256), 0, st, d, V, bufs.U, ldv,   \
+                         bufs.R[0], s, pin);                                                     \
+    int nchunk = 0;                                                                              \
+    if (M32) REFL_CGP_PASS(float, M32, NBV)                                                      \
+    else REFL_CGP_PASS(double, M, NBV)                                                           \
+    hipLaunchKernelGGL((k_cg_update<NBV>), dim3(nrg, nb), dim3(256), 0, st, work, wld, nchunk, d, \
+                       V, bufs.U, ldv, bufs, s, pin, pout, it, max_iter);                        \
+  }
+  REFL_NB_DISPATCH(nb, REFL_CGP)
+  else return hipErrorInvalidValue;
+#undef REFL_CGP
+#undef REFL_CGP_PASS
+  return hipGetLastError();
+}
+
+// One CG iteration (two launches); `it` counts from 0 within a solve.// One CG iteration (two launches); `it` counts from 0 within a solve.
 hipError_t cg_iteration(const double* M, const float* M32, int64_t ldm, int d, int nb,
                         const double* V, int64_t ldv, const CgBufs& bufs, void* state,
                         double* work, double* part, int it, int max_iter, hipStream_t st) {

@@ -571,7 +571,7 @@ refl_status_t orthonormalise(refl_handle_t h, Work& w, double*& V, double*& spar
 // r in cb.R[0], cb.Z zeroed), over H in FP64 or its FP32 copy.  On return
 // *hs holds the final state (iters, done).
 refl_status_t cg_solve(refl_handle_t h, Work& w, bool use32, const double* V, int k, const CgBufs& cb,
-                       int max_iter, CgHost* hs) {
+                       int max_iter, CgHost* hs, bool pipe = false) {
   hipStream_t st = h->stream;
   const int64_t ld = w.dp;
   HIPCHK(hipMemcpyAsync(w.cgstate, hs, sizeof(CgHost), hipMemcpyHostToDevice, st));
@@ -581,9 +581,14 @@ refl_status_t cg_solve(refl_handle_t h, Work& w, bool use32, const double* V, in
     // then 16 between host checks of the convergence flag.  Iteration
     // max_iter + 1 only runs the convergence test.
     const int batch = issued == 0 ? 32 : 16;
-    for (int b = 0; b < batch && issued <= max_iter + 1; ++b, ++issued)
-      HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, w.d, k, V, ld, cb, w.cgstate, w.thin,
-                          w.cgpart, issued, max_iter, st));
+    for (int b = 0; b < batch && issued <= max_iter + 1; ++b, ++issued) {
+      if (pipe)
+        HIPCHK(cg_pipe_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, w.d, k, k, V, ld, cb, w.cgstate,
+                                 w.thin, w.cgpart, issued, max_iter, st));
+      else
+        HIPCHK(cg_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, w.d, k, V, ld, cb, w.cgstate, w.thin,
+                            w.cgpart, issued, max_iter, st));
+    }
     HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (hs->done || issued > max_iter + 1) break;
@@ -664,7 +669,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     // the next Rayleigh-Ritz step: spare (not V), Wm and Wspare.
     HIPCHK(lincomb(d, k, -1.0, w.Rr, ld, 0.0, w.Rr, ld, st));
     HIPCHK(lincomb(d, k, 0.0, w.Rr, ld, 0.0, w.Z, ld, st));
-    const CgBufs cb = {{w.Rr, spare}, {w.P[0], w.P[1]}, {Wm, Wspare}, w.AP, w.Z};
+    const CgBufs cb = {{w.Rr, spare}, {w.P[0], w.P[1]}, {Wm, Wspare}, w.AP, w.Z, Wspare};
     std::memset(hs, 0, sizeof(CgHost));
     for (int c = 0; c < k; ++c) {
       hs->theta[c] = th[c];
@@ -673,7 +678,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     hs->tol2 = p.cg_tol * p.cg_tol;
     hs->k = k;
     hs->nb = k;
-    refl_status_t cr = cg_solve(h, w, use32, V, k, cb, p.cg_max_iter, hs);
+    refl_status_t cr = cg_solve(h, w, use32, V, k, cb, p.cg_max_iter, hs, true);
     if (cr != REFL_OK) return cr;
     cg_total += hs->iters;
     // V <- orth(V + Z)
@@ -2322,7 +2327,7 @@ refl_status_t grad_mixed(refl_handle_t h, int64_t d, const double* dH, int64_t l
     hs->tol2 = GRAD_CG_TOL * GRAD_CG_TOL;
     hs->k = k;
     hs->nb = k;
-    const CgBufs cb = {{w.Rr, spare}, {w.P[0], w.P[1]}, {w.W, w.T2}, w.AP, w.Z};
+    const CgBufs cb = {{w.Rr, spare}, {w.P[0], w.P[1]}, {w.W, w.T2}, w.AP, w.Z, nullptr};
     const int cap = 4 * p.cg_max_iter;
     rs = cg_solve(h, w, false, V, k, cb, cap, hs);
     if (rs != REFL_OK) return rs;

@@ -89,8 +89,10 @@ hipError_t launch_init_x0_f64(const double* Hf, int dp, int d, double s, const d
                               double* X, hipStream_t st);
 hipError_t launch_init_x0_f32(const double* Hf, int dp, int d, double s, const double* scal,
                               float* X, hipStream_t st);
+// With H32 != null the same pass also writes the FP32 copy of H (dp x dp).
 hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, double s,
-                                const double* scal, uint16_t* X, int64_t ps, hipStream_t st);
+                                const double* scal, uint16_t* X, int64_t ps, float* H32,
+                                hipStream_t st);
 // FP32 copy of H - sI (the operator of the inner solves).
 hipError_t launch_shifted_f32(const double* Hf, int dp, int d, double s, float* Hs,
                               hipStream_t st);

@@ -139,16 +139,20 @@ __global__ __launch_bounds__(256) void k_init_x0(const double* __restrict__ Hf, 
                 (int64_t)gridDim.x * 256);
 }
 
+// With H32 != null it also writes the FP32 copy of H (unshifted) that the
+// correction's inner solves read, saving that pass its own read of H.
 template <int W>
 __global__ __launch_bounds__(256) void k_init_x0_w(const double* __restrict__ Hf, int dp, int d,
                                                    double s, const double* __restrict__ scal,
-                                                   uint16_t* __restrict__ X, int64_t ps) {
+                                                   uint16_t* __restrict__ X, int64_t ps,
+                                                   float* __restrict__ H32) {
   const int64_t n = (int64_t)dp * dp;
   const double inv = 1.0 / scal[SC_ALPHA];
   for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * 256) {
     const int i = (int)(idx / dp), j = (int)(idx % dp);
     double v = Hf[idx];
+    if (H32) H32[idx] = (float)v;
     if (i == j && i < d) v -= s;
     uint16_t w[W];
     split_words<W>((float)(v * inv), w);
@@ -1611,12 +1615,13 @@ hipError_t launch_init_x0_f32(const double* Hf, int dp, int d, double s, const d
   return hipGetLastError();
 }
 hipError_t launch_init_x0_words(int words, const double* Hf, int dp, int d, double s,
-                                const double* scal, uint16_t* X, int64_t ps, hipStream_t st) {
+                                const double* scal, uint16_t* X, int64_t ps, float* H32,
+                                hipStream_t st) {
   const dim3 g(grid_elems((int64_t)dp * dp));
   switch (words) {
-    case 1: hipLaunchKernelGGL(k_init_x0_w<1>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps); break;
-    case 2: hipLaunchKernelGGL(k_init_x0_w<2>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps); break;
-    case 3: hipLaunchKernelGGL(k_init_x0_w<3>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps); break;
+    case 1: hipLaunchKernelGGL(k_init_x0_w<1>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps, H32); break;
+    case 2: hipLaunchKernelGGL(k_init_x0_w<2>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps, H32); break;
+    case 3: hipLaunchKernelGGL(k_init_x0_w<3>, g, dim3(256), 0, st, Hf, dp, d, s, scal, X, ps, H32); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

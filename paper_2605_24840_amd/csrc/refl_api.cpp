@@ -162,6 +162,7 @@ struct Work {
   double* rowsum;
   double* partials;
   double* partials_t;  // update products' trace partials (single-problem device loops)
+  bool h32_ready = false;  // H32 already holds the FP32 copy of H (written with X_0)
   int2* tiles;
   // bulk (only the ones of the precision are non-null)
   double *X64[2], *N64;
@@ -661,7 +662,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
         (p.cg_f32 == REFL_CG_FP32 ||
          (p.cg_f32 == REFL_CG_AUTO && theta_max < s && info &&
           0x1.0p-24 * info->alpha / (s - theta_max) < 1e-3))) {
-      HIPCHK(launch_shifted_f32(w.Hf, w.dp, d, 0.0, w.H32, st));
+      if (!w.h32_ready) HIPCHK(launch_shifted_f32(w.Hf, w.dp, d, 0.0, w.H32, st));
       use32 = true;
     }
     // Correction: (I - VV^T)(H - theta_c)(I - VV^T) z_c = -E_c by block CG.
@@ -1116,7 +1117,8 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     HIPCHK(launch_init_x0_f32(w.Hf, w.dp, (int)d, s, w.scal, w.X32[0], st));
     HIPCHK(launch_trace_f32(w.X32[0], w.dp, (int)d, w.scal, SC_TRACE, st));
   } else {
-    HIPCHK(launch_init_x0_words(W, w.Hf, w.dp, (int)d, s, w.scal, w.Xw[0], w.ps, st));
+    HIPCHK(launch_init_x0_words(W, w.Hf, w.dp, (int)d, s, w.scal, w.Xw[0], w.ps, w.H32, st));
+    w.h32_ready = w.H32 != nullptr;
     HIPCHK(launch_trace_words(W, w.Xw[0], w.ps, w.dp, (int)d, w.scal, SC_TRACE, st));
   }
   HIPCHK(hipMemcpyAsync(hsc, w.scal, sizeof(double) * 4, hipMemcpyDeviceToHost, st));

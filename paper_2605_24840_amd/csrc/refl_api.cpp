@@ -1150,9 +1150,11 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
   if (p.timing) {
     if (h->no_alloc && h->ev.size() < 2 * max_ev)
       return fail(h, REFL_ERR_INVALID_ARG, "params.timing creates events: not available without allocation");
+    // Timing only: no system-scope fence at each record (the cache
+    // writeback and invalidation it implies cost about 10 us per step).
     while (h->ev.size() < 2 * max_ev) {
       hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       h->ev.push_back(e);
     }
   }
@@ -1894,7 +1896,7 @@ refl_status_t batched_impl(refl_handle_t h, int nprob, const int64_t* d, const d
   auto ev_pair = [&]() -> hipError_t {
     while (h->ev.size() < 2 * (nev + 1)) {
       hipEvent_t e;
-      hipError_t er = hipEventCreate(&e);
+      hipError_t er = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);  // timing only
       if (er != hipSuccess) return er;
       h->ev.push_back(e);
     }
@@ -2440,7 +2442,7 @@ refl_status_t grad_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     if (on) {
       while (h->ev.size() < 2 * (nev + 1)) {
         hipEvent_t e;
-        hipError_t er = hipEventCreate(&e);
+        hipError_t er = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);  // timing only
         if (er != hipSuccess) return er;
         h->ev.push_back(e);
       }

@@ -162,6 +162,8 @@ struct Work {
   double* rowsum;
   double* partials;
   double* partials_t;  // update products' trace partials (single-problem device loops)
+  double *qr_gp[2], *qr_B;  // device Cholesky QR of the correction's blocks: Gram partials, R
+  int* qr_flag;
   bool h32_ready = false;  // H32 already holds the FP32 copy of H (written with X_0)
   int2* tiles;
   // bulk (only the ones of the precision are non-null)
@@ -403,6 +405,10 @@ size_t layout(Work& w, void* base, int64_t d, const refl_params_t& p, LayoutKind
   w.gwork = c.take<double>(gram_work_doubles((int)dp));
   w.cgpart = c.take<double>(cg_part_doubles((int)dp));
   w.cgstate = c.take<char>(cg_state_bytes());
+  w.qr_gp[0] = c.take<double>(lz_gram_part_doubles((int)dp, MAXB));
+  w.qr_gp[1] = c.take<double>(lz_gram_part_doubles((int)dp, MAXB));
+  w.qr_B = c.take<double>(MAXB * MAXB);
+  w.qr_flag = c.take<int>(4);
   if (!for_apply && p.shift_mode == REFL_SHIFT_LANCZOS) carve_lanczos(c, w.lz, d, w.dp, p.k, p.lanczos_steps);
   return c.off + 256;
 }
@@ -549,23 +555,28 @@ bool small_order(int64_t d, bool fp64) {
 static_assert(sizeof(SmallProb) == 32 && sizeof(BatchRule) == 16 && sizeof(BatchStep) == 48,
               "staging layout of the small-order launch");
 
-// Orthonormalise the d x nb block V (ld dp) by two rounds of Cholesky QR.
+// Orthonormalise the d x nb block V (ld dp) by two rounds of Cholesky QR,
+// on the device with the block-Lanczos kernels (slab Gram partials, then
+// two k_lz_cholqr rounds; no host round trip).  A pivot that is not
+// positive sets bit 1 of w.qr_flag, which the caller clears before its
+// first call; the flag is copied to the pinned slot qr_flag_host() behind
+// the kernels and tested at the caller's next synchronisation
+// (qr_lost_rank).
+int* qr_flag_host(refl_handle_t h) {
+  return reinterpret_cast<int*>(reinterpret_cast<char*>(h->pinned + SC_COUNT) + sizeof(CgHost) + 128);
+}
 refl_status_t orthonormalise(refl_handle_t h, Work& w, double*& V, double*& spare, int nb) {
-  std::vector<double> G(nb * nb), L(nb * nb), C(nb * nb);
-  for (int round = 0; round < 2; ++round) {
-    HIPCHK(gram(V, w.dp, nb, V, w.dp, nb, w.d, w.G, w.gwork, h->stream));
-    HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * nb * nb, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    // G column-major == row-major for a symmetric matrix.
-    if (cholesky_small(nb, G.data(), L.data()) != 0)
-      return fail(h, REFL_ERR_NOT_CONVERGED, "Cholesky QR: block lost rank");
-    inv_lower_transpose(nb, L.data(), C.data());
-    HIPCHK(hipMemcpyAsync(w.G, C.data(), sizeof(double) * nb * nb, hipMemcpyHostToDevice, h->stream));
-    HIPCHK(block_axpy(w.d, nb, nb, 0.0, spare, w.dp, 1.0, V, w.dp, w.G, h->stream));
-    std::swap(V, spare);
-  }
+  hipStream_t st = h->stream;
+  HIPCHK(lz_gram(V, w.dp, nb, w.d, w.qr_gp[0], st));
+  HIPCHK(lz_cholqr(w.qr_gp[0], LZ_GRAM_ROWS, w.d, nb, 0.0, w.qr_B, 0, nullptr, nullptr, w.qr_flag, 1, V,
+                   w.dp, spare, w.dp, w.qr_gp[1], LZ_QR_PLAIN, nullptr, st));
+  HIPCHK(lz_cholqr(w.qr_gp[1], 256, w.d, nb, 0.0, w.qr_B, 1, nullptr, nullptr, w.qr_flag, 2, spare,
+                   w.dp, spare, w.dp, nullptr, LZ_QR_PLAIN, nullptr, st));
+  HIPCHK(hipMemcpyAsync(qr_flag_host(h), w.qr_flag, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  std::swap(V, spare);
   return REFL_OK;
 }
+bool qr_lost_rank(refl_handle_t h) { return (qr_flag_host(h)[0] & 1) != 0; }
 
 // Block CG on (I - V V^T)(H - theta_c)(I - V V^T) z_c = r_c, c < k (V: d x k,
 // ld dp), from the state *hs (theta, rho0, tol2, k, nb set by the caller;
@@ -608,6 +619,8 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
   hipStream_t st = h->stream;
   double* V = w.V;
   double* spare = w.T1;
+  HIPCHK(hipMemsetAsync(w.qr_flag, 0, 4 * sizeof(int), st));
+  qr_flag_host(h)[0] = 0;
   HIPCHK(random_block(V, ld, d, k, p.seed ^ 0x5EEDull, st));
   // Subspace extraction with the approximate projector (I - X)/2.
   for (int it = 0; it < 2; ++it) {
@@ -629,6 +642,7 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     HIPCHK(gram(V, ld, k, Wm, ld, k, d, w.G, w.gwork, st));
     HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (qr_lost_rank(h)) return fail(h, REFL_ERR_NOT_CONVERGED, "Cholesky QR: block lost rank");
     if (sym_eig_small(k, G.data(), th.data(), Q.data()) != 0)
       return fail(h, REFL_ERR_NOT_CONVERGED, "Rayleigh-Ritz eigensolver failed");
     for (int i = 0; i < k; ++i)

@@ -132,39 +132,6 @@ int sym_eig_small(int n, const double* A_in, double* w, double* Q_out) {
   return 0;
 }
 
-int cholesky_small(int n, const double* G, double* L) {
-  for (int i = 0; i < n * n; ++i) L[i] = 0.0;
-  for (int j = 0; j < n; ++j) {
-    double s = G[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
-    if (!(s > 0.0)) return -1;
-    const double ljj = std::sqrt(s);
-    L[(size_t)j * n + j] = ljj;
-    for (int i = j + 1; i < n; ++i) {
-      double t = G[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
-      L[(size_t)i * n + j] = t / ljj;
-    }
-  }
-  return 0;
-}
-
-void inv_lower_transpose(int n, const double* L, double* C) {
-  // C = L^{-T} (upper triangular), column-major n x n (C[i + n*j]).
-  std::vector<double> Li((size_t)n * n, 0.0);  // L^{-1}, row-major
-  for (int j = 0; j < n; ++j) {
-    Li[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s += L[(size_t)i * n + k] * Li[(size_t)k * n + j];
-      Li[(size_t)i * n + j] = -s / L[(size_t)i * n + i];
-    }
-  }
-  // (L^{-T})_{ij} = (L^{-1})_{ji}
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) C[i + (size_t)n * j] = Li[(size_t)j * n + i];
-}
-
 void band_tridiag(int n, int bw, const double* Lb, double* diag, double* sub) {
   // Working storage with one extra diagonal for the bulge:
   // A[i][j] (i >= j, i - j <= bw + 1) at S[i * ws + (i - j)], ws = bw + 2.

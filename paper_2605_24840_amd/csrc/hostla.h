@@ -10,12 +10,6 @@ namespace refl {
 // columns.  Returns 0, or -1 if the QL iteration failed to converge.
 int sym_eig_small(int n, const double* A_in, double* w, double* Q_out);
 
-// G = L L^T for symmetric positive definite G (row-major); -1 if not.
-int cholesky_small(int n, const double* G, double* L);
-
-// C = L^{-T} for lower-triangular L (row-major), written column-major.
-void inv_lower_transpose(int n, const double* L, double* C);
-
 // Symmetric band matrices of order n and half-bandwidth bw, given by their
 // lower band: Lb[i * (bw + 1) + (i - j)] = T[i][j] for 0 <= i - j <= bw.
 

@@ -55,22 +55,6 @@ static int dense_eig(int n) {
     }
   }
   CHECK(worst <= 1e-12 * n * (scale + 1.0), "eig residual %g n=%d", worst, n);
-  // Cholesky of A^T A + I and the inverse transpose of its factor.
-  std::vector<double> G(n * n, 0.0), L(n * n), C(n * n);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double s = i == j ? 1.0 : 0.0;
-      for (int t = 0; t < n; ++t) s += A[t * n + i] * A[t * n + j];
-      G[i * n + j] = s;
-    }
-  CHECK(cholesky_small(n, G.data(), L.data()) == 0, "cholesky failed n=%d", n);
-  inv_lower_transpose(n, L.data(), C.data());
-  for (int i = 0; i < n; ++i)       // L^T C = I with C column-major
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int t = 0; t < n; ++t) s += L[t * n + i] * C[t + n * j];
-      CHECK(std::fabs(s - (i == j)) <= 1e-10, "inverse n=%d", n);
-    }
   return 0;
 }
 

@@ -111,7 +111,9 @@ typedef struct {
   int32_t lanczos_steps;/* REFL_SHIFT_LANCZOS: cap on block steps (0 = automatic) */
   uint64_t seed;        /* start blocks of Lanczos and of the subspace extraction */
   int32_t timing;       /* 1: record HIP events around every bulk product and report their
-                           summed durations in info (adds no synchronisation) */
+                           summed durations in info (adds no synchronisation); N > 1: in
+                           the MIXED bulk, only around the products of every N-th step
+                           (a sample: each event pair costs the device some microseconds) */
   int32_t grad_mode;    /* refl_sign_grad: REFL_GRAD_REVERSE (default) or REFL_GRAD_TANGENT */
   int32_t ckpt_every;   /* refl_sign_grad, reverse mode: keep every c-th iterate and
                            recompute the others.  0: keep every iterate and its N = I - X^2

@@ -469,6 +469,7 @@ refl_status_t check_params(refl_handle_t h, int64_t d, const refl_params_t* p) {
   if (p->shift_mode == REFL_SHIFT_GIVEN && !std::isfinite(p->s))
     return fail(h, REFL_ERR_NOT_FINITE, "shift is not finite");
   if (p->max_iter < 1) return fail(h, REFL_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (p->timing < 0) return fail(h, REFL_ERR_INVALID_ARG, "timing must be >= 0");
   if (p->fixed_steps < 0) return fail(h, REFL_ERR_INVALID_ARG, "fixed_steps must be >= 0");
   if (p->precision == REFL_PREC_MIXED) {
     if (p->words < 1 || p->words > 3) return fail(h, REFL_ERR_INVALID_ARG, "words must be 1..3");
@@ -1224,23 +1225,27 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
       HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       lev.push_back(e);
     }
+    // With params.timing = N > 1 only the products of every N-th step are
+    // timed (each event pair costs the device some microseconds).
+    const int tstride = p.timing > 1 ? p.timing : 1;
     auto enqueue_step = [&](int m) -> hipError_t {
       uint16_t* Xm = w.Xw[m % 3];
       uint16_t* Xn = w.Xw[(m + 1) % 3];
+      const bool tm = m % tstride == 0;
       hipError_t e;
-      if ((e = ev_start()) != hipSuccess) return e;
+      if (tm && (e = ev_start()) != hipSuccess) return e;
       if ((e = launch_sym_gemm_words(W, w.ts, GEMM_RESIDUAL, Xm, Xm, nullptr, w.Nw, w.dp, w.ps, (int)d,
                                      w.dk, w.tiles, w.ntiles, w.partials, st, d_live)) != hipSuccess)
         return e;
-      if ((e = ev_stop()) != hipSuccess) return e;
+      if (tm && (e = ev_stop()) != hipSuccess) return e;
       if ((e = launch_reduce_decide(w.partials, w.partials_t, w.ntiles, w.scal, d_ru, d_sq, d_live,
                                     d_ctl, m % 3, st)) != hipSuccess)
         return e;
-      if ((e = ev_start()) != hipSuccess) return e;
+      if (tm && (e = ev_start()) != hipSuccess) return e;
       if ((e = launch_sym_gemm_words(W, w.ts, GEMM_UPDATE, Xm, w.Nw, Xm, Xn, w.dp, w.ps, (int)d, w.dk,
                                      w.tiles, w.ntiles, w.partials_t, st, d_live)) != hipSuccess)
         return e;
-      return ev_stop();
+      return tm ? ev_stop() : hipSuccess;
     };
     int enq = 0;  // steps enqueued
     int group = STEPS_AHEAD;
@@ -1285,8 +1290,10 @@ refl_status_t sign_impl(refl_handle_t h, int64_t d, const double* dH, int64_t ld
     if (sq->state == BATCH_NONFINITE)
       bulk_status = fail(h, REFL_ERR_NOT_FINITE, "iterate diverged at step %d", b.steps);
     // Timed launches: those of the steps taken (residual products of steps
-    // 0..m, update products of steps 0..m-1).
-    nev = std::min(nev, (size_t)(2 * b.steps + 1));
+    // 0..m, update products of steps 0..m-1), in enqueue order.
+    size_t taken = 0;
+    for (int m = 0; m <= b.steps; m += tstride) taken += m < b.steps ? 2 : 1;
+    nev = std::min(nev, taken);
   } else if (p.precision != REFL_PREC_MIXED && small_order(d, p.precision == REFL_PREC_FP64)) {
     // Every step in one launch, X and N held in LDS, the stopping rule on
     // the device.  Problem, rule and step record are staged through the

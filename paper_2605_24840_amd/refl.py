@@ -388,7 +388,7 @@ def make_params(k, s=None, precision="fp64", tol=None, max_iter=100, fixed_steps
     p.cg_max_iter = int(cg_max_iter)
     p.lanczos_steps = int(lanczos_steps)
     p.seed = int(seed)
-    p.timing = 1 if timing else 0
+    p.timing = (1 if timing else 0) if isinstance(timing, bool) else int(timing)
     p.grad_mode = GRAD_MODE[grad_mode]
     p.ckpt_every = int(ckpt_every)
     p.cg_f32 = CG_PREC[cg_prec]

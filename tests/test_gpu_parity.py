@@ -393,6 +393,31 @@ def test_mixed_planted_d1024(R, handle, grel):
     assert err <= 1e-8 * np.sqrt(d)
 
 
+def test_mixed_timing_sampled(R, handle):
+    # params.timing on the MIXED bulk: the events change nothing in the
+    # result; timing = 1 times the products of every step taken (m + 1
+    # residual, m update), timing = 3 those of steps 0, 3, 6, ... only.
+    d, k = 1024, 8
+    H, lam, Q = inputs.planted_hessian(d, k, 0.02, 0)
+    s = 0.5 * (lam[k - 1] + lam[k])
+    Hg = _gpu(H)
+    _say(f"mixed timing sampled d={d} k={k}")
+    runs = {}
+    for t in (0, 1, 3):
+        Rg, info, st = R.sign(Hg, k, s, handle=handle, precision="mixed", check=False, timing=t)
+        assert st == 0
+        runs[t] = (Rg.clone(), info)
+    m = runs[0][1]["ns_steps"]
+    assert m >= 6
+    for t in (1, 3):
+        assert torch.equal(runs[0][0], runs[t][0])
+        assert runs[t][1]["ns_steps"] == m
+    assert runs[0][1]["gemm_launches"] == 0
+    assert runs[1][1]["gemm_launches"] == 2 * m + 1
+    assert runs[3][1]["gemm_launches"] == sum(2 if j < m else 1 for j in range(0, m + 1, 3))
+    assert runs[3][1]["ms_gemm"] > 0.0
+
+
 def _allen_cahn_golden(seed=0):
     path = os.path.join(GOLDEN, f"allen_cahn_n64_seed{seed}.npz")
     if not os.path.exists(path):

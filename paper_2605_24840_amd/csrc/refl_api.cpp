@@ -588,12 +588,18 @@ refl_status_t cg_solve(refl_handle_t h, Work& w, bool use32, const double* V, in
   hipStream_t st = h->stream;
   const int64_t ld = w.dp;
   HIPCHK(hipMemcpyAsync(w.cgstate, hs, sizeof(CgHost), hipMemcpyHostToDevice, st));
-  int issued = 0;
+  // The first batch is 32 iterations (every correction solve here needs
+  // more); each later one runs to where the residuals, extrapolated
+  // geometrically from the last two checks, reach the tolerance (plus two),
+  // within 8..64: a host check drains the queue, so fewer checks save more
+  // than the few iterations queued past convergence cost (they return at
+  // once).  Iteration max_iter + 1 only runs the convergence test.
+  const int nb = hs->nb;
+  const double tol2 = hs->tol2;
+  std::vector<double> rho0(hs->rho0, hs->rho0 + nb), gprev(rho0);
+  int itprev = 0;
+  int issued = 0, batch = 32;
   while (true) {
-    // First batch 32 iterations (every correction solve here needs more),
-    // then 16 between host checks of the convergence flag.  Iteration
-    // max_iter + 1 only runs the convergence test.
-    const int batch = issued == 0 ? 32 : 16;
     for (int b = 0; b < batch && issued <= max_iter + 1; ++b, ++issued) {
       if (pipe)
         HIPCHK(cg_pipe_iteration(w.Hf, use32 ? w.H32 : nullptr, ld, w.d, k, k, V, ld, cb, w.cgstate,
@@ -605,6 +611,28 @@ refl_status_t cg_solve(refl_handle_t h, Work& w, bool use32, const double* V, in
     HIPCHK(hipMemcpyAsync(hs, w.cgstate, sizeof(CgHost), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (hs->done || issued > max_iter + 1) break;
+    // The newest residual norms (the two state slots hold the last two
+    // iterations'; the smaller of each pair is taken).
+    const int itnow = hs->iters;
+    double need = 0.0;
+    bool known = itnow > itprev;
+    for (int c = 0; c < nb && known; ++c) {
+      const double g = std::min(hs->gam[0][c], hs->gam[1][c]);
+      if (!(g > tol2 * rho0[c])) continue;
+      if (!(g < gprev[c]) || !(gprev[c] > 0.0)) {
+        known = false;
+        break;
+      }
+      const double rate = std::log(g / gprev[c]) / (itnow - itprev);  // < 0
+      need = std::max(need, std::log(tol2 * rho0[c] / g) / rate);
+    }
+    if (known) {
+      for (int c = 0; c < nb; ++c) gprev[c] = std::min(hs->gam[0][c], hs->gam[1][c]);
+      itprev = itnow;
+      batch = std::min(64, std::max(8, (int)std::ceil(need) + 2));
+    } else {
+      batch = 16;
+    }
   }
   return REFL_OK;
 }

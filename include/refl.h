@@ -59,7 +59,7 @@ typedef enum {
                                   params.sym_tol times max |H_ij| (section 2.1 takes H
                                   symmetric; by default only the upper triangle is read and
                                   this is not checked) */
-  REFL_ERR_UNSUPPORTED = 8,    /* valid request this build does not implement */
+  REFL_ERR_UNSUPPORTED = 8,    /* valid request the library does not implement */
   REFL_ERR_NOT_FINITE = 9      /* H (or the shift/scale) holds a NaN or an infinity */
 } refl_status_t;
 

@@ -555,18 +555,18 @@ __device__ void lz_record(int nb, int round, double* __restrict__ Bacc,
                           const double* __restrict__ Arec, double* __restrict__ Brec,
                           int* __restrict__ flag, int tag, LzFactor& f) {
   const int t = threadIdx.x;
-  if (t < nb) {
-    for (int i = 0; i < nb; ++i) {
-      const double rij = (i <= t) ? f.G[t][i] : 0.0;  // R[i][t] = L[t][i]
-      double s;
-      if (round == 0) {
-        s = rij;
-      } else {
-        s = 0.0;
-        for (int m = i; m <= t; ++m) s += f.G[m][i] * f.Bo[m][t];  // R[i][m] B[m][t]
-      }
-      f.Bt[i][t] = s;
+  // One entry (i, c) of the new B per thread (the sum over m in the same
+  // order as one thread per column would take it).
+  for (int e = t; e < nb * nb; e += 256) {
+    const int i = e % nb, c = e / nb;
+    double s;
+    if (round == 0) {
+      s = (i <= c) ? f.G[c][i] : 0.0;  // R[i][c] = L[c][i]
+    } else {
+      s = 0.0;
+      for (int m = i; m <= c; ++m) s += f.G[m][i] * f.Bo[m][c];  // R[i][m] B[m][c]
     }
+    f.Bt[i][c] = s;
   }
   __syncthreads();
   for (int e = t; e < nb * nb; e += 256) {

@@ -60,7 +60,9 @@ typedef enum {
                                   symmetric; by default only the upper triangle is read and
                                   this is not checked) */
   REFL_ERR_UNSUPPORTED = 8,    /* valid request the library does not implement */
-  REFL_ERR_NOT_FINITE = 9      /* H (or the shift/scale) holds a NaN or an infinity */
+  REFL_ERR_NOT_FINITE = 9,     /* H (or the shift/scale) holds a NaN or an infinity */
+  REFL_ERR_BOUNDS = 10         /* debug build only: a kernel's launch-extent guard tripped
+                                  (refl_last_error names the kernel); outputs are undefined */
 } refl_status_t;
 
 /* Arithmetic of the Newton-Schulz matrix products. */
@@ -459,6 +461,17 @@ refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, c
 /* Static strings; never NULL. */
 const char *refl_status_string(refl_status_t s);
 const char *refl_last_error(refl_handle_t h);
+
+/* 1 if this library is the bounds-checked debug build (compiled with
+ * -DREFL_DEBUG), else 0.  In that build every guarded kernel checks on
+ * entry that the tiles, rows, K-slices and block columns it touches lie
+ * inside the extents it was launched with; a block that fails returns
+ * before any memory access and records the kernel.  Each entry point that
+ * runs device work then synchronises the handle's stream, reads and clears
+ * the records, and returns REFL_ERR_BOUNDS if one is set.  Not a check of
+ * the paper's mathematics: a development aid, slower than the release
+ * build by one stream synchronisation per call. */
+int refl_debug_build(void);
 
 #ifdef __cplusplus
 }

@@ -19,10 +19,13 @@
 // step k).  The epilogue stages the tile in LDS, so that the direct and the
 // transposed stores are both row-contiguous.
 #include "common.h"
+#include "dbg.h"
 #include "launch.h"
 #include "rule.h"
 
 namespace refl {
+
+REFL_DBG_UNIT(gemm_f)
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -93,6 +96,9 @@ __device__ __forceinline__ void sym_gemm_f_tile(const Pairs<T, NP>& op, const T*
   constexpr int MB = C::MB;
   const int i0 = I * TS, j0 = J * TS;
   const bool diag = SYM && (I == J);
+  REFL_GUARD(I >= 0 && J >= 0 && (!SYM || I <= J) && i0 + TS <= dp && j0 + TS <= dp && d <= dp &&
+                 dp <= ld && dp % C::BK == 0,
+             DBG_GEMM_F_TILE);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 

@@ -29,9 +29,12 @@
 #include <type_traits>
 
 #include "common.h"
+#include "dbg.h"
 #include "launch.h"
 
 namespace refl {
+
+REFL_DBG_UNIT(gemm_w)
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -81,6 +84,9 @@ __global__ __launch_bounds__(256) void k_sym_gemm_w(const uint16_t* __restrict__
   const int2 tl = tiles[blockIdx.x];
   const int i0 = tl.x * TS, j0 = tl.y * TS;
   const bool diag = (tl.x == tl.y);
+  REFL_GUARD(tl.x >= 0 && tl.x <= tl.y && j0 + TS <= ld && d <= dk && dk <= ld && dk % 32 == 0 &&
+                 ps >= (int64_t)ld * ld,
+             DBG_GEMM_W_TILE);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 
@@ -357,6 +363,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const int2 tl = tiles[blockIdx.x];
   const int i0 = tl.x * TS, j0 = tl.y * TS;
   const bool diag = (tl.x == tl.y);
+  REFL_GUARD(tl.x >= 0 && tl.x <= tl.y && j0 + TS <= ld && d <= dk && dk <= ld && dk % 32 == 0 &&
+                 ps >= (int64_t)ld * ld,
+             DBG_GEMM_WD_TILE);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = wave >> 1, wc = wave & 1;
 

@@ -27,10 +27,13 @@
 #include <type_traits>
 
 #include "common.h"
+#include "dbg.h"
 #include "sync.h"
 #include "launch.h"
 
 namespace refl {
+
+REFL_DBG_UNIT(lanczos)
 
 constexpr int LZ_RC = 64;   // rows per block of the projection partials
 
@@ -53,6 +56,7 @@ __global__ __launch_bounds__(256) void k_lz_proj_partial(const double* __restric
   const int cg = t & 31, jg = t >> 5;
   const int c0 = blockIdx.x * 64;
   const int r0 = blockIdx.y * LZ_RC;
+  REFL_GUARD(nb >= 1 && nb <= NB && c0 < n && r0 < d && ldv >= d && ldw >= d, DBG_LZ);
   const int r1 = min(d, r0 + LZ_RC);
   double acc[2][JQ];
 #pragma unroll
@@ -122,6 +126,7 @@ __global__ __launch_bounds__(256) void k_lz_proj_finish(const double* __restrict
                                                         int accumulate, int cblocks,
                                                         const double* __restrict__ gsrc,
                                                         int gslab, double* __restrict__ gdst) {
+  REFL_GUARD(nb >= 1 && nb <= NB, DBG_LZ);
   if ((int)blockIdx.x >= cblocks) {
     const int g2 = ((int)blockIdx.x - cblocks) * 256 + (int)threadIdx.x;
     const int q = g2 & 15, o = g2 >> 4;
@@ -237,6 +242,7 @@ __global__ __launch_bounds__(LZ_AR * lz_ag<NB>()) void k_lz_apply_rows(
   __shared__ typename std::conditional<QR, LzChol, char>::type fc;
   const int t = threadIdx.x, row = t % LZ_AR, g = t / LZ_AR;
   const int r0 = blockIdx.x * LZ_AR, r = r0 + row;
+  REFL_GUARD(nb >= 1 && nb <= NB && r0 < d && ldv >= d, DBG_LZ);
   // With QR, the summed Gram matrix is requested first (it is needed
   // first), then the slab of W (LZ_AR x NB) and the first chunk of C; masked
   // loads without branches (a load in a branch is waited for where the
@@ -624,6 +630,7 @@ __global__ __launch_bounds__(256) void k_lz_cholqr(const double* __restrict__ gi
                                                    double* __restrict__ gout, int mode,
                                                    double* dst_last) {
   if (mode == LZ_QR_SKIPPABLE && flag[2] == tag + 1) return;
+  REFL_GUARD(nb >= 1 && nb <= NB, DBG_LZ);
   __shared__ LzFactor f;
   __shared__ double sX[256][NB + 1];
   const int r = blockIdx.x * 256 + threadIdx.x;

@@ -6,11 +6,14 @@
 #include <type_traits>
 
 #include "common.h"
+#include "dbg.h"
 #include "sync.h"
 #include "launch.h"
 #include "rule.h"
 
 namespace refl {
+
+REFL_DBG_UNIT(misc)
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -45,6 +48,7 @@ __global__ __launch_bounds__(256) void k_mirror_upper(const double* __restrict__
                                                       int d, double* __restrict__ Hf, int dp) {
   const int I = blockIdx.y, J = blockIdx.x;
   if (I > J) return;
+  REFL_GUARD(J * 64 < dp && d <= dp && ldh >= d, DBG_MIRROR);
   __shared__ double t[64][65];
   mirror_tile(H, ldh, d, Hf, dp, I, J, t);
 }
@@ -76,6 +80,7 @@ __device__ __forceinline__ void rowabs_row(const double* __restrict__ Hf, int dp
 __global__ __launch_bounds__(256) void k_rowabs(const double* __restrict__ Hf, int dp, int d,
                                                 double s, int norm, double* __restrict__ rowsum,
                                                 double* __restrict__ nonfinite_rows) {
+  REFL_GUARD(d <= dp, DBG_ROWABS);
   rowabs_row(Hf, dp, d, s, norm, rowsum, nonfinite_rows, blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
@@ -134,6 +139,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_init_x0(const double* __restrict__ Hf, int dp, int d,
                                                  double s, const double* __restrict__ scal,
                                                  T* __restrict__ X) {
+  REFL_GUARD(d <= dp, DBG_INIT_X0);
   const double inv = 1.0 / scal[SC_ALPHA];
   init_x0_elems(Hf, dp, d, s, inv, X, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)dp * dp,
                 (int64_t)gridDim.x * 256);
@@ -146,6 +152,7 @@ __global__ __launch_bounds__(256) void k_init_x0_w(const double* __restrict__ Hf
                                                    double s, const double* __restrict__ scal,
                                                    uint16_t* __restrict__ X, int64_t ps,
                                                    float* __restrict__ H32) {
+  REFL_GUARD(d <= dp && ps >= (int64_t)dp * dp, DBG_INIT_X0);
   const int64_t n = (int64_t)dp * dp;
   const double inv = 1.0 / scal[SC_ALPHA];
   for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
@@ -577,6 +584,7 @@ __global__ __launch_bounds__(256) void k_thin_finish(const double* __restrict__ 
                                                      double* __restrict__ Y, int64_t ldy) {
   const int row = blockIdx.x * 256 + threadIdx.x;
   const int c = blockIdx.y;
+  REFL_GUARD(nb <= NB && (int)blockIdx.x * 256 < d && ldy >= d, DBG_THIN_FINISH);
   if (row >= d || c >= nb) return;
   double s = 0.0;
   if (BLK) {
@@ -666,6 +674,7 @@ __global__ __launch_bounds__(256) void k_form_reflector(const double* __restrict
                                                         int64_t ldr) {
   __shared__ double vi[64][33], vj[64][33];
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  REFL_GUARD(k >= 0 && k <= 32 && ldv >= d && ldr >= d && i0 < d && j0 < d, DBG_FORM_R);
   for (int e = threadIdx.x; e < 64 * 32; e += 256) {
     const int r = e & 63, c = e >> 6;
     vi[r][c] = (i0 + r < d && c < k) ? V[(int64_t)c * ldv + i0 + r] : 0.0;
@@ -884,6 +893,7 @@ __global__ __launch_bounds__(256 * KS) void k_symthin(const MT* __restrict__ M, 
   __shared__ double pv[CHUNK][NB];
   __shared__ ThinRed<KS, NB> red;
   const int j0 = blockIdx.y * CHUNK;
+  REFL_GUARD(nb >= 1 && nb <= NB && j0 < d && ldv >= d, DBG_SYMTHIN);
   for (int e = threadIdx.x; e < CHUNK * NB; e += 256 * KS) {
     const int jj = e / NB, c = e % NB, j = j0 + jj;
     pv[jj][c] = ldsel(V, (int64_t)c * ldv + j, j < d && c < nb);
@@ -1285,6 +1295,7 @@ __global__ __launch_bounds__(256) void k_cg_init(int d, const double* __restrict
                                                  double* __restrict__ part) {
   __shared__ double sp[2 * NB + 2][65];
   const int k = st->k, c = blockIdx.y;
+  REFL_GUARD(k <= NB && (int)blockIdx.x * 64 < d && ldv >= d, DBG_CG_INIT);
   const int tid = threadIdx.x, sub = tid & 3;
   const int row = blockIdx.x * 64 + (tid >> 2);
   const bool owner = sub == 0 && row < d;
@@ -1314,6 +1325,7 @@ __global__ __launch_bounds__(256 * KS) void k_cg_pass(const MT* __restrict__ M, 
   const int nb = st->nb;
   const int tid = threadIdx.x;
   const int j0 = blockIdx.y * CHUNK;
+  REFL_GUARD(nb >= 1 && nb <= NB && j0 < d && ldx >= d, DBG_CG_PASS);
   double rv[(NB * CHUNK + NT - 1) / NT];
 #pragma unroll
   for (int u = 0; u < (NB * CHUNK + NT - 1) / NT; ++u) {
@@ -1349,6 +1361,9 @@ __global__ __launch_bounds__(256) void k_cg_update(const double* __restrict__ wo
   __shared__ double sv[3 * 32 + 68];  // gamma, delta of every column, then this column's sums
   const int nb = st->nb, k = st->k, nv = 2 * k + 2;
   const int c = blockIdx.y, nrg = gridDim.x;
+  REFL_GUARD(nb >= 1 && nb <= NB && nb <= 32 && k <= NB && c < nb && (int)blockIdx.x * 64 < d &&
+                 ldv >= d,
+             DBG_CG_UPDATE);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & 3;
   const int row = blockIdx.x * 64 + (tid >> 2);

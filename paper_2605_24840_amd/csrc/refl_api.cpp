@@ -38,6 +38,7 @@
 
 #include "../../include/refl.h"
 #include "common.h"
+#include "dbg.h"
 #include "hostla.h"
 #include "launch.h"
 
@@ -2683,6 +2684,36 @@ refl_status_t estimate_impl(refl_handle_t h, int64_t d, const double* dH, int64_
   return lanczos_run(h, w.Hf, w.dp, d, k, seed, w.lz, w.thin, lr, start, d, ritz_out, d);
 }
 
+#ifdef REFL_DEBUG
+}  // namespace
+namespace refl {
+int refl_dbg_take_gemm_w();
+int refl_dbg_take_gemm_f();
+int refl_dbg_take_misc();
+int refl_dbg_take_lanczos();
+}  // namespace refl
+namespace {
+// Reads and clears every unit's guard record after the stream's work; a
+// tripped guard takes precedence over the call's own status.
+refl_status_t dbg_finish(refl_handle_t h, refl_status_t rs) {
+  if (!h) return rs;
+  if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+    return rs == REFL_OK ? fail(h, REFL_ERR_DEVICE, "stream synchronisation failed") : rs;
+  int (*const take[])() = {refl_dbg_take_gemm_w, refl_dbg_take_gemm_f, refl_dbg_take_misc,
+                           refl_dbg_take_lanczos};
+  int site = 0;
+  for (auto f : take) {
+    const int v = f();
+    if (v != 0 && site <= 0) site = v;
+  }
+  if (site < 0) return fail(h, REFL_ERR_DEVICE, "debug guard records unreadable");
+  if (site > 0) return fail(h, REFL_ERR_BOUNDS, "launch-extent guard tripped: %s", dbg_site_name(site));
+  return rs;
+}
+#else
+inline refl_status_t dbg_finish(refl_handle_t, refl_status_t rs) { return rs; }
+#endif
+
 }  // namespace
 
 extern "C" {
@@ -2815,7 +2846,7 @@ refl_status_t refl_sign(refl_handle_t h, int64_t d, const double* dH, int64_t ld
                         const refl_params_t* p, double* dR, int64_t ldr, refl_info_t* info) {
   if (!h) return REFL_ERR_INVALID_ARG;
   if (!dR || ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "R is NULL or ldr < d");
-  return sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info);
+  return dbg_finish(h, sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info));
 }
 
 refl_status_t refl_sign_noalloc(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2829,7 +2860,7 @@ refl_status_t refl_sign_noalloc(refl_handle_t h, int64_t d, const double* dH, in
     explicit Scope(refl_handle_t hh) : h(hh) { h->no_alloc = true; }
     ~Scope() { h->no_alloc = false; }
   } scope(h);
-  return sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info);
+  return dbg_finish(h, sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info));
 }
 
 refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2838,7 +2869,7 @@ refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double* dH, int6
   if (!h) return REFL_ERR_INVALID_ARG;
   if (nrhs < 1 || !dV || !dY || ldv < d || ldy < d)
     return fail(h, REFL_ERR_INVALID_ARG, "bad V/Y block (nrhs >= 1, ld >= d)");
-  return sign_impl(h, d, dH, ldh, p, nullptr, 0, nrhs, dV, ldv, dY, ldy, info);
+  return dbg_finish(h, sign_impl(h, d, dH, ldh, p, nullptr, 0, nrhs, dV, ldv, dY, ldy, info));
 }
 
 refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t ldr, int64_t nrhs,
@@ -2859,7 +2890,7 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t l
     const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
     HIPCHK(thin_gemm_f64(dR, ldr, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, h->stream));
   }
-  return REFL_OK;
+  return dbg_finish(h, REFL_OK);
 }
 
 refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2868,7 +2899,7 @@ refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, 
   if (!h) return REFL_ERR_INVALID_ARG;
   if (!s || !lam_k || !lam_k1 || !eps || !rho) return fail(h, REFL_ERR_INVALID_ARG, "NULL output");
   LzResult lr;
-  refl_status_t rs = estimate_impl(h, d, dH, ldh, k, steps, seed, lr);
+  refl_status_t rs = dbg_finish(h, estimate_impl(h, d, dH, ldh, k, steps, seed, lr));
   if (rs != REFL_OK) return rs;
   *s = lr.s;
   *lam_k = lr.lam_k;
@@ -2899,7 +2930,7 @@ refl_status_t refl_sign_batched(refl_handle_t h, int32_t nprob, const int64_t* d
                                 const refl_params_t* params, double* const* dR,
                                 const int64_t* ldr, refl_info_t* info, refl_status_t* status) {
   if (!h) return REFL_ERR_INVALID_ARG;
-  return batched_impl(h, nprob, d, dH, ldh, params, dR, ldr, info, status);
+  return dbg_finish(h, batched_impl(h, nprob, d, dH, ldh, params, dR, ldr, info, status));
 }
 
 refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2907,7 +2938,7 @@ refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double* dH, int64
                              int64_t ldgr, double* loss, double* dR, int64_t ldr,
                              refl_info_t* info) {
   if (!h) return REFL_ERR_INVALID_ARG;
-  return grad_impl(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info);
+  return dbg_finish(h, grad_impl(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info));
 }
 
 refl_status_t refl_policy_create(refl_handle_t h, const refl_policy_params_t* pp,
@@ -2942,8 +2973,8 @@ refl_status_t refl_policy_destroy(refl_policy_t pol) {
   return REFL_OK;
 }
 
-refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, const double* dH,
-                                int64_t ldh, double* s_out, refl_policy_info_t* info) {
+static refl_status_t policy_shift_impl(refl_handle_t h, refl_policy_t pol, int64_t d, const double* dH,
+                                       int64_t ldh, double* s_out, refl_policy_info_t* info) {
   if (!h || !pol || !s_out) return REFL_ERR_INVALID_ARG;
   if (pol->device != h->device) return fail(h, REFL_ERR_INVALID_ARG, "policy and handle devices differ");
   if (!dH || ldh < d || d < 2 || pol->pp.k > d - 1)
@@ -3073,6 +3104,19 @@ refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, c
   return REFL_OK;
 }
 
+refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, const double* dH,
+                                int64_t ldh, double* s_out, refl_policy_info_t* info) {
+  return dbg_finish(h, policy_shift_impl(h, pol, d, dH, ldh, s_out, info));
+}
+
+int refl_debug_build(void) {
+#ifdef REFL_DEBUG
+  return 1;
+#else
+  return 0;
+#endif
+}
+
 const char* refl_status_string(refl_status_t s) {
   // A C caller may pass any int: read the code as an int rather than load
   // an out-of-range value of the enum type.
@@ -3090,6 +3134,7 @@ const char* refl_status_string(refl_status_t s) {
     case REFL_ERR_NOT_SYMMETRIC: return "REFL_ERR_NOT_SYMMETRIC";
     case REFL_ERR_NOT_FINITE: return "REFL_ERR_NOT_FINITE";
     case REFL_ERR_UNSUPPORTED: return "REFL_ERR_UNSUPPORTED";
+    case REFL_ERR_BOUNDS: return "REFL_ERR_BOUNDS";
   }
   return "REFL_ERR_UNKNOWN";
 }

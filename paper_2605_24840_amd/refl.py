@@ -12,14 +12,17 @@ import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librefl.so")
+# The same library with the kernels' launch-extent guards (-DREFL_DEBUG).
+DEBUG_LIB_PATH = os.path.join(_PKG, "librefl_debug.so")
 
 REFL_OK = 0
 STATUS = {0: "REFL_OK", 1: "REFL_ERR_INVALID_ARG", 2: "REFL_ERR_DEVICE", 3: "REFL_ERR_NO_MEMORY",
           4: "REFL_ERR_NOT_CONVERGED", 5: "REFL_ERR_NOT_ADMISSIBLE", 6: "REFL_ERR_NO_GAP",
-          7: "REFL_ERR_NOT_SYMMETRIC", 8: "REFL_ERR_UNSUPPORTED", 9: "REFL_ERR_NOT_FINITE"}
+          7: "REFL_ERR_NOT_SYMMETRIC", 8: "REFL_ERR_UNSUPPORTED", 9: "REFL_ERR_NOT_FINITE",
+          10: "REFL_ERR_BOUNDS"}
 (REFL_ERR_INVALID_ARG, REFL_ERR_DEVICE, REFL_ERR_NO_MEMORY, REFL_ERR_NOT_CONVERGED,
  REFL_ERR_NOT_ADMISSIBLE, REFL_ERR_NO_GAP, REFL_ERR_NOT_SYMMETRIC, REFL_ERR_UNSUPPORTED,
- REFL_ERR_NOT_FINITE) = range(1, 10)
+ REFL_ERR_NOT_FINITE, REFL_ERR_BOUNDS) = range(1, 11)
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 SHIFT = {"given": 0, "lanczos": 1}
 SCALE = {"inf": 0, "fro": 1, "lanczos": 2, "given": 3}
@@ -33,7 +36,8 @@ EXPORTS = ["refl_params_default", "refl_create", "refl_destroy", "refl_set_strea
            "refl_workspace_size", "refl_set_workspace", "refl_estimate_shift", "refl_sign",
            "refl_sign_noalloc", "refl_apply", "refl_sign_apply", "refl_sign_batched",
            "refl_sign_batched_workspace_size", "refl_sign_grad", "refl_policy_create",
-           "refl_policy_destroy", "refl_policy_shift", "refl_status_string", "refl_last_error"]
+           "refl_policy_destroy", "refl_policy_shift", "refl_status_string", "refl_last_error",
+           "refl_debug_build"]
 
 
 class refl_params_t(ctypes.Structure):
@@ -90,12 +94,21 @@ class refl_info_t(ctypes.Structure):
 
 
 _lib = None
+_loaded = {}
 
 
-def load(path: str = LIB_PATH):
-    """Load ``librefl.so`` and declare the C signatures.  Raises if absent."""
+def load(path: str = None):
+    """The current library: ``librefl.so`` unless ``path`` names another
+    build (``DEBUG_LIB_PATH``), which then becomes current; each file is
+    opened once and its C signatures declared.  Raises if the file is absent.
+    Handles remember the library that created them."""
     global _lib
-    if _lib is not None:
+    if path is None:
+        if _lib is not None:
+            return _lib
+        path = LIB_PATH
+    if path in _loaded:
+        _lib = _loaded[path]
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2605_24840_amd.build.build()")
@@ -125,11 +138,13 @@ def load(path: str = LIB_PATH):
         "refl_policy_shift": [H, vp, i64, vp, i64, P(dbl), P(refl_policy_info_t)],
         "refl_status_string": [ctypes.c_int],
         "refl_last_error": [H],
+        "refl_debug_build": [],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_char_p if name in ("refl_status_string", "refl_last_error") else ctypes.c_int
+    _loaded[path] = lib
     _lib = lib
     return lib
 
@@ -327,6 +342,7 @@ class Handle:
     def __init__(self, device=None):
         import torch
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.lib = load()
         self.h = refl_create(self.device.index or 0, torch.cuda.current_stream(self.device).cuda_stream)
         self._ws = None
 
@@ -346,7 +362,7 @@ class Handle:
 
     def close(self):
         if self.h is not None:
-            refl_destroy(self.h)
+            self.lib.refl_destroy(self.h)
             self.h = None
 
     def __del__(self):

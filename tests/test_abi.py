@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "refl.h")
 
 def _declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:refl_status_t|const char\s*\*)\s*(refl_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:refl_status_t|const char\s*\*|int)\s*(refl_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_expected_entry_points():
@@ -32,6 +32,21 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared_functions()) <= exported
     # Nothing else leaks out under the refl_ prefix.
     assert exported == set(_declared_functions())
+
+
+def test_debug_build_exports_the_same_symbols():
+    """The bounds-checked build (-DREFL_DEBUG) is the same boundary: the
+    same exported names, and refl_debug_build() tells the two apart (a call
+    that touches no device)."""
+    assert os.path.exists(refl.DEBUG_LIB_PATH), "build it with build(debug=True)"
+    out = subprocess.run(["nm", "-D", "--defined-only", refl.DEBUG_LIB_PATH], capture_output=True,
+                         text=True).stdout
+    assert set(re.findall(r" T (refl_\w+)", out)) == set(_declared_functions())
+    rel = ctypes.CDLL(refl.LIB_PATH)
+    dbg = ctypes.CDLL(refl.DEBUG_LIB_PATH)
+    assert rel.refl_debug_build() == 0 and dbg.refl_debug_build() == 1
+    dbg.refl_status_string.restype = ctypes.c_char_p
+    assert dbg.refl_status_string(refl.REFL_ERR_BOUNDS) == b"REFL_ERR_BOUNDS"
 
 
 def test_struct_layout_matches_header(tmp_path):
@@ -84,14 +99,14 @@ def _header_enum(name):
 def test_enum_values_match_header_and_binding():
     """The binding's code tables equal the header's enumerators, and the
     status and scale codes are those of the boundary sketch (statuses
-    0..8 in its order, REFL_ERR_NOT_FINITE added as 9; scales INF, FRO,
-    LANCZOS, GIVEN = 0..3)."""
+    0..8 in its order, REFL_ERR_NOT_FINITE added as 9 and the debug build's
+    REFL_ERR_BOUNDS as 10; scales INF, FRO, LANCZOS, GIVEN = 0..3)."""
     st = _header_enum("refl_status_t")
     assert {v: k for k, v in st.items()} == refl.STATUS
     assert [st[n] for n in ("REFL_OK", "REFL_ERR_INVALID_ARG", "REFL_ERR_DEVICE", "REFL_ERR_NO_MEMORY",
                             "REFL_ERR_NOT_CONVERGED", "REFL_ERR_NOT_ADMISSIBLE", "REFL_ERR_NO_GAP",
                             "REFL_ERR_NOT_SYMMETRIC", "REFL_ERR_UNSUPPORTED",
-                            "REFL_ERR_NOT_FINITE")] == list(range(10))
+                            "REFL_ERR_NOT_FINITE", "REFL_ERR_BOUNDS")] == list(range(11))
     sc = _header_enum("refl_scale_mode_t")
     assert sc == {"REFL_SCALE_INF": 0, "REFL_SCALE_FRO": 1, "REFL_SCALE_LANCZOS": 2, "REFL_SCALE_GIVEN": 3}
     assert {"REFL_SCALE_" + k.upper(): v for k, v in refl.SCALE.items()} == sc

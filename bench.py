@@ -52,6 +52,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def emit(out, args):
+    """Print the JSON line; with --log also append it, stamped with the UTC
+    time and host name, to that JSONL file (one row per run)."""
+    print(json.dumps(out), flush=True)
+    if getattr(args, "log", None):
+        import platform
+        row = dict(out, time_utc=time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()),
+                   host=platform.node())
+        with open(args.log, "a") as f:
+            f.write(json.dumps(row) + "\n")
+
+
 def measured_traffic():
     """HBM bytes per launch of the bulk products from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE passes scaled by the copy-kernel
@@ -91,6 +103,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="counter-collection workload: one mixed solve, then a 256 MiB elementwise "
                          "kernel (reads 256 MiB, writes 256 MiB) that calibrates FETCH_SIZE/WRITE_SIZE")
+    ap.add_argument("--log", default=os.environ.get("REFL_BENCH_LOG"),
+                    help="also append the JSON line, with the time and host, to this JSONL file "
+                         "(default: $REFL_BENCH_LOG, none if unset)")
     args = ap.parse_args()
     if args.steps < 1 or args.fp64_steps < 1 or args.lanczos_steps < 1:
         ap.error("--steps, --fp64-steps and --lanczos-steps must be at least 1")
@@ -279,7 +294,7 @@ def main():
         "cpu_baseline": cpu,
     }
     h.close()
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 FP32_PEAK = 157.3e12
@@ -445,7 +460,7 @@ def bench_grad(args):
                      "launches": info["gemm_launches"], "avg_launch_ms": 1e3 * gemm_s / max(info["gemm_launches"], 1)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 def bench_kscan(args):
@@ -500,7 +515,7 @@ def bench_kscan(args):
         "roofline": None,
         "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 def bench_batched(args):
@@ -631,7 +646,7 @@ def bench_batched(args):
                      "launches": launches, "avg_launch_ms": 1e3 * gemm_s / max(launches, 1)},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    emit(out, args)
 
 
 if __name__ == "__main__":

@@ -20,8 +20,7 @@ enum DbgSite {
   DBG_NONE = 0,
   DBG_GEMM_W_TILE,      // word product: tile or K range outside the padded order
   DBG_GEMM_WD_TILE,     // word product (direct-to-LDS): the same
-  DBG_GEMM_F_TILE,      // FP64/FP32 product: the same
-  DBG_GEMM_F_GROUPED,   // grouped FP32/FP64 product: problem or tile index
+  DBG_GEMM_F_TILE,      // FP64/FP32 product (single, grouped, adjoint): the same
   DBG_MIRROR,           // mirror of the upper triangle: tile outside d
   DBG_ROWABS,           // row sums: rows outside d
   DBG_INIT_X0,          // X_0 = (H - sI)/alpha: rows or columns outside the padded order
@@ -38,8 +37,8 @@ enum DbgSite {
 // Site names for the host's error message, in DbgSite order.
 inline const char* dbg_site_name(int s) {
   static const char* const names[DBG_SITES] = {
-      "none", "k_sym_gemm_w tile", "k_sym_gemm_wd tile", "k_sym_gemm_f tile",
-      "k_sym_gemm_f_grouped problem/tile", "k_mirror_upper tile", "k_rowabs rows",
+      "none", "k_sym_gemm_w tile", "k_sym_gemm_wd tile", "k_sym_gemm_f* tile",
+      "k_mirror_upper tile", "k_rowabs rows",
       "k_init_x0 extent", "k_form_reflector rows", "k_symthin chunk", "k_thin_finish rows",
       "k_cg_pass chunk/columns", "k_cg_update rows/column", "k_cg_init rows/column",
       "block-Lanczos kernel extent"};

@@ -2714,6 +2714,36 @@ refl_status_t dbg_finish(refl_handle_t h, refl_status_t rs) {
 inline refl_status_t dbg_finish(refl_handle_t, refl_status_t rs) { return rs; }
 #endif
 
+// REFL_LOG (environment, read once): when set and not "0", every entry point
+// that runs device work writes one line to stderr as it returns: its name,
+// the order, the status and, where the caller passed a refl_info_t, the
+// solve's figures (steps, sweeps, inner iterations, certified index, the
+// last residual, the Davis-Kahan bound, wall-clock per phase); on an error
+// also the handle's message.
+bool log_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("REFL_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+  }();
+  return on;
+}
+
+refl_status_t log_call(refl_handle_t h, const char* name, int64_t d, refl_status_t rs,
+                       const refl_info_t* info) {
+  if (!log_enabled()) return rs;
+  if (info)
+    std::fprintf(stderr,
+                 "refl: %s d=%lld status=%s steps=%d sweeps=%d cg=%d j=%d tile=%d words=%d "
+                 "resid=%.3e dk=%.3e ms=%.3f (setup %.3f bulk %.3f polish %.3f)\n",
+                 name, (long long)d, refl_status_string(rs), info->ns_steps, info->polish_sweeps,
+                 info->cg_iters, info->index_j, info->bulk_tile, info->bulk_words, info->resid_fro,
+                 info->dk_bound, info->ms_total, info->ms_setup, info->ms_bulk, info->ms_polish);
+  else
+    std::fprintf(stderr, "refl: %s d=%lld status=%s\n", name, (long long)d, refl_status_string(rs));
+  if (rs != REFL_OK && h) std::fprintf(stderr, "refl:   %s\n", h->err);
+  return rs;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2846,7 +2876,9 @@ refl_status_t refl_sign(refl_handle_t h, int64_t d, const double* dH, int64_t ld
                         const refl_params_t* p, double* dR, int64_t ldr, refl_info_t* info) {
   if (!h) return REFL_ERR_INVALID_ARG;
   if (!dR || ldr < d) return fail(h, REFL_ERR_INVALID_ARG, "R is NULL or ldr < d");
-  return dbg_finish(h, sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info));
+  return log_call(h, "refl_sign", d,
+                  dbg_finish(h, sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info)),
+                  info);
 }
 
 refl_status_t refl_sign_noalloc(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2860,7 +2892,9 @@ refl_status_t refl_sign_noalloc(refl_handle_t h, int64_t d, const double* dH, in
     explicit Scope(refl_handle_t hh) : h(hh) { h->no_alloc = true; }
     ~Scope() { h->no_alloc = false; }
   } scope(h);
-  return dbg_finish(h, sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info));
+  return log_call(h, "refl_sign_noalloc", d,
+                  dbg_finish(h, sign_impl(h, d, dH, ldh, p, dR, ldr, 0, nullptr, 0, nullptr, 0, info)),
+                  info);
 }
 
 refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2869,7 +2903,9 @@ refl_status_t refl_sign_apply(refl_handle_t h, int64_t d, const double* dH, int6
   if (!h) return REFL_ERR_INVALID_ARG;
   if (nrhs < 1 || !dV || !dY || ldv < d || ldy < d)
     return fail(h, REFL_ERR_INVALID_ARG, "bad V/Y block (nrhs >= 1, ld >= d)");
-  return dbg_finish(h, sign_impl(h, d, dH, ldh, p, nullptr, 0, nrhs, dV, ldv, dY, ldy, info));
+  return log_call(h, "refl_sign_apply", d,
+                  dbg_finish(h, sign_impl(h, d, dH, ldh, p, nullptr, 0, nrhs, dV, ldv, dY, ldy, info)),
+                  info);
 }
 
 refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t ldr, int64_t nrhs,
@@ -2890,7 +2926,7 @@ refl_status_t refl_apply(refl_handle_t h, int64_t d, const double* dR, int64_t l
     const int nb = (int)std::min<int64_t>(MAXB, nrhs - c0);
     HIPCHK(thin_gemm_f64(dR, ldr, (int)d, dV + c0 * ldv, ldv, nb, dY + c0 * ldy, ldy, w.thin, h->stream));
   }
-  return dbg_finish(h, REFL_OK);
+  return log_call(h, "refl_apply", d, dbg_finish(h, REFL_OK), nullptr);
 }
 
 refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2900,13 +2936,13 @@ refl_status_t refl_estimate_shift(refl_handle_t h, int64_t d, const double* dH, 
   if (!s || !lam_k || !lam_k1 || !eps || !rho) return fail(h, REFL_ERR_INVALID_ARG, "NULL output");
   LzResult lr;
   refl_status_t rs = dbg_finish(h, estimate_impl(h, d, dH, ldh, k, steps, seed, lr));
-  if (rs != REFL_OK) return rs;
+  if (rs != REFL_OK) return log_call(h, "refl_estimate_shift", d, rs, nullptr);
   *s = lr.s;
   *lam_k = lr.lam_k;
   *lam_k1 = lr.lam_k1;
   *eps = lr.eps;
   *rho = lr.rho;
-  return lanczos_status(h, lr);
+  return log_call(h, "refl_estimate_shift", d, lanczos_status(h, lr), nullptr);
 }
 
 refl_status_t refl_sign_batched_workspace_size(refl_handle_t h, int32_t nprob, const int64_t* d,
@@ -2930,7 +2966,9 @@ refl_status_t refl_sign_batched(refl_handle_t h, int32_t nprob, const int64_t* d
                                 const refl_params_t* params, double* const* dR,
                                 const int64_t* ldr, refl_info_t* info, refl_status_t* status) {
   if (!h) return REFL_ERR_INVALID_ARG;
-  return dbg_finish(h, batched_impl(h, nprob, d, dH, ldh, params, dR, ldr, info, status));
+  return log_call(h, "refl_sign_batched (order of problem 0)", nprob > 0 && d ? d[0] : 0,
+                  dbg_finish(h, batched_impl(h, nprob, d, dH, ldh, params, dR, ldr, info, status)),
+                  nullptr);
 }
 
 refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double* dH, int64_t ldh,
@@ -2938,7 +2976,9 @@ refl_status_t refl_sign_grad(refl_handle_t h, int64_t d, const double* dH, int64
                              int64_t ldgr, double* loss, double* dR, int64_t ldr,
                              refl_info_t* info) {
   if (!h) return REFL_ERR_INVALID_ARG;
-  return dbg_finish(h, grad_impl(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info));
+  return log_call(h, "refl_sign_grad", d,
+                  dbg_finish(h, grad_impl(h, d, dH, ldh, p, dG, ldg, dGrad, ldgr, loss, dR, ldr, info)),
+                  info);
 }
 
 refl_status_t refl_policy_create(refl_handle_t h, const refl_policy_params_t* pp,
@@ -3106,7 +3146,8 @@ static refl_status_t policy_shift_impl(refl_handle_t h, refl_policy_t pol, int64
 
 refl_status_t refl_policy_shift(refl_handle_t h, refl_policy_t pol, int64_t d, const double* dH,
                                 int64_t ldh, double* s_out, refl_policy_info_t* info) {
-  return dbg_finish(h, policy_shift_impl(h, pol, d, dH, ldh, s_out, info));
+  return log_call(h, "refl_policy_shift", d,
+                  dbg_finish(h, policy_shift_impl(h, pol, d, dH, ldh, s_out, info)), nullptr);
 }
 
 int refl_debug_build(void) {

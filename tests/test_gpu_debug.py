@@ -87,3 +87,28 @@ def test_debug_build_matches_release_and_trips_no_guard():
         for x, y in zip(va, vb):
             assert x.shape == y.shape and np.array_equal(x, y, equal_nan=True), name
     _say(f"  {len(a)} cases: debug build bit-equal to release, no guard tripped")
+
+
+def test_refl_log_line():
+    """REFL_LOG=1 makes each device entry point write one line to stderr with
+    its status and figures.  The variable is read once per process, so the
+    call runs in a child process (one small MIXED solve)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = (
+        "import sys, torch; sys.path.insert(0, %r)\n"
+        "from paper_2605_24840_amd import inputs, refl\n"
+        "H, lam, _ = inputs.planted_hessian(300, 4, 0.1, 3)\n"
+        "R, info, st = refl.sign(torch.from_numpy(H).to('cuda:0'), 4, 0.5 * (lam[3] + lam[4]), precision='mixed')\n"
+        "print('status', st, info['ns_steps'], info['cg_iters'], flush=True)\n" % root)
+    _say("child process with REFL_LOG=1: mixed d=300 k=4")
+    r = subprocess.run([sys.executable, "-c", script], env=dict(os.environ, REFL_LOG="1"),
+                       capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    _, st, steps, cg = r.stdout.split()[-4:]
+    lines = [x for x in r.stderr.splitlines() if x.startswith("refl: refl_sign ")]
+    assert len(lines) == 1, r.stderr[-2000:]
+    assert f"d=300 status=REFL_OK steps={steps} " in lines[0] and f" cg={cg} j=4 " in lines[0], lines[0]
+    _say(f"  {lines[0]}")

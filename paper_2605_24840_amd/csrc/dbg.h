@@ -31,6 +31,13 @@ enum DbgSite {
   DBG_CG_UPDATE,        // inner solve's update: row group or column outside the block
   DBG_CG_INIT,          // inner solve's first partials: the same
   DBG_LZ,               // block-Lanczos kernels: block or rows outside the basis
+  DBG_CG_STEP,          // FP64 inner solve's step: chunk outside d, block wider than instantiated
+  DBG_CG_APPLY,         // FP64 inner solve's apply: row group or column outside the block
+  DBG_GRAM,             // Gram partials: more than 32 columns, rows outside d
+  DBG_THIN_PARTIAL,     // thin product (column form): chunk or block width
+  DBG_COPY_OUT,         // word planes to FP64: row outside d, planes overlapping
+  DBG_TRACE,            // trace of the word planes: d above the padded order
+  DBG_SHIFTED_F32,      // FP32 copy of H - sI: d above the padded order
   DBG_SITES
 };
 
@@ -41,7 +48,9 @@ inline const char* dbg_site_name(int s) {
       "k_mirror_upper tile", "k_rowabs rows",
       "k_init_x0 extent", "k_form_reflector rows", "k_symthin chunk", "k_thin_finish rows",
       "k_cg_pass chunk/columns", "k_cg_update rows/column", "k_cg_init rows/column",
-      "block-Lanczos kernel extent"};
+      "block-Lanczos kernel extent", "k_cg_step chunk/columns", "k_cg_apply rows/column",
+      "k_gram_partial columns/rows", "k_thin_partial chunk/columns", "k_copy_out_w rows",
+      "k_trace_w extent", "k_shifted_f32 extent"};
   return (s > 0 && s < DBG_SITES) ? names[s] : "unknown";
 }
 

@@ -170,6 +170,7 @@ __global__ __launch_bounds__(256) void k_init_x0_w(const double* __restrict__ Hf
 
 __global__ __launch_bounds__(256) void k_shifted_f32(const double* __restrict__ Hf, int dp, int d,
                                                      double s, float* __restrict__ Hs) {
+  REFL_GUARD(d <= dp, DBG_SHIFTED_F32);
   const int64_t n = (int64_t)dp * dp;
   for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * 256) {
@@ -309,6 +310,7 @@ __global__ __launch_bounds__(256) void k_trace_w(const uint16_t* __restrict__ X,
                                                  int dp, int d, double* __restrict__ scal,
                                                  int slot) {
   __shared__ double red[4];
+  REFL_GUARD(d <= dp && ps >= (int64_t)dp * dp && slot >= 0 && slot < SC_COUNT, DBG_TRACE);
   double a = 0.0;
   for (int i = threadIdx.x; i < d; i += 256) {
     float x = 0.f;
@@ -546,6 +548,7 @@ __global__ __launch_bounds__(256) void k_thin_partial(const MT* __restrict__ M, 
   constexpr int PER = CH / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j0 = blockIdx.y * CH;
+  REFL_GUARD(nb >= 1 && nb <= NB && j0 < d && ldv >= d, DBG_THIN_PARTIAL);
   double v[PER][NB];
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
@@ -614,6 +617,7 @@ __global__ __launch_bounds__(256) void k_gram_partial(const double* __restrict__
                                                       double* __restrict__ work) {
   __shared__ double sa[64][33], sb[64][33];
   const int r0 = blockIdx.x * 64;
+  REFL_GUARD(na >= 0 && na <= 32 && nb >= 0 && nb <= 32 && r0 < d && lda >= d && ldb >= d, DBG_GRAM);
   for (int e = threadIdx.x; e < 64 * 32; e += 256) {
     const int r = e & 63, c = e >> 6;
     const int row = r0 + r;
@@ -972,6 +976,7 @@ __global__ __launch_bounds__(256 * KS) void k_cg_step(const MT* __restrict__ M, 
   const int nb = st->nb, k = st->k;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int j0 = blockIdx.y * CHUNK;
+  REFL_GUARD(nb >= 1 && nb <= NB && k <= 32 && j0 < d && ldv >= d, DBG_CG_STEP);
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
   // Every global load of the block's set-up is issued before the first wait
   // (and the first rows of M after them), and the barriers between the
@@ -1148,6 +1153,8 @@ __global__ __launch_bounds__(256) void k_cg_apply(const double* __restrict__ wor
   __shared__ double red[4][35];
   const int nb = st->nb, k = st->k;
   const int c = blockIdx.y;
+  REFL_GUARD(nb >= 1 && nb <= NB && k <= 32 && c < nb && (int)blockIdx.x * 64 < d && ldv >= d,
+             DBG_CG_APPLY);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int sub = tid & 3;
   const int row = blockIdx.x * 64 + (tid >> 2);
@@ -1519,6 +1526,7 @@ __global__ __launch_bounds__(256) void k_copy_out_w(const uint16_t* __restrict__
                                                     int dp, int d, double* __restrict__ R,
                                                     int64_t ldr) {
   const int i = blockIdx.y;
+  REFL_GUARD(i < d && d <= dp && ps >= (int64_t)dp * dp && ldr >= d, DBG_COPY_OUT);
   for (int j = blockIdx.x * 256 + threadIdx.x; j < d; j += gridDim.x * 256) {
     float x = 0.f;
 #pragma unroll

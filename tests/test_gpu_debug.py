@@ -7,7 +7,8 @@ Cases cover each guarded kernel family: FP64 and FP32 products at ragged
 orders (FP64/FP32 tiles, mirror, row sums, X_0, reflector), the MIXED path
 with its correction (word products, thin passes, inner-solve pass, update
 and first partials, Cholesky QR), R V without forming R, the block-Lanczos
-shift estimate, a batched call and a gradient.  The release library's
+shift estimate, a batched call and two gradients (FP64 adjoint, and the
+MIXED limit's FP64 block CG).  The release library's
 results are themselves checked against the oracle by the other GPU tests.
 """
 import numpy as np
@@ -61,6 +62,11 @@ def _run_all(refl):
         G = torch.from_numpy(inputs.symmetric_normal(200, 5)).to("cuda:0")
         grad, loss, _, _, st = refl.sign_grad(H, G, 4, s, handle=h, tol=1e-10)
         out["grad"] = ([st], [grad.cpu().numpy(), np.array([loss])])
+        _say("  sign_grad mixed d=400 k=3 (FP64 block CG of the gradient)")
+        H, s = _planted(400, 3, 0.1, 23)
+        G = torch.from_numpy(inputs.symmetric_normal(400, 6)).to("cuda:0")
+        grad, loss, _, _, st = refl.sign_grad(H, G, 3, s, handle=h, precision="mixed")
+        out["grad_mixed"] = ([st], [grad.cpu().numpy(), np.array([loss])])
     finally:
         h.close()
     return out

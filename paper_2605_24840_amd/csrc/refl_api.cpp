@@ -567,6 +567,15 @@ static_assert(sizeof(SmallProb) == 32 && sizeof(BatchRule) == 16 && sizeof(Batch
 int* qr_flag_host(refl_handle_t h) {
   return reinterpret_cast<int*>(reinterpret_cast<char*>(h->pinned + SC_COUNT) + sizeof(CgHost) + 128);
 }
+// Pinned staging of the Rayleigh-Ritz exchanges (behind the 256-byte tail):
+// slot 0 and 1 hold MAXB x MAXB doubles (a Gram matrix read back, the Ritz
+// rotation sent), slot 2 MAXB doubles.  A copy from pinned memory is queued
+// without the runtime's pageable staging; a slot is rewritten only after
+// the next synchronisation of the stream, when its copy has completed.
+double* rr_pin(refl_handle_t h, int slot) {
+  return reinterpret_cast<double*>(reinterpret_cast<char*>(h->pinned + SC_COUNT) + sizeof(CgHost) + 256) +
+         (size_t)slot * MAXB * MAXB;
+}
 refl_status_t orthonormalise(refl_handle_t h, Work& w, double*& V, double*& spare, int nb) {
   hipStream_t st = h->stream;
   HIPCHK(lz_gram(V, w.dp, nb, w.d, w.qr_gp[0], st));
@@ -659,7 +668,10 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     refl_status_t r = orthonormalise(h, w, V, spare, k);
     if (r != REFL_OK) return r;
   }
-  std::vector<double> G(k * k), Q(k * k), th(k), Cc(k * k), nrm(k);
+  std::vector<double> Q(k * k), th(k);
+  double* G = rr_pin(h, 0);    // Gram matrices read back
+  double* Cc = rr_pin(h, 1);   // Ritz rotation sent
+  double* nrm = rr_pin(h, 2);  // -theta sent
   double* Wm = w.W;
   double* Wspare = w.T2;
   double E_fro = NaN, theta_max = NaN, dk = NaN;
@@ -670,27 +682,27 @@ refl_status_t polish(refl_handle_t h, Work& w, const refl_params_t& p, double s,
     // Rayleigh-Ritz on span(V) with H (FP64).
     HIPCHK(symthin_f64(w.Hf, ld, d, V, ld, k, Wm, ld, w.thin, st));
     HIPCHK(gram(V, ld, k, Wm, ld, k, d, w.G, w.gwork, st));
-    HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(G, w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (qr_lost_rank(h)) return fail(h, REFL_ERR_NOT_CONVERGED, "Cholesky QR: block lost rank");
-    if (sym_eig_small(k, G.data(), th.data(), Q.data()) != 0)
+    if (sym_eig_small(k, G, th.data(), Q.data()) != 0)
       return fail(h, REFL_ERR_NOT_CONVERGED, "Rayleigh-Ritz eigensolver failed");
     for (int i = 0; i < k; ++i)
       for (int j = 0; j < k; ++j) Cc[i + k * j] = Q[(size_t)i * k + j];  // column-major
-    HIPCHK(hipMemcpyAsync(w.G, Cc.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.G, Cc, sizeof(double) * k * k, hipMemcpyHostToDevice, st));
     HIPCHK(block_axpy(d, k, k, 0.0, spare, ld, 1.0, V, ld, w.G, st));
     std::swap(V, spare);
     HIPCHK(block_axpy(d, k, k, 0.0, Wspare, ld, 1.0, Wm, ld, w.G, st));
     std::swap(Wm, Wspare);
     // Residual E = W - V Theta, projected onto the complement of V.
     for (int c = 0; c < k; ++c) nrm[c] = -th[c];
-    HIPCHK(hipMemcpyAsync(w.G + MAXB * MAXB, nrm.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(w.G + MAXB * MAXB, nrm, sizeof(double) * k, hipMemcpyHostToDevice, st));
     HIPCHK(lincomb(d, k, 1.0, Wm, ld, 0.0, w.Rr, ld, st));
     HIPCHK(col_axpy(d, k, w.Rr, ld, w.G + MAXB * MAXB, V, ld, st));
     HIPCHK(gram(V, ld, k, w.Rr, ld, k, d, w.G, w.gwork, st));
     HIPCHK(block_axpy(d, k, k, 1.0, w.Rr, ld, -1.0, V, ld, w.G, st));
     HIPCHK(gram(w.Rr, ld, k, w.Rr, ld, k, d, w.G, w.gwork, st));
-    HIPCHK(hipMemcpyAsync(G.data(), w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(G, w.G, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     double e2 = 0.0;
     for (int c = 0; c < k; ++c) e2 += G[c + k * c];
@@ -2793,7 +2805,8 @@ refl_status_t refl_create(refl_handle_t* out, int device, void* hip_stream) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       ncu > 0)
     h->ncu = ncu;
-  const size_t pin_bytes = sizeof(double) * SC_COUNT + sizeof(CgHost) + 256;
+  const size_t pin_bytes = sizeof(double) * SC_COUNT + sizeof(CgHost) + 256 +
+                           sizeof(double) * (2 * MAXB * MAXB + MAXB);
   if (hipHostMalloc((void**)&h->pinned, pin_bytes, hipHostMallocDefault) != hipSuccess) {
     delete h;
     return REFL_ERR_NO_MEMORY;
